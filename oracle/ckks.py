@@ -1,0 +1,507 @@
+"""Python side of the O2 CPU RNS-CKKS oracle -- test infrastructure only.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s cpu_baseline
+leg may import this module.  It loads ``oracle/libckks_oracle.so`` (plain C,
+built from ``oracle/ckks_oracle.c``) for the ring arithmetic and keeps the
+scale bookkeeping, the constant encodings and the CutMax schedule here, in
+float64 Python, written from the conventions in DESIGN.md ("CKKS conventions",
+"Encrypted CutMax schedule").  It shares no code with the HIP path.
+
+Paper anchors: CKKS correctness and homomorphic properties (Sec. 2.1);
+SIMD slots, rotations and rotate-and-sum (Sec. 3.2, App. D); the encrypted
+CutMax (Alg. 2) and its Goldschmidt inverse (App. B.1); the nucleus sampler
+(Alg. 3).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ckks_oracle.c")
+_LIB = os.path.join(_HERE, "libckks_oracle.so")
+
+u64p = ctypes.POINTER(ctypes.c_uint64)
+i64p = ctypes.POINTER(ctypes.c_int64)
+dblp = ctypes.POINTER(ctypes.c_double)
+
+
+def build_oracle(force: bool = False) -> str:
+    """Compile the C oracle (gcc, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=gnu11",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        L = ctypes.CDLL(build_oracle())
+        V = ctypes.c_void_p
+        L.oc_ctx_create.restype = V
+        L.oc_ctx_create.argtypes = [ctypes.c_int] * 6 + [ctypes.c_uint64]
+        L.oc_ctx_free.argtypes = [V]
+        L.oc_ctx_info.argtypes = [V] + [ctypes.POINTER(ctypes.c_int)] * 4
+        L.oc_ctx_primes.argtypes = [V, u64p]
+        L.oc_ctx_secret.argtypes = [V, ctypes.POINTER(ctypes.c_int8)]
+        L.oc_set_nonce.argtypes = [V, ctypes.c_uint32]
+        L.oc_get_nonce.restype = ctypes.c_uint32
+        L.oc_get_nonce.argtypes = [V]
+        L.oc_keygen.argtypes = [V, ctypes.c_int]
+        L.oc_ct_free.argtypes = [V]
+        L.oc_ct_level.argtypes = [V]
+        L.oc_ct_export.argtypes = [V, V, u64p]
+        L.oc_ct_import.restype = V
+        L.oc_ct_import.argtypes = [V, u64p, ctypes.c_int]
+        L.oc_encrypt.restype = V
+        L.oc_encrypt.argtypes = [V, i64p]
+        L.oc_decrypt.argtypes = [V, V, dblp]
+        for name in ("oc_add", "oc_sub", "oc_mul", "oc_mul_norescale"):
+            getattr(L, name).restype = V
+            getattr(L, name).argtypes = [V, V, V]
+        for name in ("oc_mul_int", "oc_add_const_int", "oc_mul_int_rescale"):
+            getattr(L, name).restype = V
+            getattr(L, name).argtypes = [V, V, ctypes.c_int64]
+        L.oc_drop.restype = V
+        L.oc_drop.argtypes = [V, V, ctypes.c_int]
+        L.oc_rescale.restype = V
+        L.oc_rescale.argtypes = [V, V]
+        L.oc_rotate.restype = V
+        L.oc_rotate.argtypes = [V, V, ctypes.c_int]
+        L.oc_automorph.restype = V
+        L.oc_automorph.argtypes = [V, V, ctypes.c_uint64]
+        L.oc_keyswitch.argtypes = [V, u64p, ctypes.c_int, ctypes.c_int, u64p, u64p]
+        L.oc_schoolbook.argtypes = [u64p, u64p, u64p, ctypes.c_int, ctypes.c_uint64]
+        L.oc_ring_mul.argtypes = [V, ctypes.c_int, u64p, u64p, u64p]
+        L.oc_philox4x32_10.argtypes = [ctypes.POINTER(ctypes.c_uint32)] * 3
+        L.oc_num_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a, t):
+    return a.ctypes.data_as(t)
+
+
+def philox4x32_10(ctr, key):
+    c = (ctypes.c_uint32 * 4)(*ctr)
+    k = (ctypes.c_uint32 * 2)(*key)
+    o = (ctypes.c_uint32 * 4)()
+    lib().oc_philox4x32_10(c, k, o)
+    return list(o)
+
+
+def llround(x: float) -> int:
+    """C llround: nearest integer, halves away from zero."""
+    f = math.floor(x)
+    d = x - f
+    if d > 0.5 or (d == 0.5 and x > 0):
+        return int(f) + 1
+    return int(f)
+
+
+# ----------------------------------------------------------------------------
+# parameters
+# ----------------------------------------------------------------------------
+@dataclass(frozen=True)
+class Params:
+    log_n: int
+    n_q: int          # number of Q primes (q_0 .. q_L), L = n_q - 1
+    q0_bits: int
+    q_bits: int
+    p_bits: int
+    dnum: int
+    log2_scale: float
+    seed: int = 1
+
+    @property
+    def N(self):
+        return 1 << self.log_n
+
+    @property
+    def slots(self):
+        return self.N // 2
+
+
+# ----------------------------------------------------------------------------
+# encoding (canonical embedding, slot j <-> zeta^(5^j mod 2N), zeta = e^{i pi/N})
+# ----------------------------------------------------------------------------
+def slot_exponents(N: int) -> np.ndarray:
+    t = np.empty(N // 2, dtype=np.int64)
+    v = 1
+    for j in range(N // 2):
+        t[j] = v
+        v = (v * 5) % (2 * N)
+    return t
+
+
+def encode_direct(z: np.ndarray, N: int, scale: float) -> np.ndarray:
+    """m_k = round((2 scale / N) sum_j z_j cos(pi t_j k / N)), real slots z (small N)."""
+    t = slot_exponents(N)
+    k = np.arange(N)
+    ang = np.pi * np.outer(t, k).astype(np.float64) / N % (2 * np.pi)
+    m = (2.0 * scale / N) * (np.asarray(z, dtype=np.float64) @ np.cos(ang))
+    return np.array([llround(v) for v in m], dtype=np.int64)
+
+
+def decode_direct(m: np.ndarray, N: int, scale: float) -> np.ndarray:
+    """z_j = Re m(zeta^{t_j}) / scale, by direct evaluation (small N)."""
+    t = slot_exponents(N)
+    k = np.arange(N)
+    ang = np.pi * np.outer(t, k).astype(np.float64) / N % (2 * np.pi)
+    return (np.cos(ang) @ np.asarray(m, dtype=np.float64)) / scale
+
+
+def _eval_all_odd(m: np.ndarray, N: int) -> np.ndarray:
+    """m(zeta^(2k+1)) for k < N as a twisted DFT: sum_i (m_i zeta^i) omega^(ik)."""
+    i = np.arange(N)
+    tw = np.exp(1j * np.pi * i / N)
+    return np.fft.ifft(np.asarray(m, dtype=np.float64) * tw) * N
+
+
+def decode_fft(m: np.ndarray, N: int, scale: float) -> np.ndarray:
+    ev = _eval_all_odd(m, N)
+    t = slot_exponents(N)
+    return ev[(t - 1) // 2].real / scale
+
+
+def encode_fft(z: np.ndarray, N: int, scale: float) -> np.ndarray:
+    t = slot_exponents(N)
+    E = np.zeros(N, dtype=np.complex128)
+    zz = np.asarray(z, dtype=np.float64) * scale
+    E[(t - 1) // 2] = zz
+    E[(2 * N - t - 1) // 2] = zz          # conjugate slots (real input)
+    i = np.arange(N)
+    v = np.fft.fft(E) / N * np.exp(-1j * np.pi * i / N)
+    return np.array([llround(x) for x in v.real], dtype=np.int64)
+
+
+def encode(z, N, scale):
+    return encode_direct(z, N, scale) if N <= 4096 else encode_fft(z, N, scale)
+
+
+def decode(m, N, scale):
+    return decode_direct(m, N, scale) if N <= 4096 else decode_fft(m, N, scale)
+
+
+# ----------------------------------------------------------------------------
+# ciphertext handle with scale bookkeeping
+# ----------------------------------------------------------------------------
+class Ct:
+    __slots__ = ("h", "level", "scale", "ctx")
+
+    def __init__(self, ctx, h, scale):
+        if not h:
+            raise RuntimeError("oracle op failed")
+        self.ctx, self.h, self.scale = ctx, h, float(scale)
+        self.level = lib().oc_ct_level(h)
+
+    def __del__(self):
+        try:
+            if self.h:
+                lib().oc_ct_free(self.h)
+        except Exception:
+            pass
+
+    def export(self) -> np.ndarray:
+        N = self.ctx.N
+        out = np.empty((2, self.level + 1, N), dtype=np.uint64)
+        lib().oc_ct_export(self.ctx.h, self.h, _p(out, u64p))
+        return out
+
+
+class SchedError(RuntimeError):
+    pass
+
+
+class Oracle:
+    """CPU RNS-CKKS context: primes, secret, keys, and the evaluator ops."""
+
+    def __init__(self, prm: Params):
+        self.prm = prm
+        self.h = lib().oc_ctx_create(prm.log_n, prm.n_q, prm.q0_bits, prm.q_bits, prm.p_bits,
+                                     prm.dnum, ctypes.c_uint64(prm.seed))
+        if not self.h:
+            raise ValueError("bad parameters")
+        N, L, A, npr = (ctypes.c_int() for _ in range(4))
+        lib().oc_ctx_info(self.h, ctypes.byref(N), ctypes.byref(L), ctypes.byref(A), ctypes.byref(npr))
+        self.N, self.L, self.alpha, self.np = N.value, L.value, A.value, npr.value
+        self.primes = np.empty(self.np, dtype=np.uint64)
+        lib().oc_ctx_primes(self.h, _p(self.primes, u64p))
+        self.q = [int(v) for v in self.primes]
+        self.Delta = 2.0 ** prm.log2_scale
+        self.slots = self.N // 2
+
+    def __del__(self):
+        try:
+            lib().oc_ctx_free(self.h)
+        except Exception:
+            pass
+
+    # keys --------------------------------------------------------------
+    def keygen(self, relin=True, rot_logs: Sequence[int] = ()):
+        if relin:
+            lib().oc_keygen(self.h, 0)
+        for r in rot_logs:
+            lib().oc_keygen(self.h, 1 + int(r))
+
+    def keygen_cutmax(self):
+        self.keygen(True, range(int(math.log2(self.slots))))
+
+    def secret(self) -> np.ndarray:
+        s = np.empty(self.N, dtype=np.int8)
+        lib().oc_ctx_secret(self.h, _p(s, ctypes.POINTER(ctypes.c_int8)))
+        return s
+
+    @property
+    def nonce(self):
+        return lib().oc_get_nonce(self.h)
+
+    @nonce.setter
+    def nonce(self, v):
+        lib().oc_set_nonce(self.h, v)
+
+    # encryption --------------------------------------------------------
+    def encrypt_coeffs(self, m: np.ndarray, scale: float) -> Ct:
+        m = np.ascontiguousarray(m, dtype=np.int64)
+        assert m.size == self.N
+        return Ct(self, lib().oc_encrypt(self.h, _p(m, i64p)), scale)
+
+    def encrypt(self, z: np.ndarray, scale: Optional[float] = None) -> Ct:
+        scale = self.Delta if scale is None else scale
+        return self.encrypt_coeffs(encode(z, self.N, scale), scale)
+
+    def decrypt_coeffs(self, ct: Ct) -> np.ndarray:
+        out = np.empty(self.N, dtype=np.float64)
+        lib().oc_decrypt(self.h, ct.h, _p(out, dblp))
+        return out
+
+    def decrypt(self, ct: Ct) -> np.ndarray:
+        return decode(self.decrypt_coeffs(ct), self.N, ct.scale)
+
+    def import_ct(self, limbs: np.ndarray, scale: float) -> Ct:
+        limbs = np.ascontiguousarray(limbs, dtype=np.uint64)
+        level = limbs.shape[1] - 1
+        return Ct(self, lib().oc_ct_import(self.h, _p(limbs, u64p), level), scale)
+
+    # evaluator ops (scales per DESIGN.md "CKKS conventions") -----------
+    def add(self, a: Ct, b: Ct) -> Ct:
+        if a.level != b.level:
+            raise SchedError("add: level mismatch")
+        if abs(a.scale - b.scale) > 1e-9 * a.scale:
+            raise SchedError(f"add: scale mismatch {a.scale} {b.scale}")
+        return Ct(self, lib().oc_add(self.h, a.h, b.h), a.scale)
+
+    def sub(self, a: Ct, b: Ct) -> Ct:
+        if a.level != b.level:
+            raise SchedError("sub: level mismatch")
+        if abs(a.scale - b.scale) > 1e-9 * a.scale:
+            raise SchedError(f"sub: scale mismatch {a.scale} {b.scale}")
+        return Ct(self, lib().oc_sub(self.h, a.h, b.h), a.scale)
+
+    def mul_int(self, a: Ct, k: int) -> Ct:
+        return Ct(self, lib().oc_mul_int(self.h, a.h, int(k)), a.scale)
+
+    def add_const(self, a: Ct, c: float) -> Ct:
+        return Ct(self, lib().oc_add_const_int(self.h, a.h, llround(c * a.scale)), a.scale)
+
+    def drop(self, a: Ct, level: int) -> Ct:
+        if level == a.level:
+            return a
+        return Ct(self, lib().oc_drop(self.h, a.h, level), a.scale)
+
+    def rescale(self, a: Ct) -> Ct:
+        return Ct(self, lib().oc_rescale(self.h, a.h), a.scale / self.q[a.level])
+
+    def _const_K(self, a: Ct, kappa: float, s_want: float) -> int:
+        if a.level < 1:
+            raise SchedError("constant multiply needs a level")
+        q = float(self.q[a.level])
+        K = llround(((kappa * s_want) * q) / a.scale)
+        if K == 0 or abs(K) >= 2 ** 62:
+            raise SchedError(f"constant {kappa} not encodable (K={K})")
+        return K
+
+    def cm_exact(self, a: Ct, kappa: float, s_want: float) -> Ct:
+        """x * kappa with one rescale; the declared scale is the exact one."""
+        K = self._const_K(a, kappa, s_want)
+        q = float(self.q[a.level])
+        s = ((a.scale * float(K)) / q) / kappa
+        return Ct(self, lib().oc_mul_int_rescale(self.h, a.h, K), s)
+
+    def cm_target(self, a: Ct, kappa: float, s_target: float) -> Ct:
+        """x * kappa with one rescale, declared at the requested scale."""
+        K = self._const_K(a, kappa, s_target)
+        return Ct(self, lib().oc_mul_int_rescale(self.h, a.h, K), s_target)
+
+    def mul(self, a: Ct, b: Ct) -> Ct:
+        if a.level != b.level:
+            raise SchedError("mul: level mismatch")
+        q = float(self.q[a.level])
+        return Ct(self, lib().oc_mul(self.h, a.h, b.h), (a.scale * b.scale) / q)
+
+    def rotate(self, a: Ct, r: int) -> Ct:
+        return Ct(self, lib().oc_rotate(self.h, a.h, int(r)), a.scale)
+
+    # composite steps of Alg. 2 -------------------------------------------
+    def rotsum(self, x: Ct) -> Ct:
+        """Rotate-and-sum: x <- x + rot(x, 2^r), r = 0..log2(slots)-1 (Sec. 3.2)."""
+        for r in range(int(math.log2(self.slots))):
+            x = self.add(x, self.rotate(x, r))
+        return x
+
+    def sum_list(self, xs: List[Ct]) -> Ct:
+        acc = xs[0]
+        for x in xs[1:]:
+            acc = self.add(acc, x)
+        return acc
+
+    def power(self, y: Ct, p: int) -> Ct:
+        """y^p by repeated squaring; depth ceil(log2(p+1)) - ... (Sec. 3.2: log p mults)."""
+        if p < 1:
+            raise SchedError("p must be >= 1")
+        pw = [y]
+        for _ in range(1, p.bit_length()):
+            pw.append(self.mul(pw[-1], pw[-1]))
+        acc = None
+        for i in range(p.bit_length()):
+            if (p >> i) & 1:
+                if acc is None:
+                    acc = pw[i]
+                else:
+                    lv = min(acc.level, pw[i].level)
+                    acc = self.mul(self.drop(acc, lv), self.drop(pw[i], lv))
+        return acc
+
+    def invsqr(self, U: Ct, coef: Sequence[float], C: float, newton: int, s_final: float) -> Ct:
+        """Initial-guess polynomial sum_k coef[k] u^k (already scaled by C) plus
+        Newton steps h <- 1.5 h - (0.5/C^2) u h^3, landing at scale s_final."""
+        d = len(coef) - 1
+        q = self.q
+        lu = U.level
+        su = U.scale
+        S = s_final if newton == 0 else self.Delta
+        if d == 1:
+            H = self.add_const(self.cm_target(U, coef[1], S), coef[0])
+        elif d == 2:
+            U2 = self.mul(U, U)
+            T2 = self.cm_target(U2, coef[2], S)
+            T1 = self.cm_target(self.drop(U, lu - 1), coef[1], S)
+            H = self.add_const(self.add(T2, T1), coef[0])
+        elif d == 3:
+            U2 = self.mul(U, U)
+            s2 = U2.scale
+            sA = (S * float(q[lu - 1])) / s2
+            T3 = self.mul(self.cm_target(U, coef[3], sA), U2)
+            sB = (S * float(q[lu - 1])) / su
+            T2 = self.mul(self.cm_target(U, coef[2], sB), self.drop(U, lu - 1))
+            T1 = self.cm_target(self.drop(U, lu - 1), coef[1], S)
+            H = self.add_const(self.add(self.add(T3, T2), T1), coef[0])
+        elif d == 4:
+            U2 = self.mul(U, U)
+            s2 = U2.scale
+            sC = (S * float(q[lu - 2])) / s2
+            T4 = self.mul(self.cm_target(U2, coef[4], sC), self.drop(U2, lu - 2))
+            sD = (S * float(q[lu - 2])) / su
+            T3 = self.mul(self.cm_target(U2, coef[3], sD), self.drop(U, lu - 2))
+            T2 = self.cm_target(self.drop(U2, lu - 2), coef[2], S)
+            T1 = self.cm_target(self.drop(U, lu - 2), coef[1], S)
+            H = self.add_const(self.add(self.add(self.add(T4, T3), T2), T1), coef[0])
+        else:
+            raise SchedError("initial-guess degree must be 1..4")
+        for it in range(newton):
+            St = s_final if it == newton - 1 else self.Delta
+            lh, sh = H.level, H.scale
+            G2 = self.mul(H, H)
+            sA = (((St * float(q[lh])) * float(q[lh - 1])) / sh) / G2.scale
+            A = self.drop(self.cm_target(U, -0.5 / (C * C), sA), lh)
+            B = self.mul(A, H)
+            T = self.mul(B, G2)
+            L1 = self.drop(self.cm_target(H, 1.5, St), lh - 2)
+            H = self.add(T, L1)
+        return H
+
+
+def invsqr_depth(degree: int, newton: int) -> int:
+    return {1: 1, 2: 2, 3: 2, 4: 3}[degree] + 2 * newton
+
+
+@dataclass
+class HECfg:
+    """Schedule constants of the encrypted CutMax for one request."""
+    T: int
+    p: Sequence[int]
+    c: Sequence[float]
+    v_lo: Sequence[float]
+    v_hi: Sequence[float]
+    coef: Sequence[Sequence[float]]   # per iteration, power basis in u = var/v_hi, times sqrt(n)/c
+    newton: int = 0
+    sum_lo: float = 1.0                # bounds of mean(y^(T)) = sum/n
+    sum_hi: float = 3.0
+    gold_d: int = 3
+
+    def levels_needed(self) -> int:
+        lv = 0
+        for t in range(self.T):
+            lv += 2 + invsqr_depth(len(self.coef[t]) - 1, self.newton) + 1 + (int(self.p[t]).bit_length() - 1) \
+                + (1 if bin(int(self.p[t])).count("1") > 1 else 0)
+        return lv + self.gold_d + 3
+
+
+def cutmax_he(O: Oracle, Y: List[Ct], cfg: HECfg, rotsum_cache=None) -> List[Ct]:
+    """Alg. 2 on one request whose packed vector spans len(Y) ciphertexts."""
+    a = len(Y)
+    n = a * O.slots
+    for t in range(cfg.T):
+        S = O.rotsum(O.sum_list(Y))
+        D = [O.sub(O.mul_int(y, n), S) for y in Y]
+        kE = 1.0 / (float(n) * math.sqrt(float(n) * cfg.v_hi[t]))
+        E = [O.cm_exact(d, kE, O.Delta) for d in D]
+        F = [O.mul(e, e) for e in E]
+        U = O.rotsum(O.sum_list(F))
+        C = math.sqrt(float(n)) / cfg.c[t]
+        lh = U.level - invsqr_depth(len(cfg.coef[t]) - 1, cfg.newton)
+        if lh < 1:
+            raise SchedError("chain too short")
+        sE = E[0].scale
+        S_H = (O.Delta * float(O.q[lh])) / sE
+        H = O.invsqr(U, cfg.coef[t], C, cfg.newton, S_H)
+        Yn = [O.add_const(O.mul(O.drop(e, H.level), H), 1.0) for e in E]
+        Y = [O.power(y, int(cfg.p[t])) for y in Yn]
+    S = O.rotsum(O.sum_list(Y))
+    B = cfg.sum_hi * float(n)
+    X = O.cm_exact(S, 1.0 / B, O.Delta)
+    E0 = O.add_const(O.mul_int(X, -1), 1.0)
+    P = O.add_const(E0, 1.0)
+    Ei = E0
+    for _ in range(cfg.gold_d):
+        Ei = O.mul(Ei, Ei)
+        P = O.mul(O.drop(P, Ei.level), O.add_const(Ei, 1.0))
+    Z = []
+    for y in Y:
+        yb = O.cm_exact(y, 1.0 / B, O.Delta)
+        Z.append(O.mul(O.drop(yb, P.level), P))
+    return Z
+
+
+def topp_he(O: Oracle, X: List[Ct], G: List[Ct], temperature: float, cfg: HECfg,
+            prescaled: bool = False) -> List[Ct]:
+    """Alg. 3 server side: CutMax(X + tau*G) (equal to CutMax(X/tau + G))."""
+    if prescaled:
+        Xt = [O.add(x, g) for x, g in zip(X, G)]
+    else:
+        Gs = [O.cm_target(g, temperature, x.scale) for x, g in zip(X, G)]
+        Xt = [O.add(O.drop(x, gs.level), gs) for x, gs in zip(X, Gs)]
+    return cutmax_he(O, Xt, cfg)

@@ -1,0 +1,195 @@
+"""Pins of the CPU RNS-CKKS oracle (O2) against textbook definitions and the CKKS
+properties the paper relies on (Sec. 2.1 correctness/homomorphism; Sec. 3.2 rotations)."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import ckks
+from oracle.cutmax_fp64 import MirrorCfg, chebyshev_invsqrt, cutmax_exact, cutmax_mirror, slot_layout
+from workloads import random_residues, toy_logits
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+TOY = ckks.Params(log_n=10, n_q=8, q0_bits=40, q_bits=30, p_bits=40, dnum=3, log2_scale=30, seed=3)
+CFG1 = ckks.Params(log_n=12, n_q=36, q0_bits=40, q_bits=30, p_bits=40, dnum=3, log2_scale=30, seed=7)
+
+
+@pytest.fixture(scope="module")
+def toy():
+    O = ckks.Oracle(TOY)
+    O.keygen(True, range(int(math.log2(O.slots))))
+    return O
+
+
+def test_philox_known_answers():
+    with open(os.path.join(GOLD, "philox_kat.txt")) as f:
+        for ln in f:
+            if ln.startswith("#") or not ln.strip():
+                continue
+            v = [int(t, 16) for t in ln.split()]
+            assert ckks.philox4x32_10(v[0:4], v[4:6]) == v[6:10]
+
+
+def _is_prime_trial(n):
+    # independent check: Fermat with many bases plus small-factor trial division
+    if any(n % p == 0 for p in range(2, 2000)):
+        return False
+    return all(pow(a, n - 1, n) == 1 for a in (2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41))
+
+
+def test_primes_are_ntt_friendly():
+    O = ckks.Oracle(CFG1)
+    assert O.L == 35 and O.alpha == 12 and len(set(O.q)) == O.np
+    for i, q in enumerate(O.q):
+        bits = 40 if (i == 0 or i > O.L) else 30
+        assert q < 2 ** bits and q > 2 ** (bits - 1)
+        assert q % (2 * O.N) == 1
+        assert _is_prime_trial(q)
+
+
+@pytest.mark.parametrize("log_n", [3, 4, 6])
+def test_ring_mul_matches_schoolbook(log_n):
+    """NTT-based negacyclic product == schoolbook convolution mod (X^N + 1, q)."""
+    prm = ckks.Params(log_n=log_n, n_q=2, q0_bits=40, q_bits=30, p_bits=40, dnum=1, log2_scale=20)
+    O = ckks.Oracle(prm)
+    N = O.N
+    for pi in range(O.np):
+        q = O.q[pi]
+        a, b = random_residues(100 + pi, [q, q], N)
+        a, b = np.ascontiguousarray(a), np.ascontiguousarray(b)
+        c1 = np.empty(N, dtype=np.uint64)
+        c2 = np.empty(N, dtype=np.uint64)
+        ckks.lib().oc_ring_mul(O.h, pi, a.ctypes.data_as(ckks.u64p), b.ctypes.data_as(ckks.u64p),
+                               c1.ctypes.data_as(ckks.u64p))
+        ckks.lib().oc_schoolbook(a.ctypes.data_as(ckks.u64p), b.ctypes.data_as(ckks.u64p),
+                                 c2.ctypes.data_as(ckks.u64p), N, q)
+        # independent pure-Python schoolbook as well
+        ai, bi = [int(v) for v in a], [int(v) for v in b]
+        ref = [0] * N
+        for i in range(N):
+            for j in range(N):
+                k = i + j
+                if k < N:
+                    ref[k] += ai[i] * bi[j]
+                else:
+                    ref[k - N] -= ai[i] * bi[j]
+        ref = [v % q for v in ref]
+        assert [int(v) for v in c2] == ref
+        assert [int(v) for v in c1] == ref
+
+
+def test_encode_decode_routes_agree():
+    N, scale = 1024, 2.0 ** 30
+    z = np.random.default_rng(0).uniform(-5, 5, N // 2)
+    m1 = ckks.encode_direct(z, N, scale)
+    m2 = ckks.encode_fft(z, N, scale)
+    assert np.abs(m1 - m2).max() <= 1
+    np.testing.assert_allclose(ckks.decode_direct(m1, N, scale), z, atol=1e-7)
+    np.testing.assert_allclose(ckks.decode_fft(m1, N, scale), z, atol=1e-7)
+    # the constant polynomial c*scale decodes to c in every slot
+    m = np.zeros(N)
+    m[0] = 3 * scale
+    np.testing.assert_allclose(ckks.decode_direct(m, N, scale), 3.0, atol=1e-12)
+
+
+def test_secret_is_ternary(toy):
+    s = toy.secret()
+    assert set(np.unique(s).tolist()) <= {-1, 0, 1}
+    frac = np.bincount(s + 1) / s.size
+    assert np.all(np.abs(frac - 1 / 3) < 0.06)
+
+
+def test_decrypt_encrypt_identity(toy):
+    z = np.random.default_rng(1).uniform(-10, 10, toy.slots)
+    ct = toy.encrypt(z)
+    assert ct.level == toy.L
+    np.testing.assert_allclose(toy.decrypt(ct), z, atol=1e-5)
+    # fresh encryptions of the same message differ (nonce advances)
+    ct2 = toy.encrypt(z)
+    assert not np.array_equal(ct.export(), ct2.export())
+
+
+def test_homomorphic_add_mul_rescale_rotate(toy):
+    rng = np.random.default_rng(2)
+    x = rng.uniform(-2, 2, toy.slots)
+    y = rng.uniform(-2, 2, toy.slots)
+    cx, cy = toy.encrypt(x), toy.encrypt(y)
+    np.testing.assert_allclose(toy.decrypt(toy.add(cx, cy)), x + y, atol=1e-5)
+    np.testing.assert_allclose(toy.decrypt(toy.sub(cx, cy)), x - y, atol=1e-5)
+    np.testing.assert_allclose(toy.decrypt(toy.mul_int(cx, -7)), -7 * x, atol=1e-4)
+    np.testing.assert_allclose(toy.decrypt(toy.add_const(cx, 1.5)), x + 1.5, atol=1e-5)
+    m = toy.mul(cx, cy)
+    assert m.level == toy.L - 1
+    np.testing.assert_allclose(toy.decrypt(m), x * y, atol=1e-4)
+    r = toy.rescale(toy.mul_int(cx, 1 << 30))
+    assert r.level == toy.L - 1 and r.scale == toy.Delta / toy.q[toy.L]
+    np.testing.assert_allclose(toy.decrypt(r) / 2.0 ** 30, x, atol=1e-4)
+    for rr in range(int(math.log2(toy.slots))):
+        np.testing.assert_allclose(toy.decrypt(toy.rotate(cx, rr)), np.roll(x, -(1 << rr)), atol=1e-4)
+    ce = toy.cm_exact(cx, 0.37, toy.Delta)
+    np.testing.assert_allclose(toy.decrypt(ce), 0.37 * x, atol=1e-4)
+    ct_ = toy.cm_target(cx, -1.25, 2.0 ** 29)
+    assert ct_.scale == 2.0 ** 29
+    np.testing.assert_allclose(toy.decrypt(ct_), -1.25 * x, atol=1e-4)
+
+
+def test_rotate_and_mul_at_low_levels(toy):
+    """Partial key-switch digits below the top level still switch keys correctly."""
+    x = np.random.default_rng(3).uniform(-1, 1, toy.slots)
+    cx = toy.encrypt(x)
+    for lv in (1, 2, 3, 5):
+        d = toy.drop(cx, lv)
+        np.testing.assert_allclose(toy.decrypt(toy.rotate(d, 2)), np.roll(x, -4), atol=1e-4)
+        np.testing.assert_allclose(toy.decrypt(toy.mul(d, d)), x * x, atol=1e-4)
+
+
+def test_rotsum(toy):
+    x = np.random.default_rng(4).uniform(-1, 1, toy.slots)
+    s = toy.decrypt(toy.rotsum(toy.encrypt(x)))
+    np.testing.assert_allclose(s, x.sum(), atol=1e-3)
+
+
+def test_tampered_limb_is_detected(toy):
+    x = np.random.default_rng(5).uniform(-1, 1, toy.slots)
+    ct = toy.encrypt(x)
+    limbs = ct.export()
+    limbs[0, 0, 10] = (int(limbs[0, 0, 10]) + 12345) % toy.q[0]
+    bad = toy.import_ct(limbs, ct.scale)
+    assert np.abs(toy.decrypt(bad) - x).max() > 1e-3
+
+
+def _cfg1_schedule(O, y, T=4):
+    n = y.size
+    p, c = [3] * T, [5.0] * T
+    vlo, vhi = [0.5, 0.25, 0.3, 0.6][:T], [2.0, 0.75, 3.0, 128.0][:T]
+    coef = [chebyshev_invsqrt(vlo[t] / vhi[t], 3, math.sqrt(n) / c[t]) for t in range(T)]
+    he = ckks.HECfg(T=T, p=p, c=c, v_lo=vlo, v_hi=vhi, coef=coef, sum_lo=1.0, sum_hi=3.0, gold_d=3)
+    mc = MirrorCfg(T=T, p=p, c=c, v_hi=vhi, v_lo=vlo, coef=coef, B=3.0 * n, gold_d=3, sum_lo=1.0 * n)
+    return he, mc
+
+
+@pytest.mark.slow
+def test_he_cutmax_matches_mirror_config1():
+    """Alg. 2 on the oracle CKKS: decrypted Z within 1e-3 of the FP64 mirror, argmax recovered."""
+    O = ckks.Oracle(CFG1)
+    O.keygen_cutmax()
+    x = toy_logits(11)
+    y, a, rep = slot_layout(x, O.slots)
+    he, mc = _cfg1_schedule(O, y)
+    assert he.levels_needed() <= O.L
+    Z = ckks.cutmax_he(O, [O.encrypt(y)], he)
+    dz = O.decrypt(Z[0])
+    assert np.abs(dz - cutmax_mirror(y, mc)).max() < 1e-3
+    assert int(np.argmax(dz[:x.size])) == int(np.argmax(x))
+    assert abs(dz.sum() - 1) < 1e-2
+    # and the exact Algorithm 1 picks the same index
+    assert int(np.argmax(cutmax_exact(y, 3, 5.0, 4))) == int(np.argmax(x))
+
+
+def test_schedule_rejects_short_chain(toy):
+    x = toy_logits(1, 512)
+    he, _ = _cfg1_schedule(toy, x)
+    with pytest.raises(ckks.SchedError):
+        ckks.cutmax_he(toy, [toy.encrypt(x)], he)

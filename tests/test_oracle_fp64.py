@@ -1,0 +1,189 @@
+"""Pins of the float64 CutMax oracle (O1) against what the paper and mathematics fix."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle.cutmax_fp64 import (MirrorCfg, Trace, beta_alpha, beta_noise, chebyshev_invsqrt,
+                                cutmax_exact, cutmax_mirror, delta_gap, gap_ratio,
+                                goldschmidt_factor, newton_invsqrt_step, nucleus_argmax,
+                                nucleus_set, poly_eval, semi_standardize, slot_layout, tmin)
+from workloads import llm_logits, toy_logits, uniform_noise
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rows(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return [ln.split() for ln in f if ln.strip() and not ln.startswith("#")]
+
+
+def test_table4_tmin_reproduced():
+    """App. E table: T_min for n=32768, p=13, c=5 from the convergence theorem."""
+    for d, k10, k100 in _rows("table4_tmin.txt"):
+        assert tmin(32768, 13, 5.0, float(d), 10) == int(k10)
+        assert tmin(32768, 13, 5.0, float(d), 100) == int(k100)
+
+
+def test_n2_closed_form_any_T():
+    row = [r for r in _rows("cutmax_closed_forms.txt") if r[0] == "n2"][0]
+    want = np.array([float(row[3]), float(row[4])])
+    rng = np.random.default_rng(3)
+    for T in (1, 2, 3, 5):
+        a, b = sorted(rng.normal(size=2) * 7)[::-1]
+        Z = cutmax_exact(np.array([a, b]), 3, 5.0, T)
+        np.testing.assert_allclose(Z, want, rtol=0, atol=1e-15)
+        np.testing.assert_allclose(Z, [27 / 35, 8 / 35], atol=1e-15)
+
+
+@pytest.mark.parametrize("n", [1024, 32768])
+def test_spike_fixed_point(n):
+    row = [r for r in _rows("cutmax_closed_forms.txt") if r[0] == "spike" and r[1] == f"n={n}"][0]
+    want = float(row[4])
+    x = np.zeros(n)
+    x[17] = 3.5
+    for T in (1, 2, 4):
+        Z = cutmax_exact(x, 3, 5.0, T)
+        assert abs(Z[17] - want) < 5e-7
+        assert int(np.argmax(Z)) == 17
+
+
+def test_sum_to_one_and_argmax():
+    for s in range(5):
+        x = llm_logits(s, 4000)
+        Z = cutmax_exact(x, 3, 5.0, 3)
+        assert abs(Z.sum() - 1) < 1e-12
+        assert int(np.argmax(Z)) == int(np.argmax(x))
+
+
+def test_semi_standardization_order_and_gap():
+    """Lemma (S_c strictly increasing) and Lemma (delta-gap -> delta/c gap)."""
+    rng = np.random.default_rng(1)
+    for _ in range(10):
+        y = rng.normal(size=300) * rng.uniform(0.1, 10)
+        for c in (1.0, 3.0, 5.0, 27.0):
+            z = semi_standardize(y, c)
+            assert np.array_equal(np.argsort(z), np.argsort(y))
+            d = delta_gap(y)
+            i1, i2 = np.argsort(y)[-1], np.argsort(y)[-2]
+            assert z[i1] - z[i2] >= d / c - 1e-12
+
+
+def test_affine_invariance_and_permutation():
+    rng = np.random.default_rng(2)
+    x = rng.normal(size=500)
+    Z = cutmax_exact(x, 3, 5.0, 3)
+    np.testing.assert_allclose(cutmax_exact(4.2 * x - 17.0, 3, 5.0, 3), Z, atol=1e-13)
+    perm = rng.permutation(500)
+    np.testing.assert_allclose(cutmax_exact(x[perm], 3, 5.0, 3), Z[perm], atol=1e-15)
+
+
+def test_per_step_gap_growth_bound():
+    """Lemma (unconditional growth): z*/z** >= 1 + delta/(c + sqrt n) when all z > 0,
+    with delta the measured gap of the current iterate."""
+    for s in range(8):
+        y = llm_logits(s, 2000)
+        n = y.size
+        for t in range(3):
+            c = 5.0
+            z = semi_standardize(y, c)
+            assert z.min() > 0
+            d = delta_gap(y)
+            i1, i2 = np.argsort(y)[-1], np.argsort(y)[-2]
+            assert z[i1] / z[i2] >= 1 + d / (c + math.sqrt(n)) - 1e-12
+            y = z ** 3
+            # variance of z is exactly 1/c^2, hence Var(z^p) >= 1/c^2 (derived from Def. S_c)
+            assert abs(z.var() - 1 / c ** 2) < 1e-12
+            assert y.var() >= 1 / c ** 2
+
+
+def test_gamma_monotone_for_positive_iterates():
+    y = llm_logits(4, 3000)
+    tr = Trace()
+    cutmax_exact(y, 3, 5.0, 4, tr)
+    g = [gap_ratio(v) for v in tr.ys]
+    assert all(b >= a for a, b in zip(g, g[1:]))
+
+
+def test_goldschmidt_closed_form():
+    """prod_{i=0}^d (1 + e^(2^i)) = (1 - e^(2^(d+1))) / (1 - e)  (App. B.1)."""
+    for e in np.linspace(-0.9, 0.95, 37):
+        for d in range(6):
+            want = (1 - e ** (2 ** (d + 1))) / (1 - e)
+            assert abs(goldschmidt_factor(e, d) - want) < 1e-12 * max(1, abs(want))
+    x = 0.3
+    assert abs(goldschmidt_factor(1 - x, 6) * x - 1) < 1e-9
+
+
+def test_newton_error_recursion():
+    """y = (1+eps)/sqrt(x) -> next relative error -(1.5 eps^2 + 0.5 eps^3)."""
+    for x in (0.05, 0.5, 1.0):
+        for eps in (-0.3, -0.05, 0.01, 0.2):
+            h = (1 + eps) / math.sqrt(x)
+            h2 = newton_invsqrt_step(h, x, 1.0)
+            got = h2 * math.sqrt(x) - 1
+            assert abs(got + (1.5 * eps ** 2 + 0.5 * eps ** 3)) < 1e-14
+    # with a folded constant C: h ~ C/sqrt(u)
+    C, u = 36.2, 0.4
+    h = 1.1 * C / math.sqrt(u)
+    assert abs(newton_invsqrt_step(h, u, C) * math.sqrt(u) / C - 1 + (1.5 * 0.01 + 0.5 * 0.001)) < 1e-12
+
+
+def test_chebyshev_interpolates_at_nodes():
+    for ulo in (0.05, 0.4):
+        for d in (2, 3, 4):
+            a = chebyshev_invsqrt(ulo, d, 2.0)
+            k = np.arange(d + 1)
+            u = 0.5 * (1 + ulo) + 0.5 * (1 - ulo) * np.cos(np.pi * (k + 0.5) / (d + 1))
+            np.testing.assert_allclose(poly_eval(a, u), 2.0 / np.sqrt(u), rtol=1e-11)
+    a = chebyshev_invsqrt(0.5, 4)
+    u = np.linspace(0.5, 1, 101)
+    assert np.abs(poly_eval(a, u) * np.sqrt(u) - 1).max() < 2e-4
+
+
+def test_mirror_equals_exact_when_approximations_are_exact():
+    """With many Newton steps and a long Goldschmidt product the mirror converges to Alg. 1."""
+    x = toy_logits(5, 256)
+    y, a, rep = slot_layout(x, 512)
+    n = y.size
+    T, p, c = 3, [3] * 3, [5.0] * 3
+    tr = Trace()
+    Ze = cutmax_exact(y, p, c, T, tr)
+    vhi = [v * 1.5 for v in tr.var]
+    vlo = [v * 0.7 for v in tr.var]
+    coef = [chebyshev_invsqrt(vlo[t] / vhi[t], 3, math.sqrt(n) / c[t]) for t in range(T)]
+    S = tr.ys[-1].sum()
+    cfg = MirrorCfg(T=T, p=p, c=c, v_hi=vhi, v_lo=vlo, coef=coef, newton=4, B=1.5 * S,
+                    gold_d=7, sum_lo=0.5 * S)
+    Zm = cutmax_mirror(y, cfg)
+    np.testing.assert_allclose(Zm, Ze, atol=1e-12)
+
+
+def test_slot_layout():
+    y, a, rep = slot_layout(np.arange(4.0), 8)
+    assert rep and a == 1 and list(y) == [0, 1, 2, 3, 0, 1, 2, 3]
+    y, a, rep = slot_layout(np.arange(10.0), 8, pad=-1)
+    assert not rep and a == 2 and y.size == 16 and y[10] == -1 and y[9] == 9
+    x = toy_logits(0)
+    y, a, rep = slot_layout(x, 2048)
+    assert abs(y.mean() - x.mean()) < 1e-14 and abs(y.var() - x.var()) < 1e-13
+
+
+def test_beta_lemma_monte_carlo():
+    """Lemma "Beta": G = U^(1/alpha), alpha = ln(1-p)/ln p gives P(G > p) = p."""
+    for top_p in (0.9, 0.5, 0.75):
+        al = beta_alpha(top_p)
+        assert abs(top_p ** al - (1 - top_p)) < 1e-14
+        g = beta_noise(uniform_noise(42, 400000), al)
+        frac = float((g > top_p).mean())
+        assert abs(frac - top_p) < 4 * math.sqrt(top_p * (1 - top_p) / 400000)
+    assert abs(beta_alpha(0.9) - 21.854345326782834) < 1e-12
+
+
+def test_nucleus_helpers():
+    x = np.array([5.0, 4.9, 1.0, -3.0])
+    s = nucleus_set(x, 0.9)
+    assert set(s.tolist()) == {0, 1}
+    assert nucleus_argmax(x, np.zeros(4), 0.8) == 0
+    assert nucleus_argmax(x, np.array([0, 0.2, 0, 0]), 1.0) == 1
