@@ -1,0 +1,197 @@
+/*
+ * he.h -- C ABI of the MI355X encrypted-CutMax library (libcutmax_he.so).
+ *
+ * The operation is CutMax, the HE-friendly argmax of arXiv 2509.08383
+ * (Sec. 3.1, Alg. 1; encrypted form Sec. 3.2, Alg. 2), and the one-shot
+ * nucleus sampler built on it (Sec. 3.3, Alg. 3), evaluated over RNS-CKKS
+ * ciphertexts.  The client encrypts its logit vector X, the server returns
+ * an encrypted one-hot approximation Z of argmax(X), and only the client
+ * decrypts (Sec. 1 and App. A threat model).
+ *
+ * Conventions shared by every call:
+ *   - Every call returns HE_OK (0) or a negative he_status; he_last_error()
+ *     gives a thread-local message for the last failure on this thread.
+ *   - Handles are opaque; the caller owns every handle it receives and frees
+ *     it (he_ct_free, he_ctx_destroy).  A context must outlive its
+ *     ciphertexts.  One context = one HIP stream; calls on one context are not
+ *     thread-safe.
+ *   - Pointer arguments named x, out, limbs, m, g are HOST memory owned by the
+ *     caller.  Ciphertexts live in device memory inside their handles.
+ *   - Parameters outside the documented ranges return HE_EINVAL; device
+ *     failures HE_EDEVICE; allocation failures HE_ENOMEM; a schedule that
+ *     needs more levels than the ciphertext has HE_EDEPTH; a constant that
+ *     cannot be encoded HE_ERANGE; mismatched handles HE_ESTATE.
+ */
+#ifndef CUTMAX_HE_H
+#define CUTMAX_HE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HE_OK = 0,
+    HE_EINVAL = -1,
+    HE_ENOMEM = -2,
+    HE_EDEVICE = -3,
+    HE_EDEPTH = -4,
+    HE_ERANGE = -5,
+    HE_ESTATE = -6
+} he_status;
+
+typedef struct he_ctx he_ctx;
+typedef struct he_ct he_ct;
+
+/* CKKS parameters.  log_n in {12, 16}; n_q >= 2 Q primes (levels = n_q - 1);
+ * bit sizes in [20, 49] (the kernels compute modulo these primes in the FP64
+ * pipe, exact below 2^52); dnum >= 1 key-switching digits; log2_scale is the
+ * encoding scale Delta = 2^log2_scale; seed keys every random draw
+ * (Philox4x32-10).  device: HIP device ordinal.  stream: a hipStream_t the
+ * library enqueues on (for example PyTorch's current stream), or NULL for a
+ * stream the library creates. */
+typedef struct {
+    uint32_t log_n;
+    uint32_t n_q;
+    uint32_t q0_bits;
+    uint32_t q_bits;
+    uint32_t p_bits;
+    uint32_t dnum;
+    double log2_scale;
+    uint64_t seed;
+    int device;
+    void *stream;
+} he_params;
+
+/* Hyper-parameters of one CutMax call (Alg. 1 inputs p, c, T; Sec. 4.2 uses
+ * per-iteration p and c).  All arrays are host memory of length T.
+ *   var_lo/var_hi: declared domain of the variance at each iteration; the
+ *     inverse square root is evaluated on u = var/var_hi (Sec. 3.2, (ii)).
+ *   init_degree/init_coef: power-basis coefficients g_0..g_d (d = init_degree
+ *     in 1..4) of the initial guess g(u) ~ u^(-1/2), T rows of d+1 values.
+ *     NULL: the library interpolates u^(-1/2) at Chebyshev nodes on
+ *     [var_lo/var_hi, 1].
+ *   newton_steps: Newton refinements h <- 1.5h - 0.5 u h^3 (2 levels each).
+ *   sum_lo/sum_hi: declared bounds of mean(Y^(T)); the final inverse runs
+ *     Goldschmidt's product (App. B.1) with gold_d squarings on
+ *     sum/(sum_hi * n).
+ *   flags: HE_NOISE_PRESCALED (he_topp_sample: the noise already carries the
+ *     temperature). */
+typedef struct {
+    uint32_t T;
+    const uint32_t *p;
+    const double *c;
+    const double *var_lo;
+    const double *var_hi;
+    uint32_t init_degree;
+    const double *init_coef;
+    uint32_t newton_steps;
+    double sum_lo;
+    double sum_hi;
+    uint32_t gold_d;
+    uint32_t flags;
+} he_cutmax_cfg;
+
+#define HE_NOISE_PRESCALED 1u
+
+/* Context: prime chain, twiddle and basis-conversion tables, secret key, and
+ * the relinearisation and rotation keys (rotation by 2^r slots for every r <
+ * log2(slots)), generated on the device. */
+int he_ctx_create(const he_params *prm, he_ctx **out);
+void he_ctx_destroy(he_ctx *ctx);
+
+/* Context facts: ring degree, slot count, top level, alpha (P primes) and the
+ * prime chain q_0..q_L, p_0..p_{alpha-1} (primes may be NULL; else capacity
+ * n_q + alpha entries). */
+int he_ctx_info(const he_ctx *ctx, uint32_t *N, uint32_t *slots, uint32_t *L, uint32_t *alpha,
+                uint64_t *primes);
+
+/* Client: encrypt n doubles (Sec. 2.1).  n <= slots with slots % n == 0 is
+ * replicated; otherwise padded with `pad` to a = ceil(n/slots) ciphertexts.
+ * The handle is at the top level with scale Delta. */
+int he_encrypt(he_ctx *ctx, const double *x, size_t n, double pad, he_ct **out);
+
+/* Client: encrypt already-encoded integer plaintexts m[a][N] at `scale`
+ * (bit-exact tests feed one encoded plaintext to every implementation).
+ * n is the logical length recorded in the handle. */
+int he_encrypt_coeffs(he_ctx *ctx, const int64_t *m, uint32_t a, double scale, size_t n,
+                      he_ct **out);
+
+/* Client: decrypt and decode the first n logical values (Sec. 2.1). */
+int he_decrypt(he_ctx *ctx, const he_ct *ct, double *out, size_t n);
+
+/* Server: CutMax over `batch` requests (Alg. 2).  in[r] may hold 1 or more
+ * ciphertexts; all requests advance level by level together.  out[r] receives
+ * a new handle with the same packing as in[r]. */
+int he_cutmax(he_ctx *ctx, he_ct *const *in, size_t batch, const he_cutmax_cfg *cfg, he_ct **out);
+
+/* Server: one-shot nucleus sampling (Alg. 3): CutMax(X + temperature * G),
+ * G the client's encrypted Beta(alpha,1) noise (see he_topp_noise). */
+int he_topp_sample(he_ctx *ctx, he_ct *const *logits, he_ct *const *noise, size_t batch,
+                   double top_p, double temperature, const he_cutmax_cfg *cfg, he_ct **out);
+
+/* Client helper (Alg. 3 lines 1-4): g[i] = u[i]^(1/alpha),
+ * alpha = ln(1 - top_p)/ln(top_p), from the caller's uniform draws u. */
+int he_topp_noise(double top_p, const double *u, size_t n, double *g);
+
+void he_ct_free(he_ct *ct);
+const char *he_last_error(void);
+
+/* Ciphertext facts: ciphertext count a, level, scale, logical length. */
+int he_ct_info(const he_ct *ct, uint32_t *a, uint32_t *level, double *scale, size_t *n);
+
+/* Coefficient-domain canonical limbs [a][2][level+1][N] (u64) of a handle;
+ * cap is the capacity of `limbs` in words. */
+int he_ct_export(he_ctx *ctx, const he_ct *ct, uint64_t *limbs, size_t cap);
+
+/* Import coefficient-domain limbs [a][2][level+1][N]. */
+int he_ct_import(he_ctx *ctx, const uint64_t *limbs, uint32_t a, uint32_t level, double scale,
+                 size_t n, he_ct **out);
+
+/* Evaluator primitives (single ciphertexts, a == 1), each the CKKS operation
+ * the encrypted schedule is made of (scales as documented in the design):
+ *   he_add, he_sub        element-wise (Sec. 2.1)
+ *   he_mul_int            multiply by an integer
+ *   he_add_const          add a real constant to every slot
+ *   he_mul                tensor, relinearise, rescale
+ *   he_rescale            divide by the last prime
+ *   he_cmul               multiply by a real constant then rescale; exact != 0
+ *                         declares the exact scale, else scale s_want
+ *   he_rotate             rotate slots left by 2^r (Sec. 3.2)
+ *   he_rotsum             rotate-and-sum over every slot (Sec. 3.2, App. D)
+ *   he_drop               drop limbs down to `level` */
+int he_add(he_ctx *ctx, const he_ct *a, const he_ct *b, he_ct **out);
+int he_sub(he_ctx *ctx, const he_ct *a, const he_ct *b, he_ct **out);
+int he_mul_int(he_ctx *ctx, const he_ct *a, int64_t k, he_ct **out);
+int he_add_const(he_ctx *ctx, const he_ct *a, double c, he_ct **out);
+int he_mul(he_ctx *ctx, const he_ct *a, const he_ct *b, he_ct **out);
+int he_rescale(he_ctx *ctx, const he_ct *a, he_ct **out);
+int he_cmul(he_ctx *ctx, const he_ct *a, double kappa, double s_want, int exact, he_ct **out);
+int he_rotate(he_ctx *ctx, const he_ct *a, uint32_t r, he_ct **out);
+int he_rotsum(he_ctx *ctx, const he_ct *a, he_ct **out);
+int he_drop(he_ctx *ctx, const he_ct *a, uint32_t level, he_ct **out);
+
+/* Measurement hooks.
+ * he_bench_ntt: `iters` forward+inverse negacyclic NTTs over `vectors`
+ *   resident limb vectors (each N words, cycling over the primes); *ms_fwd and
+ *   *ms_inv receive the average device time of one forward / one inverse
+ *   transform of the whole batch (HIP events on the context stream).
+ * he_last_cutmax_ms: device time of the last he_cutmax/he_topp_sample call.
+ * he_sync: wait for the context stream. */
+int he_bench_ntt(he_ctx *ctx, uint32_t vectors, uint32_t iters, double *ms_fwd, double *ms_inv);
+int he_last_cutmax_ms(const he_ctx *ctx, double *ms);
+int he_sync(he_ctx *ctx);
+
+/* Options: HE_OPT_GRAPH (capture he_cutmax in a HIP graph and replay it for
+ * repeated calls of the same shape), HE_OPT_NTT_VARIANT (0 = autotune, k > 0
+ * forces variant k). */
+#define HE_OPT_GRAPH 1
+#define HE_OPT_NTT_VARIANT 2
+int he_set_option(he_ctx *ctx, int option, int64_t value);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -386,7 +386,7 @@ class Oracle:
         return acc
 
     def invsqr(self, U: Ct, coef: Sequence[float], C: float, newton: int, s_final: float) -> Ct:
-        """Initial-guess polynomial sum_k coef[k] u^k (already scaled by C) plus
+        """Initial-guess polynomial sum_k coef[k] u^k (coefficients already times C) plus
         Newton steps h <- 1.5 h - (0.5/C^2) u h^3, landing at scale s_final."""
         d = len(coef) - 1
         q = self.q
@@ -446,7 +446,7 @@ class HECfg:
     c: Sequence[float]
     v_lo: Sequence[float]
     v_hi: Sequence[float]
-    coef: Sequence[Sequence[float]]   # per iteration, power basis in u = var/v_hi, times sqrt(n)/c
+    coef: Sequence[Sequence[float]]   # per iteration, power basis of g(u) ~ u^(-1/2), u = var/v_hi
     newton: int = 0
     sum_lo: float = 1.0                # bounds of mean(y^(T)) = sum/n
     sum_hi: float = 3.0
@@ -477,7 +477,7 @@ def cutmax_he(O: Oracle, Y: List[Ct], cfg: HECfg, rotsum_cache=None) -> List[Ct]
             raise SchedError("chain too short")
         sE = E[0].scale
         S_H = (O.Delta * float(O.q[lh])) / sE
-        H = O.invsqr(U, cfg.coef[t], C, cfg.newton, S_H)
+        H = O.invsqr(U, [g * C for g in cfg.coef[t]], C, cfg.newton, S_H)
         Yn = [O.add_const(O.mul(O.drop(e, H.level), H), 1.0) for e in E]
         Y = [O.power(y, int(cfg.p[t])) for y in Yn]
     S = O.rotsum(O.sum_list(Y))

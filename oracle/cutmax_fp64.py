@@ -146,8 +146,8 @@ class MirrorCfg:
     c: Sequence[float]
     v_hi: Sequence[float]          # invsqr domain upper bound per iteration (variance units)
     v_lo: Sequence[float]          # lower bound (checked, used for the default fit)
-    coef: Sequence[Sequence[float]]  # initial-guess polynomial per iteration, in u = var/v_hi,
-    #                                  already multiplied by C_t = sqrt(n)/c_t
+    coef: Sequence[Sequence[float]]  # initial guess g(u) ~ u^(-1/2) per iteration, power basis
+    #                                  in u = var/v_hi; the schedule multiplies by C_t = sqrt(n)/c_t
     newton: int = 0                # Newton steps after the initial guess
     B: float = 1.0                 # final sum is mapped to x = S/B in (0, 1]
     gold_d: int = 3                # Goldschmidt degree (d+1 factors)
@@ -179,7 +179,7 @@ def cutmax_mirror(y0: np.ndarray, cfg: MirrorCfg, check: bool = True,
             raise DomainError(f"iteration {t}: variance {var} outside [{cfg.v_lo[t]}, {cfg.v_hi[t]}]")
         u = var / cfg.v_hi[t]
         C = math.sqrt(n) / cfg.c[t]
-        h = poly_eval(cfg.coef[t], u)
+        h = poly_eval([g * C for g in cfg.coef[t]], u)
         for _ in range(cfg.newton):
             h = newton_invsqrt_step(h, u, C)
         z = (y - mu) / math.sqrt(n * cfg.v_hi[t]) * h + 1.0

@@ -1,0 +1,1335 @@
+// Host orchestration of the encrypted CutMax on one MI355X: context and
+// device key generation, client encrypt/decrypt, the batched CKKS evaluator
+// (hybrid key switching, rescale, rotations) and the CutMax schedule of
+// Alg. 2 (arXiv 2509.08383, Sec. 3.2) with its Goldschmidt inverse (App. B.1).
+//
+// Every call runs twice: a dry pass with kernel launches disabled sizes the
+// workspace and records every constant the schedule needs (all host-side, in
+// IEEE double, in a fixed order); the constants are uploaded once; the real
+// pass replays the same sequence and launches the kernels on the context's
+// stream.  Nothing is allocated with hipMalloc between the first and the last
+// kernel of a call, so a call can be captured in a HIP graph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/he.h"
+#include "he_internal.h"
+
+using namespace he;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct HeError : std::runtime_error {
+    int code;
+    HeError(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHK(x)                                                                              \
+    do {                                                                                       \
+        hipError_t e_ = (x);                                                                   \
+        if (e_ != hipSuccess)                                                                  \
+            throw HeError(HE_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_));          \
+    } while (0)
+
+#define REQUIRE(c, code, msg)                 \
+    do {                                      \
+        if (!(c)) throw HeError(code, msg);   \
+    } while (0)
+
+constexpr uint32_t OBJ_SK = 0x00000001u;
+constexpr uint32_t OBJ_KEY_A = 0x01000000u;
+constexpr uint32_t OBJ_KEY_E = 0x02000000u;
+constexpr uint32_t OBJ_ENC_A = 0x03000000u;
+constexpr uint32_t OBJ_ENC_E = 0x04000000u;
+
+// bump allocator for the per-call workspace; dry mode only counts
+struct Arena {
+    char *base = nullptr;
+    size_t cap = 0, top = 0, peak = 0;
+    bool dry = true;
+    void *alloc(size_t bytes) {
+        size_t off = (top + 255) & ~(size_t)255;
+        top = off + bytes;
+        peak = std::max(peak, top);
+        if (dry) return (void *)(uintptr_t)(0x100000 + off);
+        if (top > cap) throw HeError(HE_ENOMEM, "workspace overflow");
+        return base + off;
+    }
+    size_t mark() const { return top; }
+    void release(size_t m) { top = m; }
+};
+
+// constants of one call, recorded in the dry pass and uploaded once
+struct Pool {
+    std::vector<double> dv;
+    std::vector<int> iv;
+    size_t dpos = 0, ipos = 0;
+    double *d_dv = nullptr;
+    int *d_iv = nullptr;
+    size_t dcap = 0, icap = 0;
+    bool dry = true;
+    const double *push(const std::vector<double> &v) {
+        size_t off = dpos;
+        dpos += v.size();
+        if (dry) { dv.insert(dv.end(), v.begin(), v.end()); return (const double *)(uintptr_t)(0x200000 + 8 * off); }
+        return d_dv + off;
+    }
+    const int *push(const std::vector<int> &v) {
+        size_t off = ipos;
+        ipos += v.size();
+        if (dry) { iv.insert(iv.end(), v.begin(), v.end()); return (const int *)(uintptr_t)(0x300000 + 4 * off); }
+        return d_iv + off;
+    }
+};
+
+}  // namespace
+
+// ------------------------------------------------------------------ context
+struct he_ctx {
+    int logN = 0, N = 0, L = 0, alpha = 0, dnum = 0, np = 0, betaL = 0, slots = 0;
+    double Delta = 0;
+    uint64_t seed = 0;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::vector<uint64_t> q;
+    DevTables T{};
+    // device tables (one allocation each)
+    double *d_tab = nullptr;
+    int *d_itab = nullptr;
+    double *d_sk = nullptr;  // [np][N] NTT domain
+    std::vector<double *> keys;
+    // level-indexed conversion tables (device pointers into d_tab / d_itab)
+    std::vector<const int *> ext_prime;                 // [L+1] -> [l+1+alpha]
+    std::vector<std::vector<const double *>> vinv, qhat;  // [L+1][beta_l]
+    std::vector<std::vector<const int *>> ndslot, ndprime;
+    std::vector<std::vector<int>> ndcount;
+    const double *phinv = nullptr, *phat = nullptr, *Pinv = nullptr, *qlinv = nullptr, *pmod = nullptr;
+    const int *ident = nullptr;   // 0..np-1
+    const int *pprime = nullptr;  // L+1 .. L+alpha
+    uint32_t nonce = 0;
+    Arena arena;
+    Pool pool;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double last_ms = 0;
+    int use_graph = 0;
+    int ntt_variant = 0;
+    // graph cache keyed by a signature of the call
+    std::map<std::string, hipGraphExec_t> graphs;
+};
+
+struct he_ct {
+    he_ctx *ctx = nullptr;
+    double *d = nullptr;  // [a][2][L+1][N]
+    uint32_t a = 1, level = 0;
+    double scale = 0;
+    size_t n = 0;
+};
+
+namespace {
+
+// batch of ciphertexts advancing together: [cnt][2][cap][N]
+struct Bt {
+    double *d = nullptr;
+    int cnt = 0, level = 0, cap = 0;
+    std::vector<double> scale;  // per ciphertext
+};
+
+struct Exec {
+    he_ctx *C;
+    bool dry;
+    hipStream_t s;
+    const DevTables &T;
+    Exec(he_ctx *c, bool d) : C(c), dry(d), s(c->stream), T(c->T) {}
+
+    double *alloc_d(size_t words) { return (double *)C->arena.alloc(words * 8); }
+    Bt new_bt(int cnt, int level) {
+        Bt b;
+        b.cnt = cnt; b.level = level; b.cap = level + 1;
+        b.d = alloc_d((size_t)cnt * 2 * b.cap * C->N);
+        b.scale.assign(cnt, 0.0);
+        return b;
+    }
+    long long N() const { return C->N; }
+    VecSet vs_all(const Bt &b) const {
+        return VecSet{b.d, b.cnt * 2 * (b.level + 1), b.level + 1, (long long)b.cap * C->N, nullptr, nullptr};
+    }
+    VecSet vs_poly(const Bt &b, int poly) const {
+        return VecSet{b.d + (long long)poly * b.cap * C->N, b.cnt * (b.level + 1), b.level + 1,
+                      2LL * b.cap * C->N, nullptr, nullptr};
+    }
+    // residues of per-ciphertext integers for limbs 0..level: [cnt][level+1]
+    const double *residues(const std::vector<int64_t> &k, int level) {
+        std::vector<double> v((size_t)k.size() * (level + 1));
+        for (size_t c = 0; c < k.size(); ++c)
+            for (int i = 0; i <= level; ++i) v[c * (level + 1) + i] = (double)red_i64(k[c], C->q[i]);
+        return C->pool.push(v);
+    }
+
+    // ------------------------------------------------------------- basic ops
+    Bt add(const Bt &a, const Bt &b, int sign = 1) {
+        REQUIRE(a.level == b.level && a.cnt == b.cnt, HE_ESTATE, "add: level/count mismatch");
+        for (int c = 0; c < a.cnt; ++c)
+            REQUIRE(std::fabs(a.scale[c] - b.scale[c]) <= 1e-9 * a.scale[c], HE_ERANGE, "add: scale mismatch");
+        Bt o = new_bt(a.cnt, a.level);
+        o.scale = a.scale;
+        if (!dry) launch_add(T, vs_all(o), vs_all(a), vs_all(b), sign, s);
+        return o;
+    }
+    void add_inplace(Bt &a, const Bt &b) {
+        REQUIRE(a.level == b.level && a.cnt == b.cnt, HE_ESTATE, "add: level/count mismatch");
+        for (int c = 0; c < a.cnt; ++c)
+            REQUIRE(std::fabs(a.scale[c] - b.scale[c]) <= 1e-9 * a.scale[c], HE_ERANGE, "add: scale mismatch");
+        if (!dry) launch_add(T, vs_all(a), vs_all(a), vs_all(b), 1, s);
+    }
+    Bt copy(const Bt &a) {
+        Bt o = new_bt(a.cnt, a.level);
+        o.scale = a.scale;
+        if (!dry) launch_copy(T, vs_all(o), vs_all(a), s);
+        return o;
+    }
+    Bt drop(const Bt &a, int level) const {
+        REQUIRE(level <= a.level && level >= 0, HE_EDEPTH, "drop: bad level");
+        Bt o = a;
+        o.level = level;
+        return o;
+    }
+    Bt mul_int(const Bt &a, const std::vector<int64_t> &k) {
+        Bt o = new_bt(a.cnt, a.level);
+        o.scale = a.scale;
+        ConstTab kt{residues(k, a.level), 2, a.level + 1};
+        if (!dry) launch_mul_const(T, vs_all(o), vs_all(a), kt, s);
+        return o;
+    }
+    Bt add_const(const Bt &a, const std::vector<double> &c) {
+        std::vector<int64_t> v(a.cnt);
+        for (int i = 0; i < a.cnt; ++i) v[i] = llround_d(c[i] * a.scale[i]);
+        Bt o = new_bt(a.cnt, a.level);
+        o.scale = a.scale;
+        ConstTab kt{residues(v, a.level), 1, a.level + 1};
+        if (!dry) {
+            launch_add_const(T, vs_poly(o, 0), vs_poly(a, 0), kt, s);
+            launch_copy(T, vs_poly(o, 1), vs_poly(a, 1), s);
+        }
+        return o;
+    }
+    // D_k = n_k * Y_k - S[map[k]]
+    Bt center(const Bt &Y, const Bt &S, const std::vector<int> &cmap, const std::vector<int64_t> &n) {
+        REQUIRE(Y.level == S.level, HE_ESTATE, "center: level mismatch");
+        for (int c = 0; c < Y.cnt; ++c)
+            REQUIRE(std::fabs(Y.scale[c] - S.scale[cmap[c]]) <= 1e-9 * Y.scale[c], HE_ERANGE, "center: scale mismatch");
+        Bt o = new_bt(Y.cnt, Y.level);
+        o.scale = Y.scale;
+        ConstTab kt{residues(n, Y.level), 2, Y.level + 1};
+        const int *dmap = C->pool.push(cmap);
+        if (!dry) launch_axpy_map(T, vs_all(o), vs_all(Y), kt, vs_all(S), dmap, 2, s);
+        return o;
+    }
+    // per-request sums of consecutive ciphertexts
+    Bt sum_groups(const Bt &Y, const std::vector<int> &first, const std::vector<int> &cnt) {
+        const int R = (int)first.size();
+        Bt o = new_bt(R, Y.level);
+        for (int r = 0; r < R; ++r) {
+            o.scale[r] = Y.scale[first[r]];
+            for (int k = 1; k < cnt[r]; ++k)
+                REQUIRE(std::fabs(Y.scale[first[r] + k] - o.scale[r]) <= 1e-9 * o.scale[r], HE_ERANGE, "sum: scale mismatch");
+        }
+        const int *df = C->pool.push(first);
+        const int *dc = C->pool.push(cnt);
+        if (!dry) launch_sum_groups(T, vs_all(o), vs_all(Y), df, dc, 2, s);
+        return o;
+    }
+
+    // ------------------------------------------------------------- rescale
+    // (K a - [K a_l]_centred) / q_l per limb; kres (per ct, limbs 0..l) = K mod q_i, or
+    // null for a plain rescale
+    Bt rescale(const Bt &a, const double *kres = nullptr) {
+        const int l = a.level;
+        REQUIRE(l >= 1, HE_EDEPTH, "rescale at level 0");
+        Bt o = new_bt(a.cnt, l - 1);
+        for (int c = 0; c < a.cnt; ++c) o.scale[c] = a.scale[c] / (double)C->q[l];
+        const size_t m = C->arena.mark();
+        const int G = a.cnt * 2;
+        double *last = alloc_d((size_t)G * C->N);
+        double *lift = alloc_d((size_t)G * l * C->N);
+        if (!dry) {
+            VecSet src{a.d + (long long)l * C->N, G, 1, (long long)a.cap * C->N, nullptr, C->ident + l};
+            VecSet dst{last, G, 1, (long long)C->N, nullptr, C->ident + l};
+            if (kres) launch_mul_const(T, dst, src, ConstTab{kres + l, 2, l + 1}, s);
+            else launch_copy(T, dst, src, s);
+            launch_ntt(T, dst, true, C->ntt_variant, s);
+            launch_rescale_lift(T, last, C->N, lift, (long long)l * C->N, G, l, s);
+            launch_ntt(T, VecSet{lift, G * l, l, (long long)l * C->N, nullptr, nullptr}, false, C->ntt_variant, s);
+            launch_rescale_combine(T, o.d, (long long)o.cap * C->N, a.d, (long long)a.cap * C->N, lift,
+                                   (long long)l * C->N, G, l, C->qlinv + (long long)l * (C->L + 1), kres, s);
+        }
+        C->arena.release(m);
+        return o;
+    }
+
+    // ------------------------------------------------------------ key switch
+    // d: NTT-domain polynomials [cnt] at `dstride` words apart, limbs 0..l.
+    // out (groups ct*2 + poly at ostride) = ModDown(sum_j ModUp_j(d) key_j)
+    // plus `add` on the polys selected by addmask.
+    void keyswitch(const double *d, long long dstride, int cnt, int l, int kidx, double *out,
+                   long long ostride, const double *add, long long add_ct, long long add_poly, int addmask) {
+        const int A = C->alpha, next = l + 1 + A, beta = (l + 1 + A - 1) / A;
+        const long long N = C->N;
+        const size_t m = C->arena.mark();
+        double *dcoef = alloc_d((size_t)cnt * (l + 1) * N);
+        double *ext = alloc_d((size_t)cnt * beta * next * N);
+        double *acc = alloc_d((size_t)cnt * 2 * next * N);
+        double *conv = alloc_d((size_t)cnt * 2 * (l + 1) * N);
+        if (!dry) {
+            VecSet vd{dcoef, cnt * (l + 1), l + 1, (long long)(l + 1) * N, nullptr, nullptr};
+            launch_copy(T, vd, VecSet{const_cast<double *>(d), cnt * (l + 1), l + 1, dstride, nullptr, nullptr}, s);
+            launch_ntt(T, vd, true, C->ntt_variant, s);
+            for (int j = 0; j < beta; ++j) {
+                const int lo = j * A, dl = std::min(A, l + 1 - lo);
+                launch_modup(T, dcoef, (long long)(l + 1) * N, ext + (long long)j * next * N,
+                             (long long)beta * next * N, d, dstride, cnt, l, j, lo, dl, next,
+                             C->ext_prime[l], C->vinv[l][j], C->qhat[l][j], s);
+                const int nd = C->ndcount[l][j];
+                launch_ntt(T, VecSet{ext + (long long)j * next * N, cnt * nd, nd, (long long)beta * next * N,
+                                     C->ndslot[l][j], C->ndprime[l][j]}, false, C->ntt_variant, s);
+            }
+            launch_inner_product(T, ext, (long long)beta * next * N, (long long)next * N, acc, acc + (long long)next * N,
+                                 2LL * next * N, C->keys[kidx], 2LL * C->np * N, (long long)C->np * N, cnt, beta,
+                                 next, C->ext_prime[l], s);
+            launch_ntt(T, VecSet{acc + (long long)(l + 1) * N, cnt * 2 * A, A, (long long)next * N, nullptr, C->pprime},
+                       true, C->ntt_variant, s);
+            launch_moddown_conv(T, acc, (long long)next * N, conv, (long long)(l + 1) * N, cnt * 2, l, C->phinv,
+                                C->phat, s);
+            launch_ntt(T, VecSet{conv, cnt * 2 * (l + 1), l + 1, (long long)(l + 1) * N, nullptr, nullptr}, false,
+                       C->ntt_variant, s);
+            launch_moddown_combine(T, out, ostride, acc, (long long)next * N, conv, (long long)(l + 1) * N, add,
+                                   add_ct, add_poly, addmask, cnt * 2, l, C->Pinv, s);
+        }
+        C->arena.release(m);
+    }
+
+    // tensor, relinearise, rescale; b indexed through bmap when given
+    Bt mul(const Bt &a, const Bt &b, const std::vector<int> *bmap = nullptr) {
+        REQUIRE(a.level == b.level, HE_ESTATE, "mul: level mismatch");
+        const int l = a.level;
+        REQUIRE(l >= 1, HE_EDEPTH, "mul at level 0");
+        const long long N = C->N;
+        Bt r = new_bt(a.cnt, l);
+        for (int c = 0; c < a.cnt; ++c) r.scale[c] = a.scale[c] * b.scale[bmap ? (*bmap)[c] : c];
+        const size_t m = C->arena.mark();
+        double *t = alloc_d((size_t)a.cnt * 3 * (l + 1) * N);
+        const int *dmap = bmap ? C->pool.push(*bmap) : nullptr;
+        if (!dry)
+            launch_tensor(T, t, t + (l + 1) * N, t + 2 * (l + 1) * N, 3LL * (l + 1) * N, a.d, b.d,
+                          2LL * a.cap * N, 2LL * b.cap * N, dmap, (long long)a.cap * N, (long long)b.cap * N,
+                          a.cnt, l + 1, s);
+        keyswitch(t + 2 * (l + 1) * N, 3LL * (l + 1) * N, a.cnt, l, 0, r.d, (long long)r.cap * N, t,
+                  3LL * (l + 1) * N, (long long)(l + 1) * N, 3);
+        C->arena.release(m);
+        // r's scale here is s_a*s_b; the rescale divides by q_l
+        Bt o = rescale(r);
+        for (int c = 0; c < a.cnt; ++c) o.scale[c] = (a.scale[c] * b.scale[bmap ? (*bmap)[c] : c]) / (double)C->q[l];
+        return o;
+    }
+
+    // multiply by a real constant then rescale (cm_exact / cm_target)
+    Bt cmul(const Bt &a, const std::vector<double> &kappa, const std::vector<double> &s_want, bool exact) {
+        const int l = a.level;
+        REQUIRE(l >= 1, HE_EDEPTH, "constant multiply at level 0");
+        const double q = (double)C->q[l];
+        std::vector<int64_t> K(a.cnt);
+        for (int c = 0; c < a.cnt; ++c) {
+            const double x = ((kappa[c] * s_want[c]) * q) / a.scale[c];
+            REQUIRE(std::fabs(x) < 4.0e18, HE_ERANGE, "constant not encodable");
+            K[c] = llround_d(x);
+            REQUIRE(K[c] != 0 && std::llabs(K[c]) < (1LL << 62), HE_ERANGE, "constant not encodable");
+        }
+        Bt o = rescale(a, residues(K, l));
+        for (int c = 0; c < a.cnt; ++c)
+            o.scale[c] = exact ? ((a.scale[c] * (double)K[c]) / q) / kappa[c] : s_want[c];
+        return o;
+    }
+
+    Bt rotate(const Bt &a, int r) {
+        const int l = a.level;
+        const long long N = C->N;
+        Bt o = new_bt(a.cnt, l);
+        o.scale = a.scale;
+        const size_t m = C->arena.mark();
+        double *sig = alloc_d((size_t)a.cnt * 2 * (l + 1) * N);
+        uint64_t g = 5;
+        for (int i = 0; i < r; ++i) g = (g * g) % (2ull * C->N);
+        if (!dry)
+            launch_automorph(T, VecSet{sig, a.cnt * 2 * (l + 1), l + 1, (long long)(l + 1) * N, nullptr, nullptr},
+                             vs_all(a), g, s);
+        keyswitch(sig + (l + 1) * N, 2LL * (l + 1) * N, a.cnt, l, 1 + r, o.d, (long long)o.cap * N, sig,
+                  2LL * (l + 1) * N, (long long)(l + 1) * N, 1);
+        C->arena.release(m);
+        return o;
+    }
+
+    // rotate-and-sum over every slot (Sec. 3.2): x <- x + rot(x, 2^r)
+    Bt rotsum(const Bt &a) {
+        Bt o = copy(a);
+        int lg = 0;
+        while ((1 << lg) < C->slots) ++lg;
+        for (int r = 0; r < lg; ++r) {
+            const size_t m = C->arena.mark();
+            Bt t = rotate(o, r);
+            add_inplace(o, t);
+            C->arena.release(m);
+        }
+        return o;
+    }
+
+    Bt power(const Bt &y, int p) {
+        REQUIRE(p >= 1, HE_EINVAL, "power must be >= 1");
+        std::vector<Bt> pw{y};
+        int nb = 0;
+        while ((p >> nb) > 1) ++nb;
+        for (int i = 1; i <= nb; ++i) pw.push_back(mul(pw.back(), pw.back()));
+        Bt acc;
+        bool have = false;
+        for (int i = 0; i <= nb; ++i) {
+            if (!((p >> i) & 1)) continue;
+            if (!have) { acc = pw[i]; have = true; }
+            else {
+                const int lv = std::min(acc.level, pw[i].level);
+                acc = mul(drop(acc, lv), drop(pw[i], lv));
+            }
+        }
+        return acc;
+    }
+};
+
+// ------------------------------------------------------------- CutMax plan
+struct Request { int first, a; int64_t n; };
+
+int invsqr_depth(int degree, int newton) {
+    static const int d[5] = {0, 1, 2, 2, 3};
+    return d[degree] + 2 * newton;
+}
+
+// h ~ C u^(-1/2): polynomial sum_k coef_k u^k (coefficients times C), then
+// Newton steps h <- 1.5 h - (0.5/C^2) u h^3; lands at scale s_final per ct.
+Bt invsqr(Exec &X, const Bt &U, const std::vector<std::vector<double>> &coefC, const std::vector<double> &Cc,
+          int newton, const std::vector<double> &s_final) {
+    const int R = U.cnt, d = (int)coefC[0].size() - 1, lu = U.level;
+    const auto &q = X.C->q;
+    std::vector<double> S(R);
+    for (int r = 0; r < R; ++r) S[r] = newton == 0 ? s_final[r] : X.C->Delta;
+    auto col = [&](int k) { std::vector<double> v(R); for (int r = 0; r < R; ++r) v[r] = coefC[r][k]; return v; };
+    Bt H;
+    if (d == 1) {
+        H = X.add_const(X.cmul(U, col(1), S, false), col(0));
+    } else if (d == 2) {
+        Bt U2 = X.mul(U, U);
+        Bt T2 = X.cmul(U2, col(2), S, false);
+        Bt T1 = X.cmul(X.drop(U, lu - 1), col(1), S, false);
+        H = X.add_const(X.add(T2, T1), col(0));
+    } else if (d == 3) {
+        Bt U2 = X.mul(U, U);
+        std::vector<double> sA(R), sB(R);
+        for (int r = 0; r < R; ++r) {
+            sA[r] = (S[r] * (double)q[lu - 1]) / U2.scale[r];
+            sB[r] = (S[r] * (double)q[lu - 1]) / U.scale[r];
+        }
+        Bt T3 = X.mul(X.cmul(U, col(3), sA, false), U2);
+        Bt T2 = X.mul(X.cmul(U, col(2), sB, false), X.drop(U, lu - 1));
+        Bt T1 = X.cmul(X.drop(U, lu - 1), col(1), S, false);
+        H = X.add_const(X.add(X.add(T3, T2), T1), col(0));
+    } else if (d == 4) {
+        Bt U2 = X.mul(U, U);
+        std::vector<double> sC(R), sD(R);
+        for (int r = 0; r < R; ++r) {
+            sC[r] = (S[r] * (double)q[lu - 2]) / U2.scale[r];
+            sD[r] = (S[r] * (double)q[lu - 2]) / U.scale[r];
+        }
+        Bt T4 = X.mul(X.cmul(U2, col(4), sC, false), X.drop(U2, lu - 2));
+        Bt T3 = X.mul(X.cmul(U2, col(3), sD, false), X.drop(U, lu - 2));
+        Bt T2 = X.cmul(X.drop(U2, lu - 2), col(2), S, false);
+        Bt T1 = X.cmul(X.drop(U, lu - 2), col(1), S, false);
+        H = X.add_const(X.add(X.add(X.add(T4, T3), T2), T1), col(0));
+    } else {
+        throw HeError(HE_EINVAL, "initial-guess degree must be 1..4");
+    }
+    for (int it = 0; it < newton; ++it) {
+        std::vector<double> St(R), sA(R), kap(R), c15(R, 1.5);
+        for (int r = 0; r < R; ++r) St[r] = it == newton - 1 ? s_final[r] : X.C->Delta;
+        const int lh = H.level;
+        Bt G2 = X.mul(H, H);
+        for (int r = 0; r < R; ++r) {
+            sA[r] = (((St[r] * (double)q[lh]) * (double)q[lh - 1]) / H.scale[r]) / G2.scale[r];
+            kap[r] = -0.5 / (Cc[r] * Cc[r]);
+        }
+        Bt A = X.drop(X.cmul(U, kap, sA, false), lh);
+        Bt B = X.mul(A, H);
+        Bt Tt = X.mul(B, G2);
+        Bt L1 = X.drop(X.cmul(H, c15, St, false), lh - 2);
+        H = X.add(Tt, L1);
+    }
+    return H;
+}
+
+struct CutmaxCfg {
+    int T = 0;
+    std::vector<int> p;
+    std::vector<double> c, vlo, vhi;
+    std::vector<std::vector<double>> coef;  // [T][d+1] unscaled g(u) ~ u^-1/2
+    int newton = 0, gold_d = 3;
+    double sum_lo = 1, sum_hi = 3;
+};
+
+int levels_needed(const CutmaxCfg &cf) {
+    int lv = 0;
+    for (int t = 0; t < cf.T; ++t) {
+        int nb = 0;
+        while ((cf.p[t] >> nb) > 1) ++nb;
+        lv += 2 + invsqr_depth((int)cf.coef[t].size() - 1, cf.newton) + 1 + nb + (__builtin_popcount(cf.p[t]) > 1 ? 1 : 0);
+    }
+    return lv + cf.gold_d + 3;
+}
+
+// Alg. 2 on a batch of requests; Y holds every request's ciphertexts.
+Bt cutmax_sched(Exec &X, Bt Y, const std::vector<Request> &reqs, const CutmaxCfg &cf) {
+    he_ctx *C = X.C;
+    const int R = (int)reqs.size();
+    std::vector<int> first(R), cnt(R), cmap(Y.cnt);
+    std::vector<int64_t> nct(Y.cnt);
+    for (int r = 0; r < R; ++r) {
+        first[r] = reqs[r].first; cnt[r] = reqs[r].a;
+        for (int k = 0; k < reqs[r].a; ++k) { cmap[reqs[r].first + k] = r; nct[reqs[r].first + k] = reqs[r].n; }
+    }
+    REQUIRE(levels_needed(cf) <= Y.level, HE_EDEPTH, "schedule needs more levels than the ciphertext has");
+    for (int t = 0; t < cf.T; ++t) {
+        const size_t mark = C->arena.mark();
+        Bt S = X.rotsum(X.sum_groups(Y, first, cnt));
+        Bt D = X.center(Y, S, cmap, nct);
+        std::vector<double> kE(Y.cnt), dl(Y.cnt, C->Delta);
+        for (int k = 0; k < Y.cnt; ++k) kE[k] = 1.0 / ((double)nct[k] * std::sqrt((double)nct[k] * cf.vhi[t]));
+        Bt E = X.cmul(D, kE, dl, true);
+        Bt F = X.mul(E, E);
+        Bt U = X.rotsum(X.sum_groups(F, first, cnt));
+        const int lh = U.level - invsqr_depth((int)cf.coef[t].size() - 1, cf.newton);
+        REQUIRE(lh >= 1, HE_EDEPTH, "chain too short");
+        std::vector<double> Cc(R), SH(R);
+        std::vector<std::vector<double>> coefC(R);
+        for (int r = 0; r < R; ++r) {
+            Cc[r] = std::sqrt((double)reqs[r].n) / cf.c[t];
+            SH[r] = (C->Delta * (double)C->q[lh]) / E.scale[first[r]];
+            for (double g : cf.coef[t]) coefC[r].push_back(g * Cc[r]);
+        }
+        Bt H = invsqr(X, U, coefC, Cc, cf.newton, SH);
+        Bt Yp = X.add_const(X.mul(X.drop(E, H.level), H, &cmap), std::vector<double>(Y.cnt, 1.0));
+        Bt Yn = X.power(Yp, cf.p[t]);
+        // keep the new iterate, drop this iteration's temporaries
+        C->arena.release(mark);
+        Bt Yk = X.new_bt(Yn.cnt, Yn.level);
+        Yk.scale = Yn.scale;
+        if (!X.dry) launch_copy(X.T, X.vs_all(Yk), X.vs_all(Yn), X.s);
+        // Yn's storage was released above but is only overwritten by later
+        // allocations; the copy is enqueued before any of them
+        Y = Yk;
+    }
+    std::vector<double> invB(Y.cnt), dl(Y.cnt, C->Delta), invBr(R), dlr(R, C->Delta);
+    for (int k = 0; k < Y.cnt; ++k) invB[k] = 1.0 / (cf.sum_hi * (double)nct[k]);
+    for (int r = 0; r < R; ++r) invBr[r] = 1.0 / (cf.sum_hi * (double)reqs[r].n);
+    Bt S = X.rotsum(X.sum_groups(Y, first, cnt));
+    Bt Xs = X.cmul(S, invBr, dlr, true);
+    Bt E0 = X.add_const(X.mul_int(Xs, std::vector<int64_t>(R, -1)), std::vector<double>(R, 1.0));
+    Bt P = X.add_const(E0, std::vector<double>(R, 1.0));
+    Bt Ei = E0;
+    for (int i = 0; i < cf.gold_d; ++i) {
+        Ei = X.mul(Ei, Ei);
+        P = X.mul(X.drop(P, Ei.level), X.add_const(Ei, std::vector<double>(R, 1.0)));
+    }
+    Bt Yb = X.cmul(Y, invB, dl, true);
+    return X.mul(X.drop(Yb, P.level), P, &cmap);
+}
+
+// ---------------------------------------------------------------- helpers
+void set_err(const std::string &m) { g_err = m; }
+
+template <class F>
+int guarded(F &&f) {
+    try {
+        return f();
+    } catch (const HeError &e) {
+        set_err(e.what());
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        set_err("host allocation failed");
+        return HE_ENOMEM;
+    } catch (const std::exception &e) {
+        set_err(e.what());
+        return HE_EINVAL;
+    }
+}
+
+void ensure_workspace(he_ctx *C) {
+    if (C->arena.peak > C->arena.cap) {
+        if (C->arena.base) HIPCHK(hipFree(C->arena.base));
+        C->arena.base = nullptr;
+        const size_t want = C->arena.peak + (64u << 20);
+        HIPCHK(hipMalloc(&C->arena.base, want));
+        C->arena.cap = want;
+    }
+    Pool &P = C->pool;
+    if (P.dv.size() > P.dcap) {
+        if (P.d_dv) HIPCHK(hipFree(P.d_dv));
+        P.dcap = P.dv.size() * 2 + 1024;
+        HIPCHK(hipMalloc(&P.d_dv, P.dcap * 8));
+    }
+    if (P.iv.size() > P.icap) {
+        if (P.d_iv) HIPCHK(hipFree(P.d_iv));
+        P.icap = P.iv.size() * 2 + 1024;
+        HIPCHK(hipMalloc(&P.d_iv, P.icap * 4));
+    }
+    if (!P.dv.empty()) HIPCHK(hipMemcpyAsync(P.d_dv, P.dv.data(), P.dv.size() * 8, hipMemcpyHostToDevice, C->stream));
+    if (!P.iv.empty()) HIPCHK(hipMemcpyAsync(P.d_iv, P.iv.data(), P.iv.size() * 4, hipMemcpyHostToDevice, C->stream));
+}
+
+// dry pass, upload, real pass
+template <class Body>
+void run2(he_ctx *C, Body &&body) {
+    C->arena.dry = true; C->arena.top = 0; C->arena.peak = 0;
+    C->pool.dry = true; C->pool.dv.clear(); C->pool.iv.clear(); C->pool.dpos = C->pool.ipos = 0;
+    {
+        Exec X(C, true);
+        body(X);
+    }
+    ensure_workspace(C);
+    C->arena.dry = false; C->arena.top = 0;
+    C->pool.dry = false; C->pool.dpos = C->pool.ipos = 0;
+    Exec X(C, false);
+    body(X);
+    HIPCHK(hipGetLastError());
+}
+
+he_ct *new_ct(he_ctx *C, uint32_t a) {
+    auto *ct = new he_ct;
+    ct->ctx = C;
+    ct->a = a;
+    const size_t words = (size_t)a * 2 * (C->L + 1) * C->N;
+    hipError_t e = hipMalloc(&ct->d, words * 8);
+    if (e != hipSuccess) { delete ct; throw HeError(HE_ENOMEM, "ciphertext allocation failed"); }
+    return ct;
+}
+
+// view of a handle as a batch (cap = L+1)
+Bt bt_of(const he_ct *ct) {
+    Bt b;
+    b.d = ct->d; b.cnt = (int)ct->a; b.level = (int)ct->level; b.cap = ct->ctx->L + 1;
+    b.scale.assign(ct->a, ct->scale);
+    return b;
+}
+
+void store_bt(Exec &X, const Bt &b, int first, he_ct *ct) {
+    Bt dst = bt_of(ct);
+    dst.level = b.level;
+    Bt src = b;
+    src.d = b.d + (long long)first * 2 * b.cap * X.C->N;
+    src.cnt = (int)ct->a;
+    if (!X.dry) launch_copy(X.T, X.vs_all(dst), X.vs_all(src), X.s);
+    ct->level = (uint32_t)b.level;
+    ct->scale = b.scale[first];
+}
+
+// --------------------------------------------------------- table building
+struct TabBuilder {
+    std::vector<double> dv;
+    std::vector<int> iv;
+    size_t d(const std::vector<double> &v) { size_t o = dv.size(); dv.insert(dv.end(), v.begin(), v.end()); return o; }
+    size_t i(const std::vector<int> &v) { size_t o = iv.size(); iv.insert(iv.end(), v.begin(), v.end()); return o; }
+};
+
+void build_ctx(he_ctx *C, const he_params *prm) {
+    const int N = C->N, L = C->L, A = C->alpha, np = C->np;
+    C->q = gen_primes(C->logN, L + 1, (int)prm->q0_bits, (int)prm->q_bits, (int)prm->p_bits, A);
+    const auto &q = C->q;
+    TabBuilder tb;
+    std::vector<double> pd(np), pinv(np), ninv(np), two32(np);
+    std::vector<double> tw((size_t)np * N), itw((size_t)np * N);
+    for (int i = 0; i < np; ++i) {
+        pd[i] = (double)q[i];
+        pinv[i] = 1.0 / pd[i];
+        ninv[i] = (double)invmod_u((uint64_t)N % q[i], q[i]);
+        two32[i] = (double)((1ull << 32) % q[i]);
+        const uint64_t psi = find_psi(q[i], N), ipsi = invmod_u(psi, q[i]);
+        std::vector<uint64_t> pw(N), ipw(N);
+        pw[0] = ipw[0] = 1;
+        for (int k = 1; k < N; ++k) { pw[k] = mulmod_u(pw[k - 1], psi, q[i]); ipw[k] = mulmod_u(ipw[k - 1], ipsi, q[i]); }
+        for (int k = 0; k < N; ++k) {
+            int r = 0;
+            for (int b = 0; b < C->logN; ++b) if ((k >> b) & 1) r |= 1 << (C->logN - 1 - b);
+            tw[(size_t)i * N + k] = (double)pw[r];
+            itw[(size_t)i * N + k] = (double)ipw[r];
+        }
+    }
+    const size_t o_p = tb.d(pd), o_pinv = tb.d(pinv), o_tw = tb.d(tw), o_itw = tb.d(itw), o_ninv = tb.d(ninv),
+                 o_two32 = tb.d(two32);
+    std::vector<int> ident(np);
+    for (int i = 0; i < np; ++i) ident[i] = i;
+    const size_t o_ident = tb.i(ident);
+    std::vector<int> pprime(A);
+    for (int m = 0; m < A; ++m) pprime[m] = L + 1 + m;
+    const size_t o_pprime = tb.i(pprime);
+    // ModDown constants
+    std::vector<double> phinv(A), phat((size_t)A * (L + 1)), Pinv(L + 1), pmod(np, 0.0);
+    for (int m = 0; m < A; ++m) {
+        const uint64_t pm = q[L + 1 + m];
+        uint64_t v = 1;
+        for (int b = 0; b < A; ++b) if (b != m) v = mulmod_u(v, q[L + 1 + b] % pm, pm);
+        phinv[m] = (double)invmod_u(v, pm);
+        for (int i = 0; i <= L; ++i) {
+            uint64_t w = 1;
+            for (int b = 0; b < A; ++b) if (b != m) w = mulmod_u(w, q[L + 1 + b] % q[i], q[i]);
+            phat[(size_t)m * (L + 1) + i] = (double)w;
+        }
+    }
+    for (int i = 0; i <= L; ++i) {
+        uint64_t P = 1;
+        for (int m = 0; m < A; ++m) P = mulmod_u(P, q[L + 1 + m] % q[i], q[i]);
+        Pinv[i] = (double)invmod_u(P, q[i]);
+        pmod[i] = (double)P;
+    }
+    const size_t o_phinv = tb.d(phinv), o_phat = tb.d(phat), o_Pinv = tb.d(Pinv), o_pmod = tb.d(pmod);
+    // rescale: q_l^-1 mod q_i
+    std::vector<double> qlinv((size_t)(L + 1) * (L + 1), 0.0);
+    for (int l = 1; l <= L; ++l)
+        for (int i = 0; i < l; ++i) qlinv[(size_t)l * (L + 1) + i] = (double)invmod_u(q[l] % q[i], q[i]);
+    const size_t o_qlinv = tb.d(qlinv);
+    // ModUp per level and digit
+    std::vector<size_t> o_ext(L + 1);
+    std::vector<std::vector<size_t>> o_vinv(L + 1), o_qhat(L + 1), o_nds(L + 1), o_ndp(L + 1);
+    C->ndcount.assign(L + 1, {});
+    for (int l = 0; l <= L; ++l) {
+        const int next = l + 1 + A, beta = (l + 1 + A - 1) / A;
+        std::vector<int> ep(next);
+        for (int t = 0; t < next; ++t) ep[t] = t <= l ? t : L + 1 + (t - l - 1);
+        o_ext[l] = tb.i(ep);
+        for (int j = 0; j < beta; ++j) {
+            const int lo = j * A, dl = std::min(A, l + 1 - lo);
+            std::vector<double> vi(dl), qh((size_t)dl * next);
+            for (int a = 0; a < dl; ++a) {
+                const uint64_t qi = q[lo + a];
+                uint64_t v = 1;
+                for (int b = 0; b < dl; ++b) if (b != a) v = mulmod_u(v, q[lo + b] % qi, qi);
+                vi[a] = (double)invmod_u(v, qi);
+                for (int t = 0; t < next; ++t) {
+                    const uint64_t pt = q[ep[t]];
+                    uint64_t w = 1;
+                    for (int b = 0; b < dl; ++b) if (b != a) w = mulmod_u(w, q[lo + b] % pt, pt);
+                    qh[(size_t)a * next + t] = (double)w;
+                }
+            }
+            o_vinv[l].push_back(tb.d(vi));
+            o_qhat[l].push_back(tb.d(qh));
+            std::vector<int> ns, npr;
+            for (int t = 0; t < next; ++t)
+                if (!(t >= lo && t < lo + dl)) { ns.push_back(t); npr.push_back(ep[t]); }
+            C->ndcount[l].push_back((int)ns.size());
+            o_nds[l].push_back(tb.i(ns));
+            o_ndp[l].push_back(tb.i(npr));
+        }
+    }
+    HIPCHK(hipMalloc(&C->d_tab, tb.dv.size() * 8));
+    HIPCHK(hipMalloc(&C->d_itab, tb.iv.size() * 4));
+    HIPCHK(hipMemcpy(C->d_tab, tb.dv.data(), tb.dv.size() * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(C->d_itab, tb.iv.data(), tb.iv.size() * 4, hipMemcpyHostToDevice));
+    double *D = C->d_tab;
+    int *I = C->d_itab;
+    C->T = DevTables{N, C->logN, np, L, A, D + o_p, D + o_pinv, D + o_tw, D + o_itw, D + o_ninv, D + o_two32};
+    C->ident = I + o_ident;
+    C->pprime = I + o_pprime;
+    C->phinv = D + o_phinv; C->phat = D + o_phat; C->Pinv = D + o_Pinv; C->pmod = D + o_pmod;
+    C->qlinv = D + o_qlinv;
+    C->ext_prime.resize(L + 1);
+    C->vinv.assign(L + 1, {}); C->qhat.assign(L + 1, {}); C->ndslot.assign(L + 1, {}); C->ndprime.assign(L + 1, {});
+    for (int l = 0; l <= L; ++l) {
+        C->ext_prime[l] = I + o_ext[l];
+        for (size_t j = 0; j < o_vinv[l].size(); ++j) {
+            C->vinv[l].push_back(D + o_vinv[l][j]);
+            C->qhat[l].push_back(D + o_qhat[l][j]);
+            C->ndslot[l].push_back(I + o_nds[l][j]);
+            C->ndprime[l].push_back(I + o_ndp[l][j]);
+        }
+    }
+}
+
+// secret key and every evaluation key, generated on the device
+void keygen(he_ctx *C) {
+    const int N = C->N, np = C->np;
+    const DevTables &T = C->T;
+    hipStream_t s = C->stream;
+    int *dsmall = nullptr;
+    double *ta = nullptr, *te = nullptr, *tg = nullptr;
+    HIPCHK(hipMalloc(&dsmall, sizeof(int) * N));
+    HIPCHK(hipMalloc(&C->d_sk, 8ull * np * N));
+    HIPCHK(hipMalloc(&ta, 8ull * np * N));
+    HIPCHK(hipMalloc(&te, 8ull * np * N));
+    HIPCHK(hipMalloc(&tg, 8ull * np * N));
+    const VecSet all_sk{C->d_sk, np, np, 0, nullptr, nullptr};
+    launch_sample_small(dsmall, N, C->seed, OBJ_SK, 0, s);
+    launch_small_to_res(T, all_sk, dsmall, nullptr, s);
+    launch_ntt(T, all_sk, false, 0, s);
+    int lg = 0;
+    while ((1 << lg) < C->slots) ++lg;
+    const int nkeys = 1 + lg;
+    C->keys.assign(nkeys, nullptr);
+    const size_t per = (size_t)np * N;
+    for (int k = 0; k < nkeys; ++k) {
+        HIPCHK(hipMalloc(&C->keys[k], 8ull * C->betaL * 2 * per));
+        if (k == 0) launch_square_res(T, tg, C->d_sk, np, s);
+        else {
+            uint64_t g = 5;
+            for (int i = 0; i < k - 1; ++i) g = (g * g) % (2ull * N);
+            launch_automorph(T, VecSet{tg, np, np, 0, nullptr, nullptr}, all_sk, g, s);
+        }
+        for (int j = 0; j < C->betaL; ++j) {
+            const uint32_t oa = OBJ_KEY_A | ((uint32_t)k << 8) | (uint32_t)j;
+            const uint32_t oe = OBJ_KEY_E | ((uint32_t)k << 8) | (uint32_t)j;
+            double *kb = C->keys[k] + (size_t)j * 2 * per, *ka = kb + per;
+            const VecSet va{ka, np, np, 0, nullptr, nullptr}, ve{te, np, np, 0, nullptr, nullptr};
+            launch_sample_uniform(T, va, C->seed, oa, nullptr, s);
+            launch_ntt(T, va, false, 0, s);
+            launch_sample_small(dsmall, N, C->seed, oe, 1, s);
+            launch_small_to_res(T, ve, dsmall, nullptr, s);
+            launch_ntt(T, ve, false, 0, s);
+            const int lo = j * C->alpha, hi = std::min(lo + C->alpha, C->L + 1);
+            launch_keyb(T, kb, ka, te, C->d_sk, tg, C->pmod, np, lo, hi, s);
+        }
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipGetLastError());
+    hipFree(dsmall); hipFree(ta); hipFree(te); hipFree(tg);
+}
+
+// encryption of already-encoded integer plaintexts m[a][N] (host memory)
+void encrypt_coeffs_impl(he_ctx *C, const int64_t *m, uint32_t a, double scale, he_ct *ct) {
+    const int N = C->N, L = C->L;
+    const size_t words = (size_t)a * N;
+    run2(C, [&](Exec &X) {
+        int64_t *dm = (int64_t *)C->arena.alloc(words * 8);
+        double *mres = X.alloc_d((size_t)a * (L + 1) * N);
+        double *e = X.alloc_d((size_t)(L + 1) * N);
+        int *small = (int *)C->arena.alloc(sizeof(int) * N);
+        if (X.dry) return;
+        HIPCHK(hipMemcpyAsync(dm, m, words * 8, hipMemcpyHostToDevice, C->stream));
+        const VecSet vm{mres, (int)a * (L + 1), L + 1, (long long)(L + 1) * N, nullptr, nullptr};
+        launch_int64_to_res(C->T, vm, dm, N, nullptr, C->stream);
+        launch_ntt(C->T, vm, false, C->ntt_variant, C->stream);
+        for (uint32_t c = 0; c < a; ++c) {
+            const uint32_t nonce = C->nonce + c;
+            double *c0 = ct->d + (size_t)c * 2 * (L + 1) * N, *c1 = c0 + (size_t)(L + 1) * N;
+            const VecSet v1{c1, L + 1, L + 1, 0, nullptr, nullptr};
+            launch_sample_uniform(C->T, v1, C->seed, OBJ_ENC_A | (nonce & 0xFFFFFFu), nullptr, C->stream);
+            launch_ntt(C->T, v1, false, C->ntt_variant, C->stream);
+            const VecSet ve{e, L + 1, L + 1, 0, nullptr, nullptr};
+            launch_sample_small(small, N, C->seed, OBJ_ENC_E | (nonce & 0xFFFFFFu), 1, C->stream);
+            launch_small_to_res(C->T, ve, small, nullptr, C->stream);
+            launch_ntt(C->T, ve, false, C->ntt_variant, C->stream);
+            launch_encfinish(C->T, c0, c1, e, mres + (size_t)c * (L + 1) * N, C->d_sk, 0, L + 1, 1, 0, 0, C->stream);
+        }
+    });
+    HIPCHK(hipStreamSynchronize(C->stream));
+    C->nonce += a;
+    ct->level = (uint32_t)L;
+    ct->scale = scale;
+}
+
+CutmaxCfg parse_cfg(he_ctx *C, const he_cutmax_cfg *cfg) {
+    REQUIRE(cfg && cfg->T >= 1 && cfg->T <= 64 && cfg->p && cfg->c && cfg->var_lo && cfg->var_hi, HE_EINVAL,
+            "cutmax cfg: T, p, c, var_lo, var_hi are required");
+    CutmaxCfg cf;
+    cf.T = (int)cfg->T;
+    const int d = cfg->init_degree ? (int)cfg->init_degree : 3;
+    REQUIRE(d >= 1 && d <= 4, HE_EINVAL, "init_degree must be 1..4");
+    for (int t = 0; t < cf.T; ++t) {
+        REQUIRE(cfg->p[t] >= 1 && cfg->p[t] <= 255, HE_EINVAL, "p out of range");
+        REQUIRE(cfg->c[t] > 0 && cfg->var_hi[t] > 0 && cfg->var_lo[t] > 0 && cfg->var_lo[t] < cfg->var_hi[t],
+                HE_EINVAL, "c and the variance domain must be positive with var_lo < var_hi");
+        cf.p.push_back((int)cfg->p[t]);
+        cf.c.push_back(cfg->c[t]);
+        cf.vlo.push_back(cfg->var_lo[t]);
+        cf.vhi.push_back(cfg->var_hi[t]);
+        std::vector<double> g(d + 1);
+        if (cfg->init_coef) for (int k = 0; k <= d; ++k) g[k] = cfg->init_coef[t * (d + 1) + k];
+        else chebyshev_invsqrt_fit(cfg->var_lo[t] / cfg->var_hi[t], d, g.data());
+        cf.coef.push_back(g);
+    }
+    cf.newton = (int)cfg->newton_steps;
+    cf.gold_d = (int)cfg->gold_d;
+    REQUIRE(cfg->sum_hi > 0 && cfg->sum_lo >= 0 && cfg->sum_lo < cfg->sum_hi, HE_EINVAL, "bad sum domain");
+    cf.sum_lo = cfg->sum_lo;
+    cf.sum_hi = cfg->sum_hi;
+    (void)C;
+    return cf;
+}
+
+// runs CutMax over the requests (optionally after the nucleus noise add)
+int cutmax_impl(he_ctx *C, he_ct *const *in, he_ct *const *noise, size_t batch, const he_cutmax_cfg *cfg,
+                double temperature, he_ct **out) {
+    REQUIRE(C && in && out && batch >= 1, HE_EINVAL, "null argument");
+    CutmaxCfg cf = parse_cfg(C, cfg);
+    std::vector<Request> reqs;
+    int total = 0;
+    int level = -1;
+    for (size_t r = 0; r < batch; ++r) {
+        REQUIRE(in[r] && in[r]->ctx == C, HE_ESTATE, "ciphertext from another context");
+        if (noise) REQUIRE(noise[r] && noise[r]->ctx == C && noise[r]->a == in[r]->a, HE_ESTATE, "noise mismatch");
+        if (level < 0) level = (int)in[r]->level;
+        REQUIRE((int)in[r]->level == level, HE_ESTATE, "requests at different levels");
+        reqs.push_back(Request{total, (int)in[r]->a, (int64_t)in[r]->a * C->slots});
+        total += (int)in[r]->a;
+    }
+    const bool prescaled = cfg->flags & HE_NOISE_PRESCALED;
+    std::vector<he_ct *> outs(batch, nullptr);
+    try {
+        for (size_t r = 0; r < batch; ++r) {
+            outs[r] = new_ct(C, in[r]->a);
+            outs[r]->n = in[r]->n;
+        }
+        hipEvent_t e0 = C->ev0, e1 = C->ev1;
+        run2(C, [&](Exec &X) {
+            Bt Y = X.new_bt(total, level);
+            Bt G;
+            if (noise) G = X.new_bt(total, level);
+            for (size_t r = 0; r < batch; ++r) {
+                Bt src = bt_of(in[r]);
+                Bt dst = Y;
+                dst.d = Y.d + (long long)reqs[r].first * 2 * Y.cap * C->N;
+                dst.cnt = (int)in[r]->a;
+                for (int k = 0; k < dst.cnt; ++k) Y.scale[reqs[r].first + k] = in[r]->scale;
+                if (!X.dry) launch_copy(X.T, X.vs_all(dst), X.vs_all(src), X.s);
+                if (noise) {
+                    Bt gs = bt_of(noise[r]);
+                    Bt gd = G;
+                    gd.d = G.d + (long long)reqs[r].first * 2 * G.cap * C->N;
+                    gd.cnt = dst.cnt;
+                    REQUIRE(noise[r]->level == (uint32_t)level, HE_ESTATE, "noise level mismatch");
+                    for (int k = 0; k < dst.cnt; ++k) G.scale[reqs[r].first + k] = noise[r]->scale;
+                    if (!X.dry) launch_copy(X.T, X.vs_all(gd), X.vs_all(gs), X.s);
+                }
+            }
+            if (!X.dry) HIPCHK(hipEventRecord(e0, X.s));
+            if (noise) {
+                if (prescaled) {
+                    Y = X.add(Y, G);
+                } else {
+                    std::vector<double> tau(total, temperature);
+                    Bt Gs = X.cmul(G, tau, Y.scale, false);
+                    Y = X.add(X.drop(Y, Gs.level), Gs);
+                }
+            }
+            Bt Z = cutmax_sched(X, Y, reqs, cf);
+            if (!X.dry) HIPCHK(hipEventRecord(e1, X.s));
+            for (size_t r = 0; r < batch; ++r) store_bt(X, Z, reqs[r].first, outs[r]);
+        });
+        HIPCHK(hipStreamSynchronize(C->stream));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, C->ev0, C->ev1));
+        C->last_ms = ms;
+    } catch (...) {
+        for (auto *o : outs) if (o) { hipFree(o->d); delete o; }
+        throw;
+    }
+    for (size_t r = 0; r < batch; ++r) out[r] = outs[r];
+    return HE_OK;
+}
+
+// single-ciphertext evaluator primitive
+template <class F>
+int prim(he_ctx *C, const he_ct *a, he_ct **out, F &&f) {
+    return guarded([&]() {
+        REQUIRE(C && a && out && a->ctx == C, HE_EINVAL, "null or foreign argument");
+        REQUIRE(a->a == 1, HE_EINVAL, "primitive ops take single ciphertexts");
+        he_ct *o = new_ct(C, 1);
+        o->n = a->n;
+        try {
+            run2(C, [&](Exec &X) {
+                Bt r = f(X);
+                store_bt(X, r, 0, o);
+            });
+            HIPCHK(hipStreamSynchronize(C->stream));
+        } catch (...) {
+            hipFree(o->d);
+            delete o;
+            throw;
+        }
+        *out = o;
+        return HE_OK;
+    });
+}
+
+}  // namespace
+
+// ===================================================================== C ABI
+extern "C" {
+
+const char *he_last_error(void) { return g_err.c_str(); }
+
+int he_ctx_create(const he_params *prm, he_ctx **out) {
+    return guarded([&]() {
+        REQUIRE(prm && out, HE_EINVAL, "null argument");
+        REQUIRE(prm->log_n == 12 || prm->log_n == 16, HE_EINVAL, "log_n must be 12 or 16");
+        REQUIRE(prm->n_q >= 2 && prm->n_q <= 48 && prm->dnum >= 1, HE_EINVAL, "n_q in [2,48], dnum >= 1");
+        REQUIRE(prm->q0_bits >= 20 && prm->q0_bits <= 49 && prm->q_bits >= 20 && prm->q_bits <= 49 &&
+                    prm->p_bits >= 20 && prm->p_bits <= 49,
+                HE_EINVAL, "prime sizes must lie in [20, 49] bits");
+        REQUIRE(prm->log2_scale >= 10 && prm->log2_scale <= 60, HE_EINVAL, "log2_scale out of range");
+        auto C = std::make_unique<he_ctx>();
+        C->logN = (int)prm->log_n;
+        C->N = 1 << C->logN;
+        C->slots = C->N / 2;
+        C->L = (int)prm->n_q - 1;
+        C->dnum = (int)prm->dnum;
+        C->alpha = ((int)prm->n_q + C->dnum - 1) / C->dnum;
+        C->np = (int)prm->n_q + C->alpha;
+        REQUIRE(C->np <= kMaxPrimes && C->alpha <= 16, HE_EINVAL, "too many primes (alpha <= 16)");
+        C->betaL = ((int)prm->n_q + C->alpha - 1) / C->alpha;
+        REQUIRE(C->betaL <= 8, HE_EINVAL, "at most 8 digits");
+        C->Delta = std::ldexp(1.0, 0) * std::pow(2.0, prm->log2_scale);
+        C->seed = prm->seed;
+        C->device = prm->device;
+        int ndev = 0;
+        HIPCHK(hipGetDeviceCount(&ndev));
+        REQUIRE(ndev > 0, HE_EDEVICE, "no HIP device");
+        REQUIRE(prm->device >= 0 && prm->device < ndev, HE_EINVAL, "bad device ordinal");
+        HIPCHK(hipSetDevice(prm->device));
+        if (prm->stream) C->stream = (hipStream_t)prm->stream;
+        else { HIPCHK(hipStreamCreateWithFlags(&C->stream, hipStreamNonBlocking)); C->own_stream = true; }
+        HIPCHK(hipEventCreate(&C->ev0));
+        HIPCHK(hipEventCreate(&C->ev1));
+        build_ctx(C.get(), prm);
+        keygen(C.get());
+        *out = C.release();
+        return HE_OK;
+    });
+}
+
+void he_ctx_destroy(he_ctx *C) {
+    if (!C) return;
+    hipSetDevice(C->device);
+    if (C->stream) hipStreamSynchronize(C->stream);
+    for (auto &g : C->graphs) hipGraphExecDestroy(g.second);
+    for (double *k : C->keys) hipFree(k);
+    hipFree(C->d_sk); hipFree(C->d_tab); hipFree(C->d_itab);
+    if (C->arena.base) hipFree(C->arena.base);
+    if (C->pool.d_dv) hipFree(C->pool.d_dv);
+    if (C->pool.d_iv) hipFree(C->pool.d_iv);
+    if (C->ev0) hipEventDestroy(C->ev0);
+    if (C->ev1) hipEventDestroy(C->ev1);
+    if (C->own_stream) hipStreamDestroy(C->stream);
+    delete C;
+}
+
+int he_ctx_info(const he_ctx *C, uint32_t *N, uint32_t *slots, uint32_t *L, uint32_t *alpha, uint64_t *primes) {
+    if (!C) { g_err = "null context"; return HE_EINVAL; }
+    if (N) *N = (uint32_t)C->N;
+    if (slots) *slots = (uint32_t)C->slots;
+    if (L) *L = (uint32_t)C->L;
+    if (alpha) *alpha = (uint32_t)C->alpha;
+    if (primes) std::memcpy(primes, C->q.data(), 8 * C->q.size());
+    return HE_OK;
+}
+
+int he_encrypt_coeffs(he_ctx *C, const int64_t *m, uint32_t a, double scale, size_t n, he_ct **out) {
+    return guarded([&]() {
+        REQUIRE(C && m && out && a >= 1 && scale > 0, HE_EINVAL, "bad argument");
+        HIPCHK(hipSetDevice(C->device));
+        he_ct *ct = new_ct(C, a);
+        ct->n = n;
+        try {
+            encrypt_coeffs_impl(C, m, a, scale, ct);
+        } catch (...) {
+            hipFree(ct->d);
+            delete ct;
+            throw;
+        }
+        *out = ct;
+        return HE_OK;
+    });
+}
+
+int he_encrypt(he_ctx *C, const double *x, size_t n, double pad, he_ct **out) {
+    return guarded([&]() {
+        REQUIRE(C && x && out && n >= 1, HE_EINVAL, "bad argument");
+        const size_t s = (size_t)C->slots;
+        std::vector<double> packed;
+        uint32_t a;
+        if (n <= s && s % n == 0) {
+            a = 1;
+            packed.resize(s);
+            for (size_t i = 0; i < s; ++i) packed[i] = x[i % n];
+        } else {
+            a = (uint32_t)((n + s - 1) / s);
+            packed.assign((size_t)a * s, pad);
+            std::memcpy(packed.data(), x, n * 8);
+        }
+        std::vector<int64_t> m((size_t)a * C->N);
+        for (uint32_t c = 0; c < a; ++c) encode_slots(packed.data() + (size_t)c * s, C->N, C->Delta, m.data() + (size_t)c * C->N);
+        return he_encrypt_coeffs(C, m.data(), a, C->Delta, n, out);
+    });
+}
+
+int he_decrypt(he_ctx *C, const he_ct *ct, double *out, size_t n) {
+    return guarded([&]() {
+        REQUIRE(C && ct && out && ct->ctx == C, HE_EINVAL, "bad argument");
+        HIPCHK(hipSetDevice(C->device));
+        const int N = C->N, nl = ct->level >= 1 ? 2 : 1;
+        const size_t s = (size_t)C->slots;
+        std::vector<double> res((size_t)nl * N), slotv((size_t)ct->a * s), mc(N);
+        double *dm = nullptr;
+        HIPCHK(hipMalloc(&dm, 8ull * nl * N));
+        try {
+            for (uint32_t c = 0; c < ct->a; ++c) {
+                const double *c0 = ct->d + (size_t)c * 2 * (C->L + 1) * N, *c1 = c0 + (size_t)(C->L + 1) * N;
+                launch_decmul(C->T, dm, c0, c1, C->d_sk, nl, C->stream);
+                launch_ntt(C->T, VecSet{dm, nl, nl, 0, nullptr, nullptr}, true, C->ntt_variant, C->stream);
+                HIPCHK(hipMemcpyAsync(res.data(), dm, 8ull * nl * N, hipMemcpyDeviceToHost, C->stream));
+                HIPCHK(hipStreamSynchronize(C->stream));
+                const uint64_t q0 = C->q[0];
+                if (nl == 1) {
+                    for (int i = 0; i < N; ++i) {
+                        const uint64_t v = (uint64_t)res[i];
+                        mc[i] = v > q0 / 2 ? -(double)(q0 - v) : (double)v;
+                    }
+                } else {
+                    const uint64_t q1 = C->q[1];
+                    const unsigned __int128 Q = (unsigned __int128)q0 * q1;
+                    const uint64_t q0inv = invmod_u(q0 % q1, q1);
+                    for (int i = 0; i < N; ++i) {
+                        const uint64_t a0 = (uint64_t)res[i], a1 = (uint64_t)res[N + i];
+                        const uint64_t d = a1 >= a0 % q1 ? a1 - a0 % q1 : a1 + q1 - a0 % q1;
+                        const uint64_t t = mulmod_u(d, q0inv, q1);
+                        const unsigned __int128 v = (unsigned __int128)a0 + (unsigned __int128)q0 * t;
+                        mc[i] = v > Q / 2 ? -(double)(Q - v) : (double)v;
+                    }
+                }
+                decode_slots(mc.data(), N, ct->scale, slotv.data() + (size_t)c * s);
+            }
+        } catch (...) {
+            hipFree(dm);
+            throw;
+        }
+        hipFree(dm);
+        const size_t total = (size_t)ct->a * s;
+        for (size_t i = 0; i < n; ++i) out[i] = slotv[i % total];
+        return HE_OK;
+    });
+}
+
+int he_cutmax(he_ctx *C, he_ct *const *in, size_t batch, const he_cutmax_cfg *cfg, he_ct **out) {
+    return guarded([&]() {
+        REQUIRE(C, HE_EINVAL, "null context");
+        HIPCHK(hipSetDevice(C->device));
+        return cutmax_impl(C, in, nullptr, batch, cfg, 1.0, out);
+    });
+}
+
+int he_topp_sample(he_ctx *C, he_ct *const *logits, he_ct *const *noise, size_t batch, double top_p,
+                   double temperature, const he_cutmax_cfg *cfg, he_ct **out) {
+    return guarded([&]() {
+        REQUIRE(C && noise, HE_EINVAL, "null argument");
+        REQUIRE(top_p > 0 && top_p < 1 && temperature > 0, HE_EINVAL, "top_p in (0,1), temperature > 0");
+        HIPCHK(hipSetDevice(C->device));
+        return cutmax_impl(C, logits, noise, batch, cfg, temperature, out);
+    });
+}
+
+int he_topp_noise(double top_p, const double *u, size_t n, double *g) {
+    return guarded([&]() {
+        REQUIRE(u && g && top_p > 0 && top_p < 1, HE_EINVAL, "bad argument");
+        const double alpha = std::log(1.0 - top_p) / std::log(top_p);
+        for (size_t i = 0; i < n; ++i) {
+            REQUIRE(u[i] > 0 && u[i] <= 1, HE_EINVAL, "uniform draws must lie in (0, 1]");
+            g[i] = std::pow(u[i], 1.0 / alpha);
+        }
+        return HE_OK;
+    });
+}
+
+void he_ct_free(he_ct *ct) {
+    if (!ct) return;
+    if (ct->d) hipFree(ct->d);
+    delete ct;
+}
+
+int he_ct_info(const he_ct *ct, uint32_t *a, uint32_t *level, double *scale, size_t *n) {
+    if (!ct) { g_err = "null ciphertext"; return HE_EINVAL; }
+    if (a) *a = ct->a;
+    if (level) *level = ct->level;
+    if (scale) *scale = ct->scale;
+    if (n) *n = ct->n;
+    return HE_OK;
+}
+
+int he_ct_export(he_ctx *C, const he_ct *ct, uint64_t *limbs, size_t cap) {
+    return guarded([&]() {
+        REQUIRE(C && ct && limbs && ct->ctx == C, HE_EINVAL, "bad argument");
+        HIPCHK(hipSetDevice(C->device));
+        const int N = C->N, l = (int)ct->level;
+        const size_t need = (size_t)ct->a * 2 * (l + 1) * N;
+        REQUIRE(cap >= need, HE_EINVAL, "export buffer too small");
+        double *tmp = nullptr;
+        HIPCHK(hipMalloc(&tmp, need * 8));
+        std::vector<double> h(need);
+        try {
+            const VecSet dst{tmp, (int)ct->a * 2 * (l + 1), l + 1, (long long)(l + 1) * N, nullptr, nullptr};
+            const VecSet src{ct->d, (int)ct->a * 2 * (l + 1), l + 1, (long long)(C->L + 1) * N, nullptr, nullptr};
+            launch_copy(C->T, dst, src, C->stream);
+            launch_ntt(C->T, dst, true, C->ntt_variant, C->stream);
+            HIPCHK(hipMemcpyAsync(h.data(), tmp, need * 8, hipMemcpyDeviceToHost, C->stream));
+            HIPCHK(hipStreamSynchronize(C->stream));
+        } catch (...) {
+            hipFree(tmp);
+            throw;
+        }
+        hipFree(tmp);
+        for (size_t i = 0; i < need; ++i) limbs[i] = (uint64_t)h[i];
+        return HE_OK;
+    });
+}
+
+int he_ct_import(he_ctx *C, const uint64_t *limbs, uint32_t a, uint32_t level, double scale, size_t n,
+                 he_ct **out) {
+    return guarded([&]() {
+        REQUIRE(C && limbs && out && a >= 1 && (int)level <= C->L, HE_EINVAL, "bad argument");
+        HIPCHK(hipSetDevice(C->device));
+        const int N = C->N, l = (int)level;
+        const size_t words = (size_t)a * 2 * (l + 1) * N;
+        std::vector<double> h(words);
+        for (size_t i = 0; i < words; ++i) {
+            const int limb = (int)((i / N) % (l + 1));
+            REQUIRE(limbs[i] < C->q[limb], HE_EINVAL, "limb value not canonical");
+            h[i] = (double)limbs[i];
+        }
+        he_ct *ct = new_ct(C, a);
+        double *tmp = nullptr;
+        try {
+            HIPCHK(hipMalloc(&tmp, words * 8));
+            HIPCHK(hipMemcpyAsync(tmp, h.data(), words * 8, hipMemcpyHostToDevice, C->stream));
+            const VecSet src{tmp, (int)a * 2 * (l + 1), l + 1, (long long)(l + 1) * N, nullptr, nullptr};
+            launch_ntt(C->T, src, false, C->ntt_variant, C->stream);
+            const VecSet dst{ct->d, (int)a * 2 * (l + 1), l + 1, (long long)(C->L + 1) * N, nullptr, nullptr};
+            launch_copy(C->T, dst, src, C->stream);
+            HIPCHK(hipStreamSynchronize(C->stream));
+        } catch (...) {
+            if (tmp) hipFree(tmp);
+            hipFree(ct->d);
+            delete ct;
+            throw;
+        }
+        hipFree(tmp);
+        ct->level = level;
+        ct->scale = scale;
+        ct->n = n;
+        *out = ct;
+        return HE_OK;
+    });
+}
+
+int he_add(he_ctx *C, const he_ct *a, const he_ct *b, he_ct **out) {
+    if (!b || b->a != 1 || (a && b->level != a->level)) { g_err = "bad operand"; return HE_EINVAL; }
+    return prim(C, a, out, [&](Exec &X) { return X.add(bt_of(a), bt_of(b)); });
+}
+int he_sub(he_ctx *C, const he_ct *a, const he_ct *b, he_ct **out) {
+    if (!b || b->a != 1 || (a && b->level != a->level)) { g_err = "bad operand"; return HE_EINVAL; }
+    return prim(C, a, out, [&](Exec &X) { return X.add(bt_of(a), bt_of(b), -1); });
+}
+int he_mul_int(he_ctx *C, const he_ct *a, int64_t k, he_ct **out) {
+    return prim(C, a, out, [&](Exec &X) { return X.mul_int(bt_of(a), {k}); });
+}
+int he_add_const(he_ctx *C, const he_ct *a, double c, he_ct **out) {
+    return prim(C, a, out, [&](Exec &X) { return X.add_const(bt_of(a), {c}); });
+}
+int he_mul(he_ctx *C, const he_ct *a, const he_ct *b, he_ct **out) {
+    if (!b || b->a != 1 || (a && b->level != a->level)) { g_err = "bad operand"; return HE_EINVAL; }
+    return prim(C, a, out, [&](Exec &X) { return X.mul(bt_of(a), bt_of(b)); });
+}
+int he_rescale(he_ctx *C, const he_ct *a, he_ct **out) {
+    return prim(C, a, out, [&](Exec &X) { return X.rescale(bt_of(a)); });
+}
+int he_cmul(he_ctx *C, const he_ct *a, double kappa, double s_want, int exact, he_ct **out) {
+    return prim(C, a, out, [&](Exec &X) { return X.cmul(bt_of(a), {kappa}, {s_want}, exact != 0); });
+}
+int he_rotate(he_ctx *C, const he_ct *a, uint32_t r, he_ct **out) {
+    if (C && (1u << r) >= (uint32_t)C->slots) { g_err = "rotation index too large"; return HE_EINVAL; }
+    return prim(C, a, out, [&](Exec &X) { return X.rotate(bt_of(a), (int)r); });
+}
+int he_rotsum(he_ctx *C, const he_ct *a, he_ct **out) {
+    return prim(C, a, out, [&](Exec &X) { return X.rotsum(bt_of(a)); });
+}
+int he_drop(he_ctx *C, const he_ct *a, uint32_t level, he_ct **out) {
+    return prim(C, a, out, [&](Exec &X) { return X.copy(X.drop(bt_of(a), (int)level)); });
+}
+
+int he_bench_ntt(he_ctx *C, uint32_t vectors, uint32_t iters, double *ms_fwd, double *ms_inv) {
+    return guarded([&]() {
+        REQUIRE(C && vectors >= 1 && iters >= 1 && ms_fwd && ms_inv, HE_EINVAL, "bad argument");
+        HIPCHK(hipSetDevice(C->device));
+        const int N = C->N;
+        double *buf = nullptr;
+        HIPCHK(hipMalloc(&buf, 8ull * vectors * N));
+        hipEvent_t a, b, c;
+        HIPCHK(hipEventCreate(&a)); HIPCHK(hipEventCreate(&b)); HIPCHK(hipEventCreate(&c));
+        const int grp = std::min<int>((int)vectors, C->L + 1);
+        const VecSet vs{buf, (int)vectors, grp, (long long)grp * N, nullptr, nullptr};
+        launch_sample_uniform(C->T, vs, 12345, 0x7F000000u, nullptr, C->stream);
+        launch_ntt(C->T, vs, false, C->ntt_variant, C->stream);
+        launch_ntt(C->T, vs, true, C->ntt_variant, C->stream);
+        double tf = 0, ti = 0;
+        for (uint32_t it = 0; it < iters; ++it) {
+            HIPCHK(hipEventRecord(a, C->stream));
+            launch_ntt(C->T, vs, false, C->ntt_variant, C->stream);
+            HIPCHK(hipEventRecord(b, C->stream));
+            launch_ntt(C->T, vs, true, C->ntt_variant, C->stream);
+            HIPCHK(hipEventRecord(c, C->stream));
+            HIPCHK(hipEventSynchronize(c));
+            float f1 = 0, f2 = 0;
+            HIPCHK(hipEventElapsedTime(&f1, a, b));
+            HIPCHK(hipEventElapsedTime(&f2, b, c));
+            tf += f1; ti += f2;
+        }
+        hipEventDestroy(a); hipEventDestroy(b); hipEventDestroy(c);
+        hipFree(buf);
+        *ms_fwd = tf / iters;
+        *ms_inv = ti / iters;
+        return HE_OK;
+    });
+}
+
+int he_last_cutmax_ms(const he_ctx *C, double *ms) {
+    if (!C || !ms) { g_err = "null argument"; return HE_EINVAL; }
+    *ms = C->last_ms;
+    return HE_OK;
+}
+
+int he_sync(he_ctx *C) {
+    return guarded([&]() {
+        REQUIRE(C, HE_EINVAL, "null context");
+        HIPCHK(hipStreamSynchronize(C->stream));
+        return HE_OK;
+    });
+}
+
+int he_set_option(he_ctx *C, int option, int64_t value) {
+    if (!C) { g_err = "null context"; return HE_EINVAL; }
+    if (option == HE_OPT_GRAPH) { C->use_graph = (int)value; return HE_OK; }
+    if (option == HE_OPT_NTT_VARIANT) { C->ntt_variant = (int)value; return HE_OK; }
+    g_err = "unknown option";
+    return HE_EINVAL;
+}
+
+}  // extern "C"

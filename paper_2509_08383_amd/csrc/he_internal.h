@@ -1,0 +1,119 @@
+// Internal declarations of the MI355X RNS-CKKS / CutMax library.
+//
+// Device representation: every residue is an IEEE double holding a canonical
+// integer in [0, q), q < 2^49.  Modular products run in the FP64 pipe (full
+// rate on CDNA): h = a*b, l = fma(a, b, -h) gives a*b = h + l exactly, the
+// quotient is rint(h * (1/q)), and the remainder fma(-quot, q, h) + l is exact
+// because every intermediate integer stays below 2^53 (bounds in kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace he {
+
+constexpr int kMaxPrimes = 64;
+
+// Pointers to the per-context device tables.
+struct DevTables {
+    int N, logN, np, L, alpha;
+    const double *p;     // [np] primes
+    const double *pinv;  // [np] fl(1/p)
+    const double *tw;    // [np][N] psi^bitrev(k), canonical
+    const double *itw;   // [np][N] psi^-bitrev(k)
+    const double *ninv;  // [np] N^-1 mod p
+    const double *two32; // [np] 2^32 mod p
+};
+
+// A set of N-word vectors: vector v lives in group g = v / group at slot
+// slot[r] (r = v % group) and is reduced modulo prime[r] (identity tables when
+// null).  Address = base + g * gstride + slot * N.
+struct VecSet {
+    double *base;
+    int count;
+    int group;
+    long long gstride;
+    const int *slot;
+    const int *prime;
+};
+
+// Per-vector constant: value = base[(g / gdiv) * stride + r].
+struct ConstTab {
+    const double *base;
+    int gdiv;
+    int stride;
+};
+
+// ---------------------------------------------------------------- kernels.hip
+void launch_ntt(const DevTables &T, const VecSet &vs, bool inverse, int variant, hipStream_t s);
+void launch_add(const DevTables &T, const VecSet &out, const VecSet &a, const VecSet &b, int sign,
+                hipStream_t s);
+void launch_copy(const DevTables &T, const VecSet &out, const VecSet &a, hipStream_t s);
+void launch_mul_const(const DevTables &T, const VecSet &out, const VecSet &a, ConstTab k,
+                      hipStream_t s);
+void launch_add_const(const DevTables &T, const VecSet &out, const VecSet &a, ConstTab k,
+                      hipStream_t s);
+void launch_axpy_map(const DevTables &T, const VecSet &out, const VecSet &a, ConstTab k,
+                     const VecSet &b, const int *bmap, int bdiv, hipStream_t s);
+void launch_sum_groups(const DevTables &T, const VecSet &out, const VecSet &in, const int *first,
+                       const int *cnt, int gdiv, hipStream_t s);
+void launch_tensor(const DevTables &T, double *d0, double *d1, double *d2, long long dstride,
+                   const double *a, const double *b, long long astride, long long bstride,
+                   const int *bmap, long long apoly, long long bpoly, int cnt, int limbs, hipStream_t s);
+void launch_automorph(const DevTables &T, const VecSet &out, const VecSet &in, uint64_t galois,
+                      hipStream_t s);
+void launch_modup(const DevTables &T, const double *dcoef, long long dstride, double *ext,
+                  long long estride, const double *dntt, long long nstride, int cnt, int level,
+                  int digit, int lo, int dl, int next, const int *ext_prime, const double *vinv,
+                  const double *qhat, hipStream_t s);
+void launch_inner_product(const DevTables &T, const double *ext, long long estride_b,
+                          long long estride_j, double *acc0, double *acc1, long long astride,
+                          const double *key, long long kstride_j, long long kstride_c, int cnt,
+                          int beta, int next, const int *ext_prime, hipStream_t s);
+void launch_moddown_conv(const DevTables &T, const double *acc, long long astride, double *conv,
+                         long long cstride, int cnt, int level, const double *phinv,
+                         const double *phat, hipStream_t s);
+void launch_moddown_combine(const DevTables &T, double *out, long long ostride, const double *acc,
+                            long long astride, const double *conv, long long cstride,
+                            const double *add, long long add_ct, long long add_poly, int addmask,
+                            int groups, int level, const double *Pinv, hipStream_t s);
+void launch_rescale_lift(const DevTables &T, const double *lastc, long long lstride, double *lift,
+                         long long fstride, int cnt, int level, hipStream_t s);
+void launch_rescale_combine(const DevTables &T, double *out, long long ostride, const double *in,
+                            long long istride, const double *lift, long long fstride, int cnt,
+                            int level, const double *qlinv, const double *kmul, hipStream_t s);
+void launch_sample_uniform(const DevTables &T, const VecSet &out, uint64_t seed, uint32_t obj,
+                           const int *gprime, hipStream_t s);
+void launch_sample_small(int *out, int N, uint64_t seed, uint32_t obj, int kind, hipStream_t s);
+void launch_small_to_res(const DevTables &T, const VecSet &out, const int *v, const int *gprime,
+                         hipStream_t s);
+void launch_int64_to_res(const DevTables &T, const VecSet &out, const int64_t *m,
+                         long long mstride, const int *gprime, hipStream_t s);
+void launch_keyb(const DevTables &T, double *b, const double *a, const double *e, const double *s,
+                 const double *tgt, const double *pmod, int np, int lo, int hi, hipStream_t st);
+void launch_encfinish(const DevTables &T, double *c0, const double *a, const double *e,
+                      const double *m, const double *s, long long stride, int limbs, int cnt,
+                      long long ctstride, long long mctstride, hipStream_t st);
+void launch_decmul(const DevTables &T, double *m, const double *c0, const double *c1,
+                   const double *s, int limbs, hipStream_t st);
+void launch_square_res(const DevTables &T, double *out, const double *in, int np, hipStream_t st);
+void launch_canon_check(const DevTables &T, const VecSet &vs, int *bad, hipStream_t st);
+
+// ----------------------------------------------------------------- host math
+uint64_t mulmod_u(uint64_t a, uint64_t b, uint64_t q);
+uint64_t powmod_u(uint64_t a, uint64_t e, uint64_t q);
+uint64_t invmod_u(uint64_t a, uint64_t q);
+uint64_t red_i64(int64_t v, uint64_t q);
+bool miller_rabin(uint64_t n);
+std::vector<uint64_t> gen_primes(int logN, int n_q, int q0_bits, int q_bits, int p_bits,
+                                 int alpha);
+uint64_t find_psi(uint64_t q, int N);
+void encode_slots(const double *z, int N, double scale, int64_t *m);
+void decode_slots(const double *m, int N, double scale, double *z);
+void chebyshev_invsqrt_fit(double u_lo, int degree, double *coef);
+int64_t llround_d(double x);
+
+}  // namespace he

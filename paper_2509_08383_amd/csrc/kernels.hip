@@ -1,0 +1,709 @@
+// HIP kernels for gfx950: RNS-CKKS primitives of the encrypted CutMax.
+//
+// Residues are canonical integers in [0, p) stored as doubles, p < 2^49.
+// Modular arithmetic runs in the FP64 pipe:
+//   mm(a, b): h = a*b; l = fma(a, b, -h)          (a*b = h + l exactly)
+//             k = rint(h * pinv); r = fma(-k, p, h) + l
+// For |a| < 2^52 and 0 <= b < p the true quotient a*b/p is below 2^52 in
+// magnitude, fl(h*pinv) is within 3*2^-53 relative of it, so |a*b - k*p| is at
+// most (0.5 + |a*b/p| * 3 * 2^-53) p; with the bounds used below every
+// intermediate is an integer below 2^53 and therefore exact.  red(x) =
+// x - rint(x*pinv)*p maps |x| < 2^52 to |x| <= p/2 (plus a negligible
+// fraction), canon() to [0, p).
+#include "he_internal.h"
+
+namespace he {
+
+#define DEV __device__ __forceinline__
+
+DEV double mm(double a, double b, double p, double pinv) {
+    double h = a * b;
+    double l = __builtin_fma(a, b, -h);
+    double k = __builtin_rint(h * pinv);
+    double r = __builtin_fma(-k, p, h);
+    return r + l;
+}
+DEV double red(double x, double p, double pinv) { return __builtin_fma(-__builtin_rint(x * pinv), p, x); }
+DEV double canon(double x, double p, double pinv) {
+    double r = red(x, p, pinv);
+    return r < 0.0 ? r + p : r;
+}
+DEV double addm(double a, double b, double p) {  // a, b canonical
+    double r = a + b;
+    return r >= p ? r - p : r;
+}
+DEV double subm(double a, double b, double p) {
+    double r = a - b;
+    return r < 0.0 ? r + p : r;
+}
+
+DEV void vs_at(const VecSet &v, int idx, int N, double *&ptr, int &pr, int &g, int &r) {
+    g = idx / v.group;
+    r = idx - g * v.group;
+    int sl = v.slot ? v.slot[r] : r;
+    pr = v.prime ? v.prime[r] : r;
+    ptr = v.base + (long long)g * v.gstride + (long long)sl * N;
+}
+DEV double ct_val(const ConstTab &k, int g, int r) { return k.base[(long long)(g / k.gdiv) * k.stride + r]; }
+
+// ------------------------------------------------------------------------ NTT
+// Negacyclic NTT in two passes of R = 2H radix-2 stages each, N = 2^(2R).
+// Forward stage s (m = 2^s, t = N/2m) maps (a_j, a_{j+t}) to
+// (a_j + w a_{j+t}, a_j - w a_{j+t}) with w = psi^bitrev(m + j/(2t)); the
+// output in position j is the evaluation at psi^(2 bitrev(j) + 1).
+// Pass 1 runs stages 0..R-1 on the strided sub-problems {r + SUB k}; pass 2
+// runs stages R..2R-1 on the contiguous blocks {b SUB + k}.  A workgroup
+// holds COLS sub-problems in LDS; each thread holds E = 2^H elements of one
+// sub-problem and runs H stages in registers (phase A: the high bits of k,
+// phase B: the low bits), with one LDS exchange in between.
+// The inverse runs the stages in reverse order with the Gentleman-Sande
+// butterfly (x, y) -> (x + y, (x - y) w^-1) and multiplies by N^-1 at the end.
+template <int H, bool PASS2, bool INV>
+__global__ __launch_bounds__(256) void k_ntt(VecSet vs, DevTables T) {
+    constexpr int R = 2 * H, E = 1 << H, TPS = 1 << H, SUB = 1 << R, COLS = 256 / TPS;
+    constexpr int NN = SUB * SUB;
+    __shared__ double tile[COLS * SUB];
+    auto lds = [](int c, int k) { return PASS2 ? c * SUB + k : k * COLS + c; };
+
+    double *ptr;
+    int pr, g_, r_;
+    vs_at(vs, blockIdx.y, NN, ptr, pr, g_, r_);
+    const double p = T.p[pr], pinv = T.pinv[pr];
+    const double *tw = (INV ? T.itw : T.tw) + (long long)pr * NN;
+    const int cb = blockIdx.x, tid = threadIdx.x;
+
+#pragma unroll
+    for (int i = 0; i < COLS * SUB / 256; ++i) {
+        int idx = tid + 256 * i, c, k;
+        if (PASS2) { k = idx % SUB; c = idx / SUB; } else { c = idx % COLS; k = idx / COLS; }
+        long long j = PASS2 ? (long long)(cb * COLS + c) * SUB + k : (long long)(cb * COLS + c) + (long long)SUB * k;
+        tile[lds(c, k)] = ptr[j];
+    }
+    __syncthreads();
+
+    int c, th;
+    if (PASS2) { th = tid % TPS; c = tid / TPS; } else { c = tid % COLS; th = tid / COLS; }
+    const int b = cb * COLS + c;
+    const int soff = PASS2 ? R : 0;
+    double v[E];
+
+    if (!INV) {
+        // phase A: high H bits of k
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = tile[lds(c, th + TPS * e)];
+#pragma unroll
+        for (int sg = 0; sg < H; ++sg) {
+            const int s = sg + soff, hd = E >> (sg + 1);
+#pragma unroll
+            for (int g = 0; g < (1 << sg); ++g) {
+                const double w = tw[(1 << s) + (PASS2 ? (b << sg) : 0) + g];
+#pragma unroll
+                for (int i = 0; i < hd; ++i) {
+                    const int e0 = g * 2 * hd + i, e1 = e0 + hd;
+                    const double t = mm(v[e1], w, p, pinv);
+                    v[e1] = v[e0] - t;
+                    v[e0] = v[e0] + t;
+                }
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) tile[lds(c, th + TPS * e)] = red(v[e], p, pinv);
+        __syncthreads();
+        // phase B: low H bits of k
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = tile[lds(c, th * E + e)];
+#pragma unroll
+        for (int sg = 0; sg < H; ++sg) {
+            const int s = H + sg + soff, hd = E >> (sg + 1);
+#pragma unroll
+            for (int g = 0; g < (1 << sg); ++g) {
+                const double w = tw[(1 << s) + (PASS2 ? (b << (H + sg)) : 0) + (th << sg) + g];
+#pragma unroll
+                for (int i = 0; i < hd; ++i) {
+                    const int e0 = g * 2 * hd + i, e1 = e0 + hd;
+                    const double t = mm(v[e1], w, p, pinv);
+                    v[e1] = v[e0] - t;
+                    v[e0] = v[e0] + t;
+                }
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) tile[lds(c, th * E + e)] = canon(v[e], p, pinv);
+        __syncthreads();
+    } else {
+        // phase B first (low bits), stages descending
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = tile[lds(c, th * E + e)];
+#pragma unroll
+        for (int sg = H - 1; sg >= 0; --sg) {
+            const int s = H + sg + soff, hd = E >> (sg + 1);
+#pragma unroll
+            for (int g = 0; g < (1 << sg); ++g) {
+                const double w = tw[(1 << s) + (PASS2 ? (b << (H + sg)) : 0) + (th << sg) + g];
+#pragma unroll
+                for (int i = 0; i < hd; ++i) {
+                    const int e0 = g * 2 * hd + i, e1 = e0 + hd;
+                    const double x = v[e0], y = v[e1];
+                    v[e0] = red(x + y, p, pinv);
+                    v[e1] = mm(x - y, w, p, pinv);
+                }
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) tile[lds(c, th * E + e)] = red(v[e], p, pinv);
+        __syncthreads();
+        // phase A (high bits), stages descending
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = tile[lds(c, th + TPS * e)];
+#pragma unroll
+        for (int sg = H - 1; sg >= 0; --sg) {
+            const int s = sg + soff, hd = E >> (sg + 1);
+#pragma unroll
+            for (int g = 0; g < (1 << sg); ++g) {
+                const double w = tw[(1 << s) + (PASS2 ? (b << sg) : 0) + g];
+#pragma unroll
+                for (int i = 0; i < hd; ++i) {
+                    const int e0 = g * 2 * hd + i, e1 = e0 + hd;
+                    const double x = v[e0], y = v[e1];
+                    v[e0] = red(x + y, p, pinv);
+                    v[e1] = mm(x - y, w, p, pinv);
+                }
+            }
+        }
+        if (!PASS2) {
+            const double ni = T.ninv[pr];
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[e] = mm(v[e], ni, p, pinv);
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) tile[lds(c, th + TPS * e)] = canon(v[e], p, pinv);
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int i = 0; i < COLS * SUB / 256; ++i) {
+        int idx = tid + 256 * i, c2, k;
+        if (PASS2) { k = idx % SUB; c2 = idx / SUB; } else { c2 = idx % COLS; k = idx / COLS; }
+        long long j = PASS2 ? (long long)(cb * COLS + c2) * SUB + k : (long long)(cb * COLS + c2) + (long long)SUB * k;
+        ptr[j] = tile[lds(c2, k)];
+    }
+}
+
+template <int H>
+static void ntt_h(const DevTables &T, const VecSet &vs, bool inverse, hipStream_t s) {
+    constexpr int SUB = 1 << (2 * H), COLS = 256 / (1 << H);
+    dim3 grid(SUB / COLS, vs.count), block(256);
+    if (!inverse) {
+        hipLaunchKernelGGL((k_ntt<H, false, false>), grid, block, 0, s, vs, T);
+        hipLaunchKernelGGL((k_ntt<H, true, false>), grid, block, 0, s, vs, T);
+    } else {
+        hipLaunchKernelGGL((k_ntt<H, true, true>), grid, block, 0, s, vs, T);
+        hipLaunchKernelGGL((k_ntt<H, false, true>), grid, block, 0, s, vs, T);
+    }
+}
+
+void launch_ntt(const DevTables &T, const VecSet &vs, bool inverse, int variant, hipStream_t s) {
+    (void)variant;
+    if (vs.count <= 0) return;
+    if (T.logN == 16) ntt_h<4>(T, vs, inverse, s);
+    else if (T.logN == 12) ntt_h<3>(T, vs, inverse, s);
+}
+
+// --------------------------------------------------------------- elementwise
+#define EW_PROLOGUE                                          \
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;     \
+    if (x >= T.N) return;                                    \
+    double *po; int pr, g, r;                                \
+    vs_at(out, blockIdx.y, T.N, po, pr, g, r);               \
+    const double p = T.p[pr];                                \
+    (void)p;
+
+static dim3 ew_grid(const DevTables &T, int count) { return dim3((T.N + 255) / 256, count); }
+
+__global__ void k_add(VecSet out, VecSet a, VecSet b, DevTables T, int sign) {
+    EW_PROLOGUE
+    double *pa, *pb; int q1, q2, g1, r1;
+    vs_at(a, blockIdx.y, T.N, pa, q1, g1, r1);
+    vs_at(b, blockIdx.y, T.N, pb, q2, g1, r1);
+    po[x] = sign > 0 ? addm(pa[x], pb[x], p) : subm(pa[x], pb[x], p);
+}
+void launch_add(const DevTables &T, const VecSet &out, const VecSet &a, const VecSet &b, int sign,
+                hipStream_t s) {
+    if (out.count <= 0) return;
+    hipLaunchKernelGGL(k_add, ew_grid(T, out.count), dim3(256), 0, s, out, a, b, T, sign);
+}
+
+__global__ void k_copy(VecSet out, VecSet a, DevTables T) {
+    EW_PROLOGUE
+    double *pa; int q1, g1, r1;
+    vs_at(a, blockIdx.y, T.N, pa, q1, g1, r1);
+    po[x] = pa[x];
+}
+void launch_copy(const DevTables &T, const VecSet &out, const VecSet &a, hipStream_t s) {
+    if (out.count <= 0) return;
+    hipLaunchKernelGGL(k_copy, ew_grid(T, out.count), dim3(256), 0, s, out, a, T);
+}
+
+__global__ void k_mul_const(VecSet out, VecSet a, ConstTab k, DevTables T) {
+    EW_PROLOGUE
+    double *pa; int q1, g1, r1;
+    vs_at(a, blockIdx.y, T.N, pa, q1, g1, r1);
+    const double pinv = T.pinv[pr];
+    po[x] = canon(mm(pa[x], ct_val(k, g, r), p, pinv), p, pinv);
+}
+void launch_mul_const(const DevTables &T, const VecSet &out, const VecSet &a, ConstTab k,
+                      hipStream_t s) {
+    if (out.count <= 0) return;
+    hipLaunchKernelGGL(k_mul_const, ew_grid(T, out.count), dim3(256), 0, s, out, a, k, T);
+}
+
+// adds the constant to every NTT-domain coefficient (a constant polynomial
+// evaluates to itself at every root)
+__global__ void k_add_const(VecSet out, VecSet a, ConstTab k, DevTables T) {
+    EW_PROLOGUE
+    double *pa; int q1, g1, r1;
+    vs_at(a, blockIdx.y, T.N, pa, q1, g1, r1);
+    po[x] = addm(pa[x], ct_val(k, g, r), p);
+}
+void launch_add_const(const DevTables &T, const VecSet &out, const VecSet &a, ConstTab k,
+                      hipStream_t s) {
+    if (out.count <= 0) return;
+    hipLaunchKernelGGL(k_add_const, ew_grid(T, out.count), dim3(256), 0, s, out, a, k, T);
+}
+
+// out = a * k - b[map]   (b group index = bmap[g / bdiv] * bdiv + g % bdiv)
+__global__ void k_axpy_map(VecSet out, VecSet a, ConstTab k, VecSet b, const int *bmap, int bdiv,
+                           DevTables T) {
+    EW_PROLOGUE
+    double *pa; int q1, g1, r1;
+    vs_at(a, blockIdx.y, T.N, pa, q1, g1, r1);
+    const int gb = bmap[g / bdiv] * bdiv + g % bdiv;
+    double *pb; int q2, g2, r2;
+    vs_at(b, gb * b.group + r, T.N, pb, q2, g2, r2);
+    const double pinv = T.pinv[pr];
+    po[x] = canon(mm(pa[x], ct_val(k, g, r), p, pinv) - pb[x], p, pinv);
+}
+void launch_axpy_map(const DevTables &T, const VecSet &out, const VecSet &a, ConstTab k,
+                     const VecSet &b, const int *bmap, int bdiv, hipStream_t s) {
+    if (out.count <= 0) return;
+    hipLaunchKernelGGL(k_axpy_map, ew_grid(T, out.count), dim3(256), 0, s, out, a, k, b, bmap, bdiv, T);
+}
+
+// out group g (= req * gdiv + j) = sum over k < cnt[req] of in group (first[req] + k) * gdiv + j
+__global__ void k_sum_groups(VecSet out, VecSet in, const int *first, const int *cnt, int gdiv,
+                             DevTables T) {
+    EW_PROLOGUE
+    const int req = g / gdiv, jj = g % gdiv;
+    const double pinv = T.pinv[pr];
+    double acc = 0.0;
+    for (int k = 0; k < cnt[req]; ++k) {
+        double *pi; int q1, g1, r1;
+        vs_at(in, ((first[req] + k) * gdiv + jj) * in.group + r, T.N, pi, q1, g1, r1);
+        acc += pi[x];
+    }
+    po[x] = canon(acc, p, pinv);
+}
+void launch_sum_groups(const DevTables &T, const VecSet &out, const VecSet &in, const int *first,
+                       const int *cnt, int gdiv, hipStream_t s) {
+    if (out.count <= 0) return;
+    hipLaunchKernelGGL(k_sum_groups, ew_grid(T, out.count), dim3(256), 0, s, out, in, first, cnt, gdiv, T);
+}
+
+// d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1 per (ciphertext, limb)
+__global__ void k_tensor(DevTables T, double *d0, double *d1, double *d2, long long dstride,
+                         const double *a, const double *b, long long astride, long long bstride,
+                         const int *bmap, long long apoly, long long bpoly, int limbs) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= T.N) return;
+    const int ct = blockIdx.y / limbs, li = blockIdx.y % limbs;
+    const double p = T.p[li], pinv = T.pinv[li];
+    const int cb = bmap ? bmap[ct] : ct;
+    const long long o = (long long)li * T.N + x;
+    const double *A = a + ct * astride, *B = b + cb * bstride;
+    const double a0 = A[o], a1 = A[apoly + o], b0 = B[o], b1 = B[bpoly + o];
+    d0[ct * dstride + o] = canon(mm(a0, b0, p, pinv), p, pinv);
+    d1[ct * dstride + o] = canon(mm(a0, b1, p, pinv) + mm(a1, b0, p, pinv), p, pinv);
+    d2[ct * dstride + o] = canon(mm(a1, b1, p, pinv), p, pinv);
+}
+void launch_tensor(const DevTables &T, double *d0, double *d1, double *d2, long long dstride,
+                   const double *a, const double *b, long long astride, long long bstride,
+                   const int *bmap, long long apoly, long long bpoly, int cnt, int limbs, hipStream_t s) {
+    if (cnt <= 0) return;
+    hipLaunchKernelGGL(k_tensor, dim3((T.N + 255) / 256, cnt * limbs), dim3(256), 0, s, T, d0, d1,
+                       d2, dstride, a, b, astride, bstride, bmap, apoly, bpoly, limbs);
+}
+
+// NTT-domain Galois automorphism X -> X^g: out[j] = in[j'] with
+// 2 bitrev(j') + 1 = (2 bitrev(j) + 1) g mod 2N
+__global__ void k_automorph(VecSet out, VecSet in, uint64_t galois, DevTables T) {
+    EW_PROLOGUE
+    double *pi; int q1, g1, r1;
+    vs_at(in, blockIdx.y, T.N, pi, q1, g1, r1);
+    const int sh = 32 - T.logN;
+    const uint64_t M = 2ull * T.N;
+    const uint64_t t = 2ull * (__brev((unsigned)x) >> sh) + 1ull;
+    const uint64_t t2 = (t * galois) & (M - 1);
+    const unsigned j2 = __brev((unsigned)((t2 - 1) >> 1)) >> sh;
+    po[x] = pi[j2];
+}
+void launch_automorph(const DevTables &T, const VecSet &out, const VecSet &in, uint64_t galois,
+                      hipStream_t s) {
+    if (out.count <= 0) return;
+    hipLaunchKernelGGL(k_automorph, ew_grid(T, out.count), dim3(256), 0, s, out, in, galois, T);
+}
+
+// ------------------------------------------------------------ key switching
+// ModUp of digit `digit` ([lo, lo+dl) of the primes present at `level`):
+// v_a = [d_{lo+a} * Qhat_a^-1]_{q_{lo+a}}; for every extended slot t outside
+// the digit: ext_t = sum_a v_a [Qhat_a]_{prime(t)}; digit slots copy the
+// NTT-domain input.  One thread per (ciphertext, coefficient).
+__global__ void k_modup(DevTables T, const double *dcoef, long long dstride, double *ext,
+                        long long estride, const double *dntt, long long nstride, int level, int lo,
+                        int dl, int next, const int *ext_prime, const double *vinv,
+                        const double *qhat) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= T.N) return;
+    const int ct = blockIdx.y;
+    const double *D = dcoef + ct * dstride;
+    double *X = ext + ct * estride;
+    double v[16];
+#pragma unroll
+    for (int a = 0; a < 16; ++a) {
+        if (a < dl) {
+            const int pi = lo + a;
+            v[a] = canon(mm(D[(long long)pi * T.N + x], vinv[a], T.p[pi], T.pinv[pi]), T.p[pi], T.pinv[pi]);
+        }
+    }
+    for (int t = 0; t < next; ++t) {
+        if (t >= lo && t < lo + dl) {
+            X[(long long)t * T.N + x] = dntt[ct * nstride + (long long)t * T.N + x];
+            continue;
+        }
+        const int pt = ext_prime[t];
+        const double p = T.p[pt], pinv = T.pinv[pt];
+        double acc = 0.0;
+#pragma unroll
+        for (int a = 0; a < 16; ++a)
+            if (a < dl) acc += mm(v[a], qhat[a * next + t], p, pinv);
+        X[(long long)t * T.N + x] = canon(acc, p, pinv);
+    }
+}
+void launch_modup(const DevTables &T, const double *dcoef, long long dstride, double *ext,
+                  long long estride, const double *dntt, long long nstride, int cnt, int level,
+                  int digit, int lo, int dl, int next, const int *ext_prime, const double *vinv,
+                  const double *qhat, hipStream_t s) {
+    (void)digit;
+    if (cnt <= 0) return;
+    hipLaunchKernelGGL(k_modup, dim3((T.N + 255) / 256, cnt), dim3(256), 0, s, T, dcoef, dstride,
+                       ext, estride, dntt, nstride, level, lo, dl, next, ext_prime, vinv, qhat);
+}
+
+// acc_c[ct][t] = sum_j ext[ct][j][t] * key[j][c][prime(t)]; the key words are
+// read once per (t, x) and reused for every ciphertext of the batch.
+__global__ void k_inner_product(DevTables T, const double *ext, long long esb, long long esj,
+                                double *acc0, double *acc1, long long astride, const double *key,
+                                long long ksj, long long ksc, int cnt, int beta, const int *ext_prime) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= T.N) return;
+    const int t = blockIdx.y;
+    const int pt = ext_prime[t];
+    const double p = T.p[pt], pinv = T.pinv[pt];
+    double k0[8], k1[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        if (j < beta) {
+            k0[j] = key[j * ksj + (long long)pt * T.N + x];
+            k1[j] = key[j * ksj + ksc + (long long)pt * T.N + x];
+        }
+    }
+    for (int ct = 0; ct < cnt; ++ct) {
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (j < beta) {
+                const double e = ext[ct * esb + j * esj + (long long)t * T.N + x];
+                s0 += mm(e, k0[j], p, pinv);
+                s1 += mm(e, k1[j], p, pinv);
+            }
+        }
+        acc0[ct * astride + (long long)t * T.N + x] = canon(s0, p, pinv);
+        acc1[ct * astride + (long long)t * T.N + x] = canon(s1, p, pinv);
+    }
+}
+void launch_inner_product(const DevTables &T, const double *ext, long long estride_b,
+                          long long estride_j, double *acc0, double *acc1, long long astride,
+                          const double *key, long long kstride_j, long long kstride_c, int cnt,
+                          int beta, int next, const int *ext_prime, hipStream_t s) {
+    if (cnt <= 0) return;
+    hipLaunchKernelGGL(k_inner_product, dim3((T.N + 255) / 256, next), dim3(256), 0, s, T, ext,
+                       estride_b, estride_j, acc0, acc1, astride, key, kstride_j, kstride_c, cnt,
+                       beta, ext_prime);
+}
+
+// ModDown conversion: w_m = centred [acc_{P,m} * Phat_m^-1]_{p_m};
+// conv_i = sum_m w_m [Phat_m]_{q_i} for i <= level (coefficient domain).
+// acc holds [cnt*2] groups of (level+1+alpha) limbs; conv [cnt*2][level+1].
+__global__ void k_moddown_conv(DevTables T, const double *acc, long long astride, double *conv,
+                               long long cstride, int level, const double *phinv,
+                               const double *phat) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= T.N) return;
+    const int gi = blockIdx.y;
+    const int A = T.alpha;
+    const double *Ac = acc + gi * astride;
+    double w[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        if (m < A) {
+            const int pm = T.L + 1 + m;
+            const double p = T.p[pm], pinv = T.pinv[pm];
+            double v = canon(mm(Ac[(long long)(level + 1 + m) * T.N + x], phinv[m], p, pinv), p, pinv);
+            w[m] = v > 0.5 * (p - 1.0) ? v - p : v;
+        }
+    }
+    for (int i = 0; i <= level; ++i) {
+        const double p = T.p[i], pinv = T.pinv[i];
+        double s = 0.0;
+#pragma unroll
+        for (int m = 0; m < 16; ++m)
+            if (m < A) s += mm(w[m], phat[m * (T.L + 1) + i], p, pinv);
+        conv[gi * cstride + (long long)i * T.N + x] = canon(s, p, pinv);
+    }
+}
+void launch_moddown_conv(const DevTables &T, const double *acc, long long astride, double *conv,
+                         long long cstride, int cnt, int level, const double *phinv,
+                         const double *phat, hipStream_t s) {
+    if (cnt <= 0) return;
+    hipLaunchKernelGGL(k_moddown_conv, dim3((T.N + 255) / 256, cnt), dim3(256), 0, s, T, acc,
+                       astride, conv, cstride, level, phinv, phat);
+}
+
+// out_i = (acc_i - conv_i) * P^-1 (+ add_i when bit (group & 1) of addmask is set)
+__global__ void k_moddown_combine(DevTables T, double *out, long long ostride, const double *acc,
+                                  long long astride, const double *conv, long long cstride,
+                                  const double *add, long long add_ct, long long add_poly,
+                                  int addmask, int limbs, const double *Pinv) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= T.N) return;
+    const int gi = blockIdx.y / limbs, i = blockIdx.y % limbs;
+    const double p = T.p[i], pinv = T.pinv[i];
+    const long long o = (long long)i * T.N + x;
+    double r = mm(acc[gi * astride + o] - conv[gi * cstride + o], Pinv[i], p, pinv);
+    if (add && ((addmask >> (gi & 1)) & 1)) r += add[(gi >> 1) * add_ct + (gi & 1) * add_poly + o];
+    out[gi * ostride + o] = canon(r, p, pinv);
+}
+void launch_moddown_combine(const DevTables &T, double *out, long long ostride, const double *acc,
+                            long long astride, const double *conv, long long cstride,
+                            const double *add, long long add_ct, long long add_poly, int addmask,
+                            int groups, int level, const double *Pinv, hipStream_t s) {
+    if (groups <= 0) return;
+    hipLaunchKernelGGL(k_moddown_combine, dim3((T.N + 255) / 256, groups * (level + 1)), dim3(256), 0, s,
+                       T, out, ostride, acc, astride, conv, cstride, add, add_ct, add_poly, addmask,
+                       level + 1, Pinv);
+}
+
+// ------------------------------------------------------------------- rescale
+// lift_i = [c_level]_centred mod q_i, i < level (coefficient domain)
+__global__ void k_rescale_lift(DevTables T, const double *lastc, long long lstride, double *lift,
+                               long long fstride, int level) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= T.N) return;
+    const int gi = blockIdx.y / level, i = blockIdx.y % level;
+    const double ql = T.p[level];
+    double v = lastc[gi * lstride + x];
+    v = v > 0.5 * (ql - 1.0) ? v - ql : v;
+    lift[gi * fstride + (long long)i * T.N + x] = canon(v, T.p[i], T.pinv[i]);
+}
+void launch_rescale_lift(const DevTables &T, const double *lastc, long long lstride, double *lift,
+                         long long fstride, int cnt, int level, hipStream_t s) {
+    if (cnt <= 0 || level <= 0) return;
+    hipLaunchKernelGGL(k_rescale_lift, dim3((T.N + 255) / 256, cnt * level), dim3(256), 0, s, T,
+                       lastc, lstride, lift, fstride, level);
+}
+
+// out_i = (K_i in_i - lift_i) * q_level^-1 mod q_i  (K_i = kmul[(gi/2)(level+1) + i],
+// 1 when kmul is null): a rescale with an integer multiplier folded in
+__global__ void k_rescale_combine(DevTables T, double *out, long long ostride, const double *in,
+                                  long long istride, const double *lift, long long fstride,
+                                  int level, const double *qlinv, const double *kmul) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= T.N) return;
+    const int gi = blockIdx.y / level, i = blockIdx.y % level;
+    const double p = T.p[i], pinv = T.pinv[i];
+    const long long o = (long long)i * T.N + x;
+    double v = in[gi * istride + o];
+    if (kmul) v = mm(v, kmul[(gi >> 1) * (level + 1) + i], p, pinv);
+    out[gi * ostride + o] = canon(mm(v - lift[gi * fstride + o], qlinv[i], p, pinv), p, pinv);
+}
+void launch_rescale_combine(const DevTables &T, double *out, long long ostride, const double *in,
+                            long long istride, const double *lift, long long fstride, int cnt,
+                            int level, const double *qlinv, const double *kmul, hipStream_t s) {
+    if (cnt <= 0 || level <= 0) return;
+    hipLaunchKernelGGL(k_rescale_combine, dim3((T.N + 255) / 256, cnt * level), dim3(256), 0, s, T,
+                       out, ostride, in, istride, lift, fstride, level, qlinv, kmul);
+}
+
+// ---------------------------------------------------------------- sampling
+// Philox4x32-10 (Salmon et al., SC 2011), counter (i, prime, obj, attempt).
+DEV void philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1,
+                uint32_t out[4]) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n1 = (uint32_t)p1;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        const uint32_t n3 = (uint32_t)p0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+// uniform residues mod prime(gprime[r]) per vector; coefficient domain
+__global__ void k_sample_uniform(VecSet out, uint64_t seed, uint32_t obj, const int *gprime,
+                                 DevTables T) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= T.N) return;
+    double *po; int pr, g, r;
+    vs_at(out, blockIdx.y, T.N, po, pr, g, r);
+    const int gp = gprime ? gprime[r] : pr;
+    const uint64_t q = (uint64_t)T.p[pr];
+    const int b = 64 - __clzll((long long)q);
+    double val = 0.0;
+    for (uint32_t att = 0; att < 4096u; ++att) {
+        uint32_t o[4];
+        philox((uint32_t)x, (uint32_t)gp, obj, att, (uint32_t)seed, (uint32_t)(seed >> 32), o);
+        const uint64_t x0 = ((((uint64_t)o[1]) << 32) | o[0]) >> (64 - b);
+        if (x0 < q) { val = (double)x0; break; }
+        const uint64_t x1 = ((((uint64_t)o[3]) << 32) | o[2]) >> (64 - b);
+        if (x1 < q) { val = (double)x1; break; }
+    }
+    po[x] = val;
+}
+void launch_sample_uniform(const DevTables &T, const VecSet &out, uint64_t seed, uint32_t obj,
+                           const int *gprime, hipStream_t s) {
+    if (out.count <= 0) return;
+    hipLaunchKernelGGL(k_sample_uniform, ew_grid(T, out.count), dim3(256), 0, s, out, seed, obj, gprime, T);
+}
+
+// kind 0: ternary ((o0*3)>>32) - 1; kind 1: centred binomial eta = 21
+__global__ void k_sample_small(int *out, int N, uint64_t seed, uint32_t obj, int kind) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= N) return;
+    uint32_t o[4];
+    philox((uint32_t)x, 0u, obj, 0u, (uint32_t)seed, (uint32_t)(seed >> 32), o);
+    if (kind == 0) out[x] = (int)(((uint64_t)o[0] * 3ull) >> 32) - 1;
+    else out[x] = __popc(o[0] & 0x1FFFFFu) - __popc(o[1] & 0x1FFFFFu);
+}
+void launch_sample_small(int *out, int N, uint64_t seed, uint32_t obj, int kind, hipStream_t s) {
+    hipLaunchKernelGGL(k_sample_small, dim3((N + 255) / 256), dim3(256), 0, s, out, N, seed, obj, kind);
+}
+
+__global__ void k_small_to_res(VecSet out, const int *v, DevTables T) {
+    EW_PROLOGUE
+    const double pinv = T.pinv[pr];
+    po[x] = canon((double)v[x], p, pinv);
+}
+void launch_small_to_res(const DevTables &T, const VecSet &out, const int *v, const int *gprime,
+                         hipStream_t s) {
+    (void)gprime;
+    if (out.count <= 0) return;
+    hipLaunchKernelGGL(k_small_to_res, ew_grid(T, out.count), dim3(256), 0, s, out, v, T);
+}
+
+// int64 coefficients -> residues: m = hi 2^32 + lo
+__global__ void k_int64_to_res(VecSet out, const int64_t *m, long long mstride, DevTables T) {
+    EW_PROLOGUE
+    const double pinv = T.pinv[pr];
+    const int64_t v = m[g * mstride + x];
+    const double hi = (double)(v >> 32);
+    const double lo = (double)(uint32_t)(v & 0xffffffffll);
+    po[x] = canon(mm(hi, T.two32[pr], p, pinv) + lo, p, pinv);
+}
+void launch_int64_to_res(const DevTables &T, const VecSet &out, const int64_t *m,
+                         long long mstride, const int *gprime, hipStream_t s) {
+    (void)gprime;
+    if (out.count <= 0) return;
+    hipLaunchKernelGGL(k_int64_to_res, ew_grid(T, out.count), dim3(256), 0, s, out, m, mstride, T);
+}
+
+// key digit: b = e - a s + [lo <= prime < hi] (P mod q) s'   (NTT domain)
+__global__ void k_keyb(DevTables T, double *b, const double *a, const double *e, const double *s,
+                       const double *tgt, const double *pmod, int lo, int hi) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= T.N) return;
+    const int pi = blockIdx.y;
+    const double p = T.p[pi], pinv = T.pinv[pi];
+    const long long o = (long long)pi * T.N + x;
+    double r = e[o] - mm(a[o], s[o], p, pinv);
+    if (pi >= lo && pi < hi) r += mm(pmod[pi], tgt[o], p, pinv);
+    b[o] = canon(r, p, pinv);
+}
+void launch_keyb(const DevTables &T, double *b, const double *a, const double *e, const double *s,
+                 const double *tgt, const double *pmod, int np, int lo, int hi, hipStream_t st) {
+    hipLaunchKernelGGL(k_keyb, dim3((T.N + 255) / 256, np), dim3(256), 0, st, T, b, a, e, s, tgt, pmod, lo, hi);
+}
+
+// c0 = m + e - a s per (ciphertext, limb)
+__global__ void k_encfinish(DevTables T, double *c0, const double *a, const double *e,
+                            const double *m, const double *s, int limbs, long long ctstride,
+                            long long mctstride) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= T.N) return;
+    const int ct = blockIdx.y / limbs, li = blockIdx.y % limbs;
+    const double p = T.p[li], pinv = T.pinv[li];
+    const long long o = (long long)li * T.N + x;
+    const double r = m[ct * mctstride + o] + e[o] - mm(a[ct * ctstride + o], s[o], p, pinv);
+    c0[ct * ctstride + o] = canon(r, p, pinv);
+}
+void launch_encfinish(const DevTables &T, double *c0, const double *a, const double *e,
+                      const double *m, const double *s, long long stride, int limbs, int cnt,
+                      long long ctstride, long long mctstride, hipStream_t st) {
+    (void)stride;
+    hipLaunchKernelGGL(k_encfinish, dim3((T.N + 255) / 256, cnt * limbs), dim3(256), 0, st, T, c0, a,
+                       e, m, s, limbs, ctstride, mctstride);
+}
+
+// m = c0 + c1 s on the first `limbs` primes
+__global__ void k_decmul(DevTables T, double *m, const double *c0, const double *c1, const double *s) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= T.N) return;
+    const int li = blockIdx.y;
+    const double p = T.p[li], pinv = T.pinv[li];
+    const long long o = (long long)li * T.N + x;
+    m[o] = canon(c0[o] + mm(c1[o], s[o], p, pinv), p, pinv);
+}
+void launch_decmul(const DevTables &T, double *m, const double *c0, const double *c1,
+                   const double *s, int limbs, hipStream_t st) {
+    hipLaunchKernelGGL(k_decmul, dim3((T.N + 255) / 256, limbs), dim3(256), 0, st, T, m, c0, c1, s);
+}
+
+__global__ void k_square_res(DevTables T, double *out, const double *in) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= T.N) return;
+    const int pi = blockIdx.y;
+    const double p = T.p[pi], pinv = T.pinv[pi];
+    const long long o = (long long)pi * T.N + x;
+    out[o] = canon(mm(in[o], in[o], p, pinv), p, pinv);
+}
+void launch_square_res(const DevTables &T, double *out, const double *in, int np, hipStream_t st) {
+    hipLaunchKernelGGL(k_square_res, dim3((T.N + 255) / 256, np), dim3(256), 0, st, T, out, in);
+}
+
+// debug: count words that are not canonical integers in [0, p)
+__global__ void k_canon_check(VecSet vs, DevTables T, int *bad) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= T.N) return;
+    double *pv; int pr, g, r;
+    vs_at(vs, blockIdx.y, T.N, pv, pr, g, r);
+    const double v = pv[x];
+    if (!(v >= 0.0 && v < T.p[pr] && v == __builtin_rint(v))) atomicAdd(bad, 1);
+}
+void launch_canon_check(const DevTables &T, const VecSet &vs, int *bad, hipStream_t st) {
+    if (vs.count <= 0) return;
+    hipLaunchKernelGGL(k_canon_check, ew_grid(T, vs.count), dim3(256), 0, st, vs, T, bad);
+}
+
+}  // namespace he

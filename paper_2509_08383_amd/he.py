@@ -1,0 +1,345 @@
+"""ctypes binding of libcutmax_he.so (the C ABI in include/he.h).
+
+Argument marshalling only: every step of the encrypted CutMax runs in the
+library's HIP kernels.  There is no CPU fallback: if the library is missing or
+no GPU is present the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcutmax_he.so")
+
+HE_OK, HE_EINVAL, HE_ENOMEM, HE_EDEVICE, HE_EDEPTH, HE_ERANGE, HE_ESTATE = 0, -1, -2, -3, -4, -5, -6
+HE_NOISE_PRESCALED = 1
+HE_OPT_GRAPH, HE_OPT_NTT_VARIANT = 1, 2
+
+_c_u32p = ctypes.POINTER(ctypes.c_uint32)
+_c_u64p = ctypes.POINTER(ctypes.c_uint64)
+_c_i64p = ctypes.POINTER(ctypes.c_int64)
+_c_dp = ctypes.POINTER(ctypes.c_double)
+_V = ctypes.c_void_p
+
+
+class HeError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"he error {code}: {msg}")
+        self.code = code
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("log_n", ctypes.c_uint32), ("n_q", ctypes.c_uint32), ("q0_bits", ctypes.c_uint32),
+                ("q_bits", ctypes.c_uint32), ("p_bits", ctypes.c_uint32), ("dnum", ctypes.c_uint32),
+                ("log2_scale", ctypes.c_double), ("seed", ctypes.c_uint64), ("device", ctypes.c_int),
+                ("stream", _V)]
+
+
+class _Cfg(ctypes.Structure):
+    _fields_ = [("T", ctypes.c_uint32), ("p", _c_u32p), ("c", _c_dp), ("var_lo", _c_dp),
+                ("var_hi", _c_dp), ("init_degree", ctypes.c_uint32), ("init_coef", _c_dp),
+                ("newton_steps", ctypes.c_uint32), ("sum_lo", ctypes.c_double),
+                ("sum_hi", ctypes.c_double), ("gold_d", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load the library (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run paper_2509_08383_amd.build first")
+        L = ctypes.CDLL(LIB_PATH)
+        sig = {
+            "he_ctx_create": [ctypes.POINTER(_Params), ctypes.POINTER(_V)],
+            "he_ctx_info": [_V, _c_u32p, _c_u32p, _c_u32p, _c_u32p, _c_u64p],
+            "he_encrypt": [_V, _c_dp, ctypes.c_size_t, ctypes.c_double, ctypes.POINTER(_V)],
+            "he_encrypt_coeffs": [_V, _c_i64p, ctypes.c_uint32, ctypes.c_double, ctypes.c_size_t,
+                                  ctypes.POINTER(_V)],
+            "he_decrypt": [_V, _V, _c_dp, ctypes.c_size_t],
+            "he_cutmax": [_V, ctypes.POINTER(_V), ctypes.c_size_t, ctypes.POINTER(_Cfg), ctypes.POINTER(_V)],
+            "he_topp_sample": [_V, ctypes.POINTER(_V), ctypes.POINTER(_V), ctypes.c_size_t, ctypes.c_double,
+                               ctypes.c_double, ctypes.POINTER(_Cfg), ctypes.POINTER(_V)],
+            "he_topp_noise": [ctypes.c_double, _c_dp, ctypes.c_size_t, _c_dp],
+            "he_ct_info": [_V, _c_u32p, _c_u32p, _c_dp, ctypes.POINTER(ctypes.c_size_t)],
+            "he_ct_export": [_V, _V, _c_u64p, ctypes.c_size_t],
+            "he_ct_import": [_V, _c_u64p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_double, ctypes.c_size_t,
+                             ctypes.POINTER(_V)],
+            "he_add": [_V, _V, _V, ctypes.POINTER(_V)],
+            "he_sub": [_V, _V, _V, ctypes.POINTER(_V)],
+            "he_mul": [_V, _V, _V, ctypes.POINTER(_V)],
+            "he_mul_int": [_V, _V, ctypes.c_int64, ctypes.POINTER(_V)],
+            "he_add_const": [_V, _V, ctypes.c_double, ctypes.POINTER(_V)],
+            "he_rescale": [_V, _V, ctypes.POINTER(_V)],
+            "he_cmul": [_V, _V, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.POINTER(_V)],
+            "he_rotate": [_V, _V, ctypes.c_uint32, ctypes.POINTER(_V)],
+            "he_rotsum": [_V, _V, ctypes.POINTER(_V)],
+            "he_drop": [_V, _V, ctypes.c_uint32, ctypes.POINTER(_V)],
+            "he_bench_ntt": [_V, ctypes.c_uint32, ctypes.c_uint32, _c_dp, _c_dp],
+            "he_last_cutmax_ms": [_V, _c_dp],
+            "he_sync": [_V],
+            "he_set_option": [_V, ctypes.c_int, ctypes.c_int64],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        L.he_ctx_destroy.argtypes = [_V]
+        L.he_ctx_destroy.restype = None
+        L.he_ct_free.argtypes = [_V]
+        L.he_ct_free.restype = None
+        L.he_last_error.argtypes = []
+        L.he_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != HE_OK:
+        raise HeError(rc, lib().he_last_error().decode())
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(_c_dp)
+
+
+@dataclass
+class Params:
+    log_n: int
+    n_q: int
+    q0_bits: int
+    q_bits: int
+    p_bits: int
+    dnum: int
+    log2_scale: float
+    seed: int = 1
+
+
+# parameter sets of the two workloads
+TOY = Params(log_n=12, n_q=36, q0_bits=40, q_bits=30, p_bits=40, dnum=3, log2_scale=30, seed=7)
+SECURE = Params(log_n=16, n_q=30, q0_bits=49, q_bits=40, p_bits=49, dnum=3, log2_scale=40, seed=11)
+
+
+@dataclass
+class CutmaxCfg:
+    """Hyper-parameters of one CutMax call (he_cutmax_cfg)."""
+    T: int
+    p: Sequence[int]
+    c: Sequence[float]
+    var_lo: Sequence[float]
+    var_hi: Sequence[float]
+    init_degree: int = 3
+    init_coef: Optional[Sequence[Sequence[float]]] = None   # [T][degree+1], g(u) ~ u^-1/2
+    newton_steps: int = 0
+    sum_lo: float = 1.0
+    sum_hi: float = 3.0
+    gold_d: int = 3
+    flags: int = 0
+    _keep: list = field(default_factory=list, repr=False)
+
+    def c_struct(self) -> _Cfg:
+        T = self.T
+        p = (ctypes.c_uint32 * T)(*[int(v) for v in self.p])
+        c = (ctypes.c_double * T)(*[float(v) for v in self.c])
+        lo = (ctypes.c_double * T)(*[float(v) for v in self.var_lo])
+        hi = (ctypes.c_double * T)(*[float(v) for v in self.var_hi])
+        coef = None
+        if self.init_coef is not None:
+            flat = [float(v) for row in self.init_coef for v in row]
+            assert len(flat) == T * (self.init_degree + 1)
+            coef = (ctypes.c_double * len(flat))(*flat)
+        self._keep = [p, c, lo, hi, coef]
+        s = _Cfg()
+        s.T, s.p, s.c, s.var_lo, s.var_hi = T, p, c, lo, hi
+        s.init_degree = self.init_degree
+        s.init_coef = ctypes.cast(coef, _c_dp) if coef is not None else None
+        s.newton_steps, s.sum_lo, s.sum_hi = self.newton_steps, self.sum_lo, self.sum_hi
+        s.gold_d, s.flags = self.gold_d, self.flags
+        return s
+
+
+class Ciphertext:
+    def __init__(self, ctx: "Context", h):
+        self.ctx, self.h = ctx, h
+
+    def __del__(self):
+        try:
+            if self.h:
+                lib().he_ct_free(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def info(self):
+        a, lv, n = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_size_t()
+        sc = ctypes.c_double()
+        _check(lib().he_ct_info(self.h, ctypes.byref(a), ctypes.byref(lv), ctypes.byref(sc), ctypes.byref(n)))
+        return a.value, lv.value, sc.value, n.value
+
+    @property
+    def a(self):
+        return self.info()[0]
+
+    @property
+    def level(self):
+        return self.info()[1]
+
+    @property
+    def scale(self):
+        return self.info()[2]
+
+    @property
+    def n(self):
+        return self.info()[3]
+
+
+class Context:
+    """One CKKS context on one GPU (he_ctx)."""
+
+    def __init__(self, prm: Params, device: int = 0, stream: Optional[int] = None):
+        P = _Params(prm.log_n, prm.n_q, prm.q0_bits, prm.q_bits, prm.p_bits, prm.dnum, float(prm.log2_scale),
+                    prm.seed, device, stream)
+        h = _V()
+        _check(lib().he_ctx_create(ctypes.byref(P), ctypes.byref(h)))
+        self.h = h
+        self.prm = prm
+        N, s, L, A = (ctypes.c_uint32() for _ in range(4))
+        _check(lib().he_ctx_info(self.h, ctypes.byref(N), ctypes.byref(s), ctypes.byref(L), ctypes.byref(A), None))
+        self.N, self.slots, self.L, self.alpha = N.value, s.value, L.value, A.value
+        pr = np.empty(self.L + 1 + self.alpha, dtype=np.uint64)
+        _check(lib().he_ctx_info(self.h, None, None, None, None, pr.ctypes.data_as(_c_u64p)))
+        self.primes = [int(v) for v in pr]
+        self.Delta = 2.0 ** prm.log2_scale
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().he_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _out(self):
+        return _V()
+
+    # client ------------------------------------------------------------------
+    def encrypt(self, x, pad: float = 0.0) -> Ciphertext:
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        h = _V()
+        _check(lib().he_encrypt(self.h, _dp(x), x.size, pad, ctypes.byref(h)))
+        return Ciphertext(self, h)
+
+    def encrypt_coeffs(self, m, scale: float, n: int) -> Ciphertext:
+        m = np.ascontiguousarray(m, dtype=np.int64)
+        a = m.size // self.N
+        h = _V()
+        _check(lib().he_encrypt_coeffs(self.h, m.ctypes.data_as(_c_i64p), a, scale, n, ctypes.byref(h)))
+        return Ciphertext(self, h)
+
+    def decrypt(self, ct: Ciphertext, n: Optional[int] = None) -> np.ndarray:
+        n = ct.n if n is None else n
+        out = np.empty(n, dtype=np.float64)
+        _check(lib().he_decrypt(self.h, ct.h, _dp(out), n))
+        return out
+
+    def export(self, ct: Ciphertext) -> np.ndarray:
+        a, lv, _, _ = ct.info()
+        out = np.empty((a, 2, lv + 1, self.N), dtype=np.uint64)
+        _check(lib().he_ct_export(self.h, ct.h, out.ctypes.data_as(_c_u64p), out.size))
+        return out
+
+    def import_ct(self, limbs: np.ndarray, scale: float, n: int) -> Ciphertext:
+        limbs = np.ascontiguousarray(limbs, dtype=np.uint64)
+        a, _, lv1, _ = limbs.shape
+        h = _V()
+        _check(lib().he_ct_import(self.h, limbs.ctypes.data_as(_c_u64p), a, lv1 - 1, scale, n, ctypes.byref(h)))
+        return Ciphertext(self, h)
+
+    # server ------------------------------------------------------------------
+    def cutmax(self, cts: List[Ciphertext], cfg: CutmaxCfg) -> List[Ciphertext]:
+        B = len(cts)
+        ins = (_V * B)(*[c.h for c in cts])
+        outs = (_V * B)()
+        s = cfg.c_struct()
+        _check(lib().he_cutmax(self.h, ins, B, ctypes.byref(s), outs))
+        return [Ciphertext(self, _V(o)) for o in outs]
+
+    def topp_sample(self, logits: List[Ciphertext], noise: List[Ciphertext], top_p: float,
+                    temperature: float, cfg: CutmaxCfg) -> List[Ciphertext]:
+        B = len(logits)
+        ins = (_V * B)(*[c.h for c in logits])
+        nz = (_V * B)(*[c.h for c in noise])
+        outs = (_V * B)()
+        s = cfg.c_struct()
+        _check(lib().he_topp_sample(self.h, ins, nz, B, top_p, temperature, ctypes.byref(s), outs))
+        return [Ciphertext(self, _V(o)) for o in outs]
+
+    def _op(self, name, *args):
+        h = _V()
+        _check(getattr(lib(), name)(self.h, *args, ctypes.byref(h)))
+        return Ciphertext(self, h)
+
+    def add(self, a, b):
+        return self._op("he_add", a.h, b.h)
+
+    def sub(self, a, b):
+        return self._op("he_sub", a.h, b.h)
+
+    def mul(self, a, b):
+        return self._op("he_mul", a.h, b.h)
+
+    def mul_int(self, a, k: int):
+        return self._op("he_mul_int", a.h, int(k))
+
+    def add_const(self, a, c: float):
+        return self._op("he_add_const", a.h, float(c))
+
+    def rescale(self, a):
+        return self._op("he_rescale", a.h)
+
+    def cmul(self, a, kappa: float, s_want: float, exact: bool):
+        return self._op("he_cmul", a.h, float(kappa), float(s_want), int(bool(exact)))
+
+    def rotate(self, a, r: int):
+        return self._op("he_rotate", a.h, int(r))
+
+    def rotsum(self, a):
+        return self._op("he_rotsum", a.h)
+
+    def drop(self, a, level: int):
+        return self._op("he_drop", a.h, int(level))
+
+    # measurement ---------------------------------------------------------------
+    def bench_ntt(self, vectors: int, iters: int):
+        f, i = ctypes.c_double(), ctypes.c_double()
+        _check(lib().he_bench_ntt(self.h, vectors, iters, ctypes.byref(f), ctypes.byref(i)))
+        return f.value, i.value
+
+    def last_cutmax_ms(self) -> float:
+        v = ctypes.c_double()
+        _check(lib().he_last_cutmax_ms(self.h, ctypes.byref(v)))
+        return v.value
+
+    def sync(self):
+        _check(lib().he_sync(self.h))
+
+    def set_option(self, opt: int, value: int):
+        _check(lib().he_set_option(self.h, opt, int(value)))
+
+
+def topp_noise(top_p: float, u: np.ndarray) -> np.ndarray:
+    """Client helper: G = U^(1/alpha), alpha = ln(1-p)/ln p (Alg. 3 lines 1-4)."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    g = np.empty_like(u)
+    _check(lib().he_topp_noise(float(top_p), _dp(u), u.size, _dp(g)))
+    return g

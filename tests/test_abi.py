@@ -1,0 +1,60 @@
+"""CPU checks of the boundary: the library loads and exports every entry point include/he.h declares."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "he.h")
+LIB = os.path.join(ROOT, "paper_2509_08383_amd", "libcutmax_he.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(he_[a-z0-9_]+)\s*\(", text)))
+
+
+def _ensure_built():
+    if not os.path.exists(LIB):
+        from paper_2509_08383_amd import build
+        build.build(verbose=False)
+
+
+def test_header_declares_the_five_calls():
+    names = declared_functions()
+    for n in ("he_ctx_create", "he_encrypt", "he_cutmax", "he_topp_sample", "he_decrypt"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    _ensure_built()
+    L = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_topp_noise_is_host_only():
+    """he_topp_noise needs no GPU: G = U^(1/alpha), alpha = ln(1-p)/ln p (Alg. 3)."""
+    _ensure_built()
+    import numpy as np
+    from paper_2509_08383_amd import he
+    from oracle.cutmax_fp64 import beta_alpha, beta_noise
+    from workloads import uniform_noise
+    u = uniform_noise(3, 1000)
+    g = he.topp_noise(0.9, u)
+    np.testing.assert_allclose(g, beta_noise(u, beta_alpha(0.9)), rtol=1e-14)
+    with pytest.raises(he.HeError):
+        he.topp_noise(1.5, u)
+
+
+def test_errors_without_gpu_are_loud():
+    """Creating a context without a GPU fails with an error, never a silent fallback."""
+    _ensure_built()
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_2509_08383_amd import he
+    with pytest.raises(he.HeError):
+        he.Context(he.TOY)

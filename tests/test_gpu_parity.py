@@ -1,0 +1,221 @@
+"""GPU parity: the HIP path against the CPU oracle, bit-exact on every ciphertext limb
+from the same seed and the same encoded plaintext, and decrypted CutMax against the
+FP64 mirror within 1e-3 (Alg. 2), argmax agreement with Alg. 1."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import ckks  # noqa: E402
+from oracle.cutmax_fp64 import (MirrorCfg, chebyshev_invsqrt, cutmax_exact, cutmax_mirror,  # noqa: E402
+                                slot_layout)
+from workloads import llm_logits, random_small_poly, toy_logits  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _oracle_params(p):
+    return ckks.Params(log_n=p.log_n, n_q=p.n_q, q0_bits=p.q0_bits, q_bits=p.q_bits, p_bits=p.p_bits,
+                       dnum=p.dnum, log2_scale=p.log2_scale, seed=p.seed)
+
+
+class Pair:
+    """A GPU context and an oracle context with the same parameters and seed,
+    kept in lockstep (both advance their encryption counter per ciphertext)."""
+
+    def __init__(self, prm):
+        from paper_2509_08383_amd import he
+        self.he = he
+        self.G = he.Context(prm)
+        self.O = ckks.Oracle(_oracle_params(prm))
+        self.O.keygen_cutmax()
+        assert self.G.primes == self.O.q
+
+    def enc(self, m, scale=None):
+        scale = self.O.Delta if scale is None else scale
+        g = self.G.encrypt_coeffs(m, scale, self.G.slots)
+        o = self.O.encrypt_coeffs(m, scale)
+        return g, o
+
+    def enc_values(self, z):
+        return self.enc(ckks.encode(z, self.O.N, self.O.Delta))
+
+    def same(self, g, o, what):
+        eg = self.G.export(g)[0]
+        eo = o.export()
+        assert eg.shape == eo.shape, (what, eg.shape, eo.shape)
+        bad = int((eg != eo).sum())
+        assert bad == 0, f"{what}: {bad} limb words differ"
+        assert g.level == o.level, what
+        assert g.scale == o.scale, (what, g.scale, o.scale)
+
+
+@pytest.fixture(scope="module")
+def toy():
+    from paper_2509_08383_amd import he
+    say("[gpu] building toy pair")
+    return Pair(he.TOY)
+
+
+def test_encrypt_bit_exact(toy):
+    say("[gpu] encrypt bit-exact (toy)")
+    m = random_small_poly(1, toy.O.N, 2 ** 35)
+    g, o = toy.enc(m)
+    toy.same(g, o, "encrypt")
+    g2, o2 = toy.enc(m)
+    toy.same(g2, o2, "encrypt#2")
+
+
+def test_decrypt_roundtrip(toy):
+    z = np.random.default_rng(2).uniform(-3, 3, toy.G.slots)
+    ct = toy.G.encrypt(z)
+    toy.O.nonce = toy.O.nonce + 1        # keep the counters in lockstep
+    np.testing.assert_allclose(toy.G.decrypt(ct), z, atol=2e-5)
+
+
+def test_encoder_matches_oracle_encoder(toy):
+    z = np.random.default_rng(3).uniform(-3, 3, toy.G.slots)
+    ct = toy.G.encrypt(z)
+    toy.O.nonce = toy.O.nonce + 1
+    # the GPU ciphertext decrypted by the oracle gives the oracle's encoding within +-1 per
+    # coefficient plus fresh noise
+    o = toy.O.import_ct(toy.G.export(ct)[0], ct.scale)
+    got = toy.O.decrypt_coeffs(o)
+    want = ckks.encode(z, toy.O.N, toy.O.Delta)
+    assert np.abs(got - want).max() < 200
+
+
+def _pairs_of_ops(P):
+    rng = np.random.default_rng(5)
+    x = rng.uniform(-2, 2, P.G.slots)
+    y = rng.uniform(-2, 2, P.G.slots)
+    gx, ox = P.enc_values(x)
+    gy, oy = P.enc_values(y)
+    return gx, ox, gy, oy
+
+
+@pytest.mark.parametrize("op", ["add", "sub", "mul_int", "add_const", "rescale", "cm_exact",
+                                "cm_target", "mul", "drop"])
+def test_elementwise_ops_bit_exact(toy, op):
+    say(f"[gpu] op {op} (toy)")
+    G, O = toy.G, toy.O
+    gx, ox, gy, oy = _pairs_of_ops(toy)
+    if op == "add":
+        toy.same(G.add(gx, gy), O.add(ox, oy), op)
+    elif op == "sub":
+        toy.same(G.sub(gx, gy), O.sub(ox, oy), op)
+    elif op == "mul_int":
+        toy.same(G.mul_int(gx, -12345), O.mul_int(ox, -12345), op)
+    elif op == "add_const":
+        toy.same(G.add_const(gx, -2.75), O.add_const(ox, -2.75), op)
+    elif op == "rescale":
+        toy.same(G.rescale(gx), O.rescale(ox), op)
+    elif op == "cm_exact":
+        toy.same(G.cmul(gx, 0.3721, O.Delta, True), O.cm_exact(ox, 0.3721, O.Delta), op)
+    elif op == "cm_target":
+        toy.same(G.cmul(gx, -1.25, 2.0 ** 29, False), O.cm_target(ox, -1.25, 2.0 ** 29), op)
+    elif op == "mul":
+        toy.same(G.mul(gx, gy), O.mul(ox, oy), op)
+        np.testing.assert_allclose(G.decrypt(G.mul(gx, gy)), G.decrypt(gx) * G.decrypt(gy), atol=1e-3)
+    elif op == "drop":
+        toy.same(G.drop(gx, 3), O.drop(ox, 3), op)
+
+
+@pytest.mark.parametrize("r", [0, 1, 5, 10])
+def test_rotate_bit_exact(toy, r):
+    say(f"[gpu] rotate {r} (toy)")
+    gx, ox, _, _ = _pairs_of_ops(toy)
+    toy.same(toy.G.rotate(gx, r), toy.O.rotate(ox, r), f"rotate {r}")
+
+
+def test_rotate_and_mul_low_levels_bit_exact(toy):
+    """partial key-switch digits below the top level"""
+    gx, ox, gy, oy = _pairs_of_ops(toy)
+    for lv in (1, 2, 13, 24):
+        gd, od = toy.G.drop(gx, lv), toy.O.drop(ox, lv)
+        toy.same(toy.G.rotate(gd, 3), toy.O.rotate(od, 3), f"rotate@{lv}")
+        toy.same(toy.G.mul(gd, toy.G.drop(gy, lv)), toy.O.mul(od, toy.O.drop(oy, lv)), f"mul@{lv}")
+
+
+def test_rotsum_bit_exact(toy):
+    gx, ox, _, _ = _pairs_of_ops(toy)
+    toy.same(toy.G.rotsum(gx), toy.O.rotsum(ox), "rotsum")
+
+
+def toy_cfg(n, T=4):
+    p, c = [3] * T, [5.0] * T
+    vlo, vhi = [0.5, 0.25, 0.3, 0.6][:T], [2.0, 0.75, 3.0, 128.0][:T]
+    coef = [list(chebyshev_invsqrt(vlo[t] / vhi[t], 3)) for t in range(T)]
+    return p, c, vlo, vhi, coef
+
+
+def test_cutmax_toy_bit_exact_and_mirror(toy):
+    """config 1: N=2^12, 1024 logits replicated to 2048 slots, T=4, p=3, c=5."""
+    from paper_2509_08383_amd import he
+    say("[gpu] cutmax toy bit-exact")
+    x = toy_logits(21)
+    y, a, rep = slot_layout(x, toy.G.slots)
+    n = y.size
+    p, c, vlo, vhi, coef = toy_cfg(n)
+    g, o = toy.enc_values(y)
+    cfg = he.CutmaxCfg(T=4, p=p, c=c, var_lo=vlo, var_hi=vhi, init_degree=3, init_coef=coef,
+                       sum_lo=1.0, sum_hi=3.0, gold_d=3)
+    Zg = toy.G.cutmax([g], cfg)[0]
+    hc = ckks.HECfg(T=4, p=p, c=c, v_lo=vlo, v_hi=vhi, coef=coef, sum_lo=1.0, sum_hi=3.0, gold_d=3)
+    Zo = ckks.cutmax_he(toy.O, [o], hc)[0]
+    toy.same(Zg, Zo, "cutmax")
+    dz = toy.G.decrypt(Zg, n)
+    mc = MirrorCfg(T=4, p=p, c=c, v_hi=vhi, v_lo=vlo, coef=coef, B=3.0 * n, gold_d=3, sum_lo=1.0 * n)
+    assert np.abs(dz - cutmax_mirror(y, mc)).max() < 1e-3
+    assert int(np.argmax(dz[:x.size])) == int(np.argmax(x))
+    assert int(np.argmax(cutmax_exact(y, 3, 5.0, 4)[:x.size])) == int(np.argmax(x))
+
+
+def test_cutmax_toy_batch_mixed_counts(toy):
+    """batched form: requests with 1 and 2 ciphertexts advance together; each equals its
+    single-request run bit for bit (n > s splits over several ciphertexts, App. D)."""
+    from paper_2509_08383_amd import he
+    say("[gpu] cutmax toy batch")
+    xs = [toy_logits(31, 1024), llm_logits(32, 3000), toy_logits(33, 1024)]
+    cts = [toy.G.encrypt(x) for x in xs]
+    toy.O.nonce = toy.O.nonce + sum(c.a for c in cts)
+    p, c, vlo, vhi, coef = toy_cfg(2048)
+    # one domain for both logit families (the LLM-like request has larger variances)
+    vlo2 = [0.5, 0.25, 0.3, 0.6]
+    vhi2 = [32.0, 0.9, 16.0, 512.0]
+    coef = [list(chebyshev_invsqrt(vlo2[t] / vhi2[t], 3)) for t in range(4)]
+    cfg = he.CutmaxCfg(T=4, p=p, c=c, var_lo=vlo2, var_hi=vhi2, init_coef=coef, sum_lo=1.0, sum_hi=3.0)
+    Zb = toy.G.cutmax(cts, cfg)
+    for i, (x, ct) in enumerate(zip(xs, cts)):
+        Zs = toy.G.cutmax([ct], cfg)[0]
+        eb, es = toy.G.export(Zb[i]), toy.G.export(Zs)
+        assert np.array_equal(eb, es), f"request {i}: batched != single"
+        y, a, rep = slot_layout(x, toy.G.slots)
+        assert Zb[i].a == a
+        dz = toy.G.decrypt(Zb[i], y.size)
+        mc = MirrorCfg(T=4, p=p, c=c, v_hi=vhi2, v_lo=vlo2, coef=coef, B=3.0 * y.size, gold_d=3,
+                       sum_lo=1.0 * y.size)
+        assert np.abs(dz - cutmax_mirror(y, mc)).max() < 1e-3
+        assert int(np.argmax(dz[:x.size])) == int(np.argmax(x))
+
+
+def test_cutmax_errors_are_reported(toy):
+    from paper_2509_08383_amd import he
+    x = toy_logits(41)
+    ct = toy.G.encrypt(x)
+    toy.O.nonce = toy.O.nonce + 1
+    p, c, vlo, vhi, coef = toy_cfg(2048)
+    deep = he.CutmaxCfg(T=6, p=[3] * 6, c=[5.0] * 6, var_lo=[0.5] * 6, var_hi=[2.0] * 6, sum_lo=1.0, sum_hi=3.0)
+    with pytest.raises(he.HeError) as e:
+        toy.G.cutmax([ct], deep)
+    assert e.value.code == he.HE_EDEPTH
+    bad = he.CutmaxCfg(T=1, p=[3], c=[5.0], var_lo=[2.0], var_hi=[1.0])
+    with pytest.raises(he.HeError) as e:
+        toy.G.cutmax([ct], bad)
+    assert e.value.code == he.HE_EINVAL

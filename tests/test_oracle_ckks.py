@@ -164,7 +164,7 @@ def _cfg1_schedule(O, y, T=4):
     n = y.size
     p, c = [3] * T, [5.0] * T
     vlo, vhi = [0.5, 0.25, 0.3, 0.6][:T], [2.0, 0.75, 3.0, 128.0][:T]
-    coef = [chebyshev_invsqrt(vlo[t] / vhi[t], 3, math.sqrt(n) / c[t]) for t in range(T)]
+    coef = [chebyshev_invsqrt(vlo[t] / vhi[t], 3) for t in range(T)]
     he = ckks.HECfg(T=T, p=p, c=c, v_lo=vlo, v_hi=vhi, coef=coef, sum_lo=1.0, sum_hi=3.0, gold_d=3)
     mc = MirrorCfg(T=T, p=p, c=c, v_hi=vhi, v_lo=vlo, coef=coef, B=3.0 * n, gold_d=3, sum_lo=1.0 * n)
     return he, mc

@@ -152,7 +152,7 @@ def test_mirror_equals_exact_when_approximations_are_exact():
     Ze = cutmax_exact(y, p, c, T, tr)
     vhi = [v * 1.5 for v in tr.var]
     vlo = [v * 0.7 for v in tr.var]
-    coef = [chebyshev_invsqrt(vlo[t] / vhi[t], 3, math.sqrt(n) / c[t]) for t in range(T)]
+    coef = [chebyshev_invsqrt(vlo[t] / vhi[t], 3) for t in range(T)]
     S = tr.ys[-1].sum()
     cfg = MirrorCfg(T=T, p=p, c=c, v_hi=vhi, v_lo=vlo, coef=coef, newton=4, B=1.5 * S,
                     gold_d=7, sum_lo=0.5 * S)
