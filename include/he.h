@@ -184,6 +184,14 @@ int he_bench_ntt(he_ctx *ctx, uint32_t vectors, uint32_t iters, double *ms_fwd, 
 int he_last_cutmax_ms(const he_ctx *ctx, double *ms);
 int he_sync(he_ctx *ctx);
 
+/* Per-kernel timing: between he_profile_begin and he_profile_end every kernel
+ * launch is bracketed by HIP events on the stream it is launched on (this adds
+ * a little launch overhead).  he_profile_end waits for the stream and writes a
+ * JSON object {"kernel": [launches, total_ms], ...} into buf (host, cap bytes).
+ * One profile at a time per process. */
+int he_profile_begin(he_ctx *ctx);
+int he_profile_end(he_ctx *ctx, char *buf, size_t cap);
+
 /* Options: HE_OPT_GRAPH (capture he_cutmax in a HIP graph and replay it for
  * repeated calls of the same shape), HE_OPT_NTT_VARIANT (0 = autotune, k > 0
  * forces variant k). */

@@ -25,6 +25,30 @@
 
 using namespace he;
 
+namespace he {
+struct KProf {
+    struct Rec { const char *name; hipEvent_t a, b; double bytes; };
+    std::vector<Rec> recs;
+    double pending = 0;
+};
+KProf *g_kprof = nullptr;
+void kprof_set_bytes(double b) {
+    if (g_kprof) g_kprof->pending = b;
+}
+void kprof_mark(const char *name, hipStream_t s, bool end) {
+    if (!end) {
+        KProf::Rec r{name, nullptr, nullptr, g_kprof->pending};
+        g_kprof->pending = 0;
+        hipEventCreate(&r.a);
+        hipEventCreate(&r.b);
+        hipEventRecord(r.a, s);
+        g_kprof->recs.push_back(r);
+    } else {
+        hipEventRecord(g_kprof->recs.back().b, s);
+    }
+}
+}  // namespace he
+
 namespace {
 
 thread_local std::string g_err;
@@ -1320,6 +1344,50 @@ int he_sync(he_ctx *C) {
     return guarded([&]() {
         REQUIRE(C, HE_EINVAL, "null context");
         HIPCHK(hipStreamSynchronize(C->stream));
+        return HE_OK;
+    });
+}
+
+int he_profile_begin(he_ctx *C) {
+    return guarded([&]() {
+        REQUIRE(C, HE_EINVAL, "null context");
+        REQUIRE(!g_kprof, HE_ESTATE, "a profile is already running");
+        HIPCHK(hipSetDevice(C->device));
+        g_kprof = new KProf;
+        return HE_OK;
+    });
+}
+
+int he_profile_end(he_ctx *C, char *buf, size_t cap) {
+    return guarded([&]() {
+        REQUIRE(C && buf && cap > 2, HE_EINVAL, "bad argument");
+        REQUIRE(g_kprof, HE_ESTATE, "no profile running");
+        KProf *P = g_kprof;
+        g_kprof = nullptr;
+        HIPCHK(hipStreamSynchronize(C->stream));
+        struct Agg { long n = 0; double ms = 0, bytes = 0; };
+        std::map<std::string, Agg> agg;
+        for (auto &r : P->recs) {
+            float ms = 0;
+            hipEventElapsedTime(&ms, r.a, r.b);
+            auto &e = agg[r.name];
+            e.n += 1;
+            e.ms += ms;
+            e.bytes += r.bytes;
+            hipEventDestroy(r.a);
+            hipEventDestroy(r.b);
+        }
+        delete P;
+        std::string js = "{";
+        for (auto &kv : agg) {
+            char tmp[256];
+            std::snprintf(tmp, sizeof tmp, "%s\"%s\": [%ld, %.6f, %.1f]", js.size() > 1 ? ", " : "",
+                          kv.first.c_str(), kv.second.n, kv.second.ms, kv.second.bytes);
+            js += tmp;
+        }
+        js += "}";
+        REQUIRE(js.size() + 1 <= cap, HE_EINVAL, "profile buffer too small");
+        std::memcpy(buf, js.c_str(), js.size() + 1);
         return HE_OK;
     });
 }

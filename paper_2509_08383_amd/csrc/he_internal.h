@@ -47,6 +47,13 @@ struct ConstTab {
     int stride;
 };
 
+// optional per-kernel profiler: when set, every launch is bracketed by HIP
+// events on its stream (see he_profile_begin / he_profile_end)
+struct KProf;
+extern KProf *g_kprof;
+void kprof_mark(const char *name, hipStream_t s, bool end);
+void kprof_set_bytes(double algorithmic_bytes);  // for the next launch
+
 // ---------------------------------------------------------------- kernels.hip
 void launch_ntt(const DevTables &T, const VecSet &vs, bool inverse, int variant, hipStream_t s);
 void launch_add(const DevTables &T, const VecSet &out, const VecSet &a, const VecSet &b, int sign,

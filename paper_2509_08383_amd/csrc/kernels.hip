@@ -16,6 +16,14 @@ namespace he {
 
 #define DEV __device__ __forceinline__
 
+// kernel launch with the optional per-kernel event profiler around it
+#define KL(name, kern, grid, block, shm, stream, ...)                 \
+    do {                                                              \
+        if (g_kprof) kprof_mark(name, stream, false);                 \
+        hipLaunchKernelGGL(kern, grid, block, shm, stream, __VA_ARGS__); \
+        if (g_kprof) kprof_mark(name, stream, true);                  \
+    } while (0)
+
 DEV double mm(double a, double b, double p, double pinv) {
     double h = a * b;
     double l = __builtin_fma(a, b, -h);
@@ -193,12 +201,18 @@ template <int H>
 static void ntt_h(const DevTables &T, const VecSet &vs, bool inverse, hipStream_t s) {
     constexpr int SUB = 1 << (2 * H), COLS = 256 / (1 << H);
     dim3 grid(SUB / COLS, vs.count), block(256);
+    // each pass reads and writes every word once
+    const double bytes = 16.0 * SUB * SUB * vs.count;
     if (!inverse) {
-        hipLaunchKernelGGL((k_ntt<H, false, false>), grid, block, 0, s, vs, T);
-        hipLaunchKernelGGL((k_ntt<H, true, false>), grid, block, 0, s, vs, T);
+        kprof_set_bytes(bytes);
+        KL("ntt_fwd_pass1", (k_ntt<H, false, false>), grid, block, 0, s, vs, T);
+        kprof_set_bytes(bytes);
+        KL("ntt_fwd_pass2", (k_ntt<H, true, false>), grid, block, 0, s, vs, T);
     } else {
-        hipLaunchKernelGGL((k_ntt<H, true, true>), grid, block, 0, s, vs, T);
-        hipLaunchKernelGGL((k_ntt<H, false, true>), grid, block, 0, s, vs, T);
+        kprof_set_bytes(bytes);
+        KL("ntt_inv_pass2", (k_ntt<H, true, true>), grid, block, 0, s, vs, T);
+        kprof_set_bytes(bytes);
+        KL("ntt_inv_pass1", (k_ntt<H, false, true>), grid, block, 0, s, vs, T);
     }
 }
 
@@ -230,7 +244,7 @@ __global__ void k_add(VecSet out, VecSet a, VecSet b, DevTables T, int sign) {
 void launch_add(const DevTables &T, const VecSet &out, const VecSet &a, const VecSet &b, int sign,
                 hipStream_t s) {
     if (out.count <= 0) return;
-    hipLaunchKernelGGL(k_add, ew_grid(T, out.count), dim3(256), 0, s, out, a, b, T, sign);
+    KL("k_add", k_add, ew_grid(T, out.count), dim3(256), 0, s, out, a, b, T, sign);
 }
 
 __global__ void k_copy(VecSet out, VecSet a, DevTables T) {
@@ -241,7 +255,7 @@ __global__ void k_copy(VecSet out, VecSet a, DevTables T) {
 }
 void launch_copy(const DevTables &T, const VecSet &out, const VecSet &a, hipStream_t s) {
     if (out.count <= 0) return;
-    hipLaunchKernelGGL(k_copy, ew_grid(T, out.count), dim3(256), 0, s, out, a, T);
+    KL("k_copy", k_copy, ew_grid(T, out.count), dim3(256), 0, s, out, a, T);
 }
 
 __global__ void k_mul_const(VecSet out, VecSet a, ConstTab k, DevTables T) {
@@ -254,7 +268,7 @@ __global__ void k_mul_const(VecSet out, VecSet a, ConstTab k, DevTables T) {
 void launch_mul_const(const DevTables &T, const VecSet &out, const VecSet &a, ConstTab k,
                       hipStream_t s) {
     if (out.count <= 0) return;
-    hipLaunchKernelGGL(k_mul_const, ew_grid(T, out.count), dim3(256), 0, s, out, a, k, T);
+    KL("k_mul_const", k_mul_const, ew_grid(T, out.count), dim3(256), 0, s, out, a, k, T);
 }
 
 // adds the constant to every NTT-domain coefficient (a constant polynomial
@@ -268,7 +282,7 @@ __global__ void k_add_const(VecSet out, VecSet a, ConstTab k, DevTables T) {
 void launch_add_const(const DevTables &T, const VecSet &out, const VecSet &a, ConstTab k,
                       hipStream_t s) {
     if (out.count <= 0) return;
-    hipLaunchKernelGGL(k_add_const, ew_grid(T, out.count), dim3(256), 0, s, out, a, k, T);
+    KL("k_add_const", k_add_const, ew_grid(T, out.count), dim3(256), 0, s, out, a, k, T);
 }
 
 // out = a * k - b[map]   (b group index = bmap[g / bdiv] * bdiv + g % bdiv)
@@ -286,7 +300,7 @@ __global__ void k_axpy_map(VecSet out, VecSet a, ConstTab k, VecSet b, const int
 void launch_axpy_map(const DevTables &T, const VecSet &out, const VecSet &a, ConstTab k,
                      const VecSet &b, const int *bmap, int bdiv, hipStream_t s) {
     if (out.count <= 0) return;
-    hipLaunchKernelGGL(k_axpy_map, ew_grid(T, out.count), dim3(256), 0, s, out, a, k, b, bmap, bdiv, T);
+    KL("k_axpy_map", k_axpy_map, ew_grid(T, out.count), dim3(256), 0, s, out, a, k, b, bmap, bdiv, T);
 }
 
 // out group g (= req * gdiv + j) = sum over k < cnt[req] of in group (first[req] + k) * gdiv + j
@@ -306,7 +320,7 @@ __global__ void k_sum_groups(VecSet out, VecSet in, const int *first, const int 
 void launch_sum_groups(const DevTables &T, const VecSet &out, const VecSet &in, const int *first,
                        const int *cnt, int gdiv, hipStream_t s) {
     if (out.count <= 0) return;
-    hipLaunchKernelGGL(k_sum_groups, ew_grid(T, out.count), dim3(256), 0, s, out, in, first, cnt, gdiv, T);
+    KL("k_sum_groups", k_sum_groups, ew_grid(T, out.count), dim3(256), 0, s, out, in, first, cnt, gdiv, T);
 }
 
 // d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1 per (ciphertext, limb)
@@ -329,7 +343,8 @@ void launch_tensor(const DevTables &T, double *d0, double *d1, double *d2, long 
                    const double *a, const double *b, long long astride, long long bstride,
                    const int *bmap, long long apoly, long long bpoly, int cnt, int limbs, hipStream_t s) {
     if (cnt <= 0) return;
-    hipLaunchKernelGGL(k_tensor, dim3((T.N + 255) / 256, cnt * limbs), dim3(256), 0, s, T, d0, d1,
+    kprof_set_bytes(8.0 * T.N * cnt * limbs * 7);  // 4 words in, 3 out
+    KL("k_tensor", k_tensor, dim3((T.N + 255) / 256, cnt * limbs), dim3(256), 0, s, T, d0, d1,
                        d2, dstride, a, b, astride, bstride, bmap, apoly, bpoly, limbs);
 }
 
@@ -349,7 +364,7 @@ __global__ void k_automorph(VecSet out, VecSet in, uint64_t galois, DevTables T)
 void launch_automorph(const DevTables &T, const VecSet &out, const VecSet &in, uint64_t galois,
                       hipStream_t s) {
     if (out.count <= 0) return;
-    hipLaunchKernelGGL(k_automorph, ew_grid(T, out.count), dim3(256), 0, s, out, in, galois, T);
+    KL("k_automorph", k_automorph, ew_grid(T, out.count), dim3(256), 0, s, out, in, galois, T);
 }
 
 // ------------------------------------------------------------ key switching
@@ -394,7 +409,8 @@ void launch_modup(const DevTables &T, const double *dcoef, long long dstride, do
                   const double *qhat, hipStream_t s) {
     (void)digit;
     if (cnt <= 0) return;
-    hipLaunchKernelGGL(k_modup, dim3((T.N + 255) / 256, cnt), dim3(256), 0, s, T, dcoef, dstride,
+    kprof_set_bytes(8.0 * T.N * cnt * (2 * dl + next));  // digit in (coef + NTT copy), all limbs out
+    KL("k_modup", k_modup, dim3((T.N + 255) / 256, cnt), dim3(256), 0, s, T, dcoef, dstride,
                        ext, estride, dntt, nstride, level, lo, dl, next, ext_prime, vinv, qhat);
 }
 
@@ -435,7 +451,9 @@ void launch_inner_product(const DevTables &T, const double *ext, long long estri
                           const double *key, long long kstride_j, long long kstride_c, int cnt,
                           int beta, int next, const int *ext_prime, hipStream_t s) {
     if (cnt <= 0) return;
-    hipLaunchKernelGGL(k_inner_product, dim3((T.N + 255) / 256, next), dim3(256), 0, s, T, ext,
+    // key words once, extended digits and both accumulators per ciphertext
+    kprof_set_bytes(8.0 * T.N * next * (2.0 * beta + cnt * (beta + 2.0)));
+    KL("k_inner_product", k_inner_product, dim3((T.N + 255) / 256, next), dim3(256), 0, s, T, ext,
                        estride_b, estride_j, acc0, acc1, astride, key, kstride_j, kstride_c, cnt,
                        beta, ext_prime);
 }
@@ -474,7 +492,8 @@ void launch_moddown_conv(const DevTables &T, const double *acc, long long astrid
                          long long cstride, int cnt, int level, const double *phinv,
                          const double *phat, hipStream_t s) {
     if (cnt <= 0) return;
-    hipLaunchKernelGGL(k_moddown_conv, dim3((T.N + 255) / 256, cnt), dim3(256), 0, s, T, acc,
+    kprof_set_bytes(8.0 * T.N * cnt * (T.alpha + level + 1));
+    KL("k_moddown_conv", k_moddown_conv, dim3((T.N + 255) / 256, cnt), dim3(256), 0, s, T, acc,
                        astride, conv, cstride, level, phinv, phat);
 }
 
@@ -497,7 +516,8 @@ void launch_moddown_combine(const DevTables &T, double *out, long long ostride, 
                             const double *add, long long add_ct, long long add_poly, int addmask,
                             int groups, int level, const double *Pinv, hipStream_t s) {
     if (groups <= 0) return;
-    hipLaunchKernelGGL(k_moddown_combine, dim3((T.N + 255) / 256, groups * (level + 1)), dim3(256), 0, s,
+    kprof_set_bytes(8.0 * T.N * groups * (level + 1) * (add ? 4.0 - 0.5 * (addmask == 1) : 3.0));
+    KL("k_moddown_combine", k_moddown_combine, dim3((T.N + 255) / 256, groups * (level + 1)), dim3(256), 0, s,
                        T, out, ostride, acc, astride, conv, cstride, add, add_ct, add_poly, addmask,
                        level + 1, Pinv);
 }
@@ -517,7 +537,7 @@ __global__ void k_rescale_lift(DevTables T, const double *lastc, long long lstri
 void launch_rescale_lift(const DevTables &T, const double *lastc, long long lstride, double *lift,
                          long long fstride, int cnt, int level, hipStream_t s) {
     if (cnt <= 0 || level <= 0) return;
-    hipLaunchKernelGGL(k_rescale_lift, dim3((T.N + 255) / 256, cnt * level), dim3(256), 0, s, T,
+    KL("k_rescale_lift", k_rescale_lift, dim3((T.N + 255) / 256, cnt * level), dim3(256), 0, s, T,
                        lastc, lstride, lift, fstride, level);
 }
 
@@ -539,7 +559,7 @@ void launch_rescale_combine(const DevTables &T, double *out, long long ostride, 
                             long long istride, const double *lift, long long fstride, int cnt,
                             int level, const double *qlinv, const double *kmul, hipStream_t s) {
     if (cnt <= 0 || level <= 0) return;
-    hipLaunchKernelGGL(k_rescale_combine, dim3((T.N + 255) / 256, cnt * level), dim3(256), 0, s, T,
+    KL("k_rescale_combine", k_rescale_combine, dim3((T.N + 255) / 256, cnt * level), dim3(256), 0, s, T,
                        out, ostride, in, istride, lift, fstride, level, qlinv, kmul);
 }
 
@@ -585,7 +605,7 @@ __global__ void k_sample_uniform(VecSet out, uint64_t seed, uint32_t obj, const 
 void launch_sample_uniform(const DevTables &T, const VecSet &out, uint64_t seed, uint32_t obj,
                            const int *gprime, hipStream_t s) {
     if (out.count <= 0) return;
-    hipLaunchKernelGGL(k_sample_uniform, ew_grid(T, out.count), dim3(256), 0, s, out, seed, obj, gprime, T);
+    KL("k_sample_uniform", k_sample_uniform, ew_grid(T, out.count), dim3(256), 0, s, out, seed, obj, gprime, T);
 }
 
 // kind 0: ternary ((o0*3)>>32) - 1; kind 1: centred binomial eta = 21
@@ -598,7 +618,7 @@ __global__ void k_sample_small(int *out, int N, uint64_t seed, uint32_t obj, int
     else out[x] = __popc(o[0] & 0x1FFFFFu) - __popc(o[1] & 0x1FFFFFu);
 }
 void launch_sample_small(int *out, int N, uint64_t seed, uint32_t obj, int kind, hipStream_t s) {
-    hipLaunchKernelGGL(k_sample_small, dim3((N + 255) / 256), dim3(256), 0, s, out, N, seed, obj, kind);
+    KL("k_sample_small", k_sample_small, dim3((N + 255) / 256), dim3(256), 0, s, out, N, seed, obj, kind);
 }
 
 __global__ void k_small_to_res(VecSet out, const int *v, DevTables T) {
@@ -610,7 +630,7 @@ void launch_small_to_res(const DevTables &T, const VecSet &out, const int *v, co
                          hipStream_t s) {
     (void)gprime;
     if (out.count <= 0) return;
-    hipLaunchKernelGGL(k_small_to_res, ew_grid(T, out.count), dim3(256), 0, s, out, v, T);
+    KL("k_small_to_res", k_small_to_res, ew_grid(T, out.count), dim3(256), 0, s, out, v, T);
 }
 
 // int64 coefficients -> residues: m = hi 2^32 + lo
@@ -626,7 +646,7 @@ void launch_int64_to_res(const DevTables &T, const VecSet &out, const int64_t *m
                          long long mstride, const int *gprime, hipStream_t s) {
     (void)gprime;
     if (out.count <= 0) return;
-    hipLaunchKernelGGL(k_int64_to_res, ew_grid(T, out.count), dim3(256), 0, s, out, m, mstride, T);
+    KL("k_int64_to_res", k_int64_to_res, ew_grid(T, out.count), dim3(256), 0, s, out, m, mstride, T);
 }
 
 // key digit: b = e - a s + [lo <= prime < hi] (P mod q) s'   (NTT domain)
@@ -643,7 +663,7 @@ __global__ void k_keyb(DevTables T, double *b, const double *a, const double *e,
 }
 void launch_keyb(const DevTables &T, double *b, const double *a, const double *e, const double *s,
                  const double *tgt, const double *pmod, int np, int lo, int hi, hipStream_t st) {
-    hipLaunchKernelGGL(k_keyb, dim3((T.N + 255) / 256, np), dim3(256), 0, st, T, b, a, e, s, tgt, pmod, lo, hi);
+    KL("k_keyb", k_keyb, dim3((T.N + 255) / 256, np), dim3(256), 0, st, T, b, a, e, s, tgt, pmod, lo, hi);
 }
 
 // c0 = m + e - a s per (ciphertext, limb)
@@ -662,7 +682,7 @@ void launch_encfinish(const DevTables &T, double *c0, const double *a, const dou
                       const double *m, const double *s, long long stride, int limbs, int cnt,
                       long long ctstride, long long mctstride, hipStream_t st) {
     (void)stride;
-    hipLaunchKernelGGL(k_encfinish, dim3((T.N + 255) / 256, cnt * limbs), dim3(256), 0, st, T, c0, a,
+    KL("k_encfinish", k_encfinish, dim3((T.N + 255) / 256, cnt * limbs), dim3(256), 0, st, T, c0, a,
                        e, m, s, limbs, ctstride, mctstride);
 }
 
@@ -677,7 +697,7 @@ __global__ void k_decmul(DevTables T, double *m, const double *c0, const double 
 }
 void launch_decmul(const DevTables &T, double *m, const double *c0, const double *c1,
                    const double *s, int limbs, hipStream_t st) {
-    hipLaunchKernelGGL(k_decmul, dim3((T.N + 255) / 256, limbs), dim3(256), 0, st, T, m, c0, c1, s);
+    KL("k_decmul", k_decmul, dim3((T.N + 255) / 256, limbs), dim3(256), 0, st, T, m, c0, c1, s);
 }
 
 __global__ void k_square_res(DevTables T, double *out, const double *in) {
@@ -689,7 +709,7 @@ __global__ void k_square_res(DevTables T, double *out, const double *in) {
     out[o] = canon(mm(in[o], in[o], p, pinv), p, pinv);
 }
 void launch_square_res(const DevTables &T, double *out, const double *in, int np, hipStream_t st) {
-    hipLaunchKernelGGL(k_square_res, dim3((T.N + 255) / 256, np), dim3(256), 0, st, T, out, in);
+    KL("k_square_res", k_square_res, dim3((T.N + 255) / 256, np), dim3(256), 0, st, T, out, in);
 }
 
 // debug: count words that are not canonical integers in [0, p)
@@ -703,7 +723,7 @@ __global__ void k_canon_check(VecSet vs, DevTables T, int *bad) {
 }
 void launch_canon_check(const DevTables &T, const VecSet &vs, int *bad, hipStream_t st) {
     if (vs.count <= 0) return;
-    hipLaunchKernelGGL(k_canon_check, ew_grid(T, vs.count), dim3(256), 0, st, vs, T, bad);
+    KL("k_canon_check", k_canon_check, ew_grid(T, vs.count), dim3(256), 0, st, vs, T, bad);
 }
 
 }  // namespace he

@@ -86,6 +86,8 @@ def lib():
             "he_last_cutmax_ms": [_V, _c_dp],
             "he_sync": [_V],
             "he_set_option": [_V, ctypes.c_int, ctypes.c_int64],
+            "he_profile_begin": [_V],
+            "he_profile_end": [_V, ctypes.c_char_p, ctypes.c_size_t],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -335,6 +337,15 @@ class Context:
 
     def set_option(self, opt: int, value: int):
         _check(lib().he_set_option(self.h, opt, int(value)))
+
+    def profile_begin(self):
+        _check(lib().he_profile_begin(self.h))
+
+    def profile_end(self) -> dict:
+        import json
+        buf = ctypes.create_string_buffer(1 << 16)
+        _check(lib().he_profile_end(self.h, buf, len(buf)))
+        return {k: (v[0], v[1], v[2]) for k, v in json.loads(buf.value.decode()).items()}
 
 
 def topp_noise(top_p: float, u: np.ndarray) -> np.ndarray:

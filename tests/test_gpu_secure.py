@@ -1,0 +1,120 @@
+"""GPU parity at the 128-bit parameter set (N = 2^16, 30 Q primes, dnum = 3): primitives
+bit-exact against the CPU oracle at full size; encrypted CutMax on 32000 LLM-like logits
+against the FP64 mirror within 1e-3 with the argmax recovered; the batched form (config 3)
+with 1- and 4-ciphertext requests."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import ckks  # noqa: E402
+from oracle.cutmax_fp64 import (MirrorCfg, chebyshev_invsqrt, cutmax_exact, cutmax_mirror,  # noqa: E402
+                                slot_layout)
+from workloads import llm_logits  # noqa: E402
+from test_gpu_parity import Pair, say  # noqa: E402
+
+VLO, VHI = [12.0, 0.4, 0.8], [24.0, 0.9, 16.0]
+
+
+@pytest.fixture(scope="module")
+def sec():
+    from paper_2509_08383_amd import he
+    say("[gpu] building secure pair (N=2^16)")
+    return Pair(he.SECURE)
+
+
+def cfg2(he, T=3, coef=None, degree=3):
+    if coef is None:
+        coef = [list(chebyshev_invsqrt(VLO[t] / VHI[t], degree)) for t in range(T)]
+    return he.CutmaxCfg(T=T, p=[3] * T, c=[5.0] * T, var_lo=VLO[:T], var_hi=VHI[:T], init_degree=degree,
+                        init_coef=coef, sum_lo=1.0, sum_hi=3.0, gold_d=3), coef
+
+
+def mirror2(y, coef, T=3):
+    return MirrorCfg(T=T, p=[3] * T, c=[5.0] * T, v_hi=VHI[:T], v_lo=VLO[:T], coef=coef, B=3.0 * y.size,
+                     gold_d=3, sum_lo=1.0 * y.size)
+
+
+def test_secure_chain(sec):
+    G = sec.G
+    assert G.N == 65536 and G.L == 29 and G.alpha == 10
+    bits = sum(math.log2(q) for q in G.primes)
+    assert bits <= 1772, bits           # 128-bit bound at N = 2^16, ternary secret
+
+
+def test_encrypt_and_primitives_full_size(sec):
+    say("[gpu] secure: encrypt/mul/rotate/cmul bit-exact")
+    rng = np.random.default_rng(9)
+    x = rng.uniform(-4, 4, sec.G.slots)
+    y = rng.uniform(-4, 4, sec.G.slots)
+    gx, ox = sec.enc_values(x)
+    gy, oy = sec.enc_values(y)
+    sec.same(gx, ox, "encrypt")
+    sec.same(sec.G.mul(gx, gy), sec.O.mul(ox, oy), "mul")
+    sec.same(sec.G.rotate(gx, 14), sec.O.rotate(ox, 14), "rotate 2^14")
+    sec.same(sec.G.rotate(gx, 0), sec.O.rotate(ox, 0), "rotate 1")
+    sec.same(sec.G.cmul(gx, 1e-3, sec.O.Delta, True), sec.O.cm_exact(ox, 1e-3, sec.O.Delta), "cm_exact")
+    lv = 9
+    sec.same(sec.G.mul(sec.G.drop(gx, lv), sec.G.drop(gy, lv)), sec.O.mul(sec.O.drop(ox, lv), sec.O.drop(oy, lv)),
+             "mul@9")
+    np.testing.assert_allclose(sec.G.decrypt(sec.G.mul(gx, gy)), x * y, atol=1e-6)
+
+
+def test_cutmax_secure_T1_bit_exact(sec):
+    """one CutMax iteration plus the final inverse at full size, bit for bit"""
+    from paper_2509_08383_amd import he
+    say("[gpu] secure: CutMax T=1 bit-exact")
+    x = llm_logits(101)
+    y, a, _ = slot_layout(x, sec.G.slots)
+    cfg, coef = cfg2(he, T=1)
+    g, o = sec.enc_values(y)
+    Zg = sec.G.cutmax([g], cfg)[0]
+    Zo = ckks.cutmax_he(sec.O, [o], ckks.HECfg(T=1, p=[3], c=[5.0], v_lo=VLO[:1], v_hi=VHI[:1], coef=coef,
+                                               sum_lo=1.0, sum_hi=3.0))[0]
+    sec.same(Zg, Zo, "cutmax T=1")
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_cutmax_config2_vs_mirror(sec, seed):
+    """config 2: 32000 logits (3 Gumbel - 1.1 ln rank) zero-padded to 32768 slots, T=3, p=3, c=5"""
+    from paper_2509_08383_amd import he
+    say(f"[gpu] secure: CutMax config 2 seed {seed}")
+    x = llm_logits(seed)
+    y, a, _ = slot_layout(x, sec.G.slots)
+    cfg, coef = cfg2(he)
+    ct = sec.G.encrypt(x)
+    sec.O.nonce = sec.O.nonce + 1
+    Z = sec.G.cutmax([ct], cfg)[0]
+    assert Z.level == sec.G.L - 27
+    dz = sec.G.decrypt(Z, y.size)
+    err = np.abs(dz - cutmax_mirror(y, mirror2(y, coef))).max()
+    say(f"  |Z - mirror| = {err:.3e}, {sec.G.last_cutmax_ms():.1f} ms")
+    assert err < 1e-3
+    assert int(np.argmax(dz[:x.size])) == int(np.argmax(x))
+    assert int(np.argmax(cutmax_exact(y, 3, 5.0, 3)[:x.size])) == int(np.argmax(x))
+
+
+def test_cutmax_config3_batched(sec):
+    """config 3: 16 requests, even ids 32000 logits (1 ciphertext), odd ids 128256 (4 ciphertexts)"""
+    from paper_2509_08383_amd import he
+    say("[gpu] secure: batched config 3")
+    xs = [llm_logits(200 + r, 32000 if r % 2 == 0 else 128256) for r in range(16)]
+    cts = [sec.G.encrypt(x) for x in xs]
+    sec.O.nonce = sec.O.nonce + sum(c.a for c in cts)
+    assert [c.a for c in cts] == [1, 4] * 8
+    cfg, coef = cfg2(he)
+    Z = sec.G.cutmax(cts, cfg)
+    say(f"  batch of 16: {sec.G.last_cutmax_ms():.1f} ms")
+    for r in (0, 1, 6, 15):
+        y, a, _ = slot_layout(xs[r], sec.G.slots)
+        dz = sec.G.decrypt(Z[r], y.size)
+        err = np.abs(dz - cutmax_mirror(y, mirror2(y, coef))).max()
+        assert err < 1e-3, (r, err)
+        assert int(np.argmax(dz[:xs[r].size])) == int(np.argmax(xs[r])), r
+    # a batched request equals its single run bit for bit
+    for r in (0, 1):
+        Zs = sec.G.cutmax([cts[r]], cfg)[0]
+        assert np.array_equal(sec.G.export(Zs), sec.G.export(Z[r])), r
