@@ -215,6 +215,7 @@ def main():
         "argmax_ok": bool(argmax_ok),
         "batched": batch,
         "ntt": ntt,
+        "ntt_tuning": ctx.ntt_tuning(),
         "roofline": roof,
         "kernels": {k: {"launches": v[0], "ms": v[1], "bytes": v[2]} for k, v in kern.items()},
         "cpu_baseline": cpu,

@@ -199,6 +199,11 @@ int he_profile_end(he_ctx *ctx, char *buf, size_t cap);
 #define HE_OPT_NTT_VARIANT 2
 int he_set_option(he_ctx *ctx, int option, int64_t value);
 
+/* NTT autotuner result: the workgroup-width variant (1: 4 or 8 sub-transforms
+ * per workgroup, 2: 8 or 16, 3: 16 or 32 for N = 2^16 / 2^12) chosen for batch
+ * buckets of <=16, <=64, <=256, <=1024, ... vectors (n entries, at most 8). */
+int he_ntt_tuning(const he_ctx *ctx, int32_t *variants, uint32_t n);
+
 #ifdef __cplusplus
 }
 #endif

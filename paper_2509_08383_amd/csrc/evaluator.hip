@@ -139,6 +139,8 @@ struct he_ctx {
     std::vector<std::vector<const int *>> ndslot, ndprime;
     std::vector<std::vector<int>> ndcount;
     const double *phinv = nullptr, *phat = nullptr, *Pinv = nullptr, *qlinv = nullptr, *pmod = nullptr;
+    std::vector<const double *> mu_scale;  // [L+1] -> [l+1]: N^-1 Qhat_i^-1 mod q_i at level l
+    const double *md_scale = nullptr;      // [alpha]: N^-1 Phat_m^-1 mod p_m
     const int *ident = nullptr;   // 0..np-1
     const int *pprime = nullptr;  // L+1 .. L+alpha
     uint32_t nonce = 0;
@@ -171,10 +173,12 @@ struct Bt {
 
 struct Exec {
     he_ctx *C;
-    bool dry;
+    bool dry;            // sizing pass: fake addresses, no launches
+    bool quiet = false;  // replay pass: real addresses, the kernels come from a captured graph
     hipStream_t s;
     const DevTables &T;
     Exec(he_ctx *c, bool d) : C(c), dry(d), s(c->stream), T(c->T) {}
+    bool go() const { return !dry && !quiet; }
 
     double *alloc_d(size_t words) { return (double *)C->arena.alloc(words * 8); }
     Bt new_bt(int cnt, int level) {
@@ -207,19 +211,19 @@ struct Exec {
             REQUIRE(std::fabs(a.scale[c] - b.scale[c]) <= 1e-9 * a.scale[c], HE_ERANGE, "add: scale mismatch");
         Bt o = new_bt(a.cnt, a.level);
         o.scale = a.scale;
-        if (!dry) launch_add(T, vs_all(o), vs_all(a), vs_all(b), sign, s);
+        if (go()) launch_add(T, vs_all(o), vs_all(a), vs_all(b), sign, s);
         return o;
     }
     void add_inplace(Bt &a, const Bt &b) {
         REQUIRE(a.level == b.level && a.cnt == b.cnt, HE_ESTATE, "add: level/count mismatch");
         for (int c = 0; c < a.cnt; ++c)
             REQUIRE(std::fabs(a.scale[c] - b.scale[c]) <= 1e-9 * a.scale[c], HE_ERANGE, "add: scale mismatch");
-        if (!dry) launch_add(T, vs_all(a), vs_all(a), vs_all(b), 1, s);
+        if (go()) launch_add(T, vs_all(a), vs_all(a), vs_all(b), 1, s);
     }
     Bt copy(const Bt &a) {
         Bt o = new_bt(a.cnt, a.level);
         o.scale = a.scale;
-        if (!dry) launch_copy(T, vs_all(o), vs_all(a), s);
+        if (go()) launch_copy(T, vs_all(o), vs_all(a), s);
         return o;
     }
     Bt drop(const Bt &a, int level) const {
@@ -232,7 +236,7 @@ struct Exec {
         Bt o = new_bt(a.cnt, a.level);
         o.scale = a.scale;
         ConstTab kt{residues(k, a.level), 2, a.level + 1};
-        if (!dry) launch_mul_const(T, vs_all(o), vs_all(a), kt, s);
+        if (go()) launch_mul_const(T, vs_all(o), vs_all(a), kt, s);
         return o;
     }
     Bt add_const(const Bt &a, const std::vector<double> &c) {
@@ -241,7 +245,7 @@ struct Exec {
         Bt o = new_bt(a.cnt, a.level);
         o.scale = a.scale;
         ConstTab kt{residues(v, a.level), 1, a.level + 1};
-        if (!dry) {
+        if (go()) {
             launch_add_const(T, vs_poly(o, 0), vs_poly(a, 0), kt, s);
             launch_copy(T, vs_poly(o, 1), vs_poly(a, 1), s);
         }
@@ -256,7 +260,7 @@ struct Exec {
         o.scale = Y.scale;
         ConstTab kt{residues(n, Y.level), 2, Y.level + 1};
         const int *dmap = C->pool.push(cmap);
-        if (!dry) launch_axpy_map(T, vs_all(o), vs_all(Y), kt, vs_all(S), dmap, 2, s);
+        if (go()) launch_axpy_map(T, vs_all(o), vs_all(Y), kt, vs_all(S), dmap, 2, s);
         return o;
     }
     // per-request sums of consecutive ciphertexts
@@ -270,7 +274,7 @@ struct Exec {
         }
         const int *df = C->pool.push(first);
         const int *dc = C->pool.push(cnt);
-        if (!dry) launch_sum_groups(T, vs_all(o), vs_all(Y), df, dc, 2, s);
+        if (go()) launch_sum_groups(T, vs_all(o), vs_all(Y), df, dc, 2, s);
         return o;
     }
 
@@ -286,12 +290,15 @@ struct Exec {
         const int G = a.cnt * 2;
         double *last = alloc_d((size_t)G * C->N);
         double *lift = alloc_d((size_t)G * l * C->N);
-        if (!dry) {
+        if (go()) {
             VecSet src{a.d + (long long)l * C->N, G, 1, (long long)a.cap * C->N, nullptr, C->ident + l};
             VecSet dst{last, G, 1, (long long)C->N, nullptr, C->ident + l};
-            if (kres) launch_mul_const(T, dst, src, ConstTab{kres + l, 2, l + 1}, s);
-            else launch_copy(T, dst, src, s);
-            launch_ntt(T, dst, true, C->ntt_variant, s);
+            if (kres) {
+                launch_mul_const(T, dst, src, ConstTab{kres + l, 2, l + 1}, s);
+                launch_ntt(T, dst, true, C->ntt_variant, s);
+            } else {
+                launch_ntt(T, dst, true, C->ntt_variant, s, &src);
+            }
             launch_rescale_lift(T, last, C->N, lift, (long long)l * C->N, G, l, s);
             launch_ntt(T, VecSet{lift, G * l, l, (long long)l * C->N, nullptr, nullptr}, false, C->ntt_variant, s);
             launch_rescale_combine(T, o.d, (long long)o.cap * C->N, a.d, (long long)a.cap * C->N, lift,
@@ -314,15 +321,20 @@ struct Exec {
         double *ext = alloc_d((size_t)cnt * beta * next * N);
         double *acc = alloc_d((size_t)cnt * 2 * next * N);
         double *conv = alloc_d((size_t)cnt * 2 * (l + 1) * N);
-        if (!dry) {
+        if (go()) {
+            // coefficient-domain digits, already scaled by Qhat_i^-1 (folded into N^-1)
             VecSet vd{dcoef, cnt * (l + 1), l + 1, (long long)(l + 1) * N, nullptr, nullptr};
-            launch_copy(T, vd, VecSet{const_cast<double *>(d), cnt * (l + 1), l + 1, dstride, nullptr, nullptr}, s);
-            launch_ntt(T, vd, true, C->ntt_variant, s);
+            const VecSet vsrc{const_cast<double *>(d), cnt * (l + 1), l + 1, dstride, nullptr, nullptr};
+            launch_ntt(T, vd, true, C->ntt_variant, s, &vsrc, C->mu_scale[l]);
+            ModUpDigits dg{};
             for (int j = 0; j < beta; ++j) {
-                const int lo = j * A, dl = std::min(A, l + 1 - lo);
-                launch_modup(T, dcoef, (long long)(l + 1) * N, ext + (long long)j * next * N,
-                             (long long)beta * next * N, d, dstride, cnt, l, j, lo, dl, next,
-                             C->ext_prime[l], C->vinv[l][j], C->qhat[l][j], s);
+                dg.qhat[j] = C->qhat[l][j];
+                dg.lo[j] = j * A;
+                dg.dl[j] = std::min(A, l + 1 - j * A);
+            }
+            launch_modup(T, dcoef, (long long)(l + 1) * N, ext, (long long)beta * next * N, (long long)next * N, d,
+                         dstride, cnt, beta, next, C->ext_prime[l], dg, s);
+            for (int j = 0; j < beta; ++j) {
                 const int nd = C->ndcount[l][j];
                 launch_ntt(T, VecSet{ext + (long long)j * next * N, cnt * nd, nd, (long long)beta * next * N,
                                      C->ndslot[l][j], C->ndprime[l][j]}, false, C->ntt_variant, s);
@@ -330,10 +342,10 @@ struct Exec {
             launch_inner_product(T, ext, (long long)beta * next * N, (long long)next * N, acc, acc + (long long)next * N,
                                  2LL * next * N, C->keys[kidx], 2LL * C->np * N, (long long)C->np * N, cnt, beta,
                                  next, C->ext_prime[l], s);
+            // P slots to the coefficient domain, scaled by Phat_m^-1
             launch_ntt(T, VecSet{acc + (long long)(l + 1) * N, cnt * 2 * A, A, (long long)next * N, nullptr, C->pprime},
-                       true, C->ntt_variant, s);
-            launch_moddown_conv(T, acc, (long long)next * N, conv, (long long)(l + 1) * N, cnt * 2, l, C->phinv,
-                                C->phat, s);
+                       true, C->ntt_variant, s, nullptr, C->md_scale);
+            launch_moddown_conv(T, acc, (long long)next * N, conv, (long long)(l + 1) * N, cnt * 2, l, C->phat, s);
             launch_ntt(T, VecSet{conv, cnt * 2 * (l + 1), l + 1, (long long)(l + 1) * N, nullptr, nullptr}, false,
                        C->ntt_variant, s);
             launch_moddown_combine(T, out, ostride, acc, (long long)next * N, conv, (long long)(l + 1) * N, add,
@@ -353,7 +365,7 @@ struct Exec {
         const size_t m = C->arena.mark();
         double *t = alloc_d((size_t)a.cnt * 3 * (l + 1) * N);
         const int *dmap = bmap ? C->pool.push(*bmap) : nullptr;
-        if (!dry)
+        if (go())
             launch_tensor(T, t, t + (l + 1) * N, t + 2 * (l + 1) * N, 3LL * (l + 1) * N, a.d, b.d,
                           2LL * a.cap * N, 2LL * b.cap * N, dmap, (long long)a.cap * N, (long long)b.cap * N,
                           a.cnt, l + 1, s);
@@ -393,7 +405,7 @@ struct Exec {
         double *sig = alloc_d((size_t)a.cnt * 2 * (l + 1) * N);
         uint64_t g = 5;
         for (int i = 0; i < r; ++i) g = (g * g) % (2ull * C->N);
-        if (!dry)
+        if (go())
             launch_automorph(T, VecSet{sig, a.cnt * 2 * (l + 1), l + 1, (long long)(l + 1) * N, nullptr, nullptr},
                              vs_all(a), g, s);
         keyswitch(sig + (l + 1) * N, 2LL * (l + 1) * N, a.cnt, l, 1 + r, o.d, (long long)o.cap * N, sig,
@@ -560,7 +572,7 @@ Bt cutmax_sched(Exec &X, Bt Y, const std::vector<Request> &reqs, const CutmaxCfg
         C->arena.release(mark);
         Bt Yk = X.new_bt(Yn.cnt, Yn.level);
         Yk.scale = Yn.scale;
-        if (!X.dry) launch_copy(X.T, X.vs_all(Yk), X.vs_all(Yn), X.s);
+        if (X.go()) launch_copy(X.T, X.vs_all(Yk), X.vs_all(Yn), X.s);
         // Yn's storage was released above but is only overwritten by later
         // allocations; the copy is enqueued before any of them
         Y = Yk;
@@ -728,13 +740,19 @@ void build_ctx(he_ctx *C, const he_params *prm) {
         pmod[i] = (double)P;
     }
     const size_t o_phinv = tb.d(phinv), o_phat = tb.d(phat), o_Pinv = tb.d(Pinv), o_pmod = tb.d(pmod);
+    std::vector<double> mds(A);
+    for (int m = 0; m < A; ++m) {
+        const uint64_t pm = q[L + 1 + m];
+        mds[m] = (double)mulmod_u((uint64_t)ninv[L + 1 + m], (uint64_t)phinv[m], pm);
+    }
+    const size_t o_mds = tb.d(mds);
     // rescale: q_l^-1 mod q_i
     std::vector<double> qlinv((size_t)(L + 1) * (L + 1), 0.0);
     for (int l = 1; l <= L; ++l)
         for (int i = 0; i < l; ++i) qlinv[(size_t)l * (L + 1) + i] = (double)invmod_u(q[l] % q[i], q[i]);
     const size_t o_qlinv = tb.d(qlinv);
     // ModUp per level and digit
-    std::vector<size_t> o_ext(L + 1);
+    std::vector<size_t> o_ext(L + 1), o_mus(L + 1);
     std::vector<std::vector<size_t>> o_vinv(L + 1), o_qhat(L + 1), o_nds(L + 1), o_ndp(L + 1);
     C->ndcount.assign(L + 1, {});
     for (int l = 0; l <= L; ++l) {
@@ -742,6 +760,7 @@ void build_ctx(he_ctx *C, const he_params *prm) {
         std::vector<int> ep(next);
         for (int t = 0; t < next; ++t) ep[t] = t <= l ? t : L + 1 + (t - l - 1);
         o_ext[l] = tb.i(ep);
+        std::vector<double> mus(l + 1);
         for (int j = 0; j < beta; ++j) {
             const int lo = j * A, dl = std::min(A, l + 1 - lo);
             std::vector<double> vi(dl), qh((size_t)dl * next);
@@ -750,6 +769,7 @@ void build_ctx(he_ctx *C, const he_params *prm) {
                 uint64_t v = 1;
                 for (int b = 0; b < dl; ++b) if (b != a) v = mulmod_u(v, q[lo + b] % qi, qi);
                 vi[a] = (double)invmod_u(v, qi);
+                mus[lo + a] = (double)mulmod_u((uint64_t)ninv[lo + a], (uint64_t)vi[a], qi);
                 for (int t = 0; t < next; ++t) {
                     const uint64_t pt = q[ep[t]];
                     uint64_t w = 1;
@@ -766,6 +786,7 @@ void build_ctx(he_ctx *C, const he_params *prm) {
             o_nds[l].push_back(tb.i(ns));
             o_ndp[l].push_back(tb.i(npr));
         }
+        o_mus[l] = tb.d(mus);
     }
     HIPCHK(hipMalloc(&C->d_tab, tb.dv.size() * 8));
     HIPCHK(hipMalloc(&C->d_itab, tb.iv.size() * 4));
@@ -778,6 +799,9 @@ void build_ctx(he_ctx *C, const he_params *prm) {
     C->pprime = I + o_pprime;
     C->phinv = D + o_phinv; C->phat = D + o_phat; C->Pinv = D + o_Pinv; C->pmod = D + o_pmod;
     C->qlinv = D + o_qlinv;
+    C->md_scale = D + o_mds;
+    C->mu_scale.resize(L + 1);
+    for (int l = 0; l <= L; ++l) C->mu_scale[l] = D + o_mus[l];
     C->ext_prime.resize(L + 1);
     C->vinv.assign(L + 1, {}); C->qhat.assign(L + 1, {}); C->ndslot.assign(L + 1, {}); C->ndprime.assign(L + 1, {});
     for (int l = 0; l <= L; ++l) {
@@ -837,6 +861,55 @@ void keygen(he_ctx *C) {
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipGetLastError());
     hipFree(dsmall); hipFree(ta); hipFree(te); hipFree(tg);
+}
+
+// NTT autotuner: times every workgroup-width variant of the forward + inverse
+// transform at batch sizes 16, 64, 256 and 1024 vectors on random residues and
+// keeps the fastest per batch bucket (larger batches use the 1024 choice).  Runs
+// once per process and ring degree; the choice is also kept in the context.
+int g_tuned_logN[2] = {0, 0};
+int g_tuned_choice[2][8];
+
+void autotune_ntt(he_ctx *C) {
+    const int li = C->logN == 16 ? 1 : 0;
+    if (!g_tuned_logN[li]) {
+        const int counts[4] = {16, 64, 256, 1024};
+        const int N = C->N;
+        double *buf = nullptr;
+        HIPCHK(hipMalloc(&buf, 8ull * 1024 * N));
+        hipEvent_t a, b;
+        HIPCHK(hipEventCreate(&a));
+        HIPCHK(hipEventCreate(&b));
+        const int grp = C->L + 1;
+        for (int ci = 0; ci < 4; ++ci) {
+            const int cnt = counts[ci];
+            const VecSet vs{buf, cnt, std::min(cnt, grp), (long long)std::min(cnt, grp) * N, nullptr, nullptr};
+            launch_sample_uniform(C->T, vs, 99, 0x7E000000u, nullptr, C->stream);
+            double best = 1e30;
+            int bestv = 3;
+            for (int v = 1; v <= 3; ++v) {
+                launch_ntt(C->T, vs, false, v, C->stream);
+                launch_ntt(C->T, vs, true, v, C->stream);
+                HIPCHK(hipEventRecord(a, C->stream));
+                for (int rep = 0; rep < 3; ++rep) {
+                    launch_ntt(C->T, vs, false, v, C->stream);
+                    launch_ntt(C->T, vs, true, v, C->stream);
+                }
+                HIPCHK(hipEventRecord(b, C->stream));
+                HIPCHK(hipEventSynchronize(b));
+                float ms = 0;
+                HIPCHK(hipEventElapsedTime(&ms, a, b));
+                if (ms < best) { best = ms; bestv = v; }
+            }
+            g_tuned_choice[li][ci] = bestv;
+        }
+        for (int bk = 4; bk < 8; ++bk) g_tuned_choice[li][bk] = g_tuned_choice[li][3];
+        hipEventDestroy(a);
+        hipEventDestroy(b);
+        hipFree(buf);
+        g_tuned_logN[li] = 1;
+    }
+    for (int bk = 0; bk < 8; ++bk) set_ntt_tuning(C->logN, bk, g_tuned_choice[li][bk]);
 }
 
 // encryption of already-encoded integer plaintexts m[a][N] (host memory)
@@ -925,6 +998,18 @@ int cutmax_impl(he_ctx *C, he_ct *const *in, he_ct *const *noise, size_t batch, 
             outs[r]->n = in[r]->n;
         }
         hipEvent_t e0 = C->ev0, e1 = C->ev1;
+        // the kernel sequence of the schedule depends only on the structure of the
+        // call (constants are read from the pool at run time), so a captured graph
+        // replays any later call with the same structure and workspace
+        const bool use_graph = C->use_graph && !g_kprof;
+        std::string gkey;
+        if (use_graph) {
+            gkey = "L" + std::to_string(level) + (noise ? (prescaled ? "np" : "nt") : "") + "T" +
+                   std::to_string(cf.T) + "n" + std::to_string(cf.newton) + "g" + std::to_string(cf.gold_d);
+            for (auto &r : reqs) gkey += "a" + std::to_string(r.a);
+            for (int t = 0; t < cf.T; ++t)
+                gkey += "p" + std::to_string(cf.p[t]) + "d" + std::to_string(cf.coef[t].size());
+        }
         run2(C, [&](Exec &X) {
             Bt Y = X.new_bt(total, level);
             Bt G;
@@ -947,16 +1032,54 @@ int cutmax_impl(he_ctx *C, he_ct *const *in, he_ct *const *noise, size_t batch, 
                 }
             }
             if (!X.dry) HIPCHK(hipEventRecord(e0, X.s));
-            if (noise) {
-                if (prescaled) {
-                    Y = X.add(Y, G);
+            hipGraphExec_t gexec = nullptr;
+            bool capture = false;
+            std::string key;
+            if (!X.dry && use_graph) {
+                char ptrs[96];
+                std::snprintf(ptrs, sizeof ptrs, "@%p/%p/%p", (void *)C->arena.base, (void *)C->pool.d_dv,
+                              (void *)C->pool.d_iv);
+                key = gkey + ptrs;
+                auto it = C->graphs.find(key);
+                if (it != C->graphs.end()) {
+                    gexec = it->second;
+                    X.quiet = true;
                 } else {
-                    std::vector<double> tau(total, temperature);
-                    Bt Gs = X.cmul(G, tau, Y.scale, false);
-                    Y = X.add(X.drop(Y, Gs.level), Gs);
+                    capture = true;
+                    HIPCHK(hipStreamBeginCapture(X.s, hipStreamCaptureModeRelaxed));
                 }
             }
-            Bt Z = cutmax_sched(X, Y, reqs, cf);
+            Bt Z;
+            try {
+                if (noise) {
+                    if (prescaled) {
+                        Y = X.add(Y, G);
+                    } else {
+                        std::vector<double> tau(total, temperature);
+                        Bt Gs = X.cmul(G, tau, Y.scale, false);
+                        Y = X.add(X.drop(Y, Gs.level), Gs);
+                    }
+                }
+                Z = cutmax_sched(X, Y, reqs, cf);
+            } catch (...) {
+                if (capture) {
+                    hipGraph_t g = nullptr;
+                    hipStreamEndCapture(X.s, &g);
+                    if (g) hipGraphDestroy(g);
+                }
+                throw;
+            }
+            if (capture) {
+                hipGraph_t g = nullptr;
+                HIPCHK(hipStreamEndCapture(X.s, &g));
+                HIPCHK(hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0));
+                hipGraphDestroy(g);
+                C->graphs[key] = gexec;
+            }
+            if (gexec) {
+                X.quiet = false;
+                HIPCHK(hipGraphLaunch(gexec, X.s));
+            }
             if (!X.dry) HIPCHK(hipEventRecord(e1, X.s));
             for (size_t r = 0; r < batch; ++r) store_bt(X, Z, reqs[r].first, outs[r]);
         });
@@ -1036,6 +1159,7 @@ int he_ctx_create(const he_params *prm, he_ctx **out) {
         HIPCHK(hipEventCreate(&C->ev0));
         HIPCHK(hipEventCreate(&C->ev1));
         build_ctx(C.get(), prm);
+        autotune_ntt(C.get());
         keygen(C.get());
         *out = C.release();
         return HE_OK;
@@ -1390,6 +1514,13 @@ int he_profile_end(he_ctx *C, char *buf, size_t cap) {
         std::memcpy(buf, js.c_str(), js.size() + 1);
         return HE_OK;
     });
+}
+
+int he_ntt_tuning(const he_ctx *C, int32_t *variants, uint32_t n) {
+    if (!C || !variants) { g_err = "null argument"; return HE_EINVAL; }
+    const int li = C->logN == 16 ? 1 : 0;
+    for (uint32_t i = 0; i < n && i < 8; ++i) variants[i] = g_tuned_choice[li][i];
+    return HE_OK;
 }
 
 int he_set_option(he_ctx *C, int option, int64_t value) {

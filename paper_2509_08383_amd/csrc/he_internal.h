@@ -54,8 +54,22 @@ extern KProf *g_kprof;
 void kprof_mark(const char *name, hipStream_t s, bool end);
 void kprof_set_bytes(double algorithmic_bytes);  // for the next launch
 
+#define KLN(name, kern, grid, block, shm, stream, ...)                   \
+    do {                                                                 \
+        if (g_kprof) kprof_mark(name, stream, false);                    \
+        hipLaunchKernelGGL(kern, grid, block, shm, stream, __VA_ARGS__); \
+        if (g_kprof) kprof_mark(name, stream, true);                     \
+    } while (0)
+
+// NTT workgroup-width tuning (ntt.hip): variant 1..3 per (log N, batch bucket)
+void set_ntt_tuning(int logN, int bucket, int variant);
+int ntt_bucket(int count);
+
 // ---------------------------------------------------------------- kernels.hip
-void launch_ntt(const DevTables &T, const VecSet &vs, bool inverse, int variant, hipStream_t s);
+// in place, or from *src into vs; the inverse multiplies by oscale[r] (per slot)
+// instead of N^-1 when oscale is given
+void launch_ntt(const DevTables &T, const VecSet &vs, bool inverse, int variant, hipStream_t s,
+                const VecSet *src = nullptr, const double *oscale = nullptr);
 void launch_add(const DevTables &T, const VecSet &out, const VecSet &a, const VecSet &b, int sign,
                 hipStream_t s);
 void launch_copy(const DevTables &T, const VecSet &out, const VecSet &a, hipStream_t s);
@@ -72,17 +86,19 @@ void launch_tensor(const DevTables &T, double *d0, double *d1, double *d2, long 
                    const int *bmap, long long apoly, long long bpoly, int cnt, int limbs, hipStream_t s);
 void launch_automorph(const DevTables &T, const VecSet &out, const VecSet &in, uint64_t galois,
                       hipStream_t s);
-void launch_modup(const DevTables &T, const double *dcoef, long long dstride, double *ext,
-                  long long estride, const double *dntt, long long nstride, int cnt, int level,
-                  int digit, int lo, int dl, int next, const int *ext_prime, const double *vinv,
-                  const double *qhat, hipStream_t s);
+struct ModUpDigits {
+    const double *qhat[8];  // [dl][next] per digit
+    int lo[8], dl[8];
+};
+void launch_modup(const DevTables &T, const double *v, long long vstride, double *ext, long long esb,
+                  long long esj, const double *dntt, long long nstride, int cnt, int beta, int next,
+                  const int *ext_prime, const ModUpDigits &dg, hipStream_t s);
 void launch_inner_product(const DevTables &T, const double *ext, long long estride_b,
                           long long estride_j, double *acc0, double *acc1, long long astride,
                           const double *key, long long kstride_j, long long kstride_c, int cnt,
                           int beta, int next, const int *ext_prime, hipStream_t s);
 void launch_moddown_conv(const DevTables &T, const double *acc, long long astride, double *conv,
-                         long long cstride, int cnt, int level, const double *phinv,
-                         const double *phat, hipStream_t s);
+                         long long cstride, int groups, int level, const double *phat, hipStream_t s);
 void launch_moddown_combine(const DevTables &T, double *out, long long ostride, const double *acc,
                             long long astride, const double *conv, long long cstride,
                             const double *add, long long add_ct, long long add_poly, int addmask,

@@ -54,175 +54,6 @@ DEV void vs_at(const VecSet &v, int idx, int N, double *&ptr, int &pr, int &g, i
 }
 DEV double ct_val(const ConstTab &k, int g, int r) { return k.base[(long long)(g / k.gdiv) * k.stride + r]; }
 
-// ------------------------------------------------------------------------ NTT
-// Negacyclic NTT in two passes of R = 2H radix-2 stages each, N = 2^(2R).
-// Forward stage s (m = 2^s, t = N/2m) maps (a_j, a_{j+t}) to
-// (a_j + w a_{j+t}, a_j - w a_{j+t}) with w = psi^bitrev(m + j/(2t)); the
-// output in position j is the evaluation at psi^(2 bitrev(j) + 1).
-// Pass 1 runs stages 0..R-1 on the strided sub-problems {r + SUB k}; pass 2
-// runs stages R..2R-1 on the contiguous blocks {b SUB + k}.  A workgroup
-// holds COLS sub-problems in LDS; each thread holds E = 2^H elements of one
-// sub-problem and runs H stages in registers (phase A: the high bits of k,
-// phase B: the low bits), with one LDS exchange in between.
-// The inverse runs the stages in reverse order with the Gentleman-Sande
-// butterfly (x, y) -> (x + y, (x - y) w^-1) and multiplies by N^-1 at the end.
-template <int H, bool PASS2, bool INV>
-__global__ __launch_bounds__(256) void k_ntt(VecSet vs, DevTables T) {
-    constexpr int R = 2 * H, E = 1 << H, TPS = 1 << H, SUB = 1 << R, COLS = 256 / TPS;
-    constexpr int NN = SUB * SUB;
-    __shared__ double tile[COLS * SUB];
-    auto lds = [](int c, int k) { return PASS2 ? c * SUB + k : k * COLS + c; };
-
-    double *ptr;
-    int pr, g_, r_;
-    vs_at(vs, blockIdx.y, NN, ptr, pr, g_, r_);
-    const double p = T.p[pr], pinv = T.pinv[pr];
-    const double *tw = (INV ? T.itw : T.tw) + (long long)pr * NN;
-    const int cb = blockIdx.x, tid = threadIdx.x;
-
-#pragma unroll
-    for (int i = 0; i < COLS * SUB / 256; ++i) {
-        int idx = tid + 256 * i, c, k;
-        if (PASS2) { k = idx % SUB; c = idx / SUB; } else { c = idx % COLS; k = idx / COLS; }
-        long long j = PASS2 ? (long long)(cb * COLS + c) * SUB + k : (long long)(cb * COLS + c) + (long long)SUB * k;
-        tile[lds(c, k)] = ptr[j];
-    }
-    __syncthreads();
-
-    int c, th;
-    if (PASS2) { th = tid % TPS; c = tid / TPS; } else { c = tid % COLS; th = tid / COLS; }
-    const int b = cb * COLS + c;
-    const int soff = PASS2 ? R : 0;
-    double v[E];
-
-    if (!INV) {
-        // phase A: high H bits of k
-#pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = tile[lds(c, th + TPS * e)];
-#pragma unroll
-        for (int sg = 0; sg < H; ++sg) {
-            const int s = sg + soff, hd = E >> (sg + 1);
-#pragma unroll
-            for (int g = 0; g < (1 << sg); ++g) {
-                const double w = tw[(1 << s) + (PASS2 ? (b << sg) : 0) + g];
-#pragma unroll
-                for (int i = 0; i < hd; ++i) {
-                    const int e0 = g * 2 * hd + i, e1 = e0 + hd;
-                    const double t = mm(v[e1], w, p, pinv);
-                    v[e1] = v[e0] - t;
-                    v[e0] = v[e0] + t;
-                }
-            }
-        }
-#pragma unroll
-        for (int e = 0; e < E; ++e) tile[lds(c, th + TPS * e)] = red(v[e], p, pinv);
-        __syncthreads();
-        // phase B: low H bits of k
-#pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = tile[lds(c, th * E + e)];
-#pragma unroll
-        for (int sg = 0; sg < H; ++sg) {
-            const int s = H + sg + soff, hd = E >> (sg + 1);
-#pragma unroll
-            for (int g = 0; g < (1 << sg); ++g) {
-                const double w = tw[(1 << s) + (PASS2 ? (b << (H + sg)) : 0) + (th << sg) + g];
-#pragma unroll
-                for (int i = 0; i < hd; ++i) {
-                    const int e0 = g * 2 * hd + i, e1 = e0 + hd;
-                    const double t = mm(v[e1], w, p, pinv);
-                    v[e1] = v[e0] - t;
-                    v[e0] = v[e0] + t;
-                }
-            }
-        }
-#pragma unroll
-        for (int e = 0; e < E; ++e) tile[lds(c, th * E + e)] = canon(v[e], p, pinv);
-        __syncthreads();
-    } else {
-        // phase B first (low bits), stages descending
-#pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = tile[lds(c, th * E + e)];
-#pragma unroll
-        for (int sg = H - 1; sg >= 0; --sg) {
-            const int s = H + sg + soff, hd = E >> (sg + 1);
-#pragma unroll
-            for (int g = 0; g < (1 << sg); ++g) {
-                const double w = tw[(1 << s) + (PASS2 ? (b << (H + sg)) : 0) + (th << sg) + g];
-#pragma unroll
-                for (int i = 0; i < hd; ++i) {
-                    const int e0 = g * 2 * hd + i, e1 = e0 + hd;
-                    const double x = v[e0], y = v[e1];
-                    v[e0] = red(x + y, p, pinv);
-                    v[e1] = mm(x - y, w, p, pinv);
-                }
-            }
-        }
-#pragma unroll
-        for (int e = 0; e < E; ++e) tile[lds(c, th * E + e)] = red(v[e], p, pinv);
-        __syncthreads();
-        // phase A (high bits), stages descending
-#pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = tile[lds(c, th + TPS * e)];
-#pragma unroll
-        for (int sg = H - 1; sg >= 0; --sg) {
-            const int s = sg + soff, hd = E >> (sg + 1);
-#pragma unroll
-            for (int g = 0; g < (1 << sg); ++g) {
-                const double w = tw[(1 << s) + (PASS2 ? (b << sg) : 0) + g];
-#pragma unroll
-                for (int i = 0; i < hd; ++i) {
-                    const int e0 = g * 2 * hd + i, e1 = e0 + hd;
-                    const double x = v[e0], y = v[e1];
-                    v[e0] = red(x + y, p, pinv);
-                    v[e1] = mm(x - y, w, p, pinv);
-                }
-            }
-        }
-        if (!PASS2) {
-            const double ni = T.ninv[pr];
-#pragma unroll
-            for (int e = 0; e < E; ++e) v[e] = mm(v[e], ni, p, pinv);
-        }
-#pragma unroll
-        for (int e = 0; e < E; ++e) tile[lds(c, th + TPS * e)] = canon(v[e], p, pinv);
-        __syncthreads();
-    }
-
-#pragma unroll
-    for (int i = 0; i < COLS * SUB / 256; ++i) {
-        int idx = tid + 256 * i, c2, k;
-        if (PASS2) { k = idx % SUB; c2 = idx / SUB; } else { c2 = idx % COLS; k = idx / COLS; }
-        long long j = PASS2 ? (long long)(cb * COLS + c2) * SUB + k : (long long)(cb * COLS + c2) + (long long)SUB * k;
-        ptr[j] = tile[lds(c2, k)];
-    }
-}
-
-template <int H>
-static void ntt_h(const DevTables &T, const VecSet &vs, bool inverse, hipStream_t s) {
-    constexpr int SUB = 1 << (2 * H), COLS = 256 / (1 << H);
-    dim3 grid(SUB / COLS, vs.count), block(256);
-    // each pass reads and writes every word once
-    const double bytes = 16.0 * SUB * SUB * vs.count;
-    if (!inverse) {
-        kprof_set_bytes(bytes);
-        KL("ntt_fwd_pass1", (k_ntt<H, false, false>), grid, block, 0, s, vs, T);
-        kprof_set_bytes(bytes);
-        KL("ntt_fwd_pass2", (k_ntt<H, true, false>), grid, block, 0, s, vs, T);
-    } else {
-        kprof_set_bytes(bytes);
-        KL("ntt_inv_pass2", (k_ntt<H, true, true>), grid, block, 0, s, vs, T);
-        kprof_set_bytes(bytes);
-        KL("ntt_inv_pass1", (k_ntt<H, false, true>), grid, block, 0, s, vs, T);
-    }
-}
-
-void launch_ntt(const DevTables &T, const VecSet &vs, bool inverse, int variant, hipStream_t s) {
-    (void)variant;
-    if (vs.count <= 0) return;
-    if (T.logN == 16) ntt_h<4>(T, vs, inverse, s);
-    else if (T.logN == 12) ntt_h<3>(T, vs, inverse, s);
-}
-
 // --------------------------------------------------------------- elementwise
 #define EW_PROLOGUE                                          \
     const int x = blockIdx.x * blockDim.x + threadIdx.x;     \
@@ -368,28 +199,38 @@ void launch_automorph(const DevTables &T, const VecSet &out, const VecSet &in, u
 }
 
 // ------------------------------------------------------------ key switching
-// ModUp of digit `digit` ([lo, lo+dl) of the primes present at `level`):
-// v_a = [d_{lo+a} * Qhat_a^-1]_{q_{lo+a}}; for every extended slot t outside
-// the digit: ext_t = sum_a v_a [Qhat_a]_{prime(t)}; digit slots copy the
-// NTT-domain input.  One thread per (ciphertext, coefficient).
-__global__ void k_modup(DevTables T, const double *dcoef, long long dstride, double *ext,
-                        long long estride, const double *dntt, long long nstride, int level, int lo,
-                        int dl, int next, const int *ext_prime, const double *vinv,
-                        const double *qhat) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+// ModUp of every digit j ([lo_j, lo_j+dl_j) of the primes present at the level):
+// v holds v_a = [d_{lo+a} * Qhat_a^-1]_{q_{lo+a}} in the coefficient domain (the
+// inverse NTT applied that scaling); for every extended slot t outside the digit
+// ext_j,t = sum_a v_a [Qhat_a]_{prime(t)}; digit slots copy the NTT-domain input.
+// Grid: x = blocks of MU_TB target slots (fastest, so the v words of one
+// coefficient block stay in L2 across target blocks), y = coefficient blocks,
+// z = (ciphertext, digit).
+constexpr int MU_TB = 8;
+__global__ void k_modup(DevTables T, const double *v, long long vstride, double *ext, long long esb,
+                        long long esj, const double *dntt, long long nstride, int beta, int next,
+                        const int *ext_prime, ModUpDigits dg) {
+    const int x = blockIdx.y * blockDim.x + threadIdx.x;
     if (x >= T.N) return;
-    const int ct = blockIdx.y;
-    const double *D = dcoef + ct * dstride;
-    double *X = ext + ct * estride;
-    double v[16];
-#pragma unroll
-    for (int a = 0; a < 16; ++a) {
-        if (a < dl) {
-            const int pi = lo + a;
-            v[a] = canon(mm(D[(long long)pi * T.N + x], vinv[a], T.p[pi], T.pinv[pi]), T.p[pi], T.pinv[pi]);
-        }
+    const int ct = blockIdx.z / beta, j = blockIdx.z % beta;
+    const int lo = dg.lo[j], dl = dg.dl[j];
+    const double *qh = dg.qhat[j];
+    double *X = ext + ct * esb + j * esj;
+    const int t0 = blockIdx.x * MU_TB;
+    bool need = false;
+    for (int tt = 0; tt < MU_TB; ++tt) {
+        const int t = t0 + tt;
+        if (t < next && !(t >= lo && t < lo + dl)) need = true;
     }
-    for (int t = 0; t < next; ++t) {
+    double va[16];
+    if (need) {
+#pragma unroll
+        for (int a = 0; a < 16; ++a)
+            if (a < dl) va[a] = v[ct * vstride + (long long)(lo + a) * T.N + x];
+    }
+    for (int tt = 0; tt < MU_TB; ++tt) {
+        const int t = t0 + tt;
+        if (t >= next) break;
         if (t >= lo && t < lo + dl) {
             X[(long long)t * T.N + x] = dntt[ct * nstride + (long long)t * T.N + x];
             continue;
@@ -399,19 +240,17 @@ __global__ void k_modup(DevTables T, const double *dcoef, long long dstride, dou
         double acc = 0.0;
 #pragma unroll
         for (int a = 0; a < 16; ++a)
-            if (a < dl) acc += mm(v[a], qhat[a * next + t], p, pinv);
+            if (a < dl) acc += mm(va[a], qh[a * next + t], p, pinv);
         X[(long long)t * T.N + x] = canon(acc, p, pinv);
     }
 }
-void launch_modup(const DevTables &T, const double *dcoef, long long dstride, double *ext,
-                  long long estride, const double *dntt, long long nstride, int cnt, int level,
-                  int digit, int lo, int dl, int next, const int *ext_prime, const double *vinv,
-                  const double *qhat, hipStream_t s) {
-    (void)digit;
+void launch_modup(const DevTables &T, const double *v, long long vstride, double *ext, long long esb,
+                  long long esj, const double *dntt, long long nstride, int cnt, int beta, int next,
+                  const int *ext_prime, const ModUpDigits &dg, hipStream_t s) {
     if (cnt <= 0) return;
-    kprof_set_bytes(8.0 * T.N * cnt * (2 * dl + next));  // digit in (coef + NTT copy), all limbs out
-    KL("k_modup", k_modup, dim3((T.N + 255) / 256, cnt), dim3(256), 0, s, T, dcoef, dstride,
-                       ext, estride, dntt, nstride, level, lo, dl, next, ext_prime, vinv, qhat);
+    kprof_set_bytes(8.0 * T.N * cnt * beta * (next + 2.0 * next / beta));  // digits in, every slot out
+    KL("k_modup", k_modup, dim3((next + MU_TB - 1) / MU_TB, (T.N + 255) / 256, cnt * beta), dim3(256), 0, s,
+       T, v, vstride, ext, esb, esj, dntt, nstride, beta, next, ext_prime, dg);
 }
 
 // acc_c[ct][t] = sum_j ext[ct][j][t] * key[j][c][prime(t)]; the key words are
@@ -458,28 +297,31 @@ void launch_inner_product(const DevTables &T, const double *ext, long long estri
                        beta, ext_prime);
 }
 
-// ModDown conversion: w_m = centred [acc_{P,m} * Phat_m^-1]_{p_m};
-// conv_i = sum_m w_m [Phat_m]_{q_i} for i <= level (coefficient domain).
-// acc holds [cnt*2] groups of (level+1+alpha) limbs; conv [cnt*2][level+1].
+// ModDown conversion: the P slots of acc hold w_m = [acc_{P,m} * Phat_m^-1]_{p_m}
+// (coefficient domain, scaled by the inverse NTT); each is lifted to its centred
+// representative and conv_i = sum_m w_m [Phat_m]_{q_i} for i <= level.
+// acc holds groups of (level+1+alpha) limbs at astride; conv [groups][level+1].
+// Grid: x = blocks of MU_TB target primes, y = coefficient blocks, z = group.
 __global__ void k_moddown_conv(DevTables T, const double *acc, long long astride, double *conv,
-                               long long cstride, int level, const double *phinv,
-                               const double *phat) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+                               long long cstride, int level, const double *phat) {
+    const int x = blockIdx.y * blockDim.x + threadIdx.x;
     if (x >= T.N) return;
-    const int gi = blockIdx.y;
+    const int gi = blockIdx.z;
     const int A = T.alpha;
     const double *Ac = acc + gi * astride;
     double w[16];
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
         if (m < A) {
-            const int pm = T.L + 1 + m;
-            const double p = T.p[pm], pinv = T.pinv[pm];
-            double v = canon(mm(Ac[(long long)(level + 1 + m) * T.N + x], phinv[m], p, pinv), p, pinv);
+            const double p = T.p[T.L + 1 + m];
+            const double v = Ac[(long long)(level + 1 + m) * T.N + x];
             w[m] = v > 0.5 * (p - 1.0) ? v - p : v;
         }
     }
-    for (int i = 0; i <= level; ++i) {
+    const int i0 = blockIdx.x * MU_TB;
+    for (int ii = 0; ii < MU_TB; ++ii) {
+        const int i = i0 + ii;
+        if (i > level) break;
         const double p = T.p[i], pinv = T.pinv[i];
         double s = 0.0;
 #pragma unroll
@@ -489,12 +331,11 @@ __global__ void k_moddown_conv(DevTables T, const double *acc, long long astride
     }
 }
 void launch_moddown_conv(const DevTables &T, const double *acc, long long astride, double *conv,
-                         long long cstride, int cnt, int level, const double *phinv,
-                         const double *phat, hipStream_t s) {
-    if (cnt <= 0) return;
-    kprof_set_bytes(8.0 * T.N * cnt * (T.alpha + level + 1));
-    KL("k_moddown_conv", k_moddown_conv, dim3((T.N + 255) / 256, cnt), dim3(256), 0, s, T, acc,
-                       astride, conv, cstride, level, phinv, phat);
+                         long long cstride, int groups, int level, const double *phat, hipStream_t s) {
+    if (groups <= 0) return;
+    kprof_set_bytes(8.0 * T.N * groups * (T.alpha + level + 1));
+    KL("k_moddown_conv", k_moddown_conv, dim3((level + 1 + MU_TB - 1) / MU_TB, (T.N + 255) / 256, groups),
+       dim3(256), 0, s, T, acc, astride, conv, cstride, level, phat);
 }
 
 // out_i = (acc_i - conv_i) * P^-1 (+ add_i when bit (group & 1) of addmask is set)

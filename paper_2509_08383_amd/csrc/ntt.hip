@@ -1,0 +1,247 @@
+// Batched negacyclic NTT / inverse NTT over RNS limbs for gfx950, with an autotuned
+// workgroup width.
+//
+// Forward stage s (m = 2^s, t = N/2m) maps (a_j, a_{j+t}) to
+// (a_j + w a_{j+t}, a_j - w a_{j+t}) with w = psi^bitrev(m + j/(2t)) (Cooley-Tukey,
+// twiddles merged with the negacyclic twist); output position j holds the evaluation
+// at psi^(2 bitrev(j) + 1).  The inverse runs the stages in reverse order with the
+// Gentleman-Sande butterfly (x, y) -> (x + y, (x - y) w^-1) and multiplies by N^-1
+// (or a caller-supplied per-slot constant that includes N^-1) at the end.
+//
+// N = 2^(2R) is split into two passes of R = 2H stages: pass 1 runs stages 0..R-1
+// on the strided sub-problems {r + SUB k}, pass 2 runs stages R..2R-1 on the
+// contiguous blocks {b SUB + k} (SUB = 2^R).  A workgroup holds COLS sub-problems;
+// each thread holds E = 2^H words of one sub-problem and runs H stages in registers
+// on the high bits of k (phase A) and H stages on the low bits (phase B), exchanging
+// through LDS once in between.  Global accesses are made directly from registers
+// where the layout is coalesced (phase A side in both passes, phase B side in
+// pass 1); pass 2's phase B side goes through LDS.  The LDS tile is skewed so that
+// both phases are free of bank conflicts: pass 1 word (c, k) at (k + k/E) COLS + c,
+// pass 2 at c (SUB + SUB/E) + k + k/E.
+//
+// Value bounds: canonical inputs; H lazy CT stages grow |x| below 5p < 2^52, then a
+// reduction; GS stages reduce the sum every stage; outputs canonical in [0, p).
+#include "he_internal.h"
+
+namespace he {
+
+#define DEV __device__ __forceinline__
+
+DEV double nmm(double a, double b, double p, double pinv) {
+    double h = a * b;
+    double l = __builtin_fma(a, b, -h);
+    double k = __builtin_rint(h * pinv);
+    double r = __builtin_fma(-k, p, h);
+    return r + l;
+}
+DEV double nred(double x, double p, double pinv) { return __builtin_fma(-__builtin_rint(x * pinv), p, x); }
+DEV double ncanon(double x, double p, double pinv) {
+    double r = nred(x, p, pinv);
+    return r < 0.0 ? r + p : r;
+}
+
+DEV void nvs_at(const VecSet &v, int idx, int N, double *&ptr, int &pr, int &r) {
+    const int g = idx / v.group;
+    r = idx - g * v.group;
+    const int sl = v.slot ? v.slot[r] : r;
+    pr = v.prime ? v.prime[r] : r;
+    ptr = v.base + (long long)g * v.gstride + (long long)sl * N;
+}
+
+template <int H, int COLS, bool PASS2, bool INV>
+__global__ __launch_bounds__(COLS *(1 << H)) void k_ntt(VecSet vs, VecSet src, const double *oscale,
+                                                        DevTables T) {
+    constexpr int R = 2 * H, E = 1 << H, TPS = 1 << H, SUB = 1 << R, NT = COLS * TPS;
+    constexpr int NN = SUB * SUB, S2 = SUB + SUB / E;
+    __shared__ double tile[COLS * S2];
+    auto lds = [](int c, int k) { return PASS2 ? c * S2 + k + (k >> H) : (k + (k >> H)) * COLS + c; };
+
+    double *ptr;
+    int pr, r_;
+    nvs_at(vs, blockIdx.y, NN, ptr, pr, r_);
+    const double *iptr = ptr;
+    if (src.base) {
+        double *sp;
+        int a1, a2;
+        nvs_at(src, blockIdx.y, NN, sp, a1, a2);
+        iptr = sp;
+    }
+    const double p = T.p[pr], pinv = T.pinv[pr];
+    const double *tw = (INV ? T.itw : T.tw) + (long long)pr * NN;
+    const int cb = blockIdx.x, tid = threadIdx.x;
+    int c, th;
+    if (PASS2) { th = tid % TPS; c = tid / TPS; } else { c = tid % COLS; th = tid / COLS; }
+    const int b = cb * COLS + c;
+    auto gidx = [cb](int cc, int k) -> long long {
+        return PASS2 ? (long long)(cb * COLS + cc) * SUB + k : (long long)(cb * COLS + cc) + (long long)SUB * k;
+    };
+    constexpr int soff = PASS2 ? R : 0;
+    double v[E];
+
+    if (!INV) {
+        // phase A (high bits of k), loaded straight from global memory
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = iptr[gidx(c, th + TPS * e)];
+#pragma unroll
+        for (int sg = 0; sg < H; ++sg) {
+            const int s = sg + soff, hd = E >> (sg + 1);
+#pragma unroll
+            for (int g = 0; g < (1 << sg); ++g) {
+                const double w = tw[(1 << s) + (PASS2 ? (b << sg) : 0) + g];
+#pragma unroll
+                for (int i = 0; i < hd; ++i) {
+                    const int e0 = g * 2 * hd + i, e1 = e0 + hd;
+                    const double t = nmm(v[e1], w, p, pinv);
+                    v[e1] = v[e0] - t;
+                    v[e0] = v[e0] + t;
+                }
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) tile[lds(c, th + TPS * e)] = nred(v[e], p, pinv);
+        __syncthreads();
+        // phase B (low bits of k)
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = tile[lds(c, th * E + e)];
+#pragma unroll
+        for (int sg = 0; sg < H; ++sg) {
+            const int s = H + sg + soff, hd = E >> (sg + 1);
+#pragma unroll
+            for (int g = 0; g < (1 << sg); ++g) {
+                const double w = tw[(1 << s) + (PASS2 ? (b << (H + sg)) : 0) + (th << sg) + g];
+#pragma unroll
+                for (int i = 0; i < hd; ++i) {
+                    const int e0 = g * 2 * hd + i, e1 = e0 + hd;
+                    const double t = nmm(v[e1], w, p, pinv);
+                    v[e1] = v[e0] - t;
+                    v[e0] = v[e0] + t;
+                }
+            }
+        }
+        if (!PASS2) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) ptr[gidx(c, th * E + e)] = ncanon(v[e], p, pinv);
+        } else {
+#pragma unroll
+            for (int e = 0; e < E; ++e) tile[lds(c, th * E + e)] = ncanon(v[e], p, pinv);
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < SUB / TPS; ++i) {
+                const int idx = tid + NT * i, k = idx % SUB, cc = idx / SUB;
+                ptr[gidx(cc, k)] = tile[lds(cc, k)];
+            }
+        }
+    } else {
+        // phase B first (low bits), stages descending
+        if (PASS2) {
+#pragma unroll
+            for (int i = 0; i < SUB / TPS; ++i) {
+                const int idx = tid + NT * i, k = idx % SUB, cc = idx / SUB;
+                tile[lds(cc, k)] = iptr[gidx(cc, k)];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[e] = tile[lds(c, th * E + e)];
+        } else {
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[e] = iptr[gidx(c, th * E + e)];
+        }
+#pragma unroll
+        for (int sg = H - 1; sg >= 0; --sg) {
+            const int s = H + sg + soff, hd = E >> (sg + 1);
+#pragma unroll
+            for (int g = 0; g < (1 << sg); ++g) {
+                const double w = tw[(1 << s) + (PASS2 ? (b << (H + sg)) : 0) + (th << sg) + g];
+#pragma unroll
+                for (int i = 0; i < hd; ++i) {
+                    const int e0 = g * 2 * hd + i, e1 = e0 + hd;
+                    const double x = v[e0], y = v[e1];
+                    v[e0] = nred(x + y, p, pinv);
+                    v[e1] = nmm(x - y, w, p, pinv);
+                }
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) tile[lds(c, th * E + e)] = nred(v[e], p, pinv);
+        __syncthreads();
+        // phase A (high bits), stages descending, stored straight to global memory
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = tile[lds(c, th + TPS * e)];
+#pragma unroll
+        for (int sg = H - 1; sg >= 0; --sg) {
+            const int s = sg + soff, hd = E >> (sg + 1);
+#pragma unroll
+            for (int g = 0; g < (1 << sg); ++g) {
+                const double w = tw[(1 << s) + (PASS2 ? (b << sg) : 0) + g];
+#pragma unroll
+                for (int i = 0; i < hd; ++i) {
+                    const int e0 = g * 2 * hd + i, e1 = e0 + hd;
+                    const double x = v[e0], y = v[e1];
+                    v[e0] = nred(x + y, p, pinv);
+                    v[e1] = nmm(x - y, w, p, pinv);
+                }
+            }
+        }
+        if (!PASS2) {
+            const double ni = oscale ? oscale[r_] : T.ninv[pr];
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[e] = nmm(v[e], ni, p, pinv);
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) ptr[gidx(c, th + TPS * e)] = ncanon(v[e], p, pinv);
+    }
+}
+
+// tuned workgroup width per (log N, batch bucket); 0 = not tuned (use the default)
+static int g_ntt_tune[2][8];
+
+static int bucket_of(int count) {
+    int b = 0;
+    while (b < 7 && (16 << (2 * b)) < count) ++b;  // <=16, <=64, <=256, <=1024, ...
+    return b;
+}
+
+void set_ntt_tuning(int logN, int bucket, int variant) {
+    if (bucket >= 0 && bucket < 8) g_ntt_tune[logN == 16 ? 1 : 0][bucket] = variant;
+}
+int ntt_bucket(int count) { return bucket_of(count); }
+
+template <int H, int COLS>
+static void ntt_run(const DevTables &T, const VecSet &vs, const VecSet *src, bool inverse, const double *oscale,
+                    hipStream_t s) {
+    constexpr int SUB = 1 << (2 * H), NT = COLS * (1 << H);
+    dim3 grid(SUB / COLS, vs.count), block(NT);
+    const VecSet none{nullptr, 0, 1, 0, nullptr, nullptr};
+    const VecSet first = src ? *src : none;
+    const double bytes = 16.0 * SUB * SUB * vs.count;  // each pass reads and writes every word once
+    if (!inverse) {
+        kprof_set_bytes(bytes);
+        KLN("ntt_fwd_pass1", (k_ntt<H, COLS, false, false>), grid, block, 0, s, vs, first, nullptr, T);
+        kprof_set_bytes(bytes);
+        KLN("ntt_fwd_pass2", (k_ntt<H, COLS, true, false>), grid, block, 0, s, vs, none, nullptr, T);
+    } else {
+        kprof_set_bytes(bytes);
+        KLN("ntt_inv_pass2", (k_ntt<H, COLS, true, true>), grid, block, 0, s, vs, first, nullptr, T);
+        kprof_set_bytes(bytes);
+        KLN("ntt_inv_pass1", (k_ntt<H, COLS, false, true>), grid, block, 0, s, vs, none, oscale, T);
+    }
+}
+
+void launch_ntt(const DevTables &T, const VecSet &vs, bool inverse, int variant, hipStream_t s,
+                const VecSet *src, const double *oscale) {
+    if (vs.count <= 0) return;
+    int v = variant;
+    if (v <= 0) v = g_ntt_tune[T.logN == 16 ? 1 : 0][bucket_of(vs.count)];
+    if (v <= 0 || v > 3) v = 3;
+    if (T.logN == 16) {
+        if (v == 1) ntt_run<4, 4>(T, vs, src, inverse, oscale, s);
+        else if (v == 2) ntt_run<4, 8>(T, vs, src, inverse, oscale, s);
+        else ntt_run<4, 16>(T, vs, src, inverse, oscale, s);
+    } else if (T.logN == 12) {
+        if (v == 1) ntt_run<3, 8>(T, vs, src, inverse, oscale, s);
+        else if (v == 2) ntt_run<3, 16>(T, vs, src, inverse, oscale, s);
+        else ntt_run<3, 32>(T, vs, src, inverse, oscale, s);
+    }
+}
+
+}  // namespace he

@@ -86,6 +86,7 @@ def lib():
             "he_last_cutmax_ms": [_V, _c_dp],
             "he_sync": [_V],
             "he_set_option": [_V, ctypes.c_int, ctypes.c_int64],
+            "he_ntt_tuning": [_V, ctypes.POINTER(ctypes.c_int32), ctypes.c_uint32],
             "he_profile_begin": [_V],
             "he_profile_end": [_V, ctypes.c_char_p, ctypes.c_size_t],
         }
@@ -337,6 +338,11 @@ class Context:
 
     def set_option(self, opt: int, value: int):
         _check(lib().he_set_option(self.h, opt, int(value)))
+
+    def ntt_tuning(self):
+        v = (ctypes.c_int32 * 8)()
+        _check(lib().he_ntt_tuning(self.h, v, 8))
+        return list(v)
 
     def profile_begin(self):
         _check(lib().he_profile_begin(self.h))

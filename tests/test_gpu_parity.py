@@ -143,6 +143,21 @@ def test_rotate_and_mul_low_levels_bit_exact(toy):
         toy.same(toy.G.mul(gd, toy.G.drop(gy, lv)), toy.O.mul(od, toy.O.drop(oy, lv)), f"mul@{lv}")
 
 
+@pytest.mark.parametrize("variant", [1, 2, 3])
+def test_ntt_variants_bit_exact(toy, variant):
+    """every NTT workgroup-width variant the autotuner can pick gives the same ciphertexts"""
+    from paper_2509_08383_amd import he
+    say(f"[gpu] ntt variant {variant}")
+    gx, ox, gy, oy = _pairs_of_ops(toy)
+    toy.G.set_option(he.HE_OPT_NTT_VARIANT, variant)
+    try:
+        toy.same(toy.G.mul(gx, gy), toy.O.mul(ox, oy), f"mul v{variant}")
+        toy.same(toy.G.rotate(gx, 4), toy.O.rotate(ox, 4), f"rotate v{variant}")
+    finally:
+        toy.G.set_option(he.HE_OPT_NTT_VARIANT, 0)
+    assert all(1 <= v <= 3 for v in toy.G.ntt_tuning())
+
+
 def test_rotsum_bit_exact(toy):
     gx, ox, _, _ = _pairs_of_ops(toy)
     toy.same(toy.G.rotsum(gx), toy.O.rotsum(ox), "rotsum")
@@ -203,6 +218,29 @@ def test_cutmax_toy_batch_mixed_counts(toy):
                        sum_lo=1.0 * y.size)
         assert np.abs(dz - cutmax_mirror(y, mc)).max() < 1e-3
         assert int(np.argmax(dz[:x.size])) == int(np.argmax(x))
+
+
+def test_cutmax_graph_replays_match_eager(toy):
+    """HIP-graph mode: the first call captures, later calls replay; every replay (with eager
+    work in between) equals the eager result bit for bit."""
+    from paper_2509_08383_amd import he
+    say("[gpu] graph capture/replay")
+    x = toy_logits(51)
+    ct = toy.G.encrypt(x)
+    toy.O.nonce = toy.O.nonce + 1
+    p, c, vlo, vhi, coef = toy_cfg(2048)
+    cfg = he.CutmaxCfg(T=4, p=p, c=c, var_lo=vlo, var_hi=vhi, init_coef=coef, sum_lo=1.0, sum_hi=3.0)
+    ref = toy.G.export(toy.G.cutmax([ct], cfg)[0])
+    toy.G.set_option(he.HE_OPT_GRAPH, 1)
+    try:
+        for i in range(4):
+            z = toy.G.export(toy.G.cutmax([ct], cfg)[0])
+            assert np.array_equal(z, ref), f"graph call {i} differs"
+            other = toy.G.encrypt(toy_logits(60 + i))       # eager work between replays
+            toy.O.nonce = toy.O.nonce + 1
+            toy.G.mul(other, other)
+    finally:
+        toy.G.set_option(he.HE_OPT_GRAPH, 0)
 
 
 def test_cutmax_errors_are_reported(toy):
