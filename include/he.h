@@ -204,6 +204,39 @@ int he_set_option(he_ctx *ctx, int option, int64_t value);
  * buckets of <=16, <=64, <=256, <=1024, ... vectors (n entries, at most 8). */
 int he_ntt_tuning(const he_ctx *ctx, int32_t *variants, uint32_t n);
 
+/* ---------------------------------------------------------------------------
+ * Learned initial guess for the inverse square root of Alg. 2 line 5 (an
+ * addition to the paper's method).  A 1 -> 16 -> 16 -> 1 network with square
+ * activations, z = (u - mean)/sd, h1 = W1 z + b1, a1 = h1^2, h2 = W2 a1 + b2,
+ * a2 = h2^2, y = W3 . a2 + b3, trained in FP32 on the GPU to minimise the mean
+ * of (y sqrt(u) - 1)^2; y is a degree-4 polynomial of u, which he_mlp_to_poly
+ * returns for he_cutmax_cfg.init_coef (init_degree = 4).
+ * Parameter vector (321 floats): W1[16], b1[16], W2[16][16] (row = output),
+ * b2[16], W3[16], b3.  All array arguments are host memory.  Errors of these
+ * calls are reported by he_mlp_last_error(). */
+typedef struct he_mlp he_mlp;
+int he_mlp_create(uint64_t seed, int device, he_mlp **out);
+void he_mlp_destroy(he_mlp *mlp);
+int he_mlp_set_params(he_mlp *mlp, const float *theta, size_t n, float mean, float sd);
+int he_mlp_get_params(const he_mlp *mlp, float *theta, size_t n, float *mean, float *sd);
+/* one forward + backward pass over u[m]: mean loss and its gradient (theta order) */
+int he_mlp_grad(he_mlp *mlp, const float *u, size_t m, float *loss, float *grad);
+int he_mlp_forward(he_mlp *mlp, const float *u, size_t m, float *y);
+/* Adam over shuffled mini-batches of u[m] (input normalisation maps [min u, max u] to [-1, 1]),
+ * cosine-decayed step size from lr; *final_loss = loss over u afterwards */
+int he_mlp_train(he_mlp *mlp, const float *u, size_t m, uint32_t epochs, uint32_t batch, float lr,
+                 uint64_t seed, float *final_loss);
+/* coef[0..4]: power-basis coefficients of y(u) */
+int he_mlp_to_poly(const he_mlp *mlp, double *coef);
+/* Training data: plaintext CutMax (Alg. 1) runs on the GPU over synthetic
+ * LLM-like logits (vocab tokens zero-padded to `slots`, per-run Gumbel scale
+ * ~U[1.5,4.5] and Zipf exponent ~U[0.9,1.3]); var_out[runs][T] receives the
+ * population variance entering each iteration, ymean_out[runs] (nullable) the
+ * mean of the last iterate. */
+int he_variance_log(uint64_t seed, uint32_t runs, uint32_t vocab, uint32_t slots, uint32_t T,
+                    uint32_t p, double c, int device, float *var_out, float *ymean_out);
+const char *he_mlp_last_error(void);
+
 #ifdef __cplusplus
 }
 #endif

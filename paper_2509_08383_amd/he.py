@@ -354,6 +354,106 @@ class Context:
         return {k: (v[0], v[1], v[2]) for k, v in json.loads(buf.value.decode()).items()}
 
 
+_c_fp = ctypes.POINTER(ctypes.c_float)
+MLP_NPARAM = 321
+
+
+def _mlp_lib():
+    L = lib()
+    if not getattr(L, "_mlp_ready", False):
+        sig = {
+            "he_mlp_create": [ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(_V)],
+            "he_mlp_set_params": [_V, _c_fp, ctypes.c_size_t, ctypes.c_float, ctypes.c_float],
+            "he_mlp_get_params": [_V, _c_fp, ctypes.c_size_t, _c_fp, _c_fp],
+            "he_mlp_grad": [_V, _c_fp, ctypes.c_size_t, _c_fp, _c_fp],
+            "he_mlp_forward": [_V, _c_fp, ctypes.c_size_t, _c_fp],
+            "he_mlp_train": [_V, _c_fp, ctypes.c_size_t, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_float,
+                             ctypes.c_uint64, _c_fp],
+            "he_mlp_to_poly": [_V, _c_dp],
+            "he_variance_log": [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                ctypes.c_uint32, ctypes.c_uint32, ctypes.c_double, ctypes.c_int, _c_fp, _c_fp],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        L.he_mlp_destroy.argtypes = [_V]
+        L.he_mlp_destroy.restype = None
+        L.he_mlp_last_error.restype = ctypes.c_char_p
+        L._mlp_ready = True
+    return L
+
+
+def _mcheck(rc: int):
+    if rc != HE_OK:
+        raise HeError(rc, _mlp_lib().he_mlp_last_error().decode())
+
+
+def _fp(a):
+    return a.ctypes.data_as(_c_fp)
+
+
+class InvSqrtMLP:
+    """The learned initial guess (he_mlp): FP32 training on the GPU, collapse to a quartic."""
+
+    def __init__(self, seed: int = 0, device: int = 0):
+        h = _V()
+        _mcheck(_mlp_lib().he_mlp_create(seed, device, ctypes.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                _mlp_lib().he_mlp_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def set_params(self, theta, mean: float, sd: float):
+        t = np.ascontiguousarray(theta, dtype=np.float32)
+        _mcheck(_mlp_lib().he_mlp_set_params(self.h, _fp(t), t.size, mean, sd))
+
+    def get_params(self):
+        t = np.empty(MLP_NPARAM, dtype=np.float32)
+        m, s = ctypes.c_float(), ctypes.c_float()
+        _mcheck(_mlp_lib().he_mlp_get_params(self.h, _fp(t), t.size, ctypes.byref(m), ctypes.byref(s)))
+        return t, m.value, s.value
+
+    def grad(self, u):
+        u = np.ascontiguousarray(u, dtype=np.float32)
+        g = np.empty(MLP_NPARAM, dtype=np.float32)
+        loss = ctypes.c_float()
+        _mcheck(_mlp_lib().he_mlp_grad(self.h, _fp(u), u.size, ctypes.byref(loss), _fp(g)))
+        return loss.value, g
+
+    def forward(self, u):
+        u = np.ascontiguousarray(u, dtype=np.float32)
+        y = np.empty_like(u)
+        _mcheck(_mlp_lib().he_mlp_forward(self.h, _fp(u), u.size, _fp(y)))
+        return y
+
+    def train(self, u, epochs: int = 20, batch: int = 1024, lr: float = 1e-2, seed: int = 0) -> float:
+        u = np.ascontiguousarray(u, dtype=np.float32)
+        loss = ctypes.c_float()
+        _mcheck(_mlp_lib().he_mlp_train(self.h, _fp(u), u.size, epochs, batch, lr, seed, ctypes.byref(loss)))
+        return loss.value
+
+    def to_poly(self) -> np.ndarray:
+        c = np.empty(5, dtype=np.float64)
+        _mcheck(_mlp_lib().he_mlp_to_poly(self.h, _dp(c)))
+        return c
+
+
+def variance_log(seed: int, runs: int, vocab: int = 32000, slots: int = 32768, T: int = 3, p: int = 3,
+                 c: float = 5.0, device: int = 0):
+    """Variances entering each iteration of `runs` plaintext CutMax runs (GPU), and the
+    mean of the last iterate."""
+    v = np.empty((runs, T), dtype=np.float32)
+    ym = np.empty(runs, dtype=np.float32)
+    _mcheck(_mlp_lib().he_variance_log(seed, runs, vocab, slots, T, p, c, device, _fp(v), _fp(ym)))
+    return v, ym
+
+
 def topp_noise(top_p: float, u: np.ndarray) -> np.ndarray:
     """Client helper: G = U^(1/alpha), alpha = ln(1-p)/ln p (Alg. 3 lines 1-4)."""
     u = np.ascontiguousarray(u, dtype=np.float64)
