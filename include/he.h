@@ -181,6 +181,10 @@ int he_drop(he_ctx *ctx, const he_ct *a, uint32_t level, he_ct **out);
  * he_last_cutmax_ms: device time of the last he_cutmax/he_topp_sample call.
  * he_sync: wait for the context stream. */
 int he_bench_ntt(he_ctx *ctx, uint32_t vectors, uint32_t iters, double *ms_fwd, double *ms_inv);
+/* he_bench_copy: the library's element-wise copy kernel over `vectors` limb
+ *   vectors (N words read and N written each), average device time per launch;
+ *   the achievable-bandwidth reference and the calibration of byte counters. */
+int he_bench_copy(he_ctx *ctx, uint32_t vectors, uint32_t iters, double *ms);
 int he_last_cutmax_ms(const he_ctx *ctx, double *ms);
 int he_sync(he_ctx *ctx);
 

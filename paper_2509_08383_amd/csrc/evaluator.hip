@@ -138,6 +138,8 @@ struct he_ctx {
     std::vector<std::vector<const double *>> vinv, qhat;  // [L+1][beta_l]
     std::vector<std::vector<const int *>> ndslot, ndprime;
     std::vector<std::vector<int>> ndcount;
+    std::vector<int> ndall;                              // [L+1]: converted limbs over all digits
+    std::vector<const int *> ndall_slot, ndall_prime;    // [L+1] -> [ndall]: j*next + t, prime(t)
     const double *phinv = nullptr, *phat = nullptr, *Pinv = nullptr, *qlinv = nullptr, *pmod = nullptr;
     std::vector<const double *> mu_scale;  // [L+1] -> [l+1]: N^-1 Qhat_i^-1 mod q_i at level l
     const double *md_scale = nullptr;      // [alpha]: N^-1 Phat_m^-1 mod p_m
@@ -169,6 +171,14 @@ struct Bt {
     double *d = nullptr;
     int cnt = 0, level = 0, cap = 0;
     std::vector<double> scale;  // per ciphertext
+};
+
+// an addend of the key-switch output: word (ct, poly, limb, j) at
+// p + ct * ct_stride + poly * poly_stride + limb N + j, on the polys in mask
+struct Addend {
+    const double *p;
+    long long ct, poly;
+    int mask;
 };
 
 struct Exec {
@@ -280,7 +290,8 @@ struct Exec {
 
     // ------------------------------------------------------------- rescale
     // (K a - [K a_l]_centred) / q_l per limb; kres (per ct, limbs 0..l) = K mod q_i, or
-    // null for a plain rescale
+    // null for a plain rescale.  The lift of the last limb to the other primes is
+    // computed while loading the forward NTT, and the combine happens on its store.
     Bt rescale(const Bt &a, const double *kres = nullptr) {
         const int l = a.level;
         REQUIRE(l >= 1, HE_EDEPTH, "rescale at level 0");
@@ -288,21 +299,29 @@ struct Exec {
         for (int c = 0; c < a.cnt; ++c) o.scale[c] = a.scale[c] / (double)C->q[l];
         const size_t m = C->arena.mark();
         const int G = a.cnt * 2;
-        double *last = alloc_d((size_t)G * C->N);
-        double *lift = alloc_d((size_t)G * l * C->N);
+        const long long N = C->N;
+        double *last = alloc_d((size_t)G * N);
+        double *lift = alloc_d((size_t)G * l * N);
         if (go()) {
-            VecSet src{a.d + (long long)l * C->N, G, 1, (long long)a.cap * C->N, nullptr, C->ident + l};
-            VecSet dst{last, G, 1, (long long)C->N, nullptr, C->ident + l};
+            VecSet src{a.d + (long long)l * N, G, 1, (long long)a.cap * N, nullptr, C->ident + l};
+            VecSet dst{last, G, 1, N, nullptr, C->ident + l};
             if (kres) {
                 launch_mul_const(T, dst, src, ConstTab{kres + l, 2, l + 1}, s);
                 launch_ntt(T, dst, true, C->ntt_variant, s);
             } else {
                 launch_ntt(T, dst, true, C->ntt_variant, s, &src);
             }
-            launch_rescale_lift(T, last, C->N, lift, (long long)l * C->N, G, l, s);
-            launch_ntt(T, VecSet{lift, G * l, l, (long long)l * C->N, nullptr, nullptr}, false, C->ntt_variant, s);
-            launch_rescale_combine(T, o.d, (long long)o.cap * C->N, a.d, (long long)a.cap * C->N, lift,
-                                   (long long)l * C->N, G, l, C->qlinv + (long long)l * (C->L + 1), kres, s);
+            NttPro pro{1, last, N, (double)C->q[l]};
+            NttEpi epi{};
+            epi.kind = 2;
+            epi.out = o.d;
+            epi.o_g = (long long)o.cap * N;
+            epi.in = a.d;
+            epi.i_g = (long long)a.cap * N;
+            epi.cst = C->qlinv + (long long)l * (C->L + 1);
+            epi.kmul = kres;
+            epi.kstride = l + 1;
+            launch_ntt_fused(T, VecSet{lift, G * l, l, (long long)l * N, nullptr, nullptr}, pro, epi, C->ntt_variant, s);
         }
         C->arena.release(m);
         return o;
@@ -310,10 +329,9 @@ struct Exec {
 
     // ------------------------------------------------------------ key switch
     // d: NTT-domain polynomials [cnt] at `dstride` words apart, limbs 0..l.
-    // out (groups ct*2 + poly at ostride) = ModDown(sum_j ModUp_j(d) key_j)
-    // plus `add` on the polys selected by addmask.
-    void keyswitch(const double *d, long long dstride, int cnt, int l, int kidx, double *out,
-                   long long ostride, const double *add, long long add_ct, long long add_poly, int addmask) {
+    // out (groups ct*2 + poly at ostride) = ModDown(sum_j ModUp_j(d) key_j) + a1 + a2.
+    void keyswitch(const double *d, long long dstride, int cnt, int l, int kidx, double *out, long long ostride,
+                   Addend a1 = Addend{nullptr, 0, 0, 0}, Addend a2 = Addend{nullptr, 0, 0, 0}) {
         const int A = C->alpha, next = l + 1 + A, beta = (l + 1 + A - 1) / A;
         const long long N = C->N;
         const size_t m = C->arena.mark();
@@ -334,11 +352,10 @@ struct Exec {
             }
             launch_modup(T, dcoef, (long long)(l + 1) * N, ext, (long long)beta * next * N, (long long)next * N, d,
                          dstride, cnt, beta, next, C->ext_prime[l], dg, s);
-            for (int j = 0; j < beta; ++j) {
-                const int nd = C->ndcount[l][j];
-                launch_ntt(T, VecSet{ext + (long long)j * next * N, cnt * nd, nd, (long long)beta * next * N,
-                                     C->ndslot[l][j], C->ndprime[l][j]}, false, C->ntt_variant, s);
-            }
+            // every digit's converted limbs in one transform
+            const int nd = C->ndall[l];
+            launch_ntt(T, VecSet{ext, cnt * nd, nd, (long long)beta * next * N, C->ndall_slot[l], C->ndall_prime[l]},
+                       false, C->ntt_variant, s);
             launch_inner_product(T, ext, (long long)beta * next * N, (long long)next * N, acc, acc + (long long)next * N,
                                  2LL * next * N, C->keys[kidx], 2LL * C->np * N, (long long)C->np * N, cnt, beta,
                                  next, C->ext_prime[l], s);
@@ -346,10 +363,18 @@ struct Exec {
             launch_ntt(T, VecSet{acc + (long long)(l + 1) * N, cnt * 2 * A, A, (long long)next * N, nullptr, C->pprime},
                        true, C->ntt_variant, s, nullptr, C->md_scale);
             launch_moddown_conv(T, acc, (long long)next * N, conv, (long long)(l + 1) * N, cnt * 2, l, C->phat, s);
-            launch_ntt(T, VecSet{conv, cnt * 2 * (l + 1), l + 1, (long long)(l + 1) * N, nullptr, nullptr}, false,
-                       C->ntt_variant, s);
-            launch_moddown_combine(T, out, ostride, acc, (long long)next * N, conv, (long long)(l + 1) * N, add,
-                                   add_ct, add_poly, addmask, cnt * 2, l, C->Pinv, s);
+            // transform the conversion and combine on store: (acc - conv) P^-1 + addends
+            NttEpi epi{};
+            epi.kind = 1;
+            epi.out = out;
+            epi.o_g = ostride;
+            epi.in = acc;
+            epi.i_g = (long long)next * N;
+            epi.add1 = a1.p; epi.a1_ct = a1.ct; epi.a1_poly = a1.poly; epi.m1 = a1.mask;
+            epi.add2 = a2.p; epi.a2_ct = a2.ct; epi.a2_poly = a2.poly; epi.m2 = a2.mask;
+            epi.cst = C->Pinv;
+            launch_ntt_fused(T, VecSet{conv, cnt * 2 * (l + 1), l + 1, (long long)(l + 1) * N, nullptr, nullptr},
+                             NttPro{}, epi, C->ntt_variant, s);
         }
         C->arena.release(m);
     }
@@ -369,8 +394,8 @@ struct Exec {
             launch_tensor(T, t, t + (l + 1) * N, t + 2 * (l + 1) * N, 3LL * (l + 1) * N, a.d, b.d,
                           2LL * a.cap * N, 2LL * b.cap * N, dmap, (long long)a.cap * N, (long long)b.cap * N,
                           a.cnt, l + 1, s);
-        keyswitch(t + 2 * (l + 1) * N, 3LL * (l + 1) * N, a.cnt, l, 0, r.d, (long long)r.cap * N, t,
-                  3LL * (l + 1) * N, (long long)(l + 1) * N, 3);
+        keyswitch(t + 2 * (l + 1) * N, 3LL * (l + 1) * N, a.cnt, l, 0, r.d, (long long)r.cap * N,
+                  Addend{t, 3LL * (l + 1) * N, (long long)(l + 1) * N, 3});
         C->arena.release(m);
         // r's scale here is s_a*s_b; the rescale divides by q_l
         Bt o = rescale(r);
@@ -396,11 +421,17 @@ struct Exec {
         return o;
     }
 
-    Bt rotate(const Bt &a, int r) {
+    // rotation by 2^r slots; with `into`, the result is added into that batch in place
+    Bt rotate(const Bt &a, int r, Bt *into = nullptr) {
         const int l = a.level;
         const long long N = C->N;
-        Bt o = new_bt(a.cnt, l);
-        o.scale = a.scale;
+        Bt o;
+        if (into) {
+            o = *into;
+        } else {
+            o = new_bt(a.cnt, l);
+            o.scale = a.scale;
+        }
         const size_t m = C->arena.mark();
         double *sig = alloc_d((size_t)a.cnt * 2 * (l + 1) * N);
         uint64_t g = 5;
@@ -408,8 +439,10 @@ struct Exec {
         if (go())
             launch_automorph(T, VecSet{sig, a.cnt * 2 * (l + 1), l + 1, (long long)(l + 1) * N, nullptr, nullptr},
                              vs_all(a), g, s);
-        keyswitch(sig + (l + 1) * N, 2LL * (l + 1) * N, a.cnt, l, 1 + r, o.d, (long long)o.cap * N, sig,
-                  2LL * (l + 1) * N, (long long)(l + 1) * N, 1);
+        Addend acc{nullptr, 0, 0, 0};
+        if (into) acc = Addend{into->d, 2LL * into->cap * N, (long long)into->cap * N, 3};
+        keyswitch(sig + (l + 1) * N, 2LL * (l + 1) * N, a.cnt, l, 1 + r, o.d, (long long)o.cap * N,
+                  Addend{sig, 2LL * (l + 1) * N, (long long)(l + 1) * N, 1}, acc);
         C->arena.release(m);
         return o;
     }
@@ -421,8 +454,7 @@ struct Exec {
         while ((1 << lg) < C->slots) ++lg;
         for (int r = 0; r < lg; ++r) {
             const size_t m = C->arena.mark();
-            Bt t = rotate(o, r);
-            add_inplace(o, t);
+            rotate(o, r, &o);
             C->arena.release(m);
         }
         return o;
@@ -752,7 +784,8 @@ void build_ctx(he_ctx *C, const he_params *prm) {
         for (int i = 0; i < l; ++i) qlinv[(size_t)l * (L + 1) + i] = (double)invmod_u(q[l] % q[i], q[i]);
     const size_t o_qlinv = tb.d(qlinv);
     // ModUp per level and digit
-    std::vector<size_t> o_ext(L + 1), o_mus(L + 1);
+    std::vector<size_t> o_ext(L + 1), o_mus(L + 1), o_nas(L + 1), o_nap(L + 1);
+    C->ndall.assign(L + 1, 0);
     std::vector<std::vector<size_t>> o_vinv(L + 1), o_qhat(L + 1), o_nds(L + 1), o_ndp(L + 1);
     C->ndcount.assign(L + 1, {});
     for (int l = 0; l <= L; ++l) {
@@ -787,6 +820,15 @@ void build_ctx(he_ctx *C, const he_params *prm) {
             o_ndp[l].push_back(tb.i(npr));
         }
         o_mus[l] = tb.d(mus);
+        std::vector<int> as, ap;
+        for (int j = 0; j < beta; ++j) {
+            const int lo = j * A, dl = std::min(A, l + 1 - lo);
+            for (int t = 0; t < next; ++t)
+                if (!(t >= lo && t < lo + dl)) { as.push_back(j * next + t); ap.push_back(ep[t]); }
+        }
+        C->ndall[l] = (int)as.size();
+        o_nas[l] = tb.i(as);
+        o_nap[l] = tb.i(ap);
     }
     HIPCHK(hipMalloc(&C->d_tab, tb.dv.size() * 8));
     HIPCHK(hipMalloc(&C->d_itab, tb.iv.size() * 4));
@@ -802,6 +844,12 @@ void build_ctx(he_ctx *C, const he_params *prm) {
     C->md_scale = D + o_mds;
     C->mu_scale.resize(L + 1);
     for (int l = 0; l <= L; ++l) C->mu_scale[l] = D + o_mus[l];
+    C->ndall_slot.resize(L + 1);
+    C->ndall_prime.resize(L + 1);
+    for (int l = 0; l <= L; ++l) {
+        C->ndall_slot[l] = I + o_nas[l];
+        C->ndall_prime[l] = I + o_nap[l];
+    }
     C->ext_prime.resize(L + 1);
     C->vinv.assign(L + 1, {}); C->qhat.assign(L + 1, {}); C->ndslot.assign(L + 1, {}); C->ndprime.assign(L + 1, {});
     for (int l = 0; l <= L; ++l) {
@@ -1454,6 +1502,35 @@ int he_bench_ntt(he_ctx *C, uint32_t vectors, uint32_t iters, double *ms_fwd, do
         hipFree(buf);
         *ms_fwd = tf / iters;
         *ms_inv = ti / iters;
+        return HE_OK;
+    });
+}
+
+int he_bench_copy(he_ctx *C, uint32_t vectors, uint32_t iters, double *ms) {
+    return guarded([&]() {
+        REQUIRE(C && vectors >= 1 && iters >= 1 && ms, HE_EINVAL, "bad argument");
+        HIPCHK(hipSetDevice(C->device));
+        const int N = C->N;
+        double *buf = nullptr;
+        HIPCHK(hipMalloc(&buf, 16ull * vectors * N));
+        hipEvent_t a, b;
+        HIPCHK(hipEventCreate(&a));
+        HIPCHK(hipEventCreate(&b));
+        const int grp = std::min<int>((int)vectors, C->L + 1);
+        const VecSet src{buf, (int)vectors, grp, (long long)grp * N, nullptr, nullptr};
+        const VecSet dst{buf + (size_t)vectors * N, (int)vectors, grp, (long long)grp * N, nullptr, nullptr};
+        launch_sample_uniform(C->T, src, 777, 0x7D000000u, nullptr, C->stream);
+        launch_copy(C->T, dst, src, C->stream);
+        HIPCHK(hipEventRecord(a, C->stream));
+        for (uint32_t it = 0; it < iters; ++it) launch_copy(C->T, dst, src, C->stream);
+        HIPCHK(hipEventRecord(b, C->stream));
+        HIPCHK(hipEventSynchronize(b));
+        float f = 0;
+        HIPCHK(hipEventElapsedTime(&f, a, b));
+        hipEventDestroy(a);
+        hipEventDestroy(b);
+        hipFree(buf);
+        *ms = f / iters;
         return HE_OK;
     });
 }

@@ -70,6 +70,38 @@ int ntt_bucket(int count);
 // instead of N^-1 when oscale is given
 void launch_ntt(const DevTables &T, const VecSet &vs, bool inverse, int variant, hipStream_t s,
                 const VecSet *src = nullptr, const double *oscale = nullptr);
+
+// Forward-NTT prologue: kind 1 loads, for vector (g, r), the centred lift of the
+// coefficient-domain word last[g * l_g + j] (modulo ql) reduced modulo prime(r).
+struct NttPro {
+    int kind;
+    const double *last;
+    long long l_g;
+    double ql;
+};
+// Forward-NTT epilogue on the transformed word w of vector (g, r), position j:
+//   kind 1 (ModDown): out = (in - w) * cst[r] + [m1] add1 + [m2] add2
+//   kind 2 (rescale): out = (K in - w) * cst[r], K = kmul[(g >> 1) * kstride + r] or 1
+// with in = in[g * i_g + r N + j], out[g * o_g + r N + j], addk[(g>>1) ak_ct +
+// (g&1) ak_poly + r N + j] applied when bit (g & 1) of mk is set.
+struct NttEpi {
+    int kind;
+    double *out;
+    long long o_g;
+    const double *in;
+    long long i_g;
+    const double *add1;
+    long long a1_ct, a1_poly;
+    int m1;
+    const double *add2;
+    long long a2_ct, a2_poly;
+    int m2;
+    const double *cst;
+    const double *kmul;
+    int kstride;
+};
+void launch_ntt_fused(const DevTables &T, const VecSet &vs, const NttPro &pro, const NttEpi &epi, int variant,
+                      hipStream_t s);
 void launch_add(const DevTables &T, const VecSet &out, const VecSet &a, const VecSet &b, int sign,
                 hipStream_t s);
 void launch_copy(const DevTables &T, const VecSet &out, const VecSet &a, hipStream_t s);

@@ -40,32 +40,35 @@ DEV double ncanon(double x, double p, double pinv) {
     return r < 0.0 ? r + p : r;
 }
 
-DEV void nvs_at(const VecSet &v, int idx, int N, double *&ptr, int &pr, int &r) {
-    const int g = idx / v.group;
+DEV void nvs_at(const VecSet &v, int idx, int N, double *&ptr, int &pr, int &r, int &g) {
+    g = idx / v.group;
     r = idx - g * v.group;
     const int sl = v.slot ? v.slot[r] : r;
     pr = v.prime ? v.prime[r] : r;
     ptr = v.base + (long long)g * v.gstride + (long long)sl * N;
 }
 
-template <int H, int COLS, bool PASS2, bool INV>
+// PRO / EPI: fused prologue (forward pass 1 loads) and epilogue (forward pass 2
+// stores), see NttPro / NttEpi
+template <int H, int COLS, bool PASS2, bool INV, int PRO, int EPI>
 __global__ __launch_bounds__(COLS *(1 << H)) void k_ntt(VecSet vs, VecSet src, const double *oscale,
-                                                        DevTables T) {
+                                                        DevTables T, NttPro pro, NttEpi epi) {
     constexpr int R = 2 * H, E = 1 << H, TPS = 1 << H, SUB = 1 << R, NT = COLS * TPS;
     constexpr int NN = SUB * SUB, S2 = SUB + SUB / E;
     __shared__ double tile[COLS * S2];
     auto lds = [](int c, int k) { return PASS2 ? c * S2 + k + (k >> H) : (k + (k >> H)) * COLS + c; };
 
     double *ptr;
-    int pr, r_;
-    nvs_at(vs, blockIdx.y, NN, ptr, pr, r_);
+    int pr, r_, g_;
+    nvs_at(vs, blockIdx.y, NN, ptr, pr, r_, g_);
     const double *iptr = ptr;
     if (src.base) {
         double *sp;
-        int a1, a2;
-        nvs_at(src, blockIdx.y, NN, sp, a1, a2);
+        int a1, a2, a3;
+        nvs_at(src, blockIdx.y, NN, sp, a1, a2, a3);
         iptr = sp;
     }
+    if (PRO == 1) iptr = pro.last + (long long)g_ * pro.l_g;
     const double p = T.p[pr], pinv = T.pinv[pr];
     const double *tw = (INV ? T.itw : T.tw) + (long long)pr * NN;
     const int cb = blockIdx.x, tid = threadIdx.x;
@@ -80,8 +83,18 @@ __global__ __launch_bounds__(COLS *(1 << H)) void k_ntt(VecSet vs, VecSet src, c
 
     if (!INV) {
         // phase A (high bits of k), loaded straight from global memory
+        if (PRO == 1) {
+            const double hq = 0.5 * (pro.ql - 1.0);
 #pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = iptr[gidx(c, th + TPS * e)];
+            for (int e = 0; e < E; ++e) {
+                double x = iptr[gidx(c, th + TPS * e)];
+                x = x > hq ? x - pro.ql : x;
+                v[e] = ncanon(x, p, pinv);
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[e] = iptr[gidx(c, th + TPS * e)];
+        }
 #pragma unroll
         for (int sg = 0; sg < H; ++sg) {
             const int s = sg + soff, hd = E >> (sg + 1);
@@ -125,10 +138,36 @@ __global__ __launch_bounds__(COLS *(1 << H)) void k_ntt(VecSet vs, VecSet src, c
 #pragma unroll
             for (int e = 0; e < E; ++e) tile[lds(c, th * E + e)] = ncanon(v[e], p, pinv);
             __syncthreads();
+            if (EPI == 0) {
 #pragma unroll
-            for (int i = 0; i < SUB / TPS; ++i) {
-                const int idx = tid + NT * i, k = idx % SUB, cc = idx / SUB;
-                ptr[gidx(cc, k)] = tile[lds(cc, k)];
+                for (int i = 0; i < SUB / TPS; ++i) {
+                    const int idx = tid + NT * i, k = idx % SUB, cc = idx / SUB;
+                    ptr[gidx(cc, k)] = tile[lds(cc, k)];
+                }
+            } else {
+                const long long rN = (long long)r_ * NN;
+                const double cst = epi.cst[r_];
+                const double *in = epi.in + (long long)g_ * epi.i_g + rN;
+                double *out = epi.out + (long long)g_ * epi.o_g + rN;
+                const bool use1 = epi.add1 && ((epi.m1 >> (g_ & 1)) & 1);
+                const bool use2 = epi.add2 && ((epi.m2 >> (g_ & 1)) & 1);
+                const double *ad1 = use1 ? epi.add1 + (long long)(g_ >> 1) * epi.a1_ct + (g_ & 1) * epi.a1_poly + rN : nullptr;
+                const double *ad2 = use2 ? epi.add2 + (long long)(g_ >> 1) * epi.a2_ct + (g_ & 1) * epi.a2_poly + rN : nullptr;
+                const double km = (EPI == 2 && epi.kmul) ? epi.kmul[(long long)(g_ >> 1) * epi.kstride + r_] : 1.0;
+#pragma unroll
+                for (int i = 0; i < SUB / TPS; ++i) {
+                    const int idx = tid + NT * i, k = idx % SUB, cc = idx / SUB;
+                    const long long j = gidx(cc, k);
+                    const double w = tile[lds(cc, k)];
+                    double x = in[j];
+                    if (EPI == 2 && epi.kmul) x = nmm(x, km, p, pinv);
+                    double o = nmm(x - w, cst, p, pinv);
+                    if (EPI == 1) {
+                        if (use1) o += ad1[j];
+                        if (use2) o += ad2[j];
+                    }
+                    out[j] = ncanon(o, p, pinv);
+                }
             }
         }
     } else {
@@ -206,9 +245,9 @@ void set_ntt_tuning(int logN, int bucket, int variant) {
 }
 int ntt_bucket(int count) { return bucket_of(count); }
 
-template <int H, int COLS>
+template <int H, int COLS, int PRO, int EPI>
 static void ntt_run(const DevTables &T, const VecSet &vs, const VecSet *src, bool inverse, const double *oscale,
-                    hipStream_t s) {
+                    const NttPro &pro, const NttEpi &epi, hipStream_t s) {
     constexpr int SUB = 1 << (2 * H), NT = COLS * (1 << H);
     dim3 grid(SUB / COLS, vs.count), block(NT);
     const VecSet none{nullptr, 0, 1, 0, nullptr, nullptr};
@@ -216,32 +255,53 @@ static void ntt_run(const DevTables &T, const VecSet &vs, const VecSet *src, boo
     const double bytes = 16.0 * SUB * SUB * vs.count;  // each pass reads and writes every word once
     if (!inverse) {
         kprof_set_bytes(bytes);
-        KLN("ntt_fwd_pass1", (k_ntt<H, COLS, false, false>), grid, block, 0, s, vs, first, nullptr, T);
-        kprof_set_bytes(bytes);
-        KLN("ntt_fwd_pass2", (k_ntt<H, COLS, true, false>), grid, block, 0, s, vs, none, nullptr, T);
+        KLN(PRO ? "ntt_fwd_pass1_lift" : "ntt_fwd_pass1", (k_ntt<H, COLS, false, false, PRO, 0>), grid, block, 0, s,
+            vs, first, nullptr, T, pro, epi);
+        // a fused epilogue also reads `in` (and the addends) and writes `out`
+        kprof_set_bytes(EPI ? bytes * (EPI == 1 ? 1.5 + 0.5 * ((epi.add1 != nullptr) + (epi.add2 != nullptr)) : 1.5)
+                            : bytes);
+        KLN(EPI == 1 ? "ntt_fwd_pass2_moddown" : (EPI == 2 ? "ntt_fwd_pass2_rescale" : "ntt_fwd_pass2"),
+            (k_ntt<H, COLS, true, false, 0, EPI>), grid, block, 0, s, vs, none, nullptr, T, pro, epi);
     } else {
         kprof_set_bytes(bytes);
-        KLN("ntt_inv_pass2", (k_ntt<H, COLS, true, true>), grid, block, 0, s, vs, first, nullptr, T);
+        KLN("ntt_inv_pass2", (k_ntt<H, COLS, true, true, 0, 0>), grid, block, 0, s, vs, first, nullptr, T, pro, epi);
         kprof_set_bytes(bytes);
-        KLN("ntt_inv_pass1", (k_ntt<H, COLS, false, true>), grid, block, 0, s, vs, none, oscale, T);
+        KLN("ntt_inv_pass1", (k_ntt<H, COLS, false, true, 0, 0>), grid, block, 0, s, vs, none, oscale, T, pro, epi);
     }
 }
 
-void launch_ntt(const DevTables &T, const VecSet &vs, bool inverse, int variant, hipStream_t s,
-                const VecSet *src, const double *oscale) {
+template <int PRO, int EPI>
+static void ntt_dispatch(const DevTables &T, const VecSet &vs, bool inverse, int variant, hipStream_t s,
+                         const VecSet *src, const double *oscale, const NttPro &pro, const NttEpi &epi) {
     if (vs.count <= 0) return;
     int v = variant;
     if (v <= 0) v = g_ntt_tune[T.logN == 16 ? 1 : 0][bucket_of(vs.count)];
     if (v <= 0 || v > 3) v = 3;
     if (T.logN == 16) {
-        if (v == 1) ntt_run<4, 4>(T, vs, src, inverse, oscale, s);
-        else if (v == 2) ntt_run<4, 8>(T, vs, src, inverse, oscale, s);
-        else ntt_run<4, 16>(T, vs, src, inverse, oscale, s);
+        if (v == 1) ntt_run<4, 4, PRO, EPI>(T, vs, src, inverse, oscale, pro, epi, s);
+        else if (v == 2) ntt_run<4, 8, PRO, EPI>(T, vs, src, inverse, oscale, pro, epi, s);
+        else ntt_run<4, 16, PRO, EPI>(T, vs, src, inverse, oscale, pro, epi, s);
     } else if (T.logN == 12) {
-        if (v == 1) ntt_run<3, 8>(T, vs, src, inverse, oscale, s);
-        else if (v == 2) ntt_run<3, 16>(T, vs, src, inverse, oscale, s);
-        else ntt_run<3, 32>(T, vs, src, inverse, oscale, s);
+        if (v == 1) ntt_run<3, 8, PRO, EPI>(T, vs, src, inverse, oscale, pro, epi, s);
+        else if (v == 2) ntt_run<3, 16, PRO, EPI>(T, vs, src, inverse, oscale, pro, epi, s);
+        else ntt_run<3, 32, PRO, EPI>(T, vs, src, inverse, oscale, pro, epi, s);
     }
+}
+
+void launch_ntt(const DevTables &T, const VecSet &vs, bool inverse, int variant, hipStream_t s,
+                const VecSet *src, const double *oscale) {
+    const NttPro pro{};
+    const NttEpi epi{};
+    ntt_dispatch<0, 0>(T, vs, inverse, variant, s, src, oscale, pro, epi);
+}
+
+void launch_ntt_fused(const DevTables &T, const VecSet &vs, const NttPro &pro, const NttEpi &epi, int variant,
+                      hipStream_t s) {
+    if (pro.kind == 1 && epi.kind == 2) ntt_dispatch<1, 2>(T, vs, false, variant, s, nullptr, nullptr, pro, epi);
+    else if (pro.kind == 0 && epi.kind == 1) ntt_dispatch<0, 1>(T, vs, false, variant, s, nullptr, nullptr, pro, epi);
+    else if (pro.kind == 1 && epi.kind == 0) ntt_dispatch<1, 0>(T, vs, false, variant, s, nullptr, nullptr, pro, epi);
+    else if (pro.kind == 0 && epi.kind == 2) ntt_dispatch<0, 2>(T, vs, false, variant, s, nullptr, nullptr, pro, epi);
+    else ntt_dispatch<0, 0>(T, vs, false, variant, s, nullptr, nullptr, pro, epi);
 }
 
 }  // namespace he

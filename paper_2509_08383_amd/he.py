@@ -83,6 +83,7 @@ def lib():
             "he_rotsum": [_V, _V, ctypes.POINTER(_V)],
             "he_drop": [_V, _V, ctypes.c_uint32, ctypes.POINTER(_V)],
             "he_bench_ntt": [_V, ctypes.c_uint32, ctypes.c_uint32, _c_dp, _c_dp],
+            "he_bench_copy": [_V, ctypes.c_uint32, ctypes.c_uint32, _c_dp],
             "he_last_cutmax_ms": [_V, _c_dp],
             "he_sync": [_V],
             "he_set_option": [_V, ctypes.c_int, ctypes.c_int64],
@@ -327,6 +328,11 @@ class Context:
         f, i = ctypes.c_double(), ctypes.c_double()
         _check(lib().he_bench_ntt(self.h, vectors, iters, ctypes.byref(f), ctypes.byref(i)))
         return f.value, i.value
+
+    def bench_copy(self, vectors: int, iters: int) -> float:
+        v = ctypes.c_double()
+        _check(lib().he_bench_copy(self.h, vectors, iters, ctypes.byref(v)))
+        return v.value
 
     def last_cutmax_ms(self) -> float:
         v = ctypes.c_double()
