@@ -148,7 +148,14 @@ def main():
                              "inv_GBps": alg / (i * 1e-3) / 1e9}
     log(f"[bench] ntt {ntt}")
 
-    # --- batched argmaxes/s (config 3)
+    # --- plain copy of 64 limb vectors (32 MiB read + 32 MiB written per launch): the
+    # achievable-bandwidth reference, and the known-size kernel that calibrates byte counters
+    cms = ctx.bench_copy(64, 10)
+    copy = {"vectors": 64, "bytes_per_launch": 2 * 64 * ctx.N * 8, "ms": cms,
+            "GBps": 2 * 64 * ctx.N * 8 / (cms * 1e-3) / 1e9}
+    log(f"[bench] copy {copy}")
+
+    # --- batched argmaxes/s (16 mixed-vocabulary requests)
     batch = None
     if not args.no_batch:
         xs = [llm_logits(200 + r, 32000 if r % 2 == 0 else 128256) for r in range(16)]
@@ -208,13 +215,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "config 2: encrypted CutMax, N=2^16 RNS-CKKS 128-bit (30x Q, dnum=3), "
+        "config": {"workload": "encrypted CutMax, N=2^16 RNS-CKKS 128-bit (30x Q, dnum=3), "
                                "one ciphertext of 32000 LLM-like logits in 32768 slots, T=3, p=3, c=5",
                    "global_batch": 1, "seq_len": VOCAB2, "parallelism": "none"},
         "device_ms_median": float(np.median(dev_ms)),
         "argmax_ok": bool(argmax_ok),
         "batched": batch,
         "ntt": ntt,
+        "copy": copy,
         "ntt_tuning": ctx.ntt_tuning(),
         "roofline": roof,
         "kernels": {k: {"launches": v[0], "ms": v[1], "bytes": v[2]} for k, v in kern.items()},

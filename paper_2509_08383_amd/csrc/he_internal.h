@@ -131,15 +131,6 @@ void launch_inner_product(const DevTables &T, const double *ext, long long estri
                           int beta, int next, const int *ext_prime, hipStream_t s);
 void launch_moddown_conv(const DevTables &T, const double *acc, long long astride, double *conv,
                          long long cstride, int groups, int level, const double *phat, hipStream_t s);
-void launch_moddown_combine(const DevTables &T, double *out, long long ostride, const double *acc,
-                            long long astride, const double *conv, long long cstride,
-                            const double *add, long long add_ct, long long add_poly, int addmask,
-                            int groups, int level, const double *Pinv, hipStream_t s);
-void launch_rescale_lift(const DevTables &T, const double *lastc, long long lstride, double *lift,
-                         long long fstride, int cnt, int level, hipStream_t s);
-void launch_rescale_combine(const DevTables &T, double *out, long long ostride, const double *in,
-                            long long istride, const double *lift, long long fstride, int cnt,
-                            int level, const double *qlinv, const double *kmul, hipStream_t s);
 void launch_sample_uniform(const DevTables &T, const VecSet &out, uint64_t seed, uint32_t obj,
                            const int *gprime, hipStream_t s);
 void launch_sample_small(int *out, int N, uint64_t seed, uint32_t obj, int kind, hipStream_t s);

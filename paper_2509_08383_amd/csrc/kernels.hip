@@ -203,54 +203,95 @@ void launch_automorph(const DevTables &T, const VecSet &out, const VecSet &in, u
 // v holds v_a = [d_{lo+a} * Qhat_a^-1]_{q_{lo+a}} in the coefficient domain (the
 // inverse NTT applied that scaling); for every extended slot t outside the digit
 // ext_j,t = sum_a v_a [Qhat_a]_{prime(t)}; digit slots copy the NTT-domain input.
-// Grid: x = blocks of MU_TB target slots (fastest, so the v words of one
-// coefficient block stay in L2 across target blocks), y = coefficient blocks,
-// z = (ciphertext, digit).
-constexpr int MU_TB = 8;
-__global__ void k_modup(DevTables T, const double *v, long long vstride, double *ext, long long esb,
-                        long long esj, const double *dntt, long long nstride, int beta, int next,
-                        const int *ext_prime, ModUpDigits dg) {
-    const int x = blockIdx.y * blockDim.x + threadIdx.x;
-    if (x >= T.N) return;
-    const int ct = blockIdx.z / beta, j = blockIdx.z % beta;
+// Grid: x = blocks of TB target slots (fastest, so the v words of one coefficient
+// block stay in L2 across target blocks), y = coefficient blocks, z = (ciphertext,
+// digit).  The block's [Qhat_a]_{prime(t)} table and moduli are staged in LDS (every
+// lane reads the same word: a broadcast); terms a >= dl and own-digit targets carry
+// zero constants, so the DL products of a target run without branches as independent
+// chains.  |sum| <= DL (p/2 + 2^44) < 2^52 for DL <= 16.
+template <int DL, int TB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_modup(DevTables T, const double *__restrict__ v, long long vstride,
+                                               double *__restrict__ ext, long long esb, long long esj,
+                                               const double *__restrict__ dntt, long long nstride, int beta,
+                                               int next, const int *__restrict__ ext_prime, ModUpDigits dg) {
+    __shared__ double sq[DL * TB];
+    __shared__ double sp[TB], si[TB];
+    const int ct = blockIdx.z / beta, j = blockIdx.z - (blockIdx.z / beta) * beta;
     const int lo = dg.lo[j], dl = dg.dl[j];
-    const double *qh = dg.qhat[j];
-    double *X = ext + ct * esb + j * esj;
-    const int t0 = blockIdx.x * MU_TB;
+    const int t0 = blockIdx.x * TB, tid = threadIdx.x;
+    {
+        const double *qh = dg.qhat[j];
+        for (int i = tid; i < DL * TB; i += blockDim.x) {
+            const int a = i / TB, t = t0 + (i - (i / TB) * TB);
+            const bool own = t >= lo && t < lo + dl;
+            sq[i] = (a < dl && t < next && !own) ? qh[a * next + t] : 0.0;
+        }
+        if (tid < TB) {
+            const int pt = ext_prime[t0 + tid < next ? t0 + tid : 0];
+            sp[tid] = T.p[pt];
+            si[tid] = T.pinv[pt];
+        }
+    }
+    __syncthreads();
+    const int x = blockIdx.y * blockDim.x + tid;
+    if (x >= T.N) return;
     bool need = false;
-    for (int tt = 0; tt < MU_TB; ++tt) {
-        const int t = t0 + tt;
-        if (t < next && !(t >= lo && t < lo + dl)) need = true;
-    }
-    double va[16];
-    if (need) {
 #pragma unroll
-        for (int a = 0; a < 16; ++a)
-            if (a < dl) va[a] = v[ct * vstride + (long long)(lo + a) * T.N + x];
+    for (int tt = 0; tt < TB; ++tt) {
+        const int t = t0 + tt;
+        need |= t < next && !(t >= lo && t < lo + dl);
     }
-    for (int tt = 0; tt < MU_TB; ++tt) {
+    double va[DL];
+    const double *vp = v + ct * vstride + (long long)lo * T.N + x;
+#pragma unroll
+    for (int a = 0; a < DL; ++a) va[a] = (need && a < dl) ? vp[(long long)a * T.N] : 0.0;
+    double *X = ext + ct * esb + j * esj + x;
+#pragma unroll
+    for (int tt = 0; tt < TB; ++tt) {
         const int t = t0 + tt;
         if (t >= next) break;
-        if (t >= lo && t < lo + dl) {
-            X[(long long)t * T.N + x] = dntt[ct * nstride + (long long)t * T.N + x];
-            continue;
-        }
-        const int pt = ext_prime[t];
-        const double p = T.p[pt], pinv = T.pinv[pt];
+        const double p = sp[tt], pinv = si[tt];
         double acc = 0.0;
 #pragma unroll
-        for (int a = 0; a < 16; ++a)
-            if (a < dl) acc += mm(va[a], qh[a * next + t], p, pinv);
-        X[(long long)t * T.N + x] = canon(acc, p, pinv);
+        for (int a = 0; a < DL; ++a) acc += mm(va[a], sq[a * TB + tt], p, pinv);
+        if (t >= lo && t < lo + dl) X[(long long)t * T.N] = dntt[ct * nstride + (long long)t * T.N + x];
+        else X[(long long)t * T.N] = canon(acc, p, pinv);
     }
 }
+
+// smallest compiled digit length that holds dl words
+static int digit_len(int dl) { return dl <= 4 ? 4 : dl <= 8 ? 8 : dl <= 10 ? 10 : dl <= 12 ? 12 : 16; }
+
+template <int TB>
+static void modup_tb(int DL, dim3 grid, hipStream_t s, const DevTables &T, const double *v, long long vstride,
+                     double *ext, long long esb, long long esj, const double *dntt, long long nstride, int beta,
+                     int next, const int *ext_prime, const ModUpDigits &dg) {
+#define MU_CASE(D)                                                                                          \
+    case D:                                                                                                 \
+        KL("k_modup", (k_modup<D, TB>), grid, dim3(256), 0, s, T, v, vstride, ext, esb, esj, dntt, nstride, \
+           beta, next, ext_prime, dg);                                                                      \
+        break;
+    switch (DL) { MU_CASE(4) MU_CASE(8) MU_CASE(10) MU_CASE(12) MU_CASE(16) }
+#undef MU_CASE
+}
+
 void launch_modup(const DevTables &T, const double *v, long long vstride, double *ext, long long esb,
                   long long esj, const double *dntt, long long nstride, int cnt, int beta, int next,
                   const int *ext_prime, const ModUpDigits &dg, hipStream_t s) {
     if (cnt <= 0) return;
+    int dmax = 0;
+    for (int j = 0; j < beta; ++j) dmax = dg.dl[j] > dmax ? dg.dl[j] : dmax;
+    const int DL = digit_len(dmax);
+    const int cblk = (T.N + 255) / 256;
+    // wide target blocks when they still give a few waves per SIMD
+    const bool wide = (long long)((next + 7) / 8) * cblk * cnt * beta >= 2048;
     kprof_set_bytes(8.0 * T.N * cnt * beta * (next + 2.0 * next / beta));  // digits in, every slot out
-    KL("k_modup", k_modup, dim3((next + MU_TB - 1) / MU_TB, (T.N + 255) / 256, cnt * beta), dim3(256), 0, s,
-       T, v, vstride, ext, esb, esj, dntt, nstride, beta, next, ext_prime, dg);
+    if (wide)
+        modup_tb<8>(DL, dim3((next + 7) / 8, cblk, cnt * beta), s, T, v, vstride, ext, esb, esj, dntt, nstride,
+                    beta, next, ext_prime, dg);
+    else
+        modup_tb<4>(DL, dim3((next + 3) / 4, cblk, cnt * beta), s, T, v, vstride, ext, esb, esj, dntt, nstride,
+                    beta, next, ext_prime, dg);
 }
 
 // acc_c[ct][t] = sum_j ext[ct][j][t] * key[j][c][prime(t)]; the key words are
@@ -301,107 +342,76 @@ void launch_inner_product(const DevTables &T, const double *ext, long long estri
 // (coefficient domain, scaled by the inverse NTT); each is lifted to its centred
 // representative and conv_i = sum_m w_m [Phat_m]_{q_i} for i <= level.
 // acc holds groups of (level+1+alpha) limbs at astride; conv [groups][level+1].
-// Grid: x = blocks of MU_TB target primes, y = coefficient blocks, z = group.
-__global__ void k_moddown_conv(DevTables T, const double *acc, long long astride, double *conv,
-                               long long cstride, int level, const double *phat) {
-    const int x = blockIdx.y * blockDim.x + threadIdx.x;
+// Grid: x = blocks of TB target primes, y = coefficient blocks, z = group; the
+// block's [Phat_m]_{q_i} table is staged in LDS as in k_modup.
+template <int AL, int TB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_moddown_conv(DevTables T, const double *__restrict__ acc,
+                                                      long long astride, double *__restrict__ conv,
+                                                      long long cstride, int level,
+                                                      const double *__restrict__ phat) {
+    __shared__ double sq[AL * TB];
+    __shared__ double sp[TB], si[TB];
+    const int A = T.alpha, i0 = blockIdx.x * TB, tid = threadIdx.x;
+    for (int k = tid; k < AL * TB; k += blockDim.x) {
+        const int m = k / TB, i = i0 + (k - (k / TB) * TB);
+        sq[k] = (m < A && i <= level) ? phat[m * (T.L + 1) + i] : 0.0;
+    }
+    if (tid < TB) {
+        const int i = i0 + tid <= level ? i0 + tid : 0;
+        sp[tid] = T.p[i];
+        si[tid] = T.pinv[i];
+    }
+    __syncthreads();
+    const int x = blockIdx.y * blockDim.x + tid;
     if (x >= T.N) return;
-    const int gi = blockIdx.z;
-    const int A = T.alpha;
-    const double *Ac = acc + gi * astride;
-    double w[16];
+    const double *Ac = acc + blockIdx.z * astride + (long long)(level + 1) * T.N + x;
+    double w[AL];
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
+    for (int m = 0; m < AL; ++m) {
         if (m < A) {
             const double p = T.p[T.L + 1 + m];
-            const double v = Ac[(long long)(level + 1 + m) * T.N + x];
-            w[m] = v > 0.5 * (p - 1.0) ? v - p : v;
+            const double u = Ac[(long long)m * T.N];
+            w[m] = u > 0.5 * (p - 1.0) ? u - p : u;
+        } else {
+            w[m] = 0.0;
         }
     }
-    const int i0 = blockIdx.x * MU_TB;
-    for (int ii = 0; ii < MU_TB; ++ii) {
+    double *out = conv + blockIdx.z * cstride + x;
+#pragma unroll
+    for (int ii = 0; ii < TB; ++ii) {
         const int i = i0 + ii;
         if (i > level) break;
-        const double p = T.p[i], pinv = T.pinv[i];
-        double s = 0.0;
+        const double p = sp[ii], pinv = si[ii];
+        double sacc = 0.0;
 #pragma unroll
-        for (int m = 0; m < 16; ++m)
-            if (m < A) s += mm(w[m], phat[m * (T.L + 1) + i], p, pinv);
-        conv[gi * cstride + (long long)i * T.N + x] = canon(s, p, pinv);
+        for (int m = 0; m < AL; ++m) sacc += mm(w[m], sq[m * TB + ii], p, pinv);
+        out[(long long)i * T.N] = canon(sacc, p, pinv);
     }
 }
+
+template <int TB>
+static void conv_tb(int AL, dim3 grid, hipStream_t s, const DevTables &T, const double *acc, long long astride,
+                    double *conv, long long cstride, int level, const double *phat) {
+#define MD_CASE(D)                                                                                             \
+    case D:                                                                                                    \
+        KL("k_moddown_conv", (k_moddown_conv<D, TB>), grid, dim3(256), 0, s, T, acc, astride, conv, cstride, \
+           level, phat);                                                                                       \
+        break;
+    switch (AL) { MD_CASE(4) MD_CASE(8) MD_CASE(10) MD_CASE(12) MD_CASE(16) }
+#undef MD_CASE
+}
+
 void launch_moddown_conv(const DevTables &T, const double *acc, long long astride, double *conv,
                          long long cstride, int groups, int level, const double *phat, hipStream_t s) {
     if (groups <= 0) return;
+    const int AL = digit_len(T.alpha);
+    const int cblk = (T.N + 255) / 256;
+    const bool wide = (long long)((level + 8) / 8) * cblk * groups >= 2048;
     kprof_set_bytes(8.0 * T.N * groups * (T.alpha + level + 1));
-    KL("k_moddown_conv", k_moddown_conv, dim3((level + 1 + MU_TB - 1) / MU_TB, (T.N + 255) / 256, groups),
-       dim3(256), 0, s, T, acc, astride, conv, cstride, level, phat);
-}
-
-// out_i = (acc_i - conv_i) * P^-1 (+ add_i when bit (group & 1) of addmask is set)
-__global__ void k_moddown_combine(DevTables T, double *out, long long ostride, const double *acc,
-                                  long long astride, const double *conv, long long cstride,
-                                  const double *add, long long add_ct, long long add_poly,
-                                  int addmask, int limbs, const double *Pinv) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= T.N) return;
-    const int gi = blockIdx.y / limbs, i = blockIdx.y % limbs;
-    const double p = T.p[i], pinv = T.pinv[i];
-    const long long o = (long long)i * T.N + x;
-    double r = mm(acc[gi * astride + o] - conv[gi * cstride + o], Pinv[i], p, pinv);
-    if (add && ((addmask >> (gi & 1)) & 1)) r += add[(gi >> 1) * add_ct + (gi & 1) * add_poly + o];
-    out[gi * ostride + o] = canon(r, p, pinv);
-}
-void launch_moddown_combine(const DevTables &T, double *out, long long ostride, const double *acc,
-                            long long astride, const double *conv, long long cstride,
-                            const double *add, long long add_ct, long long add_poly, int addmask,
-                            int groups, int level, const double *Pinv, hipStream_t s) {
-    if (groups <= 0) return;
-    kprof_set_bytes(8.0 * T.N * groups * (level + 1) * (add ? 4.0 - 0.5 * (addmask == 1) : 3.0));
-    KL("k_moddown_combine", k_moddown_combine, dim3((T.N + 255) / 256, groups * (level + 1)), dim3(256), 0, s,
-                       T, out, ostride, acc, astride, conv, cstride, add, add_ct, add_poly, addmask,
-                       level + 1, Pinv);
-}
-
-// ------------------------------------------------------------------- rescale
-// lift_i = [c_level]_centred mod q_i, i < level (coefficient domain)
-__global__ void k_rescale_lift(DevTables T, const double *lastc, long long lstride, double *lift,
-                               long long fstride, int level) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= T.N) return;
-    const int gi = blockIdx.y / level, i = blockIdx.y % level;
-    const double ql = T.p[level];
-    double v = lastc[gi * lstride + x];
-    v = v > 0.5 * (ql - 1.0) ? v - ql : v;
-    lift[gi * fstride + (long long)i * T.N + x] = canon(v, T.p[i], T.pinv[i]);
-}
-void launch_rescale_lift(const DevTables &T, const double *lastc, long long lstride, double *lift,
-                         long long fstride, int cnt, int level, hipStream_t s) {
-    if (cnt <= 0 || level <= 0) return;
-    KL("k_rescale_lift", k_rescale_lift, dim3((T.N + 255) / 256, cnt * level), dim3(256), 0, s, T,
-                       lastc, lstride, lift, fstride, level);
-}
-
-// out_i = (K_i in_i - lift_i) * q_level^-1 mod q_i  (K_i = kmul[(gi/2)(level+1) + i],
-// 1 when kmul is null): a rescale with an integer multiplier folded in
-__global__ void k_rescale_combine(DevTables T, double *out, long long ostride, const double *in,
-                                  long long istride, const double *lift, long long fstride,
-                                  int level, const double *qlinv, const double *kmul) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= T.N) return;
-    const int gi = blockIdx.y / level, i = blockIdx.y % level;
-    const double p = T.p[i], pinv = T.pinv[i];
-    const long long o = (long long)i * T.N + x;
-    double v = in[gi * istride + o];
-    if (kmul) v = mm(v, kmul[(gi >> 1) * (level + 1) + i], p, pinv);
-    out[gi * ostride + o] = canon(mm(v - lift[gi * fstride + o], qlinv[i], p, pinv), p, pinv);
-}
-void launch_rescale_combine(const DevTables &T, double *out, long long ostride, const double *in,
-                            long long istride, const double *lift, long long fstride, int cnt,
-                            int level, const double *qlinv, const double *kmul, hipStream_t s) {
-    if (cnt <= 0 || level <= 0) return;
-    KL("k_rescale_combine", k_rescale_combine, dim3((T.N + 255) / 256, cnt * level), dim3(256), 0, s, T,
-                       out, ostride, in, istride, lift, fstride, level, qlinv, kmul);
+    if (wide)
+        conv_tb<8>(AL, dim3((level + 8) / 8, cblk, groups), s, T, acc, astride, conv, cstride, level, phat);
+    else
+        conv_tb<4>(AL, dim3((level + 4) / 4, cblk, groups), s, T, acc, astride, conv, cstride, level, phat);
 }
 
 // ---------------------------------------------------------------- sampling

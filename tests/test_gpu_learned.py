@@ -1,4 +1,4 @@
-"""GPU checks of the learned inverse-square-root initial guess (config 5): FP32 gradients
+"""GPU checks of the learned inverse-square-root initial guess: FP32 gradients
 against the FP64 reference, the variance logger against plaintext Alg. 1, the quartic
 collapse, the gain over the fixed Chebyshev guess at equal depth, and the encrypted
 CutMax with the learned guess (N = 2^16, batch 16) against the FP64 mirror."""
@@ -119,12 +119,12 @@ def test_learned_guess_beats_chebyshev_at_equal_depth(learned):
 
 
 def test_cutmax_with_learned_guess_batch16(learned):
-    """config 5: 16 requests at N = 2^16 with the learned degree-4 guess (29 levels) against the
+    """16 requests at N = 2^16 with the learned degree-4 guess (29 levels) against the
     fixed degree-3 Chebyshev schedule; both recover every argmax, the learned run matches its
     FP64 mirror within 1e-3"""
     from paper_2509_08383_amd import he
     coefs, _, _ = learned
-    say("[gpu] config 5 CutMax")
+    say("[gpu] learned-guess CutMax batch")
     G = he.Context(he.SECURE)
     xs = [llm_logits_var(5000 + r) for r in range(16)]
     cts = [G.encrypt(x) for x in xs]

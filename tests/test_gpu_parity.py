@@ -171,7 +171,7 @@ def toy_cfg(n, T=4):
 
 
 def test_cutmax_toy_bit_exact_and_mirror(toy):
-    """config 1: N=2^12, 1024 logits replicated to 2048 slots, T=4, p=3, c=5."""
+    """toy: N=2^12, 1024 logits replicated to 2048 slots, T=4, p=3, c=5."""
     from paper_2509_08383_amd import he
     say("[gpu] cutmax toy bit-exact")
     x = toy_logits(21)

@@ -1,6 +1,6 @@
 """GPU parity at the 128-bit parameter set (N = 2^16, 30 Q primes, dnum = 3): primitives
 bit-exact against the CPU oracle at full size; encrypted CutMax on 32000 LLM-like logits
-against the FP64 mirror within 1e-3 with the argmax recovered; the batched form (config 3)
+against the FP64 mirror within 1e-3 with the argmax recovered; the batched form (16 mixed requests)
 with 1- and 4-ciphertext requests."""
 import math
 import sys
@@ -79,9 +79,9 @@ def test_cutmax_secure_T1_bit_exact(sec):
 
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_cutmax_config2_vs_mirror(sec, seed):
-    """config 2: 32000 logits (3 Gumbel - 1.1 ln rank) zero-padded to 32768 slots, T=3, p=3, c=5"""
+    """32000 logits (3 Gumbel - 1.1 ln rank) zero-padded to 32768 slots, T=3, p=3, c=5"""
     from paper_2509_08383_amd import he
-    say(f"[gpu] secure: CutMax config 2 seed {seed}")
+    say(f"[gpu] secure: CutMax 32000 logits seed {seed}")
     x = llm_logits(seed)
     y, a, _ = slot_layout(x, sec.G.slots)
     cfg, coef = cfg2(he)
@@ -98,9 +98,9 @@ def test_cutmax_config2_vs_mirror(sec, seed):
 
 
 def test_cutmax_config3_batched(sec):
-    """config 3: 16 requests, even ids 32000 logits (1 ciphertext), odd ids 128256 (4 ciphertexts)"""
+    """16 requests, even ids 32000 logits (1 ciphertext), odd ids 128256 (4 ciphertexts)"""
     from paper_2509_08383_amd import he
-    say("[gpu] secure: batched config 3")
+    say("[gpu] secure: batched 16 requests")
     xs = [llm_logits(200 + r, 32000 if r % 2 == 0 else 128256) for r in range(16)]
     cts = [sec.G.encrypt(x) for x in xs]
     sec.O.nonce = sec.O.nonce + sum(c.a for c in cts)

@@ -1,4 +1,4 @@
-"""GPU checks of the encrypted one-shot nucleus sampler (Alg. 3, config 4): 32000-token
+"""GPU checks of the encrypted one-shot nucleus sampler (Alg. 3): 32000-token
 logits at temperature 0.8, client-drawn uniform noise turned into Beta(alpha, 1) noise
 (alpha = ln(0.1)/ln(0.9)) and encrypted, batch 8; the decrypted one-hot approximation
 picks the token the FP64 sampler argmax(x/tau + G) picks on the same noise."""
