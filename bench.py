@@ -15,6 +15,7 @@ Prints one JSON line.  --gpus N > 1 is not supported (one GPU per box).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -28,6 +29,9 @@ if ROOT not in sys.path:
 import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+# hardware-counter summary of one CutMax (rocprofv3 FETCH_SIZE / WRITE_SIZE / VALU passes),
+# valid only for the library sources it was taken with
+PMC_FILE = os.path.join(ROOT, "profiles", "pmc_cutmax_32k.json")
 VOCAB2 = 32000
 T, P, C = 3, 3, 5.0
 VLO, VHI = [12.0, 0.4, 0.8], [24.0, 0.9, 16.0]
@@ -40,6 +44,32 @@ def log(*a):
 def cfg_secure(he):
     return he.CutmaxCfg(T=T, p=[P] * T, c=[C] * T, var_lo=VLO, var_hi=VHI, init_degree=3, init_coef=None,
                         newton_steps=0, sum_lo=1.0, sum_hi=3.0, gold_d=3)
+
+
+def src_digest() -> str:
+    """sha256 (16 hex digits) over the library's HIP/C++ sources and its C header."""
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2509_08383_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    with open(os.path.join(ROOT, "include", "he.h"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def pmc_entry(kernel: str, digest: str):
+    """Counter summary of `kernel` if it was measured on these exact sources, else None."""
+    try:
+        with open(PMC_FILE) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("src_digest") != digest:
+        return None
+    return next((e for e in d.get("kernels", []) if e["kernel"] == kernel), None)
 
 
 def keyswitch_levels(L: int, T_: int, gold_d: int, slots: int):
@@ -94,6 +124,7 @@ def main():
     from workloads import llm_logits
 
     assert torch.cuda.is_available(), "no GPU"
+    digest = src_digest()
     log("[bench] context N=2^16")
     ctx = he.Context(he.SECURE, device=0)
     if args.graph:
@@ -132,10 +163,16 @@ def main():
         name = dom[0]
         launches, ms_total, bytes_total = dom[1]
         achieved = (bytes_total / (ms_total * 1e-3)) / 1e9 if bytes_total > 0 else None
+        pm = pmc_entry(name, digest)
+        traffic = None
+        if pm and "fetch_MiB" in pm and "write_MiB" in pm:
+            traffic = (pm["fetch_MiB"] + pm["write_MiB"]) * 2**20
         roof = {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
-                "launches": launches, "avg_launch_ms": ms_total / launches,
-                "share_of_kernel_time": ms_total / tot}
+                "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "alg_bytes_per_launch": bytes_total / launches, "launches": launches,
+                "avg_launch_ms": ms_total / launches, "share_of_kernel_time": ms_total / tot,
+                "valu_frac": pm.get("valu_util") if pm else None}
         log(f"[bench] dominant kernel {name}: {launches} launches, {ms_total:.3f} ms, {achieved} GB/s")
 
     # --- NTT GB/s (algorithmic 2 N 8 bytes per limb-NTT)
@@ -171,6 +208,11 @@ def main():
         ok = sum(int(np.argmax(ctx.decrypt(Zb[r], xs[r].size)) == int(np.argmax(xs[r]))) for r in range(16))
         batch = {"requests": 16, "ciphertexts": sum(c.a for c in cts), "ms_per_batch": per_batch * 1e3,
                  "argmaxes_per_s": 16.0 / per_batch, "device_ms": ctx.last_cutmax_ms(), "argmax_ok": ok}
+        if not args.no_profile:
+            ctx.profile_begin()
+            ctx.cutmax(cts, cfg)
+            kb = ctx.profile_end()
+            batch["kernels"] = {k: {"launches": v[0], "ms": v[1], "bytes": v[2]} for k, v in kb.items()}
         log(f"[bench] batch {batch}")
         del cts, Zb
 
@@ -219,6 +261,7 @@ def main():
                                "one ciphertext of 32000 LLM-like logits in 32768 slots, T=3, p=3, c=5",
                    "global_batch": 1, "seq_len": VOCAB2, "parallelism": "none"},
         "device_ms_median": float(np.median(dev_ms)),
+        "src_digest": digest,
         "argmax_ok": bool(argmax_ok),
         "batched": batch,
         "ntt": ntt,

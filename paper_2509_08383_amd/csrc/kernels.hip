@@ -75,6 +75,7 @@ __global__ void k_add(VecSet out, VecSet a, VecSet b, DevTables T, int sign) {
 void launch_add(const DevTables &T, const VecSet &out, const VecSet &a, const VecSet &b, int sign,
                 hipStream_t s) {
     if (out.count <= 0) return;
+    kprof_set_bytes(24.0 * T.N * out.count);
     KL("k_add", k_add, ew_grid(T, out.count), dim3(256), 0, s, out, a, b, T, sign);
 }
 
@@ -86,6 +87,7 @@ __global__ void k_copy(VecSet out, VecSet a, DevTables T) {
 }
 void launch_copy(const DevTables &T, const VecSet &out, const VecSet &a, hipStream_t s) {
     if (out.count <= 0) return;
+    kprof_set_bytes(16.0 * T.N * out.count);
     KL("k_copy", k_copy, ew_grid(T, out.count), dim3(256), 0, s, out, a, T);
 }
 
@@ -99,6 +101,7 @@ __global__ void k_mul_const(VecSet out, VecSet a, ConstTab k, DevTables T) {
 void launch_mul_const(const DevTables &T, const VecSet &out, const VecSet &a, ConstTab k,
                       hipStream_t s) {
     if (out.count <= 0) return;
+    kprof_set_bytes(16.0 * T.N * out.count);
     KL("k_mul_const", k_mul_const, ew_grid(T, out.count), dim3(256), 0, s, out, a, k, T);
 }
 
@@ -113,6 +116,7 @@ __global__ void k_add_const(VecSet out, VecSet a, ConstTab k, DevTables T) {
 void launch_add_const(const DevTables &T, const VecSet &out, const VecSet &a, ConstTab k,
                       hipStream_t s) {
     if (out.count <= 0) return;
+    kprof_set_bytes(16.0 * T.N * out.count);
     KL("k_add_const", k_add_const, ew_grid(T, out.count), dim3(256), 0, s, out, a, k, T);
 }
 
@@ -131,6 +135,7 @@ __global__ void k_axpy_map(VecSet out, VecSet a, ConstTab k, VecSet b, const int
 void launch_axpy_map(const DevTables &T, const VecSet &out, const VecSet &a, ConstTab k,
                      const VecSet &b, const int *bmap, int bdiv, hipStream_t s) {
     if (out.count <= 0) return;
+    kprof_set_bytes(24.0 * T.N * out.count);
     KL("k_axpy_map", k_axpy_map, ew_grid(T, out.count), dim3(256), 0, s, out, a, k, b, bmap, bdiv, T);
 }
 
@@ -195,6 +200,7 @@ __global__ void k_automorph(VecSet out, VecSet in, uint64_t galois, DevTables T)
 void launch_automorph(const DevTables &T, const VecSet &out, const VecSet &in, uint64_t galois,
                       hipStream_t s) {
     if (out.count <= 0) return;
+    kprof_set_bytes(16.0 * T.N * out.count);
     KL("k_automorph", k_automorph, ew_grid(T, out.count), dim3(256), 0, s, out, in, galois, T);
 }
 
@@ -285,7 +291,10 @@ void launch_modup(const DevTables &T, const double *v, long long vstride, double
     const int cblk = (T.N + 255) / 256;
     // wide target blocks when they still give a few waves per SIMD
     const bool wide = (long long)((next + 7) / 8) * cblk * cnt * beta >= 2048;
-    kprof_set_bytes(8.0 * T.N * cnt * beta * (next + 2.0 * next / beta));  // digits in, every slot out
+    int lp1 = 0;
+    for (int j = 0; j < beta; ++j) lp1 += dg.dl[j];
+    // the l+1 digit words and the l+1 NTT-domain words in, every extended slot out
+    kprof_set_bytes(8.0 * T.N * cnt * (2.0 * lp1 + (double)beta * next));
     if (wide)
         modup_tb<8>(DL, dim3((next + 7) / 8, cblk, cnt * beta), s, T, v, vstride, ext, esb, esj, dntt, nstride,
                     beta, next, ext_prime, dg);

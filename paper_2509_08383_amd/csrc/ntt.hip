@@ -252,20 +252,28 @@ static void ntt_run(const DevTables &T, const VecSet &vs, const VecSet *src, boo
     dim3 grid(SUB / COLS, vs.count), block(NT);
     const VecSet none{nullptr, 0, 1, 0, nullptr, nullptr};
     const VecSet first = src ? *src : none;
-    const double bytes = 16.0 * SUB * SUB * vs.count;  // each pass reads and writes every word once
+    // algorithmic bytes: a limb-NTT reads and writes every word once (2 N 8 bytes), half
+    // of it booked to each pass; a fused prologue reads the shared last limb once per
+    // group; a fused epilogue adds its element-wise operands (in, addends)
+    const double half = 8.0 * SUB * SUB;
+    const double nvec = vs.count, ngrp = (vs.count + vs.group - 1) / vs.group;
     if (!inverse) {
-        kprof_set_bytes(bytes);
+        kprof_set_bytes(half * (PRO ? ngrp : nvec));
         KLN(PRO ? "ntt_fwd_pass1_lift" : "ntt_fwd_pass1", (k_ntt<H, COLS, false, false, PRO, 0>), grid, block, 0, s,
             vs, first, nullptr, T, pro, epi);
-        // a fused epilogue also reads `in` (and the addends) and writes `out`
-        kprof_set_bytes(EPI ? bytes * (EPI == 1 ? 1.5 + 0.5 * ((epi.add1 != nullptr) + (epi.add2 != nullptr)) : 1.5)
-                            : bytes);
+        double extra = 0.0;
+        if (EPI) {
+            extra = 1.0;  // in
+            if (EPI == 1 && epi.add1) extra += __builtin_popcount(epi.m1 & 3) * 0.5;
+            if (EPI == 1 && epi.add2) extra += __builtin_popcount(epi.m2 & 3) * 0.5;
+        }
+        kprof_set_bytes(half * nvec * (1.0 + extra));
         KLN(EPI == 1 ? "ntt_fwd_pass2_moddown" : (EPI == 2 ? "ntt_fwd_pass2_rescale" : "ntt_fwd_pass2"),
             (k_ntt<H, COLS, true, false, 0, EPI>), grid, block, 0, s, vs, none, nullptr, T, pro, epi);
     } else {
-        kprof_set_bytes(bytes);
+        kprof_set_bytes(half * nvec);
         KLN("ntt_inv_pass2", (k_ntt<H, COLS, true, true, 0, 0>), grid, block, 0, s, vs, first, nullptr, T, pro, epi);
-        kprof_set_bytes(bytes);
+        kprof_set_bytes(half * nvec);
         KLN("ntt_inv_pass1", (k_ntt<H, COLS, false, true, 0, 0>), grid, block, 0, s, vs, none, oscale, T, pro, epi);
     }
 }

@@ -6,7 +6,9 @@ Inputs are rocprofv3 output directories written with ``--output-format csv`` (th
 * ``--trace DIR``: a ``--kernel-trace --stats`` run (durations);
 * ``--fetch DIR`` / ``--write DIR``: ``--pmc FETCH_SIZE`` and ``--pmc WRITE_SIZE`` runs;
 * ``--valu DIR``: a run with SQ_INSTS_VALU, SQ_INSTS_VALU_{FMA,MUL,ADD}_F64, GRBM_GUI_ACTIVE;
-* ``--lds DIR``: a run with SQ_INSTS_LDS, SQ_LDS_BANK_CONFLICT, SQ_LDS_IDX_ACTIVE.
+* ``--lds DIR``: a run with SQ_INSTS_LDS, SQ_LDS_BANK_CONFLICT, SQ_LDS_IDX_ACTIVE;
+* ``--bench-json FILE``: bench.py's JSON line with the event profiler's algorithmic
+  bytes per kernel and the digest of the library sources that ran.
 
 The dispatches of the timed CutMax are the second half of those between the last
 encryption kernel (k_encfinish) and the first decryption kernel (k_decmul): the bench
@@ -51,7 +53,7 @@ def kernel_class(name: str) -> str:
         return s
     base = re.sub(r"\(.*", "", name)
     base = re.sub(r"^void ", "", base)
-    return base.split("::")[-1]
+    return re.sub(r"<.*", "", base.split("::")[-1])
 
 
 def _trace(d: str):
@@ -125,9 +127,12 @@ def summarize(trace=None, fetch=None, write=None, valu=None, lds=None, bench_jso
                     "SQ_INSTS_VALU_INT32", "SQ_INSTS_VALU_TRANS_F64"])
     ll = raw(lds, ["SQ_INSTS_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_LDS_IDX_ACTIVE"])
     alg = {}
+    digest = None
     if bench_json:
-        line = open(bench_json).read().strip().splitlines()[-1]
-        for k, v in json.loads(line).get("kernels", {}).items():
+        lines = [ln for ln in open(bench_json).read().splitlines() if ln.startswith('{"metric"')]
+        bj = json.loads(lines[-1])
+        digest = bj.get("src_digest")
+        for k, v in bj.get("kernels", {}).items():
             alg[k] = v["bytes"] / v["launches"] if v["launches"] else 0.0
 
     total = sum(dur.values())
@@ -157,7 +162,7 @@ def summarize(trace=None, fetch=None, write=None, valu=None, lds=None, bench_jso
         res.append(e)
     res.sort(key=lambda e: -e["total_ms"])
     return {"dispatches": len(win), "total_ms": total * 1e3, "fetch_scale": fscale, "write_scale": wscale,
-            "kernels": res}
+            "src_digest": digest, "kernels": res}
 
 
 def to_markdown(s) -> str:
@@ -179,12 +184,17 @@ def to_markdown(s) -> str:
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    for k in ("trace", "fetch", "write", "valu", "lds", "bench_json"):
-        ap.add_argument("--" + k.replace("_", "-"))
-    ap.add_argument("--json", action="store_true")
+    for k in ("trace", "fetch", "write", "valu", "lds"):
+        ap.add_argument("--" + k)
+    ap.add_argument("--bench-json", help="a file holding bench.py's JSON line (algorithmic bytes, "
+                    "source digest); the counter runs' own logs hold one")
+    ap.add_argument("--json-out", help="also write the summary as JSON to this file")
     a = ap.parse_args()
     s = summarize(a.trace, a.fetch, a.write, a.valu, a.lds, a.bench_json)
-    print(json.dumps(s, indent=1) if a.json else to_markdown(s))
+    if a.json_out:
+        with open(a.json_out, "w") as fh:
+            json.dump(s, fh, indent=1)
+    print(to_markdown(s))
 
 
 if __name__ == "__main__":
