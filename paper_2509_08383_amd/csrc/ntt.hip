@@ -79,7 +79,19 @@ __global__ __launch_bounds__(COLS *(1 << H)) void k_ntt(VecSet vs, VecSet src, c
         return PASS2 ? (long long)(cb * COLS + cc) * SUB + k : (long long)(cb * COLS + cc) + (long long)SUB * k;
     };
     constexpr int soff = PASS2 ? R : 0;
+    constexpr int NW = (1 << H) - 1;  // twiddles per phase: 2^sg for stage group sg < H
+    // every twiddle of both phases is loaded at the start, so no memory round trip
+    // is left between the phases or behind the barrier
+    double wa[NW], wb[NW];
+#pragma unroll
+    for (int sg = 0; sg < H; ++sg)
+#pragma unroll
+        for (int g = 0; g < (1 << sg); ++g) {
+            wa[(1 << sg) - 1 + g] = tw[(1 << (sg + soff)) + (PASS2 ? (b << sg) : 0) + g];
+            wb[(1 << sg) - 1 + g] = tw[(1 << (H + sg + soff)) + (PASS2 ? (b << (H + sg)) : 0) + (th << sg) + g];
+        }
     double v[E];
+    constexpr int EW = SUB / TPS;  // words per thread in the coalesced epilogue
 
     if (!INV) {
         // phase A (high bits of k), loaded straight from global memory
@@ -97,10 +109,10 @@ __global__ __launch_bounds__(COLS *(1 << H)) void k_ntt(VecSet vs, VecSet src, c
         }
 #pragma unroll
         for (int sg = 0; sg < H; ++sg) {
-            const int s = sg + soff, hd = E >> (sg + 1);
+            const int hd = E >> (sg + 1);
 #pragma unroll
             for (int g = 0; g < (1 << sg); ++g) {
-                const double w = tw[(1 << s) + (PASS2 ? (b << sg) : 0) + g];
+                const double w = wa[(1 << sg) - 1 + g];
 #pragma unroll
                 for (int i = 0; i < hd; ++i) {
                     const int e0 = g * 2 * hd + i, e1 = e0 + hd;
@@ -113,15 +125,33 @@ __global__ __launch_bounds__(COLS *(1 << H)) void k_ntt(VecSet vs, VecSet src, c
 #pragma unroll
         for (int e = 0; e < E; ++e) tile[lds(c, th + TPS * e)] = nred(v[e], p, pinv);
         __syncthreads();
+        // epilogue operands, in flight while phase B computes
+        double ex[EPI ? EW : 1], es[EPI == 1 ? EW : 1];
+        long long rN = 0;
+        if (EPI) {
+            rN = (long long)r_ * NN;
+            const double *in = epi.in + (long long)g_ * epi.i_g + rN;
+            const bool use1 = epi.add1 && ((epi.m1 >> (g_ & 1)) & 1);
+            const bool use2 = epi.add2 && ((epi.m2 >> (g_ & 1)) & 1);
+            const double *ad1 = use1 ? epi.add1 + (long long)(g_ >> 1) * epi.a1_ct + (g_ & 1) * epi.a1_poly + rN : nullptr;
+            const double *ad2 = use2 ? epi.add2 + (long long)(g_ >> 1) * epi.a2_ct + (g_ & 1) * epi.a2_poly + rN : nullptr;
+#pragma unroll
+            for (int i = 0; i < EW; ++i) {
+                const int idx = tid + NT * i, k = idx % SUB, cc = idx / SUB;
+                const long long j = gidx(cc, k);
+                ex[i] = in[j];
+                if (EPI == 1) es[i] = (use1 ? ad1[j] : 0.0) + (use2 ? ad2[j] : 0.0);
+            }
+        }
         // phase B (low bits of k)
 #pragma unroll
         for (int e = 0; e < E; ++e) v[e] = tile[lds(c, th * E + e)];
 #pragma unroll
         for (int sg = 0; sg < H; ++sg) {
-            const int s = H + sg + soff, hd = E >> (sg + 1);
+            const int hd = E >> (sg + 1);
 #pragma unroll
             for (int g = 0; g < (1 << sg); ++g) {
-                const double w = tw[(1 << s) + (PASS2 ? (b << (H + sg)) : 0) + (th << sg) + g];
+                const double w = wb[(1 << sg) - 1 + g];
 #pragma unroll
                 for (int i = 0; i < hd; ++i) {
                     const int e0 = g * 2 * hd + i, e1 = e0 + hd;
@@ -135,38 +165,29 @@ __global__ __launch_bounds__(COLS *(1 << H)) void k_ntt(VecSet vs, VecSet src, c
 #pragma unroll
             for (int e = 0; e < E; ++e) ptr[gidx(c, th * E + e)] = ncanon(v[e], p, pinv);
         } else {
+            // each thread rewrites only the tile words it read in phase B
 #pragma unroll
             for (int e = 0; e < E; ++e) tile[lds(c, th * E + e)] = ncanon(v[e], p, pinv);
             __syncthreads();
             if (EPI == 0) {
 #pragma unroll
-                for (int i = 0; i < SUB / TPS; ++i) {
+                for (int i = 0; i < EW; ++i) {
                     const int idx = tid + NT * i, k = idx % SUB, cc = idx / SUB;
                     ptr[gidx(cc, k)] = tile[lds(cc, k)];
                 }
             } else {
-                const long long rN = (long long)r_ * NN;
                 const double cst = epi.cst[r_];
-                const double *in = epi.in + (long long)g_ * epi.i_g + rN;
                 double *out = epi.out + (long long)g_ * epi.o_g + rN;
-                const bool use1 = epi.add1 && ((epi.m1 >> (g_ & 1)) & 1);
-                const bool use2 = epi.add2 && ((epi.m2 >> (g_ & 1)) & 1);
-                const double *ad1 = use1 ? epi.add1 + (long long)(g_ >> 1) * epi.a1_ct + (g_ & 1) * epi.a1_poly + rN : nullptr;
-                const double *ad2 = use2 ? epi.add2 + (long long)(g_ >> 1) * epi.a2_ct + (g_ & 1) * epi.a2_poly + rN : nullptr;
                 const double km = (EPI == 2 && epi.kmul) ? epi.kmul[(long long)(g_ >> 1) * epi.kstride + r_] : 1.0;
 #pragma unroll
-                for (int i = 0; i < SUB / TPS; ++i) {
+                for (int i = 0; i < EW; ++i) {
                     const int idx = tid + NT * i, k = idx % SUB, cc = idx / SUB;
-                    const long long j = gidx(cc, k);
                     const double w = tile[lds(cc, k)];
-                    double x = in[j];
+                    double x = ex[i];
                     if (EPI == 2 && epi.kmul) x = nmm(x, km, p, pinv);
                     double o = nmm(x - w, cst, p, pinv);
-                    if (EPI == 1) {
-                        if (use1) o += ad1[j];
-                        if (use2) o += ad2[j];
-                    }
-                    out[j] = ncanon(o, p, pinv);
+                    if (EPI == 1) o += es[i];
+                    out[gidx(cc, k)] = ncanon(o, p, pinv);
                 }
             }
         }
@@ -174,7 +195,7 @@ __global__ __launch_bounds__(COLS *(1 << H)) void k_ntt(VecSet vs, VecSet src, c
         // phase B first (low bits), stages descending
         if (PASS2) {
 #pragma unroll
-            for (int i = 0; i < SUB / TPS; ++i) {
+            for (int i = 0; i < EW; ++i) {
                 const int idx = tid + NT * i, k = idx % SUB, cc = idx / SUB;
                 tile[lds(cc, k)] = iptr[gidx(cc, k)];
             }
@@ -187,10 +208,10 @@ __global__ __launch_bounds__(COLS *(1 << H)) void k_ntt(VecSet vs, VecSet src, c
         }
 #pragma unroll
         for (int sg = H - 1; sg >= 0; --sg) {
-            const int s = H + sg + soff, hd = E >> (sg + 1);
+            const int hd = E >> (sg + 1);
 #pragma unroll
             for (int g = 0; g < (1 << sg); ++g) {
-                const double w = tw[(1 << s) + (PASS2 ? (b << (H + sg)) : 0) + (th << sg) + g];
+                const double w = wb[(1 << sg) - 1 + g];
 #pragma unroll
                 for (int i = 0; i < hd; ++i) {
                     const int e0 = g * 2 * hd + i, e1 = e0 + hd;
@@ -208,10 +229,10 @@ __global__ __launch_bounds__(COLS *(1 << H)) void k_ntt(VecSet vs, VecSet src, c
         for (int e = 0; e < E; ++e) v[e] = tile[lds(c, th + TPS * e)];
 #pragma unroll
         for (int sg = H - 1; sg >= 0; --sg) {
-            const int s = sg + soff, hd = E >> (sg + 1);
+            const int hd = E >> (sg + 1);
 #pragma unroll
             for (int g = 0; g < (1 << sg); ++g) {
-                const double w = tw[(1 << s) + (PASS2 ? (b << sg) : 0) + g];
+                const double w = wa[(1 << sg) - 1 + g];
 #pragma unroll
                 for (int i = 0; i < hd; ++i) {
                     const int e0 = g * 2 * hd + i, e1 = e0 + hd;
