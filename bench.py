@@ -94,7 +94,8 @@ def keyswitch_levels(L: int, T_: int, gold_d: int, slots: int):
 
 
 def ks_cost(levels, alpha):
-    """limb-NTT count of hybrid key switching at each level (SURVEY cost model)."""
+    """limb-NTT count of hybrid key switching at each level: INTT of the input, NTT of the
+    converted digits, INTT of the 2 alpha P limbs, NTT of the 2 (l+1) ModDown limbs."""
     tot = 0
     for l in levels:
         beta = -(-(l + 1) // alpha)
@@ -115,8 +116,8 @@ def main():
     ap.add_argument("--cpu-T", type=int, default=3, help="iterations of the oracle sample (1..3)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                          "(requests shard across GPUs with no exchange, see DESIGN.md)"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 "
+                          "(requests shard across GPUs with no exchange between them)"}))
         sys.exit(2)
 
     import torch

@@ -4,8 +4,9 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s cpu_baseline
 leg may import this module.  It loads ``oracle/libckks_oracle.so`` (plain C,
 built from ``oracle/ckks_oracle.c``) for the ring arithmetic and keeps the
 scale bookkeeping, the constant encodings and the CutMax schedule here, in
-float64 Python, written from the conventions in DESIGN.md ("CKKS conventions",
-"Encrypted CutMax schedule").  It shares no code with the HIP path.
+float64 Python, written from the CKKS conventions (scale rules, constant
+encodings) and the encrypted CutMax schedule stated in this module.  It shares
+no code with the HIP path.
 
 Paper anchors: CKKS correctness and homomorphic properties (Sec. 2.1);
 SIMD slots, rotations and rotate-and-sum (Sec. 3.2, App. D); the encrypted
@@ -296,7 +297,7 @@ class Oracle:
         level = limbs.shape[1] - 1
         return Ct(self, lib().oc_ct_import(self.h, _p(limbs, u64p), level), scale)
 
-    # evaluator ops (scales per DESIGN.md "CKKS conventions") -----------
+    # evaluator ops (scales: mul s_a s_b / q_l, rescale s / q_l) --------
     def add(self, a: Ct, b: Ct) -> Ct:
         if a.level != b.level:
             raise SchedError("add: level mismatch")

@@ -3,8 +3,9 @@
  *
  * Only tests/, __graft_entry__.smoke() and bench.py's cpu_baseline leg may load
  * this library.  It shares no code, header, table or constant generator with
- * the HIP path; the two meet only in the conventions written in the design doc
- * ("CKKS conventions"), each side implementing them on its own.
+ * the HIP path; the two meet only in shared conventions (prime search order,
+ * Philox counters and object ids, key layout, rounding rules), each side
+ * implementing them on its own from their statement.
  *
  * The paper runs its encrypted experiments in CKKS (Sec. 2.1 properties;
  * Sec. 3.2 SIMD slots and rotations; Alg. 2).  It states no scheme internals,

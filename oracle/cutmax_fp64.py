@@ -14,7 +14,7 @@ Two forms of Algorithm 1 (CutMax) are given:
   reference for decrypted results: the difference between it and a decryption
   is CKKS error only.
 
-Readings of the paper used here (each listed in the design doc):
+Readings of the paper used here:
 
 * Alg. 1 normalises ``Y^(T)`` although the loop last writes ``Y^(T+1)``; the
   last computed iterate is normalised (otherwise the last iteration is wasted).

@@ -126,7 +126,7 @@ class Params:
     seed: int = 1
 
 
-# parameter sets of the two workloads
+# parameter sets: a non-secure toy chain at N = 2^12 and the 128-bit chain at N = 2^16
 TOY = Params(log_n=12, n_q=36, q0_bits=40, q_bits=30, p_bits=40, dnum=3, log2_scale=30, seed=7)
 SECURE = Params(log_n=16, n_q=30, q0_bits=49, q_bits=40, p_bits=49, dnum=3, log2_scale=40, seed=11)
 
