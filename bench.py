@@ -224,7 +224,7 @@ def main():
         from oracle.cutmax_fp64 import chebyshev_invsqrt, slot_layout
         prm = he.SECURE
         O = ckks.Oracle(ckks.Params(prm.log_n, prm.n_q, prm.q0_bits, prm.q_bits, prm.p_bits, prm.dnum,
-                                    prm.log2_scale, prm.seed))
+                                    prm.log2_scale, prm.seed, prm.hoist))
         O.keygen_cutmax()
         y, a, _ = slot_layout(x, O.slots)
         oc = O.encrypt(y)

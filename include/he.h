@@ -51,7 +51,14 @@ typedef struct he_ct he_ct;
  * encoding scale Delta = 2^log2_scale; seed keys every random draw
  * (Philox4x32-10).  device: HIP device ordinal.  stream: a hipStream_t the
  * library enqueues on (for example PyTorch's current stream), or NULL for a
- * stream the library creates. */
+ * stream the library creates.  hoist: how rotate-and-sum (Sec. 3.2, App. D)
+ * runs: 0 = one rotation by 2^r at a time, each rotation a full key switch
+ * followed by an add; h in 1..4 = steps of radix 2^h, x <- x + sum_{r=1}^{2^h-1}
+ * rot(x, r k) for k = 1, 2^h, 2^2h, ... (the last step takes the bits left), each
+ * step extending the digits of c1 once (ModUp), applying every rotation's
+ * automorphism to the extended digits, summing the key products of all its
+ * rotations and running one ModDown.  h >= 2 adds rotation keys for the amounts
+ * r k that are not powers of two. */
 typedef struct {
     uint32_t log_n;
     uint32_t n_q;
@@ -63,6 +70,7 @@ typedef struct {
     uint64_t seed;
     int device;
     void *stream;
+    uint32_t hoist;
 } he_params;
 
 /* Hyper-parameters of one CutMax call (Alg. 1 inputs p, c, T; Sec. 4.2 uses
@@ -98,7 +106,8 @@ typedef struct {
 
 /* Context: prime chain, twiddle and basis-conversion tables, secret key, and
  * the relinearisation and rotation keys (rotation by 2^r slots for every r <
- * log2(slots)), generated on the device. */
+ * log2(slots), and the amounts of the hoisted rotate-and-sum steps), generated
+ * on the device. */
 int he_ctx_create(const he_params *prm, he_ctx **out);
 void he_ctx_destroy(he_ctx *ctx);
 

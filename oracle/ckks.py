@@ -61,6 +61,9 @@ def lib():
         L.oc_get_nonce.restype = ctypes.c_uint32
         L.oc_get_nonce.argtypes = [V]
         L.oc_keygen.argtypes = [V, ctypes.c_int]
+        L.oc_keygen_galois.argtypes = [V, ctypes.c_int, ctypes.c_uint64]
+        L.oc_rotsum_step.restype = V
+        L.oc_rotsum_step.argtypes = [V, V, ctypes.c_int, ctypes.POINTER(ctypes.c_int), u64p]
         L.oc_ct_free.argtypes = [V]
         L.oc_ct_level.argtypes = [V]
         L.oc_ct_export.argtypes = [V, V, u64p]
@@ -126,6 +129,7 @@ class Params:
     dnum: int
     log2_scale: float
     seed: int = 1
+    hoist: int = 0    # rotate-and-sum: 0 one rotation at a time, h >= 1 hoisted radix-2^h steps
 
     @property
     def N(self):
@@ -227,6 +231,34 @@ class SchedError(RuntimeError):
     pass
 
 
+def hoist_steps(slots: int, h: int) -> List[List[int]]:
+    """Rotation amounts of each step of the hoisted rotate-and-sum with radix 2^h over
+    log2(slots) bits: step b covers bits [b, b + hb), hb = min(h, bits left), and
+    rotates by r 2^b for r = 1 .. 2^hb - 1."""
+    lg = int(math.log2(slots))
+    out, b = [], 0
+    while b < lg:
+        hb = min(h, lg - b)
+        out.append([r << b for r in range(1, 1 << hb)])
+        b += hb
+    return out
+
+
+def rotation_keys(slots: int, h: int) -> dict:
+    """Key index of every rotation amount the hoisted rotate-and-sum uses: a power of
+    two 2^e has key 1 + e (the single-rotation keys); the other amounts follow, in
+    step order, from 1 + log2(slots)."""
+    lg = int(math.log2(slots))
+    keys = {1 << e: 1 + e for e in range(lg)}
+    nxt = 1 + lg
+    for step in hoist_steps(slots, h):
+        for a in step:
+            if a not in keys:
+                keys[a] = nxt
+                nxt += 1
+    return keys
+
+
 class Oracle:
     """CPU RNS-CKKS context: primes, secret, keys, and the evaluator ops."""
 
@@ -260,6 +292,9 @@ class Oracle:
 
     def keygen_cutmax(self):
         self.keygen(True, range(int(math.log2(self.slots))))
+        if self.prm.hoist >= 1:
+            for amount, k in rotation_keys(self.slots, self.prm.hoist).items():
+                lib().oc_keygen_galois(self.h, k, pow(5, amount, 2 * self.N))
 
     def secret(self) -> np.ndarray:
         s = np.empty(self.N, dtype=np.int8)
@@ -358,10 +393,28 @@ class Oracle:
 
     # composite steps of Alg. 2 -------------------------------------------
     def rotsum(self, x: Ct) -> Ct:
-        """Rotate-and-sum: x <- x + rot(x, 2^r), r = 0..log2(slots)-1 (Sec. 3.2)."""
-        for r in range(int(math.log2(self.slots))):
-            x = self.add(x, self.rotate(x, r))
+        """Rotate-and-sum (Sec. 3.2): every slot ends up holding the sum of all slots.
+        hoist 0: x <- x + rot(x, 2^r), r = 0..log2(slots)-1, one key switch each.
+        hoist h >= 1: steps of radix R = 2^h, x <- x + sum_{r=1}^{R-1} rot(x, r k) for
+        k = 1, R, R^2, ... (the last step takes the remaining bits), each step one
+        hoisted ModUp, the key products of its R-1 rotations summed, one ModDown."""
+        if self.prm.hoist <= 0:
+            for r in range(int(math.log2(self.slots))):
+                x = self.add(x, self.rotate(x, r))
+            return x
+        keys = rotation_keys(self.slots, self.prm.hoist)
+        for amounts in hoist_steps(self.slots, self.prm.hoist):
+            x = self.rotsum_step(x, amounts, keys)
         return x
+
+    def rotsum_step(self, x: Ct, amounts: Sequence[int], keys: dict) -> Ct:
+        """x + sum_r rot(x, a_r) with one hoisted key switch (oc_rotsum_step)."""
+        kid = (ctypes.c_int * len(amounts))(*[keys[a] for a in amounts])
+        gal = np.array([pow(5, a, 2 * self.N) for a in amounts], dtype=np.uint64)
+        h = lib().oc_rotsum_step(self.h, x.h, len(amounts), kid, _p(gal, u64p))
+        if not h:
+            raise SchedError("rotsum step: missing key")
+        return Ct(self, h, x.scale)
 
     def sum_list(self, xs: List[Ct]) -> Ct:
         acc = xs[0]

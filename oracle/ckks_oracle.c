@@ -230,7 +230,7 @@ oc_ctx *oc_ctx_create(int log_n, int n_q, int q0_bits, int q_bits, int p_bits, i
         for (int i = 0; i < N; i++) C->sk_ntt[p][i] = red_i64(C->sk[i], C->q[p]);
         fwd(C, p, C->sk_ntt[p]);
     }
-    C->nkeys = 2 + 20;
+    C->nkeys = 256;
     C->keys = (uint64_t **)calloc(C->nkeys, sizeof(void *));
     return C;
 }
@@ -272,16 +272,18 @@ static void automorph_small(const int8_t *in, int8_t *out, int N, uint64_t g) {
 }
 
 /* Key index 0: relinearisation key for s^2.  Key index k >= 1: rotation key
- * for s(X^g), g = 5^(2^(k-1)).  Digit j of the key, per prime index pi:
+ * for s(X^g); oc_keygen uses g = 5^(2^(k-1)) (rotation by 2^(k-1) slots),
+ * oc_keygen_galois takes g from the caller (rotation by any amount a: g = 5^a).
+ * Digit j of the key, per prime index pi:
  *   b = -a s + e + [pi in digit j] (P mod q_pi) s'     a uniform, e ~ CBD(21)   */
-int oc_keygen(oc_ctx *C, int kidx) {
+int oc_keygen_galois(oc_ctx *C, int kidx, uint64_t galois) {
     if (kidx < 0 || kidx >= C->nkeys) return -1;
     if (C->keys[kidx]) return 0;
     int N = C->N, np = C->np, beta = n_digits(C, C->L);
     /* target s' as residues per prime (coefficient domain then transformed) */
     uint64_t **tgt = (uint64_t **)malloc(sizeof(void *) * np);
     int8_t *sg = (int8_t *)malloc(N);
-    if (kidx >= 1) automorph_small(C->sk, sg, N, galois_of_key(C, kidx));
+    if (kidx >= 1) automorph_small(C->sk, sg, N, galois);
     #pragma omp parallel for schedule(dynamic)
     for (int p = 0; p < np; p++) {
         uint64_t q = C->q[p];
@@ -325,6 +327,11 @@ int oc_keygen(oc_ctx *C, int kidx) {
     free(tgt); free(sg); free(Pmod);
     C->keys[kidx] = K;
     return 0;
+}
+
+int oc_keygen(oc_ctx *C, int kidx) {
+    if (kidx < 0 || kidx >= C->nkeys) return -1;
+    return oc_keygen_galois(C, kidx, kidx >= 1 ? galois_of_key(C, kidx) : 0);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -524,6 +531,63 @@ oc_ct *oc_mul_int_rescale(const oc_ctx *C, const oc_ct *a, int64_t K) {
     return r;
 }
 
+/* ModDown of the NTT-domain accumulators acc0/acc1 over Q_l u P ([l+1+alpha][N],
+ * gidx = global prime index of each extended limb; transformed back in place):
+ * out_i = (acc_i - conv_P->q_i(acc_P)) * P^-1 mod q_i, coefficient domain */
+static void moddown(const oc_ctx *C, int l, uint64_t *acc0, uint64_t *acc1, const int *gidx, uint64_t *out0,
+                    uint64_t *out1) {
+    int N = C->N, nq = l + 1, A = C->alpha, next = nq + A;
+    /* back to coefficients */
+    #pragma omp parallel for schedule(dynamic)
+    for (int k = 0; k < 2 * next; k++) {
+        int kk = k % next; uint64_t *acc = k < next ? acc0 : acc1;
+        inv(C, gidx[kk], acc + (size_t)kk * N);
+    }
+    /* ModDown: out_i = (acc_i - conv_P->q_i(acc_P)) * P^-1 mod q_i, where the conversion
+     * lifts each [acc_m * Phat_m^-1]_{p_m} to its centred representative, so the
+     * division by P rounds with a mean-zero error */
+    uint64_t *phinv = (uint64_t *)malloc(8 * A);
+    for (int m = 0; m < A; m++) {
+        uint64_t pm = C->q[C->L + 1 + m], v = 1;
+        for (int b = 0; b < A; b++) if (b != m) v = mulm(v, C->q[C->L + 1 + b] % pm, pm);
+        phinv[m] = invm(v, pm);
+    }
+    for (int c = 0; c < 2; c++) {
+        uint64_t *acc = c ? acc1 : acc0, *out = c ? out1 : out0;
+        uint64_t *w = (uint64_t *)malloc(8 * (size_t)A * N);
+        for (int m = 0; m < A; m++) {
+            uint64_t pm = C->q[C->L + 1 + m];
+            for (int i = 0; i < N; i++) w[(size_t)m * N + i] = mulm(acc[(size_t)(nq + m) * N + i], phinv[m], pm);
+        }
+        #pragma omp parallel for schedule(dynamic)
+        for (int k = 0; k < nq; k++) {
+            uint64_t q = C->q[k];
+            uint64_t *ph = (uint64_t *)malloc(8 * A);
+            uint64_t Pm = 1;
+            for (int m = 0; m < A; m++) {
+                uint64_t v = 1;
+                for (int b = 0; b < A; b++) if (b != m) v = mulm(v, C->q[C->L + 1 + b] % q, q);
+                ph[m] = v;
+                Pm = mulm(Pm, C->q[C->L + 1 + m] % q, q);
+            }
+            uint64_t Pinv = invm(Pm, q);
+            for (int i = 0; i < N; i++) {
+                uint64_t s = 0;
+                for (int m = 0; m < A; m++) {
+                    /* centred lift of w_m to (-p_m/2, p_m/2], then reduced mod q_k */
+                    uint64_t pm = C->q[C->L + 1 + m], v = w[(size_t)m * N + i];
+                    uint64_t vk = v > (pm - 1) / 2 ? subm(0, (pm - v) % q, q) : v % q;
+                    s = addm(s, mulm(vk, ph[m], q), q);
+                }
+                out[(size_t)k * N + i] = mulm(subm(acc[(size_t)k * N + i], s, q), Pinv, q);
+            }
+            free(ph);
+        }
+        free(w);
+    }
+    free(phinv);
+}
+
 /* hybrid key switch of d (level l, coefficient domain) with key kidx.
  * out0/out1: [l+1][N] coefficient domain. */
 static int keyswitch(const oc_ctx *C, const uint64_t *d, int l, int kidx, uint64_t *out0, uint64_t *out1) {
@@ -581,55 +645,8 @@ static int keyswitch(const oc_ctx *C, const uint64_t *d, int l, int kidx, uint64
         }
         free(qhinv); free(vv);
     }
-    /* back to coefficients */
-    #pragma omp parallel for schedule(dynamic)
-    for (int k = 0; k < 2 * next; k++) {
-        int kk = k % next; uint64_t *acc = k < next ? acc0 : acc1;
-        inv(C, gidx[kk], acc + (size_t)kk * N);
-    }
-    /* ModDown: out_i = (acc_i - conv_P->q_i(acc_P)) * P^-1 mod q_i, where the conversion
-     * lifts each [acc_m * Phat_m^-1]_{p_m} to its centred representative, so the
-     * division by P rounds with a mean-zero error */
-    uint64_t *phinv = (uint64_t *)malloc(8 * A);
-    for (int m = 0; m < A; m++) {
-        uint64_t pm = C->q[C->L + 1 + m], v = 1;
-        for (int b = 0; b < A; b++) if (b != m) v = mulm(v, C->q[C->L + 1 + b] % pm, pm);
-        phinv[m] = invm(v, pm);
-    }
-    for (int c = 0; c < 2; c++) {
-        uint64_t *acc = c ? acc1 : acc0, *out = c ? out1 : out0;
-        uint64_t *w = (uint64_t *)malloc(8 * (size_t)A * N);
-        for (int m = 0; m < A; m++) {
-            uint64_t pm = C->q[C->L + 1 + m];
-            for (int i = 0; i < N; i++) w[(size_t)m * N + i] = mulm(acc[(size_t)(nq + m) * N + i], phinv[m], pm);
-        }
-        #pragma omp parallel for schedule(dynamic)
-        for (int k = 0; k < nq; k++) {
-            uint64_t q = C->q[k];
-            uint64_t *ph = (uint64_t *)malloc(8 * A);
-            uint64_t Pm = 1;
-            for (int m = 0; m < A; m++) {
-                uint64_t v = 1;
-                for (int b = 0; b < A; b++) if (b != m) v = mulm(v, C->q[C->L + 1 + b] % q, q);
-                ph[m] = v;
-                Pm = mulm(Pm, C->q[C->L + 1 + m] % q, q);
-            }
-            uint64_t Pinv = invm(Pm, q);
-            for (int i = 0; i < N; i++) {
-                uint64_t s = 0;
-                for (int m = 0; m < A; m++) {
-                    /* centred lift of w_m to (-p_m/2, p_m/2], then reduced mod q_k */
-                    uint64_t pm = C->q[C->L + 1 + m], v = w[(size_t)m * N + i];
-                    uint64_t vk = v > (pm - 1) / 2 ? subm(0, (pm - v) % q, q) : v % q;
-                    s = addm(s, mulm(vk, ph[m], q), q);
-                }
-                out[(size_t)k * N + i] = mulm(subm(acc[(size_t)k * N + i], s, q), Pinv, q);
-            }
-            free(ph);
-        }
-        free(w);
-    }
-    free(phinv); free(acc0); free(acc1); free(gidx);
+    moddown(C, l, acc0, acc1, gidx, out0, out1);
+    free(acc0); free(acc1); free(gidx);
     return 0;
 }
 
@@ -725,6 +742,104 @@ oc_ct *oc_rotate(const oc_ctx *C, const oc_ct *a, int r) {
     for (int p = 0; p <= l; p++)
         for (int i = 0; i < N; i++) { size_t x = (size_t)p * N + i; o->c[0][x] = addm(o->c[0][x], s0[x], C->q[p]); }
     free(s0); free(s1);
+    return o;
+}
+
+/* a(X) -> a(X^g) on one limb of residues mod q (coefficient domain) */
+static void automorph_limb(const uint64_t *in, uint64_t *out, int N, uint64_t g, uint64_t q) {
+    uint64_t M = 2 * (uint64_t)N;
+    for (int i = 0; i < N; i++) {
+        uint64_t e = ((uint64_t)i * g) % M, v = in[i];
+        if (e < (uint64_t)N) out[e] = v; else out[e - N] = v ? q - v : 0;
+    }
+}
+
+/* One step of a hoisted rotate-and-sum: x + sum_r rot(x, a_r) for nr rotations with
+ * Galois elements gal[r] = 5^(a_r) and keys kidx[r].  The digits of c1 are extended
+ * once (ModUp); every rotation applies its automorphism to the extended digits and
+ * multiplies by its own key; the products of all rotations are summed over Q_l u P
+ * and brought back by a single ModDown:
+ *   A    = sum_r sum_j sigma_r(ModUp_j(c1)) * key_{r,j}
+ *   out0 = c0 + sum_r sigma_r(c0) + ModDown(A)_0,   out1 = c1 + ModDown(A)_1.
+ * (Halevi-Shoup hoisting of the ModUp, and one ModDown for the whole sum.) */
+oc_ct *oc_rotsum_step(const oc_ctx *C, const oc_ct *x, int nr, const int *kidx, const uint64_t *gal) {
+    if (nr < 1) return NULL;
+    for (int r = 0; r < nr; r++)
+        if (kidx[r] < 1 || kidx[r] >= C->nkeys || !C->keys[kidx[r]]) return NULL;
+    int N = C->N, l = x->level, nq = l + 1, A = C->alpha, next = nq + A;
+    int beta = n_digits(C, l);
+    size_t per = (size_t)C->np * N;
+    const uint64_t *d = x->c[1];
+    int *gidx = (int *)malloc(sizeof(int) * next);
+    for (int k = 0; k < nq; k++) gidx[k] = k;
+    for (int m = 0; m < A; m++) gidx[nq + m] = C->L + 1 + m;
+    uint64_t *acc0 = (uint64_t *)calloc((size_t)next * N, 8);
+    uint64_t *acc1 = (uint64_t *)calloc((size_t)next * N, 8);
+    for (int j = 0; j < beta; j++) {
+        int lo = j * A, hi = lo + A; if (hi > nq) hi = nq;
+        int dl = hi - lo;
+        uint64_t *qhinv = (uint64_t *)malloc(8 * dl);
+        for (int a = 0; a < dl; a++) {
+            uint64_t qi = C->q[lo + a], v = 1;
+            for (int b = 0; b < dl; b++) if (b != a) v = mulm(v, C->q[lo + b] % qi, qi);
+            qhinv[a] = invm(v, qi);
+        }
+        uint64_t *vv = (uint64_t *)malloc(8 * (size_t)dl * N);
+        for (int a = 0; a < dl; a++)
+            for (int i = 0; i < N; i++) vv[(size_t)a * N + i] = mulm(d[(size_t)(lo + a) * N + i], qhinv[a], C->q[lo + a]);
+        #pragma omp parallel for schedule(dynamic)
+        for (int k = 0; k < next; k++) {
+            int g = gidx[k]; uint64_t pk = C->q[g];
+            uint64_t *e = (uint64_t *)malloc(8 * N), *t = (uint64_t *)malloc(8 * N);
+            if (k >= lo && k < hi) memcpy(e, d + (size_t)k * N, 8 * N);
+            else {
+                uint64_t *qh = (uint64_t *)malloc(8 * dl);
+                for (int a = 0; a < dl; a++) {
+                    uint64_t v = 1;
+                    for (int b = 0; b < dl; b++) if (b != a) v = mulm(v, C->q[lo + b] % pk, pk);
+                    qh[a] = v;
+                }
+                for (int i = 0; i < N; i++) {
+                    uint64_t sum = 0;
+                    for (int a = 0; a < dl; a++) sum = addm(sum, mulm(vv[(size_t)a * N + i] % pk, qh[a], pk), pk);
+                    e[i] = sum;
+                }
+                free(qh);
+            }
+            for (int r = 0; r < nr; r++) {
+                automorph_limb(e, t, N, gal[r], pk);
+                fwd(C, g, t);
+                const uint64_t *K = C->keys[kidx[r]];
+                const uint64_t *kb = K + ((size_t)j * 2 + 0) * per + (size_t)g * N;
+                const uint64_t *ka = K + ((size_t)j * 2 + 1) * per + (size_t)g * N;
+                for (int i = 0; i < N; i++) {
+                    acc0[(size_t)k * N + i] = addm(acc0[(size_t)k * N + i], mulm(t[i], kb[i], pk), pk);
+                    acc1[(size_t)k * N + i] = addm(acc1[(size_t)k * N + i], mulm(t[i], ka[i], pk), pk);
+                }
+            }
+            free(e); free(t);
+        }
+        free(qhinv); free(vv);
+    }
+    oc_ct *o = ct_new(C, l);
+    moddown(C, l, acc0, acc1, gidx, o->c[0], o->c[1]);
+    size_t n = (size_t)nq * N;
+    uint64_t *s0 = (uint64_t *)malloc(8 * n);
+    for (int r = 0; r < nr; r++) {
+        automorph(C, x->c[0], s0, l, gal[r]);
+        for (int p = 0; p < nq; p++)
+            for (int i = 0; i < N; i++) {
+                size_t z = (size_t)p * N + i;
+                o->c[0][z] = addm(o->c[0][z], s0[z], C->q[p]);
+            }
+    }
+    for (int p = 0; p < nq; p++)
+        for (int i = 0; i < N; i++) {
+            size_t z = (size_t)p * N + i;
+            o->c[0][z] = addm(o->c[0][z], x->c[0][z], C->q[p]);
+            o->c[1][z] = addm(o->c[1][z], x->c[1][z], C->q[p]);
+        }
+    free(s0); free(acc0); free(acc1); free(gidx);
     return o;
 }
 

@@ -152,6 +152,10 @@ struct he_ctx {
     double last_ms = 0;
     int use_graph = 0;
     int ntt_variant = 0;
+    // rotate-and-sum: 0 = one rotation at a time, h = hoisted radix-2^h steps
+    int hoist = 0;
+    std::map<int, int> rot_key;     // rotation amount -> key index
+    std::vector<uint32_t> key_gal;  // key index -> Galois element (0 for relinearisation)
     // graph cache keyed by a signature of the call
     std::map<std::string, hipGraphExec_t> graphs;
 };
@@ -180,6 +184,8 @@ struct Addend {
     long long ct, poly;
     int mask;
 };
+
+std::vector<std::vector<int>> hoist_steps(int slots, int h);
 
 struct Exec {
     he_ctx *C;
@@ -330,8 +336,11 @@ struct Exec {
     // ------------------------------------------------------------ key switch
     // d: NTT-domain polynomials [cnt] at `dstride` words apart, limbs 0..l.
     // out (groups ct*2 + poly at ostride) = ModDown(sum_j ModUp_j(d) key_j) + a1 + a2.
+    // With rot, the key products are those of a hoisted rotate-and-sum step: every
+    // rotation's automorphism applied to the extended digits, its key, summed (kidx unused).
     void keyswitch(const double *d, long long dstride, int cnt, int l, int kidx, double *out, long long ostride,
-                   Addend a1 = Addend{nullptr, 0, 0, 0}, Addend a2 = Addend{nullptr, 0, 0, 0}) {
+                   Addend a1 = Addend{nullptr, 0, 0, 0}, Addend a2 = Addend{nullptr, 0, 0, 0},
+                   const RotSet *rot = nullptr) {
         const int A = C->alpha, next = l + 1 + A, beta = (l + 1 + A - 1) / A;
         const long long N = C->N;
         const size_t m = C->arena.mark();
@@ -356,9 +365,14 @@ struct Exec {
             const int nd = C->ndall[l];
             launch_ntt(T, VecSet{ext, cnt * nd, nd, (long long)beta * next * N, C->ndall_slot[l], C->ndall_prime[l]},
                        false, C->ntt_variant, s);
-            launch_inner_product(T, ext, (long long)beta * next * N, (long long)next * N, acc, acc + (long long)next * N,
-                                 2LL * next * N, C->keys[kidx], 2LL * C->np * N, (long long)C->np * N, cnt, beta,
-                                 next, C->ext_prime[l], s);
+            if (rot)
+                launch_inner_product_rot(T, ext, (long long)beta * next * N, (long long)next * N, acc,
+                                         acc + (long long)next * N, 2LL * next * N, *rot, 2LL * C->np * N,
+                                         (long long)C->np * N, cnt, beta, next, C->ext_prime[l], s);
+            else
+                launch_inner_product(T, ext, (long long)beta * next * N, (long long)next * N, acc,
+                                     acc + (long long)next * N, 2LL * next * N, C->keys[kidx], 2LL * C->np * N,
+                                     (long long)C->np * N, cnt, beta, next, C->ext_prime[l], s);
             // P slots to the coefficient domain, scaled by Phat_m^-1
             launch_ntt(T, VecSet{acc + (long long)(l + 1) * N, cnt * 2 * A, A, (long long)next * N, nullptr, C->pprime},
                        true, C->ntt_variant, s, nullptr, C->md_scale);
@@ -447,9 +461,18 @@ struct Exec {
         return o;
     }
 
-    // rotate-and-sum over every slot (Sec. 3.2): x <- x + rot(x, 2^r)
+    // rotate-and-sum over every slot (Sec. 3.2): x <- x + rot(x, 2^r) one rotation at
+    // a time, or hoisted steps x <- x + sum_r rot(x, a_r)
     Bt rotsum(const Bt &a) {
         Bt o = copy(a);
+        if (C->hoist >= 1) {
+            for (const auto &st : hoist_steps(C->slots, C->hoist)) {
+                const size_t m = C->arena.mark();
+                rotsum_step(o, st);
+                C->arena.release(m);
+            }
+            return o;
+        }
         int lg = 0;
         while ((1 << lg) < C->slots) ++lg;
         for (int r = 0; r < lg; ++r) {
@@ -458,6 +481,30 @@ struct Exec {
             C->arena.release(m);
         }
         return o;
+    }
+
+    // one hoisted step in place: c1 is extended once, each rotation's automorphism
+    // acts on the extended digits inside the key products, one ModDown for all:
+    //   out0 = c0 + sum_r sigma_r(c0) + MD_0,  out1 = c1 + MD_1
+    void rotsum_step(Bt &x, const std::vector<int> &amounts) {
+        const int l = x.level;
+        const long long N = C->N;
+        REQUIRE(!amounts.empty() && (int)amounts.size() <= kMaxHoist, HE_EINVAL, "hoisted step size");
+        RotSet rs{};
+        rs.nr = (int)amounts.size();
+        for (int r = 0; r < rs.nr; ++r) {
+            auto it = C->rot_key.find(amounts[r]);
+            REQUIRE(it != C->rot_key.end(), HE_ESTATE, "no key for a hoisted rotation");
+            rs.key[r] = C->keys[it->second];
+            rs.g[r] = C->key_gal[it->second];
+        }
+        double *s0 = alloc_d((size_t)x.cnt * (l + 1) * N);
+        if (go())
+            launch_autsum(T, VecSet{s0, x.cnt * (l + 1), l + 1, (long long)(l + 1) * N, nullptr, nullptr},
+                          VecSet{x.d, x.cnt * (l + 1), l + 1, 2LL * x.cap * N, nullptr, nullptr}, rs, s);
+        keyswitch(x.d + (long long)x.cap * N, 2LL * x.cap * N, x.cnt, l, -1, x.d, (long long)x.cap * N,
+                  Addend{s0, (long long)(l + 1) * N, 0, 1}, Addend{x.d, 2LL * x.cap * N, (long long)x.cap * N, 2},
+                  &rs);
     }
 
     Bt power(const Bt &y, int p) {
@@ -863,6 +910,51 @@ void build_ctx(he_ctx *C, const he_params *prm) {
     }
 }
 
+// Rotation amounts of the hoisted rotate-and-sum steps with radix 2^h over
+// log2(slots) bits: step b covers bits [b, b + hb), hb = min(h, bits left), and
+// rotates by r 2^b for r = 1 .. 2^hb - 1.
+std::vector<std::vector<int>> hoist_steps(int slots, int h) {
+    int lg = 0;
+    while ((1 << lg) < slots) ++lg;
+    std::vector<std::vector<int>> out;
+    for (int b = 0; b < lg;) {
+        const int hb = std::min(h, lg - b);
+        std::vector<int> st;
+        for (int r = 1; r < (1 << hb); ++r) st.push_back(r << b);
+        out.push_back(st);
+        b += hb;
+    }
+    return out;
+}
+
+// Key plan: index 0 relinearisation; 1 + e rotation by 2^e for every e <
+// log2(slots); then, in step order, every other amount of the hoisted steps.
+// The Galois element of a rotation by a slots is 5^a mod 2N.
+void plan_rotation_keys(he_ctx *C) {
+    int lg = 0;
+    while ((1 << lg) < C->slots) ++lg;
+    const uint64_t M = 2ull * C->N;
+    auto gal = [M](int a) {
+        uint64_t g = 1, b = 5;
+        for (uint64_t e = (uint64_t)a; e; e >>= 1, b = (b * b) % M)
+            if (e & 1) g = (g * b) % M;
+        return (uint32_t)g;
+    };
+    C->rot_key.clear();
+    C->key_gal.assign(1, 0u);
+    for (int e = 0; e < lg; ++e) {
+        C->rot_key[1 << e] = (int)C->key_gal.size();
+        C->key_gal.push_back(gal(1 << e));
+    }
+    if (C->hoist >= 1)
+        for (const auto &st : hoist_steps(C->slots, C->hoist))
+            for (int a : st)
+                if (!C->rot_key.count(a)) {
+                    C->rot_key[a] = (int)C->key_gal.size();
+                    C->key_gal.push_back(gal(a));
+                }
+}
+
 // secret key and every evaluation key, generated on the device
 void keygen(he_ctx *C) {
     const int N = C->N, np = C->np;
@@ -879,19 +971,14 @@ void keygen(he_ctx *C) {
     launch_sample_small(dsmall, N, C->seed, OBJ_SK, 0, s);
     launch_small_to_res(T, all_sk, dsmall, nullptr, s);
     launch_ntt(T, all_sk, false, 0, s);
-    int lg = 0;
-    while ((1 << lg) < C->slots) ++lg;
-    const int nkeys = 1 + lg;
+    plan_rotation_keys(C);
+    const int nkeys = (int)C->key_gal.size();
     C->keys.assign(nkeys, nullptr);
     const size_t per = (size_t)np * N;
     for (int k = 0; k < nkeys; ++k) {
         HIPCHK(hipMalloc(&C->keys[k], 8ull * C->betaL * 2 * per));
         if (k == 0) launch_square_res(T, tg, C->d_sk, np, s);
-        else {
-            uint64_t g = 5;
-            for (int i = 0; i < k - 1; ++i) g = (g * g) % (2ull * N);
-            launch_automorph(T, VecSet{tg, np, np, 0, nullptr, nullptr}, all_sk, g, s);
-        }
+        else launch_automorph(T, VecSet{tg, np, np, 0, nullptr, nullptr}, all_sk, C->key_gal[k], s);
         for (int j = 0; j < C->betaL; ++j) {
             const uint32_t oa = OBJ_KEY_A | ((uint32_t)k << 8) | (uint32_t)j;
             const uint32_t oe = OBJ_KEY_E | ((uint32_t)k << 8) | (uint32_t)j;
@@ -1194,6 +1281,8 @@ int he_ctx_create(const he_params *prm, he_ctx **out) {
         REQUIRE(C->np <= kMaxPrimes && C->alpha <= 16, HE_EINVAL, "too many primes (alpha <= 16)");
         C->betaL = ((int)prm->n_q + C->alpha - 1) / C->alpha;
         REQUIRE(C->betaL <= 8, HE_EINVAL, "at most 8 digits");
+        REQUIRE(prm->hoist <= 4, HE_EINVAL, "hoist must be 0..4");
+        C->hoist = (int)prm->hoist;
         C->Delta = std::ldexp(1.0, 0) * std::pow(2.0, prm->log2_scale);
         C->seed = prm->seed;
         C->device = prm->device;

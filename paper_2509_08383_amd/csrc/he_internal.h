@@ -129,6 +129,18 @@ void launch_inner_product(const DevTables &T, const double *ext, long long estri
                           long long estride_j, double *acc0, double *acc1, long long astride,
                           const double *key, long long kstride_j, long long kstride_c, int cnt,
                           int beta, int next, const int *ext_prime, hipStream_t s);
+// rotations of one hoisted rotate-and-sum step: key and Galois element of each
+constexpr int kMaxHoist = 15;
+struct RotSet {
+    const double *key[kMaxHoist];
+    uint32_t g[kMaxHoist];
+    int nr;
+};
+void launch_inner_product_rot(const DevTables &T, const double *ext, long long estride_b, long long estride_j,
+                              double *acc0, double *acc1, long long astride, const RotSet &rs, long long kstride_j,
+                              long long kstride_c, int cnt, int beta, int next, const int *ext_prime, hipStream_t s);
+// out = in + sum_r sigma_r(in) on NTT-domain limbs
+void launch_autsum(const DevTables &T, const VecSet &out, const VecSet &in, const RotSet &rs, hipStream_t s);
 void launch_moddown_conv(const DevTables &T, const double *acc, long long astride, double *conv,
                          long long cstride, int groups, int level, const double *phat, hipStream_t s);
 void launch_sample_uniform(const DevTables &T, const VecSet &out, uint64_t seed, uint32_t obj,

@@ -185,17 +185,19 @@ void launch_tensor(const DevTables &T, double *d0, double *d1, double *d2, long 
 }
 
 // NTT-domain Galois automorphism X -> X^g: out[j] = in[j'] with
-// 2 bitrev(j') + 1 = (2 bitrev(j) + 1) g mod 2N
+// 2 bitrev(j') + 1 = (2 bitrev(j) + 1) g mod 2N.  2N divides 2^32, so the
+// product is taken modulo 2^32 and masked.
+DEV unsigned aut_src(unsigned j, uint32_t g, int logN) {
+    const int sh = 32 - logN;
+    const uint32_t t = 2u * (__brev(j) >> sh) + 1u;
+    const uint32_t t2 = (t * g) & ((2u << logN) - 1u);
+    return __brev((t2 - 1u) >> 1) >> sh;
+}
 __global__ void k_automorph(VecSet out, VecSet in, uint64_t galois, DevTables T) {
     EW_PROLOGUE
     double *pi; int q1, g1, r1;
     vs_at(in, blockIdx.y, T.N, pi, q1, g1, r1);
-    const int sh = 32 - T.logN;
-    const uint64_t M = 2ull * T.N;
-    const uint64_t t = 2ull * (__brev((unsigned)x) >> sh) + 1ull;
-    const uint64_t t2 = (t * galois) & (M - 1);
-    const unsigned j2 = __brev((unsigned)((t2 - 1) >> 1)) >> sh;
-    po[x] = pi[j2];
+    po[x] = pi[aut_src((unsigned)x, (uint32_t)galois, T.logN)];
 }
 void launch_automorph(const DevTables &T, const VecSet &out, const VecSet &in, uint64_t galois,
                       hipStream_t s) {
@@ -345,6 +347,73 @@ void launch_inner_product(const DevTables &T, const double *ext, long long estri
     KL("k_inner_product", k_inner_product, dim3((T.N + 255) / 256, next), dim3(256), 0, s, T, ext,
                        estride_b, estride_j, acc0, acc1, astride, key, kstride_j, kstride_c, cnt,
                        beta, ext_prime);
+}
+
+// Inner product of a hoisted rotate-and-sum step: for rotation r with Galois
+// element g_r and key K_r, acc_c[ct][t][x] = sum_r sum_j ext[ct][j][t][src_r(x)]
+// K_r[j][c][prime(t)][x], the automorphism of the NTT-domain extended digits being
+// a gather (src_r = aut_src).  The partial sums are reduced after every rotation,
+// so |sum| <= p/2 + beta (p/2 + 2^44) < 2^52 for beta <= 8.
+__global__ __launch_bounds__(256) void k_inner_product_rot(DevTables T, const double *__restrict__ ext,
+                                                           long long esb, long long esj, double *__restrict__ acc0,
+                                                           double *__restrict__ acc1, long long astride, RotSet rs,
+                                                           long long ksj, long long ksc, int cnt, int beta,
+                                                           const int *__restrict__ ext_prime) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= T.N) return;
+    const int t = blockIdx.y;
+    const int pt = ext_prime[t];
+    const double p = T.p[pt], pinv = T.pinv[pt];
+    const long long ko = (long long)pt * T.N + x;
+    for (int ct = 0; ct < cnt; ++ct) {
+        const double *E = ext + ct * esb + (long long)t * T.N;
+        double s0 = 0.0, s1 = 0.0;
+        for (int r = 0; r < rs.nr; ++r) {
+            const unsigned src = aut_src((unsigned)x, rs.g[r], T.logN);
+            const double *K = rs.key[r];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if (j < beta) {
+                    const double e = E[j * esj + src];
+                    s0 += mm(e, K[j * ksj + ko], p, pinv);
+                    s1 += mm(e, K[j * ksj + ksc + ko], p, pinv);
+                }
+            }
+            s0 = red(s0, p, pinv);
+            s1 = red(s1, p, pinv);
+        }
+        acc0[ct * astride + (long long)t * T.N + x] = canon(s0, p, pinv);
+        acc1[ct * astride + (long long)t * T.N + x] = canon(s1, p, pinv);
+    }
+}
+void launch_inner_product_rot(const DevTables &T, const double *ext, long long estride_b, long long estride_j,
+                              double *acc0, double *acc1, long long astride, const RotSet &rs, long long kstride_j,
+                              long long kstride_c, int cnt, int beta, int next, const int *ext_prime, hipStream_t s) {
+    if (cnt <= 0) return;
+    // every rotation's key words once, the extended digits once per rotation and
+    // both accumulators, per ciphertext
+    kprof_set_bytes(8.0 * T.N * next * (2.0 * beta * rs.nr + cnt * (beta * rs.nr + 2.0)));
+    KL("k_inner_product_rot", k_inner_product_rot, dim3((T.N + 255) / 256, next), dim3(256), 0, s, T, ext,
+       estride_b, estride_j, acc0, acc1, astride, rs, kstride_j, kstride_c, cnt, beta, ext_prime);
+}
+
+// out = in + sum_r sigma_r(in): the c0 part of a hoisted rotate-and-sum step
+__global__ void k_autsum(VecSet out, VecSet in, RotSet rs, DevTables T) {
+    EW_PROLOGUE
+    double *pi; int q1, g1, r1;
+    vs_at(in, blockIdx.y, T.N, pi, q1, g1, r1);
+    const double pinv = T.pinv[pr];
+    double v = pi[x];
+    for (int r = 0; r < rs.nr; ++r) {
+        v += pi[aut_src((unsigned)x, rs.g[r], T.logN)];
+        if ((r & 3) == 3) v = red(v, p, pinv);
+    }
+    po[x] = canon(v, p, pinv);
+}
+void launch_autsum(const DevTables &T, const VecSet &out, const VecSet &in, const RotSet &rs, hipStream_t s) {
+    if (out.count <= 0) return;
+    kprof_set_bytes(8.0 * T.N * out.count * (2.0 + rs.nr));
+    KL("k_autsum", k_autsum, ew_grid(T, out.count), dim3(256), 0, s, out, in, rs, T);
 }
 
 // ModDown conversion: the P slots of acc hold w_m = [acc_{P,m} * Phat_m^-1]_{p_m}

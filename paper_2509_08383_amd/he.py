@@ -37,7 +37,7 @@ class _Params(ctypes.Structure):
     _fields_ = [("log_n", ctypes.c_uint32), ("n_q", ctypes.c_uint32), ("q0_bits", ctypes.c_uint32),
                 ("q_bits", ctypes.c_uint32), ("p_bits", ctypes.c_uint32), ("dnum", ctypes.c_uint32),
                 ("log2_scale", ctypes.c_double), ("seed", ctypes.c_uint64), ("device", ctypes.c_int),
-                ("stream", _V)]
+                ("stream", _V), ("hoist", ctypes.c_uint32)]
 
 
 class _Cfg(ctypes.Structure):
@@ -124,11 +124,12 @@ class Params:
     dnum: int
     log2_scale: float
     seed: int = 1
+    hoist: int = 0  # rotate-and-sum: 0 one rotation at a time, h = hoisted radix-2^h steps
 
 
 # parameter sets: a non-secure toy chain at N = 2^12 and the 128-bit chain at N = 2^16
-TOY = Params(log_n=12, n_q=36, q0_bits=40, q_bits=30, p_bits=40, dnum=3, log2_scale=30, seed=7)
-SECURE = Params(log_n=16, n_q=30, q0_bits=49, q_bits=40, p_bits=49, dnum=3, log2_scale=40, seed=11)
+TOY = Params(log_n=12, n_q=36, q0_bits=40, q_bits=30, p_bits=40, dnum=3, log2_scale=30, seed=7, hoist=3)
+SECURE = Params(log_n=16, n_q=30, q0_bits=49, q_bits=40, p_bits=49, dnum=3, log2_scale=40, seed=11, hoist=3)
 
 
 @dataclass
@@ -209,7 +210,7 @@ class Context:
 
     def __init__(self, prm: Params, device: int = 0, stream: Optional[int] = None):
         P = _Params(prm.log_n, prm.n_q, prm.q0_bits, prm.q_bits, prm.p_bits, prm.dnum, float(prm.log2_scale),
-                    prm.seed, device, stream)
+                    prm.seed, device, stream, prm.hoist)
         h = _V()
         _check(lib().he_ctx_create(ctypes.byref(P), ctypes.byref(h)))
         self.h = h

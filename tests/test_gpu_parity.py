@@ -22,7 +22,7 @@ def say(*a):
 
 def _oracle_params(p):
     return ckks.Params(log_n=p.log_n, n_q=p.n_q, q0_bits=p.q0_bits, q_bits=p.q_bits, p_bits=p.p_bits,
-                       dnum=p.dnum, log2_scale=p.log2_scale, seed=p.seed)
+                       dnum=p.dnum, log2_scale=p.log2_scale, seed=p.seed, hoist=p.hoist)
 
 
 class Pair:
@@ -161,6 +161,20 @@ def test_ntt_variants_bit_exact(toy, variant):
 def test_rotsum_bit_exact(toy):
     gx, ox, _, _ = _pairs_of_ops(toy)
     toy.same(toy.G.rotsum(gx), toy.O.rotsum(ox), "rotsum")
+
+
+@pytest.mark.parametrize("h", [0, 1, 2])
+def test_rotsum_hoisting_variants_bit_exact(h):
+    """rotate-and-sum one rotation at a time (h = 0) and in hoisted radix-2^h steps, on a
+    short chain (8 Q primes, alpha = 3) at the top level and with a partial last digit"""
+    from paper_2509_08383_amd import he
+    say(f"[gpu] rotsum hoist={h}")
+    P = Pair(he.Params(log_n=12, n_q=8, q0_bits=40, q_bits=30, p_bits=40, dnum=3, log2_scale=30, seed=9, hoist=h))
+    z = np.random.default_rng(50 + h).uniform(-1, 1, P.O.slots)
+    gx, ox = P.enc_values(z)
+    P.same(P.G.rotsum(gx), P.O.rotsum(ox), f"rotsum h={h}")
+    P.same(P.G.rotsum(P.G.drop(gx, 4)), P.O.rotsum(P.O.drop(ox, 4)), f"rotsum h={h} level 4")
+    np.testing.assert_allclose(P.O.decrypt(P.O.rotsum(ox)), z.sum(), atol=1e-2)
 
 
 def toy_cfg(n, T=4):

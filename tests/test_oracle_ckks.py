@@ -1,5 +1,6 @@
 """Pins of the CPU RNS-CKKS oracle (O2) against textbook definitions and the CKKS
 properties the paper relies on (Sec. 2.1 correctness/homomorphism; Sec. 3.2 rotations)."""
+import dataclasses
 import math
 import os
 
@@ -149,6 +150,36 @@ def test_rotsum(toy):
     x = np.random.default_rng(4).uniform(-1, 1, toy.slots)
     s = toy.decrypt(toy.rotsum(toy.encrypt(x)))
     np.testing.assert_allclose(s, x.sum(), atol=1e-3)
+
+
+@pytest.mark.parametrize("h", [1, 2, 3])
+def test_hoist_plan_covers_every_shift_once(h):
+    """picking one amount (or none) per step of the hoisted plan gives every shift
+    0..slots-1 exactly once, which is what makes the steps a rotate-and-sum"""
+    for slots in (2, 8, 512, 2048, 32768):
+        sums = [0]
+        for step in ckks.hoist_steps(slots, h):
+            sums = [s + a for s in sums for a in [0] + step]
+        assert sorted(sums) == list(range(slots))
+        keys = ckks.rotation_keys(slots, h)
+        lg = int(math.log2(slots))
+        assert all(keys[1 << e] == 1 + e for e in range(lg))
+        assert sorted(keys.values()) == list(range(1, 1 + len(keys)))
+
+
+@pytest.mark.parametrize("h", [1, 2, 3])
+def test_hoisted_rotsum_gives_the_slot_sum(h):
+    O = ckks.Oracle(dataclasses.replace(TOY, hoist=h))
+    O.keygen_cutmax()
+    x = np.random.default_rng(40 + h).uniform(-1, 1, O.slots)
+    cx = O.encrypt(x)
+    np.testing.assert_allclose(O.decrypt(O.rotsum(cx)), x.sum(), atol=1e-3)
+    # one step on its own, at a level with a partial last digit
+    keys = ckks.rotation_keys(O.slots, h)
+    amounts = ckks.hoist_steps(O.slots, h)[0]
+    d = O.drop(cx, 4)
+    want = x + sum(np.roll(x, -a) for a in amounts)
+    np.testing.assert_allclose(O.decrypt(O.rotsum_step(d, amounts, keys)), want, atol=1e-4)
 
 
 def test_tampered_limb_is_detected(toy):
