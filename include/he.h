@@ -159,8 +159,9 @@ int he_ct_export(he_ctx *ctx, const he_ct *ct, uint64_t *limbs, size_t cap);
 int he_ct_import(he_ctx *ctx, const uint64_t *limbs, uint32_t a, uint32_t level, double scale,
                  size_t n, he_ct **out);
 
-/* Evaluator primitives (single ciphertexts, a == 1), each the CKKS operation
- * the encrypted schedule is made of (scales as documented in the design):
+/* Evaluator primitives (single ciphertexts, a == 1, except he_rotsum and he_drop,
+ * which act on every ciphertext of a handle independently), each the CKKS
+ * operation the encrypted schedule is made of:
  *   he_add, he_sub        element-wise (Sec. 2.1)
  *   he_mul_int            multiply by an integer
  *   he_add_const          add a real constant to every slot

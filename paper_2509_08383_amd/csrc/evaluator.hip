@@ -1230,13 +1230,14 @@ int cutmax_impl(he_ctx *C, he_ct *const *in, he_ct *const *noise, size_t batch, 
     return HE_OK;
 }
 
-// single-ciphertext evaluator primitive
+// evaluator primitive on a single ciphertext, or (multi) on every ciphertext of a
+// handle independently
 template <class F>
-int prim(he_ctx *C, const he_ct *a, he_ct **out, F &&f) {
+int prim(he_ctx *C, const he_ct *a, he_ct **out, F &&f, bool multi = false) {
     return guarded([&]() {
         REQUIRE(C && a && out && a->ctx == C, HE_EINVAL, "null or foreign argument");
-        REQUIRE(a->a == 1, HE_EINVAL, "primitive ops take single ciphertexts");
-        he_ct *o = new_ct(C, 1);
+        REQUIRE(a->a == 1 || multi, HE_EINVAL, "primitive ops take single ciphertexts");
+        he_ct *o = new_ct(C, a->a);
         o->n = a->n;
         try {
             run2(C, [&](Exec &X) {
@@ -1554,10 +1555,10 @@ int he_rotate(he_ctx *C, const he_ct *a, uint32_t r, he_ct **out) {
     return prim(C, a, out, [&](Exec &X) { return X.rotate(bt_of(a), (int)r); });
 }
 int he_rotsum(he_ctx *C, const he_ct *a, he_ct **out) {
-    return prim(C, a, out, [&](Exec &X) { return X.rotsum(bt_of(a)); });
+    return prim(C, a, out, [&](Exec &X) { return X.rotsum(bt_of(a)); }, true);
 }
 int he_drop(he_ctx *C, const he_ct *a, uint32_t level, he_ct **out) {
-    return prim(C, a, out, [&](Exec &X) { return X.copy(X.drop(bt_of(a), (int)level)); });
+    return prim(C, a, out, [&](Exec &X) { return X.copy(X.drop(bt_of(a), (int)level)); }, true);
 }
 
 int he_bench_ntt(he_ctx *C, uint32_t vectors, uint32_t iters, double *ms_fwd, double *ms_inv) {

@@ -386,15 +386,84 @@ __global__ __launch_bounds__(256) void k_inner_product_rot(DevTables T, const do
         acc1[ct * astride + (long long)t * T.N + x] = canon(s1, p, pinv);
     }
 }
+// The same products with every key word of the step held in registers (NR
+// rotations, at most 3 digits) and reused for every ciphertext of the batch.  The
+// grid is one-dimensional and XCD-aware: the 8 XCDs take workgroups round-robin
+// (workgroup b runs on XCD b mod 8), and every XCD is given whole targets t, all
+// x-blocks of a target one after the other, so the gathered words of a target's
+// extended digits are re-read from that XCD's L2 rather than from HBM.
+template <int NR>
+__global__ __launch_bounds__(256) void k_inner_product_rot_reg(DevTables T, const double *__restrict__ ext,
+                                                               long long esb, long long esj,
+                                                               double *__restrict__ acc0, double *__restrict__ acc1,
+                                                               long long astride, RotSet rs, long long ksj,
+                                                               long long ksc, int cnt, int beta, int next,
+                                                               const int *__restrict__ ext_prime, int xblocks) {
+    const int b = blockIdx.x, slot = b >> 3;
+    const int t = (b & 7) + 8 * (slot / xblocks);
+    if (t >= next) return;
+    const int x = (slot % xblocks) * blockDim.x + threadIdx.x;
+    if (x >= T.N) return;
+    const int pt = ext_prime[t];
+    const double p = T.p[pt], pinv = T.pinv[pt];
+    const long long ko = (long long)pt * T.N + x;
+    double k0[NR][3], k1[NR][3];
+    unsigned src[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        src[r] = aut_src((unsigned)x, rs.g[r], T.logN);
+        const double *K = rs.key[r];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            k0[r][j] = j < beta ? K[j * ksj + ko] : 0.0;
+            k1[r][j] = j < beta ? K[j * ksj + ksc + ko] : 0.0;
+        }
+    }
+    for (int ct = 0; ct < cnt; ++ct) {
+        const double *E = ext + ct * esb + (long long)t * T.N;
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                if (j < beta) {
+                    const double e = E[j * esj + src[r]];
+                    s0 += mm(e, k0[r][j], p, pinv);
+                    s1 += mm(e, k1[r][j], p, pinv);
+                }
+            }
+            s0 = red(s0, p, pinv);
+            s1 = red(s1, p, pinv);
+        }
+        acc0[ct * astride + (long long)t * T.N + x] = canon(s0, p, pinv);
+        acc1[ct * astride + (long long)t * T.N + x] = canon(s1, p, pinv);
+    }
+}
+
 void launch_inner_product_rot(const DevTables &T, const double *ext, long long estride_b, long long estride_j,
                               double *acc0, double *acc1, long long astride, const RotSet &rs, long long kstride_j,
                               long long kstride_c, int cnt, int beta, int next, const int *ext_prime, hipStream_t s) {
     if (cnt <= 0) return;
-    // every rotation's key words once, the extended digits once per rotation and
-    // both accumulators, per ciphertext
-    kprof_set_bytes(8.0 * T.N * next * (2.0 * beta * rs.nr + cnt * (beta * rs.nr + 2.0)));
-    KL("k_inner_product_rot", k_inner_product_rot, dim3((T.N + 255) / 256, next), dim3(256), 0, s, T, ext,
-       estride_b, estride_j, acc0, acc1, astride, rs, kstride_j, kstride_c, cnt, beta, ext_prime);
+    // every rotation's key words once; the extended digits and both accumulators
+    // once per ciphertext
+    kprof_set_bytes(8.0 * T.N * next * (2.0 * beta * rs.nr + cnt * (beta + 2.0)));
+    const int xblocks = (T.N + 255) / 256;
+    const dim3 g1(8 * ((next + 7) / 8) * xblocks);
+    // one ciphertext: the key stream alone bounds the kernel, and the lighter
+    // generic kernel keeps more loads in flight
+    const bool reg = cnt >= 2 && beta <= 3;
+    if (reg && rs.nr == 7)
+        KL("k_inner_product_rot", k_inner_product_rot_reg<7>, g1, dim3(256), 0, s, T, ext, estride_b, estride_j, acc0,
+           acc1, astride, rs, kstride_j, kstride_c, cnt, beta, next, ext_prime, xblocks);
+    else if (reg && rs.nr == 3)
+        KL("k_inner_product_rot", k_inner_product_rot_reg<3>, g1, dim3(256), 0, s, T, ext, estride_b, estride_j, acc0,
+           acc1, astride, rs, kstride_j, kstride_c, cnt, beta, next, ext_prime, xblocks);
+    else if (reg && rs.nr == 1)
+        KL("k_inner_product_rot", k_inner_product_rot_reg<1>, g1, dim3(256), 0, s, T, ext, estride_b, estride_j, acc0,
+           acc1, astride, rs, kstride_j, kstride_c, cnt, beta, next, ext_prime, xblocks);
+    else
+        KL("k_inner_product_rot", k_inner_product_rot, dim3(xblocks, next), dim3(256), 0, s, T, ext, estride_b,
+           estride_j, acc0, acc1, astride, rs, kstride_j, kstride_c, cnt, beta, ext_prime);
 }
 
 // out = in + sum_r sigma_r(in): the c0 part of a hoisted rotate-and-sum step

@@ -175,6 +175,14 @@ def test_rotsum_hoisting_variants_bit_exact(h):
     P.same(P.G.rotsum(gx), P.O.rotsum(ox), f"rotsum h={h}")
     P.same(P.G.rotsum(P.G.drop(gx, 4)), P.O.rotsum(P.O.drop(ox, 4)), f"rotsum h={h} level 4")
     np.testing.assert_allclose(P.O.decrypt(P.O.rotsum(ox)), z.sum(), atol=1e-2)
+    # two ciphertexts in one handle: the batched kernels (keys reused across ciphertexts)
+    m = np.concatenate([ckks.encode(np.random.default_rng(60 + h + k).uniform(-1, 1, P.O.slots), P.O.N, P.O.Delta)
+                        for k in range(2)])
+    g2 = P.G.encrypt_coeffs(m, P.O.Delta, 2 * P.G.slots)
+    o2 = [P.O.encrypt_coeffs(m[k * P.O.N:(k + 1) * P.O.N], P.O.Delta) for k in range(2)]
+    eg = P.G.export(P.G.rotsum(g2))
+    for k in range(2):
+        assert int((eg[k] != P.O.rotsum(o2[k]).export()).sum()) == 0, f"rotsum h={h} batch ct {k}"
 
 
 def toy_cfg(n, T=4):
