@@ -15,6 +15,7 @@ Prints one JSON line.  --gpus N > 1 is not supported (one GPU per box).
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import math
@@ -113,6 +114,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--graph", type=int, default=0)
+    ap.add_argument("--hoist", type=int, default=None,
+                    help="rotate-and-sum radix log2 (default: the parameter set's)")
     ap.add_argument("--cpu-T", type=int, default=3, help="iterations of the oracle sample (1..3)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -127,7 +130,8 @@ def main():
     assert torch.cuda.is_available(), "no GPU"
     digest = src_digest()
     log("[bench] context N=2^16")
-    ctx = he.Context(he.SECURE, device=0)
+    prm = he.SECURE if args.hoist is None else dataclasses.replace(he.SECURE, hoist=args.hoist)
+    ctx = he.Context(prm, device=0)
     if args.graph:
         ctx.set_option(he.HE_OPT_GRAPH, 1)
     cfg = cfg_secure(he)
@@ -222,7 +226,6 @@ def main():
     if not args.no_cpu_baseline:
         from oracle import ckks
         from oracle.cutmax_fp64 import chebyshev_invsqrt, slot_layout
-        prm = he.SECURE
         O = ckks.Oracle(ckks.Params(prm.log_n, prm.n_q, prm.q0_bits, prm.q_bits, prm.p_bits, prm.dnum,
                                     prm.log2_scale, prm.seed, prm.hoist))
         O.keygen_cutmax()
@@ -262,6 +265,7 @@ def main():
                                "one ciphertext of 32000 LLM-like logits in 32768 slots, T=3, p=3, c=5",
                    "global_batch": 1, "seq_len": VOCAB2, "parallelism": "none"},
         "device_ms_median": float(np.median(dev_ms)),
+        "rotsum_hoist_log2": prm.hoist,
         "src_digest": digest,
         "argmax_ok": bool(argmax_ok),
         "batched": batch,
