@@ -132,7 +132,7 @@ struct he_ctx {
     double *d_tab = nullptr;
     int *d_itab = nullptr;
     double *d_sk = nullptr;  // [np][N] NTT domain
-    std::vector<double *> keys;
+    std::vector<KeyRef> keys;  // packed 48-bit words (owned)
     // level-indexed conversion tables (device pointers into d_tab / d_itab)
     std::vector<const int *> ext_prime;                 // [L+1] -> [l+1+alpha]
     std::vector<std::vector<const double *>> vinv, qhat;  // [L+1][beta_l]
@@ -973,16 +973,22 @@ void keygen(he_ctx *C) {
     launch_ntt(T, all_sk, false, 0, s);
     plan_rotation_keys(C);
     const int nkeys = (int)C->key_gal.size();
-    C->keys.assign(nkeys, nullptr);
-    const size_t per = (size_t)np * N;
+    C->keys.assign(nkeys, KeyRef{nullptr, nullptr});
+    const size_t per = (size_t)np * N, kw = (size_t)C->betaL * 2 * per;
+    double *tk = nullptr;  // one key as doubles, packed after generation
+    HIPCHK(hipMalloc(&tk, 8ull * kw));
     for (int k = 0; k < nkeys; ++k) {
-        HIPCHK(hipMalloc(&C->keys[k], 8ull * C->betaL * 2 * per));
+        uint32_t *klo = nullptr;
+        uint16_t *khi = nullptr;
+        HIPCHK(hipMalloc(&klo, 4ull * kw));
+        HIPCHK(hipMalloc(&khi, 2ull * kw));
+        C->keys[k] = KeyRef{klo, khi};
         if (k == 0) launch_square_res(T, tg, C->d_sk, np, s);
         else launch_automorph(T, VecSet{tg, np, np, 0, nullptr, nullptr}, all_sk, C->key_gal[k], s);
         for (int j = 0; j < C->betaL; ++j) {
             const uint32_t oa = OBJ_KEY_A | ((uint32_t)k << 8) | (uint32_t)j;
             const uint32_t oe = OBJ_KEY_E | ((uint32_t)k << 8) | (uint32_t)j;
-            double *kb = C->keys[k] + (size_t)j * 2 * per, *ka = kb + per;
+            double *kb = tk + (size_t)j * 2 * per, *ka = kb + per;
             const VecSet va{ka, np, np, 0, nullptr, nullptr}, ve{te, np, np, 0, nullptr, nullptr};
             launch_sample_uniform(T, va, C->seed, oa, nullptr, s);
             launch_ntt(T, va, false, 0, s);
@@ -992,10 +998,11 @@ void keygen(he_ctx *C) {
             const int lo = j * C->alpha, hi = std::min(lo + C->alpha, C->L + 1);
             launch_keyb(T, kb, ka, te, C->d_sk, tg, C->pmod, np, lo, hi, s);
         }
+        launch_pack_key(tk, klo, khi, kw, s);
     }
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipGetLastError());
-    hipFree(dsmall); hipFree(ta); hipFree(te); hipFree(tg);
+    hipFree(dsmall); hipFree(ta); hipFree(te); hipFree(tg); hipFree(tk);
 }
 
 // NTT autotuner: times every workgroup-width variant of the forward + inverse
@@ -1267,9 +1274,9 @@ int he_ctx_create(const he_params *prm, he_ctx **out) {
         REQUIRE(prm && out, HE_EINVAL, "null argument");
         REQUIRE(prm->log_n == 12 || prm->log_n == 16, HE_EINVAL, "log_n must be 12 or 16");
         REQUIRE(prm->n_q >= 2 && prm->n_q <= 48 && prm->dnum >= 1, HE_EINVAL, "n_q in [2,48], dnum >= 1");
-        REQUIRE(prm->q0_bits >= 20 && prm->q0_bits <= 49 && prm->q_bits >= 20 && prm->q_bits <= 49 &&
-                    prm->p_bits >= 20 && prm->p_bits <= 49,
-                HE_EINVAL, "prime sizes must lie in [20, 49] bits");
+        REQUIRE(prm->q0_bits >= 20 && prm->q0_bits <= 48 && prm->q_bits >= 20 && prm->q_bits <= 48 &&
+                    prm->p_bits >= 20 && prm->p_bits <= 48,
+                HE_EINVAL, "prime sizes must lie in [20, 48] bits");
         REQUIRE(prm->log2_scale >= 10 && prm->log2_scale <= 60, HE_EINVAL, "log2_scale out of range");
         auto C = std::make_unique<he_ctx>();
         C->logN = (int)prm->log_n;
@@ -1309,7 +1316,10 @@ void he_ctx_destroy(he_ctx *C) {
     hipSetDevice(C->device);
     if (C->stream) hipStreamSynchronize(C->stream);
     for (auto &g : C->graphs) hipGraphExecDestroy(g.second);
-    for (double *k : C->keys) hipFree(k);
+    for (const KeyRef &k : C->keys) {
+        hipFree(const_cast<uint32_t *>(k.lo));
+        hipFree(const_cast<uint16_t *>(k.hi));
+    }
     hipFree(C->d_sk); hipFree(C->d_tab); hipFree(C->d_itab);
     if (C->arena.base) hipFree(C->arena.base);
     if (C->pool.d_dv) hipFree(C->pool.d_dv);

@@ -47,6 +47,13 @@ struct ConstTab {
     int stride;
 };
 
+// An evaluation key [beta][2][np][N] of residues below 2^48, stored as two planes:
+// the low 32 bits and the high 16 bits of every word (6 bytes a word).
+struct KeyRef {
+    const uint32_t *lo;
+    const uint16_t *hi;
+};
+
 // optional per-kernel profiler: when set, every launch is bracketed by HIP
 // events on its stream (see he_profile_begin / he_profile_end)
 struct KProf;
@@ -127,12 +134,14 @@ void launch_modup(const DevTables &T, const double *v, long long vstride, double
                   const int *ext_prime, const ModUpDigits &dg, hipStream_t s);
 void launch_inner_product(const DevTables &T, const double *ext, long long estride_b,
                           long long estride_j, double *acc0, double *acc1, long long astride,
-                          const double *key, long long kstride_j, long long kstride_c, int cnt,
+                          KeyRef key, long long kstride_j, long long kstride_c, int cnt,
                           int beta, int next, const int *ext_prime, hipStream_t s);
+void launch_pack_key(const double *src, uint32_t *lo, uint16_t *hi, size_t n, hipStream_t s);
+
 // rotations of one hoisted rotate-and-sum step: key and Galois element of each
 constexpr int kMaxHoist = 15;
 struct RotSet {
-    const double *key[kMaxHoist];
+    KeyRef key[kMaxHoist];
     uint32_t g[kMaxHoist];
     int nr;
 };

@@ -305,10 +305,25 @@ void launch_modup(const DevTables &T, const double *v, long long vstride, double
                     beta, next, ext_prime, dg);
 }
 
+// key word i of a packed key: hi 2^32 + lo, exact (below 2^48)
+DEV double key_at(const KeyRef &k, long long i) { return __builtin_fma((double)k.hi[i], 4294967296.0, (double)k.lo[i]); }
+
+__global__ void k_pack_key(const double *__restrict__ src, uint32_t *__restrict__ lo, uint16_t *__restrict__ hi,
+                           size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const uint64_t v = (uint64_t)src[i];
+        lo[i] = (uint32_t)v;
+        hi[i] = (uint16_t)(v >> 32);
+    }
+}
+void launch_pack_key(const double *src, uint32_t *lo, uint16_t *hi, size_t n, hipStream_t s) {
+    KL("k_pack_key", k_pack_key, dim3(4096), dim3(256), 0, s, src, lo, hi, n);
+}
+
 // acc_c[ct][t] = sum_j ext[ct][j][t] * key[j][c][prime(t)]; the key words are
 // read once per (t, x) and reused for every ciphertext of the batch.
 __global__ void k_inner_product(DevTables T, const double *ext, long long esb, long long esj,
-                                double *acc0, double *acc1, long long astride, const double *key,
+                                double *acc0, double *acc1, long long astride, KeyRef key,
                                 long long ksj, long long ksc, int cnt, int beta, const int *ext_prime) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= T.N) return;
@@ -319,8 +334,8 @@ __global__ void k_inner_product(DevTables T, const double *ext, long long esb, l
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         if (j < beta) {
-            k0[j] = key[j * ksj + (long long)pt * T.N + x];
-            k1[j] = key[j * ksj + ksc + (long long)pt * T.N + x];
+            k0[j] = key_at(key, j * ksj + (long long)pt * T.N + x);
+            k1[j] = key_at(key, j * ksj + ksc + (long long)pt * T.N + x);
         }
     }
     for (int ct = 0; ct < cnt; ++ct) {
@@ -339,7 +354,7 @@ __global__ void k_inner_product(DevTables T, const double *ext, long long esb, l
 }
 void launch_inner_product(const DevTables &T, const double *ext, long long estride_b,
                           long long estride_j, double *acc0, double *acc1, long long astride,
-                          const double *key, long long kstride_j, long long kstride_c, int cnt,
+                          KeyRef key, long long kstride_j, long long kstride_c, int cnt,
                           int beta, int next, const int *ext_prime, hipStream_t s) {
     if (cnt <= 0) return;
     // key words once, extended digits and both accumulators per ciphertext
@@ -370,13 +385,13 @@ __global__ __launch_bounds__(256) void k_inner_product_rot(DevTables T, const do
         double s0 = 0.0, s1 = 0.0;
         for (int r = 0; r < rs.nr; ++r) {
             const unsigned src = aut_src((unsigned)x, rs.g[r], T.logN);
-            const double *K = rs.key[r];
+            const KeyRef K = rs.key[r];
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 if (j < beta) {
                     const double e = E[j * esj + src];
-                    s0 += mm(e, K[j * ksj + ko], p, pinv);
-                    s1 += mm(e, K[j * ksj + ksc + ko], p, pinv);
+                    s0 += mm(e, key_at(K, j * ksj + ko), p, pinv);
+                    s1 += mm(e, key_at(K, j * ksj + ksc + ko), p, pinv);
                 }
             }
             s0 = red(s0, p, pinv);
@@ -412,11 +427,11 @@ __global__ __launch_bounds__(256) void k_inner_product_rot_reg(DevTables T, cons
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         src[r] = aut_src((unsigned)x, rs.g[r], T.logN);
-        const double *K = rs.key[r];
+        const KeyRef K = rs.key[r];
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            k0[r][j] = j < beta ? K[j * ksj + ko] : 0.0;
-            k1[r][j] = j < beta ? K[j * ksj + ksc + ko] : 0.0;
+            k0[r][j] = j < beta ? key_at(K, j * ksj + ko) : 0.0;
+            k1[r][j] = j < beta ? key_at(K, j * ksj + ksc + ko) : 0.0;
         }
     }
     for (int ct = 0; ct < cnt; ++ct) {

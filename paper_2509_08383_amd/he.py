@@ -129,7 +129,7 @@ class Params:
 
 # parameter sets: a non-secure toy chain at N = 2^12 and the 128-bit chain at N = 2^16
 TOY = Params(log_n=12, n_q=36, q0_bits=40, q_bits=30, p_bits=40, dnum=3, log2_scale=30, seed=7, hoist=3)
-SECURE = Params(log_n=16, n_q=30, q0_bits=49, q_bits=40, p_bits=49, dnum=3, log2_scale=40, seed=11, hoist=3)
+SECURE = Params(log_n=16, n_q=30, q0_bits=48, q_bits=40, p_bits=48, dnum=3, log2_scale=40, seed=11, hoist=3)
 
 
 @dataclass
