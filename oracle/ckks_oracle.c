@@ -588,20 +588,18 @@ static void moddown(const oc_ctx *C, int l, uint64_t *acc0, uint64_t *acc1, cons
     free(phinv);
 }
 
-/* hybrid key switch of d (level l, coefficient domain) with key kidx.
- * out0/out1: [l+1][N] coefficient domain. */
-static int keyswitch(const oc_ctx *C, const uint64_t *d, int l, int kidx, uint64_t *out0, uint64_t *out1) {
+/* key products of a key switch of d (level l, coefficient domain) with key kidx:
+ * acc0/acc1 [l+1+alpha][N] (zeroed by the caller) receive sum_j ModUp_j(d) key_j in the
+ * NTT domain; gidx[l+1+alpha] gets the global prime index of each extended limb */
+static int ks_products(const oc_ctx *C, const uint64_t *d, int l, int kidx, uint64_t *acc0, uint64_t *acc1,
+                       int *gidx) {
     const uint64_t *K = C->keys[kidx];
     if (!K) return -1;
     int N = C->N, nq = l + 1, A = C->alpha, next = nq + A;
     int beta = n_digits(C, l);
     size_t per = (size_t)C->np * N;
-    /* global prime index of extended limb k */
-    int *gidx = (int *)malloc(sizeof(int) * next);
     for (int k = 0; k < nq; k++) gidx[k] = k;
     for (int m = 0; m < A; m++) gidx[nq + m] = C->L + 1 + m;
-    uint64_t *acc0 = (uint64_t *)calloc((size_t)next * N, 8);
-    uint64_t *acc1 = (uint64_t *)calloc((size_t)next * N, 8);
     for (int j = 0; j < beta; j++) {
         int lo = j * A, hi = lo + A; if (hi > nq) hi = nq;
         int dl = hi - lo;
@@ -645,9 +643,90 @@ static int keyswitch(const oc_ctx *C, const uint64_t *d, int l, int kidx, uint64
         }
         free(qhinv); free(vv);
     }
-    moddown(C, l, acc0, acc1, gidx, out0, out1);
-    free(acc0); free(acc1); free(gidx);
     return 0;
+}
+
+/* hybrid key switch of d (level l, coefficient domain) with key kidx.
+ * out0/out1: [l+1][N] coefficient domain. */
+static int keyswitch(const oc_ctx *C, const uint64_t *d, int l, int kidx, uint64_t *out0, uint64_t *out1) {
+    int N = C->N, next = l + 1 + C->alpha;
+    int *gidx = (int *)malloc(sizeof(int) * next);
+    uint64_t *acc0 = (uint64_t *)calloc((size_t)next * N, 8);
+    uint64_t *acc1 = (uint64_t *)calloc((size_t)next * N, 8);
+    int rc = ks_products(C, d, l, kidx, acc0, acc1, gidx);
+    if (rc == 0) moddown(C, l, acc0, acc1, gidx, out0, out1);
+    free(acc0); free(acc1); free(gidx);
+    return rc;
+}
+
+/* Relinearisation with the rescale folded into the ModDown (one rounding): with the
+ * key products acc over Q_l u P (NTT domain) and the tensor parts d0, d1 over Q_l
+ * (coefficient domain), A = acc + P d (P d vanishes mod every p_m) is divided by
+ * P q_l: over B = {q_l, p_0, .., p_{alpha-1}} each [A_b (P q_l / b)^-1]_b is lifted to
+ * its centred representative and converted to q_i, and
+ *   out_i = (A_i - sum_b w_b [P q_l / b]_{q_i}) (P q_l)^-1 mod q_i,  i < l.
+ * The result is the rescaled relinearised product at level l - 1. */
+static void moddown_rescale(const oc_ctx *C, int l, uint64_t *acc0, uint64_t *acc1, const int *gidx,
+                            const uint64_t *d0, const uint64_t *d1, uint64_t *out0, uint64_t *out1) {
+    int N = C->N, nq = l + 1, A = C->alpha, next = nq + A, nb = A + 1;
+    #pragma omp parallel for schedule(dynamic)
+    for (int k = 0; k < 2 * next; k++) {
+        int kk = k % next; uint64_t *acc = k < next ? acc0 : acc1;
+        inv(C, gidx[kk], acc + (size_t)kk * N);
+    }
+    /* basis B: extended limb slot and prime of each member */
+    int *bslot = (int *)malloc(sizeof(int) * nb);
+    uint64_t *bq = (uint64_t *)malloc(8 * nb), *bhinv = (uint64_t *)malloc(8 * nb);
+    bslot[0] = l;
+    for (int m = 0; m < A; m++) bslot[1 + m] = nq + m;
+    for (int k = 0; k < nb; k++) bq[k] = C->q[gidx[bslot[k]]];
+    for (int k = 0; k < nb; k++) {
+        uint64_t v = 1;
+        for (int b = 0; b < nb; b++) if (b != k) v = mulm(v, bq[b] % bq[k], bq[k]);
+        bhinv[k] = invm(v, bq[k]);
+    }
+    uint64_t Pql = 1;   /* P mod q_l */
+    for (int m = 0; m < A; m++) Pql = mulm(Pql, C->q[C->L + 1 + m] % C->q[l], C->q[l]);
+    for (int c = 0; c < 2; c++) {
+        uint64_t *acc = c ? acc1 : acc0, *out = c ? out1 : out0;
+        const uint64_t *d = c ? d1 : d0;
+        uint64_t *w = (uint64_t *)malloc(8 * (size_t)nb * N);
+        for (int k = 0; k < nb; k++) {
+            const uint64_t *a = acc + (size_t)bslot[k] * N;
+            for (int i = 0; i < N; i++) {
+                uint64_t v = a[i];
+                if (k == 0) v = addm(v, mulm(Pql, d[(size_t)l * N + i], bq[0]), bq[0]);
+                w[(size_t)k * N + i] = mulm(v, bhinv[k], bq[k]);
+            }
+        }
+        #pragma omp parallel for schedule(dynamic)
+        for (int t = 0; t < l; t++) {
+            uint64_t q = C->q[t];
+            uint64_t *bh = (uint64_t *)malloc(8 * nb);
+            uint64_t Pall = 1, Pm = 1;
+            for (int k = 0; k < nb; k++) {
+                uint64_t v = 1;
+                for (int b = 0; b < nb; b++) if (b != k) v = mulm(v, bq[b] % q, q);
+                bh[k] = v;
+                Pall = mulm(Pall, bq[k] % q, q);
+            }
+            for (int m = 0; m < A; m++) Pm = mulm(Pm, C->q[C->L + 1 + m] % q, q);
+            uint64_t Pinv = invm(Pall, q);
+            for (int i = 0; i < N; i++) {
+                uint64_t sum = 0;
+                for (int k = 0; k < nb; k++) {
+                    uint64_t bk = bq[k], v = w[(size_t)k * N + i];
+                    uint64_t vk = v > (bk - 1) / 2 ? subm(0, (bk - v) % q, q) : v % q;
+                    sum = addm(sum, mulm(vk, bh[k], q), q);
+                }
+                uint64_t Ai = addm(acc[(size_t)t * N + i], mulm(Pm, d[(size_t)t * N + i], q), q);
+                out[(size_t)t * N + i] = mulm(subm(Ai, sum, q), Pinv, q);
+            }
+            free(bh);
+        }
+        free(w);
+    }
+    free(bslot); free(bq); free(bhinv);
 }
 
 /* exported for primitive-level tests: key switch of a single polynomial */
@@ -668,7 +747,7 @@ static void automorph(const oc_ctx *C, const uint64_t *in, uint64_t *out, int le
     }
 }
 
-/* tensor, relinearise, rescale */
+/* tensor, then relinearise and rescale in one ModDown by P q_l */
 oc_ct *oc_mul(const oc_ctx *C, const oc_ct *a, const oc_ct *b) {
     if (a->level != b->level || a->level < 1 || !C->keys[0]) return NULL;
     int l = a->level, N = C->N;
@@ -685,17 +764,15 @@ oc_ct *oc_mul(const oc_ctx *C, const oc_ct *a, const oc_ct *b) {
         ring_mul(C, p, a->c[1] + o, b->c[1] + o, d2 + o);
         free(t);
     }
-    oc_ct *r = ct_new(C, l);
-    keyswitch(C, d2, l, 0, r->c[0], r->c[1]);
-    for (int p = 0; p <= l; p++)
-        for (int i = 0; i < N; i++) {
-            size_t o = (size_t)p * N + i;
-            r->c[0][o] = addm(r->c[0][o], d0[o], C->q[p]);
-            r->c[1][o] = addm(r->c[1][o], d1[o], C->q[p]);
-        }
+    int next = l + 1 + C->alpha;
+    int *gidx = (int *)malloc(sizeof(int) * next);
+    uint64_t *acc0 = (uint64_t *)calloc((size_t)next * N, 8);
+    uint64_t *acc1 = (uint64_t *)calloc((size_t)next * N, 8);
+    ks_products(C, d2, l, 0, acc0, acc1, gidx);
+    oc_ct *s = ct_new(C, l - 1);
+    moddown_rescale(C, l, acc0, acc1, gidx, d0, d1, s->c[0], s->c[1]);
+    free(acc0); free(acc1); free(gidx);
     free(d0); free(d1); free(d2);
-    oc_ct *s = oc_rescale(C, r);
-    oc_ct_free(r);
     return s;
 }
 

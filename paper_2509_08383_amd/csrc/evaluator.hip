@@ -143,6 +143,12 @@ struct he_ctx {
     const double *phinv = nullptr, *phat = nullptr, *Pinv = nullptr, *qlinv = nullptr, *pmod = nullptr;
     std::vector<const double *> mu_scale;  // [L+1] -> [l+1]: N^-1 Qhat_i^-1 mod q_i at level l
     const double *md_scale = nullptr;      // [alpha]: N^-1 Phat_m^-1 mod p_m
+    // ModDown by P q_l (relinearisation with the rescale folded in), per level l >= 1,
+    // basis B = {q_l, p_0, .., p_{alpha-1}}:
+    std::vector<const double *> mr_scale;  // [alpha+1]: N^-1 Bhat_b^-1 mod b
+    std::vector<const double *> mr_phat;   // [alpha+1][l]: Bhat_b mod q_i
+    std::vector<const double *> mr_inv;    // [l]: (P q_l)^-1 mod q_i
+    std::vector<double> pmod_h;            // [L+1]: P mod q_i (host copy)
     const int *ident = nullptr;   // 0..np-1
     const int *pprime = nullptr;  // L+1 .. L+alpha
     uint32_t nonce = 0;
@@ -338,9 +344,12 @@ struct Exec {
     // out (groups ct*2 + poly at ostride) = ModDown(sum_j ModUp_j(d) key_j) + a1 + a2.
     // With rot, the key products are those of a hoisted rotate-and-sum step: every
     // rotation's automorphism applied to the extended digits, its key, summed (kidx unused).
+    // With mrescale (relinearisation), a1 holds the tensor's d0/d1 over Q_l and the output
+    // is (d + relinearised d2) / q_l at level l - 1: the ModDown divides A = acc + P d by
+    // P q_l in one rounding (a2 and rot unused).
     void keyswitch(const double *d, long long dstride, int cnt, int l, int kidx, double *out, long long ostride,
                    Addend a1 = Addend{nullptr, 0, 0, 0}, Addend a2 = Addend{nullptr, 0, 0, 0},
-                   const RotSet *rot = nullptr) {
+                   const RotSet *rot = nullptr, bool mrescale = false) {
         const int A = C->alpha, next = l + 1 + A, beta = (l + 1 + A - 1) / A;
         const long long N = C->N;
         const size_t m = C->arena.mark();
@@ -369,14 +378,42 @@ struct Exec {
                 launch_inner_product_rot(T, ext, (long long)beta * next * N, (long long)next * N, acc,
                                          acc + (long long)next * N, 2LL * next * N, *rot, 2LL * C->np * N,
                                          (long long)C->np * N, cnt, beta, next, C->ext_prime[l], s);
+            else if (mrescale)
+                launch_inner_product(T, ext, (long long)beta * next * N, (long long)next * N, acc,
+                                     acc + (long long)next * N, 2LL * next * N, C->keys[kidx], 2LL * C->np * N,
+                                     (long long)C->np * N, cnt, beta, next, C->ext_prime[l], s,
+                                     a1.p + (long long)l * N, a1.ct, a1.poly, l, C->pmod_h[l]);
             else
                 launch_inner_product(T, ext, (long long)beta * next * N, (long long)next * N, acc,
                                      acc + (long long)next * N, 2LL * next * N, C->keys[kidx], 2LL * C->np * N,
                                      (long long)C->np * N, cnt, beta, next, C->ext_prime[l], s);
+            if (mrescale) {
+                // B = {q_l, P} to the coefficient domain, scaled by Bhat^-1; convert to q_0..q_{l-1};
+                // transform and combine on store: (acc - conv) (P q_l)^-1 + d q_l^-1
+                launch_ntt(T, VecSet{acc + (long long)l * N, cnt * 2 * (A + 1), A + 1, (long long)next * N, nullptr,
+                                     C->ext_prime[l] + l},
+                           true, C->ntt_variant, s, nullptr, C->mr_scale[l]);
+                launch_moddown_conv(T, acc, (long long)next * N, conv, (long long)l * N, cnt * 2,
+                                    MdIn{l, A + 1, C->ext_prime[l] + l, C->mr_phat[l], l, l}, s);
+                NttEpi epi{};
+                epi.kind = 3;
+                epi.out = out;
+                epi.o_g = ostride;
+                epi.in = acc;
+                epi.i_g = (long long)next * N;
+                epi.add1 = a1.p; epi.a1_ct = a1.ct; epi.a1_poly = a1.poly; epi.m1 = a1.mask;
+                epi.cst = C->mr_inv[l];
+                epi.cst2 = C->qlinv + (long long)l * (C->L + 1);
+                launch_ntt_fused(T, VecSet{conv, cnt * 2 * l, l, (long long)l * N, nullptr, nullptr}, NttPro{}, epi,
+                                 C->ntt_variant, s);
+                C->arena.release(m);
+                return;
+            }
             // P slots to the coefficient domain, scaled by Phat_m^-1
             launch_ntt(T, VecSet{acc + (long long)(l + 1) * N, cnt * 2 * A, A, (long long)next * N, nullptr, C->pprime},
                        true, C->ntt_variant, s, nullptr, C->md_scale);
-            launch_moddown_conv(T, acc, (long long)next * N, conv, (long long)(l + 1) * N, cnt * 2, l, C->phat, s);
+            launch_moddown_conv(T, acc, (long long)next * N, conv, (long long)(l + 1) * N, cnt * 2,
+                                MdIn{l + 1, A, C->pprime, C->phat, C->L + 1, l + 1}, s);
             // transform the conversion and combine on store: (acc - conv) P^-1 + addends
             NttEpi epi{};
             epi.kind = 1;
@@ -399,8 +436,9 @@ struct Exec {
         const int l = a.level;
         REQUIRE(l >= 1, HE_EDEPTH, "mul at level 0");
         const long long N = C->N;
-        Bt r = new_bt(a.cnt, l);
-        for (int c = 0; c < a.cnt; ++c) r.scale[c] = a.scale[c] * b.scale[bmap ? (*bmap)[c] : c];
+        // tensor, then relinearisation and rescale in one ModDown by P q_l
+        Bt o = new_bt(a.cnt, l - 1);
+        for (int c = 0; c < a.cnt; ++c) o.scale[c] = (a.scale[c] * b.scale[bmap ? (*bmap)[c] : c]) / (double)C->q[l];
         const size_t m = C->arena.mark();
         double *t = alloc_d((size_t)a.cnt * 3 * (l + 1) * N);
         const int *dmap = bmap ? C->pool.push(*bmap) : nullptr;
@@ -408,12 +446,9 @@ struct Exec {
             launch_tensor(T, t, t + (l + 1) * N, t + 2 * (l + 1) * N, 3LL * (l + 1) * N, a.d, b.d,
                           2LL * a.cap * N, 2LL * b.cap * N, dmap, (long long)a.cap * N, (long long)b.cap * N,
                           a.cnt, l + 1, s);
-        keyswitch(t + 2 * (l + 1) * N, 3LL * (l + 1) * N, a.cnt, l, 0, r.d, (long long)r.cap * N,
-                  Addend{t, 3LL * (l + 1) * N, (long long)(l + 1) * N, 3});
+        keyswitch(t + 2 * (l + 1) * N, 3LL * (l + 1) * N, a.cnt, l, 0, o.d, (long long)o.cap * N,
+                  Addend{t, 3LL * (l + 1) * N, (long long)(l + 1) * N, 3}, Addend{nullptr, 0, 0, 0}, nullptr, true);
         C->arena.release(m);
-        // r's scale here is s_a*s_b; the rescale divides by q_l
-        Bt o = rescale(r);
-        for (int c = 0; c < a.cnt; ++c) o.scale[c] = (a.scale[c] * b.scale[bmap ? (*bmap)[c] : c]) / (double)C->q[l];
         return o;
     }
 
@@ -819,12 +854,39 @@ void build_ctx(he_ctx *C, const he_params *prm) {
         pmod[i] = (double)P;
     }
     const size_t o_phinv = tb.d(phinv), o_phat = tb.d(phat), o_Pinv = tb.d(Pinv), o_pmod = tb.d(pmod);
+    C->pmod_h = pmod;
     std::vector<double> mds(A);
     for (int m = 0; m < A; ++m) {
         const uint64_t pm = q[L + 1 + m];
         mds[m] = (double)mulmod_u((uint64_t)ninv[L + 1 + m], (uint64_t)phinv[m], pm);
     }
     const size_t o_mds = tb.d(mds);
+    std::vector<size_t> o_mrs(L + 1, 0), o_mrp(L + 1, 0), o_mri(L + 1, 0);
+    for (int l = 1; l <= L; ++l) {
+        std::vector<uint64_t> B(A + 1);
+        B[0] = q[l];
+        for (int m = 0; m < A; ++m) B[1 + m] = q[L + 1 + m];
+        std::vector<double> sc(A + 1), ph((size_t)(A + 1) * l), iv(l);
+        for (int k = 0; k <= A; ++k) {
+            uint64_t v = 1;
+            for (int b = 0; b <= A; ++b) if (b != k) v = mulmod_u(v, B[b] % B[k], B[k]);
+            const int gk = k == 0 ? l : L + 1 + (k - 1);
+            sc[k] = (double)mulmod_u((uint64_t)ninv[gk], invmod_u(v, B[k]), B[k]);
+            for (int i = 0; i < l; ++i) {
+                uint64_t w = 1;
+                for (int b = 0; b <= A; ++b) if (b != k) w = mulmod_u(w, B[b] % q[i], q[i]);
+                ph[(size_t)k * l + i] = (double)w;
+            }
+        }
+        for (int i = 0; i < l; ++i) {
+            uint64_t w = 1;
+            for (int b = 0; b <= A; ++b) w = mulmod_u(w, B[b] % q[i], q[i]);
+            iv[i] = (double)invmod_u(w, q[i]);
+        }
+        o_mrs[l] = tb.d(sc);
+        o_mrp[l] = tb.d(ph);
+        o_mri[l] = tb.d(iv);
+    }
     // rescale: q_l^-1 mod q_i
     std::vector<double> qlinv((size_t)(L + 1) * (L + 1), 0.0);
     for (int l = 1; l <= L; ++l)
@@ -889,6 +951,14 @@ void build_ctx(he_ctx *C, const he_params *prm) {
     C->phinv = D + o_phinv; C->phat = D + o_phat; C->Pinv = D + o_Pinv; C->pmod = D + o_pmod;
     C->qlinv = D + o_qlinv;
     C->md_scale = D + o_mds;
+    C->mr_scale.assign(L + 1, nullptr);
+    C->mr_phat.assign(L + 1, nullptr);
+    C->mr_inv.assign(L + 1, nullptr);
+    for (int l = 1; l <= L; ++l) {
+        C->mr_scale[l] = D + o_mrs[l];
+        C->mr_phat[l] = D + o_mrp[l];
+        C->mr_inv[l] = D + o_mri[l];
+    }
     C->mu_scale.resize(L + 1);
     for (int l = 0; l <= L; ++l) C->mu_scale[l] = D + o_mus[l];
     C->ndall_slot.resize(L + 1);
@@ -1286,7 +1356,7 @@ int he_ctx_create(const he_params *prm, he_ctx **out) {
         C->dnum = (int)prm->dnum;
         C->alpha = ((int)prm->n_q + C->dnum - 1) / C->dnum;
         C->np = (int)prm->n_q + C->alpha;
-        REQUIRE(C->np <= kMaxPrimes && C->alpha <= 16, HE_EINVAL, "too many primes (alpha <= 16)");
+        REQUIRE(C->np <= kMaxPrimes && C->alpha <= 15, HE_EINVAL, "too many primes (alpha <= 15)");
         C->betaL = ((int)prm->n_q + C->alpha - 1) / C->alpha;
         REQUIRE(C->betaL <= 8, HE_EINVAL, "at most 8 digits");
         REQUIRE(prm->hoist <= 4, HE_EINVAL, "hoist must be 0..4");

@@ -89,6 +89,7 @@ struct NttPro {
 // Forward-NTT epilogue on the transformed word w of vector (g, r), position j:
 //   kind 1 (ModDown): out = (in - w) * cst[r] + [m1] add1 + [m2] add2
 //   kind 2 (rescale): out = (K in - w) * cst[r], K = kmul[(g >> 1) * kstride + r] or 1
+//   kind 3 (ModDown by P q_l): out = (in - w) * cst[r] + add1 * cst2[r]
 // with in = in[g * i_g + r N + j], out[g * o_g + r N + j], addk[(g>>1) ak_ct +
 // (g&1) ak_poly + r N + j] applied when bit (g & 1) of mk is set.
 struct NttEpi {
@@ -106,6 +107,7 @@ struct NttEpi {
     const double *cst;
     const double *kmul;
     int kstride;
+    const double *cst2;
 };
 void launch_ntt_fused(const DevTables &T, const VecSet &vs, const NttPro &pro, const NttEpi &epi, int variant,
                       hipStream_t s);
@@ -135,7 +137,9 @@ void launch_modup(const DevTables &T, const double *v, long long vstride, double
 void launch_inner_product(const DevTables &T, const double *ext, long long estride_b,
                           long long estride_j, double *acc0, double *acc1, long long astride,
                           KeyRef key, long long kstride_j, long long kstride_c, int cnt,
-                          int beta, int next, const int *ext_prime, hipStream_t s);
+                          int beta, int next, const int *ext_prime, hipStream_t s,
+                          const double *dadd = nullptr, long long dct = 0, long long dpoly = 0, int tl = -1,
+                          double pmodl = 0.0);
 void launch_pack_key(const double *src, uint32_t *lo, uint16_t *hi, size_t n, hipStream_t s);
 
 // rotations of one hoisted rotate-and-sum step: key and Galois element of each
@@ -150,8 +154,16 @@ void launch_inner_product_rot(const DevTables &T, const double *ext, long long e
                               long long kstride_c, int cnt, int beta, int next, const int *ext_prime, hipStream_t s);
 // out = in + sum_r sigma_r(in) on NTT-domain limbs
 void launch_autsum(const DevTables &T, const VecSet &out, const VecSet &in, const RotSet &rs, hipStream_t s);
+// inputs: slots in0 .. in0+nin-1 of each group, prime index in_prime[m]; targets
+// q_0 .. q_{ntgt-1}; [Bhat_m]_{q_i} = ph[m * phs + i]
+struct MdIn {
+    int in0, nin;
+    const int *in_prime;
+    const double *ph;
+    int phs, ntgt;
+};
 void launch_moddown_conv(const DevTables &T, const double *acc, long long astride, double *conv,
-                         long long cstride, int groups, int level, const double *phat, hipStream_t s);
+                         long long cstride, int groups, const MdIn &md, hipStream_t s);
 void launch_sample_uniform(const DevTables &T, const VecSet &out, uint64_t seed, uint32_t obj,
                            const int *gprime, hipStream_t s);
 void launch_sample_small(int *out, int N, uint64_t seed, uint32_t obj, int kind, hipStream_t s);

@@ -322,9 +322,12 @@ void launch_pack_key(const double *src, uint32_t *lo, uint16_t *hi, size_t n, hi
 
 // acc_c[ct][t] = sum_j ext[ct][j][t] * key[j][c][prime(t)]; the key words are
 // read once per (t, x) and reused for every ciphertext of the batch.
+// With dadd, slot tl also gets [P]_{q_tl} times the words dadd[ct dct + c dpoly + x]
+// (the tensor's d0/d1 at limb tl: the relinearisation with the rescale folded in).
 __global__ void k_inner_product(DevTables T, const double *ext, long long esb, long long esj,
                                 double *acc0, double *acc1, long long astride, KeyRef key,
-                                long long ksj, long long ksc, int cnt, int beta, const int *ext_prime) {
+                                long long ksj, long long ksc, int cnt, int beta, const int *ext_prime,
+                                const double *dadd, long long dct, long long dpoly, int tl, double pmodl) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= T.N) return;
     const int t = blockIdx.y;
@@ -348,6 +351,10 @@ __global__ void k_inner_product(DevTables T, const double *ext, long long esb, l
                 s1 += mm(e, k1[j], p, pinv);
             }
         }
+        if (dadd && t == tl) {
+            s0 += mm(dadd[ct * dct + x], pmodl, p, pinv);
+            s1 += mm(dadd[ct * dct + dpoly + x], pmodl, p, pinv);
+        }
         acc0[ct * astride + (long long)t * T.N + x] = canon(s0, p, pinv);
         acc1[ct * astride + (long long)t * T.N + x] = canon(s1, p, pinv);
     }
@@ -355,13 +362,14 @@ __global__ void k_inner_product(DevTables T, const double *ext, long long esb, l
 void launch_inner_product(const DevTables &T, const double *ext, long long estride_b,
                           long long estride_j, double *acc0, double *acc1, long long astride,
                           KeyRef key, long long kstride_j, long long kstride_c, int cnt,
-                          int beta, int next, const int *ext_prime, hipStream_t s) {
+                          int beta, int next, const int *ext_prime, hipStream_t s, const double *dadd,
+                          long long dct, long long dpoly, int tl, double pmodl) {
     if (cnt <= 0) return;
     // key words once, extended digits and both accumulators per ciphertext
     kprof_set_bytes(8.0 * T.N * next * (2.0 * beta + cnt * (beta + 2.0)));
     KL("k_inner_product", k_inner_product, dim3((T.N + 255) / 256, next), dim3(256), 0, s, T, ext,
                        estride_b, estride_j, acc0, acc1, astride, key, kstride_j, kstride_c, cnt,
-                       beta, ext_prime);
+                       beta, ext_prime, dadd, dct, dpoly, tl, pmodl);
 }
 
 // Inner product of a hoisted rotate-and-sum step: for rotation r with Galois
@@ -500,38 +508,38 @@ void launch_autsum(const DevTables &T, const VecSet &out, const VecSet &in, cons
     KL("k_autsum", k_autsum, ew_grid(T, out.count), dim3(256), 0, s, out, in, rs, T);
 }
 
-// ModDown conversion: the P slots of acc hold w_m = [acc_{P,m} * Phat_m^-1]_{p_m}
-// (coefficient domain, scaled by the inverse NTT); each is lifted to its centred
-// representative and conv_i = sum_m w_m [Phat_m]_{q_i} for i <= level.
-// acc holds groups of (level+1+alpha) limbs at astride; conv [groups][level+1].
-// Grid: x = blocks of TB target primes, y = coefficient blocks, z = group; the
-// block's [Phat_m]_{q_i} table is staged in LDS as in k_modup.
+// ModDown conversion: acc holds, at slots in0 .. in0+nin-1 of every group, the
+// coefficient-domain words w_m = [A_m * Bhat_m^-1]_{b_m} of the basis being divided
+// out (the inverse NTT applied the scaling): P (in0 = level+1) or P q_level (in0 =
+// level, the rescale folded in).  Each is lifted to its centred representative and
+// conv_i = sum_m w_m [Bhat_m]_{q_i} for the targets i < ntgt.  acc holds groups at
+// astride; conv [groups][ntgt].  Grid: x = blocks of TB targets, y = coefficient
+// blocks, z = group; the block's [Bhat_m]_{q_i} table is staged in LDS as in k_modup.
 template <int AL, int TB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_moddown_conv(DevTables T, const double *__restrict__ acc,
+__global__ __launch_bounds__(256) void k_moddown_conv(DevTables T, const double *__restrict__ acc,
                                                       long long astride, double *__restrict__ conv,
-                                                      long long cstride, int level,
-                                                      const double *__restrict__ phat) {
+                                                      long long cstride, MdIn md) {
     __shared__ double sq[AL * TB];
     __shared__ double sp[TB], si[TB];
-    const int A = T.alpha, i0 = blockIdx.x * TB, tid = threadIdx.x;
+    const int i0 = blockIdx.x * TB, tid = threadIdx.x;
     for (int k = tid; k < AL * TB; k += blockDim.x) {
         const int m = k / TB, i = i0 + (k - (k / TB) * TB);
-        sq[k] = (m < A && i <= level) ? phat[m * (T.L + 1) + i] : 0.0;
+        sq[k] = (m < md.nin && i < md.ntgt) ? md.ph[m * md.phs + i] : 0.0;
     }
     if (tid < TB) {
-        const int i = i0 + tid <= level ? i0 + tid : 0;
+        const int i = i0 + tid < md.ntgt ? i0 + tid : 0;
         sp[tid] = T.p[i];
         si[tid] = T.pinv[i];
     }
     __syncthreads();
     const int x = blockIdx.y * blockDim.x + tid;
     if (x >= T.N) return;
-    const double *Ac = acc + blockIdx.z * astride + (long long)(level + 1) * T.N + x;
+    const double *Ac = acc + blockIdx.z * astride + (long long)md.in0 * T.N + x;
     double w[AL];
 #pragma unroll
     for (int m = 0; m < AL; ++m) {
-        if (m < A) {
-            const double p = T.p[T.L + 1 + m];
+        if (m < md.nin) {
+            const double p = T.p[md.in_prime[m]];
             const double u = Ac[(long long)m * T.N];
             w[m] = u > 0.5 * (p - 1.0) ? u - p : u;
         } else {
@@ -542,7 +550,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 #pragma unroll
     for (int ii = 0; ii < TB; ++ii) {
         const int i = i0 + ii;
-        if (i > level) break;
+        if (i >= md.ntgt) break;
         const double p = sp[ii], pinv = si[ii];
         double sacc = 0.0;
 #pragma unroll
@@ -553,27 +561,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 
 template <int TB>
 static void conv_tb(int AL, dim3 grid, hipStream_t s, const DevTables &T, const double *acc, long long astride,
-                    double *conv, long long cstride, int level, const double *phat) {
+                    double *conv, long long cstride, const MdIn &md) {
 #define MD_CASE(D)                                                                                             \
     case D:                                                                                                    \
         KL("k_moddown_conv", (k_moddown_conv<D, TB>), grid, dim3(256), 0, s, T, acc, astride, conv, cstride, \
-           level, phat);                                                                                       \
+           md);                                                                                                \
         break;
     switch (AL) { MD_CASE(4) MD_CASE(8) MD_CASE(10) MD_CASE(12) MD_CASE(16) }
 #undef MD_CASE
 }
 
 void launch_moddown_conv(const DevTables &T, const double *acc, long long astride, double *conv,
-                         long long cstride, int groups, int level, const double *phat, hipStream_t s) {
+                         long long cstride, int groups, const MdIn &md, hipStream_t s) {
     if (groups <= 0) return;
-    const int AL = digit_len(T.alpha);
+    const int AL = digit_len(md.nin);
     const int cblk = (T.N + 255) / 256;
-    const bool wide = (long long)((level + 8) / 8) * cblk * groups >= 2048;
-    kprof_set_bytes(8.0 * T.N * groups * (T.alpha + level + 1));
+    const bool wide = (long long)((md.ntgt + 7) / 8) * cblk * groups >= 2048;
+    kprof_set_bytes(8.0 * T.N * groups * (md.nin + md.ntgt));
     if (wide)
-        conv_tb<8>(AL, dim3((level + 8) / 8, cblk, groups), s, T, acc, astride, conv, cstride, level, phat);
+        conv_tb<8>(AL, dim3((md.ntgt + 7) / 8, cblk, groups), s, T, acc, astride, conv, cstride, md);
     else
-        conv_tb<4>(AL, dim3((level + 4) / 4, cblk, groups), s, T, acc, astride, conv, cstride, level, phat);
+        conv_tb<4>(AL, dim3((md.ntgt + 3) / 4, cblk, groups), s, T, acc, astride, conv, cstride, md);
 }
 
 // ---------------------------------------------------------------- sampling

@@ -126,7 +126,7 @@ __global__ __launch_bounds__(COLS *(1 << H)) void k_ntt(VecSet vs, VecSet src, c
         for (int e = 0; e < E; ++e) tile[lds(c, th + TPS * e)] = nred(v[e], p, pinv);
         __syncthreads();
         // epilogue operands, in flight while phase B computes
-        double ex[EPI ? EW : 1], es[EPI == 1 ? EW : 1];
+        double ex[EPI ? EW : 1], es[(EPI == 1 || EPI == 3) ? EW : 1];
         long long rN = 0;
         if (EPI) {
             rN = (long long)r_ * NN;
@@ -141,6 +141,7 @@ __global__ __launch_bounds__(COLS *(1 << H)) void k_ntt(VecSet vs, VecSet src, c
                 const long long j = gidx(cc, k);
                 ex[i] = in[j];
                 if (EPI == 1) es[i] = (use1 ? ad1[j] : 0.0) + (use2 ? ad2[j] : 0.0);
+                if (EPI == 3) es[i] = use1 ? ad1[j] : 0.0;
             }
         }
         // phase B (low bits of k)
@@ -177,6 +178,7 @@ __global__ __launch_bounds__(COLS *(1 << H)) void k_ntt(VecSet vs, VecSet src, c
                 }
             } else {
                 const double cst = epi.cst[r_];
+                const double cst2 = EPI == 3 ? epi.cst2[r_] : 0.0;
                 double *out = epi.out + (long long)g_ * epi.o_g + rN;
                 const double km = (EPI == 2 && epi.kmul) ? epi.kmul[(long long)(g_ >> 1) * epi.kstride + r_] : 1.0;
 #pragma unroll
@@ -187,6 +189,7 @@ __global__ __launch_bounds__(COLS *(1 << H)) void k_ntt(VecSet vs, VecSet src, c
                     if (EPI == 2 && epi.kmul) x = nmm(x, km, p, pinv);
                     double o = nmm(x - w, cst, p, pinv);
                     if (EPI == 1) o += es[i];
+                    if (EPI == 3) o += nmm(es[i], cst2, p, pinv);
                     out[gidx(cc, k)] = ncanon(o, p, pinv);
                 }
             }
@@ -287,9 +290,11 @@ static void ntt_run(const DevTables &T, const VecSet &vs, const VecSet *src, boo
             extra = 1.0;  // in
             if (EPI == 1 && epi.add1) extra += __builtin_popcount(epi.m1 & 3) * 0.5;
             if (EPI == 1 && epi.add2) extra += __builtin_popcount(epi.m2 & 3) * 0.5;
+            if (EPI == 3) extra += 1.0;
         }
         kprof_set_bytes(half * nvec * (1.0 + extra));
-        KLN(EPI == 1 ? "ntt_fwd_pass2_moddown" : (EPI == 2 ? "ntt_fwd_pass2_rescale" : "ntt_fwd_pass2"),
+        KLN(EPI == 1 ? "ntt_fwd_pass2_moddown"
+                     : (EPI == 2 ? "ntt_fwd_pass2_rescale" : (EPI == 3 ? "ntt_fwd_pass2_moddown_rescale" : "ntt_fwd_pass2")),
             (k_ntt<H, COLS, true, false, 0, EPI>), grid, block, 0, s, vs, none, nullptr, T, pro, epi);
     } else {
         kprof_set_bytes(half * nvec);
@@ -330,6 +335,7 @@ void launch_ntt_fused(const DevTables &T, const VecSet &vs, const NttPro &pro, c
     else if (pro.kind == 0 && epi.kind == 1) ntt_dispatch<0, 1>(T, vs, false, variant, s, nullptr, nullptr, pro, epi);
     else if (pro.kind == 1 && epi.kind == 0) ntt_dispatch<1, 0>(T, vs, false, variant, s, nullptr, nullptr, pro, epi);
     else if (pro.kind == 0 && epi.kind == 2) ntt_dispatch<0, 2>(T, vs, false, variant, s, nullptr, nullptr, pro, epi);
+    else if (pro.kind == 0 && epi.kind == 3) ntt_dispatch<0, 3>(T, vs, false, variant, s, nullptr, nullptr, pro, epi);
     else ntt_dispatch<0, 0>(T, vs, false, variant, s, nullptr, nullptr, pro, epi);
 }
 

@@ -49,7 +49,7 @@ def kernel_class(name: str) -> str:
     if m:
         p2, inv, pro, epi = m.group(3) == "true", m.group(4) == "true", int(m.group(5)), int(m.group(6))
         s = "ntt_" + ("inv" if inv else "fwd") + ("_pass2" if p2 else "_pass1")
-        s += {1: "_lift"}.get(pro, "") + {1: "_moddown", 2: "_rescale"}.get(epi, "")
+        s += {1: "_lift"}.get(pro, "") + {1: "_moddown", 2: "_rescale", 3: "_moddown_rescale"}.get(epi, "")
         return s
     base = re.sub(r"\(.*", "", name)
     base = re.sub(r"^void ", "", base)

@@ -136,6 +136,27 @@ def test_homomorphic_add_mul_rescale_rotate(toy):
     np.testing.assert_allclose(toy.decrypt(ct_), -1.25 * x, atol=1e-4)
 
 
+def test_merged_relinearise_rescale_matches_two_steps(toy):
+    """mul divides by P q_l in one ModDown; relinearising (ModDown by P) and then
+    rescaling (by q_l) gives the same product up to the roundings: a centred rounding of
+    (c0, c1) decrypts to an error below (1 + |s|_1)/2 per coefficient, so the decrypted
+    coefficients of the two differ by less than 1 + |s|_1 (a dropped term or a wrong
+    constant differs by a multiple of the modulus), at the top level and with a partial
+    digit"""
+    s1 = int(np.abs(toy.secret().astype(np.int64)).sum())
+    rng = np.random.default_rng(12)
+    x, y = rng.uniform(-2, 2, toy.slots), rng.uniform(-2, 2, toy.slots)
+    cx, cy = toy.encrypt(x), toy.encrypt(y)
+    for lv in (toy.L, 4):
+        a, b = toy.drop(cx, lv), toy.drop(cy, lv)
+        merged = toy.mul(a, b)
+        two = toy.rescale(ckks.Ct(toy, ckks.lib().oc_mul_norescale(toy.h, a.h, b.h), a.scale * b.scale))
+        assert merged.level == two.level == lv - 1
+        d = toy.decrypt_coeffs(merged) - toy.decrypt_coeffs(two)
+        assert np.abs(d).max() < 1 + s1, (np.abs(d).max(), s1)
+        np.testing.assert_allclose(toy.decrypt(merged), x * y, atol=1e-4)
+
+
 def test_rotate_and_mul_at_low_levels(toy):
     """Partial key-switch digits below the top level still switch keys correctly."""
     x = np.random.default_rng(3).uniform(-1, 1, toy.slots)
