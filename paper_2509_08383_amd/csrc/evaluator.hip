@@ -499,15 +499,20 @@ struct Exec {
     // rotate-and-sum over every slot (Sec. 3.2): x <- x + rot(x, 2^r) one rotation at
     // a time, or hoisted steps x <- x + sum_r rot(x, a_r)
     Bt rotsum(const Bt &a) {
-        Bt o = copy(a);
         if (C->hoist >= 1) {
+            // the first step reads a and writes o, the others update o in place
+            Bt o = new_bt(a.cnt, a.level);
+            o.scale = a.scale;
+            bool first = true;
             for (const auto &st : hoist_steps(C->slots, C->hoist)) {
                 const size_t m = C->arena.mark();
-                rotsum_step(o, st);
+                rotsum_step(first ? a : o, o, st);
                 C->arena.release(m);
+                first = false;
             }
             return o;
         }
+        Bt o = copy(a);
         int lg = 0;
         while ((1 << lg) < C->slots) ++lg;
         for (int r = 0; r < lg; ++r) {
@@ -518,10 +523,11 @@ struct Exec {
         return o;
     }
 
-    // one hoisted step in place: c1 is extended once, each rotation's automorphism
-    // acts on the extended digits inside the key products, one ModDown for all:
-    //   out0 = c0 + sum_r sigma_r(c0) + MD_0,  out1 = c1 + MD_1
-    void rotsum_step(Bt &x, const std::vector<int> &amounts) {
+    // one hoisted step x -> y (y may be x): c1 is extended once, each rotation's
+    // automorphism acts on the extended digits inside the key products (where
+    // c0 + sum_r sigma_r(c0) is gathered too), one ModDown for all:
+    //   y0 = c0 + sum_r sigma_r(c0) + MD_0,  y1 = c1 + MD_1
+    void rotsum_step(const Bt &x, const Bt &y, const std::vector<int> &amounts) {
         const int l = x.level;
         const long long N = C->N;
         REQUIRE(!amounts.empty() && (int)amounts.size() <= kMaxHoist, HE_EINVAL, "hoisted step size");
@@ -534,10 +540,12 @@ struct Exec {
             rs.g[r] = C->key_gal[it->second];
         }
         double *s0 = alloc_d((size_t)x.cnt * (l + 1) * N);
-        if (go())
-            launch_autsum(T, VecSet{s0, x.cnt * (l + 1), l + 1, (long long)(l + 1) * N, nullptr, nullptr},
-                          VecSet{x.d, x.cnt * (l + 1), l + 1, 2LL * x.cap * N, nullptr, nullptr}, rs, s);
-        keyswitch(x.d + (long long)x.cap * N, 2LL * x.cap * N, x.cnt, l, -1, x.d, (long long)x.cap * N,
+        rs.c0 = x.d;
+        rs.c0_ct = 2LL * x.cap * N;
+        rs.s0 = s0;
+        rs.s0_ct = (long long)(l + 1) * N;
+        rs.lq = l;
+        keyswitch(x.d + (long long)x.cap * N, 2LL * x.cap * N, x.cnt, l, -1, y.d, (long long)y.cap * N,
                   Addend{s0, (long long)(l + 1) * N, 0, 1}, Addend{x.d, 2LL * x.cap * N, (long long)x.cap * N, 2},
                   &rs);
     }

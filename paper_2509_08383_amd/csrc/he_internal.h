@@ -148,12 +148,16 @@ struct RotSet {
     KeyRef key[kMaxHoist];
     uint32_t g[kMaxHoist];
     int nr;
+    // with c0: limbs t <= lq also get s0 = c0 + sum_r sigma_r(c0) (c0 + ct c0_ct + t N, s0 alike)
+    const double *c0;
+    long long c0_ct;
+    double *s0;
+    long long s0_ct;
+    int lq;
 };
 void launch_inner_product_rot(const DevTables &T, const double *ext, long long estride_b, long long estride_j,
                               double *acc0, double *acc1, long long astride, const RotSet &rs, long long kstride_j,
                               long long kstride_c, int cnt, int beta, int next, const int *ext_prime, hipStream_t s);
-// out = in + sum_r sigma_r(in) on NTT-domain limbs
-void launch_autsum(const DevTables &T, const VecSet &out, const VecSet &in, const RotSet &rs, hipStream_t s);
 // inputs: slots in0 .. in0+nin-1 of each group, prime index in_prime[m]; targets
 // q_0 .. q_{ntgt-1}; [Bhat_m]_{q_i} = ph[m * phs + i]
 struct MdIn {

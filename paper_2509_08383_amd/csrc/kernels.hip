@@ -388,11 +388,14 @@ __global__ __launch_bounds__(256) void k_inner_product_rot(DevTables T, const do
     const int pt = ext_prime[t];
     const double p = T.p[pt], pinv = T.pinv[pt];
     const long long ko = (long long)pt * T.N + x;
+    const bool wsum = rs.c0 && t <= rs.lq;
     for (int ct = 0; ct < cnt; ++ct) {
         const double *E = ext + ct * esb + (long long)t * T.N;
-        double s0 = 0.0, s1 = 0.0;
+        const double *C0 = wsum ? rs.c0 + ct * rs.c0_ct + (long long)t * T.N : nullptr;
+        double s0 = 0.0, s1 = 0.0, g0 = wsum ? C0[x] : 0.0;
         for (int r = 0; r < rs.nr; ++r) {
             const unsigned src = aut_src((unsigned)x, rs.g[r], T.logN);
+            if (wsum) g0 = red(g0 + C0[src], p, pinv);
             const KeyRef K = rs.key[r];
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
@@ -407,6 +410,7 @@ __global__ __launch_bounds__(256) void k_inner_product_rot(DevTables T, const do
         }
         acc0[ct * astride + (long long)t * T.N + x] = canon(s0, p, pinv);
         acc1[ct * astride + (long long)t * T.N + x] = canon(s1, p, pinv);
+        if (wsum) rs.s0[ct * rs.s0_ct + (long long)t * T.N + x] = canon(g0, p, pinv);
     }
 }
 // The same products with every key word of the step held in registers (NR
@@ -442,9 +446,17 @@ __global__ __launch_bounds__(256) void k_inner_product_rot_reg(DevTables T, cons
             k1[r][j] = j < beta ? key_at(K, j * ksj + ksc + ko) : 0.0;
         }
     }
+    const bool wsum = rs.c0 && t <= rs.lq;
     for (int ct = 0; ct < cnt; ++ct) {
         const double *E = ext + ct * esb + (long long)t * T.N;
         double s0 = 0.0, s1 = 0.0;
+        if (wsum) {
+            const double *C0 = rs.c0 + ct * rs.c0_ct + (long long)t * T.N;
+            double g0 = C0[x];
+#pragma unroll
+            for (int r = 0; r < NR; ++r) g0 += C0[src[r]];
+            rs.s0[ct * rs.s0_ct + (long long)t * T.N + x] = canon(g0, p, pinv);
+        }
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
 #pragma unroll
@@ -487,25 +499,6 @@ void launch_inner_product_rot(const DevTables &T, const double *ext, long long e
     else
         KL("k_inner_product_rot", k_inner_product_rot, dim3(xblocks, next), dim3(256), 0, s, T, ext, estride_b,
            estride_j, acc0, acc1, astride, rs, kstride_j, kstride_c, cnt, beta, ext_prime);
-}
-
-// out = in + sum_r sigma_r(in): the c0 part of a hoisted rotate-and-sum step
-__global__ void k_autsum(VecSet out, VecSet in, RotSet rs, DevTables T) {
-    EW_PROLOGUE
-    double *pi; int q1, g1, r1;
-    vs_at(in, blockIdx.y, T.N, pi, q1, g1, r1);
-    const double pinv = T.pinv[pr];
-    double v = pi[x];
-    for (int r = 0; r < rs.nr; ++r) {
-        v += pi[aut_src((unsigned)x, rs.g[r], T.logN)];
-        if ((r & 3) == 3) v = red(v, p, pinv);
-    }
-    po[x] = canon(v, p, pinv);
-}
-void launch_autsum(const DevTables &T, const VecSet &out, const VecSet &in, const RotSet &rs, hipStream_t s) {
-    if (out.count <= 0) return;
-    kprof_set_bytes(8.0 * T.N * out.count * (2.0 + rs.nr));
-    KL("k_autsum", k_autsum, ew_grid(T, out.count), dim3(256), 0, s, out, in, rs, T);
 }
 
 // ModDown conversion: acc holds, at slots in0 .. in0+nin-1 of every group, the
