@@ -113,7 +113,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--graph", type=int, default=0)
+    ap.add_argument("--graph", type=int, default=1,
+                    help="replay each CutMax from a captured HIP graph (1) or launch eagerly (0)")
     ap.add_argument("--hoist", type=int, default=None,
                     help="rotate-and-sum radix log2 (default: the parameter set's)")
     ap.add_argument("--cpu-T", type=int, default=3, help="iterations of the oracle sample (1..3)")
@@ -266,6 +267,7 @@ def main():
                    "global_batch": 1, "seq_len": VOCAB2, "parallelism": "none"},
         "device_ms_median": float(np.median(dev_ms)),
         "rotsum_hoist_log2": prm.hoist,
+        "hip_graph": bool(args.graph),
         "src_digest": digest,
         "argmax_ok": bool(argmax_ok),
         "batched": batch,

@@ -365,8 +365,8 @@ void launch_inner_product(const DevTables &T, const double *ext, long long estri
                           int beta, int next, const int *ext_prime, hipStream_t s, const double *dadd,
                           long long dct, long long dpoly, int tl, double pmodl) {
     if (cnt <= 0) return;
-    // key words once, extended digits and both accumulators per ciphertext
-    kprof_set_bytes(8.0 * T.N * next * (2.0 * beta + cnt * (beta + 2.0)));
+    // key words (6 bytes each) once, extended digits and both accumulators per ciphertext
+    kprof_set_bytes(T.N * next * (6.0 * 2.0 * beta + 8.0 * cnt * (beta + 2.0)));
     KL("k_inner_product", k_inner_product, dim3((T.N + 255) / 256, next), dim3(256), 0, s, T, ext,
                        estride_b, estride_j, acc0, acc1, astride, key, kstride_j, kstride_c, cnt,
                        beta, ext_prime, dadd, dct, dpoly, tl, pmodl);
@@ -481,7 +481,7 @@ void launch_inner_product_rot(const DevTables &T, const double *ext, long long e
     if (cnt <= 0) return;
     // every rotation's key words once; the extended digits and both accumulators
     // once per ciphertext
-    kprof_set_bytes(8.0 * T.N * next * (2.0 * beta * rs.nr + cnt * (beta + 2.0)));
+    kprof_set_bytes(T.N * next * (6.0 * 2.0 * beta * rs.nr + 8.0 * cnt * (beta + 2.0)));
     const int xblocks = (T.N + 255) / 256;
     const dim3 g1(8 * ((next + 7) / 8) * xblocks);
     // one ciphertext: the key stream alone bounds the kernel, and the lighter
