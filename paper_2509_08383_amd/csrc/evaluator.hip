@@ -161,6 +161,7 @@ struct he_ctx {
     // rotate-and-sum: 0 = one rotation at a time, h = hoisted radix-2^h steps
     int hoist = 0;
     std::map<int, int> rot_key;     // rotation amount -> key index
+    std::map<int, const int *> xorder;  // smallest amount of a hoisted step -> x-block orbit order
     std::vector<uint32_t> key_gal;  // key index -> Galois element (0 for relinearisation)
     // graph cache keyed by a signature of the call
     std::map<std::string, hipGraphExec_t> graphs;
@@ -533,6 +534,7 @@ struct Exec {
         REQUIRE(!amounts.empty() && (int)amounts.size() <= kMaxHoist, HE_EINVAL, "hoisted step size");
         RotSet rs{};
         rs.nr = (int)amounts.size();
+        rs.xorder = C->xorder.at(amounts[0]);
         for (int r = 0; r < rs.nr; ++r) {
             auto it = C->rot_key.find(amounts[r]);
             REQUIRE(it != C->rot_key.end(), HE_ESTATE, "no key for a hoisted rotation");
@@ -947,6 +949,33 @@ void build_ctx(he_ctx *C, const he_params *prm) {
         o_nas[l] = tb.i(as);
         o_nap[l] = tb.i(ap);
     }
+    // x-block orders of the hoisted rotate-and-sum steps: the automorphism by
+    // g = 5^k (k = the step's smallest rotation) maps aligned 256-blocks onto aligned
+    // 256-blocks; list the blocks orbit by orbit
+    std::map<int, size_t> o_xord;
+    if (C->hoist >= 1) {
+        const int nb = N / 256;
+        const uint64_t M = 2ull * N;
+        auto brev = [&](uint64_t v) {
+            uint64_t r = 0;
+            for (int b = 0; b < C->logN; ++b) if ((v >> b) & 1) r |= 1ull << (C->logN - 1 - b);
+            return r;
+        };
+        for (const auto &st : hoist_steps(C->slots, C->hoist)) {
+            uint64_t g = 1, b5 = 5;
+            for (uint64_t e = (uint64_t)st[0]; e; e >>= 1, b5 = (b5 * b5) % M)
+                if (e & 1) g = (g * b5) % M;
+            std::vector<int> bm(nb), order;
+            for (int B = 0; B < nb; ++B) {
+                const uint64_t t = (2 * brev((uint64_t)B * 256) + 1) * g % M;
+                bm[B] = (int)(brev((t - 1) / 2) / 256);
+            }
+            std::vector<char> seen(nb, 0);
+            for (int B = 0; B < nb; ++B)
+                for (int x = B; !seen[x]; x = bm[x]) { seen[x] = 1; order.push_back(x); }
+            o_xord[st[0]] = tb.i(order);
+        }
+    }
     HIPCHK(hipMalloc(&C->d_tab, tb.dv.size() * 8));
     HIPCHK(hipMalloc(&C->d_itab, tb.iv.size() * 4));
     HIPCHK(hipMemcpy(C->d_tab, tb.dv.data(), tb.dv.size() * 8, hipMemcpyHostToDevice));
@@ -975,6 +1004,7 @@ void build_ctx(he_ctx *C, const he_params *prm) {
         C->ndall_slot[l] = I + o_nas[l];
         C->ndall_prime[l] = I + o_nap[l];
     }
+    for (const auto &kv : o_xord) C->xorder[kv.first] = I + kv.second;
     C->ext_prime.resize(L + 1);
     C->vinv.assign(L + 1, {}); C->qhat.assign(L + 1, {}); C->ndslot.assign(L + 1, {}); C->ndprime.assign(L + 1, {});
     for (int l = 0; l <= L; ++l) {

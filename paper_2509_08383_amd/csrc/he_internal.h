@@ -154,6 +154,7 @@ struct RotSet {
     double *s0;
     long long s0_ct;
     int lq;
+    const int *xorder;  // the N/256 x-blocks in the orbit order of g[0] (device)
 };
 void launch_inner_product_rot(const DevTables &T, const double *ext, long long estride_b, long long estride_j,
                               double *acc0, double *acc1, long long astride, const RotSet &rs, long long kstride_j,

@@ -377,14 +377,24 @@ void launch_inner_product(const DevTables &T, const double *ext, long long estri
 // K_r[j][c][prime(t)][x], the automorphism of the NTT-domain extended digits being
 // a gather (src_r = aut_src).  The partial sums are reduced after every rotation,
 // so |sum| <= p/2 + beta (p/2 + 2^44) < 2^52 for beta <= 8.
+//
+// An automorphism maps every aligned block of 256 NTT positions onto one aligned
+// block, and the rotations of a step are powers pi^r of its smallest rotation pi, so
+// the sources of x-block X are X, pi(X), .., pi^nr(X).  The grid is one-dimensional
+// and XCD-aware: the 8 XCDs take workgroups round-robin (workgroup b runs on XCD
+// b mod 8); every XCD is given whole targets t and walks a target's x-blocks in the
+// order of their pi-orbits (rs.xorder), so consecutive workgroups on an XCD share all
+// but one of their source blocks and re-read them from L2.
 __global__ __launch_bounds__(256) void k_inner_product_rot(DevTables T, const double *__restrict__ ext,
                                                            long long esb, long long esj, double *__restrict__ acc0,
                                                            double *__restrict__ acc1, long long astride, RotSet rs,
-                                                           long long ksj, long long ksc, int cnt, int beta,
-                                                           const int *__restrict__ ext_prime) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+                                                           long long ksj, long long ksc, int cnt, int beta, int next,
+                                                           const int *__restrict__ ext_prime, int xblocks) {
+    const int b = blockIdx.x, slot = b >> 3;
+    const int t = (b & 7) + 8 * (slot / xblocks);
+    if (t >= next) return;
+    const int x = rs.xorder[slot % xblocks] * blockDim.x + threadIdx.x;
     if (x >= T.N) return;
-    const int t = blockIdx.y;
     const int pt = ext_prime[t];
     const double p = T.p[pt], pinv = T.pinv[pt];
     const long long ko = (long long)pt * T.N + x;
@@ -414,11 +424,8 @@ __global__ __launch_bounds__(256) void k_inner_product_rot(DevTables T, const do
     }
 }
 // The same products with every key word of the step held in registers (NR
-// rotations, at most 3 digits) and reused for every ciphertext of the batch.  The
-// grid is one-dimensional and XCD-aware: the 8 XCDs take workgroups round-robin
-// (workgroup b runs on XCD b mod 8), and every XCD is given whole targets t, all
-// x-blocks of a target one after the other, so the gathered words of a target's
-// extended digits are re-read from that XCD's L2 rather than from HBM.
+// rotations, at most 3 digits) and reused for every ciphertext of the batch, on the
+// same XCD-aware grid.
 template <int NR>
 __global__ __launch_bounds__(256) void k_inner_product_rot_reg(DevTables T, const double *__restrict__ ext,
                                                                long long esb, long long esj,
@@ -429,7 +436,7 @@ __global__ __launch_bounds__(256) void k_inner_product_rot_reg(DevTables T, cons
     const int b = blockIdx.x, slot = b >> 3;
     const int t = (b & 7) + 8 * (slot / xblocks);
     if (t >= next) return;
-    const int x = (slot % xblocks) * blockDim.x + threadIdx.x;
+    const int x = rs.xorder[slot % xblocks] * blockDim.x + threadIdx.x;
     if (x >= T.N) return;
     const int pt = ext_prime[t];
     const double p = T.p[pt], pinv = T.pinv[pt];
@@ -497,8 +504,8 @@ void launch_inner_product_rot(const DevTables &T, const double *ext, long long e
         KL("k_inner_product_rot", k_inner_product_rot_reg<1>, g1, dim3(256), 0, s, T, ext, estride_b, estride_j, acc0,
            acc1, astride, rs, kstride_j, kstride_c, cnt, beta, next, ext_prime, xblocks);
     else
-        KL("k_inner_product_rot", k_inner_product_rot, dim3(xblocks, next), dim3(256), 0, s, T, ext, estride_b,
-           estride_j, acc0, acc1, astride, rs, kstride_j, kstride_c, cnt, beta, ext_prime);
+        KL("k_inner_product_rot", k_inner_product_rot, g1, dim3(256), 0, s, T, ext, estride_b, estride_j, acc0, acc1,
+           astride, rs, kstride_j, kstride_c, cnt, beta, next, ext_prime, xblocks);
 }
 
 // ModDown conversion: acc holds, at slots in0 .. in0+nin-1 of every group, the
