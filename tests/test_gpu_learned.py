@@ -11,7 +11,7 @@ pytestmark = pytest.mark.gpu
 
 from oracle import ckks, mlp_ref  # noqa: E402
 from oracle.cutmax_fp64 import (MirrorCfg, Trace, chebyshev_invsqrt, cutmax_exact, cutmax_mirror,  # noqa: E402
-                                poly_eval, slot_layout)
+                                newton_invsqrt_step, poly_eval, slot_layout)
 from workloads import llm_logits_var  # noqa: E402
 from test_gpu_parity import say  # noqa: E402
 
@@ -116,6 +116,38 @@ def test_learned_guess_beats_chebyshev_at_equal_depth(learned):
         rms.append((rms_l, rms_c))
     assert rms[0][0] < rms[0][1] and rms[2][0] < rms[2][1]
     assert rms[1][0] < 1e-3 and rms[1][1] < 1e-3
+
+
+def _fixed_depth_to_match(u, target_rms, u_lo):
+    """smallest multiplicative depth of a fixed schedule (Chebyshev degree d on [u_lo, 1]
+    followed by k Newton steps) whose RMS relative error on u is at most target_rms"""
+    depth_of = {1: 1, 2: 2, 3: 2, 4: 3}
+    best = None
+    for d in (1, 2, 3, 4):
+        h = poly_eval(chebyshev_invsqrt(u_lo, d), u)
+        for k in range(4):
+            e = float(np.sqrt(np.mean((h * np.sqrt(u) - 1.0) ** 2)))
+            dep = depth_of[d] + 2 * k
+            if e <= target_rms and (best is None or dep < best):
+                best = dep
+            h = newton_invsqrt_step(h, u, 1.0)
+    return best
+
+
+def test_learned_guess_cuts_depth_at_equal_accuracy(learned):
+    """at the held-out RMS error the learned degree-4 guess reaches (depth 3), the fixed
+    Chebyshev + Newton schedule needs more depth where the declared domain is wide
+    (iterations 0 and 2): the learned guess saves multiplicative levels"""
+    coefs, tests, _ = learned
+    saved = []
+    for t in range(3):
+        u = tests[t]
+        e_l = float(np.sqrt(np.mean((poly_eval(coefs[t], u) * np.sqrt(u) - 1.0) ** 2)))
+        dep = _fixed_depth_to_match(u, e_l, VLO5[t] / VHI5[t])
+        say(f"  t={t}: learned rms {e_l:.2e} at depth 3; the fixed schedule needs depth {dep}")
+        saved.append(dep - 3 if dep is not None else None)
+    assert saved[0] is not None and saved[0] >= 1
+    assert saved[2] is not None and saved[2] >= 1
 
 
 def test_cutmax_with_learned_guess_batch16(learned):

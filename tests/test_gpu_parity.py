@@ -279,3 +279,28 @@ def test_cutmax_errors_are_reported(toy):
     with pytest.raises(he.HeError) as e:
         toy.G.cutmax([ct], bad)
     assert e.value.code == he.HE_EINVAL
+
+
+def test_edge_inputs_are_rejected_or_handled(toy):
+    """empty input and mismatched levels are errors; a tied maximum is split evenly, as
+    in the FP64 mirror, and the recovered index is one of the tied entries"""
+    from paper_2509_08383_amd import he
+    with pytest.raises(he.HeError) as e:
+        toy.G.encrypt(np.zeros(0))
+    assert e.value.code == he.HE_EINVAL
+    x = toy_logits(43)
+    a = toy.G.encrypt(x)
+    with pytest.raises(he.HeError) as e:
+        toy.G.add(a, toy.G.drop(a, 3))
+    assert e.value.code in (he.HE_ESTATE, he.HE_EINVAL)
+    # tie: the two largest logits made equal
+    i, j = int(np.argmax(x)), int(np.argsort(x)[-2])
+    x[j] = x[i]
+    y, _, _ = slot_layout(x, toy.G.slots)
+    p, c, vlo, vhi, coef = toy_cfg(y.size)
+    cfg = he.CutmaxCfg(T=4, p=p, c=c, var_lo=vlo, var_hi=vhi, init_degree=3, init_coef=coef, sum_lo=1.0,
+                       sum_hi=3.0, gold_d=3)
+    z = toy.G.decrypt(toy.G.cutmax([toy.G.encrypt(x)], cfg)[0], y.size)
+    mc = MirrorCfg(T=4, p=p, c=c, v_hi=vhi, v_lo=vlo, coef=coef, B=3.0 * y.size, gold_d=3, sum_lo=1.0 * y.size)
+    assert np.abs(z - cutmax_mirror(y, mc)).max() < 1e-3
+    assert int(np.argmax(z[:x.size])) in (i, j)

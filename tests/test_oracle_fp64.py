@@ -5,7 +5,7 @@ import os
 import numpy as np
 import pytest
 
-from oracle.cutmax_fp64 import (MirrorCfg, Trace, beta_alpha, beta_noise, chebyshev_invsqrt,
+from oracle.cutmax_fp64 import (DomainError, MirrorCfg, Trace, beta_alpha, beta_noise, chebyshev_invsqrt,
                                 cutmax_exact, cutmax_mirror, delta_gap, gap_ratio,
                                 goldschmidt_factor, newton_invsqrt_step, nucleus_argmax,
                                 nucleus_set, poly_eval, semi_standardize, slot_layout, tmin)
@@ -187,3 +187,30 @@ def test_nucleus_helpers():
     assert set(s.tolist()) == {0, 1}
     assert nucleus_argmax(x, np.zeros(4), 0.8) == 0
     assert nucleus_argmax(x, np.array([0, 0.2, 0, 0]), 1.0) == 1
+
+
+def test_tied_maxima_share_the_mass_equally():
+    """Alg. 1 is permutation-equivariant, so entries with equal logits get equal outputs:
+    two tied maxima (a zero gap, the degenerate case) get the same, largest, value"""
+    x = llm_logits(7, 4000)
+    i, j = int(np.argmax(x)), int(np.argsort(x)[-2])
+    x[j] = x[i]
+    Z = cutmax_exact(x, 4, 5.0, 3)
+    assert Z[i] == Z[j]
+    assert Z[i] > np.delete(Z, [i, j]).max()
+
+
+def test_constant_input_leaves_the_declared_domain():
+    """all logits equal: the variance is 0, outside every declared invsqr domain; the
+    mirror refuses rather than evaluating the polynomial outside its interval"""
+    y = np.full(2048, 0.3)
+    cfg = MirrorCfg(T=1, p=[3], c=[5.0], v_hi=[2.0], v_lo=[0.5], coef=[chebyshev_invsqrt(0.25, 3)], B=3.0 * 2048,
+                    gold_d=3, sum_lo=1.0 * 2048)
+    with pytest.raises(DomainError):
+        cutmax_mirror(y, cfg)
+
+
+def test_single_logit_is_its_own_argmax():
+    """n = 1: the only entry gets all the mass"""
+    Z = cutmax_exact(np.array([2.5, 0.0, 0.0, 0.0]), 3, 5.0, 3)
+    assert int(np.argmax(Z)) == 0 and abs(Z.sum() - 1.0) < 1e-12
