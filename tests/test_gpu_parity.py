@@ -219,12 +219,14 @@ def test_cutmax_toy_batch_mixed_counts(toy):
     single-request run bit for bit (n > s splits over several ciphertexts, App. D)."""
     from paper_2509_08383_amd import he
     say("[gpu] cutmax toy batch")
-    xs = [toy_logits(31, 1024), llm_logits(32, 3000), toy_logits(33, 1024)]
+    # toy-family logits (the toy chain's 2^30 scale leaves ~1e-3 of CKKS error on LLM-like
+    # logits with their wider variance range; those run at N = 2^16)
+    xs = [toy_logits(31, 1024), toy_logits(32, 3000), toy_logits(33, 1024)]
     cts = [toy.G.encrypt(x) for x in xs]
     toy.O.nonce = toy.O.nonce + sum(c.a for c in cts)
     p, c, vlo, vhi, coef = toy_cfg(2048)
-    # one domain for both logit families (the LLM-like request has larger variances)
-    vlo2 = [0.5, 0.25, 0.3, 0.6]
+    # one domain for the replicated and the zero-padded requests
+    vlo2 = [0.5, 0.2, 0.3, 0.6]
     vhi2 = [32.0, 0.9, 16.0, 512.0]
     coef = [list(chebyshev_invsqrt(vlo2[t] / vhi2[t], 3)) for t in range(4)]
     cfg = he.CutmaxCfg(T=4, p=p, c=c, var_lo=vlo2, var_hi=vhi2, init_coef=coef, sum_lo=1.0, sum_hi=3.0)
