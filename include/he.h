@@ -146,6 +146,19 @@ int he_topp_sample(he_ctx *ctx, he_ct *const *logits, he_ct *const *noise, size_
  * alpha = ln(1 - top_p)/ln(top_p), from the caller's uniform draws u. */
 int he_topp_noise(double top_p, const double *u, size_t n, double *g);
 
+/* Server: Gumbel-max sampling (Sec. 3.3, "Using Gumbel Distribution" and the
+ * Gumbel-max lemma): CutMax(X + temperature * G), G the client's encrypted
+ * Gumbel(0,1) noise (see he_gumbel_noise); the one-hot approximates a draw
+ * from softmax(X / temperature).  Same packing, flags (HE_NOISE_PRESCALED) and
+ * errors as he_topp_sample; the declared variance domains of cfg must cover
+ * X + temperature * G. */
+int he_gumbel_sample(he_ctx *ctx, he_ct *const *logits, he_ct *const *noise, size_t batch, double temperature,
+                     const he_cutmax_cfg *cfg, he_ct **out);
+
+/* Client helper (Sec. 3.3, Gumbel definition): g[i] = -ln(-ln u[i]) from the
+ * caller's uniform draws u[i] in (0, 1). */
+int he_gumbel_noise(const double *u, size_t n, double *g);
+
 void he_ct_free(he_ct *ct);
 const char *he_last_error(void);
 

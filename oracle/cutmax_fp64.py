@@ -238,8 +238,23 @@ def beta_noise(u: np.ndarray, alpha: float) -> np.ndarray:
 
 
 def nucleus_argmax(x: np.ndarray, g: np.ndarray, temperature: float) -> int:
-    """The token the one-shot sampler selects: argmax(x/temperature + G) (Alg. 3)."""
+    """The token a one-shot sampler selects: argmax(x/temperature + G) (Alg. 3 with Beta
+    noise; the Gumbel-max trick of Sec. 3.3 with Gumbel noise)."""
     return int(np.argmax(np.asarray(x) / temperature + np.asarray(g)))
+
+
+def gumbel_noise(u: np.ndarray) -> np.ndarray:
+    """G = -ln(-ln U) turns U ~ Uniform(0,1) into Gumbel(0,1) (Sec. 3.3, Gumbel definition)."""
+    return -np.log(-np.log(np.asarray(u, dtype=np.float64)))
+
+
+def violation_rate(x: np.ndarray, picks: Sequence[int], top_p: float, temperature: float = 1.0) -> float:
+    """Fraction of sampled tokens outside the top-p nucleus of softmax(x/temperature)
+    (the measure of Sec. 4, "Nucleus Sampling", Fig. 4)."""
+    inside = np.zeros(np.asarray(x).size, dtype=bool)
+    inside[nucleus_set(x, top_p, temperature)] = True
+    picks = np.asarray(picks, dtype=np.int64)
+    return float(1.0 - inside[picks].mean()) if picks.size else 0.0
 
 
 def nucleus_set(x: np.ndarray, top_p: float, temperature: float = 1.0) -> np.ndarray:

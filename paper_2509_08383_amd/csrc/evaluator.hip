@@ -1564,6 +1564,27 @@ int he_topp_noise(double top_p, const double *u, size_t n, double *g) {
     });
 }
 
+int he_gumbel_sample(he_ctx *C, he_ct *const *logits, he_ct *const *noise, size_t batch, double temperature,
+                     const he_cutmax_cfg *cfg, he_ct **out) {
+    return guarded([&]() {
+        REQUIRE(C && noise, HE_EINVAL, "null argument");
+        REQUIRE(temperature > 0, HE_EINVAL, "temperature > 0");
+        HIPCHK(hipSetDevice(C->device));
+        return cutmax_impl(C, logits, noise, batch, cfg, temperature, out);
+    });
+}
+
+int he_gumbel_noise(const double *u, size_t n, double *g) {
+    return guarded([&]() {
+        REQUIRE(u && g, HE_EINVAL, "bad argument");
+        for (size_t i = 0; i < n; ++i) {
+            REQUIRE(u[i] > 0 && u[i] < 1, HE_EINVAL, "uniform draws must lie in (0, 1)");
+            g[i] = -std::log(-std::log(u[i]));
+        }
+        return HE_OK;
+    });
+}
+
 void he_ct_free(he_ct *ct) {
     if (!ct) return;
     if (ct->d) hipFree(ct->d);

@@ -68,6 +68,9 @@ def lib():
             "he_topp_sample": [_V, ctypes.POINTER(_V), ctypes.POINTER(_V), ctypes.c_size_t, ctypes.c_double,
                                ctypes.c_double, ctypes.POINTER(_Cfg), ctypes.POINTER(_V)],
             "he_topp_noise": [ctypes.c_double, _c_dp, ctypes.c_size_t, _c_dp],
+            "he_gumbel_sample": [_V, ctypes.POINTER(_V), ctypes.POINTER(_V), ctypes.c_size_t, ctypes.c_double,
+                                 ctypes.POINTER(_Cfg), ctypes.POINTER(_V)],
+            "he_gumbel_noise": [_c_dp, ctypes.c_size_t, _c_dp],
             "he_ct_info": [_V, _c_u32p, _c_u32p, _c_dp, ctypes.POINTER(ctypes.c_size_t)],
             "he_ct_export": [_V, _V, _c_u64p, ctypes.c_size_t],
             "he_ct_import": [_V, _c_u64p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_double, ctypes.c_size_t,
@@ -289,6 +292,16 @@ class Context:
         _check(lib().he_topp_sample(self.h, ins, nz, B, top_p, temperature, ctypes.byref(s), outs))
         return [Ciphertext(self, _V(o)) for o in outs]
 
+    def gumbel_sample(self, logits: List[Ciphertext], noise: List[Ciphertext], temperature: float,
+                      cfg: CutmaxCfg) -> List[Ciphertext]:
+        B = len(logits)
+        ins = (_V * B)(*[c.h for c in logits])
+        nz = (_V * B)(*[c.h for c in noise])
+        outs = (_V * B)()
+        s = cfg.c_struct()
+        _check(lib().he_gumbel_sample(self.h, ins, nz, B, temperature, ctypes.byref(s), outs))
+        return [Ciphertext(self, _V(o)) for o in outs]
+
     def _op(self, name, *args):
         h = _V()
         _check(getattr(lib(), name)(self.h, *args, ctypes.byref(h)))
@@ -459,6 +472,14 @@ def variance_log(seed: int, runs: int, vocab: int = 32000, slots: int = 32768, T
     ym = np.empty(runs, dtype=np.float32)
     _mcheck(_mlp_lib().he_variance_log(seed, runs, vocab, slots, T, p, c, device, _fp(v), _fp(ym)))
     return v, ym
+
+
+def gumbel_noise(u: np.ndarray) -> np.ndarray:
+    """Client helper: G = -ln(-ln U) (Sec. 3.3, Gumbel definition)."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    g = np.empty_like(u)
+    _check(lib().he_gumbel_noise(_dp(u), u.size, _dp(g)))
+    return g
 
 
 def topp_noise(top_p: float, u: np.ndarray) -> np.ndarray:

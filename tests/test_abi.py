@@ -49,6 +49,20 @@ def test_topp_noise_is_host_only():
         he.topp_noise(1.5, u)
 
 
+def test_gumbel_noise_is_host_only():
+    """he_gumbel_noise needs no GPU: G = -ln(-ln U) (Sec. 3.3); U outside (0, 1) is an error."""
+    _ensure_built()
+    import numpy as np
+    from paper_2509_08383_amd import he
+    from oracle.cutmax_fp64 import gumbel_noise
+    from workloads import uniform_noise
+    u = uniform_noise(5, 1000)
+    np.testing.assert_allclose(he.gumbel_noise(u), gumbel_noise(u), rtol=1e-13, atol=1e-14)
+    for bad in (0.0, 1.0):
+        with pytest.raises(he.HeError):
+            he.gumbel_noise(np.array([0.5, bad]))
+
+
 def test_errors_without_gpu_are_loud():
     """Creating a context without a GPU fails with an error, never a silent fallback."""
     _ensure_built()

@@ -7,9 +7,9 @@ import pytest
 
 from oracle.cutmax_fp64 import (DomainError, MirrorCfg, Trace, beta_alpha, beta_noise, chebyshev_invsqrt,
                                 cutmax_exact, cutmax_mirror, delta_gap, gap_ratio,
-                                goldschmidt_factor, newton_invsqrt_step, nucleus_argmax,
-                                nucleus_set, poly_eval, semi_standardize, slot_layout, tmin)
-from workloads import llm_logits, toy_logits, uniform_noise
+                                goldschmidt_factor, gumbel_noise, newton_invsqrt_step, nucleus_argmax,
+                                nucleus_set, poly_eval, semi_standardize, slot_layout, tmin, violation_rate)
+from workloads import llm_logits, llm_logits_var, toy_logits, uniform_noise
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -214,3 +214,64 @@ def test_single_logit_is_its_own_argmax():
     """n = 1: the only entry gets all the mass"""
     Z = cutmax_exact(np.array([2.5, 0.0, 0.0, 0.0]), 3, 5.0, 3)
     assert int(np.argmax(Z)) == 0 and abs(Z.sum() - 1.0) < 1e-12
+
+
+def test_gumbel_definition_gives_the_standard_gumbel_law():
+    """G = -ln(-ln U) (Sec. 3.3) has CDF exp(-exp(-g)), mean Euler's gamma and variance
+    pi^2/6; a dropped or misplaced minus sign moves the mean to -gamma or yields NaNs."""
+    M = 400000
+    g = gumbel_noise(uniform_noise(11, M))
+    assert np.isfinite(g).all()
+    for t in (-1.0, 0.0, 0.5, 2.0, 5.0):
+        F = math.exp(-math.exp(-t))
+        assert abs(float((g <= t).mean()) - F) < 4 * math.sqrt(F * (1 - F) / M)
+    assert abs(g.mean() - 0.5772156649015329) < 4 * math.sqrt(math.pi ** 2 / 6 / M)
+    assert abs(g.var() - math.pi ** 2 / 6) < 0.03
+
+
+@pytest.mark.parametrize("tau", [1.0, 0.5])
+def test_gumbel_max_lemma_frequencies(tau):
+    """Gumbel-max trick (Sec. 3.3): argmax(x/tau + G) is distributed as softmax(x/tau);
+    the closed-form probabilities bound the sampled frequencies."""
+    x = np.array([1.0, 0.3, -0.4, 1.6, 0.0])
+    M = 200000
+    G = gumbel_noise(uniform_noise(21, M * x.size)).reshape(M, x.size)
+    picks = np.argmax(x / tau + G, axis=1)
+    freq = np.bincount(picks, minlength=x.size) / M
+    pr = np.exp(x / tau - (x / tau).max())
+    pr /= pr.sum()
+    assert np.all(np.abs(freq - pr) < 4 * np.sqrt(pr * (1 - pr) / M) + 1e-12)
+    assert nucleus_argmax(x, G[0], tau) == picks[0]
+
+
+def test_violation_rate_fig4_analogue():
+    """Violation rate at p = 0.9 (Sec. 4, "Nucleus Sampling", Fig. 4) on synthetic LLM-like
+    logits: Gumbel-max violates at the rate 1 - (nucleus mass) predicts (the Gumbel-max
+    trick samples softmax exactly), and the Beta-cut sampler never violates, since its
+    noise lies in [0, 1] and every token within 1 of the maximum is inside the nucleus."""
+    S, N, P = 40, 60, 0.9
+    al = beta_alpha(P)
+    vg, expect, var, vb = [], [], 0.0, []
+    for s in range(S):
+        x = llm_logits_var(5000 + s)
+        ns = nucleus_set(x, P)
+        pr = np.exp(x - x.max())
+        pr /= pr.sum()
+        m_out = 1.0 - pr[ns].sum()
+        expect.append(m_out)
+        var += m_out * (1 - m_out) / N
+        U = uniform_noise(9000 + s, N * x.size).reshape(N, x.size)
+        vg.append(violation_rate(x, np.argmax(x + gumbel_noise(U), axis=1), P))
+        pb = np.argmax(x + beta_noise(U, al), axis=1)
+        assert np.all(x[pb] >= x.max() - 1.0)
+        assert set(np.nonzero(x >= x.max() - 1.0)[0].tolist()) <= set(ns.tolist())
+        vb.append(violation_rate(x, pb, P))
+    assert abs(np.mean(vg) - np.mean(expect)) < 4 * math.sqrt(var) / S
+    assert 0.0 < np.mean(vg) < 1 - P
+    assert max(vb) == 0.0
+
+
+def test_violation_rate_counts_outside_picks():
+    x = np.array([5.0, 4.9, 1.0, -3.0])
+    assert violation_rate(x, [0, 1, 2, 3], 0.9) == 0.5
+    assert violation_rate(x, [], 0.9) == 0.0
