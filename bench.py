@@ -104,6 +104,80 @@ def ks_cost(levels, alpha):
     return tot
 
 
+def _nucleus_mask(x: np.ndarray, top_p: float):
+    """Membership of the smallest top-ranked set whose softmax mass reaches top_p, and the
+    softmax mass outside it."""
+    pr = np.exp(x - x.max())
+    pr /= pr.sum()
+    order = np.argsort(-pr)
+    k = int(np.searchsorted(np.cumsum(pr[order]), top_p) + 1)
+    m = np.zeros(x.size, dtype=bool)
+    m[order[:k]] = True
+    return m, 1.0 - float(pr[m].sum())
+
+
+def violation_main(spec: str, graph: int):
+    """Violation rate of the encrypted Gumbel-max and Beta-cut samplers (Sec. 4, "Nucleus
+    Sampling", Fig. 4): S synthetic prompts x D draws each at top_p = 0.9 and temperature 1,
+    16 requests per call; a pick is the argmax of the decrypted one-hot."""
+    import torch
+    from paper_2509_08383_amd import he
+    from workloads import llm_logits_var, uniform_noise
+
+    assert torch.cuda.is_available(), "no GPU"
+    S, D = (int(v) for v in spec.split(","))
+    top_p = 0.9
+    ctx = he.Context(he.SECURE, device=0)
+    if graph:
+        ctx.set_option(he.HE_OPT_GRAPH, 1)
+    # with the per-prompt Gumbel scale and Zipf exponent of this logit family, the variances
+    # of the three iterations span about [6, 37], [0.33, 0.77] and [1, 116]
+    vlo, vhi = [5.0, 0.3, 0.6], [48.0, 1.0, 128.0]
+    cfg = he.CutmaxCfg(T=T, p=[P] * T, c=[C] * T, var_lo=vlo, var_hi=vhi, init_degree=3, init_coef=None,
+                       newton_steps=0, sum_lo=1.0, sum_hi=4.0, gold_d=3, flags=he.HE_NOISE_PRESCALED)
+    xs = [llm_logits_var(5000 + s) for s in range(S)]
+    masks = [_nucleus_mask(x, top_p) for x in xs]
+    cts = [ctx.encrypt(x) for x in xs]
+    rate = {"gumbel": np.zeros(S), "beta_cut": np.zeros(S)}
+    agree, calls, t_he, miss_gaps = 0, 0, 0.0, []
+    for d in range(D):
+        for b0 in range(0, S, 16):
+            idx = list(range(b0, min(S, b0 + 16)))
+            us = [uniform_noise(9000 + 1000 * s + d, xs[s].size) for s in idx]
+            for kind in ("gumbel", "beta_cut"):
+                gs = [he.gumbel_noise(u) if kind == "gumbel" else he.topp_noise(top_p, u) for u in us]
+                nz = [ctx.encrypt(g) for g in gs]
+                ins = [cts[s] for s in idx]
+                ctx.sync()
+                t0 = time.perf_counter()
+                Z = ctx.gumbel_sample(ins, nz, 1.0, cfg) if kind == "gumbel" else \
+                    ctx.topp_sample(ins, nz, top_p, 1.0, cfg)
+                ctx.sync()
+                t_he += time.perf_counter() - t0
+                calls += len(idx)
+                for j, s in enumerate(idx):
+                    pick = int(np.argmax(ctx.decrypt(Z[j], xs[s].size)))
+                    w = xs[s] + gs[j]
+                    if pick == int(np.argmax(w)):
+                        agree += 1
+                    else:
+                        top = np.sort(w)[-2:]
+                        miss_gaps.append(float(top[1] - top[0]))
+                    rate[kind][s] += float(not masks[s][0][pick]) / D
+        log(f"[violation] draw {d + 1}/{D} done")
+    out = {"metric": "violation rate outside the top-p nucleus", "top_p": top_p, "temperature": 1.0,
+           "prompts": S, "draws_per_prompt": D, "data": "synthetic",
+           "workload": "32000 LLM-like logits per prompt (Gumbel scale ~U[1.5,4.5], Zipf exponent ~U[0.9,1.3]), "
+                       "N=2^16 RNS-CKKS 128-bit, T=3, p=3, c=5",
+           "gumbel_max": {"mean": float(rate["gumbel"].mean()), "std": float(rate["gumbel"].std()),
+                          "expected": float(np.mean([m[1] for m in masks]))},
+           "beta_cut": {"mean": float(rate["beta_cut"].mean()), "std": float(rate["beta_cut"].std())},
+           "encrypted_pick_equals_plaintext_pick": f"{agree}/{2 * S * D}",
+           "top2_input_gap_of_mismatches": sorted(miss_gaps),
+           "ms_per_sample": t_he * 1e3 / calls}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,11 +192,17 @@ def main():
     ap.add_argument("--hoist", type=int, default=None,
                     help="rotate-and-sum radix log2 (default: the parameter set's)")
     ap.add_argument("--cpu-T", type=int, default=3, help="iterations of the oracle sample (1..3)")
+    ap.add_argument("--violation", metavar="S,D", default=None,
+                    help="instead of the CutMax benchmark, measure the violation rate of the encrypted "
+                         "Gumbel-max and Beta-cut samplers over S prompts x D draws")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 "
                           "(requests shard across GPUs with no exchange between them)"}))
         sys.exit(2)
+    if args.violation:
+        violation_main(args.violation, args.graph)
+        return
 
     import torch
     from paper_2509_08383_amd import he

@@ -58,11 +58,12 @@ def test_encrypted_violation_counts():
     say("[gpu] encrypted violation counts, 4 prompts x 4 draws x 2 samplers")
     P, S, D = 0.9, 4, 4
     G = he.Context(he.SECURE)
-    # the per-prompt Gumbel scale of these logits spreads the first variance over [6, 18]
-    vlo, vhi = [4.0, 0.3, 0.6], [32.0, 1.0, 16.0]
+    # with the per-prompt Gumbel scale and Zipf exponent of these logits, the variances of
+    # the three iterations span about [6, 37], [0.33, 0.77] and [1, 116]
+    vlo, vhi = [5.0, 0.3, 0.6], [48.0, 1.0, 128.0]
     cfg = he.CutmaxCfg(T=3, p=[3] * 3, c=[5.0] * 3, var_lo=vlo, var_hi=vhi,
                        init_coef=[list(chebyshev_invsqrt(vlo[t] / vhi[t], 3)) for t in range(3)], sum_lo=1.0,
-                       sum_hi=3.0, gold_d=3, flags=he.HE_NOISE_PRESCALED)
+                       sum_hi=4.0, gold_d=3, flags=he.HE_NOISE_PRESCALED)
     al = beta_alpha(P)
     xs = [llm_logits_var(5000 + s) for s in range(S)]
     cts = [G.encrypt(x) for x in xs]
