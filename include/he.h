@@ -82,12 +82,17 @@ typedef struct {
  *     in 1..4) of the initial guess g(u) ~ u^(-1/2), T rows of d+1 values.
  *     NULL: the library interpolates u^(-1/2) at Chebyshev nodes on
  *     [var_lo/var_hi, 1].
- *   newton_steps: Newton refinements h <- 1.5h - 0.5 u h^3 (2 levels each).
+ *   newton_steps: refinements of the initial guess: Newton's
+ *     h <- 1.5h - 0.5 u h^3 (2 levels each), or, with HE_REFINE_GOLDSCHMIDT,
+ *     Goldschmidt's coupled inverse-square-root iteration (App. B.1 cites it
+ *     for invsqr): r = 1.5 - b/2, h <- h r, b <- b r^2 from b = u h^2
+ *     (2 levels each plus 1 for the first b).
  *   sum_lo/sum_hi: declared bounds of mean(Y^(T)); the final inverse runs
  *     Goldschmidt's product (App. B.1) with gold_d squarings on
  *     sum/(sum_hi * n).
- *   flags: HE_NOISE_PRESCALED (he_topp_sample: the noise already carries the
- *     temperature). */
+ *   flags: HE_NOISE_PRESCALED (he_topp_sample, he_gumbel_sample: the noise
+ *     already carries the temperature); HE_REFINE_GOLDSCHMIDT (see
+ *     newton_steps). */
 typedef struct {
     uint32_t T;
     const uint32_t *p;
@@ -104,6 +109,7 @@ typedef struct {
 } he_cutmax_cfg;
 
 #define HE_NOISE_PRESCALED 1u
+#define HE_REFINE_GOLDSCHMIDT 2u
 
 /* Context: prime chain, twiddle and basis-conversion tables, secret key, and
  * the relinearisation and rotation keys (rotation by 2^r slots for every r <

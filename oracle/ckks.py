@@ -439,14 +439,30 @@ class Oracle:
                     acc = self.mul(self.drop(acc, lv), self.drop(pw[i], lv))
         return acc
 
-    def invsqr(self, U: Ct, coef: Sequence[float], C: float, newton: int, s_final: float) -> Ct:
+    def invsqr(self, U: Ct, coef: Sequence[float], C: float, newton: int, s_final: float,
+               goldschmidt: bool = False) -> Ct:
         """Initial-guess polynomial sum_k coef[k] u^k (coefficients already times C) plus
-        Newton steps h <- 1.5 h - (0.5/C^2) u h^3, landing at scale s_final."""
+        `newton` refinements landing at scale s_final: Newton steps
+        h <- 1.5 h - (0.5/C^2) u h^3, or Goldschmidt's coupled iteration for the inverse
+        square root (App. B.1): with y = h/C and b = u y^2,  r = (3 - b)/2,  y <- y r,
+        b <- b r^2; here b is carried halved (b' = b/2, r = 1.5 - b')."""
         d = len(coef) - 1
         q = self.q
         lu = U.level
         su = U.scale
         S = s_final if newton == 0 else self.Delta
+        if goldschmidt and newton > 0:
+            # the scale of h is multiplied by scale(r_k)/q at every update; pick the
+            # starting scale so that the last update lands on s_final
+            lh0 = lu - {1: 1, 2: 2, 3: 2, 4: 3}[d]
+            lev, s_b, factor = lh0 - 2, self.Delta, 1.0
+            for k in range(newton):
+                if k > 0:
+                    s_r2 = s_b * s_b / float(q[lev])
+                    s_b = s_b * s_r2 / float(q[lev - 1])
+                    lev -= 2
+                factor = factor * s_b / float(q[lev])
+            S = s_final / factor
         if d == 1:
             H = self.add_const(self.cm_target(U, coef[1], S), coef[0])
         elif d == 2:
@@ -475,6 +491,20 @@ class Oracle:
             H = self.add_const(self.add(self.add(self.add(T4, T3), T2), T1), coef[0])
         else:
             raise SchedError("initial-guess degree must be 1..4")
+        if goldschmidt and newton > 0:
+            lh = H.level
+            G2 = self.mul(H, H)                                    # h^2
+            sA = (self.Delta * float(q[lh - 1])) / G2.scale
+            A = self.drop(self.cm_target(U, 0.5 / (C * C), sA), lh - 1)
+            Bh = self.mul(A, G2)                                   # b'_0 = u h^2 / (2 C^2)
+            R = self.add_const(self.mul_int(Bh, -1), 1.5)          # r_0
+            H = self.mul(self.drop(H, R.level), R)                 # h_1 = h_0 r_0
+            for _ in range(1, newton):
+                R2 = self.mul(R, R)
+                Bh = self.mul(self.drop(Bh, R2.level), R2)         # b'_k = b'_{k-1} r^2
+                R = self.add_const(self.mul_int(Bh, -1), 1.5)
+                H = self.mul(self.drop(H, R.level), R)
+            return H
         for it in range(newton):
             St = s_final if it == newton - 1 else self.Delta
             lh, sh = H.level, H.scale
@@ -488,8 +518,10 @@ class Oracle:
         return H
 
 
-def invsqr_depth(degree: int, newton: int) -> int:
-    return {1: 1, 2: 2, 3: 2, 4: 3}[degree] + 2 * newton
+def invsqr_depth(degree: int, newton: int, goldschmidt: bool = False) -> int:
+    """Levels of the initial guess plus its refinements; Goldschmidt's first b = u h^2
+    needs h^2 before the first update, one level more than Newton's steps."""
+    return {1: 1, 2: 2, 3: 2, 4: 3}[degree] + 2 * newton + (1 if goldschmidt and newton > 0 else 0)
 
 
 @dataclass
@@ -502,6 +534,7 @@ class HECfg:
     v_hi: Sequence[float]
     coef: Sequence[Sequence[float]]   # per iteration, power basis of g(u) ~ u^(-1/2), u = var/v_hi
     newton: int = 0
+    goldschmidt: bool = False          # refinements by Goldschmidt's iteration instead of Newton's
     sum_lo: float = 1.0                # bounds of mean(y^(T)) = sum/n
     sum_hi: float = 3.0
     gold_d: int = 3
@@ -509,7 +542,8 @@ class HECfg:
     def levels_needed(self) -> int:
         lv = 0
         for t in range(self.T):
-            lv += 2 + invsqr_depth(len(self.coef[t]) - 1, self.newton) + 1 + (int(self.p[t]).bit_length() - 1) \
+            lv += 2 + invsqr_depth(len(self.coef[t]) - 1, self.newton, self.goldschmidt) + 1 \
+                + (int(self.p[t]).bit_length() - 1) \
                 + (1 if bin(int(self.p[t])).count("1") > 1 else 0)
         return lv + self.gold_d + 3
 
@@ -526,12 +560,12 @@ def cutmax_he(O: Oracle, Y: List[Ct], cfg: HECfg, rotsum_cache=None) -> List[Ct]
         F = [O.mul(e, e) for e in E]
         U = O.rotsum(O.sum_list(F))
         C = math.sqrt(float(n)) / cfg.c[t]
-        lh = U.level - invsqr_depth(len(cfg.coef[t]) - 1, cfg.newton)
+        lh = U.level - invsqr_depth(len(cfg.coef[t]) - 1, cfg.newton, cfg.goldschmidt)
         if lh < 1:
             raise SchedError("chain too short")
         sE = E[0].scale
         S_H = (O.Delta * float(O.q[lh])) / sE
-        H = O.invsqr(U, [g * C for g in cfg.coef[t]], C, cfg.newton, S_H)
+        H = O.invsqr(U, [g * C for g in cfg.coef[t]], C, cfg.newton, S_H, cfg.goldschmidt)
         Yn = [O.add_const(O.mul(O.drop(e, H.level), H), 1.0) for e in E]
         Y = [O.power(y, int(cfg.p[t])) for y in Yn]
     S = O.rotsum(O.sum_list(Y))

@@ -136,6 +136,19 @@ def newton_invsqrt_step(h, u, C: float):
     return 1.5 * h - (0.5 / (C * C)) * u * h * h * h
 
 
+def goldschmidt_invsqrt(x, y0, K: int):
+    """Goldschmidt's inverse-square-root iteration (the invsqr method App. B.1 cites):
+    b_0 = x y_0^2;  r_k = (3 - b_k)/2;  y_{k+1} = y_k r_k;  b_{k+1} = b_k r_k^2.
+    y_K approximates 1/sqrt(x); b_k stays equal to x y_k^2."""
+    y = y0
+    b = x * y0 * y0
+    for _ in range(K):
+        r = (3.0 - b) / 2.0
+        y = y * r
+        b = b * r * r
+    return y
+
+
 # ----------------------------------------------------------------------------
 # Algorithm 2 mirrored in the clear
 # ----------------------------------------------------------------------------
@@ -148,7 +161,8 @@ class MirrorCfg:
     v_lo: Sequence[float]          # lower bound (checked, used for the default fit)
     coef: Sequence[Sequence[float]]  # initial guess g(u) ~ u^(-1/2) per iteration, power basis
     #                                  in u = var/v_hi; the schedule multiplies by C_t = sqrt(n)/c_t
-    newton: int = 0                # Newton steps after the initial guess
+    newton: int = 0                # refinement steps after the initial guess
+    goldschmidt: bool = False      # refine with Goldschmidt's iteration instead of Newton's
     B: float = 1.0                 # final sum is mapped to x = S/B in (0, 1]
     gold_d: int = 3                # Goldschmidt degree (d+1 factors)
     sum_lo: float = 0.0
@@ -165,7 +179,7 @@ def cutmax_mirror(y0: np.ndarray, cfg: MirrorCfg, check: bool = True,
     Per iteration (Alg. 2 lines 3-7, with the constants folded as the
     encrypted schedule folds them):
         u  = var / v_hi                     (variance mapped into (0, 1])
-        h  = poly(u) [+ Newton steps]       ~ (sqrt(n)/c) / sqrt(u)
+        h  = poly(u) [+ Newton or Goldschmidt steps]  ~ (sqrt(n)/c) / sqrt(u)
         z  = (y - mu) / sqrt(n v_hi) * h + 1   == (y - mu)/(c sigma) + 1 when h is exact
         y  = z^p
     then (Alg. 2 line 8) Z = (y / B) * prod_i (1 + e^(2^i)),  e = 1 - sum(y)/B.
@@ -180,8 +194,11 @@ def cutmax_mirror(y0: np.ndarray, cfg: MirrorCfg, check: bool = True,
         u = var / cfg.v_hi[t]
         C = math.sqrt(n) / cfg.c[t]
         h = poly_eval([g * C for g in cfg.coef[t]], u)
-        for _ in range(cfg.newton):
-            h = newton_invsqrt_step(h, u, C)
+        if cfg.goldschmidt:
+            h = C * goldschmidt_invsqrt(u, h / C, cfg.newton)
+        else:
+            for _ in range(cfg.newton):
+                h = newton_invsqrt_step(h, u, C)
         z = (y - mu) / math.sqrt(n * cfg.v_hi[t]) * h + 1.0
         if trace is not None:
             trace.mean.append(float(mu))

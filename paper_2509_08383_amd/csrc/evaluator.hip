@@ -575,19 +575,54 @@ struct Exec {
 // ------------------------------------------------------------- CutMax plan
 struct Request { int first, a; int64_t n; };
 
-int invsqr_depth(int degree, int newton) {
+// Goldschmidt's coupled iteration costs one level more than Newton's: its first
+// product u h^2 needs h^2 before the update multiplies h
+int invsqr_depth(int degree, int newton, bool gold) {
     static const int d[5] = {0, 1, 2, 2, 3};
-    return d[degree] + 2 * newton;
+    return d[degree] + 2 * newton + (gold && newton > 0 ? 1 : 0);
+}
+
+// Goldschmidt refinement of h ~ C u^(-1/2) (the inverse-square-root iteration the
+// paper's App. B.1 cites): with b = u (h/C)^2 kept as b' = b/2,
+//   r_k = 1.5 - b'_k,  h_{k+1} = h_k r_k,  b'_{k+1} = b'_k r_k^2.
+// It equals Newton's iteration in exact arithmetic (b_k = u h_k^2 / C^2 is invariant).
+// b'_0 is computed at scale Delta; the initial guess's scale is chosen on the host so
+// that the last h lands at s_final.
+struct GoldPlan { std::vector<double> s_init; };
+
+GoldPlan gold_plan(const he_ctx *C, int lh, int K, const std::vector<double> &s_final) {
+    // scale factors of h through the K updates, independent of the starting scale
+    const auto &q = C->q;
+    const double D = C->Delta;
+    double f = 1.0, sb = D, sr = D;
+    int lr = lh - 2;
+    f = f * sr / (double)q[lr];                     // h_1 = h_0 r_0 at level lh-2
+    for (int k = 1; k < K; ++k) {
+        const double s_r2 = sr * sr / (double)q[lr];  // r^2 at level lr-1
+        sb = sb * s_r2 / (double)q[lr - 1];           // b' at level lr-2
+        sr = sb;
+        lr -= 2;
+        f = f * sr / (double)q[lr];
+    }
+    GoldPlan g;
+    for (double s : s_final) g.s_init.push_back(s / f);
+    return g;
 }
 
 // h ~ C u^(-1/2): polynomial sum_k coef_k u^k (coefficients times C), then
-// Newton steps h <- 1.5 h - (0.5/C^2) u h^3; lands at scale s_final per ct.
+// Newton steps h <- 1.5 h - (0.5/C^2) u h^3 or Goldschmidt updates; lands at
+// scale s_final per ct.
 Bt invsqr(Exec &X, const Bt &U, const std::vector<std::vector<double>> &coefC, const std::vector<double> &Cc,
-          int newton, const std::vector<double> &s_final) {
+          int newton, bool gold, const std::vector<double> &s_final) {
     const int R = U.cnt, d = (int)coefC[0].size() - 1, lu = U.level;
     const auto &q = X.C->q;
     std::vector<double> S(R);
-    for (int r = 0; r < R; ++r) S[r] = newton == 0 ? s_final[r] : X.C->Delta;
+    if (gold && newton > 0) {
+        const int lh0 = lu - invsqr_depth(d, newton, true) + 2 * newton + 1;
+        S = gold_plan(X.C, lh0, newton, s_final).s_init;
+    } else {
+        for (int r = 0; r < R; ++r) S[r] = newton == 0 ? s_final[r] : X.C->Delta;
+    }
     auto col = [&](int k) { std::vector<double> v(R); for (int r = 0; r < R; ++r) v[r] = coefC[r][k]; return v; };
     Bt H;
     if (d == 1) {
@@ -623,6 +658,25 @@ Bt invsqr(Exec &X, const Bt &U, const std::vector<std::vector<double>> &coefC, c
     } else {
         throw HeError(HE_EINVAL, "initial-guess degree must be 1..4");
     }
+    if (gold && newton > 0) {
+        const int lh = H.level;
+        std::vector<double> sA(R), kap(R), c15(R, 1.5);
+        Bt G2 = X.mul(H, H);
+        for (int r = 0; r < R; ++r) {
+            sA[r] = (X.C->Delta * (double)q[lh - 1]) / G2.scale[r];
+            kap[r] = 0.5 / (Cc[r] * Cc[r]);
+        }
+        Bt Bp = X.mul(X.drop(X.cmul(U, kap, sA, false), lh - 1), G2);
+        Bt Rk = X.add_const(X.mul_int(Bp, std::vector<int64_t>(R, -1)), c15);
+        H = X.mul(X.drop(H, Rk.level), Rk);
+        for (int it = 1; it < newton; ++it) {
+            Bt R2 = X.mul(Rk, Rk);
+            Bp = X.mul(X.drop(Bp, R2.level), R2);
+            Rk = X.add_const(X.mul_int(Bp, std::vector<int64_t>(R, -1)), c15);
+            H = X.mul(X.drop(H, Rk.level), Rk);
+        }
+        return H;
+    }
     for (int it = 0; it < newton; ++it) {
         std::vector<double> St(R), sA(R), kap(R), c15(R, 1.5);
         for (int r = 0; r < R; ++r) St[r] = it == newton - 1 ? s_final[r] : X.C->Delta;
@@ -647,6 +701,7 @@ struct CutmaxCfg {
     std::vector<double> c, vlo, vhi;
     std::vector<std::vector<double>> coef;  // [T][d+1] unscaled g(u) ~ u^-1/2
     int newton = 0, gold_d = 3;
+    bool gold_refine = false;
     double sum_lo = 1, sum_hi = 3;
 };
 
@@ -655,7 +710,7 @@ int levels_needed(const CutmaxCfg &cf) {
     for (int t = 0; t < cf.T; ++t) {
         int nb = 0;
         while ((cf.p[t] >> nb) > 1) ++nb;
-        lv += 2 + invsqr_depth((int)cf.coef[t].size() - 1, cf.newton) + 1 + nb + (__builtin_popcount(cf.p[t]) > 1 ? 1 : 0);
+        lv += 2 + invsqr_depth((int)cf.coef[t].size() - 1, cf.newton, cf.gold_refine) + 1 + nb + (__builtin_popcount(cf.p[t]) > 1 ? 1 : 0);
     }
     return lv + cf.gold_d + 3;
 }
@@ -680,7 +735,7 @@ Bt cutmax_sched(Exec &X, Bt Y, const std::vector<Request> &reqs, const CutmaxCfg
         Bt E = X.cmul(D, kE, dl, true);
         Bt F = X.mul(E, E);
         Bt U = X.rotsum(X.sum_groups(F, first, cnt));
-        const int lh = U.level - invsqr_depth((int)cf.coef[t].size() - 1, cf.newton);
+        const int lh = U.level - invsqr_depth((int)cf.coef[t].size() - 1, cf.newton, cf.gold_refine);
         REQUIRE(lh >= 1, HE_EDEPTH, "chain too short");
         std::vector<double> Cc(R), SH(R);
         std::vector<std::vector<double>> coefC(R);
@@ -689,7 +744,7 @@ Bt cutmax_sched(Exec &X, Bt Y, const std::vector<Request> &reqs, const CutmaxCfg
             SH[r] = (C->Delta * (double)C->q[lh]) / E.scale[first[r]];
             for (double g : cf.coef[t]) coefC[r].push_back(g * Cc[r]);
         }
-        Bt H = invsqr(X, U, coefC, Cc, cf.newton, SH);
+        Bt H = invsqr(X, U, coefC, Cc, cf.newton, cf.gold_refine, SH);
         Bt Yp = X.add_const(X.mul(X.drop(E, H.level), H, &cmap), std::vector<double>(Y.cnt, 1.0));
         Bt Yn = X.power(Yp, cf.p[t]);
         // keep the new iterate, drop this iteration's temporaries
@@ -1216,6 +1271,7 @@ CutmaxCfg parse_cfg(he_ctx *C, const he_cutmax_cfg *cfg) {
         cf.coef.push_back(g);
     }
     cf.newton = (int)cfg->newton_steps;
+    cf.gold_refine = (cfg->flags & HE_REFINE_GOLDSCHMIDT) != 0;
     cf.gold_d = (int)cfg->gold_d;
     REQUIRE(cfg->sum_hi > 0 && cfg->sum_lo >= 0 && cfg->sum_lo < cfg->sum_hi, HE_EINVAL, "bad sum domain");
     cf.sum_lo = cfg->sum_lo;
@@ -1255,7 +1311,7 @@ int cutmax_impl(he_ctx *C, he_ct *const *in, he_ct *const *noise, size_t batch, 
         std::string gkey;
         if (use_graph) {
             gkey = "L" + std::to_string(level) + (noise ? (prescaled ? "np" : "nt") : "") + "T" +
-                   std::to_string(cf.T) + "n" + std::to_string(cf.newton) + "g" + std::to_string(cf.gold_d);
+                   std::to_string(cf.T) + "n" + std::to_string(cf.newton) + (cf.gold_refine ? "G" : "") + "g" + std::to_string(cf.gold_d);
             for (auto &r : reqs) gkey += "a" + std::to_string(r.a);
             for (int t = 0; t < cf.T; ++t)
                 gkey += "p" + std::to_string(cf.p[t]) + "d" + std::to_string(cf.coef[t].size());

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libcutmax_he.so")
 
 HE_OK, HE_EINVAL, HE_ENOMEM, HE_EDEVICE, HE_EDEPTH, HE_ERANGE, HE_ESTATE = 0, -1, -2, -3, -4, -5, -6
 HE_NOISE_PRESCALED = 1
+HE_REFINE_GOLDSCHMIDT = 2
 HE_OPT_GRAPH, HE_OPT_NTT_VARIANT = 1, 2
 
 _c_u32p = ctypes.POINTER(ctypes.c_uint32)

@@ -214,6 +214,34 @@ def test_cutmax_toy_bit_exact_and_mirror(toy):
     assert int(np.argmax(cutmax_exact(y, 3, 5.0, 4)[:x.size])) == int(np.argmax(x))
 
 
+@pytest.mark.parametrize("gold", [False, True])
+def test_cutmax_toy_refinements_bit_exact(toy, gold):
+    """T=2 with a degree-1 guess and 2 refinements per iteration, Newton or Goldschmidt
+    (HE_REFINE_GOLDSCHMIDT): bit-exact against the oracle's schedule, within 1e-3 of the
+    FP64 mirror, argmax recovered"""
+    from paper_2509_08383_amd import he
+    say(f"[gpu] cutmax toy refinements (goldschmidt={gold})")
+    x = toy_logits(23)
+    y, a, rep = slot_layout(x, toy.G.slots)
+    n = y.size
+    p, c, vlo, vhi, _ = toy_cfg(n, T=2)
+    coef = [list(chebyshev_invsqrt(vlo[t] / vhi[t], 1)) for t in range(2)]
+    g, o = toy.enc_values(y)
+    cfg = he.CutmaxCfg(T=2, p=p, c=c, var_lo=vlo, var_hi=vhi, init_degree=1, init_coef=coef, newton_steps=2,
+                       sum_lo=1.0, sum_hi=3.0, gold_d=3, flags=he.HE_REFINE_GOLDSCHMIDT if gold else 0)
+    Zg = toy.G.cutmax([g], cfg)[0]
+    hc = ckks.HECfg(T=2, p=p, c=c, v_lo=vlo, v_hi=vhi, coef=coef, newton=2, goldschmidt=gold, sum_lo=1.0,
+                    sum_hi=3.0, gold_d=3)
+    Zo = ckks.cutmax_he(toy.O, [o], hc)[0]
+    toy.same(Zg, Zo, "cutmax refinements")
+    assert Zg.level == toy.G.L - hc.levels_needed()
+    dz = toy.G.decrypt(Zg, n)
+    mc = MirrorCfg(T=2, p=p, c=c, v_hi=vhi, v_lo=vlo, coef=coef, newton=2, goldschmidt=gold, B=3.0 * n, gold_d=3,
+                   sum_lo=1.0 * n)
+    assert np.abs(dz - cutmax_mirror(y, mc)).max() < 1e-3
+    assert int(np.argmax(dz[:x.size])) == int(np.argmax(x))
+
+
 def test_cutmax_toy_batch_mixed_counts(toy):
     """batched form: requests with 1 and 2 ciphertexts advance together; each equals its
     single-request run bit for bit (n > s splits over several ciphertexts, App. D)."""

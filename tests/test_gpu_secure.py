@@ -118,3 +118,31 @@ def test_cutmax_config3_batched(sec):
     for r in (0, 1):
         Zs = sec.G.cutmax([cts[r]], cfg)[0]
         assert np.array_equal(sec.G.export(Zs), sec.G.export(Z[r])), r
+
+
+def test_goldschmidt_and_newton_refinements_at_full_size(sec):
+    """T=2, degree-1 guess + 2 refinements on 32000 logits: Newton and Goldschmidt both
+    match the FP64 mirror within 1e-3 and recover the argmax; Goldschmidt ends one level
+    lower per iteration"""
+    from paper_2509_08383_amd import he
+    say("[gpu] refinements at N=2^16")
+    G = sec.G
+    x = llm_logits(5)
+    y, _, _ = slot_layout(x, G.slots)
+    ct = G.encrypt(x)
+    coef = [list(chebyshev_invsqrt(VLO[t] / VHI[t], 1)) for t in range(2)]
+    lv = {}
+    for gold in (False, True):
+        cfg = he.CutmaxCfg(T=2, p=[3] * 2, c=[5.0] * 2, var_lo=VLO[:2], var_hi=VHI[:2], init_degree=1, init_coef=coef,
+                           newton_steps=2, sum_lo=1.0, sum_hi=3.0, gold_d=3,
+                           flags=he.HE_REFINE_GOLDSCHMIDT if gold else 0)
+        Z = G.cutmax([ct], cfg)[0]
+        Z = G.cutmax([ct], cfg)[0]
+        say(f"  goldschmidt={gold}: {G.last_cutmax_ms():.2f} ms, output level {Z.level}")
+        lv[gold] = Z.level
+        mc = MirrorCfg(T=2, p=[3] * 2, c=[5.0] * 2, v_hi=VHI[:2], v_lo=VLO[:2], coef=coef, newton=2, goldschmidt=gold,
+                       B=3.0 * y.size, gold_d=3, sum_lo=1.0 * y.size)
+        z = G.decrypt(Z, y.size)
+        assert np.abs(z - cutmax_mirror(y, mc)).max() < 1e-3
+        assert int(np.argmax(z[:x.size])) == int(np.argmax(x))
+    assert lv[False] - lv[True] == 2

@@ -8,7 +8,8 @@ import numpy as np
 import pytest
 
 from oracle import ckks
-from oracle.cutmax_fp64 import MirrorCfg, chebyshev_invsqrt, cutmax_exact, cutmax_mirror, slot_layout
+from oracle.cutmax_fp64 import (MirrorCfg, chebyshev_invsqrt, cutmax_exact, cutmax_mirror, goldschmidt_invsqrt,
+                                newton_invsqrt_step, poly_eval, slot_layout)
 from workloads import random_residues, toy_logits
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
@@ -245,3 +246,24 @@ def test_schedule_rejects_short_chain(toy):
     he, _ = _cfg1_schedule(toy, x)
     with pytest.raises(ckks.SchedError):
         ckks.cutmax_he(toy, [toy.encrypt(x)], he)
+
+
+@pytest.mark.parametrize("gold", [False, True])
+def test_encrypted_invsqr_refinements(toy, gold):
+    """the encrypted inverse square root (degree-1 guess + 2 refinements, Newton or
+    Goldschmidt) decrypts to the FP64 iteration on the same u and lands at the requested
+    scale; Goldschmidt takes one level more"""
+    u = np.random.default_rng(4).uniform(0.3, 1.0, toy.slots)
+    C = 2.0
+    coef = chebyshev_invsqrt(0.3, 1)
+    H = toy.invsqr(toy.encrypt(u), [g * C for g in coef], C, 2, toy.Delta, goldschmidt=gold)
+    assert H.level == toy.L - ckks.invsqr_depth(1, 2, gold)
+    assert H.level == toy.L - (6 if gold else 5)
+    assert abs(H.scale / toy.Delta - 1) < 1e-12
+    h0 = poly_eval(coef, u)
+    if gold:
+        ref = C * goldschmidt_invsqrt(u, h0, 2)
+    else:
+        ref = C * newton_invsqrt_step(newton_invsqrt_step(h0, u, 1.0), u, 1.0)
+    np.testing.assert_allclose(toy.decrypt(H), ref, atol=1e-3)
+    assert np.abs(ref * np.sqrt(u) / C - 1).max() < 2e-3

@@ -7,7 +7,7 @@ import pytest
 
 from oracle.cutmax_fp64 import (DomainError, MirrorCfg, Trace, beta_alpha, beta_noise, chebyshev_invsqrt,
                                 cutmax_exact, cutmax_mirror, delta_gap, gap_ratio,
-                                goldschmidt_factor, gumbel_noise, newton_invsqrt_step, nucleus_argmax,
+                                goldschmidt_factor, goldschmidt_invsqrt, gumbel_noise, newton_invsqrt_step, nucleus_argmax,
                                 nucleus_set, poly_eval, semi_standardize, slot_layout, tmin, violation_rate)
 from workloads import llm_logits, llm_logits_var, toy_logits, uniform_noise
 
@@ -275,3 +275,40 @@ def test_violation_rate_counts_outside_picks():
     x = np.array([5.0, 4.9, 1.0, -3.0])
     assert violation_rate(x, [0, 1, 2, 3], 0.9) == 0.5
     assert violation_rate(x, [], 0.9) == 0.0
+
+
+def test_goldschmidt_invsqrt_error_recursion_and_newton_equivalence():
+    """Goldschmidt's inverse-square-root iteration (App. B.1): with e = y sqrt(x) - 1 one
+    update maps e to -(3/2) e^2 - (1/2) e^3 (from y' = y (3 - x y^2)/2), so it converges
+    quadratically; it coincides with Newton's step for x^(-1/2) at every iterate."""
+    rng = np.random.default_rng(3)
+    x = rng.uniform(0.05, 1.0, 2000)
+    y0 = (1.0 + rng.uniform(-0.4, 0.4, x.size)) / np.sqrt(x)
+    e0 = y0 * np.sqrt(x) - 1.0
+    e1 = goldschmidt_invsqrt(x, y0, 1) * np.sqrt(x) - 1.0
+    np.testing.assert_allclose(e1, -1.5 * e0 ** 2 - 0.5 * e0 ** 3, atol=1e-14)
+    h = y0.copy()
+    for K in range(1, 5):
+        h = newton_invsqrt_step(h, x, 1.0)
+        np.testing.assert_allclose(goldschmidt_invsqrt(x, y0, K), h, rtol=1e-13)
+    assert np.abs(goldschmidt_invsqrt(x, y0, 7) * np.sqrt(x) - 1).max() < 1e-13
+    # from y0 = 1 on [1/4, 1] the error falls below 2^-13 within 5 updates
+    xs = np.linspace(0.25, 1.0, 1001)
+    errs = [np.abs(goldschmidt_invsqrt(xs, 1.0, K) * np.sqrt(xs) - 1).max() for K in range(1, 7)]
+    assert all(b < a for a, b in zip(errs, errs[1:]))
+    assert errs[4] < 2.0 ** -13
+
+
+def test_mirror_goldschmidt_refinement_matches_newton():
+    """the encrypted schedule's two refinements agree in exact arithmetic, so the FP64
+    mirror gives the same Z with either (to rounding)"""
+    x = llm_logits(3)
+    y, _, _ = slot_layout(x, 32768)
+    vlo, vhi = [12.0, 0.4, 0.8], [24.0, 0.9, 16.0]
+    coef = [list(chebyshev_invsqrt(vlo[t] / vhi[t], 1)) for t in range(3)]
+    kw = dict(T=3, p=[3] * 3, c=[5.0] * 3, v_hi=vhi, v_lo=vlo, coef=coef, B=3.0 * y.size, gold_d=3,
+              sum_lo=1.0 * y.size, newton=2)
+    zn = cutmax_mirror(y, MirrorCfg(**kw))
+    zg = cutmax_mirror(y, MirrorCfg(goldschmidt=True, **kw))
+    assert np.abs(zn - zg).max() < 1e-12
+    assert int(np.argmax(zg)) == int(np.argmax(x))
