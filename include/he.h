@@ -92,7 +92,15 @@ typedef struct {
  *     sum/(sum_hi * n).
  *   flags: HE_NOISE_PRESCALED (he_topp_sample, he_gumbel_sample: the noise
  *     already carries the temperature); HE_REFINE_GOLDSCHMIDT (see
- *     newton_steps). */
+ *     newton_steps); HE_MASK_PAD: for a zero-padded request (n not dividing
+ *     slots), mean, variance and the final sum run over its n logical slots
+ *     only (Alg. 1 on the n logits; Sec. 3.2 assumes n = a * slots), so the
+ *     first n outputs are CutMax of the logits alone.  The pad slots hold one
+ *     common value that a tracker ciphertext follows through the same steps;
+ *     the sums subtract (pad count) x tracker, which costs no level.  The pad
+ *     slots of the output hold the tracker's iterate, not zeros.  Accuracy
+ *     needs pad slots that do not outgrow the logits: encrypt with the mean of
+ *     x as pad (he_encrypt with pad = NaN). */
 typedef struct {
     uint32_t T;
     const uint32_t *p;
@@ -110,6 +118,7 @@ typedef struct {
 
 #define HE_NOISE_PRESCALED 1u
 #define HE_REFINE_GOLDSCHMIDT 2u
+#define HE_MASK_PAD 4u
 
 /* Context: prime chain, twiddle and basis-conversion tables, secret key, and
  * the relinearisation and rotation keys (rotation by 2^r slots for every r <
@@ -125,8 +134,10 @@ int he_ctx_info(const he_ctx *ctx, uint32_t *N, uint32_t *slots, uint32_t *L, ui
                 uint64_t *primes);
 
 /* Client: encrypt n doubles (Sec. 2.1).  n <= slots with slots % n == 0 is
- * replicated; otherwise padded with `pad` to a = ceil(n/slots) ciphertexts.
- * The handle is at the top level with scale Delta. */
+ * replicated; otherwise padded with `pad` to a = ceil(n/slots) ciphertexts
+ * (pad = NaN: the mean of x, which keeps masked CutMax accurate, see
+ * HE_MASK_PAD).  The handle is at the top level with scale Delta and records n
+ * and the pad value. */
 int he_encrypt(he_ctx *ctx, const double *x, size_t n, double pad, he_ct **out);
 
 /* Client: encrypt already-encoded integer plaintexts m[a][N] at `scale`
@@ -134,6 +145,11 @@ int he_encrypt(he_ctx *ctx, const double *x, size_t n, double pad, he_ct **out);
  * n is the logical length recorded in the handle. */
 int he_encrypt_coeffs(he_ctx *ctx, const int64_t *m, uint32_t a, double scale, size_t n,
                       he_ct **out);
+
+/* Records the value of the pad slots (beyond the logical length) of a handle
+ * made by he_encrypt_coeffs or he_ct_import (default 0); masked CutMax starts
+ * its pad tracker from it.  EINVAL for a non-finite value. */
+int he_ct_set_pad(he_ct *ct, double pad);
 
 /* Client: decrypt and decode the first n logical values (Sec. 2.1). */
 int he_decrypt(he_ctx *ctx, const he_ct *ct, double *out, size_t n);

@@ -548,17 +548,37 @@ class HECfg:
         return lv + self.gold_d + 3
 
 
-def cutmax_he(O: Oracle, Y: List[Ct], cfg: HECfg, rotsum_cache=None) -> List[Ct]:
-    """Alg. 2 on one request whose packed vector spans len(Y) ciphertexts."""
+def cutmax_he(O: Oracle, Y: List[Ct], cfg: HECfg, rotsum_cache=None, n_real: int = None,
+              pad: float = 0.0) -> List[Ct]:
+    """Alg. 2 on one request whose packed vector spans len(Y) ciphertexts.
+
+    With n_real (masked padding) the moments and the final sum are taken over the first
+    n_real slots only, so the first n_real outputs are CutMax of those entries alone.
+    The pad slots all hold one common value, which a tracker ciphertext follows through
+    the same steps (it starts as the trivial encryption of the pad value); every slot
+    sum subtracts (pad slot count) x tracker, and the variance sum subtracts the same
+    multiple of the tracker's square."""
     a = len(Y)
-    n = a * O.slots
+    masked = n_real is not None and n_real < a * O.slots
+    n = n_real if masked else a * O.slots
+    npad = a * O.slots - n
+    P = None
+    if masked:
+        P = O.mul_int(Y[0], 0)
+        if pad != 0.0:
+            P = O.add_const(P, pad)
     for t in range(cfg.T):
         S = O.rotsum(O.sum_list(Y))
-        D = [O.sub(O.mul_int(y, n), S) for y in Y]
+        if masked:
+            S = O.sub(S, O.mul_int(P, npad))
+        Yall = Y + ([P] if masked else [])
+        D = [O.sub(O.mul_int(y, n), S) for y in Yall]
         kE = 1.0 / (float(n) * math.sqrt(float(n) * cfg.v_hi[t]))
         E = [O.cm_exact(d, kE, O.Delta) for d in D]
         F = [O.mul(e, e) for e in E]
-        U = O.rotsum(O.sum_list(F))
+        U = O.rotsum(O.sum_list(F[:a]))
+        if masked:
+            U = O.sub(U, O.mul_int(F[a], npad))
         C = math.sqrt(float(n)) / cfg.c[t]
         lh = U.level - invsqr_depth(len(cfg.coef[t]) - 1, cfg.newton, cfg.goldschmidt)
         if lh < 1:
@@ -567,8 +587,11 @@ def cutmax_he(O: Oracle, Y: List[Ct], cfg: HECfg, rotsum_cache=None) -> List[Ct]
         S_H = (O.Delta * float(O.q[lh])) / sE
         H = O.invsqr(U, [g * C for g in cfg.coef[t]], C, cfg.newton, S_H, cfg.goldschmidt)
         Yn = [O.add_const(O.mul(O.drop(e, H.level), H), 1.0) for e in E]
-        Y = [O.power(y, int(cfg.p[t])) for y in Yn]
+        Yall = [O.power(y, int(cfg.p[t])) for y in Yn]
+        Y, P = Yall[:a], (Yall[a] if masked else None)
     S = O.rotsum(O.sum_list(Y))
+    if masked:
+        S = O.sub(S, O.mul_int(P, npad))
     B = cfg.sum_hi * float(n)
     X = O.cm_exact(S, 1.0 / B, O.Delta)
     E0 = O.add_const(O.mul_int(X, -1), 1.0)
@@ -585,11 +608,11 @@ def cutmax_he(O: Oracle, Y: List[Ct], cfg: HECfg, rotsum_cache=None) -> List[Ct]
 
 
 def topp_he(O: Oracle, X: List[Ct], G: List[Ct], temperature: float, cfg: HECfg,
-            prescaled: bool = False) -> List[Ct]:
+            prescaled: bool = False, n_real: int = None) -> List[Ct]:
     """Alg. 3 server side: CutMax(X + tau*G) (equal to CutMax(X/tau + G))."""
     if prescaled:
         Xt = [O.add(x, g) for x, g in zip(X, G)]
     else:
         Gs = [O.cm_target(g, temperature, x.scale) for x, g in zip(X, G)]
         Xt = [O.add(O.drop(x, gs.level), gs) for x, gs in zip(X, Gs)]
-    return cutmax_he(O, Xt, cfg)
+    return cutmax_he(O, Xt, cfg, n_real=n_real)

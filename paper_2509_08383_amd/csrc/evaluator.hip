@@ -173,6 +173,7 @@ struct he_ct {
     uint32_t a = 1, level = 0;
     double scale = 0;
     size_t n = 0;
+    double pad = 0;  // value of the slots beyond n (he_encrypt)
 };
 
 namespace {
@@ -284,6 +285,20 @@ struct Exec {
         ConstTab kt{residues(n, Y.level), 2, Y.level + 1};
         const int *dmap = C->pool.push(cmap);
         if (go()) launch_axpy_map(T, vs_all(o), vs_all(Y), kt, vs_all(S), dmap, 2, s);
+        return o;
+    }
+    // S_r - k_r * B[map[r]] for the requests with map[r] >= 0, S_r for the others
+    Bt sub_mul_map(const Bt &S, const Bt &B, const std::vector<int64_t> &k, const std::vector<int> &map) {
+        REQUIRE(S.level == B.level, HE_ESTATE, "sub_mul_map: level mismatch");
+        for (int r = 0; r < S.cnt; ++r)
+            if (map[r] >= 0)
+                REQUIRE(std::fabs(S.scale[r] - B.scale[map[r]]) <= 1e-9 * S.scale[r], HE_ERANGE,
+                        "sub_mul_map: scale mismatch");
+        Bt o = new_bt(S.cnt, S.level);
+        o.scale = S.scale;
+        ConstTab kt{residues(k, S.level), 2, S.level + 1};
+        const int *dmap = C->pool.push(map);
+        if (go()) launch_sub_mul_map(T, vs_all(o), vs_all(S), kt, vs_all(B), dmap, 2, s);
         return o;
     }
     // per-request sums of consecutive ciphertexts
@@ -573,7 +588,9 @@ struct Exec {
 };
 
 // ------------------------------------------------------------- CutMax plan
-struct Request { int first, a; int64_t n; };
+// n: the slot count the moments run over (a * slots, or the logit count with masked
+// padding); npad > 0 gives the request a pad tracker (pad: its starting value)
+struct Request { int first, a; int64_t n; int64_t npad = 0; double pad = 0; };
 
 // Goldschmidt's coupled iteration costs one level more than Newton's: its first
 // product u h^2 needs h^2 before the update multiplies h
@@ -716,25 +733,79 @@ int levels_needed(const CutmaxCfg &cf) {
 }
 
 // Alg. 2 on a batch of requests; Y holds every request's ciphertexts.
+// Masked padding: the pad slots of a request all hold one value, followed by a
+// tracker ciphertext (appended after every request's ciphertexts) that takes the same
+// steps; each slot sum subtracts npad x tracker and the variance sum npad x the
+// tracker's square, so the moments are those of the first n slots.
 Bt cutmax_sched(Exec &X, Bt Y, const std::vector<Request> &reqs, const CutmaxCfg &cf) {
     he_ctx *C = X.C;
-    const int R = (int)reqs.size();
-    std::vector<int> first(R), cnt(R), cmap(Y.cnt);
-    std::vector<int64_t> nct(Y.cnt);
+    const int R = (int)reqs.size(), total = Y.cnt;
+    std::vector<int> first(R), cnt(R), tmap(R, -1);
+    std::vector<int64_t> npad(R, 0);
+    int ntrk = 0;
+    for (int r = 0; r < R; ++r)
+        if (reqs[r].npad > 0) { tmap[r] = total + ntrk++; npad[r] = reqs[r].npad; }
+    std::vector<int> cmap(total + ntrk);
+    std::vector<int64_t> nct(total + ntrk);
     for (int r = 0; r < R; ++r) {
         first[r] = reqs[r].first; cnt[r] = reqs[r].a;
         for (int k = 0; k < reqs[r].a; ++k) { cmap[reqs[r].first + k] = r; nct[reqs[r].first + k] = reqs[r].n; }
+        if (tmap[r] >= 0) { cmap[tmap[r]] = r; nct[tmap[r]] = reqs[r].n; }
     }
     REQUIRE(levels_needed(cf) <= Y.level, HE_EDEPTH, "schedule needs more levels than the ciphertext has");
+    if (ntrk) {
+        // trackers start as trivial encryptions of the pad value (0 * ct + pad)
+        Bt Ya = X.new_bt(total + ntrk, Y.level);
+        for (int k = 0; k < total; ++k) Ya.scale[k] = Y.scale[k];
+        Bt main = Ya;
+        main.cnt = total;
+        main.scale.resize(total);
+        if (X.go()) launch_copy(X.T, X.vs_all(main), X.vs_all(Y), X.s);
+        std::vector<int64_t> zero(ntrk, 0);
+        Bt firsts = X.new_bt(ntrk, Y.level);
+        for (int r = 0, i = 0; r < R; ++r)
+            if (tmap[r] >= 0) {
+                Bt src = Y, dst = firsts;
+                src.d = Y.d + (long long)reqs[r].first * 2 * Y.cap * C->N;
+                src.cnt = 1;
+                dst.d = firsts.d + (long long)i * 2 * firsts.cap * C->N;
+                dst.cnt = 1;
+                firsts.scale[i] = Y.scale[reqs[r].first];
+                if (X.go()) launch_copy(X.T, X.vs_all(dst), X.vs_all(src), X.s);
+                ++i;
+            }
+        std::vector<double> pv;
+        for (int r = 0; r < R; ++r)
+            if (tmap[r] >= 0) pv.push_back(reqs[r].pad);
+        Bt trk = X.add_const(X.mul_int(firsts, zero), pv);
+        Bt tdst = Ya;
+        tdst.d = Ya.d + (long long)total * 2 * Ya.cap * C->N;
+        tdst.cnt = ntrk;
+        for (int i = 0; i < ntrk; ++i) Ya.scale[total + i] = trk.scale[i];
+        if (X.go()) launch_copy(X.T, X.vs_all(tdst), X.vs_all(trk), X.s);
+        Y = Ya;
+    }
+    // the trackers of a batch, as a view into it (index tmap[r] - total)
+    auto trackers = [&](const Bt &B) {
+        Bt v = B;
+        v.d = B.d + (long long)total * 2 * B.cap * C->N;
+        v.cnt = ntrk;
+        v.scale.assign(B.scale.begin() + total, B.scale.end());
+        return v;
+    };
+    std::vector<int> tidx(R, -1);
+    for (int r = 0; r < R; ++r) tidx[r] = tmap[r] >= 0 ? tmap[r] - total : -1;
     for (int t = 0; t < cf.T; ++t) {
         const size_t mark = C->arena.mark();
         Bt S = X.rotsum(X.sum_groups(Y, first, cnt));
+        if (ntrk) S = X.sub_mul_map(S, trackers(Y), npad, tidx);
         Bt D = X.center(Y, S, cmap, nct);
         std::vector<double> kE(Y.cnt), dl(Y.cnt, C->Delta);
         for (int k = 0; k < Y.cnt; ++k) kE[k] = 1.0 / ((double)nct[k] * std::sqrt((double)nct[k] * cf.vhi[t]));
         Bt E = X.cmul(D, kE, dl, true);
         Bt F = X.mul(E, E);
         Bt U = X.rotsum(X.sum_groups(F, first, cnt));
+        if (ntrk) U = X.sub_mul_map(U, trackers(F), npad, tidx);
         const int lh = U.level - invsqr_depth((int)cf.coef[t].size() - 1, cf.newton, cf.gold_refine);
         REQUIRE(lh >= 1, HE_EDEPTH, "chain too short");
         std::vector<double> Cc(R), SH(R);
@@ -756,10 +827,15 @@ Bt cutmax_sched(Exec &X, Bt Y, const std::vector<Request> &reqs, const CutmaxCfg
         // allocations; the copy is enqueued before any of them
         Y = Yk;
     }
-    std::vector<double> invB(Y.cnt), dl(Y.cnt, C->Delta), invBr(R), dlr(R, C->Delta);
-    for (int k = 0; k < Y.cnt; ++k) invB[k] = 1.0 / (cf.sum_hi * (double)nct[k]);
+    std::vector<double> invB(total), dl(total, C->Delta), invBr(R), dlr(R, C->Delta);
+    for (int k = 0; k < total; ++k) invB[k] = 1.0 / (cf.sum_hi * (double)nct[k]);
     for (int r = 0; r < R; ++r) invBr[r] = 1.0 / (cf.sum_hi * (double)reqs[r].n);
     Bt S = X.rotsum(X.sum_groups(Y, first, cnt));
+    if (ntrk) {
+        S = X.sub_mul_map(S, trackers(Y), npad, tidx);
+        Y.cnt = total;  // the trackers are done
+        Y.scale.resize(total);
+    }
     Bt Xs = X.cmul(S, invBr, dlr, true);
     Bt E0 = X.add_const(X.mul_int(Xs, std::vector<int64_t>(R, -1)), std::vector<double>(R, 1.0));
     Bt P = X.add_const(E0, std::vector<double>(R, 1.0));
@@ -1293,7 +1369,16 @@ int cutmax_impl(he_ctx *C, he_ct *const *in, he_ct *const *noise, size_t batch, 
         if (noise) REQUIRE(noise[r] && noise[r]->ctx == C && noise[r]->a == in[r]->a, HE_ESTATE, "noise mismatch");
         if (level < 0) level = (int)in[r]->level;
         REQUIRE((int)in[r]->level == level, HE_ESTATE, "requests at different levels");
-        reqs.push_back(Request{total, (int)in[r]->a, (int64_t)in[r]->a * C->slots});
+        Request q{total, (int)in[r]->a, (int64_t)in[r]->a * C->slots};
+        // masked padding for a zero-padded request (a replicated one has exact moments)
+        const int64_t nr = (int64_t)in[r]->n;
+        const bool replicated = in[r]->a == 1 && nr >= 1 && nr <= C->slots && C->slots % nr == 0;
+        if ((cfg->flags & HE_MASK_PAD) && !replicated && nr >= 1 && nr < q.n) {
+            q.npad = q.n - nr;
+            q.n = nr;
+            q.pad = in[r]->pad;
+        }
+        reqs.push_back(q);
         total += (int)in[r]->a;
     }
     const bool prescaled = cfg->flags & HE_NOISE_PRESCALED;
@@ -1312,7 +1397,7 @@ int cutmax_impl(he_ctx *C, he_ct *const *in, he_ct *const *noise, size_t batch, 
         if (use_graph) {
             gkey = "L" + std::to_string(level) + (noise ? (prescaled ? "np" : "nt") : "") + "T" +
                    std::to_string(cf.T) + "n" + std::to_string(cf.newton) + (cf.gold_refine ? "G" : "") + "g" + std::to_string(cf.gold_d);
-            for (auto &r : reqs) gkey += "a" + std::to_string(r.a);
+            for (auto &r : reqs) gkey += "a" + std::to_string(r.a) + (r.npad > 0 ? "m" : "");
             for (int t = 0; t < cf.T; ++t)
                 gkey += "p" + std::to_string(cf.p[t]) + "d" + std::to_string(cf.coef[t].size());
         }
@@ -1528,6 +1613,11 @@ int he_encrypt(he_ctx *C, const double *x, size_t n, double pad, he_ct **out) {
         const size_t s = (size_t)C->slots;
         std::vector<double> packed;
         uint32_t a;
+        if (std::isnan(pad)) {
+            double sum = 0;
+            for (size_t i = 0; i < n; ++i) sum += x[i];
+            pad = sum / (double)n;
+        }
         if (n <= s && s % n == 0) {
             a = 1;
             packed.resize(s);
@@ -1539,8 +1629,16 @@ int he_encrypt(he_ctx *C, const double *x, size_t n, double pad, he_ct **out) {
         }
         std::vector<int64_t> m((size_t)a * C->N);
         for (uint32_t c = 0; c < a; ++c) encode_slots(packed.data() + (size_t)c * s, C->N, C->Delta, m.data() + (size_t)c * C->N);
-        return he_encrypt_coeffs(C, m.data(), a, C->Delta, n, out);
+        const int rc = he_encrypt_coeffs(C, m.data(), a, C->Delta, n, out);
+        if (rc == HE_OK) (*out)->pad = pad;
+        return rc;
     });
+}
+
+int he_ct_set_pad(he_ct *ct, double pad) {
+    if (!ct || !std::isfinite(pad)) { g_err = "bad argument"; return HE_EINVAL; }
+    ct->pad = pad;
+    return HE_OK;
 }
 
 int he_decrypt(he_ctx *C, const he_ct *ct, double *out, size_t n) {

@@ -120,6 +120,8 @@ void launch_add_const(const DevTables &T, const VecSet &out, const VecSet &a, Co
                       hipStream_t s);
 void launch_axpy_map(const DevTables &T, const VecSet &out, const VecSet &a, ConstTab k,
                      const VecSet &b, const int *bmap, int bdiv, hipStream_t s);
+void launch_sub_mul_map(const DevTables &T, const VecSet &out, const VecSet &a, ConstTab k, const VecSet &b,
+                        const int *bmap, int bdiv, hipStream_t s);
 void launch_sum_groups(const DevTables &T, const VecSet &out, const VecSet &in, const int *first,
                        const int *cnt, int gdiv, hipStream_t s);
 void launch_tensor(const DevTables &T, double *d0, double *d1, double *d2, long long dstride,

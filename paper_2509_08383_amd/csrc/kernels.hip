@@ -139,6 +139,29 @@ void launch_axpy_map(const DevTables &T, const VecSet &out, const VecSet &a, Con
     KL("k_axpy_map", k_axpy_map, ew_grid(T, out.count), dim3(256), 0, s, out, a, k, b, bmap, bdiv, T);
 }
 
+// out = a - k * b[map]  for the groups whose request has map[g / bdiv] >= 0 (b group
+// map * bdiv + g % bdiv), out = a for the others
+__global__ void k_sub_mul_map(VecSet out, VecSet a, ConstTab k, VecSet b, const int *bmap, int bdiv, DevTables T) {
+    EW_PROLOGUE
+    double *pa; int q1, g1, r1;
+    vs_at(a, blockIdx.y, T.N, pa, q1, g1, r1);
+    const int m = bmap[g / bdiv];
+    if (m < 0) {
+        po[x] = pa[x];
+        return;
+    }
+    double *pb; int q2, g2, r2;
+    vs_at(b, (m * bdiv + g % bdiv) * b.group + r, T.N, pb, q2, g2, r2);
+    const double pinv = T.pinv[pr];
+    po[x] = canon(pa[x] - mm(pb[x], ct_val(k, g, r), p, pinv), p, pinv);
+}
+void launch_sub_mul_map(const DevTables &T, const VecSet &out, const VecSet &a, ConstTab k, const VecSet &b,
+                        const int *bmap, int bdiv, hipStream_t s) {
+    if (out.count <= 0) return;
+    kprof_set_bytes(24.0 * T.N * out.count);
+    KL("k_sub_mul_map", k_sub_mul_map, ew_grid(T, out.count), dim3(256), 0, s, out, a, k, b, bmap, bdiv, T);
+}
+
 // out group g (= req * gdiv + j) = sum over k < cnt[req] of in group (first[req] + k) * gdiv + j
 __global__ void k_sum_groups(VecSet out, VecSet in, const int *first, const int *cnt, int gdiv,
                              DevTables T) {
@@ -385,11 +408,18 @@ void launch_inner_product(const DevTables &T, const double *ext, long long estri
 // b mod 8); every XCD is given whole targets t and walks a target's x-blocks in the
 // order of their pi-orbits (rs.xorder), so consecutive workgroups on an XCD share all
 // but one of their source blocks and re-read them from L2.
+// BETA > 0 fixes the digit count at compile time, so the loads of all digits of a
+// rotation are issued together before the first product waits on them; BETA = 0
+// reads the runtime beta (at most 8).
+template <int BETA>
 __global__ __launch_bounds__(256) void k_inner_product_rot(DevTables T, const double *__restrict__ ext,
                                                            long long esb, long long esj, double *__restrict__ acc0,
                                                            double *__restrict__ acc1, long long astride, RotSet rs,
-                                                           long long ksj, long long ksc, int cnt, int beta, int next,
-                                                           const int *__restrict__ ext_prime, int xblocks) {
+                                                           long long ksj, long long ksc, int cnt, int beta_rt,
+                                                           int next, const int *__restrict__ ext_prime,
+                                                           int xblocks) {
+    const int beta = BETA > 0 ? BETA : beta_rt;
+    constexpr int JM = BETA > 0 ? BETA : 8;
     const int b = blockIdx.x, slot = b >> 3;
     const int t = (b & 7) + 8 * (slot / xblocks);
     if (t >= next) return;
@@ -407,12 +437,27 @@ __global__ __launch_bounds__(256) void k_inner_product_rot(DevTables T, const do
             const unsigned src = aut_src((unsigned)x, rs.g[r], T.logN);
             if (wsum) g0 = red(g0 + C0[src], p, pinv);
             const KeyRef K = rs.key[r];
+            if (BETA > 0) {
+                double e[JM], a0[JM], a1[JM];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                if (j < beta) {
-                    const double e = E[j * esj + src];
-                    s0 += mm(e, key_at(K, j * ksj + ko), p, pinv);
-                    s1 += mm(e, key_at(K, j * ksj + ksc + ko), p, pinv);
+                for (int j = 0; j < JM; ++j) {
+                    e[j] = E[j * esj + src];
+                    a0[j] = key_at(K, j * ksj + ko);
+                    a1[j] = key_at(K, j * ksj + ksc + ko);
+                }
+#pragma unroll
+                for (int j = 0; j < JM; ++j) {
+                    s0 += mm(e[j], a0[j], p, pinv);
+                    s1 += mm(e[j], a1[j], p, pinv);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < JM; ++j) {
+                    if (j < beta) {
+                        const double e = E[j * esj + src];
+                        s0 += mm(e, key_at(K, j * ksj + ko), p, pinv);
+                        s1 += mm(e, key_at(K, j * ksj + ksc + ko), p, pinv);
+                    }
                 }
             }
             s0 = red(s0, p, pinv);
@@ -503,9 +548,18 @@ void launch_inner_product_rot(const DevTables &T, const double *ext, long long e
     else if (reg && rs.nr == 1)
         KL("k_inner_product_rot", k_inner_product_rot_reg<1>, g1, dim3(256), 0, s, T, ext, estride_b, estride_j, acc0,
            acc1, astride, rs, kstride_j, kstride_c, cnt, beta, next, ext_prime, xblocks);
+    else if (beta == 3)
+        KL("k_inner_product_rot", k_inner_product_rot<3>, g1, dim3(256), 0, s, T, ext, estride_b, estride_j, acc0,
+           acc1, astride, rs, kstride_j, kstride_c, cnt, beta, next, ext_prime, xblocks);
+    else if (beta == 2)
+        KL("k_inner_product_rot", k_inner_product_rot<2>, g1, dim3(256), 0, s, T, ext, estride_b, estride_j, acc0,
+           acc1, astride, rs, kstride_j, kstride_c, cnt, beta, next, ext_prime, xblocks);
+    else if (beta == 1)
+        KL("k_inner_product_rot", k_inner_product_rot<1>, g1, dim3(256), 0, s, T, ext, estride_b, estride_j, acc0,
+           acc1, astride, rs, kstride_j, kstride_c, cnt, beta, next, ext_prime, xblocks);
     else
-        KL("k_inner_product_rot", k_inner_product_rot, g1, dim3(256), 0, s, T, ext, estride_b, estride_j, acc0, acc1,
-           astride, rs, kstride_j, kstride_c, cnt, beta, next, ext_prime, xblocks);
+        KL("k_inner_product_rot", k_inner_product_rot<0>, g1, dim3(256), 0, s, T, ext, estride_b, estride_j, acc0,
+           acc1, astride, rs, kstride_j, kstride_c, cnt, beta, next, ext_prime, xblocks);
 }
 
 // ModDown conversion: acc holds, at slots in0 .. in0+nin-1 of every group, the

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libcutmax_he.so")
 HE_OK, HE_EINVAL, HE_ENOMEM, HE_EDEVICE, HE_EDEPTH, HE_ERANGE, HE_ESTATE = 0, -1, -2, -3, -4, -5, -6
 HE_NOISE_PRESCALED = 1
 HE_REFINE_GOLDSCHMIDT = 2
+HE_MASK_PAD = 4
 HE_OPT_GRAPH, HE_OPT_NTT_VARIANT = 1, 2
 
 _c_u32p = ctypes.POINTER(ctypes.c_uint32)
@@ -69,6 +70,7 @@ def lib():
             "he_topp_sample": [_V, ctypes.POINTER(_V), ctypes.POINTER(_V), ctypes.c_size_t, ctypes.c_double,
                                ctypes.c_double, ctypes.POINTER(_Cfg), ctypes.POINTER(_V)],
             "he_topp_noise": [ctypes.c_double, _c_dp, ctypes.c_size_t, _c_dp],
+            "he_ct_set_pad": [_V, ctypes.c_double],
             "he_gumbel_sample": [_V, ctypes.POINTER(_V), ctypes.POINTER(_V), ctypes.c_size_t, ctypes.c_double,
                                  ctypes.POINTER(_Cfg), ctypes.POINTER(_V)],
             "he_gumbel_noise": [_c_dp, ctypes.c_size_t, _c_dp],
@@ -208,6 +210,10 @@ class Ciphertext:
     def n(self):
         return self.info()[3]
 
+    def set_pad(self, pad: float):
+        """Record the value of the pad slots (handles from encrypt_coeffs or import)."""
+        _check(lib().he_ct_set_pad(self.h, pad))
+
 
 class Context:
     """One CKKS context on one GPU (he_ctx)."""
@@ -243,6 +249,8 @@ class Context:
 
     # client ------------------------------------------------------------------
     def encrypt(self, x, pad: float = 0.0) -> Ciphertext:
+        """pad: value of the slots beyond len(x) when x is padded; float('nan') pads with
+        the mean of x (what masked CutMax, HE_MASK_PAD, wants)."""
         x = np.ascontiguousarray(x, dtype=np.float64)
         h = _V()
         _check(lib().he_encrypt(self.h, _dp(x), x.size, pad, ctypes.byref(h)))

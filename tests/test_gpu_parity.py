@@ -242,6 +242,41 @@ def test_cutmax_toy_refinements_bit_exact(toy, gold):
     assert int(np.argmax(dz[:x.size])) == int(np.argmax(x))
 
 
+def test_cutmax_toy_masked_padding_bit_exact(toy):
+    """HE_MASK_PAD on 1500 logits padded with their mean to 2048 slots, batched with a
+    replicated request: bit-exact against the oracle's masked schedule (pad tracker),
+    the argmax recovered; the replicated request is unchanged by the flag"""
+    from paper_2509_08383_amd import he
+    say("[gpu] cutmax toy masked padding")
+    x = toy_logits(41, 1500) - 6.0
+    pad = float(x.mean())
+    y = np.full(toy.G.slots, pad)
+    y[:x.size] = x
+    m = ckks.encode(y, toy.O.N, toy.O.Delta)
+    g = toy.G.encrypt_coeffs(m, toy.O.Delta, x.size)
+    g.set_pad(pad)
+    o = toy.O.encrypt_coeffs(m, toy.O.Delta)
+    xr = toy_logits(42, 1024)
+    yr, _, _ = slot_layout(xr, toy.G.slots)
+    gr, orr = toy.enc_values(yr)
+    p, c, vlo, vhi, coef = toy_cfg(2048)
+    flags = he.HE_MASK_PAD
+    cfg = he.CutmaxCfg(T=4, p=p, c=c, var_lo=vlo, var_hi=vhi, init_degree=3, init_coef=coef, sum_lo=1.0, sum_hi=3.0,
+                       gold_d=3, flags=flags)
+    Zg = toy.G.cutmax([g, gr], cfg)
+    hc = ckks.HECfg(T=4, p=p, c=c, v_lo=vlo, v_hi=vhi, coef=coef, sum_lo=1.0, sum_hi=3.0, gold_d=3)
+    Zo = ckks.cutmax_he(toy.O, [o], hc, n_real=x.size, pad=pad)[0]
+    toy.same(Zg[0], Zo, "masked cutmax")
+    Zr = ckks.cutmax_he(toy.O, [orr], hc)[0]
+    toy.same(Zg[1], Zr, "replicated request beside a masked one")
+    dz = toy.G.decrypt(Zg[0], x.size)
+    assert int(np.argmax(dz)) == int(np.argmax(x))
+    # the toy chain's 2^30 scale: the tracker subtraction multiplies its error by the
+    # pad count, so the mirror of the logits alone is matched to 2e-2 here (1e-3 at 2^40)
+    mc = MirrorCfg(T=4, p=p, c=c, v_hi=vhi, v_lo=vlo, coef=coef, B=3.0 * x.size, gold_d=3, sum_lo=1.0 * x.size)
+    assert np.abs(dz - cutmax_mirror(x, mc)).max() < 2e-2
+
+
 def test_cutmax_toy_batch_mixed_counts(toy):
     """batched form: requests with 1 and 2 ciphertexts advance together; each equals its
     single-request run bit for bit (n > s splits over several ciphertexts, App. D)."""

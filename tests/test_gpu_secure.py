@@ -146,3 +146,29 @@ def test_goldschmidt_and_newton_refinements_at_full_size(sec):
         assert np.abs(z - cutmax_mirror(y, mc)).max() < 1e-3
         assert int(np.argmax(z[:x.size])) == int(np.argmax(x))
     assert lv[False] - lv[True] == 2
+
+
+@pytest.mark.parametrize("shift", [0.0, 20.0])
+def test_masked_padding_full_size(sec, shift):
+    """HE_MASK_PAD at N = 2^16 on 32000 logits padded with their mean (he_encrypt pad=NaN):
+    the first 32000 outputs match the FP64 mirror run on the 32000 logits alone within
+    1e-3 and recover the argmax, also when every logit is negative (shift 20)"""
+    from paper_2509_08383_amd import he
+    say(f"[gpu] masked padding at N=2^16 (shift {shift})")
+    G = sec.G
+    x = llm_logits(9) - shift
+    ct = G.encrypt(x, pad=float("nan"))
+    vlo, vhi = [12.0, 0.4, 0.8], [24.0, 0.9, 16.0]
+    coef = [list(chebyshev_invsqrt(vlo[t] / vhi[t], 3)) for t in range(3)]
+    cfg = he.CutmaxCfg(T=3, p=[3] * 3, c=[5.0] * 3, var_lo=vlo, var_hi=vhi, init_degree=3, init_coef=coef,
+                       sum_lo=1.0, sum_hi=3.0, gold_d=3, flags=he.HE_MASK_PAD)
+    Z = G.cutmax([ct], cfg)[0]
+    Z = G.cutmax([ct], cfg)[0]
+    say(f"  {G.last_cutmax_ms():.2f} ms")
+    z = G.decrypt(Z, x.size)
+    mc = MirrorCfg(T=3, p=[3] * 3, c=[5.0] * 3, v_hi=vhi, v_lo=vlo, coef=coef, B=3.0 * x.size, gold_d=3,
+                   sum_lo=1.0 * x.size)
+    err = np.abs(z - cutmax_mirror(x, mc)).max()
+    say(f"  max |z - mirror(x)| = {err:.2e}")
+    assert err < 1e-3
+    assert int(np.argmax(z)) == int(np.argmax(x))

@@ -267,3 +267,28 @@ def test_encrypted_invsqr_refinements(toy, gold):
         ref = C * newton_invsqrt_step(newton_invsqrt_step(h0, u, 1.0), u, 1.0)
     np.testing.assert_allclose(toy.decrypt(H), ref, atol=1e-3)
     assert np.abs(ref * np.sqrt(u) / C - 1).max() < 2e-3
+
+
+@pytest.mark.slow
+def test_masked_padding_gives_cutmax_of_the_logits_alone():
+    """Masked padding: 1500 all-negative logits padded (with their mean) to 2048 slots;
+    the encrypted schedule with the pad tracker decrypts, on the first 1500 slots, to the
+    FP64 mirror run on the 1500 logits alone (another vector length), and recovers the
+    argmax; without masking the pad slots would enter mean and variance"""
+    O = ckks.Oracle(ckks.Params(log_n=12, n_q=36, q0_bits=48, q_bits=40, p_bits=48, dnum=3, log2_scale=40, seed=7))
+    O.keygen_cutmax()
+    x = toy_logits(41, 1500) - 6.0
+    pad = float(x.mean())
+    y = np.full(O.slots, pad)
+    y[:x.size] = x
+    T = 4
+    vlo, vhi = [0.5, 0.25, 0.3, 0.6], [2.0, 0.75, 3.0, 128.0]
+    coef = [list(chebyshev_invsqrt(vlo[t] / vhi[t], 3)) for t in range(T)]
+    hc = ckks.HECfg(T=T, p=[3] * T, c=[5.0] * T, v_lo=vlo, v_hi=vhi, coef=coef, sum_lo=1.0, sum_hi=3.0, gold_d=3)
+    Z = ckks.cutmax_he(O, [O.encrypt(y)], hc, n_real=x.size, pad=pad)[0]
+    dz = O.decrypt(Z)[:x.size]
+    mc = MirrorCfg(T=T, p=[3] * T, c=[5.0] * T, v_hi=vhi, v_lo=vlo, coef=coef, B=3.0 * x.size, gold_d=3,
+                   sum_lo=1.0 * x.size)
+    assert np.abs(dz - cutmax_mirror(x, mc)).max() < 1e-4
+    assert int(np.argmax(dz)) == int(np.argmax(x))
+    assert abs(dz.sum() - 1.0) < 1e-2
