@@ -82,7 +82,7 @@ def keyswitch_levels(L: int, T_: int, gold_d: int, slots: int):
         out += [lv] * lg                 # rotsum for the mean
         out += [lv - 1]                  # E^2
         out += [lv - 2] * lg             # rotsum for the variance
-        out += [lv - 2, lv - 3, lv - 3]  # degree-3 initial guess
+        out += [lv - 2, lv - 3]          # degree-3 initial guess: u^2, (g_3 u) u^2
         out += [lv - 4]                  # E * H
         out += [lv - 5, lv - 6]          # cube
         lv -= 7

@@ -475,8 +475,7 @@ class Oracle:
             s2 = U2.scale
             sA = (S * float(q[lu - 1])) / s2
             T3 = self.mul(self.cm_target(U, coef[3], sA), U2)
-            sB = (S * float(q[lu - 1])) / su
-            T2 = self.mul(self.cm_target(U, coef[2], sB), self.drop(U, lu - 1))
+            T2 = self.cm_target(U2, coef[2], S)
             T1 = self.cm_target(self.drop(U, lu - 1), coef[1], S)
             H = self.add_const(self.add(self.add(T3, T2), T1), coef[0])
         elif d == 4:

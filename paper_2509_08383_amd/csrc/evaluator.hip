@@ -650,14 +650,13 @@ Bt invsqr(Exec &X, const Bt &U, const std::vector<std::vector<double>> &coefC, c
         Bt T1 = X.cmul(X.drop(U, lu - 1), col(1), S, false);
         H = X.add_const(X.add(T2, T1), col(0));
     } else if (d == 3) {
+        // two ciphertext products: u^2, then (g_3 u) u^2; g_2 u^2 and g_1 u are
+        // constant multiplies landing on the same level
         Bt U2 = X.mul(U, U);
-        std::vector<double> sA(R), sB(R);
-        for (int r = 0; r < R; ++r) {
-            sA[r] = (S[r] * (double)q[lu - 1]) / U2.scale[r];
-            sB[r] = (S[r] * (double)q[lu - 1]) / U.scale[r];
-        }
+        std::vector<double> sA(R);
+        for (int r = 0; r < R; ++r) sA[r] = (S[r] * (double)q[lu - 1]) / U2.scale[r];
         Bt T3 = X.mul(X.cmul(U, col(3), sA, false), U2);
-        Bt T2 = X.mul(X.cmul(U, col(2), sB, false), X.drop(U, lu - 1));
+        Bt T2 = X.cmul(U2, col(2), S, false);
         Bt T1 = X.cmul(X.drop(U, lu - 1), col(1), S, false);
         H = X.add_const(X.add(X.add(T3, T2), T1), col(0));
     } else if (d == 4) {
