@@ -392,17 +392,17 @@ struct Exec {
                        false, C->ntt_variant, s);
             if (rot)
                 launch_inner_product_rot(T, ext, (long long)beta * next * N, (long long)next * N, acc,
-                                         acc + (long long)next * N, 2LL * next * N, *rot, 2LL * C->np * N,
-                                         (long long)C->np * N, cnt, beta, next, C->ext_prime[l], s);
+                                         acc + (long long)next * N, 2LL * next * N, *rot, C->betaL, cnt, beta,
+                                         next, C->ext_prime[l], s);
             else if (mrescale)
                 launch_inner_product(T, ext, (long long)beta * next * N, (long long)next * N, acc,
-                                     acc + (long long)next * N, 2LL * next * N, C->keys[kidx], 2LL * C->np * N,
-                                     (long long)C->np * N, cnt, beta, next, C->ext_prime[l], s,
-                                     a1.p + (long long)l * N, a1.ct, a1.poly, l, C->pmod_h[l]);
+                                     acc + (long long)next * N, 2LL * next * N, C->keys[kidx], C->betaL, cnt,
+                                     beta, next, C->ext_prime[l], s, a1.p + (long long)l * N, a1.ct, a1.poly, l,
+                                     C->pmod_h[l]);
             else
                 launch_inner_product(T, ext, (long long)beta * next * N, (long long)next * N, acc,
-                                     acc + (long long)next * N, 2LL * next * N, C->keys[kidx], 2LL * C->np * N,
-                                     (long long)C->np * N, cnt, beta, next, C->ext_prime[l], s);
+                                     acc + (long long)next * N, 2LL * next * N, C->keys[kidx], C->betaL, cnt,
+                                     beta, next, C->ext_prime[l], s);
             if (mrescale) {
                 // B = {q_l, P} to the coefficient domain, scaled by Bhat^-1; convert to q_0..q_{l-1};
                 // transform and combine on store: (acc - conv) (P q_l)^-1 + d q_l^-1
@@ -1236,7 +1236,7 @@ void keygen(he_ctx *C) {
             const int lo = j * C->alpha, hi = std::min(lo + C->alpha, C->L + 1);
             launch_keyb(T, kb, ka, te, C->d_sk, tg, C->pmod, np, lo, hi, s);
         }
-        launch_pack_key(tk, klo, khi, kw, s);
+        launch_pack_key(tk, klo, khi, C->betaL, np, N, s);
     }
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipGetLastError());

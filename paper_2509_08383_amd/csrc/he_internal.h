@@ -47,8 +47,11 @@ struct ConstTab {
     int stride;
 };
 
-// An evaluation key [beta][2][np][N] of residues below 2^48, stored as two planes:
-// the low 32 bits and the high 16 bits of every word (6 bytes a word).
+// An evaluation key of residues below 2^48 with the two polynomials of a digit
+// interleaved: word (limb t, digit j, position x, polynomial c) is at index
+// ((t beta_L + j) N + x) 2 + c, so a lane reads both words of a digit with one 8-byte
+// and one 4-byte load and a wave's loads are contiguous.  Stored as two planes: the
+// low 32 bits and the high 16 bits of every word (6 bytes a word).
 struct KeyRef {
     const uint32_t *lo;
     const uint16_t *hi;
@@ -138,11 +141,11 @@ void launch_modup(const DevTables &T, const double *v, long long vstride, double
                   const int *ext_prime, const ModUpDigits &dg, hipStream_t s);
 void launch_inner_product(const DevTables &T, const double *ext, long long estride_b,
                           long long estride_j, double *acc0, double *acc1, long long astride,
-                          KeyRef key, long long kstride_j, long long kstride_c, int cnt,
+                          KeyRef key, int betaL, int cnt,
                           int beta, int next, const int *ext_prime, hipStream_t s,
                           const double *dadd = nullptr, long long dct = 0, long long dpoly = 0, int tl = -1,
                           double pmodl = 0.0);
-void launch_pack_key(const double *src, uint32_t *lo, uint16_t *hi, size_t n, hipStream_t s);
+void launch_pack_key(const double *src, uint32_t *lo, uint16_t *hi, int beta, int np, int N, hipStream_t s);
 
 // rotations of one hoisted rotate-and-sum step: key and Galois element of each
 constexpr int kMaxHoist = 15;
@@ -159,8 +162,8 @@ struct RotSet {
     const int *xorder;  // the N/256 x-blocks in the orbit order of g[0] (device)
 };
 void launch_inner_product_rot(const DevTables &T, const double *ext, long long estride_b, long long estride_j,
-                              double *acc0, double *acc1, long long astride, const RotSet &rs, long long kstride_j,
-                              long long kstride_c, int cnt, int beta, int next, const int *ext_prime, hipStream_t s);
+                              double *acc0, double *acc1, long long astride, const RotSet &rs, int betaL,
+                              int cnt, int beta, int next, const int *ext_prime, hipStream_t s);
 // inputs: slots in0 .. in0+nin-1 of each group, prime index in_prime[m]; targets
 // q_0 .. q_{ntgt-1}; [Bhat_m]_{q_i} = ph[m * phs + i]
 struct MdIn {

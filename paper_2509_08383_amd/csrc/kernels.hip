@@ -328,19 +328,31 @@ void launch_modup(const DevTables &T, const double *v, long long vstride, double
                     beta, next, ext_prime, dg);
 }
 
-// key word i of a packed key: hi 2^32 + lo, exact (below 2^48)
-DEV double key_at(const KeyRef &k, long long i) { return __builtin_fma((double)k.hi[i], 4294967296.0, (double)k.lo[i]); }
+// the two words (polynomials 0, 1) of digit j of limb t at position x: hi 2^32 + lo,
+// exact (below 2^48); one 8-byte load of the low halves, one 4-byte load of the high
+DEV void key_pair(const KeyRef &k, int betaL, int t, int j, int N, int x, double &k0, double &k1) {
+    const long long i = (((long long)t * betaL + j) * N + x) * 2;
+    const uint2 l = *(const uint2 *)(k.lo + i);
+    const uint32_t h = *(const uint32_t *)(k.hi + i);
+    k0 = __builtin_fma((double)(h & 0xffffu), 4294967296.0, (double)l.x);
+    k1 = __builtin_fma((double)(h >> 16), 4294967296.0, (double)l.y);
+}
 
+// src [beta][2][np][N] doubles -> packed planes with the polynomials interleaved
 __global__ void k_pack_key(const double *__restrict__ src, uint32_t *__restrict__ lo, uint16_t *__restrict__ hi,
-                           size_t n) {
+                           int beta, int np, int N) {
+    const size_t per = (size_t)np * N, n = (size_t)beta * 2 * per;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const size_t jc = i / per, pos = i - jc * per;  // jc = 2 j + c, pos = t N + x
+        const size_t j = jc >> 1, c = jc & 1, t = pos / (size_t)N, x = pos - t * (size_t)N;
+        const size_t o = ((t * (size_t)beta + j) * (size_t)N + x) * 2 + c;
         const uint64_t v = (uint64_t)src[i];
-        lo[i] = (uint32_t)v;
-        hi[i] = (uint16_t)(v >> 32);
+        lo[o] = (uint32_t)v;
+        hi[o] = (uint16_t)(v >> 32);
     }
 }
-void launch_pack_key(const double *src, uint32_t *lo, uint16_t *hi, size_t n, hipStream_t s) {
-    KL("k_pack_key", k_pack_key, dim3(4096), dim3(256), 0, s, src, lo, hi, n);
+void launch_pack_key(const double *src, uint32_t *lo, uint16_t *hi, int beta, int np, int N, hipStream_t s) {
+    KL("k_pack_key", k_pack_key, dim3(4096), dim3(256), 0, s, src, lo, hi, beta, np, N);
 }
 
 // acc_c[ct][t] = sum_j ext[ct][j][t] * key[j][c][prime(t)]; the key words are
@@ -349,7 +361,7 @@ void launch_pack_key(const double *src, uint32_t *lo, uint16_t *hi, size_t n, hi
 // (the tensor's d0/d1 at limb tl: the relinearisation with the rescale folded in).
 __global__ void k_inner_product(DevTables T, const double *ext, long long esb, long long esj,
                                 double *acc0, double *acc1, long long astride, KeyRef key,
-                                long long ksj, long long ksc, int cnt, int beta, const int *ext_prime,
+                                int betaL, int cnt, int beta, const int *ext_prime,
                                 const double *dadd, long long dct, long long dpoly, int tl, double pmodl) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= T.N) return;
@@ -358,12 +370,8 @@ __global__ void k_inner_product(DevTables T, const double *ext, long long esb, l
     const double p = T.p[pt], pinv = T.pinv[pt];
     double k0[8], k1[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        if (j < beta) {
-            k0[j] = key_at(key, j * ksj + (long long)pt * T.N + x);
-            k1[j] = key_at(key, j * ksj + ksc + (long long)pt * T.N + x);
-        }
-    }
+    for (int j = 0; j < 8; ++j)
+        if (j < beta) key_pair(key, betaL, pt, j, T.N, x, k0[j], k1[j]);
     for (int ct = 0; ct < cnt; ++ct) {
         double s0 = 0.0, s1 = 0.0;
 #pragma unroll
@@ -384,14 +392,14 @@ __global__ void k_inner_product(DevTables T, const double *ext, long long esb, l
 }
 void launch_inner_product(const DevTables &T, const double *ext, long long estride_b,
                           long long estride_j, double *acc0, double *acc1, long long astride,
-                          KeyRef key, long long kstride_j, long long kstride_c, int cnt,
+                          KeyRef key, int betaL, int cnt,
                           int beta, int next, const int *ext_prime, hipStream_t s, const double *dadd,
                           long long dct, long long dpoly, int tl, double pmodl) {
     if (cnt <= 0) return;
     // key words (6 bytes each) once, extended digits and both accumulators per ciphertext
     kprof_set_bytes(T.N * next * (6.0 * 2.0 * beta + 8.0 * cnt * (beta + 2.0)));
     KL("k_inner_product", k_inner_product, dim3((T.N + 255) / 256, next), dim3(256), 0, s, T, ext,
-                       estride_b, estride_j, acc0, acc1, astride, key, kstride_j, kstride_c, cnt,
+                       estride_b, estride_j, acc0, acc1, astride, key, betaL, cnt,
                        beta, ext_prime, dadd, dct, dpoly, tl, pmodl);
 }
 
@@ -415,7 +423,7 @@ template <int BETA>
 __global__ __launch_bounds__(256) void k_inner_product_rot(DevTables T, const double *__restrict__ ext,
                                                            long long esb, long long esj, double *__restrict__ acc0,
                                                            double *__restrict__ acc1, long long astride, RotSet rs,
-                                                           long long ksj, long long ksc, int cnt, int beta_rt,
+                                                           int betaL, int cnt, int beta_rt,
                                                            int next, const int *__restrict__ ext_prime,
                                                            int xblocks) {
     const int beta = BETA > 0 ? BETA : beta_rt;
@@ -427,7 +435,6 @@ __global__ __launch_bounds__(256) void k_inner_product_rot(DevTables T, const do
     if (x >= T.N) return;
     const int pt = ext_prime[t];
     const double p = T.p[pt], pinv = T.pinv[pt];
-    const long long ko = (long long)pt * T.N + x;
     const bool wsum = rs.c0 && t <= rs.lq;
     for (int ct = 0; ct < cnt; ++ct) {
         const double *E = ext + ct * esb + (long long)t * T.N;
@@ -442,8 +449,7 @@ __global__ __launch_bounds__(256) void k_inner_product_rot(DevTables T, const do
 #pragma unroll
                 for (int j = 0; j < JM; ++j) {
                     e[j] = E[j * esj + src];
-                    a0[j] = key_at(K, j * ksj + ko);
-                    a1[j] = key_at(K, j * ksj + ksc + ko);
+                    key_pair(K, betaL, pt, j, T.N, x, a0[j], a1[j]);
                 }
 #pragma unroll
                 for (int j = 0; j < JM; ++j) {
@@ -455,8 +461,10 @@ __global__ __launch_bounds__(256) void k_inner_product_rot(DevTables T, const do
                 for (int j = 0; j < JM; ++j) {
                     if (j < beta) {
                         const double e = E[j * esj + src];
-                        s0 += mm(e, key_at(K, j * ksj + ko), p, pinv);
-                        s1 += mm(e, key_at(K, j * ksj + ksc + ko), p, pinv);
+                        double w0, w1;
+                        key_pair(K, betaL, pt, j, T.N, x, w0, w1);
+                        s0 += mm(e, w0, p, pinv);
+                        s1 += mm(e, w1, p, pinv);
                     }
                 }
             }
@@ -475,8 +483,8 @@ template <int NR>
 __global__ __launch_bounds__(256) void k_inner_product_rot_reg(DevTables T, const double *__restrict__ ext,
                                                                long long esb, long long esj,
                                                                double *__restrict__ acc0, double *__restrict__ acc1,
-                                                               long long astride, RotSet rs, long long ksj,
-                                                               long long ksc, int cnt, int beta, int next,
+                                                               long long astride, RotSet rs, int betaL,
+                                                               int cnt, int beta, int next,
                                                                const int *__restrict__ ext_prime, int xblocks) {
     const int b = blockIdx.x, slot = b >> 3;
     const int t = (b & 7) + 8 * (slot / xblocks);
@@ -485,7 +493,6 @@ __global__ __launch_bounds__(256) void k_inner_product_rot_reg(DevTables T, cons
     if (x >= T.N) return;
     const int pt = ext_prime[t];
     const double p = T.p[pt], pinv = T.pinv[pt];
-    const long long ko = (long long)pt * T.N + x;
     double k0[NR][3], k1[NR][3];
     unsigned src[NR];
 #pragma unroll
@@ -494,8 +501,9 @@ __global__ __launch_bounds__(256) void k_inner_product_rot_reg(DevTables T, cons
         const KeyRef K = rs.key[r];
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            k0[r][j] = j < beta ? key_at(K, j * ksj + ko) : 0.0;
-            k1[r][j] = j < beta ? key_at(K, j * ksj + ksc + ko) : 0.0;
+            k0[r][j] = 0.0;
+            k1[r][j] = 0.0;
+            if (j < beta) key_pair(K, betaL, pt, j, T.N, x, k0[r][j], k1[r][j]);
         }
     }
     const bool wsum = rs.c0 && t <= rs.lq;
@@ -528,8 +536,8 @@ __global__ __launch_bounds__(256) void k_inner_product_rot_reg(DevTables T, cons
 }
 
 void launch_inner_product_rot(const DevTables &T, const double *ext, long long estride_b, long long estride_j,
-                              double *acc0, double *acc1, long long astride, const RotSet &rs, long long kstride_j,
-                              long long kstride_c, int cnt, int beta, int next, const int *ext_prime, hipStream_t s) {
+                              double *acc0, double *acc1, long long astride, const RotSet &rs, int betaL,
+                              int cnt, int beta, int next, const int *ext_prime, hipStream_t s) {
     if (cnt <= 0) return;
     // every rotation's key words once; the extended digits and both accumulators
     // once per ciphertext
@@ -541,25 +549,25 @@ void launch_inner_product_rot(const DevTables &T, const double *ext, long long e
     const bool reg = cnt >= 2 && beta <= 3;
     if (reg && rs.nr == 7)
         KL("k_inner_product_rot", k_inner_product_rot_reg<7>, g1, dim3(256), 0, s, T, ext, estride_b, estride_j, acc0,
-           acc1, astride, rs, kstride_j, kstride_c, cnt, beta, next, ext_prime, xblocks);
+           acc1, astride, rs, betaL, cnt, beta, next, ext_prime, xblocks);
     else if (reg && rs.nr == 3)
         KL("k_inner_product_rot", k_inner_product_rot_reg<3>, g1, dim3(256), 0, s, T, ext, estride_b, estride_j, acc0,
-           acc1, astride, rs, kstride_j, kstride_c, cnt, beta, next, ext_prime, xblocks);
+           acc1, astride, rs, betaL, cnt, beta, next, ext_prime, xblocks);
     else if (reg && rs.nr == 1)
         KL("k_inner_product_rot", k_inner_product_rot_reg<1>, g1, dim3(256), 0, s, T, ext, estride_b, estride_j, acc0,
-           acc1, astride, rs, kstride_j, kstride_c, cnt, beta, next, ext_prime, xblocks);
+           acc1, astride, rs, betaL, cnt, beta, next, ext_prime, xblocks);
     else if (beta == 3)
         KL("k_inner_product_rot", k_inner_product_rot<3>, g1, dim3(256), 0, s, T, ext, estride_b, estride_j, acc0,
-           acc1, astride, rs, kstride_j, kstride_c, cnt, beta, next, ext_prime, xblocks);
+           acc1, astride, rs, betaL, cnt, beta, next, ext_prime, xblocks);
     else if (beta == 2)
         KL("k_inner_product_rot", k_inner_product_rot<2>, g1, dim3(256), 0, s, T, ext, estride_b, estride_j, acc0,
-           acc1, astride, rs, kstride_j, kstride_c, cnt, beta, next, ext_prime, xblocks);
+           acc1, astride, rs, betaL, cnt, beta, next, ext_prime, xblocks);
     else if (beta == 1)
         KL("k_inner_product_rot", k_inner_product_rot<1>, g1, dim3(256), 0, s, T, ext, estride_b, estride_j, acc0,
-           acc1, astride, rs, kstride_j, kstride_c, cnt, beta, next, ext_prime, xblocks);
+           acc1, astride, rs, betaL, cnt, beta, next, ext_prime, xblocks);
     else
         KL("k_inner_product_rot", k_inner_product_rot<0>, g1, dim3(256), 0, s, T, ext, estride_b, estride_j, acc0,
-           acc1, astride, rs, kstride_j, kstride_c, cnt, beta, next, ext_prime, xblocks);
+           acc1, astride, rs, betaL, cnt, beta, next, ext_prime, xblocks);
 }
 
 // ModDown conversion: acc holds, at slots in0 .. in0+nin-1 of every group, the
