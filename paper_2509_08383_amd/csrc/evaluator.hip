@@ -304,6 +304,16 @@ struct Exec {
     // per-request sums of consecutive ciphertexts
     Bt sum_groups(const Bt &Y, const std::vector<int> &first, const std::vector<int> &cnt) {
         const int R = (int)first.size();
+        // one ciphertext per request, in order: the sums are the ciphertexts themselves
+        // (a view; its consumers read it and write elsewhere)
+        bool ident = R <= Y.cnt;
+        for (int r = 0; r < R && ident; ++r) ident = first[r] == r && cnt[r] == 1;
+        if (ident) {
+            Bt v = Y;
+            v.cnt = R;
+            v.scale.resize(R);
+            return v;
+        }
         Bt o = new_bt(R, Y.level);
         for (int r = 0; r < R; ++r) {
             o.scale[r] = Y.scale[first[r]];

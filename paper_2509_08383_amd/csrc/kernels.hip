@@ -179,6 +179,9 @@ __global__ void k_sum_groups(VecSet out, VecSet in, const int *first, const int 
 void launch_sum_groups(const DevTables &T, const VecSet &out, const VecSet &in, const int *first,
                        const int *cnt, int gdiv, hipStream_t s) {
     if (out.count <= 0) return;
+    // the summed words are not known on the host (counts live on the device): every
+    // output word with one input word is booked
+    kprof_set_bytes(16.0 * T.N * out.count);
     KL("k_sum_groups", k_sum_groups, ew_grid(T, out.count), dim3(256), 0, s, out, in, first, cnt, gdiv, T);
 }
 
