@@ -172,3 +172,35 @@ def test_masked_padding_full_size(sec, shift):
     say(f"  max |z - mirror(x)| = {err:.2e}")
     assert err < 1e-3
     assert int(np.argmax(z)) == int(np.argmax(x))
+
+
+def test_bench_configuration_graph_replay():
+    """the configuration bench.py times: a fresh 128-bit context with HIP-graph replay, the
+    library's own degree-3 Chebyshev fit, the bench's 32000-logit input; the capture and two
+    replays equal the eager run bit for bit and decrypt to the FP64 mirror within 1e-3; the
+    16-request batch likewise replays bit-exactly"""
+    from paper_2509_08383_amd import he
+    say("[gpu] bench configuration: graph capture and replays")
+    G = he.Context(he.SECURE)
+    cfg = he.CutmaxCfg(T=3, p=[3] * 3, c=[5.0] * 3, var_lo=VLO, var_hi=VHI, init_degree=3, init_coef=None,
+                       newton_steps=0, sum_lo=1.0, sum_hi=3.0, gold_d=3)
+    x = llm_logits(0)
+    y, _, _ = slot_layout(x, G.slots)
+    ct = G.encrypt(x)
+    xs = [llm_logits(200 + r, 32000 if r % 2 == 0 else 128256) for r in range(16)]
+    cts = [G.encrypt(v) for v in xs]
+    eager = G.export(G.cutmax([ct], cfg)[0])
+    eager_b = [G.export(z) for z in G.cutmax(cts, cfg)]
+    G.set_option(he.HE_OPT_GRAPH, 1)
+    runs = [G.cutmax([ct], cfg)[0] for _ in range(3)]
+    say(f"  replay {G.last_cutmax_ms():.2f} ms")
+    for k, z in enumerate(runs):
+        assert np.array_equal(G.export(z), eager), k
+    for _ in range(2):
+        Zb = G.cutmax(cts, cfg)
+        for r in (0, 1, 14, 15):
+            assert np.array_equal(G.export(Zb[r]), eager_b[r]), r
+    coef = [list(chebyshev_invsqrt(VLO[t] / VHI[t], 3)) for t in range(3)]
+    dz = G.decrypt(runs[-1], y.size)
+    assert np.abs(dz - cutmax_mirror(y, mirror2(y, coef))).max() < 1e-3
+    assert int(np.argmax(dz[:x.size])) == int(np.argmax(x))
