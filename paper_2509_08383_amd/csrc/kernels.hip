@@ -243,16 +243,34 @@ void launch_automorph(const DevTables &T, const VecSet &out, const VecSet &in, u
 // lane reads the same word: a broadcast); terms a >= dl and own-digit targets carry
 // zero constants, so the DL products of a target run without branches as independent
 // chains.  |sum| <= DL (p/2 + 2^44) < 2^52 for DL <= 16.
+// Basis-conversion grids are one-dimensional and XCD-aware: workgroup b runs on XCD
+// b mod 8, and the target blocks of one coefficient block (which all read the same
+// input words) are consecutive workgroups of one XCD, so the input is fetched from
+// HBM once and re-read from that XCD's L2.  Returns false for padding workgroups.
+struct ConvIdx { int tb, cb, z; };
+DEV bool conv_idx(int b, int ntb, int cblk, int nz, ConvIdx &o) {
+    const int slot = b >> 3, c = (slot / ntb) * 8 + (b & 7);
+    if (c >= cblk * nz) return false;
+    o.tb = slot % ntb;
+    o.cb = c % cblk;
+    o.z = c / cblk;
+    return true;
+}
+static dim3 conv_grid(int ntb, int cblk, int nz) { return dim3(8 * ntb * ((cblk * nz + 7) / 8)); }
+
 template <int DL, int TB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_modup(DevTables T, const double *__restrict__ v, long long vstride,
                                                double *__restrict__ ext, long long esb, long long esj,
                                                const double *__restrict__ dntt, long long nstride, int beta,
-                                               int next, const int *__restrict__ ext_prime, ModUpDigits dg) {
+                                               int next, const int *__restrict__ ext_prime, ModUpDigits dg,
+                                               int ntb, int cblk, int nz) {
     __shared__ double sq[DL * TB];
     __shared__ double sp[TB], si[TB];
-    const int ct = blockIdx.z / beta, j = blockIdx.z - (blockIdx.z / beta) * beta;
+    ConvIdx ix;
+    if (!conv_idx(blockIdx.x, ntb, cblk, nz, ix)) return;
+    const int ct = ix.z / beta, j = ix.z - (ix.z / beta) * beta;
     const int lo = dg.lo[j], dl = dg.dl[j];
-    const int t0 = blockIdx.x * TB, tid = threadIdx.x;
+    const int t0 = ix.tb * TB, tid = threadIdx.x;
     {
         const double *qh = dg.qhat[j];
         for (int i = tid; i < DL * TB; i += blockDim.x) {
@@ -267,7 +285,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         }
     }
     __syncthreads();
-    const int x = blockIdx.y * blockDim.x + tid;
+    const int x = ix.cb * blockDim.x + tid;
     if (x >= T.N) return;
     bool need = false;
 #pragma unroll
@@ -297,13 +315,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 static int digit_len(int dl) { return dl <= 4 ? 4 : dl <= 8 ? 8 : dl <= 10 ? 10 : dl <= 12 ? 12 : 16; }
 
 template <int TB>
-static void modup_tb(int DL, dim3 grid, hipStream_t s, const DevTables &T, const double *v, long long vstride,
+static void modup_tb(int DL, int cblk, int nz, hipStream_t s, const DevTables &T, const double *v, long long vstride,
                      double *ext, long long esb, long long esj, const double *dntt, long long nstride, int beta,
                      int next, const int *ext_prime, const ModUpDigits &dg) {
+    const int ntb = (next + TB - 1) / TB;
+    const dim3 grid = conv_grid(ntb, cblk, nz);
 #define MU_CASE(D)                                                                                          \
     case D:                                                                                                 \
         KL("k_modup", (k_modup<D, TB>), grid, dim3(256), 0, s, T, v, vstride, ext, esb, esj, dntt, nstride, \
-           beta, next, ext_prime, dg);                                                                      \
+           beta, next, ext_prime, dg, ntb, cblk, nz);                                                       \
         break;
     switch (DL) { MU_CASE(4) MU_CASE(8) MU_CASE(10) MU_CASE(12) MU_CASE(16) }
 #undef MU_CASE
@@ -324,11 +344,11 @@ void launch_modup(const DevTables &T, const double *v, long long vstride, double
     // the l+1 digit words and the l+1 NTT-domain words in, every extended slot out
     kprof_set_bytes(8.0 * T.N * cnt * (2.0 * lp1 + (double)beta * next));
     if (wide)
-        modup_tb<8>(DL, dim3((next + 7) / 8, cblk, cnt * beta), s, T, v, vstride, ext, esb, esj, dntt, nstride,
-                    beta, next, ext_prime, dg);
+        modup_tb<8>(DL, cblk, cnt * beta, s, T, v, vstride, ext, esb, esj, dntt, nstride, beta, next, ext_prime,
+                    dg);
     else
-        modup_tb<4>(DL, dim3((next + 3) / 4, cblk, cnt * beta), s, T, v, vstride, ext, esb, esj, dntt, nstride,
-                    beta, next, ext_prime, dg);
+        modup_tb<4>(DL, cblk, cnt * beta, s, T, v, vstride, ext, esb, esj, dntt, nstride, beta, next, ext_prime,
+                    dg);
 }
 
 // the two words (polynomials 0, 1) of digit j of limb t at position x: hi 2^32 + lo,
@@ -583,10 +603,12 @@ void launch_inner_product_rot(const DevTables &T, const double *ext, long long e
 template <int AL, int TB>
 __global__ __launch_bounds__(256) void k_moddown_conv(DevTables T, const double *__restrict__ acc,
                                                       long long astride, double *__restrict__ conv,
-                                                      long long cstride, MdIn md) {
+                                                      long long cstride, MdIn md, int ntb, int cblk, int nz) {
     __shared__ double sq[AL * TB];
     __shared__ double sp[TB], si[TB];
-    const int i0 = blockIdx.x * TB, tid = threadIdx.x;
+    ConvIdx ix;
+    if (!conv_idx(blockIdx.x, ntb, cblk, nz, ix)) return;
+    const int i0 = ix.tb * TB, tid = threadIdx.x;
     for (int k = tid; k < AL * TB; k += blockDim.x) {
         const int m = k / TB, i = i0 + (k - (k / TB) * TB);
         sq[k] = (m < md.nin && i < md.ntgt) ? md.ph[m * md.phs + i] : 0.0;
@@ -597,9 +619,9 @@ __global__ __launch_bounds__(256) void k_moddown_conv(DevTables T, const double 
         si[tid] = T.pinv[i];
     }
     __syncthreads();
-    const int x = blockIdx.y * blockDim.x + tid;
+    const int x = ix.cb * blockDim.x + tid;
     if (x >= T.N) return;
-    const double *Ac = acc + blockIdx.z * astride + (long long)md.in0 * T.N + x;
+    const double *Ac = acc + ix.z * astride + (long long)md.in0 * T.N + x;
     double w[AL];
 #pragma unroll
     for (int m = 0; m < AL; ++m) {
@@ -611,7 +633,7 @@ __global__ __launch_bounds__(256) void k_moddown_conv(DevTables T, const double 
             w[m] = 0.0;
         }
     }
-    double *out = conv + blockIdx.z * cstride + x;
+    double *out = conv + ix.z * cstride + x;
 #pragma unroll
     for (int ii = 0; ii < TB; ++ii) {
         const int i = i0 + ii;
@@ -625,12 +647,14 @@ __global__ __launch_bounds__(256) void k_moddown_conv(DevTables T, const double 
 }
 
 template <int TB>
-static void conv_tb(int AL, dim3 grid, hipStream_t s, const DevTables &T, const double *acc, long long astride,
+static void conv_tb(int AL, int cblk, int nz, hipStream_t s, const DevTables &T, const double *acc, long long astride,
                     double *conv, long long cstride, const MdIn &md) {
+    const int ntb = (md.ntgt + TB - 1) / TB;
+    const dim3 grid = conv_grid(ntb, cblk, nz);
 #define MD_CASE(D)                                                                                             \
     case D:                                                                                                    \
         KL("k_moddown_conv", (k_moddown_conv<D, TB>), grid, dim3(256), 0, s, T, acc, astride, conv, cstride, \
-           md);                                                                                                \
+           md, ntb, cblk, nz);                                                                                 \
         break;
     switch (AL) { MD_CASE(4) MD_CASE(8) MD_CASE(10) MD_CASE(12) MD_CASE(16) }
 #undef MD_CASE
@@ -644,9 +668,9 @@ void launch_moddown_conv(const DevTables &T, const double *acc, long long astrid
     const bool wide = (long long)((md.ntgt + 7) / 8) * cblk * groups >= 2048;
     kprof_set_bytes(8.0 * T.N * groups * (md.nin + md.ntgt));
     if (wide)
-        conv_tb<8>(AL, dim3((md.ntgt + 7) / 8, cblk, groups), s, T, acc, astride, conv, cstride, md);
+        conv_tb<8>(AL, cblk, groups, s, T, acc, astride, conv, cstride, md);
     else
-        conv_tb<4>(AL, dim3((md.ntgt + 3) / 4, cblk, groups), s, T, acc, astride, conv, cstride, md);
+        conv_tb<4>(AL, cblk, groups, s, T, acc, astride, conv, cstride, md);
 }
 
 // ---------------------------------------------------------------- sampling
