@@ -7,7 +7,8 @@ degree-3 Chebyshev inverse-square-root guess, Goldschmidt inverse with 3 squarin
 The ciphertext is resident in HBM before the timed region.
 
 Also reported: batched argmaxes/s (16 requests: 8 x 32000 logits in 1 ciphertext and
-8 x 128256 logits in 4 ciphertexts), NTT GB/s, the roofline of the dominant kernel
+8 x 128256 logits in 4 ciphertexts), one CutMax of 151936 logits (5 ciphertexts), NTT GB/s,
+the roofline of the dominant kernel
 (HIP events on the library's stream) and the CPU oracle timed on a bounded sample.
 
 Prints one JSON line.  --gpus N > 1 is not supported (one GPU per box).
@@ -278,6 +279,21 @@ def main():
             "GBps": 2 * 64 * ctx.N * 8 / (cms * 1e-3) / 1e9}
     log(f"[bench] copy {copy}")
 
+    # --- the largest vocabulary of the paper's experiments (151936 logits, 5 ciphertexts)
+    xq = llm_logits(300, 151936)
+    ctq = ctx.encrypt(xq)
+    ctx.cutmax([ctq], cfg)
+    ctx.sync()
+    tq0 = time.perf_counter()
+    for _ in range(3):
+        Zq = ctx.cutmax([ctq], cfg)[0]
+    ctx.sync()
+    tq1 = time.perf_counter()
+    vocab_151936 = {"ciphertexts": ctq.a, "ms": (tq1 - tq0) * 1e3 / 3,
+                    "argmax_ok": int(np.argmax(ctx.decrypt(Zq, xq.size))) == int(np.argmax(xq))}
+    log(f"[bench] 151936 logits {vocab_151936}")
+    del ctq, Zq
+
     # --- batched argmaxes/s (16 mixed-vocabulary requests)
     batch = None
     if not args.no_batch:
@@ -351,6 +367,7 @@ def main():
         "src_digest": digest,
         "argmax_ok": bool(argmax_ok),
         "batched": batch,
+        "vocab_151936": vocab_151936,
         "ntt": ntt,
         "copy": copy,
         "ntt_tuning": ctx.ntt_tuning(),

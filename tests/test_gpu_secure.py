@@ -204,3 +204,33 @@ def test_bench_configuration_graph_replay():
     dz = G.decrypt(runs[-1], y.size)
     assert np.abs(dz - cutmax_mirror(y, mirror2(y, coef))).max() < 1e-3
     assert int(np.argmax(dz[:x.size])) == int(np.argmax(x))
+
+
+@pytest.mark.parametrize("masked", [False, True])
+def test_qwen_vocabulary_five_ciphertexts(sec, masked):
+    """the largest vocabulary of the paper's experiments (Qwen2.5, 151936 logits, Table 2) in
+    5 ciphertexts of 32768 slots, zero-padded or masked with mean padding: the decrypted
+    outputs match the FP64 mirror of the packed vector (or of the logits alone) within 1e-3 and
+    recover the argmax"""
+    from paper_2509_08383_amd import he
+    say(f"[gpu] 151936 logits in 5 ciphertexts (masked={masked})")
+    G = sec.G
+    x = llm_logits(300, 151936)
+    ct = G.encrypt(x, pad=float("nan") if masked else 0.0)
+    assert ct.a == 5
+    cfg, coef = cfg2(he)
+    if masked:
+        cfg.flags = he.HE_MASK_PAD
+    Z = G.cutmax([ct], cfg)[0]
+    say(f"  {G.last_cutmax_ms():.1f} ms")
+    if masked:
+        z = G.decrypt(Z, x.size)
+        mc = MirrorCfg(T=3, p=[3] * 3, c=[5.0] * 3, v_hi=VHI, v_lo=VLO, coef=coef, B=3.0 * x.size, gold_d=3,
+                       sum_lo=1.0 * x.size)
+        ref = cutmax_mirror(x, mc)
+    else:
+        y, _, _ = slot_layout(x, G.slots)
+        z = G.decrypt(Z, y.size)
+        ref = cutmax_mirror(y, mirror2(y, coef))
+    assert np.abs(z - ref).max() < 1e-3
+    assert int(np.argmax(z[:x.size])) == int(np.argmax(x))
