@@ -73,7 +73,6 @@ void kprof_set_bytes(double algorithmic_bytes);  // for the next launch
 
 // NTT workgroup-width tuning (ntt.hip): variant 1..3 per (log N, batch bucket)
 void set_ntt_tuning(int logN, int bucket, int variant);
-int ntt_bucket(int count);
 
 // ---------------------------------------------------------------- kernels.hip
 // in place, or from *src into vs; the inverse multiplies by oscale[r] (per slot)
@@ -189,7 +188,6 @@ void launch_encfinish(const DevTables &T, double *c0, const double *a, const dou
 void launch_decmul(const DevTables &T, double *m, const double *c0, const double *c1,
                    const double *s, int limbs, hipStream_t st);
 void launch_square_res(const DevTables &T, double *out, const double *in, int np, hipStream_t st);
-void launch_canon_check(const DevTables &T, const VecSet &vs, int *bad, hipStream_t st);
 
 // ----------------------------------------------------------------- host math
 uint64_t mulmod_u(uint64_t a, uint64_t b, uint64_t q);

@@ -822,18 +822,4 @@ void launch_square_res(const DevTables &T, double *out, const double *in, int np
     KL("k_square_res", k_square_res, dim3((T.N + 255) / 256, np), dim3(256), 0, st, T, out, in);
 }
 
-// debug: count words that are not canonical integers in [0, p)
-__global__ void k_canon_check(VecSet vs, DevTables T, int *bad) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= T.N) return;
-    double *pv; int pr, g, r;
-    vs_at(vs, blockIdx.y, T.N, pv, pr, g, r);
-    const double v = pv[x];
-    if (!(v >= 0.0 && v < T.p[pr] && v == __builtin_rint(v))) atomicAdd(bad, 1);
-}
-void launch_canon_check(const DevTables &T, const VecSet &vs, int *bad, hipStream_t st) {
-    if (vs.count <= 0) return;
-    KL("k_canon_check", k_canon_check, ew_grid(T, vs.count), dim3(256), 0, st, vs, T, bad);
-}
-
 }  // namespace he

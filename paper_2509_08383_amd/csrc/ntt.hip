@@ -267,7 +267,6 @@ static int bucket_of(int count) {
 void set_ntt_tuning(int logN, int bucket, int variant) {
     if (bucket >= 0 && bucket < 8) g_ntt_tune[logN == 16 ? 1 : 0][bucket] = variant;
 }
-int ntt_bucket(int count) { return bucket_of(count); }
 
 template <int H, int COLS, int PRO, int EPI>
 static void ntt_run(const DevTables &T, const VecSet &vs, const VecSet *src, bool inverse, const double *oscale,
