@@ -83,3 +83,27 @@ def test_encrypted_violation_counts():
     vb = [violation_rate(xs[s], picks["beta"][s], P) for s in range(S)]
     say(f"  Gumbel-max violation rate {np.mean(vg):.3f}, Beta-cut {np.mean(vb):.3f}")
     assert max(vb) == 0.0
+
+
+def test_gumbel_sample_with_masked_padding():
+    """Gumbel-max sampling with HE_MASK_PAD: logits padded with their mean, noise with 0, so
+    the pad slots of X + tau G hold the logits' pad value the tracker starts from; the
+    decrypted outputs on the 32000 real slots match the FP64 mirror of x + tau g alone and
+    pick argmax(x/tau + G)"""
+    from paper_2509_08383_amd import he
+    say("[gpu] Gumbel-max sampling with masked padding")
+    G = he.Context(he.SECURE)
+    xs = [llm_logits(710 + r) for r in range(4)]
+    gs = [he.gumbel_noise(uniform_noise(1910 + r, xs[r].size)) for r in range(4)]
+    cts = [G.encrypt(x, pad=float("nan")) for x in xs]
+    nz = [G.encrypt(g) for g in gs]
+    cfg, coef, gold = _cfg(he, False)
+    cfg.flags = he.HE_MASK_PAD
+    Z = G.gumbel_sample(cts, nz, TAU, cfg)
+    for r in range(4):
+        z = G.decrypt(Z[r], xs[r].size)
+        assert int(np.argmax(z)) == nucleus_argmax(xs[r], gs[r], TAU), r
+        w = xs[r] + TAU * gs[r]
+        mc = MirrorCfg(T=3, p=[3] * 3, c=[5.0] * 3, v_hi=VHI, v_lo=VLO, coef=coef, B=3.0 * w.size, gold_d=gold,
+                       sum_lo=1.0 * w.size)
+        assert np.abs(z - cutmax_mirror(w, mc)).max() < 1e-3, r
