@@ -346,3 +346,18 @@ def test_table2_hyperparameters_recover_every_argmax():
             assert int(np.argmax(Z)) == int(np.argmax(x)), (V, s)
             mx.append(Z.max())
         assert abs(np.mean(mx) - e) < 0.03, (V, np.mean(mx))
+
+
+def test_fraction_below_the_mean_grows_fig3_analogue():
+    """Fig. 3 analogue (Sec. 3.1, pruning): with (p, c) = (19, 27) and T = 3 on 50257-entry
+    synthetic logits, the fraction of iterates below their mean exceeds one half after the
+    first iteration and grows each iteration (the paper shows this on GPT-2 logits)"""
+    fr = []
+    for s in range(10):
+        x = llm_logits(s, 50257)
+        tr = Trace()
+        cutmax_exact(x, 19, 27.0, 3, tr)
+        fr.append([float((y < y.mean()).mean()) for y in tr.ys])
+    fr = np.mean(fr, axis=0)
+    assert fr[0] > 0.5
+    assert fr[0] < fr[1] < fr[2]
