@@ -151,7 +151,8 @@ int he_encrypt_coeffs(he_ctx *ctx, const int64_t *m, uint32_t a, double scale, s
  * its pad tracker from it.  EINVAL for a non-finite value. */
 int he_ct_set_pad(he_ct *ct, double pad);
 
-/* Client: decrypt and decode the first n logical values (Sec. 2.1). */
+/* Client: decrypt and decode the first n logical values (Sec. 2.1); n at most
+ * a * slots (EINVAL otherwise). */
 int he_decrypt(he_ctx *ctx, const he_ct *ct, double *out, size_t n);
 
 /* Server: CutMax over `batch` requests (Alg. 2).  in[r] may hold 1 or more

@@ -1653,6 +1653,7 @@ int he_ct_set_pad(he_ct *ct, double pad) {
 int he_decrypt(he_ctx *C, const he_ct *ct, double *out, size_t n) {
     return guarded([&]() {
         REQUIRE(C && ct && out && ct->ctx == C, HE_EINVAL, "bad argument");
+        REQUIRE(n <= (size_t)ct->a * (size_t)C->slots, HE_EINVAL, "more values than the handle's slots");
         HIPCHK(hipSetDevice(C->device));
         const int N = C->N, nl = ct->level >= 1 ? 2 : 1;
         const size_t s = (size_t)C->slots;

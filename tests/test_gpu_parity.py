@@ -358,6 +358,12 @@ def test_edge_inputs_are_rejected_or_handled(toy):
     with pytest.raises(he.HeError) as e:
         toy.G.add(a, toy.G.drop(a, 3))
     assert e.value.code in (he.HE_ESTATE, he.HE_EINVAL)
+    with pytest.raises(he.HeError) as e:
+        toy.G.decrypt(a, toy.G.slots + 1)
+    assert e.value.code == he.HE_EINVAL
+    with pytest.raises(he.HeError) as e:
+        a.set_pad(float("inf"))
+    assert e.value.code == he.HE_EINVAL
     # tie: the two largest logits made equal
     i, j = int(np.argmax(x)), int(np.argsort(x)[-2])
     x[j] = x[i]
