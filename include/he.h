@@ -2,9 +2,9 @@
  * he.h -- C ABI of the MI355X encrypted-CutMax library (libcutmax_he.so).
  *
  * The operation is CutMax, the HE-friendly argmax of arXiv 2509.08383
- * (Sec. 3.1, Alg. 1; encrypted form Sec. 3.2, Alg. 2), and the one-shot
- * nucleus sampler built on it (Sec. 3.3, Alg. 3), evaluated over RNS-CKKS
- * ciphertexts.  The client encrypts its logit vector X, the server returns
+ * (Sec. 3.1, Alg. 1; encrypted form Sec. 3.2, Alg. 2), and the samplers built
+ * on it (Sec. 3.3: Gumbel-max and the one-shot nucleus sampler, Alg. 3),
+ * evaluated over RNS-CKKS ciphertexts.  The client encrypts its logit vector X, the server returns
  * an encrypted one-hot approximation Z of argmax(X), and only the client
  * decrypts (Sec. 1 and App. A threat model).
  *
