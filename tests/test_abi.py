@@ -72,3 +72,18 @@ def test_errors_without_gpu_are_loud():
     from paper_2509_08383_amd import he
     with pytest.raises(he.HeError):
         he.Context(he.TOY)
+
+
+@pytest.mark.gpu
+def test_plain_c_client_recovers_the_argmax():
+    """a C program that sees only include/he.h (host pointers in, host pointers out) runs
+    encrypt, CutMax and decrypt on the GPU and recovers the plaintext arg-max"""
+    import subprocess
+    exe = os.path.join(ROOT, "tests", "c_client", "cutmax_client")
+    if not os.path.exists(exe):
+        pytest.skip("the C client is built by __graft_entry__.build()")
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    print(r.stdout, r.stderr)
+    assert r.returncode == 0, (r.returncode, r.stdout, r.stderr)
+    got, want = r.stdout.split()[1:3]
+    assert got == want
