@@ -876,7 +876,15 @@ int guarded(F &&f) {
     }
 }
 
+// captured graphs hold workspace and pool addresses: drop them when either moves
+static void drop_graphs(he_ctx *C) {
+    for (auto &g : C->graphs) hipGraphExecDestroy(g.second);
+    C->graphs.clear();
+}
+
 void ensure_workspace(he_ctx *C) {
+    if (C->arena.peak > C->arena.cap || C->pool.dv.size() > C->pool.dcap || C->pool.iv.size() > C->pool.icap)
+        drop_graphs(C);
     if (C->arena.peak > C->arena.cap) {
         if (C->arena.base) HIPCHK(hipFree(C->arena.base));
         C->arena.base = nullptr;

@@ -330,6 +330,32 @@ def test_cutmax_graph_replays_match_eager(toy):
         toy.G.set_option(he.HE_OPT_GRAPH, 0)
 
 
+def test_graphs_recaptured_after_the_workspace_grows():
+    """a captured graph holds workspace addresses: a larger call that grows the workspace
+    drops the cached graphs, and the next call of the first shape captures again and still
+    equals the eager result bit for bit"""
+    from paper_2509_08383_amd import he
+    say("[gpu] graph cache across workspace growth")
+    G = he.Context(he.TOY)
+    p, c, vlo, vhi, coef = toy_cfg(2048)
+    vlo2, vhi2 = [0.5, 0.2, 0.3, 0.6], [32.0, 0.9, 16.0, 512.0]
+    coef2 = [list(chebyshev_invsqrt(vlo2[t] / vhi2[t], 3)) for t in range(4)]
+    cfg = he.CutmaxCfg(T=4, p=p, c=c, var_lo=vlo2, var_hi=vhi2, init_coef=coef2, sum_lo=1.0, sum_hi=3.0)
+    small = G.encrypt(toy_logits(71))
+    big = [G.encrypt(toy_logits(72 + r, 3000)) for r in range(6)]
+    ref = G.export(G.cutmax([small], cfg)[0])
+    G.set_option(he.HE_OPT_GRAPH, 1)
+    for k in range(2):
+        assert np.array_equal(G.export(G.cutmax([small], cfg)[0]), ref), k
+    Zb = G.cutmax(big, cfg)                             # grows the workspace
+    for k in range(2):
+        assert np.array_equal(G.export(G.cutmax([small], cfg)[0]), ref), k
+    G.set_option(he.HE_OPT_GRAPH, 0)
+    Ze = G.cutmax(big, cfg)
+    for r in range(6):
+        assert np.array_equal(G.export(Zb[r]), G.export(Ze[r])), r
+
+
 def test_cutmax_errors_are_reported(toy):
     from paper_2509_08383_amd import he
     x = toy_logits(41)
