@@ -429,8 +429,9 @@ void launch_inner_product(const DevTables &T, const double *ext, long long estri
 // Inner product of a hoisted rotate-and-sum step: for rotation r with Galois
 // element g_r and key K_r, acc_c[ct][t][x] = sum_r sum_j ext[ct][j][t][src_r(x)]
 // K_r[j][c][prime(t)][x], the automorphism of the NTT-domain extended digits being
-// a gather (src_r = aut_src).  The partial sums are reduced after every rotation,
-// so |sum| <= p/2 + beta (p/2 + 2^44) < 2^52 for beta <= 8.
+// a gather (src_r = aut_src).  A modular product is below p/2 + 2^43 < 2^47.1 in
+// magnitude (p < 2^48), so a partial sum of at most 21 products stays below 2^51.6:
+// the sums are reduced once per floor(21 / beta) rotations (beta <= 8).
 //
 // An automorphism maps every aligned block of 256 NTT positions onto one aligned
 // block, and the rotations of a step are powers pi^r of its smallest rotation pi, so
@@ -451,6 +452,7 @@ __global__ __launch_bounds__(256) void k_inner_product_rot(DevTables T, const do
                                                            int xblocks) {
     const int beta = BETA > 0 ? BETA : beta_rt;
     constexpr int JM = BETA > 0 ? BETA : 8;
+    const int rk = 21 / beta > 0 ? 21 / beta : 1;  // rotations between reductions
     const int b = blockIdx.x, slot = b >> 3;
     const int t = (b & 7) + 8 * (slot / xblocks);
     if (t >= next) return;
@@ -491,8 +493,10 @@ __global__ __launch_bounds__(256) void k_inner_product_rot(DevTables T, const do
                     }
                 }
             }
-            s0 = red(s0, p, pinv);
-            s1 = red(s1, p, pinv);
+            if ((r + 1) % rk == 0) {
+                s0 = red(s0, p, pinv);
+                s1 = red(s1, p, pinv);
+            }
         }
         acc0[ct * astride + (long long)t * T.N + x] = canon(s0, p, pinv);
         acc1[ct * astride + (long long)t * T.N + x] = canon(s1, p, pinv);
@@ -516,6 +520,7 @@ __global__ __launch_bounds__(256) void k_inner_product_rot_reg(DevTables T, cons
     if (x >= T.N) return;
     const int pt = ext_prime[t];
     const double p = T.p[pt], pinv = T.pinv[pt];
+    const int rk = 21 / (beta > 0 ? beta : 1);  // rotations between reductions (beta <= 3)
     double k0[NR][3], k1[NR][3];
     unsigned src[NR];
 #pragma unroll
@@ -550,8 +555,10 @@ __global__ __launch_bounds__(256) void k_inner_product_rot_reg(DevTables T, cons
                     s1 += mm(e, k1[r][j], p, pinv);
                 }
             }
-            s0 = red(s0, p, pinv);
-            s1 = red(s1, p, pinv);
+            if ((r + 1) % rk == 0) {
+                s0 = red(s0, p, pinv);
+                s1 = red(s1, p, pinv);
+            }
         }
         acc0[ct * astride + (long long)t * T.N + x] = canon(s0, p, pinv);
         acc1[ct * astride + (long long)t * T.N + x] = canon(s1, p, pinv);
