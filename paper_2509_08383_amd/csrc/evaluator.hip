@@ -1803,6 +1803,7 @@ int he_ct_import(he_ctx *C, const uint64_t *limbs, uint32_t a, uint32_t level, d
                  he_ct **out) {
     return guarded([&]() {
         REQUIRE(C && limbs && out && a >= 1 && (int)level <= C->L, HE_EINVAL, "bad argument");
+        REQUIRE(std::isfinite(scale) && scale > 0, HE_EINVAL, "scale must be positive and finite");
         HIPCHK(hipSetDevice(C->device));
         const int N = C->N, l = (int)level;
         const size_t words = (size_t)a * 2 * (l + 1) * N;
