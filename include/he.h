@@ -137,7 +137,8 @@ int he_ctx_info(const he_ctx *ctx, uint32_t *N, uint32_t *slots, uint32_t *L, ui
  * replicated; otherwise padded with `pad` to a = ceil(n/slots) ciphertexts
  * (pad = NaN: the mean of x, which keeps masked CutMax accurate, see
  * HE_MASK_PAD).  The handle is at the top level with scale Delta and records n
- * and the pad value. */
+ * and the pad value.  EINVAL for non-finite values or |x| >= 2^61 / Delta (the
+ * encoded coefficients would not fit 64 bits). */
 int he_encrypt(he_ctx *ctx, const double *x, size_t n, double pad, he_ct **out);
 
 /* Client: encrypt already-encoded integer plaintexts m[a][N] at `scale`

@@ -1627,6 +1627,10 @@ int he_encrypt_coeffs(he_ctx *C, const int64_t *m, uint32_t a, double scale, siz
 int he_encrypt(he_ctx *C, const double *x, size_t n, double pad, he_ct **out) {
     return guarded([&]() {
         REQUIRE(C && x && out && n >= 1, HE_EINVAL, "bad argument");
+        // every encoded coefficient stays below 2^62 when |x| * Delta < 2^61
+        const double xmax = std::ldexp(1.0, 61) / C->Delta;
+        for (size_t i = 0; i < n; ++i)
+            REQUIRE(std::isfinite(x[i]) && std::fabs(x[i]) < xmax, HE_EINVAL, "values must be finite and below 2^61 / Delta");
         const size_t s = (size_t)C->slots;
         std::vector<double> packed;
         uint32_t a;
@@ -1635,6 +1639,7 @@ int he_encrypt(he_ctx *C, const double *x, size_t n, double pad, he_ct **out) {
             for (size_t i = 0; i < n; ++i) sum += x[i];
             pad = sum / (double)n;
         }
+        REQUIRE(std::isfinite(pad) && std::fabs(pad) < xmax, HE_EINVAL, "pad must be finite and below 2^61 / Delta");
         if (n <= s && s % n == 0) {
             a = 1;
             packed.resize(s);

@@ -387,6 +387,10 @@ def test_edge_inputs_are_rejected_or_handled(toy):
     with pytest.raises(he.HeError) as e:
         toy.G.decrypt(a, toy.G.slots + 1)
     assert e.value.code == he.HE_EINVAL
+    for bad in (np.nan, np.inf, 2.0 ** 40):
+        with pytest.raises(he.HeError) as e:
+            toy.G.encrypt(np.array([1.0, bad, 0.5]))
+        assert e.value.code == he.HE_EINVAL
     with pytest.raises(he.HeError) as e:
         a.set_pad(float("inf"))
     assert e.value.code == he.HE_EINVAL
