@@ -1288,16 +1288,20 @@ void autotune_ntt(he_ctx *C) {
             for (int v = 1; v <= 3; ++v) {
                 launch_ntt(C->T, vs, false, v, C->stream);
                 launch_ntt(C->T, vs, true, v, C->stream);
-                HIPCHK(hipEventRecord(a, C->stream));
-                for (int rep = 0; rep < 3; ++rep) {
-                    launch_ntt(C->T, vs, false, v, C->stream);
-                    launch_ntt(C->T, vs, true, v, C->stream);
+                // the best of 3 trials of 4 transform pairs each (small batches vary from
+                // run to run by a few microseconds)
+                for (int trial = 0; trial < 3; ++trial) {
+                    HIPCHK(hipEventRecord(a, C->stream));
+                    for (int rep = 0; rep < 4; ++rep) {
+                        launch_ntt(C->T, vs, false, v, C->stream);
+                        launch_ntt(C->T, vs, true, v, C->stream);
+                    }
+                    HIPCHK(hipEventRecord(b, C->stream));
+                    HIPCHK(hipEventSynchronize(b));
+                    float ms = 0;
+                    HIPCHK(hipEventElapsedTime(&ms, a, b));
+                    if (ms < best) { best = ms; bestv = v; }
                 }
-                HIPCHK(hipEventRecord(b, C->stream));
-                HIPCHK(hipEventSynchronize(b));
-                float ms = 0;
-                HIPCHK(hipEventElapsedTime(&ms, a, b));
-                if (ms < best) { best = ms; bestv = v; }
             }
             g_tuned_choice[li][ci] = bestv;
         }
