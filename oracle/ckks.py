@@ -53,6 +53,8 @@ def lib():
         V = ctypes.c_void_p
         L.oc_ctx_create.restype = V
         L.oc_ctx_create.argtypes = [ctypes.c_int] * 6 + [ctypes.c_uint64]
+        L.oc_ctx_create_ex.restype = V
+        L.oc_ctx_create_ex.argtypes = [ctypes.c_int] * 6 + [ctypes.c_uint64] + [ctypes.c_int] * 3
         L.oc_ctx_free.argtypes = [V]
         L.oc_ctx_info.argtypes = [V] + [ctypes.POINTER(ctypes.c_int)] * 4
         L.oc_ctx_primes.argtypes = [V, u64p]
@@ -86,6 +88,12 @@ def lib():
         L.oc_rotate.argtypes = [V, V, ctypes.c_int]
         L.oc_automorph.restype = V
         L.oc_automorph.argtypes = [V, V, ctypes.c_uint64]
+        L.oc_rotate_gal.restype = V
+        L.oc_rotate_gal.argtypes = [V, V, ctypes.c_int, ctypes.c_uint64]
+        L.oc_mul_plain.restype = V
+        L.oc_mul_plain.argtypes = [V, V, i64p]
+        L.oc_modraise.restype = V
+        L.oc_modraise.argtypes = [V, V, ctypes.c_int]
         L.oc_keyswitch.argtypes = [V, u64p, ctypes.c_int, ctypes.c_int, u64p, u64p]
         L.oc_schoolbook.argtypes = [u64p, u64p, u64p, ctypes.c_int, ctypes.c_uint64]
         L.oc_ring_mul.argtypes = [V, ctypes.c_int, u64p, u64p, u64p]
@@ -130,6 +138,9 @@ class Params:
     log2_scale: float
     seed: int = 1
     hoist: int = 0    # rotate-and-sum: 0 one rotation at a time, h >= 1 hoisted radix-2^h steps
+    n_hi: int = 0     # the top n_hi Q primes have hi_bits bits (levels a bootstrap uses first)
+    hi_bits: int = 0
+    secret_hw: int = 0  # 0: dense ternary secret; h > 0: sparse ternary with h nonzeros
 
     @property
     def N(self):
@@ -264,8 +275,9 @@ class Oracle:
 
     def __init__(self, prm: Params):
         self.prm = prm
-        self.h = lib().oc_ctx_create(prm.log_n, prm.n_q, prm.q0_bits, prm.q_bits, prm.p_bits,
-                                     prm.dnum, ctypes.c_uint64(prm.seed))
+        self.h = lib().oc_ctx_create_ex(prm.log_n, prm.n_q, prm.q0_bits, prm.q_bits, prm.p_bits,
+                                        prm.dnum, ctypes.c_uint64(prm.seed), prm.n_hi, prm.hi_bits,
+                                        prm.secret_hw)
         if not self.h:
             raise ValueError("bad parameters")
         N, L, A, npr = (ctypes.c_int() for _ in range(4))
@@ -390,6 +402,30 @@ class Oracle:
 
     def rotate(self, a: Ct, r: int) -> Ct:
         return Ct(self, lib().oc_rotate(self.h, a.h, int(r)), a.scale)
+
+    def keygen_galois(self, kidx: int, galois: int):
+        if lib().oc_keygen_galois(self.h, int(kidx), ctypes.c_uint64(int(galois))) != 0:
+            raise SchedError("bad key index")
+
+    def rotate_gal(self, a: Ct, kidx: int, galois: int) -> Ct:
+        """automorphism X -> X^galois with key kidx (5^r: rotation by r; 2N-1: conjugation)"""
+        h = lib().oc_rotate_gal(self.h, a.h, int(kidx), ctypes.c_uint64(int(galois)))
+        if not h:
+            raise SchedError("missing Galois key")
+        return Ct(self, h, a.scale)
+
+    def mul_plain(self, a: Ct, m: np.ndarray, pscale: float) -> Ct:
+        """product with the integer plaintext m encoded at pscale (no rescale)"""
+        m = np.ascontiguousarray(m, dtype=np.int64)
+        assert m.size == self.N
+        return Ct(self, lib().oc_mul_plain(self.h, a.h, _p(m, i64p)), a.scale * pscale)
+
+    def modraise(self, a: Ct, level: int, scale: float) -> Ct:
+        """level-0 ciphertext lifted to `level`, declared at `scale`"""
+        h = lib().oc_modraise(self.h, a.h, int(level))
+        if not h:
+            raise SchedError("modraise needs a level-0 ciphertext")
+        return Ct(self, h, scale)
 
     # composite steps of Alg. 2 -------------------------------------------
     def rotsum(self, x: Ct) -> Ct:

@@ -50,6 +50,10 @@ static inline uint64_t red_i64(int64_t v, uint64_t q) {
     int64_t r = v % (int64_t)q; if (r < 0) r += (int64_t)q; return (uint64_t)r;
 }
 
+/* the centred representative of v in [0, q) (in (-q/2, q/2]) reduced modulo p */
+static inline uint64_t centred_mod(uint64_t v, uint64_t q, uint64_t p) {
+    return v > (q - 1) / 2 ? subm(0, (q - v) % p, p) : v % p;
+}
 /* deterministic Miller-Rabin for 64-bit n */
 static int is_prime(uint64_t n) {
     static const uint64_t bases[12] = {2,3,5,7,11,13,17,19,23,29,31,37};
@@ -114,6 +118,7 @@ static int draw_cbd21(uint64_t seed, uint32_t i, uint32_t obj) {
 }
 
 #define OBJ_SK      0x00000001u
+#define OBJ_SKH     0x00000002u
 #define OBJ_KEY_A   0x01000000u
 #define OBJ_KEY_E   0x02000000u
 #define OBJ_ENC_A   0x03000000u
@@ -190,8 +195,17 @@ static uint64_t next_prime(int bits, int N, const uint64_t *used, int cnt) {
     }
 }
 
-oc_ctx *oc_ctx_create(int log_n, int n_q, int q0_bits, int q_bits, int p_bits, int dnum, uint64_t seed) {
+/* Prime chain: q_0 (q0_bits), then q_1 .. q_{n_q-1-n_hi} (q_bits), then the top n_hi
+ * primes (hi_bits; the levels a bootstrap consumes first), then alpha P primes (p_bits).
+ * Secret: dense ternary (secret_hw = 0) or sparse ternary with exactly secret_hw
+ * nonzero coefficients, placed one at a time: for the i-th, draw(seed, i, 0, OBJ_SKH,
+ * attempt) for attempt = 0, 1, .. until the position (word 0 mod N) is free; its sign
+ * is - for an odd word 1. */
+oc_ctx *oc_ctx_create_ex(int log_n, int n_q, int q0_bits, int q_bits, int p_bits, int dnum, uint64_t seed,
+                         int n_hi, int hi_bits, int secret_hw) {
     if (log_n < 3 || log_n > 17 || n_q < 1 || dnum < 1) return NULL;
+    if (n_hi < 0 || n_hi > n_q - 1 || (n_hi > 0 && (hi_bits < 20 || hi_bits > 48))) return NULL;
+    if (secret_hw < 0 || secret_hw > (1 << log_n)) return NULL;
     oc_ctx *C = (oc_ctx *)calloc(1, sizeof(oc_ctx));
     C->log_n = log_n; C->N = 1 << log_n; C->L = n_q - 1; C->dnum = dnum;
     C->alpha = (n_q + dnum - 1) / dnum;
@@ -200,7 +214,9 @@ oc_ctx *oc_ctx_create(int log_n, int n_q, int q0_bits, int q_bits, int p_bits, i
     C->q = (uint64_t *)calloc(C->np, sizeof(uint64_t));
     int cnt = 0;
     C->q[cnt] = next_prime(q0_bits, N, C->q, cnt); cnt++;
-    for (int i = 1; i < n_q; i++) { C->q[cnt] = next_prime(q_bits, N, C->q, cnt); cnt++; }
+    for (int i = 1; i < n_q; i++) {
+        C->q[cnt] = next_prime(i >= n_q - n_hi ? hi_bits : q_bits, N, C->q, cnt); cnt++;
+    }
     for (int i = 0; i < C->alpha; i++) { C->q[cnt] = next_prime(p_bits, N, C->q, cnt); cnt++; }
     C->rev = (int *)malloc(sizeof(int) * N);
     for (int i = 0; i < N; i++) { int r = 0; for (int b = 0; b < log_n; b++) if (i >> b & 1) r |= 1 << (log_n - 1 - b); C->rev[i] = r; }
@@ -221,9 +237,21 @@ oc_ctx *oc_ctx_create(int log_n, int n_q, int q0_bits, int q_bits, int p_bits, i
         x = 1; y = 1;
         for (int i = 0; i < N / 2; i++) { C->wtab[p][i] = x; C->iwtab[p][i] = y; x = mulm(x, om, q); y = mulm(y, iom, q); }
     }
-    /* secret key: ternary, one draw per coefficient */
+    /* secret key: ternary, one draw per coefficient, or sparse ternary */
     C->sk = (int8_t *)malloc(N);
-    for (int i = 0; i < N; i++) C->sk[i] = (int8_t)draw_ternary(seed, (uint32_t)i, OBJ_SK);
+    if (secret_hw == 0) {
+        for (int i = 0; i < N; i++) C->sk[i] = (int8_t)draw_ternary(seed, (uint32_t)i, OBJ_SK);
+    } else {
+        memset(C->sk, 0, N);
+        for (int i = 0; i < secret_hw; i++)
+            for (uint32_t att = 0;; att++) {
+                uint32_t r[4]; draw(seed, (uint32_t)i, 0, OBJ_SKH, att, r);
+                int pos = (int)(r[0] & (uint32_t)(N - 1));
+                if (C->sk[pos]) continue;
+                C->sk[pos] = (int8_t)((r[1] & 1u) ? -1 : 1);
+                break;
+            }
+    }
     C->sk_ntt = (uint64_t **)malloc(sizeof(void *) * C->np);
     for (int p = 0; p < C->np; p++) {
         C->sk_ntt[p] = (uint64_t *)malloc(8 * N);
@@ -233,6 +261,10 @@ oc_ctx *oc_ctx_create(int log_n, int n_q, int q0_bits, int q_bits, int p_bits, i
     C->nkeys = 256;
     C->keys = (uint64_t **)calloc(C->nkeys, sizeof(void *));
     return C;
+}
+
+oc_ctx *oc_ctx_create(int log_n, int n_q, int q0_bits, int q_bits, int p_bits, int dnum, uint64_t seed) {
+    return oc_ctx_create_ex(log_n, n_q, q0_bits, q_bits, p_bits, dnum, seed, 0, 0, 0);
 }
 
 void oc_ctx_free(oc_ctx *C) {
@@ -588,7 +620,12 @@ static void moddown(const oc_ctx *C, int l, uint64_t *acc0, uint64_t *acc1, cons
     free(phinv);
 }
 
-/* key products of a key switch of d (level l, coefficient domain) with key kidx:
+/* key products of a key switch of d (level l, coefficient domain) with key kidx.
+ * ModUp of digit j (primes D_j): the fast conversion sum_i [d_i Qhat_i^-1]_{q_i} Qhat_i
+ * with every [.]_{q_i} taken as its centred representative, so the extension
+ * d + u D_j has u of mean zero and the key noise it multiplies adds no bias
+ * (a non-centred u has mean dl/2 and leaves a constant offset on every
+ * coefficient, which the slot decoding concentrates near slot 0).
  * acc0/acc1 [l+1+alpha][N] (zeroed by the caller) receive sum_j ModUp_j(d) key_j in the
  * NTT domain; gidx[l+1+alpha] gets the global prime index of each extended limb */
 static int ks_products(const oc_ctx *C, const uint64_t *d, int l, int kidx, uint64_t *acc0, uint64_t *acc1,
@@ -627,7 +664,8 @@ static int ks_products(const oc_ctx *C, const uint64_t *d, int l, int kidx, uint
                 }
                 for (int i = 0; i < N; i++) {
                     uint64_t s = 0;
-                    for (int a = 0; a < dl; a++) s = addm(s, mulm(vv[(size_t)a * N + i] % pk, qh[a], pk), pk);
+                    for (int a = 0; a < dl; a++)
+                        s = addm(s, mulm(centred_mod(vv[(size_t)a * N + i], C->q[lo + a], pk), qh[a], pk), pk);
                     e[i] = s;
                 }
                 free(qh);
@@ -822,6 +860,58 @@ oc_ct *oc_rotate(const oc_ctx *C, const oc_ct *a, int r) {
     return o;
 }
 
+/* any Galois automorphism with the key kidx generated for it (oc_keygen_galois):
+ * g = 5^a is a rotation by a slots, g = 2N - 1 the complex conjugation of every slot */
+oc_ct *oc_rotate_gal(const oc_ctx *C, const oc_ct *a, int kidx, uint64_t g) {
+    if (kidx < 1 || kidx >= C->nkeys || !C->keys[kidx]) return NULL;
+    int l = a->level, N = C->N;
+    size_t n = (size_t)(l + 1) * N;
+    uint64_t *s0 = (uint64_t *)malloc(8 * n), *s1 = (uint64_t *)malloc(8 * n);
+    automorph(C, a->c[0], s0, l, g);
+    automorph(C, a->c[1], s1, l, g);
+    oc_ct *o = ct_new(C, l);
+    keyswitch(C, s1, l, kidx, o->c[0], o->c[1]);
+    for (int p = 0; p <= l; p++)
+        for (int i = 0; i < N; i++) { size_t x = (size_t)p * N + i; o->c[0][x] = addm(o->c[0][x], s0[x], C->q[p]); }
+    free(s0); free(s1);
+    return o;
+}
+
+/* both polynomials times the integer plaintext polynomial m (no rescale): the slots
+ * multiply by those m encodes */
+oc_ct *oc_mul_plain(const oc_ctx *C, const oc_ct *a, const int64_t *m) {
+    int l = a->level, N = C->N;
+    oc_ct *o = ct_new(C, l);
+    #pragma omp parallel for schedule(dynamic)
+    for (int p = 0; p <= l; p++) {
+        uint64_t q = C->q[p];
+        size_t x = (size_t)p * N;
+        uint64_t *mp = (uint64_t *)malloc(8 * N);
+        for (int i = 0; i < N; i++) mp[i] = red_i64(m[i], q);
+        ring_mul(C, p, a->c[0] + x, mp, o->c[0] + x);
+        ring_mul(C, p, a->c[1] + x, mp, o->c[1] + x);
+        free(mp);
+    }
+    return o;
+}
+
+/* ModRaise: a level-0 ciphertext's residues mod q_0, lifted to (-q_0/2, q_0/2] and
+ * reduced modulo q_0 .. q_level.  The result decrypts to m + q_0 I for a small
+ * integer polynomial I (the first step of a bootstrap). */
+oc_ct *oc_modraise(const oc_ctx *C, const oc_ct *a, int level) {
+    if (a->level != 0 || level < 0 || level > C->L) return NULL;
+    int N = C->N;
+    uint64_t q0 = C->q[0];
+    oc_ct *o = ct_new(C, level);
+    for (int c = 0; c < 2; c++)
+        for (int i = 0; i < N; i++) {
+            uint64_t v = a->c[c][i];
+            int64_t cen = v > (q0 - 1) / 2 ? -(int64_t)(q0 - v) : (int64_t)v;
+            for (int p = 0; p <= level; p++) o->c[c][(size_t)p * N + i] = red_i64(cen, C->q[p]);
+        }
+    return o;
+}
+
 /* a(X) -> a(X^g) on one limb of residues mod q (coefficient domain) */
 static void automorph_limb(const uint64_t *in, uint64_t *out, int N, uint64_t g, uint64_t q) {
     uint64_t M = 2 * (uint64_t)N;
@@ -878,7 +968,8 @@ oc_ct *oc_rotsum_step(const oc_ctx *C, const oc_ct *x, int nr, const int *kidx, 
                 }
                 for (int i = 0; i < N; i++) {
                     uint64_t sum = 0;
-                    for (int a = 0; a < dl; a++) sum = addm(sum, mulm(vv[(size_t)a * N + i] % pk, qh[a], pk), pk);
+                    for (int a = 0; a < dl; a++)
+                        sum = addm(sum, mulm(centred_mod(vv[(size_t)a * N + i], C->q[lo + a], pk), qh[a], pk), pk);
                     e[i] = sum;
                 }
                 free(qh);

@@ -236,7 +236,8 @@ void launch_automorph(const DevTables &T, const VecSet &out, const VecSet &in, u
 // ModUp of every digit j ([lo_j, lo_j+dl_j) of the primes present at the level):
 // v holds v_a = [d_{lo+a} * Qhat_a^-1]_{q_{lo+a}} in the coefficient domain (the
 // inverse NTT applied that scaling); for every extended slot t outside the digit
-// ext_j,t = sum_a v_a [Qhat_a]_{prime(t)}; digit slots copy the NTT-domain input.
+// ext_j,t = sum_a v~_a [Qhat_a]_{prime(t)} with v~_a the centred representative of v_a
+// (|v~_a| <= q/2); digit slots copy the NTT-domain input.
 // Grid: x = blocks of TB target slots (fastest, so the v words of one coefficient
 // block stay in L2 across target blocks), y = coefficient blocks, z = (ciphertext,
 // digit).  The block's [Qhat_a]_{prime(t)} table and moduli are staged in LDS (every
@@ -293,10 +294,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         const int t = t0 + tt;
         need |= t < next && !(t >= lo && t < lo + dl);
     }
+    // the digit words as centred representatives of [d_i Qhat_i^-1]_{q_i}: the
+    // extension d + u D then has u of mean zero, so the key noise it multiplies adds
+    // no constant offset to the key-switch output
     double va[DL];
     const double *vp = v + ct * vstride + (long long)lo * T.N + x;
 #pragma unroll
-    for (int a = 0; a < DL; ++a) va[a] = (need && a < dl) ? vp[(long long)a * T.N] : 0.0;
+    for (int a = 0; a < DL; ++a) {
+        const double w = (need && a < dl) ? vp[(long long)a * T.N] : 0.0;
+        const double qa = a < dl ? T.p[lo + a] : 1.0;
+        va[a] = w > 0.5 * (qa - 1.0) ? w - qa : w;
+    }
     double *X = ext + ct * esb + j * esj + x;
 #pragma unroll
     for (int tt = 0; tt < TB; ++tt) {
