@@ -59,7 +59,13 @@ typedef struct he_ct he_ct;
  * step extending the digits of c1 once (ModUp), applying every rotation's
  * automorphism to the extended digits, summing the key products of all its
  * rotations and running one ModDown.  h >= 2 adds rotation keys for the amounts
- * r k that are not powers of two. */
+ * r k that are not powers of two.
+ * n_hi, hi_bits: the top n_hi Q primes (q_{L-n_hi+1} .. q_L, the levels a
+ * bootstrap consumes first) have hi_bits bits instead of q_bits (n_hi = 0: one
+ * size); n_hi < n_q.  secret_hw: 0 = dense ternary secret (one uniform draw in
+ * {-1, 0, 1} per coefficient); h > 0 = sparse ternary secret with exactly h
+ * nonzero coefficients (a bootstrap's ModRaise error I is bounded by the
+ * secret's weight). */
 typedef struct {
     uint32_t log_n;
     uint32_t n_q;
@@ -72,6 +78,9 @@ typedef struct {
     int device;
     void *stream;
     uint32_t hoist;
+    uint32_t n_hi;
+    uint32_t hi_bits;
+    uint32_t secret_hw;
 } he_params;
 
 /* Hyper-parameters of one CutMax call (Alg. 1 inputs p, c, T; Sec. 4.2 uses
@@ -100,7 +109,17 @@ typedef struct {
  *     the sums subtract (pad count) x tracker, which costs no level.  The pad
  *     slots of the output hold the tracker's iterate, not zeros.  Accuracy
  *     needs pad slots that do not outgrow the logits: encrypt with the mean of
- *     x as pad (he_encrypt with pad = NaN). */
+ *     x as pad (he_encrypt with pad = NaN).
+ *     HE_BOOT: runs schedules deeper than the chain (the paper's Table 2
+ *     schedule T = 4, p = [16, 4, 4, 6], c = [5, 3, 3, 3] needs bootstrapping):
+ *     after the normalisation of an iteration, the iterate z is bootstrapped
+ *     (he_bootstrap, set up by he_boot_setup) whenever the power step and the
+ *     next iteration's moments, or the final normalisation, do not fit in its
+ *     levels; the bound passed is |z - 1| <= m sqrt(n - 1) / c (population
+ *     moments) times 1.02, m = the maximum of g(u) sqrt(u) over the declared
+ *     domain after the refinements (1 for an exact inverse square root).  On a
+ *     chain with wider top primes (n_hi > 0) every call runs on the levels
+ *     below them. */
 typedef struct {
     uint32_t T;
     const uint32_t *p;
@@ -119,6 +138,7 @@ typedef struct {
 #define HE_NOISE_PRESCALED 1u
 #define HE_REFINE_GOLDSCHMIDT 2u
 #define HE_MASK_PAD 4u
+#define HE_BOOT 8u
 
 /* Context: prime chain, twiddle and basis-conversion tables, secret key, and
  * the relinearisation and rotation keys (rotation by 2^r slots for every r <
@@ -220,6 +240,63 @@ int he_cmul(he_ctx *ctx, const he_ct *a, double kappa, double s_want, int exact,
 int he_rotate(he_ctx *ctx, const he_ct *a, uint32_t r, he_ct **out);
 int he_rotsum(he_ctx *ctx, const he_ct *a, he_ct **out);
 int he_drop(he_ctx *ctx, const he_ct *a, uint32_t level, he_ct **out);
+
+/* CKKS bootstrapping: a ciphertext whose levels are spent comes back at a high
+ * level with the same slot values (the paper runs its deeper CutMax schedules,
+ * T = 4 with p up to 16 (Sec. 4, Table 2), with bootstrapping, and App. B.1
+ * counts depth because it decides how often a bootstrap runs).  Steps:
+ *   ModRaise   level-0 residues, centred, reduced modulo the whole chain: the
+ *              plaintext becomes m + q_0 I with |I| <= K;
+ *   CoeffToSlot the inverse slot-decoding map as n_cts groups of butterfly
+ *              stages, each a baby-step giant-step sum of rotated diagonals
+ *              (one level each); one conjugation splits the complex slots into
+ *              the two real halves of the coefficient vector;
+ *   EvalMod    sin(2 pi x) / (2 pi) removes q_0 I: a degree-cheb_deg Chebyshev
+ *              interpolant of cos(2 pi (x - 1/4) / 2^r) in z = 2 y^2 - 1,
+ *              then r double-angle steps;
+ *   SlotToCoeff the decoding map as n_stc groups.
+ * Levels used above the output: n_cts + 1 + ceil(log2(cheb_deg + 1)) + 1 + r + n_stc.
+ * K = 0 takes ceil(6 sqrt(h / 12)) for a secret of weight h (the ModRaise
+ * overflow of a sparse secret stays below this bound with overwhelming
+ * probability); ratio_bits: the message enters EvalMod at q_0 2^-ratio_bits per
+ * unit of `bound`, which sets the sine's linearisation error; log2_s_eval: scale of
+ * the EvalMod ciphertexts (use the bit size of the primes it runs on). */
+typedef struct {
+    uint32_t n_cts;
+    uint32_t n_stc;
+    uint32_t K;
+    uint32_t ratio_bits;
+    uint32_t cheb_deg;
+    uint32_t r;
+    double log2_s_eval;
+} he_boot_cfg;
+
+/* Bootstrap set-up: generates the Galois keys the two linear transforms use
+ * (rotation amounts that already have a key keep it; the others take the next
+ * free key indices in ascending order of amount, then the conjugation key) and
+ * fixes the configuration.  Encoded diagonals are built on first use and kept in
+ * device memory.  EINVAL for a configuration whose levels exceed the chain. */
+int he_boot_setup(he_ctx *ctx, const he_boot_cfg *cfg);
+
+/* Bootstrap every ciphertext of `in` (level >= 1, real slot values with
+ * |v| <= bound): out receives them at level L - (levels used) with scale Delta.
+ * ESTATE without he_boot_setup. */
+int he_bootstrap(he_ctx *ctx, const he_ct *in, double bound, he_ct **out);
+
+/* Bootstrap primitives (single ciphertexts), each bit-exact against a plain
+ * implementation of its definition:
+ *   he_keygen_galois  key index kidx for the automorphism X -> X^galois (galois
+ *                     odd; 5^a mod 2N rotates by a slots, 2N - 1 conjugates);
+ *                     kidx must be the next free index or an existing
+ *                     Galois key's (replaced)
+ *   he_rotate_gal     automorphism X -> X^galois with key kidx
+ *   he_mul_plain      both polynomials times the integer plaintext m[N] (host),
+ *                     declared scale = scale * pscale (no rescale)
+ *   he_modraise       a level-0 ciphertext lifted to `level`, declared at `scale` */
+int he_keygen_galois(he_ctx *ctx, uint32_t kidx, uint64_t galois);
+int he_rotate_gal(he_ctx *ctx, const he_ct *a, uint32_t kidx, uint64_t galois, he_ct **out);
+int he_mul_plain(he_ctx *ctx, const he_ct *a, const int64_t *m, double pscale, he_ct **out);
+int he_modraise(he_ctx *ctx, const he_ct *a, uint32_t level, double scale, he_ct **out);
 
 /* Measurement hooks.
  * he_bench_ntt: `iters` forward+inverse negacyclic NTTs over `vectors`

@@ -20,7 +20,11 @@
 #include <string>
 #include <vector>
 
+#include <thread>
+#include <tuple>
+
 #include "../../include/he.h"
+#include "boot_plan.h"
 #include "he_internal.h"
 
 using namespace he;
@@ -71,6 +75,7 @@ struct HeError : std::runtime_error {
     } while (0)
 
 constexpr uint32_t OBJ_SK = 0x00000001u;
+constexpr uint32_t OBJ_SKH = 0x00000002u;  // sparse secret positions
 constexpr uint32_t OBJ_KEY_A = 0x01000000u;
 constexpr uint32_t OBJ_KEY_E = 0x02000000u;
 constexpr uint32_t OBJ_ENC_A = 0x03000000u;
@@ -165,6 +170,21 @@ struct he_ctx {
     std::vector<uint32_t> key_gal;  // key index -> Galois element (0 for relinearisation)
     // graph cache keyed by a signature of the call
     std::map<std::string, hipGraphExec_t> graphs;
+    int n_hi = 0, secret_hw = 0;
+    std::map<uint64_t, int> gal_key;  // Galois element -> key index (rotations, conjugation)
+    // bootstrapping (he_boot_setup): configuration, the butterfly groups of the two
+    // linear transforms, EvalMod's Chebyshev coefficients, and the encoded diagonals
+    // (device, NTT domain, built on first use) keyed by (transform, group, giant, term,
+    // level, plaintext scale bits, multiplier bits)
+    struct Boot {
+        bool ready = false;
+        int n_cts = 3, n_stc = 3, K = 0, ratio_bits = 12, cheb_deg = 31, r = 3;
+        double s_eval = 0;
+        std::vector<he::Diag> cts, stc;
+        std::vector<he::Bsgs> cts_plan, stc_plan;
+    } boot;
+    std::map<std::tuple<int, int, int, int, int, uint64_t, uint64_t>, double *> pt_cache;
+    double *mono_pos = nullptr, *mono_neg = nullptr;  // +X^(N/2), -X^(N/2): NTT residues [np][N]
 };
 
 struct he_ct {
@@ -498,6 +518,19 @@ struct Exec {
 
     // rotation by 2^r slots; with `into`, the result is added into that batch in place
     Bt rotate(const Bt &a, int r, Bt *into = nullptr) {
+        uint64_t g = 5;
+        for (int i = 0; i < r; ++i) g = (g * g) % (2ull * C->N);
+        return rotate_gal(a, 1 + r, g, into);
+    }
+
+    // automorphism X -> X^g on both polynomials, key switch of sigma(c1) with key
+    // kidx: (sigma(c0) + ks0, ks1) [+ into]
+    Bt rotate_gal(const Bt &a, int kidx, uint64_t g, Bt *into = nullptr) {
+        REQUIRE(kidx >= 1 && kidx < (int)C->keys.size() && C->keys[kidx].lo, HE_ESTATE, "no such Galois key");
+        REQUIRE(C->key_gal[kidx] == (uint32_t)g, HE_ESTATE, "key was generated for another Galois element");
+        if (into)
+            for (int c = 0; c < a.cnt; ++c)
+                REQUIRE(std::fabs(a.scale[c] - into->scale[c]) <= 1e-9 * a.scale[c], HE_ERANGE, "rotate: scale mismatch");
         const int l = a.level;
         const long long N = C->N;
         Bt o;
@@ -509,15 +542,51 @@ struct Exec {
         }
         const size_t m = C->arena.mark();
         double *sig = alloc_d((size_t)a.cnt * 2 * (l + 1) * N);
-        uint64_t g = 5;
-        for (int i = 0; i < r; ++i) g = (g * g) % (2ull * C->N);
         if (go())
             launch_automorph(T, VecSet{sig, a.cnt * 2 * (l + 1), l + 1, (long long)(l + 1) * N, nullptr, nullptr},
                              vs_all(a), g, s);
         Addend acc{nullptr, 0, 0, 0};
         if (into) acc = Addend{into->d, 2LL * into->cap * N, (long long)into->cap * N, 3};
-        keyswitch(sig + (l + 1) * N, 2LL * (l + 1) * N, a.cnt, l, 1 + r, o.d, (long long)o.cap * N,
+        keyswitch(sig + (l + 1) * N, 2LL * (l + 1) * N, a.cnt, l, kidx, o.d, (long long)o.cap * N,
                   Addend{sig, 2LL * (l + 1) * N, (long long)(l + 1) * N, 1}, acc);
+        C->arena.release(m);
+        return o;
+    }
+
+    // both polynomials times a plaintext (NTT-domain residues, limb i at pt + i N),
+    // declared scale times pscale, no rescale
+    Bt mul_plain(const Bt &a, const double *pt, double pscale) {
+        Bt o = new_bt(a.cnt, a.level);
+        for (int c = 0; c < a.cnt; ++c) o.scale[c] = a.scale[c] * pscale;
+        LtTerms tm{};
+        tm.n = 1;
+        tm.pt[0] = pt;
+        tm.x[0] = a.d;
+        tm.xct[0] = 2LL * a.cap * C->N;
+        tm.xpoly[0] = (long long)a.cap * C->N;
+        if (go()) launch_lt_inner(T, o.d, 2LL * o.cap * C->N, (long long)o.cap * C->N, tm, a.cnt, a.level + 1, s);
+        return o;
+    }
+
+    // ModRaise: the level-0 residues mod q_0 (coefficient domain), centred and reduced
+    // modulo q_0 .. q_level (the lift runs in the forward NTT's loads)
+    Bt modraise(const Bt &a, int level, double scale) {
+        REQUIRE(a.level == 0, HE_ESTATE, "modraise needs a level-0 ciphertext");
+        REQUIRE(level >= 0 && level <= C->L, HE_EINVAL, "modraise: bad level");
+        const long long N = C->N;
+        const int G = a.cnt * 2;
+        Bt o = new_bt(a.cnt, level);
+        o.scale.assign(a.cnt, scale);
+        const size_t m = C->arena.mark();
+        double *last = alloc_d((size_t)G * N);
+        if (go()) {
+            VecSet src{a.d, G, 1, (long long)a.cap * N, nullptr, C->ident};
+            VecSet dst{last, G, 1, N, nullptr, C->ident};
+            launch_ntt(T, dst, true, C->ntt_variant, s, &src);
+            NttPro pro{1, last, N, (double)C->q[0]};
+            launch_ntt_fused(T, VecSet{o.d, G * (level + 1), level + 1, (long long)o.cap * N, nullptr, nullptr}, pro,
+                             NttEpi{}, C->ntt_variant, s);
+        }
         C->arena.release(m);
         return o;
     }
@@ -729,7 +798,32 @@ struct CutmaxCfg {
     int newton = 0, gold_d = 3;
     bool gold_refine = false;
     double sum_lo = 1, sum_hi = 3;
+    bool boot = false;              // bootstrap the normalised iterate when the chain runs short
+    std::vector<double> guess_max;  // [T]: max of h(u) sqrt(u) / C over the declared domain
 };
+
+// max over u in [u_lo, 1] of g(u) sqrt(u) after the refinement steps (1 for an exact
+// inverse square root): the factor by which |z - 1| can exceed its exact bound
+double guess_overshoot(const std::vector<double> &g, double u_lo, int newton) {
+    double mx = 0.0;
+    for (int i = 0; i <= 4000; ++i) {
+        const double u = u_lo * std::pow(1.0 / u_lo, i / 4000.0);
+        double y = 0.0;
+        for (int k = (int)g.size() - 1; k >= 0; --k) y = y * u + g[k];
+        for (int it = 0; it < newton; ++it) y = 1.5 * y - 0.5 * u * y * y * y;
+        mx = std::max(mx, std::fabs(y) * std::sqrt(u));
+    }
+    return mx;
+}
+
+int pre_levels(const CutmaxCfg &cf, int t) {
+    return 2 + invsqr_depth((int)cf.coef[t].size() - 1, cf.newton, cf.gold_refine) + 1;
+}
+int power_levels(int p) {
+    int nb = 0;
+    while ((p >> nb) > 1) ++nb;
+    return nb + (__builtin_popcount(p) > 1 ? 1 : 0);
+}
 
 int levels_needed(const CutmaxCfg &cf) {
     int lv = 0;
@@ -740,6 +834,9 @@ int levels_needed(const CutmaxCfg &cf) {
     }
     return lv + cf.gold_d + 3;
 }
+
+Bt bootstrap(Exec &X, const Bt &ct, double bound);
+int boot_levels(const he_ctx *C);
 
 // Alg. 2 on a batch of requests; Y holds every request's ciphertexts.
 // Masked padding: the pad slots of a request all hold one value, followed by a
@@ -761,7 +858,15 @@ Bt cutmax_sched(Exec &X, Bt Y, const std::vector<Request> &reqs, const CutmaxCfg
         for (int k = 0; k < reqs[r].a; ++k) { cmap[reqs[r].first + k] = r; nct[reqs[r].first + k] = reqs[r].n; }
         if (tmap[r] >= 0) { cmap[tmap[r]] = r; nct[tmap[r]] = reqs[r].n; }
     }
-    REQUIRE(levels_needed(cf) <= Y.level, HE_EDEPTH, "schedule needs more levels than the ciphertext has");
+    // a chain with wider top primes (kept for bootstrapping) runs the schedule on the
+    // levels whose primes match the scale
+    if (C->n_hi > 0 && Y.level > C->L - C->n_hi) Y = X.drop(Y, C->L - C->n_hi);
+    if (cf.boot) {
+        REQUIRE(C->boot.ready, HE_ESTATE, "HE_BOOT needs he_boot_setup");
+        REQUIRE(pre_levels(cf, 0) + 1 <= Y.level, HE_EDEPTH, "first iteration needs more levels than the ciphertext has");
+    } else {
+        REQUIRE(levels_needed(cf) <= Y.level, HE_EDEPTH, "schedule needs more levels than the ciphertext has");
+    }
     if (ntrk) {
         // trackers start as trivial encryptions of the pad value (0 * ct + pad)
         Bt Ya = X.new_bt(total + ntrk, Y.level);
@@ -826,6 +931,18 @@ Bt cutmax_sched(Exec &X, Bt Y, const std::vector<Request> &reqs, const CutmaxCfg
         }
         Bt H = invsqr(X, U, coefC, Cc, cf.newton, cf.gold_refine, SH);
         Bt Yp = X.add_const(X.mul(X.drop(E, H.level), H, &cmap), std::vector<double>(Y.cnt, 1.0));
+        if (cf.boot) {
+            // bootstrap z when the power and the next iteration's moments (or the final
+            // normalisation) do not fit; |z - 1| <= (max h sqrt(u) / C) sqrt(n - 1) / c
+            const int need = power_levels(cf.p[t]) + (t + 1 < cf.T ? pre_levels(cf, t + 1) : cf.gold_d + 3);
+            if (Yp.level < need) {
+                REQUIRE(C->L - boot_levels(C) >= need, HE_EDEPTH, "bootstrapped chain too short for one iteration");
+                double bound = 0.0;
+                for (int r = 0; r < R; ++r)
+                    bound = std::max(bound, 1.0 + cf.guess_max[t] * std::sqrt((double)reqs[r].n - 1.0) / cf.c[t]);
+                Yp = bootstrap(X, Yp, 1.02 * bound);
+            }
+        }
         Bt Yn = X.power(Yp, cf.p[t]);
         // keep the new iterate, drop this iteration's temporaries
         C->arena.release(mark);
@@ -855,6 +972,331 @@ Bt cutmax_sched(Exec &X, Bt Y, const std::vector<Request> &reqs, const CutmaxCfg
     }
     Bt Yb = X.cmul(Y, invB, dl, true);
     return X.mul(X.drop(Yb, P.level), P, &cmap);
+}
+
+// ------------------------------------------------------------ bootstrapping
+void gen_keys(he_ctx *C, int from, int to = -1);
+static void drop_graphs(he_ctx *C);
+
+// NTT-domain residues [limbs][N] of integer polynomials m[k][N] in new device
+// allocations (synchronous: set-up, outside any captured call)
+std::vector<double *> upload_plains(he_ctx *C, const std::vector<std::vector<int64_t>> &m, int limbs) {
+    const int N = C->N;
+    std::vector<double *> out;
+    int64_t *dm = nullptr;
+    HIPCHK(hipMalloc(&dm, 8ull * N * std::max<size_t>(1, m.size())));
+    try {
+        for (size_t k = 0; k < m.size(); ++k) {
+            double *pt = nullptr;
+            HIPCHK(hipMalloc(&pt, 8ull * limbs * N));
+            out.push_back(pt);
+            HIPCHK(hipMemcpyAsync(dm + k * N, m[k].data(), 8ull * N, hipMemcpyHostToDevice, C->stream));
+            const VecSet v{pt, limbs, limbs, 0, nullptr, nullptr};
+            launch_int64_to_res(C->T, v, dm + k * N, 0, nullptr, C->stream);
+            launch_ntt(C->T, v, false, C->ntt_variant, C->stream);
+        }
+        HIPCHK(hipStreamSynchronize(C->stream));
+        HIPCHK(hipGetLastError());
+    } catch (...) {
+        hipFree(dm);
+        for (double *p : out) hipFree(p);
+        throw;
+    }
+    hipFree(dm);
+    return out;
+}
+
+int gal_key_of(const he_ctx *C, uint64_t g) {
+    auto it = C->gal_key.find(g);
+    REQUIRE(it != C->gal_key.end(), HE_ESTATE, "no Galois key for a bootstrap rotation");
+    return it->second;
+}
+
+uint64_t rot_gal(const he_ctx *C, long long a) {
+    const uint64_t M = 2ull * C->N;
+    uint64_t g = 1, b = 5;
+    for (uint64_t e = (uint64_t)(a % C->slots + C->slots) % C->slots; e; e >>= 1, b = (b * b) % M)
+        if (e & 1) g = (g * b) % M;
+    return g;
+}
+
+uint64_t dbits(double x) { uint64_t u; std::memcpy(&u, &x, 8); return u; }
+
+// sum_d D_d * rot_d(ct) by baby steps rot_{b h0}(ct) and giant steps
+// rot_{a B h0}(sum_b rot_{-a B h0}(mult D_d) * rot_{b h0}(ct)), the diagonals encoded
+// at rho q_l (l = the input level) and one rescale: output scale = scale * rho.
+// The encoded diagonals are made in the dry pass (first use) and cached.
+Bt lin_transform(Exec &X, const Bt &ct, const Diag &D, const Bsgs &P, double rho, int kind, int gi, double mult) {
+    he_ctx *C = X.C;
+    const int s = C->slots, l = ct.level, N = C->N;
+    const double pscale = rho * (double)C->q[l];
+    using Key = std::tuple<int, int, int, int, int, uint64_t, uint64_t>;
+    auto key = [&](int a, int j) { return Key{kind, gi, a, j, l, dbits(pscale), dbits(mult)}; };
+    if (X.dry) {
+        std::vector<Key> want;
+        std::vector<std::pair<int, int>> src;  // (shift, offset d)
+        for (const auto &at : P.terms)
+            for (size_t j = 0; j < at.second.size(); ++j)
+                if (!C->pt_cache.count(key(at.first, (int)j))) {
+                    want.push_back(key(at.first, (int)j));
+                    src.push_back({(int)(((long long)at.first * P.B * P.h0) % s), at.second[j].second});
+                }
+        if (!want.empty()) {
+            std::vector<std::vector<int64_t>> m(want.size(), std::vector<int64_t>(N));
+            const int nth = (int)std::max<size_t>(1, std::min<size_t>(16, std::thread::hardware_concurrency()));
+            std::vector<std::string> errs(nth);
+            std::vector<std::thread> th;
+            for (int w = 0; w < nth; ++w)
+                th.emplace_back([&, w]() {
+                    try {
+                        std::vector<cplx> z(s);
+                        for (size_t k = w; k < want.size(); k += nth) {
+                            const std::vector<cplx> &dv = D.at(src[k].second);
+                            const int sh = src[k].first;
+                            // rot_{-shift}(D)[t] = D[t - shift], times the group's multiplier
+                            for (int t = 0; t < s; ++t) z[t] = dv[((t - sh) % s + s) % s] * mult;
+                            encode_cplx(z, N, pscale, m[k].data());
+                        }
+                    } catch (const std::exception &e) {
+                        errs[w] = e.what();
+                    }
+                });
+            for (auto &t : th) t.join();
+            for (const auto &e : errs) REQUIRE(e.empty(), HE_ERANGE, "bootstrap diagonal: " + e);
+            std::vector<double *> pts = upload_plains(C, m, l + 1);
+            for (size_t k = 0; k < want.size(); ++k) C->pt_cache[want[k]] = pts[k];
+        }
+    }
+    std::map<int, Bt> baby;
+    baby[0] = ct;
+    for (int b : P.babies()) {
+        const uint64_t g = rot_gal(C, (long long)b * P.h0);
+        baby[b] = X.rotate_gal(ct, gal_key_of(C, g), g);
+    }
+    Bt acc;
+    bool have = false;
+    for (const auto &at : P.terms) {
+        const long long shift = ((long long)at.first * P.B * P.h0) % s;
+        Bt inner = X.new_bt(ct.cnt, l);
+        for (int c = 0; c < ct.cnt; ++c) inner.scale[c] = ct.scale[c] * pscale;
+        // chunks of at most kMaxLtTerms terms, summed
+        const int nt = (int)at.second.size();
+        for (int j0 = 0; j0 < nt; j0 += kMaxLtTerms) {
+            Bt part = j0 == 0 ? inner : X.new_bt(ct.cnt, l);
+            part.scale = inner.scale;
+            LtTerms tm{};
+            tm.n = std::min(kMaxLtTerms, nt - j0);
+            for (int j = 0; j < tm.n; ++j) {
+                const Bt &bx = baby.at(at.second[j0 + j].first);
+                double *pt = X.dry ? nullptr : C->pt_cache.at(key(at.first, j0 + j));
+                tm.pt[j] = pt;
+                tm.x[j] = bx.d;
+                tm.xct[j] = 2LL * bx.cap * N;
+                tm.xpoly[j] = (long long)bx.cap * N;
+            }
+            if (X.go())
+                launch_lt_inner(X.T, part.d, 2LL * part.cap * N, (long long)part.cap * N, tm, ct.cnt, l + 1, X.s);
+            if (j0) X.add_inplace(inner, part);
+        }
+        if (shift) {
+            const uint64_t g = rot_gal(C, shift);
+            if (have) X.rotate_gal(inner, gal_key_of(C, g), g, &acc);
+            else acc = X.rotate_gal(inner, gal_key_of(C, g), g);
+        } else {
+            if (have) X.add_inplace(acc, inner);
+            else acc = inner;
+        }
+        have = true;
+    }
+    return X.rescale(acc);
+}
+
+// x brought to `level`, declared at `scale`, through one constant product
+Bt boot_match(Exec &X, const Bt &x, int level, const std::vector<double> &scale) {
+    return X.drop(X.cmul(x, std::vector<double>(x.cnt, 1.0), scale, false), level);
+}
+
+// sum_k c_k T_k(z): T_2k = 2 T_k^2 - 1, T_{m+n} = 2 T_m T_n - T_{m-n} (m the largest
+// power of two below k); every kept term c_k T_k through a constant product at
+// s_out, all at the level a degree len(c) - 1 sum reaches; c_0 added last.  Terms
+// with |c_k| < 2^-40 (below the scale's noise) are left out and the basis stops at
+// the last kept one.
+Bt cheb_sum(Exec &X, const Bt &z, const std::vector<double> &c, double s_out) {
+    const int R = z.cnt;
+    int lg = 0;
+    while ((1 << lg) < (int)c.size()) ++lg;
+    const int lv = z.level - lg - 1;
+    std::vector<int> keep;
+    for (int k = 1; k < (int)c.size(); ++k)
+        if (std::fabs(c[k]) >= std::ldexp(1.0, -40)) keep.push_back(k);
+    REQUIRE(!keep.empty(), HE_EINVAL, "EvalMod polynomial is constant");
+    const int d = keep.back();
+    std::map<int, Bt> Tk;
+    Tk[1] = z;
+    const std::vector<int64_t> two(R, 2);
+    const std::vector<double> m1(R, -1.0);
+    for (int k = 2; k <= d; ++k) {
+        int m = 1;
+        while (2 * m <= k) m *= 2;
+        if (m == k) {
+            const Bt &h = Tk.at(k / 2);
+            Tk[k] = X.add_const(X.mul_int(X.mul(h, h), two), m1);
+        } else {
+            const int n = k - m;
+            const int lm = std::min(Tk.at(m).level, Tk.at(n).level);
+            Bt P = X.mul_int(X.mul(X.drop(Tk.at(m), lm), X.drop(Tk.at(n), lm)), two);
+            Tk[k] = X.add(P, boot_match(X, Tk.at(m - n), P.level, P.scale), -1);
+        }
+    }
+    Bt acc;
+    bool have = false;
+    for (int k : keep) {
+        Bt t = X.drop(X.cmul(Tk.at(k), std::vector<double>(R, c[k]), std::vector<double>(R, s_out), false), lv);
+        if (have) X.add_inplace(acc, t);
+        else { acc = t; have = true; }
+    }
+    return X.add_const(acc, std::vector<double>(R, c[0]));
+}
+
+std::vector<double> eval_mod_coeffs(const he_ctx *C, double Bk) {
+    const double a = 2.0 * M_PI * Bk / std::ldexp(1.0, C->boot.r);
+    return cheb_interp([a](double z) { return std::cos(a * std::sqrt(std::max(0.0, (1.0 + z) / 2.0))); },
+                       C->boot.cheb_deg);
+}
+
+// y = (x - 1/4) / Bk  ->  sin(2 pi x): z = 2 y^2 - 1, Chebyshev sum of
+// cos(2 pi (x - 1/4) / 2^r), r double angles
+Bt eval_mod(Exec &X, const Bt &y, double Bk) {
+    const int R = y.cnt;
+    const std::vector<int64_t> two(R, 2);
+    const std::vector<double> m1(R, -1.0);
+    Bt z = X.add_const(X.mul_int(X.mul(y, y), two), m1);
+    Bt v = cheb_sum(X, z, eval_mod_coeffs(X.C, Bk), X.C->boot.s_eval);
+    for (int i = 0; i < X.C->boot.r; ++i) v = X.add_const(X.mul_int(X.mul(v, v), two), m1);
+    return v;
+}
+
+int boot_levels(const he_ctx *C) {
+    int lg = 0;
+    while ((1 << lg) < C->boot.cheb_deg + 1) ++lg;
+    return C->boot.n_cts + 1 + lg + 1 + C->boot.r + C->boot.n_stc;
+}
+
+double boot_bk(const he_ctx *C) {
+    const int h = C->secret_hw ? C->secret_hw : C->N;
+    const int K = C->boot.K > 0 ? C->boot.K : (int)std::ceil(6.0 * std::sqrt(h / 12.0));
+    return K + 0.5;
+}
+
+// a batch at level >= 1 with real slot values |v| <= bound, back at level
+// L - boot_levels with the same values at scale Delta
+Bt bootstrap(Exec &X, const Bt &ct, double bound) {
+    he_ctx *C = X.C;
+    REQUIRE(C->boot.ready, HE_ESTATE, "bootstrap needs he_boot_setup");
+    REQUIRE(ct.level >= 1, HE_EDEPTH, "bootstrap input needs a level to spare");
+    REQUIRE(bound > 0 && std::isfinite(bound), HE_EINVAL, "bootstrap bound must be positive");
+    const int R = ct.cnt, N = C->N;
+    const double q0 = (double)C->q[0], Bk = boot_bk(C);
+    const double s_in = q0 * std::ldexp(1.0, -C->boot.ratio_bits) / bound;
+    // to level 0 at scale s_in; the raised plaintext m + q_0 I read at scale q_0 Bk
+    Bt c0 = X.cmul(X.drop(ct, 1), std::vector<double>(R, 1.0), std::vector<double>(R, s_in), false);
+    Bt U = X.modraise(c0, C->L, q0 * Bk);
+    // CoeffToSlot: the slots become (w / (q_0 Bk)) / 2 in bit-reversed order
+    const double rho_c = std::pow(C->boot.s_eval / U.scale[0], 1.0 / C->boot.n_cts);
+    for (int gi = 0; gi < C->boot.n_cts; ++gi)
+        U = lin_transform(X, U, C->boot.cts[gi], C->boot.cts_plan[gi], rho_c, 0, gi,
+                          gi == C->boot.n_cts - 1 ? 0.5 : 1.0);
+    const uint64_t conj = 2ull * N - 1;
+    Bt V = X.rotate_gal(U, gal_key_of(C, conj), conj);
+    // real and imaginary halves (times -i), stacked so EvalMod runs once for both
+    Bt re = X.add(U, V), im = X.mul_plain(X.add(U, V, -1), C->mono_neg, 1.0);
+    Bt Y2 = X.new_bt(2 * R, re.level);
+    {
+        Bt h0 = Y2, h1 = Y2;
+        h0.cnt = R;
+        h1.cnt = R;
+        h1.d = Y2.d + 2LL * R * Y2.cap * N;
+        for (int c = 0; c < R; ++c) { Y2.scale[c] = re.scale[c]; Y2.scale[R + c] = im.scale[c]; }
+        if (X.go()) {
+            launch_copy(X.T, X.vs_all(h0), X.vs_all(re), X.s);
+            launch_copy(X.T, X.vs_all(h1), X.vs_all(im), X.s);
+        }
+    }
+    Bt S = eval_mod(X, X.add_const(Y2, std::vector<double>(2 * R, -0.25 / Bk)), Bk);
+    Bt Sre = S, Sim = S;
+    Sre.cnt = R;
+    Sre.scale.resize(R);
+    Sim.cnt = R;
+    Sim.d = S.d + 2LL * R * S.cap * N;
+    Sim.scale.assign(S.scale.begin() + R, S.scale.end());
+    Bt Z = X.add(Sre, X.mul_plain(Sim, C->mono_pos, 1.0));
+    // SlotToCoeff, with kappa = q_0 / (2 pi s_in) turning sin(2 pi x) into m / s_in
+    const double kappa = q0 / (2.0 * M_PI * s_in);
+    const double rho_s = std::pow(C->Delta / Z.scale[0], 1.0 / C->boot.n_stc);
+    for (int gi = 0; gi < C->boot.n_stc; ++gi)
+        Z = lin_transform(X, Z, C->boot.stc[gi], C->boot.stc_plan[gi], rho_s, 1, gi, gi == 0 ? kappa : 1.0);
+    return Z;
+}
+
+// every rotation amount (mod slots) of the two linear transforms, ascending
+std::vector<int> boot_rotations(const he_ctx *C) {
+    std::vector<int> r;
+    for (const auto *pl : {&C->boot.cts_plan, &C->boot.stc_plan})
+        for (const Bsgs &P : *pl)
+            for (int a : P.rotations(C->slots))
+                if (a) r.push_back(a);
+    std::sort(r.begin(), r.end());
+    r.erase(std::unique(r.begin(), r.end()), r.end());
+    return r;
+}
+
+void boot_setup(he_ctx *C, const he_boot_cfg *cfg) {
+    REQUIRE(cfg, HE_EINVAL, "null bootstrap configuration");
+    int lg = 0;
+    while ((1 << lg) < C->slots) ++lg;
+    REQUIRE(cfg->n_cts >= 1 && (int)cfg->n_cts <= lg && cfg->n_stc >= 1 && (int)cfg->n_stc <= lg, HE_EINVAL,
+            "n_cts and n_stc must lie in [1, log2(slots)]");
+    REQUIRE(cfg->cheb_deg >= 2 && cfg->cheb_deg <= 255 && cfg->r <= 8 && cfg->ratio_bits <= 40 && cfg->K <= 4096,
+            HE_EINVAL, "bootstrap: cheb_deg in [2, 255], r <= 8, ratio_bits <= 40, K <= 4096");
+    REQUIRE(cfg->log2_s_eval >= 20 && cfg->log2_s_eval <= 60, HE_EINVAL, "log2_s_eval in [20, 60]");
+    auto &B = C->boot;
+    B.ready = false;
+    B.n_cts = (int)cfg->n_cts; B.n_stc = (int)cfg->n_stc; B.K = (int)cfg->K; B.ratio_bits = (int)cfg->ratio_bits;
+    B.cheb_deg = (int)cfg->cheb_deg; B.r = (int)cfg->r; B.s_eval = std::ldexp(1.0, 0) * std::pow(2.0, cfg->log2_s_eval);
+    REQUIRE(boot_levels(C) <= C->L - 1, HE_EINVAL, "bootstrap needs more levels than the chain has");
+    B.cts = bt_groups(C->slots, B.n_cts, true);
+    B.stc = bt_groups(C->slots, B.n_stc, false);
+    B.cts_plan.clear();
+    B.stc_plan.clear();
+    for (const Diag &D : B.cts) B.cts_plan.push_back(bsgs_plan(D, C->slots));
+    for (const Diag &D : B.stc) B.stc_plan.push_back(bsgs_plan(D, C->slots));
+    // keys: rotation amounts with a key keep it; the others take the next indices in
+    // ascending order of amount; the conjugation comes last
+    const int from = (int)C->key_gal.size();
+    for (int a : boot_rotations(C)) {
+        const uint64_t g = rot_gal(C, a);
+        if (C->gal_key.count(g)) continue;
+        C->gal_key[g] = (int)C->key_gal.size();
+        C->key_gal.push_back((uint32_t)g);
+    }
+    const uint64_t conj = 2ull * C->N - 1;
+    if (!C->gal_key.count(conj)) {
+        C->gal_key[conj] = (int)C->key_gal.size();
+        C->key_gal.push_back((uint32_t)conj);
+    }
+    gen_keys(C, from);
+    drop_graphs(C);
+    for (auto &e : C->pt_cache) hipFree(e.second);
+    C->pt_cache.clear();
+    if (!C->mono_pos) {
+        std::vector<std::vector<int64_t>> mono(2, std::vector<int64_t>(C->N, 0));
+        mono[0][C->N / 2] = 1;
+        mono[1][C->N / 2] = -1;
+        std::vector<double *> pts = upload_plains(C, mono, C->L + 1);
+        C->mono_pos = pts[0];
+        C->mono_neg = pts[1];
+    }
+    B.ready = true;
 }
 
 // ---------------------------------------------------------------- helpers
@@ -963,7 +1405,8 @@ struct TabBuilder {
 
 void build_ctx(he_ctx *C, const he_params *prm) {
     const int N = C->N, L = C->L, A = C->alpha, np = C->np;
-    C->q = gen_primes(C->logN, L + 1, (int)prm->q0_bits, (int)prm->q_bits, (int)prm->p_bits, A);
+    C->q = gen_primes(C->logN, L + 1, (int)prm->q0_bits, (int)prm->q_bits, (int)prm->p_bits, A, (int)prm->n_hi,
+                      (int)prm->hi_bits);
     const auto &q = C->q;
     TabBuilder tb;
     std::vector<double> pd(np), pinv(np), ninv(np), two32(np);
@@ -1197,6 +1640,7 @@ void plan_rotation_keys(he_ctx *C) {
         return (uint32_t)g;
     };
     C->rot_key.clear();
+    C->gal_key.clear();
     C->key_gal.assign(1, 0u);
     for (int e = 0; e < lg; ++e) {
         C->rot_key[1 << e] = (int)C->key_gal.size();
@@ -1211,36 +1655,41 @@ void plan_rotation_keys(he_ctx *C) {
                 }
 }
 
-// secret key and every evaluation key, generated on the device
-void keygen(he_ctx *C) {
+// evaluation keys from index `from` on (key_gal[k]: 0 = relinearisation, else the
+// Galois element), generated on the device; an existing key at such an index is replaced
+void gen_keys(he_ctx *C, int from, int to) {
     const int N = C->N, np = C->np;
     const DevTables &T = C->T;
     hipStream_t s = C->stream;
-    int *dsmall = nullptr;
-    double *ta = nullptr, *te = nullptr, *tg = nullptr;
-    HIPCHK(hipMalloc(&dsmall, sizeof(int) * N));
-    HIPCHK(hipMalloc(&C->d_sk, 8ull * np * N));
-    HIPCHK(hipMalloc(&ta, 8ull * np * N));
-    HIPCHK(hipMalloc(&te, 8ull * np * N));
-    HIPCHK(hipMalloc(&tg, 8ull * np * N));
-    const VecSet all_sk{C->d_sk, np, np, 0, nullptr, nullptr};
-    launch_sample_small(dsmall, N, C->seed, OBJ_SK, 0, s);
-    launch_small_to_res(T, all_sk, dsmall, nullptr, s);
-    launch_ntt(T, all_sk, false, 0, s);
-    plan_rotation_keys(C);
     const int nkeys = (int)C->key_gal.size();
-    C->keys.assign(nkeys, KeyRef{nullptr, nullptr});
+    if (to < 0 || to > nkeys) to = nkeys;
+    if (from >= to) return;
+    int *dsmall = nullptr;
+    double *te = nullptr, *tg = nullptr, *tk = nullptr;
     const size_t per = (size_t)np * N, kw = (size_t)C->betaL * 2 * per;
-    double *tk = nullptr;  // one key as doubles, packed after generation
-    HIPCHK(hipMalloc(&tk, 8ull * kw));
-    for (int k = 0; k < nkeys; ++k) {
+    HIPCHK(hipMalloc(&dsmall, sizeof(int) * N));
+    HIPCHK(hipMalloc(&te, 8ull * per));
+    HIPCHK(hipMalloc(&tg, 8ull * per));
+    HIPCHK(hipMalloc(&tk, 8ull * kw));  // one key as doubles, packed after generation
+    const VecSet all_sk{C->d_sk, np, np, 0, nullptr, nullptr};
+    C->keys.resize(nkeys, KeyRef{nullptr, nullptr});
+    for (int k = from; k < to; ++k) {
+        if (C->keys[k].lo) {
+            HIPCHK(hipStreamSynchronize(s));
+            hipFree(const_cast<uint32_t *>(C->keys[k].lo));
+            hipFree(const_cast<uint16_t *>(C->keys[k].hi));
+            C->keys[k] = KeyRef{nullptr, nullptr};
+        }
         uint32_t *klo = nullptr;
         uint16_t *khi = nullptr;
         HIPCHK(hipMalloc(&klo, 4ull * kw));
         HIPCHK(hipMalloc(&khi, 2ull * kw));
         C->keys[k] = KeyRef{klo, khi};
         if (k == 0) launch_square_res(T, tg, C->d_sk, np, s);
-        else launch_automorph(T, VecSet{tg, np, np, 0, nullptr, nullptr}, all_sk, C->key_gal[k], s);
+        else {
+            launch_automorph(T, VecSet{tg, np, np, 0, nullptr, nullptr}, all_sk, C->key_gal[k], s);
+            C->gal_key[C->key_gal[k]] = k;
+        }
         for (int j = 0; j < C->betaL; ++j) {
             const uint32_t oa = OBJ_KEY_A | ((uint32_t)k << 8) | (uint32_t)j;
             const uint32_t oe = OBJ_KEY_E | ((uint32_t)k << 8) | (uint32_t)j;
@@ -1258,7 +1707,29 @@ void keygen(he_ctx *C) {
     }
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipGetLastError());
-    hipFree(dsmall); hipFree(ta); hipFree(te); hipFree(tg); hipFree(tk);
+    hipFree(dsmall); hipFree(te); hipFree(tg); hipFree(tk);
+}
+
+// secret key (dense ternary from one draw per coefficient, or sparse ternary placed
+// on the host) and every evaluation key of the CutMax schedule
+void keygen(he_ctx *C) {
+    const int N = C->N, np = C->np;
+    int *dsmall = nullptr;
+    HIPCHK(hipMalloc(&dsmall, sizeof(int) * N));
+    HIPCHK(hipMalloc(&C->d_sk, 8ull * np * N));
+    const VecSet all_sk{C->d_sk, np, np, 0, nullptr, nullptr};
+    if (C->secret_hw > 0) {
+        const std::vector<int> sk = sparse_secret(N, C->secret_hw, C->seed, OBJ_SKH);
+        HIPCHK(hipMemcpyAsync(dsmall, sk.data(), sizeof(int) * N, hipMemcpyHostToDevice, C->stream));
+    } else {
+        launch_sample_small(dsmall, N, C->seed, OBJ_SK, 0, C->stream);
+    }
+    launch_small_to_res(C->T, all_sk, dsmall, nullptr, C->stream);
+    launch_ntt(C->T, all_sk, false, 0, C->stream);
+    HIPCHK(hipStreamSynchronize(C->stream));
+    hipFree(dsmall);
+    plan_rotation_keys(C);
+    gen_keys(C, 0);
 }
 
 // NTT autotuner: times every workgroup-width variant of the forward + inverse
@@ -1373,6 +1844,9 @@ CutmaxCfg parse_cfg(he_ctx *C, const he_cutmax_cfg *cfg) {
     REQUIRE(cfg->sum_hi > 0 && cfg->sum_lo >= 0 && cfg->sum_lo < cfg->sum_hi, HE_EINVAL, "bad sum domain");
     cf.sum_lo = cfg->sum_lo;
     cf.sum_hi = cfg->sum_hi;
+    cf.boot = (cfg->flags & HE_BOOT) != 0;
+    for (int t = 0; t < cf.T; ++t)
+        cf.guess_max.push_back(guess_overshoot(cf.coef[t], cf.vlo[t] / cf.vhi[t], cf.newton));
     (void)C;
     return cf;
 }
@@ -1418,6 +1892,16 @@ int cutmax_impl(he_ctx *C, he_ct *const *in, he_ct *const *noise, size_t batch, 
         if (use_graph) {
             gkey = "L" + std::to_string(level) + (noise ? (prescaled ? "np" : "nt") : "") + "T" +
                    std::to_string(cf.T) + "n" + std::to_string(cf.newton) + (cf.gold_refine ? "G" : "") + "g" + std::to_string(cf.gold_d);
+            // bootstrapped calls read encoded diagonals chosen by the bound (n, c, guess)
+            if (cf.boot) {
+                char b[64];
+                gkey += "B";
+                for (int t = 0; t < cf.T; ++t) {
+                    std::snprintf(b, sizeof b, "c%.17g/%.17g", cf.c[t], cf.guess_max[t]);
+                    gkey += b;
+                }
+                for (auto &r : reqs) gkey += "n" + std::to_string(r.n);
+            }
             for (auto &r : reqs) gkey += "a" + std::to_string(r.a) + (r.npad > 0 ? "m" : "");
             for (int t = 0; t < cf.T; ++t)
                 gkey += "p" + std::to_string(cf.p[t]) + "d" + std::to_string(cf.coef[t].size());
@@ -1561,6 +2045,11 @@ int he_ctx_create(const he_params *prm, he_ctx **out) {
         REQUIRE(C->betaL <= 8, HE_EINVAL, "at most 8 digits");
         REQUIRE(prm->hoist <= 4, HE_EINVAL, "hoist must be 0..4");
         C->hoist = (int)prm->hoist;
+        REQUIRE(prm->n_hi < prm->n_q && (prm->n_hi == 0 || (prm->hi_bits >= 20 && prm->hi_bits <= 48)), HE_EINVAL,
+                "n_hi < n_q and hi_bits in [20, 48]");
+        REQUIRE(prm->secret_hw <= (1u << prm->log_n), HE_EINVAL, "secret_hw at most N");
+        C->n_hi = (int)prm->n_hi;
+        C->secret_hw = (int)prm->secret_hw;
         C->Delta = std::ldexp(1.0, 0) * std::pow(2.0, prm->log2_scale);
         C->seed = prm->seed;
         C->device = prm->device;
@@ -1591,6 +2080,9 @@ void he_ctx_destroy(he_ctx *C) {
         hipFree(const_cast<uint16_t *>(k.hi));
     }
     hipFree(C->d_sk); hipFree(C->d_tab); hipFree(C->d_itab);
+    for (auto &e : C->pt_cache) hipFree(e.second);
+    if (C->mono_pos) hipFree(C->mono_pos);
+    if (C->mono_neg) hipFree(C->mono_neg);
     if (C->arena.base) hipFree(C->arena.base);
     if (C->pool.d_dv) hipFree(C->pool.d_dv);
     if (C->pool.d_iv) hipFree(C->pool.d_iv);
@@ -1880,6 +2372,71 @@ int he_rotsum(he_ctx *C, const he_ct *a, he_ct **out) {
 }
 int he_drop(he_ctx *C, const he_ct *a, uint32_t level, he_ct **out) {
     return prim(C, a, out, [&](Exec &X) { return X.copy(X.drop(bt_of(a), (int)level)); }, true);
+}
+
+int he_boot_setup(he_ctx *C, const he_boot_cfg *cfg) {
+    return guarded([&]() {
+        REQUIRE(C, HE_EINVAL, "null context");
+        HIPCHK(hipSetDevice(C->device));
+        boot_setup(C, cfg);
+        return HE_OK;
+    });
+}
+
+int he_bootstrap(he_ctx *C, const he_ct *in, double bound, he_ct **out) {
+    return prim(C, in, out, [&](Exec &X) { return bootstrap(X, bt_of(in), bound); }, true);
+}
+
+int he_keygen_galois(he_ctx *C, uint32_t kidx, uint64_t galois) {
+    return guarded([&]() {
+        REQUIRE(C, HE_EINVAL, "null context");
+        REQUIRE((galois & 1) && galois > 1 && galois < 2ull * C->N, HE_EINVAL, "Galois element must be odd in (1, 2N)");
+        if (kidx < C->key_gal.size()) {
+            REQUIRE(kidx >= 1 && C->key_gal[kidx] == (uint32_t)galois, HE_EINVAL,
+                    "key index taken by another key (use the next free index)");
+            return HE_OK;
+        }
+        REQUIRE(kidx == C->key_gal.size(), HE_EINVAL, "key index must be the next free index");
+        REQUIRE(kidx < 0x10000u, HE_EINVAL, "too many keys");
+        HIPCHK(hipSetDevice(C->device));
+        C->key_gal.push_back((uint32_t)galois);
+        try {
+            gen_keys(C, (int)kidx);
+        } catch (...) {
+            C->key_gal.pop_back();
+            C->keys.resize(C->key_gal.size());
+            throw;
+        }
+        drop_graphs(C);
+        return HE_OK;
+    });
+}
+
+int he_rotate_gal(he_ctx *C, const he_ct *a, uint32_t kidx, uint64_t galois, he_ct **out) {
+    return prim(C, a, out, [&](Exec &X) { return X.rotate_gal(bt_of(a), (int)kidx, galois); });
+}
+
+int he_mul_plain(he_ctx *C, const he_ct *a, const int64_t *m, double pscale, he_ct **out) {
+    return prim(C, a, out, [&](Exec &X) {
+        REQUIRE(m && std::isfinite(pscale) && pscale > 0, HE_EINVAL, "mul_plain: null plaintext or bad scale");
+        const int l = (int)a->level, N = C->N;
+        int64_t *dm = (int64_t *)C->arena.alloc(8ull * N);
+        double *pt = X.alloc_d((size_t)(l + 1) * N);
+        if (X.go()) {
+            HIPCHK(hipMemcpyAsync(dm, m, 8ull * N, hipMemcpyHostToDevice, C->stream));
+            const VecSet v{pt, l + 1, l + 1, 0, nullptr, nullptr};
+            launch_int64_to_res(C->T, v, dm, 0, nullptr, C->stream);
+            launch_ntt(C->T, v, false, C->ntt_variant, C->stream);
+        }
+        return X.mul_plain(bt_of(a), pt, pscale);
+    });
+}
+
+int he_modraise(he_ctx *C, const he_ct *a, uint32_t level, double scale, he_ct **out) {
+    return prim(C, a, out, [&](Exec &X) {
+        REQUIRE(std::isfinite(scale) && scale > 0, HE_EINVAL, "modraise: bad scale");
+        return X.modraise(bt_of(a), (int)level, scale);
+    });
 }
 
 int he_bench_ntt(he_ctx *C, uint32_t vectors, uint32_t iters, double *ms_fwd, double *ms_inv) {

@@ -146,6 +146,20 @@ void launch_inner_product(const DevTables &T, const double *ext, long long estri
                           double pmodl = 0.0);
 void launch_pack_key(const double *src, uint32_t *lo, uint16_t *hi, int beta, int np, int N, hipStream_t s);
 
+// terms of a plaintext-times-ciphertext sum (bootstrap linear transforms): plaintext
+// pt[t] ([limbs][N], NTT domain) times ciphertext x[t] (ciphertext c at x + c xct,
+// polynomial 1 at + xpoly, limb i at + i N)
+constexpr int kMaxLtTerms = 16;
+struct LtTerms {
+    const double *pt[kMaxLtTerms];
+    const double *x[kMaxLtTerms];
+    long long xct[kMaxLtTerms];
+    long long xpoly[kMaxLtTerms];
+    int n;
+};
+void launch_lt_inner(const DevTables &T, double *out, long long oct, long long opoly, const LtTerms &tm, int cnt,
+                     int limbs, hipStream_t s);
+
 // rotations of one hoisted rotate-and-sum step: key and Galois element of each
 constexpr int kMaxHoist = 15;
 struct RotSet {
@@ -196,7 +210,9 @@ uint64_t invmod_u(uint64_t a, uint64_t q);
 uint64_t red_i64(int64_t v, uint64_t q);
 bool miller_rabin(uint64_t n);
 std::vector<uint64_t> gen_primes(int logN, int n_q, int q0_bits, int q_bits, int p_bits,
-                                 int alpha);
+                                 int alpha, int n_hi = 0, int hi_bits = 0);
+void philox_host(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint64_t seed, uint32_t out[4]);
+std::vector<int> sparse_secret(int N, int hw, uint64_t seed, uint32_t obj);
 uint64_t find_psi(uint64_t q, int N);
 void encode_slots(const double *z, int N, double scale, int64_t *m);
 void decode_slots(const double *m, int N, double scale, double *z);

@@ -56,7 +56,8 @@ bool miller_rabin(uint64_t n) {
 
 // Primes 2^b - k*2N + 1 (k = 1, 2, ...), first unused prime per slot, in the
 // order q0, q1..q_{n_q-1}, p0..p_{alpha-1}.
-std::vector<uint64_t> gen_primes(int logN, int n_q, int q0_bits, int q_bits, int p_bits, int alpha) {
+std::vector<uint64_t> gen_primes(int logN, int n_q, int q0_bits, int q_bits, int p_bits, int alpha, int n_hi,
+                                 int hi_bits) {
     const uint64_t M = 2ull << logN;
     std::vector<uint64_t> out;
     auto next = [&](int bits) {
@@ -69,7 +70,8 @@ std::vector<uint64_t> gen_primes(int logN, int n_q, int q0_bits, int q_bits, int
         }
     };
     out.push_back(next(q0_bits));
-    for (int i = 1; i < n_q; ++i) out.push_back(next(q_bits));
+    // the top n_hi Q primes (the levels a bootstrap consumes first) have hi_bits bits
+    for (int i = 1; i < n_q; ++i) out.push_back(next(i >= n_q - n_hi ? hi_bits : q_bits));
     for (int i = 0; i < alpha; ++i) out.push_back(next(p_bits));
     return out;
 }
@@ -85,6 +87,41 @@ uint64_t find_psi(uint64_t q, int N) {
 }
 
 int64_t llround_d(double x) { return std::llround(x); }
+
+// Philox4x32-10 (Salmon et al., SC 2011) on the host; the same counter layout as the
+// device sampler: (i, prime, obj, attempt), key (seed low, seed high)
+void philox_host(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint64_t seed, uint32_t out[4]) {
+    uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    for (int r = 0; r < 10; ++r) {
+        if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n1 = (uint32_t)p1;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        const uint32_t n3 = (uint32_t)p0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+// sparse ternary secret with exactly hw nonzero coefficients: the i-th is placed at
+// word 0 mod N of draw (i, 0, obj, attempt), attempt = 0, 1, .. until that position
+// is still free; its sign is - when word 1 is odd
+std::vector<int> sparse_secret(int N, int hw, uint64_t seed, uint32_t obj) {
+    if (hw < 0 || hw > N) throw std::invalid_argument("secret weight out of range");
+    std::vector<int> s(N, 0);
+    for (int i = 0; i < hw; ++i)
+        for (uint32_t att = 0;; ++att) {
+            uint32_t o[4];
+            philox_host((uint32_t)i, 0u, obj, att, seed, o);
+            const int pos = (int)(o[0] & (uint32_t)(N - 1));
+            if (s[pos]) continue;
+            s[pos] = (o[1] & 1u) ? -1 : 1;
+            break;
+        }
+    return s;
+}
 
 // ------------------------------------------------------------------ encoding
 // Slot j <-> zeta^(t_j), t_j = 5^j mod 2N, zeta = e^{i pi / N}.  The N odd

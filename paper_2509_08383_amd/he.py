@@ -20,6 +20,7 @@ HE_OK, HE_EINVAL, HE_ENOMEM, HE_EDEVICE, HE_EDEPTH, HE_ERANGE, HE_ESTATE = 0, -1
 HE_NOISE_PRESCALED = 1
 HE_REFINE_GOLDSCHMIDT = 2
 HE_MASK_PAD = 4
+HE_BOOT = 8
 HE_OPT_GRAPH, HE_OPT_NTT_VARIANT = 1, 2
 
 _c_u32p = ctypes.POINTER(ctypes.c_uint32)
@@ -39,7 +40,14 @@ class _Params(ctypes.Structure):
     _fields_ = [("log_n", ctypes.c_uint32), ("n_q", ctypes.c_uint32), ("q0_bits", ctypes.c_uint32),
                 ("q_bits", ctypes.c_uint32), ("p_bits", ctypes.c_uint32), ("dnum", ctypes.c_uint32),
                 ("log2_scale", ctypes.c_double), ("seed", ctypes.c_uint64), ("device", ctypes.c_int),
-                ("stream", _V), ("hoist", ctypes.c_uint32)]
+                ("stream", _V), ("hoist", ctypes.c_uint32), ("n_hi", ctypes.c_uint32),
+                ("hi_bits", ctypes.c_uint32), ("secret_hw", ctypes.c_uint32)]
+
+
+class _BootCfg(ctypes.Structure):
+    _fields_ = [("n_cts", ctypes.c_uint32), ("n_stc", ctypes.c_uint32), ("K", ctypes.c_uint32),
+                ("ratio_bits", ctypes.c_uint32), ("cheb_deg", ctypes.c_uint32), ("r", ctypes.c_uint32),
+                ("log2_s_eval", ctypes.c_double)]
 
 
 class _Cfg(ctypes.Structure):
@@ -96,6 +104,12 @@ def lib():
             "he_ntt_tuning": [_V, ctypes.POINTER(ctypes.c_int32), ctypes.c_uint32],
             "he_profile_begin": [_V],
             "he_profile_end": [_V, ctypes.c_char_p, ctypes.c_size_t],
+            "he_boot_setup": [_V, ctypes.POINTER(_BootCfg)],
+            "he_bootstrap": [_V, _V, ctypes.c_double, ctypes.POINTER(_V)],
+            "he_keygen_galois": [_V, ctypes.c_uint32, ctypes.c_uint64],
+            "he_rotate_gal": [_V, _V, ctypes.c_uint32, ctypes.c_uint64, ctypes.POINTER(_V)],
+            "he_mul_plain": [_V, _V, _c_i64p, ctypes.c_double, ctypes.POINTER(_V)],
+            "he_modraise": [_V, _V, ctypes.c_uint32, ctypes.c_double, ctypes.POINTER(_V)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -131,11 +145,36 @@ class Params:
     log2_scale: float
     seed: int = 1
     hoist: int = 0  # rotate-and-sum: 0 one rotation at a time, h = hoisted radix-2^h steps
+    n_hi: int = 0      # the top n_hi Q primes have hi_bits bits (the levels a bootstrap uses first)
+    hi_bits: int = 0
+    secret_hw: int = 0  # 0 dense ternary secret, h > 0 sparse ternary with h nonzeros
+
+
+@dataclass
+class BootCfg:
+    """Bootstrap configuration (he_boot_cfg)."""
+    n_cts: int = 3
+    n_stc: int = 3
+    K: int = 0
+    ratio_bits: int = 12
+    cheb_deg: int = 31
+    r: int = 3
+    log2_s_eval: float = 48.0
+
+    def levels(self) -> int:
+        import math
+        return self.n_cts + 1 + int(math.ceil(math.log2(self.cheb_deg + 1))) + 1 + self.r + self.n_stc
 
 
 # parameter sets: a non-secure toy chain at N = 2^12 and the 128-bit chain at N = 2^16
 TOY = Params(log_n=12, n_q=36, q0_bits=40, q_bits=30, p_bits=40, dnum=3, log2_scale=30, seed=7, hoist=3)
 SECURE = Params(log_n=16, n_q=30, q0_bits=48, q_bits=40, p_bits=48, dnum=3, log2_scale=40, seed=11, hoist=3)
+# bootstrappable sets: 48-bit primes on the levels the bootstrap consumes first (CoeffToSlot
+# and EvalMod), 40-bit scaling primes below, a sparse ternary secret
+TOY_BOOT = Params(log_n=12, n_q=20, q0_bits=48, q_bits=40, p_bits=48, dnum=3, log2_scale=40, seed=5, hoist=3,
+                  n_hi=13, hi_bits=48, secret_hw=64)
+BOOT = Params(log_n=16, n_q=29, q0_bits=48, q_bits=40, p_bits=48, dnum=3, log2_scale=40, seed=13, hoist=3,
+              n_hi=13, hi_bits=48, secret_hw=192)
 
 
 @dataclass
@@ -220,7 +259,7 @@ class Context:
 
     def __init__(self, prm: Params, device: int = 0, stream: Optional[int] = None):
         P = _Params(prm.log_n, prm.n_q, prm.q0_bits, prm.q_bits, prm.p_bits, prm.dnum, float(prm.log2_scale),
-                    prm.seed, device, stream, prm.hoist)
+                    prm.seed, device, stream, prm.hoist, prm.n_hi, prm.hi_bits, prm.secret_hw)
         h = _V()
         _check(lib().he_ctx_create(ctypes.byref(P), ctypes.byref(h)))
         self.h = h
@@ -345,6 +384,28 @@ class Context:
 
     def drop(self, a, level: int):
         return self._op("he_drop", a.h, int(level))
+
+    # bootstrapping -------------------------------------------------------------
+    def boot_setup(self, cfg: BootCfg):
+        c = _BootCfg(cfg.n_cts, cfg.n_stc, cfg.K, cfg.ratio_bits, cfg.cheb_deg, cfg.r, float(cfg.log2_s_eval))
+        _check(lib().he_boot_setup(self.h, ctypes.byref(c)))
+
+    def bootstrap(self, a, bound: float):
+        return self._op("he_bootstrap", a.h, float(bound))
+
+    def keygen_galois(self, kidx: int, galois: int):
+        _check(lib().he_keygen_galois(self.h, int(kidx), ctypes.c_uint64(int(galois))))
+
+    def rotate_gal(self, a, kidx: int, galois: int):
+        return self._op("he_rotate_gal", a.h, int(kidx), ctypes.c_uint64(int(galois)))
+
+    def mul_plain(self, a, m, pscale: float):
+        m = np.ascontiguousarray(m, dtype=np.int64)
+        assert m.size == self.N
+        return self._op("he_mul_plain", a.h, m.ctypes.data_as(_c_i64p), float(pscale))
+
+    def modraise(self, a, level: int, scale: float):
+        return self._op("he_modraise", a.h, int(level), float(scale))
 
     # measurement ---------------------------------------------------------------
     def bench_ntt(self, vectors: int, iters: int):

@@ -1,0 +1,280 @@
+"""GPU bootstrapping against the CPU oracle.
+
+Bit-exact on every limb (same seed, same integer plaintexts): the sparse secret and
+mixed prime chain (through encryption), ModRaise, plaintext products, rotations by
+any Galois element and the complex conjugation, with the Galois keys the bootstrap
+set-up generates.  The whole bootstrap encodes its diagonals and EvalMod constants in
+FP64 on each side independently (like any two encoders, they agree within one unit
+per coefficient, not bit for bit), so it is checked on decrypted values: the input
+values come back within the bootstrap's precision, and the GPU and oracle outputs
+agree with each other."""
+import math
+import sys
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import boot as OB  # noqa: E402
+from oracle import ckks  # noqa: E402
+from workloads import random_small_poly  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _oracle_params(p):
+    return ckks.Params(log_n=p.log_n, n_q=p.n_q, q0_bits=p.q0_bits, q_bits=p.q_bits, p_bits=p.p_bits,
+                       dnum=p.dnum, log2_scale=p.log2_scale, seed=p.seed, hoist=p.hoist, n_hi=p.n_hi,
+                       hi_bits=p.hi_bits, secret_hw=p.secret_hw)
+
+
+class BootPair:
+    """GPU and oracle contexts with the bootstrap parameters, in lockstep."""
+
+    def __init__(self, prm):
+        from paper_2509_08383_amd import he
+        self.he = he
+        self.G = he.Context(prm)
+        self.O = ckks.Oracle(_oracle_params(prm))
+        self.O.keygen_cutmax()
+        assert self.G.primes == self.O.q
+        self.cfg = OB.BootCfg()
+        self.keys = OB.keygen_boot(self.O, self.cfg)
+        self.G.boot_setup(he.BootCfg())
+
+    def enc(self, m, scale=None):
+        scale = self.O.Delta if scale is None else scale
+        return self.G.encrypt_coeffs(m, scale, self.G.slots), self.O.encrypt_coeffs(m, scale)
+
+    def same(self, g, o, what):
+        eg = self.G.export(g)[0]
+        eo = o.export()
+        assert eg.shape == eo.shape, (what, eg.shape, eo.shape)
+        bad = int((eg != eo).sum())
+        assert bad == 0, f"{what}: {bad} limb words differ"
+        assert g.level == o.level, what
+        assert g.scale == o.scale, (what, g.scale, o.scale)
+
+
+@pytest.fixture(scope="module")
+def toy():
+    from paper_2509_08383_amd import he
+    say("[gpu] building the bootstrap toy pair (N=2^12, 20 Q primes, 13 of 48 bits, secret weight 64)")
+    return BootPair(he.TOY_BOOT)
+
+
+def test_boot_primitives_bit_exact(toy):
+    """sparse secret + mixed chain (encryption), ModRaise, plaintext products, Galois
+    rotations and the conjugation, bit for bit"""
+    G, O = toy.G, toy.O
+    N, L = O.N, O.L
+    say("[gpu] boot primitives: encrypt")
+    m = random_small_poly(3, N, 2 ** 38)
+    g, o = toy.enc(m)
+    toy.same(g, o, "encrypt (sparse secret, mixed chain)")
+    say("[gpu] boot primitives: drop + constant multiply to level 0, ModRaise")
+    g0 = G.cmul(G.drop(g, 1), 1.0, 2.0 ** 36, False)
+    o0 = O.cm_target(O.drop(o, 1), 1.0, 2.0 ** 36)
+    toy.same(g0, o0, "to level 0")
+    gr, orr = G.modraise(g0, L, 12345.0), O.modraise(o0, L, 12345.0)
+    toy.same(gr, orr, "modraise")
+    say("[gpu] boot primitives: plaintext products")
+    rng = np.random.default_rng(4)
+    pt = rng.integers(-2 ** 30, 2 ** 30, N)
+    toy.same(G.mul_plain(gr, pt, 2.0 ** 30), O.mul_plain(orr, pt, 2.0 ** 30), "mul_plain")
+    mono = np.zeros(N, dtype=np.int64)
+    mono[N // 2] = -1
+    toy.same(G.mul_plain(g, mono, 1.0), O.mul_plain(o, mono, 1.0), "mul_plain monomial")
+    say("[gpu] boot primitives: Galois rotations with the bootstrap keys")
+    M = 2 * N
+    conj = M - 1
+    toy.same(G.rotate_gal(g, toy.keys[conj], conj), O.rotate_gal(o, toy.keys[conj], conj), "conjugation")
+    for a in (3, 24, 56):
+        ga = pow(5, a, M)
+        toy.same(G.rotate_gal(g, toy.keys[ga], ga), O.rotate_gal(o, toy.keys[ga], ga), f"rotation by {a}")
+    gl = G.drop(g, 5)
+    ol = O.drop(o, 5)
+    ga = pow(5, 40, M)
+    toy.same(G.rotate_gal(gl, toy.keys[ga], ga), O.rotate_gal(ol, toy.keys[ga], ga), "rotation at level 5")
+
+
+def test_keygen_galois_appends_and_rejects(toy):
+    G = toy.G
+    from paper_2509_08383_amd import he
+    nxt = max(toy.keys.values()) + 1
+    with pytest.raises(he.HeError):
+        G.keygen_galois(nxt + 5, 7)          # not the next free index
+    with pytest.raises(he.HeError):
+        G.keygen_galois(nxt, 8)              # even Galois element
+    g = 7
+    G.keygen_galois(nxt, g)
+    toy.O.keygen_galois(nxt, g)
+    m = random_small_poly(5, toy.O.N, 2 ** 36)
+    a, b = toy.enc(m)
+    toy.same(G.rotate_gal(a, nxt, g), toy.O.rotate_gal(b, nxt, g), "automorphism X -> X^7")
+    with pytest.raises(he.HeError):
+        G.rotate_gal(a, nxt, 9)              # key made for another element
+
+
+def test_bootstrap_toy_round_trip(toy):
+    """a level-3 ciphertext of values in [-1, 1] comes back at level L - 16 with
+    scale Delta and the same values; GPU and oracle bootstraps agree"""
+    G, O = toy.G, toy.O
+    rng = np.random.default_rng(1)
+    x = rng.uniform(-1, 1, O.slots)
+    m = ckks.encode(x, O.N, O.Delta)
+    g, o = toy.enc(m)
+    g3, o3 = G.drop(g, 3), O.drop(o, 3)
+    say("[gpu] bootstrap toy: GPU")
+    t0 = time.time()
+    gb = G.bootstrap(g3, 1.0)
+    say(f"[gpu] bootstrap toy: {1e3 * (time.time() - t0):.1f} ms (first call, diagonals encoded)")
+    t0 = time.time()
+    gb = G.bootstrap(g3, 1.0)
+    say(f"[gpu] bootstrap toy: {1e3 * (time.time() - t0):.1f} ms")
+    assert gb.level == O.L - OB.levels_used(toy.cfg)
+    assert abs(gb.scale / O.Delta - 1) < 1e-9
+    dg = G.decrypt(gb, O.slots)
+    err = float(np.abs(dg - x).max())
+    say(f"[gpu] bootstrap toy: max |out - x| = {err:.2e}")
+    assert err < 1e-3, err
+    say("[gpu] bootstrap toy: oracle")
+    ob = OB.bootstrap(O, o3, 1.0, toy.cfg, toy.keys)
+    do = O.decrypt(ob)
+    assert ob.level == gb.level
+    assert float(np.abs(dg - do).max()) < 2e-3
+    # a ciphertext with its values scaled by 8 under bound 8 (the precision scales with the bound)
+    g8 = G.bootstrap(G.drop(G.mul_int(g, 8), 2), 8.0)
+    err8 = float(np.abs(G.decrypt(g8, O.slots) - 8 * x).max())
+    say(f"[gpu] bootstrap toy, bound 8: max err {err8:.2e}")
+    assert err8 < 8e-3
+
+
+def test_bootstrap_rejects_bad_input(toy):
+    from paper_2509_08383_amd import he
+    G = toy.G
+    m = random_small_poly(6, toy.O.N, 2 ** 30)
+    g, _ = toy.enc(m)
+    with pytest.raises(he.HeError):
+        G.bootstrap(G.drop(g, 0), 1.0)       # no level to spare
+    with pytest.raises(he.HeError):
+        G.bootstrap(g, -1.0)
+    with pytest.raises(he.HeError):
+        G.modraise(g, 3, 1.0)                # not at level 0
+
+
+@pytest.fixture(scope="module")
+def full():
+    """N = 2^16 bootstrappable set (29 Q primes, 13 of 48 bits, secret weight 192)"""
+    from paper_2509_08383_amd import he
+    say("[gpu] bootstrap N=2^16: context + keys")
+    G = he.Context(he.BOOT)
+    G.boot_setup(he.BootCfg(ratio_bits=6))
+    yield G
+    G.close()
+
+
+@pytest.mark.slow
+def test_bootstrap_full_size(full):
+    """values in [-1, 1] and CutMax-like iterates z in [0, 40] with bound 40 come back
+    at level L - 16 with their values"""
+    from paper_2509_08383_amd import he
+    G = full
+    rng = np.random.default_rng(7)
+    x = rng.uniform(-1, 1, G.slots)
+    ct = G.drop(G.encrypt(x), 2)
+    t0 = time.time()
+    out = G.bootstrap(ct, 1.0)
+    say(f"[gpu] bootstrap N=2^16 first call {time.time() - t0:.2f} s")
+    G.sync()
+    t0 = time.time()
+    out = G.bootstrap(ct, 1.0)
+    G.sync()
+    say(f"[gpu] bootstrap N=2^16: {1e3 * (time.time() - t0):.1f} ms")
+    assert out.level == G.L - he.BootCfg().levels()
+    err = float(np.abs(G.decrypt(out) - x).max())
+    say(f"[gpu] bootstrap N=2^16, ratio 2^-6: max err {err:.2e}")
+    assert err < 2e-3, err
+    z = 1.0 + 0.2 * rng.standard_normal(G.slots)
+    z[123] = 38.0
+    out = G.bootstrap(G.drop(G.encrypt(z), 1), 40.0)
+    errz = np.abs(G.decrypt(out) - z)
+    say(f"[gpu] bootstrap N=2^16, bound 40: max err {errz.max():.2e}, at the spike {errz[123]:.2e}")
+    assert errz.max() < 8e-2 and errz[123] < 8e-2
+
+
+VLO, VHI = [12.0, 0.4, 0.8], [24.0, 0.9, 16.0]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("seed", [0, 1])
+def test_cutmax_bootstrapped_full_size(full, seed):
+    """T = 3 CutMax on 32000 LLM-like logits on a chain whose 15 scaling levels hold
+    only two iterations: the iterate is bootstrapped twice; the decrypted one-hot agrees
+    with the FP64 mirror of the same schedule and recovers the argmax"""
+    from paper_2509_08383_amd import he
+    from oracle.cutmax_fp64 import MirrorCfg, chebyshev_invsqrt, cutmax_mirror, slot_layout
+    from workloads import llm_logits
+    G = full
+    x = llm_logits(seed)
+    y, a, _ = slot_layout(x, G.slots)
+    coef = [list(chebyshev_invsqrt(VLO[t] / VHI[t], 3)) for t in range(3)]
+    cfg = he.CutmaxCfg(T=3, p=[3] * 3, c=[5.0] * 3, var_lo=VLO, var_hi=VHI, init_degree=3, init_coef=coef,
+                       sum_lo=1.0, sum_hi=3.0, gold_d=3)
+    ct = G.encrypt(x)
+    with pytest.raises(he.HeError):
+        G.cutmax([ct], cfg)                  # needs 18 levels, the chain has 15 below its wide primes
+    cfg.flags = he.HE_BOOT
+    t0 = time.time()
+    Z = G.cutmax([ct], cfg)[0]
+    say(f"[gpu] bootstrapped CutMax seed {seed}: {1e3 * (time.time() - t0):.1f} ms wall, "
+        f"{G.last_cutmax_ms():.1f} ms device, output level {Z.level}")
+    assert Z.level == 4                      # 15 -> 8 -> 3, boot 12 -> 5, boot 12 -> 4
+    dz = G.decrypt(Z, y.size)
+    mc = MirrorCfg(T=3, p=[3] * 3, c=[5.0] * 3, v_hi=VHI, v_lo=VLO, coef=coef, B=3.0 * y.size, gold_d=3,
+                   sum_lo=1.0 * y.size)
+    ref = cutmax_mirror(y, mc)
+    err = float(np.abs(dz - ref).max())
+    say(f"[gpu] bootstrapped CutMax seed {seed}: |Z - mirror| = {err:.2e}, max Z {ref.max():.4f}")
+    assert err < 1e-3, err
+    assert int(np.argmax(dz[:x.size])) == int(np.argmax(x))
+
+
+@pytest.mark.slow
+def test_cutmax_bootstrapped_batch(full):
+    """4 requests (1 and 4 ciphertexts) bootstrapped together in one call"""
+    from paper_2509_08383_amd import he
+    from oracle.cutmax_fp64 import chebyshev_invsqrt
+    from workloads import llm_logits
+    G = full
+    coef = [list(chebyshev_invsqrt(VLO[t] / VHI[t], 3)) for t in range(3)]
+    cfg = he.CutmaxCfg(T=3, p=[3] * 3, c=[5.0] * 3, var_lo=VLO, var_hi=VHI, init_degree=3, init_coef=coef,
+                       sum_lo=1.0, sum_hi=3.0, gold_d=3, flags=he.HE_BOOT)
+    xs = [llm_logits(10 + r, 32000 if r % 2 == 0 else 128256) for r in range(4)]
+    cts = [G.encrypt(x) for x in xs]
+    t0 = time.time()
+    Zs = G.cutmax(cts, cfg)
+    say(f"[gpu] bootstrapped CutMax batch of 4 (6 ciphertexts): {1e3 * (time.time() - t0):.1f} ms wall")
+    for x, Z in zip(xs, Zs):
+        dz = G.decrypt(Z, x.size)
+        assert int(np.argmax(dz)) == int(np.argmax(x))
+
+
+@pytest.mark.slow
+def test_bootstrap_full_size_ratio12():
+    """the oracle's default ratio 2^-12: noise-bound precision (the CPU oracle measures
+    1.8e-2 on the same parameters), 64x worse than at 2^-6"""
+    from paper_2509_08383_amd import he
+    G = he.Context(he.BOOT)
+    G.boot_setup(he.BootCfg())
+    x = np.random.default_rng(7).uniform(-1, 1, G.slots)
+    out = G.bootstrap(G.drop(G.encrypt(x), 2), 1.0)
+    err = float(np.abs(G.decrypt(out) - x).max())
+    say(f"[gpu] bootstrap N=2^16, ratio 2^-12: max err {err:.2e}")
+    assert err < 5e-2, err
+    G.close()
