@@ -179,6 +179,58 @@ def violation_main(spec: str, graph: int):
     print(json.dumps(out))
 
 
+def boot_bench(he, args, x):
+    """CKKS bootstrapping at N = 2^16 (29 Q primes, the top 13 of 48 bits, sparse secret of
+    weight 192, dnum = 3): one bootstrap of a ciphertext (16 levels, ratio 2^-6), and the T = 3
+    CutMax on 32000 logits run on the 15 scaling levels below the wide primes, which hold two
+    iterations, so the iterate is bootstrapped twice (HE_BOOT)."""
+    log("[bench] bootstrappable context N=2^16")
+    bctx = he.Context(he.BOOT, device=0)
+    if args.graph:
+        bctx.set_option(he.HE_OPT_GRAPH, 1)
+    bc = he.BootCfg(ratio_bits=6)
+    bctx.boot_setup(bc)
+    rng = np.random.default_rng(5)
+    v = rng.uniform(-1, 1, bctx.slots)
+    ct = bctx.drop(bctx.encrypt(v), 2)
+    out = bctx.bootstrap(ct, 1.0)
+    bctx.sync()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = bctx.bootstrap(ct, 1.0)
+    bctx.sync()
+    boot_ms = (time.perf_counter() - t0) * 1e3 / reps
+    err = float(np.abs(bctx.decrypt(out) - v).max())
+    kern = None
+    if not args.no_profile:
+        bctx.profile_begin()
+        bctx.bootstrap(ct, 1.0)
+        kern = {k: {"launches": w[0], "ms": w[1], "bytes": w[2]} for k, w in bctx.profile_end().items()}
+    log(f"[bench] bootstrap {boot_ms:.2f} ms, max err {err:.2e}")
+    cfg = cfg_secure(he)
+    cfg.flags = he.HE_BOOT
+    ctb = bctx.encrypt(x)
+    bctx.cutmax([ctb], cfg)
+    bctx.sync()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        Zb = bctx.cutmax([ctb], cfg)[0]
+    bctx.sync()
+    cm_ms = (time.perf_counter() - t0) * 1e3 / reps
+    ok = int(np.argmax(bctx.decrypt(Zb, x.size))) == int(np.argmax(x))
+    log(f"[bench] bootstrapped CutMax {cm_ms:.2f} ms, argmax ok={ok}")
+    res = {"params": "N=2^16, 29 Q primes (q0 48 bits, 15 x 40, 13 x 48), 10 P primes, dnum=3, "
+                     "sparse ternary secret h=192",
+           "levels_used": bc.levels(), "ratio_bits": bc.ratio_bits, "bootstrap_ms": boot_ms,
+           "bootstrap_max_err_bound1": err, "out_level": out.level,
+           "cutmax_T3_bootstrapped_ms": cm_ms, "cutmax_device_ms": bctx.last_cutmax_ms(),
+           "bootstraps_per_cutmax": 2, "cutmax_argmax_ok": bool(ok), "cutmax_out_level": Zb.level,
+           "kernels": kern}
+    bctx.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,6 +240,10 @@ def main():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched and the 151936-logit measurements")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-boot", action="store_true",
+                    help="skip the bootstrapping measurements (separate bootstrappable context)")
+    ap.add_argument("--boot-only", action="store_true",
+                    help="only the bootstrapping measurements (profiling runs of the bootstrap)")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--graph", type=int, default=1,
                     help="replay each CutMax from a captured HIP graph (1) or launch eagerly (0)")
@@ -212,6 +268,9 @@ def main():
 
     assert torch.cuda.is_available(), "no GPU"
     digest = src_digest()
+    if args.boot_only:
+        print(json.dumps({"bootstrapping": boot_bench(he, args, llm_logits(0, VOCAB2))}))
+        return
     log("[bench] context N=2^16")
     prm = he.SECURE if args.hoist is None else dataclasses.replace(he.SECURE, hoist=args.hoist)
     ctx = he.Context(prm, device=0)
@@ -348,6 +407,10 @@ def main():
                "sample": f"{what} on the same 32000-logit input, one run, {sample_s:.2f} s"}
         log(f"[bench] cpu {cpu}")
 
+    boot = None
+    if not args.no_boot:
+        boot = boot_bench(he, args, x)
+
     out = {
         "metric": "ms per encrypted 32k-logit CutMax argmax",
         "value": ms_per_step,
@@ -377,6 +440,7 @@ def main():
         "roofline": roof,
         "kernels": {k: {"launches": v[0], "ms": v[1], "bytes": v[2]} for k, v in kern.items()},
         "cpu_baseline": cpu,
+        "bootstrapping": boot,
         "paper_reference": {"value_ms": 3373.0, "hardware": "1x NVIDIA H100 (HELayers)",
                             "note": "T=4, p=[16,4,4,6], c=[5,3,3,3], |V|=32768, unstated CKKS parameters; "
                                     "context only, not like-for-like"},

@@ -323,9 +323,12 @@ int he_profile_end(he_ctx *ctx, char *buf, size_t cap);
 
 /* Options: HE_OPT_GRAPH (capture he_cutmax in a HIP graph and replay it for
  * repeated calls of the same shape), HE_OPT_NTT_VARIANT (0 = autotune, k > 0
- * forces variant k). */
+ * forces variant k), HE_OPT_BOOT_HOIST (1, the default: the baby steps of a
+ * bootstrap linear transform share one ModUp; 0: one full key switch each; the
+ * results are equal word for word). */
 #define HE_OPT_GRAPH 1
 #define HE_OPT_NTT_VARIANT 2
+#define HE_OPT_BOOT_HOIST 3
 int he_set_option(he_ctx *ctx, int option, int64_t value);
 
 /* NTT autotuner result: the workgroup-width variant (1: 4 or 8 sub-transforms

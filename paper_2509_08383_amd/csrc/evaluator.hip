@@ -167,6 +167,8 @@ struct he_ctx {
     int hoist = 0;
     std::map<int, int> rot_key;     // rotation amount -> key index
     std::map<int, const int *> xorder;  // smallest amount of a hoisted step -> x-block orbit order
+    const int *xorder_id = nullptr;     // x-blocks in natural order (any rotation)
+    int boot_hoist = 1;                 // bootstrap baby steps share one ModUp
     std::vector<uint32_t> key_gal;  // key index -> Galois element (0 for relinearisation)
     // graph cache keyed by a signature of the call
     std::map<std::string, hipGraphExec_t> graphs;
@@ -393,17 +395,46 @@ struct Exec {
     // With mrescale (relinearisation), a1 holds the tensor's d0/d1 over Q_l and the output
     // is (d + relinearised d2) / q_l at level l - 1: the ModDown divides A = acc + P d by
     // P q_l in one rounding (a2 and rot unused).
+    // the extended digits [cnt][beta][next][N] of d (ModUp: inverse NTT with Qhat_i^-1
+    // folded in, basis conversion of every digit, one forward NTT of the converted limbs)
+    double *modup(const double *d, long long dstride, int cnt, int l) {
+        const int A = C->alpha, next = l + 1 + A, beta = (l + 1 + A - 1) / A;
+        const long long N = C->N;
+        double *ext = alloc_d((size_t)cnt * beta * next * N);
+        const size_t m = C->arena.mark();
+        double *dcoef = alloc_d((size_t)cnt * (l + 1) * N);
+        if (go()) {
+            VecSet vd{dcoef, cnt * (l + 1), l + 1, (long long)(l + 1) * N, nullptr, nullptr};
+            const VecSet vsrc{const_cast<double *>(d), cnt * (l + 1), l + 1, dstride, nullptr, nullptr};
+            launch_ntt(T, vd, true, C->ntt_variant, s, &vsrc, C->mu_scale[l]);
+            ModUpDigits dg{};
+            for (int j = 0; j < beta; ++j) {
+                dg.qhat[j] = C->qhat[l][j];
+                dg.lo[j] = j * A;
+                dg.dl[j] = std::min(A, l + 1 - j * A);
+            }
+            launch_modup(T, dcoef, (long long)(l + 1) * N, ext, (long long)beta * next * N, (long long)next * N, d,
+                         dstride, cnt, beta, next, C->ext_prime[l], dg, s);
+            const int nd = C->ndall[l];
+            launch_ntt(T, VecSet{ext, cnt * nd, nd, (long long)beta * next * N, C->ndall_slot[l], C->ndall_prime[l]},
+                       false, C->ntt_variant, s);
+        }
+        C->arena.release(m);
+        return ext;
+    }
+
+    // ext_pre: the extended digits of d already computed (modup), d unused
     void keyswitch(const double *d, long long dstride, int cnt, int l, int kidx, double *out, long long ostride,
                    Addend a1 = Addend{nullptr, 0, 0, 0}, Addend a2 = Addend{nullptr, 0, 0, 0},
-                   const RotSet *rot = nullptr, bool mrescale = false) {
+                   const RotSet *rot = nullptr, bool mrescale = false, const double *ext_pre = nullptr) {
         const int A = C->alpha, next = l + 1 + A, beta = (l + 1 + A - 1) / A;
         const long long N = C->N;
         const size_t m = C->arena.mark();
-        double *dcoef = alloc_d((size_t)cnt * (l + 1) * N);
-        double *ext = alloc_d((size_t)cnt * beta * next * N);
+        double *dcoef = ext_pre ? nullptr : alloc_d((size_t)cnt * (l + 1) * N);
+        double *ext = ext_pre ? const_cast<double *>(ext_pre) : alloc_d((size_t)cnt * beta * next * N);
         double *acc = alloc_d((size_t)cnt * 2 * next * N);
         double *conv = alloc_d((size_t)cnt * 2 * (l + 1) * N);
-        if (go()) {
+        if (go() && !ext_pre) {
             // coefficient-domain digits, already scaled by Qhat_i^-1 (folded into N^-1)
             VecSet vd{dcoef, cnt * (l + 1), l + 1, (long long)(l + 1) * N, nullptr, nullptr};
             const VecSet vsrc{const_cast<double *>(d), cnt * (l + 1), l + 1, dstride, nullptr, nullptr};
@@ -420,6 +451,8 @@ struct Exec {
             const int nd = C->ndall[l];
             launch_ntt(T, VecSet{ext, cnt * nd, nd, (long long)beta * next * N, C->ndall_slot[l], C->ndall_prime[l]},
                        false, C->ntt_variant, s);
+        }
+        if (go()) {
             if (rot)
                 launch_inner_product_rot(T, ext, (long long)beta * next * N, (long long)next * N, acc,
                                          acc + (long long)next * N, 2LL * next * N, *rot, C->betaL, cnt, beta,
@@ -553,6 +586,45 @@ struct Exec {
         return o;
     }
 
+    // rotations of one batch by several Galois elements sharing one ModUp: each
+    // automorphism acts on the extended NTT-domain digits inside its key products (the
+    // extension commutes with the automorphism because the digits are lifted to their
+    // centred representatives), one ModDown per rotation; equal to rotate_gal word for word
+    std::vector<Bt> rotate_many(const Bt &a, const std::vector<std::pair<int, uint64_t>> &rots) {
+        const int l = a.level;
+        const long long N = C->N;
+        std::vector<Bt> outs;
+        for (size_t r = 0; r < rots.size(); ++r) {
+            const int kidx = rots[r].first;
+            REQUIRE(kidx >= 1 && kidx < (int)C->keys.size() && C->keys[kidx].lo, HE_ESTATE, "no such Galois key");
+            REQUIRE(C->key_gal[kidx] == (uint32_t)rots[r].second, HE_ESTATE, "key was generated for another Galois element");
+            Bt o = new_bt(a.cnt, l);
+            o.scale = a.scale;
+            outs.push_back(o);
+        }
+        if (rots.empty()) return outs;
+        const size_t m = C->arena.mark();
+        double *ext = modup(a.d + (long long)a.cap * N, 2LL * a.cap * N, a.cnt, l);
+        double *s0 = alloc_d((size_t)a.cnt * (l + 1) * N);
+        for (size_t r = 0; r < rots.size(); ++r) {
+            RotSet rs{};
+            rs.nr = 1;
+            rs.key[0] = C->keys[rots[r].first];
+            rs.g[0] = (uint32_t)rots[r].second;
+            rs.xorder = C->xorder_id;
+            rs.c0 = a.d;
+            rs.c0_ct = 2LL * a.cap * N;
+            rs.s0 = s0;
+            rs.s0_ct = (long long)(l + 1) * N;
+            rs.lq = l;
+            rs.c0_id = 0;
+            keyswitch(nullptr, 0, a.cnt, l, -1, outs[r].d, (long long)outs[r].cap * N,
+                      Addend{s0, (long long)(l + 1) * N, 0, 1}, Addend{nullptr, 0, 0, 0}, &rs, false, ext);
+        }
+        C->arena.release(m);
+        return outs;
+    }
+
     // both polynomials times a plaintext (NTT-domain residues, limb i at pt + i N),
     // declared scale times pscale, no rescale
     Bt mul_plain(const Bt &a, const double *pt, double pscale) {
@@ -641,6 +713,7 @@ struct Exec {
         rs.s0 = s0;
         rs.s0_ct = (long long)(l + 1) * N;
         rs.lq = l;
+        rs.c0_id = 1;
         keyswitch(x.d + (long long)x.cap * N, 2LL * x.cap * N, x.cnt, l, -1, y.d, (long long)y.cap * N,
                   Addend{s0, (long long)(l + 1) * N, 0, 1}, Addend{x.d, 2LL * x.cap * N, (long long)x.cap * N, 2},
                   &rs);
@@ -1069,9 +1142,20 @@ Bt lin_transform(Exec &X, const Bt &ct, const Diag &D, const Bsgs &P, double rho
     }
     std::map<int, Bt> baby;
     baby[0] = ct;
-    for (int b : P.babies()) {
-        const uint64_t g = rot_gal(C, (long long)b * P.h0);
-        baby[b] = X.rotate_gal(ct, gal_key_of(C, g), g);
+    if (C->boot_hoist) {
+        std::vector<std::pair<int, uint64_t>> rots;
+        for (int b : P.babies()) {
+            const uint64_t g = rot_gal(C, (long long)b * P.h0);
+            rots.push_back({gal_key_of(C, g), g});
+        }
+        std::vector<Bt> bs = X.rotate_many(ct, rots);
+        int i = 0;
+        for (int b : P.babies()) baby[b] = bs[i++];
+    } else {
+        for (int b : P.babies()) {
+            const uint64_t g = rot_gal(C, (long long)b * P.h0);
+            baby[b] = X.rotate_gal(ct, gal_key_of(C, g), g);
+        }
     }
     Bt acc;
     bool have = false;
@@ -1567,6 +1651,9 @@ void build_ctx(he_ctx *C, const he_params *prm) {
             o_xord[st[0]] = tb.i(order);
         }
     }
+    std::vector<int> xid(std::max(1, N / 256));
+    for (int B = 0; B < (int)xid.size(); ++B) xid[B] = B;
+    const size_t o_xid = tb.i(xid);
     HIPCHK(hipMalloc(&C->d_tab, tb.dv.size() * 8));
     HIPCHK(hipMalloc(&C->d_itab, tb.iv.size() * 4));
     HIPCHK(hipMemcpy(C->d_tab, tb.dv.data(), tb.dv.size() * 8, hipMemcpyHostToDevice));
@@ -1596,6 +1683,7 @@ void build_ctx(he_ctx *C, const he_params *prm) {
         C->ndall_prime[l] = I + o_nap[l];
     }
     for (const auto &kv : o_xord) C->xorder[kv.first] = I + kv.second;
+    C->xorder_id = I + o_xid;
     C->ext_prime.resize(L + 1);
     C->vinv.assign(L + 1, {}); C->qhat.assign(L + 1, {}); C->ndslot.assign(L + 1, {}); C->ndprime.assign(L + 1, {});
     for (int l = 0; l <= L; ++l) {
@@ -2572,6 +2660,11 @@ int he_set_option(he_ctx *C, int option, int64_t value) {
     if (!C) { g_err = "null context"; return HE_EINVAL; }
     if (option == HE_OPT_GRAPH) { C->use_graph = (int)value; return HE_OK; }
     if (option == HE_OPT_NTT_VARIANT) { C->ntt_variant = (int)value; return HE_OK; }
+    if (option == HE_OPT_BOOT_HOIST) {
+        C->boot_hoist = value != 0;
+        drop_graphs(C);  // captured graphs hold the other launch sequence
+        return HE_OK;
+    }
     g_err = "unknown option";
     return HE_EINVAL;
 }

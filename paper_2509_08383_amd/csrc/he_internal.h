@@ -173,6 +173,7 @@ struct RotSet {
     long long s0_ct;
     int lq;
     const int *xorder;  // the N/256 x-blocks in the orbit order of g[0] (device)
+    int c0_id;          // 1: s0 includes c0 itself (rotate-and-sum), 0: only the rotated copies
 };
 void launch_inner_product_rot(const DevTables &T, const double *ext, long long estride_b, long long estride_j,
                               double *acc0, double *acc1, long long astride, const RotSet &rs, int betaL,

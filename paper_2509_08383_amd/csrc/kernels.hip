@@ -504,7 +504,7 @@ __global__ __launch_bounds__(256) void k_inner_product_rot(DevTables T, const do
     for (int ct = 0; ct < cnt; ++ct) {
         const double *E = ext + ct * esb + (long long)t * T.N;
         const double *C0 = wsum ? rs.c0 + ct * rs.c0_ct + (long long)t * T.N : nullptr;
-        double s0 = 0.0, s1 = 0.0, g0 = wsum ? C0[x] : 0.0;
+        double s0 = 0.0, s1 = 0.0, g0 = wsum && rs.c0_id ? C0[x] : 0.0;
         for (int r = 0; r < rs.nr; ++r) {
             const unsigned src = aut_src((unsigned)x, rs.g[r], T.logN);
             if (wsum) g0 = red(g0 + C0[src], p, pinv);
@@ -580,7 +580,7 @@ __global__ __launch_bounds__(256) void k_inner_product_rot_reg(DevTables T, cons
         double s0 = 0.0, s1 = 0.0;
         if (wsum) {
             const double *C0 = rs.c0 + ct * rs.c0_ct + (long long)t * T.N;
-            double g0 = C0[x];
+            double g0 = rs.c0_id ? C0[x] : 0.0;
 #pragma unroll
             for (int r = 0; r < NR; ++r) g0 += C0[src[r]];
             rs.s0[ct * rs.s0_ct + (long long)t * T.N + x] = canon(g0, p, pinv);

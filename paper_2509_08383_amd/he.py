@@ -21,7 +21,7 @@ HE_NOISE_PRESCALED = 1
 HE_REFINE_GOLDSCHMIDT = 2
 HE_MASK_PAD = 4
 HE_BOOT = 8
-HE_OPT_GRAPH, HE_OPT_NTT_VARIANT = 1, 2
+HE_OPT_GRAPH, HE_OPT_NTT_VARIANT, HE_OPT_BOOT_HOIST = 1, 2, 3
 
 _c_u32p = ctypes.POINTER(ctypes.c_uint32)
 _c_u64p = ctypes.POINTER(ctypes.c_uint64)

@@ -155,6 +155,22 @@ def test_bootstrap_toy_round_trip(toy):
     assert err8 < 8e-3
 
 
+def test_bootstrap_hoisted_babies_equal_plain_rotations(toy):
+    """baby steps sharing one ModUp give the same ciphertext, word for word, as one
+    full key switch per baby step"""
+    from paper_2509_08383_amd import he
+    G, O = toy.G, toy.O
+    x = np.random.default_rng(11).uniform(-1, 1, O.slots)
+    g, _ = toy.enc(ckks.encode(x, O.N, O.Delta))
+    a = G.bootstrap(G.drop(g, 3), 1.0)
+    G.set_option(he.HE_OPT_BOOT_HOIST, 0)
+    try:
+        b = G.bootstrap(G.drop(g, 3), 1.0)
+    finally:
+        G.set_option(he.HE_OPT_BOOT_HOIST, 1)
+    assert np.array_equal(G.export(a), G.export(b))
+
+
 def test_bootstrap_rejects_bad_input(toy):
     from paper_2509_08383_amd import he
     G = toy.G
