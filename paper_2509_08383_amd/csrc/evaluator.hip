@@ -1200,46 +1200,91 @@ Bt boot_match(Exec &X, const Bt &x, int level, const std::vector<double> &scale)
     return X.drop(X.cmul(x, std::vector<double>(x.cnt, 1.0), scale, false), level);
 }
 
-// sum_k c_k T_k(z): T_2k = 2 T_k^2 - 1, T_{m+n} = 2 T_m T_n - T_{m-n} (m the largest
-// power of two below k); every kept term c_k T_k through a constant product at
-// s_out, all at the level a degree len(c) - 1 sum reaches; c_0 added last.  Terms
-// with |c_k| < 2^-40 (below the scale's noise) are left out and the basis stops at
-// the last kept one.
-Bt cheb_sum(Exec &X, const Bt &z, const std::vector<double> &c, double s_out) {
-    const int R = z.cnt;
-    int lg = 0;
-    while ((1 << lg) < (int)c.size()) ++lg;
-    const int lv = z.level - lg - 1;
-    std::vector<int> keep;
-    for (int k = 1; k < (int)c.size(); ++k)
-        if (std::fabs(c[k]) >= std::ldexp(1.0, -40)) keep.push_back(k);
-    REQUIRE(!keep.empty(), HE_EINVAL, "EvalMod polynomial is constant");
-    const int d = keep.back();
+// sum_k c_k T_k(z) by baby-step giant-step (Paterson-Stockmeyer in the Chebyshev
+// basis): babies T_1..T_7, giants T_8, T_16, .. (T_2k = 2 T_k^2 - 1, T_{m+n} = 2 T_m T_n -
+// T_{m-n}); a polynomial of degree >= 8 is split at the largest power of two m <= its
+// degree, p = q T_m + r with q_0 = c_m, q_j = 2 c_{m+j}, r_i = c_i - c_{2m-i}
+// (T_{m+j} = 2 T_m T_j - T_{m-j}), and the parts are evaluated recursively; a part of
+// degree < 8 is a sum of constant multiples of the babies.  Every part is produced at a
+// prescribed level and scale, so the sums need no alignment; the result lands at level
+// z.level - ceil(log2(deg + 1)) - 1 and scale s_out (the level a plain evaluation of the
+// basis reaches), with 11 ciphertext products at degree 31 instead of 30.  Terms with
+// |c_k| < 2^-40 (below the scale's noise) are left out.
+struct ChebEval {
+    Exec &X;
+    int R;
     std::map<int, Bt> Tk;
-    Tk[1] = z;
-    const std::vector<int64_t> two(R, 2);
-    const std::vector<double> m1(R, -1.0);
-    for (int k = 2; k <= d; ++k) {
+    double eps = std::ldexp(1.0, -40);
+    Bt basis(int k) {
+        auto it = Tk.find(k);
+        if (it != Tk.end()) return it->second;
+        const std::vector<int64_t> two(R, 2);
         int m = 1;
         while (2 * m <= k) m *= 2;
+        Bt out;
         if (m == k) {
-            const Bt &h = Tk.at(k / 2);
-            Tk[k] = X.add_const(X.mul_int(X.mul(h, h), two), m1);
+            Bt h = basis(k / 2);
+            out = X.add_const(X.mul_int(X.mul(h, h), two), std::vector<double>(R, -1.0));
         } else {
-            const int n = k - m;
-            const int lm = std::min(Tk.at(m).level, Tk.at(n).level);
-            Bt P = X.mul_int(X.mul(X.drop(Tk.at(m), lm), X.drop(Tk.at(n), lm)), two);
-            Tk[k] = X.add(P, boot_match(X, Tk.at(m - n), P.level, P.scale), -1);
+            Bt a = basis(m), b = basis(k - m), c = basis(2 * m - k);
+            const int lm = std::min(a.level, b.level);
+            Bt P = X.mul_int(X.mul(X.drop(a, lm), X.drop(b, lm)), two);
+            Bt c1 = X.drop(X.cmul(c, std::vector<double>(R, 1.0), P.scale, false), P.level);
+            out = X.add(P, c1, -1);
         }
+        Tk[k] = out;
+        return out;
     }
-    Bt acc;
-    bool have = false;
-    for (int k : keep) {
-        Bt t = X.drop(X.cmul(Tk.at(k), std::vector<double>(R, c[k]), std::vector<double>(R, s_out), false), lv);
-        if (have) X.add_inplace(acc, t);
-        else { acc = t; have = true; }
+    // sum_i a_i T_i at `level` and scale S; false if every non-constant term vanished
+    // (the value is then the constant a_0)
+    bool eval(const std::vector<double> &a, int level, double S, Bt &out) {
+        int deg = 0;
+        for (int i = 1; i < (int)a.size(); ++i)
+            if (std::fabs(a[i]) >= eps) deg = i;
+        if (deg == 0) return false;
+        const std::vector<double> sv(R, S);
+        if (deg < 8) {
+            bool have = false;
+            for (int i = 1; i <= deg; ++i) {
+                if (std::fabs(a[i]) < eps) continue;
+                Bt t = X.drop(X.cmul(basis(i), std::vector<double>(R, a[i]), sv, false), level);
+                if (have) X.add_inplace(out, t);
+                else { out = t; have = true; }
+            }
+            if (a[0] != 0.0) out = X.add_const(out, std::vector<double>(R, a[0]));
+            return true;
+        }
+        int m = 8;
+        while (2 * m <= deg) m *= 2;
+        std::vector<double> q(deg - m + 1), r(m);
+        q[0] = a[m];
+        for (int j = 1; j <= deg - m; ++j) q[j] = 2.0 * a[m + j];
+        for (int i = 0; i < m; ++i) r[i] = a[i] - (i >= 1 && 2 * m - i <= deg ? a[2 * m - i] : 0.0);
+        Bt G = basis(m);
+        REQUIRE(G.level >= level + 1, HE_EDEPTH, "Chebyshev evaluation: giant step too deep");
+        Bt QT, Rp;
+        Bt Gd = X.drop(G, level + 1);
+        const double sq = (S * (double)X.C->q[level + 1]) / G.scale[0];
+        if (eval(q, level + 1, sq, QT)) {
+            QT = X.mul(QT, Gd);
+            for (int c = 0; c < R; ++c) QT.scale[c] = S;  // (sq s_G) / q_{level+1} == S up to rounding
+        } else {
+            QT = X.drop(X.cmul(G, std::vector<double>(R, q[0]), sv, false), level);
+        }
+        if (eval(r, level, S, Rp)) out = X.add(QT, Rp);
+        else out = r[0] != 0.0 ? X.add_const(QT, std::vector<double>(R, r[0])) : QT;
+        return true;
     }
-    return X.add_const(acc, std::vector<double>(R, c[0]));
+};
+
+Bt cheb_sum(Exec &X, const Bt &z, const std::vector<double> &c, double s_out) {
+    int lg = 0;
+    while ((1 << lg) < (int)c.size()) ++lg;
+    ChebEval E{X, z.cnt};
+    E.Tk[1] = z;
+    Bt out;
+    REQUIRE(E.eval(c, z.level - lg - 1, s_out, out), HE_EINVAL, "EvalMod polynomial is constant");
+    return out;
 }
 
 std::vector<double> eval_mod_coeffs(const he_ctx *C, double Bk) {
