@@ -262,6 +262,44 @@ def test_cutmax_bootstrapped_full_size(full, seed):
 
 
 @pytest.mark.slow
+def test_cutmax_bootstrapped_graph_replays_equal_eager(full):
+    """the bootstrapped CutMax captured into a HIP graph (its encoded diagonals made
+    before the capture) and replayed, with eager work in between, equals the eager run
+    word for word"""
+    from paper_2509_08383_amd import he
+    from oracle.cutmax_fp64 import chebyshev_invsqrt
+    from workloads import llm_logits
+    G = full
+    coef = [list(chebyshev_invsqrt(VLO[t] / VHI[t], 3)) for t in range(3)]
+    cfg = he.CutmaxCfg(T=3, p=[3] * 3, c=[5.0] * 3, var_lo=VLO, var_hi=VHI, init_degree=3, init_coef=coef,
+                       sum_lo=1.0, sum_hi=3.0, gold_d=3, flags=he.HE_BOOT)
+    ct = G.encrypt(llm_logits(3))
+    ref = G.export(G.cutmax([ct], cfg)[0])
+    G.set_option(he.HE_OPT_GRAPH, 1)
+    try:
+        for i in range(3):
+            Z = G.cutmax([ct], cfg)[0]          # capture, then replays
+            G.bootstrap(G.drop(G.encrypt(np.zeros(G.slots)), 1), 1.0)   # eager work in between
+            assert np.array_equal(G.export(Z), ref), f"replay {i}"
+    finally:
+        G.set_option(he.HE_OPT_GRAPH, 0)
+
+
+@pytest.mark.slow
+def test_bootstrap_multi_ciphertext_handle(full):
+    """a handle of 4 ciphertexts (128256 values) is bootstrapped in one call"""
+    G = full
+    v = np.random.default_rng(21).uniform(-1, 1, 128256)
+    ct = G.encrypt(v)
+    assert ct.a == 4
+    out = G.bootstrap(G.drop(ct, 3), 1.0)
+    assert out.a == 4
+    err = float(np.abs(G.decrypt(out, v.size) - v).max())
+    say(f"[gpu] bootstrap of 4 ciphertexts: max err {err:.2e}")
+    assert err < 2e-3
+
+
+@pytest.mark.slow
 def test_cutmax_bootstrapped_batch(full):
     """4 requests (1 and 4 ciphertexts) bootstrapped together in one call"""
     from paper_2509_08383_amd import he
