@@ -236,32 +236,41 @@ void launch_automorph(const DevTables &T, const VecSet &out, const VecSet &in, u
 // out[c][poly][i] = sum_t pt_t[i] * x_t[c][poly][i] over limbs i < limbs, both
 // polynomials: the inner sum of a baby-step giant-step linear transform (each pt_t
 // an NTT-domain diagonal, x_t a rotated copy of the input) or, with one term, a
-// plaintext product.  Each plaintext word is loaded once for both polynomials;
+// plaintext product.  Each plaintext word is loaded once for both polynomials of every
+// ciphertext (the ciphertexts are a loop inside the thread);
 // |sum| <= n (p/2 + 2^44) < 2^52 for n <= kMaxLtTerms.
 __global__ __launch_bounds__(256) void k_lt_inner(double *__restrict__ out, long long oct, long long opoly, LtTerms tm,
-                                                  DevTables T) {
+                                                  int cnt, DevTables T) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= T.N) return;
-    const int i = blockIdx.y, c = blockIdx.z;
+    const int i = blockIdx.y;
     const double p = T.p[i], pinv = T.pinv[i];
     const long long w = (long long)i * T.N + x;
-    double a0 = 0.0, a1 = 0.0;
-    for (int t = 0; t < tm.n; ++t) {
-        const double pv = tm.pt[t][w];
-        const double *xp = tm.x[t] + c * tm.xct[t] + w;
-        a0 += mm(xp[0], pv, p, pinv);
-        a1 += mm(xp[tm.xpoly[t]], pv, p, pinv);
+    // every plaintext word once, kept in registers for all ciphertexts of the batch
+    double pv[kMaxLtTerms];
+#pragma unroll
+    for (int t = 0; t < kMaxLtTerms; ++t) pv[t] = t < tm.n ? tm.pt[t][w] : 0.0;
+    for (int c = 0; c < cnt; ++c) {
+        double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+        for (int t = 0; t < kMaxLtTerms; ++t) {
+            if (t < tm.n) {
+                const double *xp = tm.x[t] + c * tm.xct[t] + w;
+                a0 += mm(xp[0], pv[t], p, pinv);
+                a1 += mm(xp[tm.xpoly[t]], pv[t], p, pinv);
+            }
+        }
+        double *o = out + c * oct + w;
+        o[0] = canon(a0, p, pinv);
+        o[opoly] = canon(a1, p, pinv);
     }
-    double *o = out + c * oct + w;
-    o[0] = canon(a0, p, pinv);
-    o[opoly] = canon(a1, p, pinv);
 }
 void launch_lt_inner(const DevTables &T, double *out, long long oct, long long opoly, const LtTerms &tm, int cnt,
                      int limbs, hipStream_t s) {
     if (cnt <= 0 || tm.n <= 0) return;
     // each term's plaintext limb once, its two ciphertext polynomials per ciphertext, two words out
     kprof_set_bytes(8.0 * T.N * limbs * ((double)tm.n * (1.0 + 2.0 * cnt) + 2.0 * cnt));
-    KL("k_lt_inner", k_lt_inner, dim3((T.N + 255) / 256, limbs, cnt), dim3(256), 0, s, out, oct, opoly, tm, T);
+    KL("k_lt_inner", k_lt_inner, dim3((T.N + 255) / 256, limbs), dim3(256), 0, s, out, oct, opoly, tm, cnt, T);
 }
 
 // ------------------------------------------------------------ key switching
