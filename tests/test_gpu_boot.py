@@ -320,6 +320,47 @@ def test_cutmax_bootstrapped_batch(full):
 
 
 @pytest.mark.slow
+def test_cutmax_bootstrapped_masked_padding(full):
+    """HE_BOOT with HE_MASK_PAD: the pad tracker is bootstrapped with the logits; the first
+    32000 outputs match the FP64 mirror run on the 32000 logits alone"""
+    from paper_2509_08383_amd import he
+    from oracle.cutmax_fp64 import MirrorCfg, chebyshev_invsqrt, cutmax_mirror
+    from workloads import llm_logits
+    G = full
+    x = llm_logits(9)
+    coef = [list(chebyshev_invsqrt(VLO[t] / VHI[t], 3)) for t in range(3)]
+    cfg = he.CutmaxCfg(T=3, p=[3] * 3, c=[5.0] * 3, var_lo=VLO, var_hi=VHI, init_degree=3, init_coef=coef,
+                       sum_lo=1.0, sum_hi=3.0, gold_d=3, flags=he.HE_BOOT | he.HE_MASK_PAD)
+    Z = G.cutmax([G.encrypt(x, pad=float("nan"))], cfg)[0]
+    z = G.decrypt(Z, x.size)
+    mc = MirrorCfg(T=3, p=[3] * 3, c=[5.0] * 3, v_hi=VHI, v_lo=VLO, coef=coef, B=3.0 * x.size, gold_d=3,
+                   sum_lo=1.0 * x.size)
+    err = float(np.abs(z - cutmax_mirror(x, mc)).max())
+    say(f"[gpu] bootstrapped masked CutMax: |z - mirror(x)| = {err:.2e}")
+    assert err < 1e-3
+    assert int(np.argmax(z)) == int(np.argmax(x))
+
+
+@pytest.mark.slow
+def test_topp_sample_bootstrapped(full):
+    """one-shot nucleus sampling (Alg. 3) through the bootstrapped CutMax: the decrypted
+    one-hot picks argmax(x + tau G) for every request"""
+    from paper_2509_08383_amd import he
+    from oracle.cutmax_fp64 import beta_alpha, beta_noise
+    from workloads import llm_logits, uniform_noise
+    G = full
+    tau = 0.8
+    coef_cfg = dict(T=3, p=[3] * 3, c=[5.0] * 3, var_lo=VLO, var_hi=VHI, init_degree=3, sum_lo=1.0, sum_hi=3.0,
+                    gold_d=3, flags=he.HE_BOOT | he.HE_NOISE_PRESCALED)
+    cfg = he.CutmaxCfg(**coef_cfg)
+    xs = [llm_logits(30 + r) for r in range(2)]
+    gs = [beta_noise(uniform_noise(70 + r, x.size), beta_alpha(0.9)) for r, x in enumerate(xs)]
+    Z = G.topp_sample([G.encrypt(x) for x in xs], [G.encrypt(tau * g) for g in gs], 0.9, tau, cfg)
+    for x, g, z in zip(xs, gs, Z):
+        assert int(np.argmax(G.decrypt(z, x.size))) == int(np.argmax(x + tau * g))
+
+
+@pytest.mark.slow
 def test_bootstrap_full_size_ratio12():
     """the oracle's default ratio 2^-12: noise-bound precision (the CPU oracle measures
     1.8e-2 on the same parameters), 64x worse than at 2^-6"""
