@@ -219,6 +219,7 @@ def boot_bench(he, args, x):
         Zb = bctx.cutmax([ctb], cfg)[0]
     bctx.sync()
     cm_ms = (time.perf_counter() - t0) * 1e3 / reps
+    cm_dev = bctx.last_cutmax_ms()
     ok = int(np.argmax(bctx.decrypt(Zb, x.size))) == int(np.argmax(x))
     log(f"[bench] bootstrapped CutMax {cm_ms:.2f} ms, argmax ok={ok}")
     zlevel = Zb.level
@@ -239,7 +240,7 @@ def boot_bench(he, args, x):
                      "sparse ternary secret h=192",
            "levels_used": bc.levels(), "ratio_bits": bc.ratio_bits, "bootstrap_ms": boot_ms,
            "bootstrap_max_err_bound1": err, "out_level": out.level,
-           "cutmax_T3_bootstrapped_ms": cm_ms, "cutmax_device_ms": bctx.last_cutmax_ms(),
+           "cutmax_T3_bootstrapped_ms": cm_ms, "cutmax_device_ms": cm_dev,
            "bootstraps_per_cutmax": 2, "cutmax_argmax_ok": bool(ok), "cutmax_out_level": zlevel,
            "batch16_ms": per_batch * 1e3, "batch16_argmaxes_per_s": 16.0 / per_batch, "batch16_argmax_ok": okb,
            "kernels": kern}

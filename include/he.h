@@ -275,7 +275,9 @@ typedef struct {
  * (rotation amounts that already have a key keep it; the others take the next
  * free key indices in ascending order of amount, then the conjugation key) and
  * fixes the configuration.  Encoded diagonals are built on first use and kept in
- * device memory.  EINVAL for a configuration whose levels exceed the chain. */
+ * device memory.  EINVAL for a configuration whose levels exceed the chain, or
+ * whose CoeffToSlot and EvalMod levels (the top n_cts + 2 + ceil(log2(cheb_deg +
+ * 1)) + r primes) are not within one bit of log2_s_eval (see he_params.n_hi). */
 int he_boot_setup(he_ctx *ctx, const he_boot_cfg *cfg);
 
 /* Bootstrap every ciphertext of `in` (level >= 1, real slot values with

@@ -879,8 +879,9 @@ struct CutmaxCfg {
 // inverse square root): the factor by which |z - 1| can exceed its exact bound
 double guess_overshoot(const std::vector<double> &g, double u_lo, int newton) {
     double mx = 0.0;
-    for (int i = 0; i <= 4000; ++i) {
-        const double u = u_lo * std::pow(1.0 / u_lo, i / 4000.0);
+    const double step = std::pow(1.0 / u_lo, 1.0 / 4000.0);
+    double u = u_lo;
+    for (int i = 0; i <= 4000; ++i, u = std::min(1.0, u * step)) {
         double y = 0.0;
         for (int k = (int)g.size() - 1; k >= 0; --k) y = y * u + g[k];
         for (int it = 0; it < newton; ++it) y = 1.5 * y - 0.5 * u * y * y * y;
@@ -1393,6 +1394,17 @@ void boot_setup(he_ctx *C, const he_boot_cfg *cfg) {
     B.n_cts = (int)cfg->n_cts; B.n_stc = (int)cfg->n_stc; B.K = (int)cfg->K; B.ratio_bits = (int)cfg->ratio_bits;
     B.cheb_deg = (int)cfg->cheb_deg; B.r = (int)cfg->r; B.s_eval = std::ldexp(1.0, 0) * std::pow(2.0, cfg->log2_s_eval);
     REQUIRE(boot_levels(C) <= C->L - 1, HE_EINVAL, "bootstrap needs more levels than the chain has");
+    // CoeffToSlot and EvalMod rescale by the primes of their levels while keeping the
+    // scale near s_eval, so those primes must have about log2(s_eval) bits
+    {
+        int lg = 0;
+        while ((1 << lg) < B.cheb_deg + 1) ++lg;
+        const int top = B.n_cts + 1 + lg + 1 + B.r;
+        for (int l = C->L; l > C->L - top; --l)
+            REQUIRE(std::fabs(std::log2((double)C->q[l]) - cfg->log2_s_eval) < 1.0, HE_EINVAL,
+                    "the primes of the levels CoeffToSlot and EvalMod use must have about log2_s_eval bits "
+                    "(a chain with n_hi >= n_cts + 2 + ceil(log2(cheb_deg + 1)) + r primes of that size)");
+    }
     B.cts = bt_groups(C->slots, B.n_cts, true);
     B.stc = bt_groups(C->slots, B.n_stc, false);
     B.cts_plan.clear();
@@ -1978,8 +1990,9 @@ CutmaxCfg parse_cfg(he_ctx *C, const he_cutmax_cfg *cfg) {
     cf.sum_lo = cfg->sum_lo;
     cf.sum_hi = cfg->sum_hi;
     cf.boot = (cfg->flags & HE_BOOT) != 0;
+    // (host work on every call, so only where a bootstrap bound needs it)
     for (int t = 0; t < cf.T; ++t)
-        cf.guess_max.push_back(guess_overshoot(cf.coef[t], cf.vlo[t] / cf.vhi[t], cf.newton));
+        cf.guess_max.push_back(cf.boot ? guess_overshoot(cf.coef[t], cf.vlo[t] / cf.vhi[t], cf.newton) : 1.0);
     (void)C;
     return cf;
 }

@@ -171,6 +171,15 @@ def test_bootstrap_hoisted_babies_equal_plain_rotations(toy):
     assert np.array_equal(G.export(a), G.export(b))
 
 
+def test_boot_setup_rejects_a_chain_without_wide_primes():
+    """CoeffToSlot and EvalMod keep their scale near 2^48: a chain of 30-bit primes is refused"""
+    from paper_2509_08383_amd import he
+    G = he.Context(he.TOY)
+    with pytest.raises(he.HeError):
+        G.boot_setup(he.BootCfg())
+    G.close()
+
+
 def test_bootstrap_rejects_bad_input(toy):
     from paper_2509_08383_amd import he
     G = toy.G
