@@ -87,3 +87,18 @@ def test_plain_c_client_recovers_the_argmax():
     assert r.returncode == 0, (r.returncode, r.stdout, r.stderr)
     got, want = r.stdout.split()[1:3]
     assert got == want
+
+
+@pytest.mark.gpu
+def test_plain_c_client_bootstraps():
+    """the same C program drives he_boot_setup and he_bootstrap through the ABI: 2048 values
+    in [-1, 1] come back from level 3 to level 3 (19 - 16) within 1e-3"""
+    import subprocess
+    exe = os.path.join(ROOT, "tests", "c_client", "cutmax_client")
+    if not os.path.exists(exe):
+        pytest.skip("the C client is built by __graft_entry__.build()")
+    r = subprocess.run([exe, "boot"], capture_output=True, text=True, timeout=120)
+    print(r.stdout, r.stderr)
+    assert r.returncode == 0, (r.returncode, r.stdout, r.stderr)
+    f = r.stdout.split()
+    assert f[0] == "boot" and float(f[2]) < 1e-3 and f[4] == "3"

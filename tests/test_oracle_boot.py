@@ -169,3 +169,47 @@ def test_bootstrap_round_trip(toy):
     c = np.full(O.slots, 0.75)
     out = B.bootstrap(O, O.drop(O.encrypt(c), 2), 1.0, cfg, keys)
     assert np.abs(O.decrypt(out) - c).max() < 1e-3
+
+
+def _is_prime(n: int) -> bool:
+    """deterministic Miller-Rabin for n < 3.3e24 (bases 2..41)"""
+    if n < 2:
+        return False
+    for p in (2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41):
+        if n % p == 0:
+            return n == p
+    d, r = n - 1, 0
+    while d % 2 == 0:
+        d //= 2
+        r += 1
+    for a in (2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41):
+        x = pow(a, d, n)
+        if x in (1, n - 1):
+            continue
+        for _ in range(r - 1):
+            x = x * x % n
+            if x == n - 1:
+                break
+        else:
+            return False
+    return True
+
+
+def test_mixed_chain_primes():
+    """q0 of q0_bits, q1..q_{L-n_hi} of q_bits, the top n_hi of hi_bits, then P: each the
+    first prime 2^b - k 2N + 1 (k = 1, 2, ..) not taken before"""
+    O = ckks.Oracle(TOY_BOOT)
+    N, L = O.N, O.L
+    bits = [TOY_BOOT.q0_bits] + [TOY_BOOT.hi_bits if i >= TOY_BOOT.n_q - TOY_BOOT.n_hi else TOY_BOOT.q_bits
+                                 for i in range(1, TOY_BOOT.n_q)] + [TOY_BOOT.p_bits] * O.alpha
+    taken = []
+    for q, b in zip(O.q, bits):
+        k = 1
+        while True:
+            c = 2 ** b - k * 2 * N + 1
+            if c not in taken and _is_prime(c):
+                break
+            k += 1
+        assert q == c, (q, c, b)
+        taken.append(q)
+    assert sum(1 for q in O.q[1:L + 1] if q.bit_length() == 48) == TOY_BOOT.n_hi
