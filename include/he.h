@@ -282,7 +282,9 @@ int he_boot_setup(he_ctx *ctx, const he_boot_cfg *cfg);
 
 /* Bootstrap every ciphertext of `in` (level >= 1, real slot values with
  * |v| <= bound): out receives them at level L - (levels used) with scale Delta.
- * ESTATE without he_boot_setup. */
+ * The error grows in proportion to the bound, which is rounded up to a power of
+ * 2^(1/8) (each rounded bound keeps one set of encoded SlotToCoeff diagonals in
+ * device memory).  ESTATE without he_boot_setup. */
 int he_bootstrap(he_ctx *ctx, const he_ct *in, double bound, he_ct **out);
 
 /* Bootstrap primitives (single ciphertexts), each bit-exact against a plain

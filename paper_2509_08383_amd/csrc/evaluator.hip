@@ -557,7 +557,11 @@ struct Exec {
     }
 
     // automorphism X -> X^g on both polynomials, key switch of sigma(c1) with key
-    // kidx: (sigma(c0) + ks0, ks1) [+ into]
+    // kidx: (sigma(c0) + ks0, ks1) [+ into].  The automorphism acts inside the key
+    // switch: c1 is extended (ModUp) as it is, the key products gather the extended
+    // NTT-domain digits at the automorphism's source positions (the centred extension
+    // commutes with the automorphism), and the ModDown epilogue adds sigma(c0), gathered
+    // by the same key-product kernel; no separate automorphism pass.
     Bt rotate_gal(const Bt &a, int kidx, uint64_t g, Bt *into = nullptr) {
         REQUIRE(kidx >= 1 && kidx < (int)C->keys.size() && C->keys[kidx].lo, HE_ESTATE, "no such Galois key");
         REQUIRE(C->key_gal[kidx] == (uint32_t)g, HE_ESTATE, "key was generated for another Galois element");
@@ -574,14 +578,23 @@ struct Exec {
             o.scale = a.scale;
         }
         const size_t m = C->arena.mark();
-        double *sig = alloc_d((size_t)a.cnt * 2 * (l + 1) * N);
-        if (go())
-            launch_automorph(T, VecSet{sig, a.cnt * 2 * (l + 1), l + 1, (long long)(l + 1) * N, nullptr, nullptr},
-                             vs_all(a), g, s);
+        double *ext = modup(a.d + (long long)a.cap * N, 2LL * a.cap * N, a.cnt, l);
+        double *s0 = alloc_d((size_t)a.cnt * (l + 1) * N);
+        RotSet rs{};
+        rs.nr = 1;
+        rs.key[0] = C->keys[kidx];
+        rs.g[0] = (uint32_t)g;
+        rs.xorder = C->xorder_id;
+        rs.c0 = a.d;
+        rs.c0_ct = 2LL * a.cap * N;
+        rs.s0 = s0;
+        rs.s0_ct = (long long)(l + 1) * N;
+        rs.lq = l;
+        rs.c0_id = 0;
         Addend acc{nullptr, 0, 0, 0};
         if (into) acc = Addend{into->d, 2LL * into->cap * N, (long long)into->cap * N, 3};
-        keyswitch(sig + (l + 1) * N, 2LL * (l + 1) * N, a.cnt, l, kidx, o.d, (long long)o.cap * N,
-                  Addend{sig, 2LL * (l + 1) * N, (long long)(l + 1) * N, 1}, acc);
+        keyswitch(nullptr, 0, a.cnt, l, -1, o.d, (long long)o.cap * N, Addend{s0, (long long)(l + 1) * N, 0, 1}, acc,
+                  &rs, false, ext);
         C->arena.release(m);
         return o;
     }
@@ -1327,6 +1340,10 @@ Bt bootstrap(Exec &X, const Bt &ct, double bound) {
     REQUIRE(bound > 0 && std::isfinite(bound), HE_EINVAL, "bootstrap bound must be positive");
     const int R = ct.cnt, N = C->N;
     const double q0 = (double)C->q[0], Bk = boot_bk(C);
+    // the bound rounded up to a power of 2^(1/8): the first SlotToCoeff group's encoded
+    // diagonals depend on it, so the cache of encoded diagonals holds a few sets instead
+    // of one per distinct bound (at most 9 % more noise than the exact bound)
+    bound = std::exp2(std::ceil(std::log2(bound) * 8.0) / 8.0);
     const double s_in = q0 * std::ldexp(1.0, -C->boot.ratio_bits) / bound;
     // to level 0 at scale s_in; the raised plaintext m + q_0 I read at scale q_0 Bk
     Bt c0 = X.cmul(X.drop(ct, 1), std::vector<double>(R, 1.0), std::vector<double>(R, s_in), false);
