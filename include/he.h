@@ -260,7 +260,11 @@ int he_drop(he_ctx *ctx, const he_ct *a, uint32_t level, he_ct **out);
  * overflow of a sparse secret stays below this bound with overwhelming
  * probability); ratio_bits: the message enters EvalMod at q_0 2^-ratio_bits per
  * unit of `bound`, which sets the sine's linearisation error; log2_s_eval: scale of
- * the EvalMod ciphertexts (use the bit size of the primes it runs on). */
+ * the EvalMod ciphertexts (use the bit size of the primes it runs on).
+ * correct_bits = c > 0: every bootstrap runs twice, the second pass on the first's
+ * residual x - BTS(x) under the bound bound 2^-c, and adds it back (the error
+ * shrinks by about 2^c at twice the time; c must leave the first pass's error below
+ * bound 2^-c, and the input must sit below the output level). */
 typedef struct {
     uint32_t n_cts;
     uint32_t n_stc;
@@ -269,6 +273,7 @@ typedef struct {
     uint32_t cheb_deg;
     uint32_t r;
     double log2_s_eval;
+    uint32_t correct_bits;
 } he_boot_cfg;
 
 /* Bootstrap set-up: generates the Galois keys the two linear transforms use

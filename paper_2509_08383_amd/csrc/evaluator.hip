@@ -180,7 +180,7 @@ struct he_ctx {
     // level, plaintext scale bits, multiplier bits)
     struct Boot {
         bool ready = false;
-        int n_cts = 3, n_stc = 3, K = 0, ratio_bits = 12, cheb_deg = 31, r = 3;
+        int n_cts = 3, n_stc = 3, K = 0, ratio_bits = 12, cheb_deg = 31, r = 3, correct_bits = 0;
         double s_eval = 0;
         std::vector<he::Diag> cts, stc;
         std::vector<he::Bsgs> cts_plan, stc_plan;
@@ -1333,7 +1333,7 @@ double boot_bk(const he_ctx *C) {
 
 // a batch at level >= 1 with real slot values |v| <= bound, back at level
 // L - boot_levels with the same values at scale Delta
-Bt bootstrap(Exec &X, const Bt &ct, double bound) {
+Bt bootstrap_pass(Exec &X, const Bt &ct, double bound) {
     he_ctx *C = X.C;
     REQUIRE(C->boot.ready, HE_ESTATE, "bootstrap needs he_boot_setup");
     REQUIRE(ct.level >= 1, HE_EDEPTH, "bootstrap input needs a level to spare");
@@ -1385,6 +1385,23 @@ Bt bootstrap(Exec &X, const Bt &ct, double bound) {
     return Z;
 }
 
+// With correct_bits = c > 0, a second pass bootstraps the first pass's error and removes
+// it: b1 = BTS(x) = x + e1; d = x - b1 = -e1 (|e1| well below bound 2^-c); b2 = BTS(d) =
+// -e1 + e2 with e2 in proportion to bound 2^-c; b1 + b2 = x + e2.
+Bt bootstrap(Exec &X, const Bt &ct, double bound) {
+    he_ctx *C = X.C;
+    if (C->boot.correct_bits <= 0) return bootstrap_pass(X, ct, bound);
+    const int lb = C->L - boot_levels(C);
+    REQUIRE(ct.level >= 1 && ct.level < lb, HE_EDEPTH,
+            "error-corrected bootstrap needs an input level between 1 and the output level - 1");
+    Bt b1 = bootstrap_pass(X, ct, bound);
+    // b1 at the input's scale and level (one constant product), then the residual
+    Bt b1s = X.drop(X.cmul(b1, std::vector<double>(ct.cnt, 1.0), ct.scale, false), ct.level);
+    Bt d = X.add(ct, b1s, -1);
+    Bt b2 = bootstrap_pass(X, d, bound * std::ldexp(1.0, -C->boot.correct_bits));
+    return X.add(b1, b2);
+}
+
 // every rotation amount (mod slots) of the two linear transforms, ascending
 std::vector<int> boot_rotations(const he_ctx *C) {
     std::vector<int> r;
@@ -1410,6 +1427,8 @@ void boot_setup(he_ctx *C, const he_boot_cfg *cfg) {
     B.ready = false;
     B.n_cts = (int)cfg->n_cts; B.n_stc = (int)cfg->n_stc; B.K = (int)cfg->K; B.ratio_bits = (int)cfg->ratio_bits;
     B.cheb_deg = (int)cfg->cheb_deg; B.r = (int)cfg->r; B.s_eval = std::ldexp(1.0, 0) * std::pow(2.0, cfg->log2_s_eval);
+    REQUIRE(cfg->correct_bits <= 30, HE_EINVAL, "correct_bits at most 30");
+    B.correct_bits = (int)cfg->correct_bits;
     REQUIRE(boot_levels(C) <= C->L - 1, HE_EINVAL, "bootstrap needs more levels than the chain has");
     // CoeffToSlot and EvalMod rescale by the primes of their levels while keeping the
     // scale near s_eval, so those primes must have about log2(s_eval) bits

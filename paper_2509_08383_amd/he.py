@@ -47,7 +47,7 @@ class _Params(ctypes.Structure):
 class _BootCfg(ctypes.Structure):
     _fields_ = [("n_cts", ctypes.c_uint32), ("n_stc", ctypes.c_uint32), ("K", ctypes.c_uint32),
                 ("ratio_bits", ctypes.c_uint32), ("cheb_deg", ctypes.c_uint32), ("r", ctypes.c_uint32),
-                ("log2_s_eval", ctypes.c_double)]
+                ("log2_s_eval", ctypes.c_double), ("correct_bits", ctypes.c_uint32)]
 
 
 class _Cfg(ctypes.Structure):
@@ -160,6 +160,7 @@ class BootCfg:
     cheb_deg: int = 31
     r: int = 3
     log2_s_eval: float = 48.0
+    correct_bits: int = 0   # > 0: a second pass removes the first pass's error (bound 2^-correct_bits)
 
     def levels(self) -> int:
         import math
@@ -387,7 +388,8 @@ class Context:
 
     # bootstrapping -------------------------------------------------------------
     def boot_setup(self, cfg: BootCfg):
-        c = _BootCfg(cfg.n_cts, cfg.n_stc, cfg.K, cfg.ratio_bits, cfg.cheb_deg, cfg.r, float(cfg.log2_s_eval))
+        c = _BootCfg(cfg.n_cts, cfg.n_stc, cfg.K, cfg.ratio_bits, cfg.cheb_deg, cfg.r, float(cfg.log2_s_eval),
+                     cfg.correct_bits)
         _check(lib().he_boot_setup(self.h, ctypes.byref(c)))
 
     def bootstrap(self, a, bound: float):
