@@ -171,6 +171,28 @@ def test_bootstrap_hoisted_babies_equal_plain_rotations(toy):
     assert np.array_equal(G.export(a), G.export(b))
 
 
+@pytest.mark.parametrize("groups", [1, 2])
+def test_bootstrap_group_counts(groups):
+    """CoeffToSlot/SlotToCoeff merged into 1 or 2 groups of butterfly stages (2047 or up to
+    127 diagonals per group at 2048 slots; with one group a giant step sums 64 plaintext
+    terms in chunks of 16): the values come back within the method's precision for that
+    split (the CPU oracle measures 6.3e-3 with one group, whose sums over 2047 rotated
+    diagonals collect far more key-switch noise, and 2.3e-4 with two)"""
+    from paper_2509_08383_amd import he
+    G = he.Context(he.TOY_BOOT)
+    try:
+        cfg = he.BootCfg(n_cts=groups, n_stc=groups)
+        G.boot_setup(cfg)
+        x = np.random.default_rng(40 + groups).uniform(-1, 1, G.slots)
+        out = G.bootstrap(G.drop(G.encrypt(x), 2), 1.0)
+        assert out.level == G.L - cfg.levels()
+        err = float(np.abs(G.decrypt(out) - x).max())
+        say(f"[gpu] bootstrap toy with {groups} group(s): max err {err:.2e}")
+        assert err < {1: 2e-2, 2: 1e-3}[groups], err
+    finally:
+        G.close()
+
+
 def test_boot_setup_rejects_a_chain_without_wide_primes():
     """CoeffToSlot and EvalMod keep their scale near 2^48: a chain of 30-bit primes is refused"""
     from paper_2509_08383_amd import he
