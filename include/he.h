@@ -332,9 +332,10 @@ int he_profile_end(he_ctx *ctx, char *buf, size_t cap);
 
 /* Options: HE_OPT_GRAPH (capture he_cutmax in a HIP graph and replay it for
  * repeated calls of the same shape), HE_OPT_NTT_VARIANT (0 = autotune, k > 0
- * forces variant k), HE_OPT_BOOT_HOIST (1, the default: the baby steps of a
- * bootstrap linear transform share one ModUp; 0: one full key switch each; the
- * results are equal word for word). */
+ * forces variant k), HE_OPT_BOOT_HOIST (2, the default: the baby steps of a
+ * bootstrap linear transform share one ModUp and the rotated giant-step sums share
+ * one ModDown per 7 rotations; 1: only the baby steps are hoisted, equal word for
+ * word to 0: one full key switch per rotation). */
 #define HE_OPT_GRAPH 1
 #define HE_OPT_NTT_VARIANT 2
 #define HE_OPT_BOOT_HOIST 3

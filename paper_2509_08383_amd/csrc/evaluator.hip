@@ -168,7 +168,7 @@ struct he_ctx {
     std::map<int, int> rot_key;     // rotation amount -> key index
     std::map<int, const int *> xorder;  // smallest amount of a hoisted step -> x-block orbit order
     const int *xorder_id = nullptr;     // x-blocks in natural order (any rotation)
-    int boot_hoist = 1;                 // bootstrap baby steps share one ModUp
+    int boot_hoist = 2;                 // 1: bootstrap baby steps share one ModUp; 2: also one ModDown per giant-step sum
     std::vector<uint32_t> key_gal;  // key index -> Galois element (0 for relinearisation)
     // graph cache keyed by a signature of the call
     std::map<std::string, hipGraphExec_t> graphs;
@@ -636,6 +636,50 @@ struct Exec {
         }
         C->arena.release(m);
         return outs;
+    }
+
+    // sum_r rot_{g_r}(x_r) [+ x0] over ciphertexts x_r of one level: every x_r extended
+    // once (ModUp), the key products of all rotations summed in one pass (each gathering
+    // its own extended digits), one ModDown whose epilogue adds sum_r sigma_r(c0_r) and x0
+    Bt rotate_sum_multi(const std::vector<Bt> &xs, const std::vector<std::pair<int, uint64_t>> &rots, const Bt *x0) {
+        REQUIRE(!xs.empty() && xs.size() == rots.size() && xs.size() <= 7, HE_EINVAL, "rotate_sum_multi: 1..7 rotations");
+        const Bt &a = xs[0];
+        const int l = a.level;
+        const long long N = C->N;
+        for (const Bt &x : xs)
+            REQUIRE(x.level == l && x.cnt == a.cnt && x.cap == a.cap, HE_ESTATE, "rotate_sum_multi: shapes differ");
+        for (int c = 0; c < a.cnt; ++c) {
+            for (const Bt &x : xs)
+                REQUIRE(std::fabs(x.scale[c] - a.scale[c]) <= 1e-9 * a.scale[c], HE_ERANGE, "rotate_sum_multi: scales");
+            if (x0) REQUIRE(std::fabs(x0->scale[c] - a.scale[c]) <= 1e-9 * a.scale[c], HE_ERANGE, "rotate_sum_multi: scales");
+        }
+        if (x0) REQUIRE(x0->level == l && x0->cnt == a.cnt, HE_ESTATE, "rotate_sum_multi: addend shape");
+        Bt o = new_bt(a.cnt, l);
+        o.scale = a.scale;
+        const size_t m = C->arena.mark();
+        RotSet rs{};
+        rs.nr = (int)xs.size();
+        rs.multi = 1;
+        rs.xorder = C->xorder_id;
+        rs.c0_ct = 2LL * a.cap * N;
+        rs.s0 = alloc_d((size_t)a.cnt * (l + 1) * N);
+        rs.s0_ct = (long long)(l + 1) * N;
+        rs.lq = l;
+        for (size_t r = 0; r < xs.size(); ++r) {
+            const int kidx = rots[r].first;
+            REQUIRE(kidx >= 1 && kidx < (int)C->keys.size() && C->keys[kidx].lo, HE_ESTATE, "no such Galois key");
+            REQUIRE(C->key_gal[kidx] == (uint32_t)rots[r].second, HE_ESTATE, "key was generated for another Galois element");
+            rs.key[r] = C->keys[kidx];
+            rs.g[r] = (uint32_t)rots[r].second;
+            rs.ext_r[r] = modup(xs[r].d + (long long)xs[r].cap * N, 2LL * xs[r].cap * N, a.cnt, l);
+            rs.c0_r[r] = xs[r].d;
+        }
+        Addend add0{nullptr, 0, 0, 0};
+        if (x0) add0 = Addend{x0->d, 2LL * x0->cap * N, (long long)x0->cap * N, 3};
+        keyswitch(nullptr, 0, a.cnt, l, -1, o.d, (long long)o.cap * N, Addend{rs.s0, (long long)(l + 1) * N, 0, 1}, add0,
+                  &rs, false, rs.ext_r[0]);
+        C->arena.release(m);
+        return o;
     }
 
     // both polynomials times a plaintext (NTT-domain residues, limb i at pt + i N),
@@ -1173,6 +1217,8 @@ Bt lin_transform(Exec &X, const Bt &ct, const Diag &D, const Bsgs &P, double rho
     }
     Bt acc;
     bool have = false;
+    std::vector<Bt> rotated;                         // giant sums still to rotate (shared ModDown)
+    std::vector<std::pair<int, uint64_t>> rot_keys;
     for (const auto &at : P.terms) {
         const long long shift = ((long long)at.first * P.B * P.h0) % s;
         Bt inner = X.new_bt(ct.cnt, l);
@@ -1196,6 +1242,12 @@ Bt lin_transform(Exec &X, const Bt &ct, const Diag &D, const Bsgs &P, double rho
                 launch_lt_inner(X.T, part.d, 2LL * part.cap * N, (long long)part.cap * N, tm, ct.cnt, l + 1, X.s);
             if (j0) X.add_inplace(inner, part);
         }
+        if (shift && C->boot_hoist >= 2) {
+            const uint64_t g = rot_gal(C, shift);
+            rotated.push_back(inner);
+            rot_keys.push_back({gal_key_of(C, g), g});
+            continue;
+        }
         if (shift) {
             const uint64_t g = rot_gal(C, shift);
             if (have) X.rotate_gal(inner, gal_key_of(C, g), g, &acc);
@@ -1204,6 +1256,14 @@ Bt lin_transform(Exec &X, const Bt &ct, const Diag &D, const Bsgs &P, double rho
             if (have) X.add_inplace(acc, inner);
             else acc = inner;
         }
+        have = true;
+    }
+    // the rotated giant sums, up to 7 per key switch, one ModDown each
+    for (size_t i = 0; i < rotated.size(); i += 7) {
+        const size_t e = std::min(rotated.size(), i + 7);
+        std::vector<Bt> xs(rotated.begin() + i, rotated.begin() + e);
+        std::vector<std::pair<int, uint64_t>> ks(rot_keys.begin() + i, rot_keys.begin() + e);
+        acc = X.rotate_sum_multi(xs, ks, have ? &acc : nullptr);
         have = true;
     }
     return X.rescale(acc);
@@ -2755,7 +2815,7 @@ int he_set_option(he_ctx *C, int option, int64_t value) {
     if (option == HE_OPT_GRAPH) { C->use_graph = (int)value; return HE_OK; }
     if (option == HE_OPT_NTT_VARIANT) { C->ntt_variant = (int)value; return HE_OK; }
     if (option == HE_OPT_BOOT_HOIST) {
-        C->boot_hoist = value != 0;
+        C->boot_hoist = value <= 0 ? 0 : (value >= 2 ? 2 : 1);
         drop_graphs(C);  // captured graphs hold the other launch sequence
         return HE_OK;
     }

@@ -174,6 +174,11 @@ struct RotSet {
     int lq;
     const int *xorder;  // the N/256 x-blocks in the orbit order of g[0] (device)
     int c0_id;          // 1: s0 includes c0 itself (rotate-and-sum), 0: only the rotated copies
+    // multi != 0: rotation r acts on its own ciphertext: extended digits ext_r[r] (same
+    // strides as ext) and c0 at c0_r[r] (stride c0_ct); s0 = sum_r sigma_r(c0_r)
+    int multi;
+    const double *ext_r[kMaxHoist];
+    const double *c0_r[kMaxHoist];
 };
 void launch_inner_product_rot(const DevTables &T, const double *ext, long long estride_b, long long estride_j,
                               double *acc0, double *acc1, long long astride, const RotSet &rs, int betaL,

@@ -614,10 +614,72 @@ __global__ __launch_bounds__(256) void k_inner_product_rot_reg(DevTables T, cons
     }
 }
 
+// The key products of rotations of different ciphertexts summed in one pass (the giant
+// steps of a bootstrap linear transform, whose rotated parts share one ModDown): rotation
+// r gathers its own extended digits rs.ext_r[r] and c0 rs.c0_r[r]; otherwise as
+// k_inner_product_rot (at most 7 rotations: the partial sums stay below 2^51.6 with one
+// reduction per floor(21 / beta) rotations).
+template <int BETA>
+__global__ __launch_bounds__(256) void k_inner_product_multi(DevTables T, long long esb, long long esj,
+                                                             double *__restrict__ acc0, double *__restrict__ acc1,
+                                                             long long astride, RotSet rs, int betaL, int cnt,
+                                                             int next, const int *__restrict__ ext_prime,
+                                                             int xblocks) {
+    const int b = blockIdx.x, slot = b >> 3;
+    const int t = (b & 7) + 8 * (slot / xblocks);
+    if (t >= next) return;
+    const int x = rs.xorder[slot % xblocks] * blockDim.x + threadIdx.x;
+    if (x >= T.N) return;
+    const int pt = ext_prime[t];
+    const double p = T.p[pt], pinv = T.pinv[pt];
+    const int rk = 21 / BETA;
+    const bool wsum = rs.c0_r[0] && t <= rs.lq;
+    for (int ct = 0; ct < cnt; ++ct) {
+        double s0 = 0.0, s1 = 0.0, g0 = 0.0;
+        for (int r = 0; r < rs.nr; ++r) {
+            const unsigned src = aut_src((unsigned)x, rs.g[r], T.logN);
+            const double *E = rs.ext_r[r] + ct * esb + (long long)t * T.N;
+            if (wsum) g0 = red(g0 + rs.c0_r[r][ct * rs.c0_ct + (long long)t * T.N + src], p, pinv);
+            const KeyRef K = rs.key[r];
+            double e[BETA], a0[BETA], a1[BETA];
+#pragma unroll
+            for (int j = 0; j < BETA; ++j) {
+                e[j] = E[j * esj + src];
+                key_pair(K, betaL, pt, j, T.N, x, a0[j], a1[j]);
+            }
+#pragma unroll
+            for (int j = 0; j < BETA; ++j) {
+                s0 += mm(e[j], a0[j], p, pinv);
+                s1 += mm(e[j], a1[j], p, pinv);
+            }
+            if ((r + 1) % rk == 0) {
+                s0 = red(s0, p, pinv);
+                s1 = red(s1, p, pinv);
+            }
+        }
+        acc0[ct * astride + (long long)t * T.N + x] = canon(s0, p, pinv);
+        acc1[ct * astride + (long long)t * T.N + x] = canon(s1, p, pinv);
+        if (wsum) rs.s0[ct * rs.s0_ct + (long long)t * T.N + x] = canon(g0, p, pinv);
+    }
+}
+
 void launch_inner_product_rot(const DevTables &T, const double *ext, long long estride_b, long long estride_j,
                               double *acc0, double *acc1, long long astride, const RotSet &rs, int betaL,
                               int cnt, int beta, int next, const int *ext_prime, hipStream_t s) {
     if (cnt <= 0) return;
+    if (rs.multi) {
+        kprof_set_bytes(T.N * next * (6.0 * 2.0 * beta * rs.nr + 8.0 * cnt * (beta * rs.nr + 2.0)));
+        const int xblocks = (T.N + 255) / 256;
+        const dim3 g1(8 * ((next + 7) / 8) * xblocks);
+#define IPM_CASE(B)                                                                                            \
+    case B:                                                                                                    \
+        KL("k_inner_product_multi", k_inner_product_multi<B>, g1, dim3(256), 0, s, T, estride_b, estride_j, acc0, \
+           acc1, astride, rs, betaL, cnt, next, ext_prime, xblocks);                                           \
+        break;
+        switch (beta) { IPM_CASE(1) IPM_CASE(2) IPM_CASE(3) IPM_CASE(4) IPM_CASE(5) IPM_CASE(6) IPM_CASE(7) IPM_CASE(8) }
+#undef IPM_CASE
+        return;
+    }
     // every rotation's key words once; the extended digits and both accumulators
     // once per ciphertext
     kprof_set_bytes(T.N * next * (6.0 * 2.0 * beta * rs.nr + 8.0 * cnt * (beta + 2.0)));
