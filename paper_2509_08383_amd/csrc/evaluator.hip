@@ -682,6 +682,31 @@ struct Exec {
         return o;
     }
 
+    // sum_t K[t cnt + c] x_t[c] for ciphertexts x_t of one level (integer constants, no
+    // rescale), declared at scale s_out
+    Bt lincomb(const std::vector<Bt> &xs, const std::vector<int64_t> &K, double s_out) {
+        REQUIRE(!xs.empty() && (int)xs.size() <= kMaxLtTerms, HE_EINVAL, "lincomb: 1..16 terms");
+        const int l = xs[0].level, cnt = xs[0].cnt;
+        REQUIRE((int)K.size() == (int)xs.size() * cnt, HE_EINVAL, "lincomb: constants");
+        Bt o = new_bt(cnt, l);
+        o.scale.assign(cnt, s_out);
+        LtTerms tm{};
+        tm.n = (int)xs.size();
+        std::vector<double> kr((size_t)xs.size() * cnt * (l + 1));
+        for (size_t t = 0; t < xs.size(); ++t) {
+            REQUIRE(xs[t].level == l && xs[t].cnt == cnt, HE_ESTATE, "lincomb: shapes differ");
+            tm.x[t] = xs[t].d;
+            tm.xct[t] = 2LL * xs[t].cap * C->N;
+            tm.xpoly[t] = (long long)xs[t].cap * C->N;
+            for (int c = 0; c < cnt; ++c)
+                for (int i = 0; i <= l; ++i)
+                    kr[(t * cnt + c) * (l + 1) + i] = (double)red_i64(K[t * cnt + c], C->q[i]);
+        }
+        const double *kd = C->pool.push(kr);
+        if (go()) launch_lincomb(T, o.d, 2LL * o.cap * C->N, (long long)o.cap * C->N, tm, kd, cnt, l + 1, s);
+        return o;
+    }
+
     // both polynomials times a plaintext (NTT-domain residues, limb i at pt + i N),
     // declared scale times pscale, no rescale
     Bt mul_plain(const Bt &a, const double *pt, double pscale) {
@@ -1318,13 +1343,24 @@ struct ChebEval {
         if (deg == 0) return false;
         const std::vector<double> sv(R, S);
         if (deg < 8) {
-            bool have = false;
+            // sum_i a_i T_i with one rescale: every T_i at level + 1 times the integer
+            // round(a_i S q_{level+1} / s_i), summed (scale S q_{level+1}), rescaled to S
+            std::vector<Bt> xs;
+            std::vector<int64_t> K;
+            const double q1 = (double)X.C->q[level + 1];
             for (int i = 1; i <= deg; ++i) {
                 if (std::fabs(a[i]) < eps) continue;
-                Bt t = X.drop(X.cmul(basis(i), std::vector<double>(R, a[i]), sv, false), level);
-                if (have) X.add_inplace(out, t);
-                else { out = t; have = true; }
+                Bt Ti = basis(i);
+                REQUIRE(Ti.level >= level + 1, HE_EDEPTH, "Chebyshev evaluation: baby step too deep");
+                xs.push_back(X.drop(Ti, level + 1));
+                for (int c = 0; c < R; ++c) {
+                    const double k = ((a[i] * S) * q1) / Ti.scale[c];
+                    REQUIRE(std::fabs(k) < 4.0e18, HE_ERANGE, "Chebyshev coefficient not encodable");
+                    K.push_back(llround_d(k));
+                }
             }
+            out = X.rescale(X.lincomb(xs, K, S * q1));
+            for (int c = 0; c < R; ++c) out.scale[c] = S;
             if (a[0] != 0.0) out = X.add_const(out, std::vector<double>(R, a[0]));
             return true;
         }

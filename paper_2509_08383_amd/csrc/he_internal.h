@@ -159,6 +159,9 @@ struct LtTerms {
 };
 void launch_lt_inner(const DevTables &T, double *out, long long oct, long long opoly, const LtTerms &tm, int cnt,
                      int limbs, hipStream_t s);
+// out = sum_t k_t x_t with integer constants (residues kres[(t cnt + c) limbs + i])
+void launch_lincomb(const DevTables &T, double *out, long long oct, long long opoly, const LtTerms &tm,
+                    const double *kres, int cnt, int limbs, hipStream_t s);
 
 // rotations of one hoisted rotate-and-sum step: key and Galois element of each
 constexpr int kMaxHoist = 15;

@@ -273,6 +273,35 @@ void launch_lt_inner(const DevTables &T, double *out, long long oct, long long o
     KL("k_lt_inner", k_lt_inner, dim3((T.N + 255) / 256, limbs), dim3(256), 0, s, out, oct, opoly, tm, cnt, T);
 }
 
+// out[c][poly][i] = sum_t k_t[c][i] * x_t[c][poly][i] (integer constants as residues,
+// kres[(t cnt + c) limbs + i]), both polynomials, limbs i < limbs: a linear combination
+// of ciphertexts at one level before a single rescale.  |sum| < 2^52 for n <= 16.
+__global__ __launch_bounds__(256) void k_lincomb(double *__restrict__ out, long long oct, long long opoly, LtTerms tm,
+                                                 const double *__restrict__ kres, int cnt, int limbs, DevTables T) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= T.N) return;
+    const int i = blockIdx.y, c = blockIdx.z;
+    const double p = T.p[i], pinv = T.pinv[i];
+    const long long w = (long long)i * T.N + x;
+    double a0 = 0.0, a1 = 0.0;
+    for (int t = 0; t < tm.n; ++t) {
+        const double k = kres[((long long)t * cnt + c) * limbs + i];
+        const double *xp = tm.x[t] + c * tm.xct[t] + w;
+        a0 += mm(xp[0], k, p, pinv);
+        a1 += mm(xp[tm.xpoly[t]], k, p, pinv);
+    }
+    double *o = out + c * oct + w;
+    o[0] = canon(a0, p, pinv);
+    o[opoly] = canon(a1, p, pinv);
+}
+void launch_lincomb(const DevTables &T, double *out, long long oct, long long opoly, const LtTerms &tm,
+                    const double *kres, int cnt, int limbs, hipStream_t s) {
+    if (cnt <= 0 || tm.n <= 0) return;
+    kprof_set_bytes(8.0 * T.N * limbs * cnt * 2.0 * (tm.n + 1.0));
+    KL("k_lincomb", k_lincomb, dim3((T.N + 255) / 256, limbs, cnt), dim3(256), 0, s, out, oct, opoly, tm, kres, cnt,
+       limbs, T);
+}
+
 // ------------------------------------------------------------ key switching
 // ModUp of every digit j ([lo_j, lo_j+dl_j) of the primes present at the level):
 // v holds v_a = [d_{lo+a} * Qhat_a^-1]_{q_{lo+a}} in the coefficient domain (the
