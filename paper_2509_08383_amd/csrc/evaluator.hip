@@ -1244,12 +1244,39 @@ Bt lin_transform(Exec &X, const Bt &ct, const Diag &D, const Bsgs &P, double rho
     bool have = false;
     std::vector<Bt> rotated;                         // giant sums still to rotate (shared ModDown)
     std::vector<std::pair<int, uint64_t>> rot_keys;
+    // with at most 8 babies and 8 giants every giant sum is computed in one pass
+    std::map<int, Bt> fused;
+    if (C->boot_hoist >= 1 && P.B <= kMaxLtBaby && (int)P.terms.size() <= kMaxLtGiant) {
+        LtGiants lg{};
+        lg.nb = P.B;
+        for (int b = 0; b < P.B; ++b) {
+            auto it = baby.find(b);
+            const Bt &bx = it != baby.end() ? it->second : ct;
+            lg.x[b] = bx.d;
+            lg.xct[b] = 2LL * bx.cap * N;
+            lg.xpoly[b] = (long long)bx.cap * N;
+        }
+        int gi = 0;
+        for (const auto &at : P.terms) {
+            Bt inner = X.new_bt(ct.cnt, l);
+            for (int c = 0; c < ct.cnt; ++c) inner.scale[c] = ct.scale[c] * pscale;
+            lg.out[gi] = inner.d;
+            lg.oct = 2LL * inner.cap * N;
+            lg.opoly = (long long)inner.cap * N;
+            for (size_t j = 0; j < at.second.size(); ++j)
+                lg.pt[gi][at.second[j].first] = X.dry ? nullptr : C->pt_cache.at(key(at.first, (int)j));
+            fused[at.first] = inner;
+            ++gi;
+        }
+        lg.ng = gi;
+        if (X.go()) launch_lt_giants(X.T, lg, ct.cnt, l + 1, X.s);
+    }
     for (const auto &at : P.terms) {
         const long long shift = ((long long)at.first * P.B * P.h0) % s;
-        Bt inner = X.new_bt(ct.cnt, l);
+        Bt inner = fused.count(at.first) ? fused[at.first] : X.new_bt(ct.cnt, l);
         for (int c = 0; c < ct.cnt; ++c) inner.scale[c] = ct.scale[c] * pscale;
         // chunks of at most kMaxLtTerms terms, summed
-        const int nt = (int)at.second.size();
+        const int nt = fused.count(at.first) ? 0 : (int)at.second.size();
         for (int j0 = 0; j0 < nt; j0 += kMaxLtTerms) {
             Bt part = j0 == 0 ? inner : X.new_bt(ct.cnt, l);
             part.scale = inner.scale;

@@ -159,6 +159,19 @@ struct LtTerms {
 };
 void launch_lt_inner(const DevTables &T, double *out, long long oct, long long opoly, const LtTerms &tm, int cnt,
                      int limbs, hipStream_t s);
+// every giant-step sum of one baby-step giant-step linear transform in one pass:
+// out[a] = sum_b pt[a][b] * x[b] (pt[a][b] null where giant a has no diagonal for baby b),
+// each baby word loaded once for all giants
+constexpr int kMaxLtBaby = 8, kMaxLtGiant = 8;
+struct LtGiants {
+    const double *pt[kMaxLtGiant][kMaxLtBaby];
+    const double *x[kMaxLtBaby];
+    long long xct[kMaxLtBaby], xpoly[kMaxLtBaby];
+    double *out[kMaxLtGiant];
+    long long oct, opoly;
+    int nb, ng;
+};
+void launch_lt_giants(const DevTables &T, const LtGiants &g, int cnt, int limbs, hipStream_t s);
 // out = sum_t k_t x_t with integer constants (residues kres[(t cnt + c) limbs + i])
 void launch_lincomb(const DevTables &T, double *out, long long oct, long long opoly, const LtTerms &tm,
                     const double *kres, int cnt, int limbs, hipStream_t s);

@@ -273,6 +273,56 @@ void launch_lt_inner(const DevTables &T, double *out, long long oct, long long o
     KL("k_lt_inner", k_lt_inner, dim3((T.N + 255) / 256, limbs), dim3(256), 0, s, out, oct, opoly, tm, cnt, T);
 }
 
+// All giant-step sums of a linear transform at once: for each position the words of
+// every baby (both polynomials) are loaded once and reused by every giant, which reads
+// only its own plaintext words; the per-giant form would re-read the babies once per
+// giant.  |sum| <= nb (p/2 + 2^44) < 2^52 for nb <= 8.
+__global__ __launch_bounds__(256) void k_lt_giants(LtGiants g, int cnt, DevTables T) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= T.N) return;
+    const int i = blockIdx.y;
+    const double p = T.p[i], pinv = T.pinv[i];
+    const long long w = (long long)i * T.N + x;
+    for (int c = 0; c < cnt; ++c) {
+        double b0[kMaxLtBaby], b1[kMaxLtBaby];
+#pragma unroll
+        for (int b = 0; b < kMaxLtBaby; ++b) {
+            if (b < g.nb) {
+                const double *xp = g.x[b] + c * g.xct[b] + w;
+                b0[b] = xp[0];
+                b1[b] = xp[g.xpoly[b]];
+            } else {
+                b0[b] = 0.0;
+                b1[b] = 0.0;
+            }
+        }
+        for (int a = 0; a < g.ng; ++a) {
+            double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+            for (int b = 0; b < kMaxLtBaby; ++b) {
+                const double *pt = g.pt[a][b];
+                if (b < g.nb && pt) {
+                    const double pv = pt[w];
+                    a0 += mm(b0[b], pv, p, pinv);
+                    a1 += mm(b1[b], pv, p, pinv);
+                }
+            }
+            double *o = g.out[a] + c * g.oct + w;
+            o[0] = canon(a0, p, pinv);
+            o[g.opoly] = canon(a1, p, pinv);
+        }
+    }
+}
+void launch_lt_giants(const DevTables &T, const LtGiants &g, int cnt, int limbs, hipStream_t s) {
+    if (cnt <= 0 || g.ng <= 0 || g.nb <= 0) return;
+    int npt = 0;
+    for (int a = 0; a < g.ng; ++a)
+        for (int b = 0; b < g.nb; ++b) npt += g.pt[a][b] != nullptr;
+    // every plaintext once, every baby once per ciphertext, every giant sum written
+    kprof_set_bytes(8.0 * T.N * limbs * (npt + 2.0 * cnt * (g.nb + g.ng)));
+    KL("k_lt_giants", k_lt_giants, dim3((T.N + 255) / 256, limbs), dim3(256), 0, s, g, cnt, T);
+}
+
 // out[c][poly][i] = sum_t k_t[c][i] * x_t[c][poly][i] (integer constants as residues,
 // kres[(t cnt + c) limbs + i]), both polynomials, limbs i < limbs: a linear combination
 // of ciphertexts at one level before a single rescale.  |sum| < 2^52 for n <= 16.
