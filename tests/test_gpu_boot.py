@@ -335,6 +335,17 @@ def test_bootstrap_multi_ciphertext_handle(full):
     err = float(np.abs(G.decrypt(out, v.size) - v).max())
     say(f"[gpu] bootstrap of 4 ciphertexts: max err {err:.2e}")
     assert err < 2e-3
+    # the batched shared-ModUp baby steps and one-pass giant sums equal one key switch per
+    # rotation and one plaintext sum per giant, word for word
+    from paper_2509_08383_amd import he
+    res = {}
+    try:
+        for opt in (0, 1):
+            G.set_option(he.HE_OPT_BOOT_HOIST, opt)
+            res[opt] = G.export(G.bootstrap(G.drop(ct, 3), 1.0))
+    finally:
+        G.set_option(he.HE_OPT_BOOT_HOIST, 2)
+    assert np.array_equal(res[0], res[1])
 
 
 @pytest.mark.slow
