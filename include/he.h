@@ -143,7 +143,18 @@ typedef struct {
 /* Context: prime chain, twiddle and basis-conversion tables, secret key, and
  * the relinearisation and rotation keys (rotation by 2^r slots for every r <
  * log2(slots), and the amounts of the hoisted rotate-and-sum steps), generated
- * on the device. */
+ * on the device.  Roles follow the paper's setting (Sec. 2.1, the CKKS scheme
+ * and its properties; App. A, threat model): the secret key stays with the
+ * client, which encrypts and decrypts; the server evaluates with the public
+ * evaluation keys only (relinearisation for products, Galois keys for the
+ * rotations of rotate-and-sum, Sec. 3.2).  One context holds both roles so the
+ * library can serve as client and server in one process; a deployment gives
+ * the server a context built from the same seed and parameters and never
+ * calls he_encrypt/he_decrypt there.
+ * prm: host memory, read during the call.  out: receives a new handle owned by
+ * the caller (he_ctx_destroy).  Errors: HE_EINVAL for parameters outside the
+ * ranges above (no prime of the requested size, too many primes), HE_EDEVICE
+ * without a usable GPU, HE_ENOMEM when the keys do not fit in device memory. */
 int he_ctx_create(const he_params *prm, he_ctx **out);
 void he_ctx_destroy(he_ctx *ctx);
 
@@ -229,7 +240,10 @@ int he_ct_import(he_ctx *ctx, const uint64_t *limbs, uint32_t a, uint32_t level,
  *                         declares the exact scale, else scale s_want
  *   he_rotate             rotate slots left by 2^r (Sec. 3.2)
  *   he_rotsum             rotate-and-sum over every slot (Sec. 3.2, App. D)
- *   he_drop               drop limbs down to `level` */
+ *   he_drop               drop limbs down to `level`
+ * Every handle must belong to ctx; for he_add, he_sub and he_mul the second
+ * operand b must also be a single ciphertext of ctx at a's level (HE_EINVAL
+ * otherwise, before any kernel runs). */
 int he_add(he_ctx *ctx, const he_ct *a, const he_ct *b, he_ct **out);
 int he_sub(he_ctx *ctx, const he_ct *a, const he_ct *b, he_ct **out);
 int he_mul_int(he_ctx *ctx, const he_ct *a, int64_t k, he_ct **out);

@@ -288,6 +288,10 @@ class Oracle:
         self.q = [int(v) for v in self.primes]
         self.Delta = 2.0 ** prm.log2_scale
         self.slots = self.N // 2
+        # plain form of the two kernel-shaped steps: with plain=True, rotsum runs the
+        # log2(slots) single rotations of Sec. 3.2 and mul relinearises (ModDown by P)
+        # and then rescales (by q_l) instead of one ModDown by P q_l
+        self.plain = False
 
     def __del__(self):
         try:
@@ -397,8 +401,18 @@ class Oracle:
     def mul(self, a: Ct, b: Ct) -> Ct:
         if a.level != b.level:
             raise SchedError("mul: level mismatch")
+        if a.level < 1:
+            raise SchedError("mul needs a level")
         q = float(self.q[a.level])
+        if self.plain:
+            return self.rescale(self.mul_relin(a, b))
         return Ct(self, lib().oc_mul(self.h, a.h, b.h), (a.scale * b.scale) / q)
+
+    def mul_relin(self, a: Ct, b: Ct) -> Ct:
+        """tensor product and relinearisation (ModDown by P), no rescale"""
+        if a.level != b.level:
+            raise SchedError("mul: level mismatch")
+        return Ct(self, lib().oc_mul_norescale(self.h, a.h, b.h), a.scale * b.scale)
 
     def rotate(self, a: Ct, r: int) -> Ct:
         return Ct(self, lib().oc_rotate(self.h, a.h, int(r)), a.scale)
@@ -434,7 +448,7 @@ class Oracle:
         hoist h >= 1: steps of radix R = 2^h, x <- x + sum_{r=1}^{R-1} rot(x, r k) for
         k = 1, R, R^2, ... (the last step takes the remaining bits), each step one
         hoisted ModUp, the key products of its R-1 rotations summed, one ModDown."""
-        if self.prm.hoist <= 0:
+        if self.prm.hoist <= 0 or self.plain:
             for r in range(int(math.log2(self.slots))):
                 x = self.add(x, self.rotate(x, r))
             return x
@@ -645,9 +659,14 @@ def cutmax_he(O: Oracle, Y: List[Ct], cfg: HECfg, rotsum_cache=None, n_real: int
 def topp_he(O: Oracle, X: List[Ct], G: List[Ct], temperature: float, cfg: HECfg,
             prescaled: bool = False, n_real: int = None) -> List[Ct]:
     """Alg. 3 server side: CutMax(X + tau*G) (equal to CutMax(X/tau + G))."""
+    return cutmax_he(O, topp_input(O, X, G, temperature, prescaled), cfg, n_real=n_real)
+
+
+def topp_input(O: Oracle, X: List[Ct], G: List[Ct], temperature: float, prescaled: bool = False) -> List[Ct]:
+    """The sampler's CutMax input X + tau*G: the noise times tau by one constant multiply
+    declared at the logits' scale (one level, the logits dropped to match), or X + G when
+    the client already scaled the noise."""
     if prescaled:
-        Xt = [O.add(x, g) for x, g in zip(X, G)]
-    else:
-        Gs = [O.cm_target(g, temperature, x.scale) for x, g in zip(X, G)]
-        Xt = [O.add(O.drop(x, gs.level), gs) for x, gs in zip(X, Gs)]
-    return cutmax_he(O, Xt, cfg, n_real=n_real)
+        return [O.add(x, g) for x, g in zip(X, G)]
+    Gs = [O.cm_target(g, temperature, x.scale) for x, g in zip(X, G)]
+    return [O.add(O.drop(x, gs.level), gs) for x, gs in zip(X, Gs)]

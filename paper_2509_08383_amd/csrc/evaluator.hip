@@ -2645,11 +2645,19 @@ int he_ct_import(he_ctx *C, const uint64_t *limbs, uint32_t a, uint32_t level, d
 }
 
 int he_add(he_ctx *C, const he_ct *a, const he_ct *b, he_ct **out) {
-    if (!b || b->a != 1 || (a && b->level != a->level)) { g_err = "bad operand"; return HE_EINVAL; }
+    // b is read with this context's ring degree and limb stride: it must belong to C
+    if (!b || b->ctx != C || b->a != 1 || (a && b->level != a->level)) {
+        g_err = "bad operand (null, from another context, several ciphertexts or another level)";
+        return HE_EINVAL;
+    }
     return prim(C, a, out, [&](Exec &X) { return X.add(bt_of(a), bt_of(b)); });
 }
 int he_sub(he_ctx *C, const he_ct *a, const he_ct *b, he_ct **out) {
-    if (!b || b->a != 1 || (a && b->level != a->level)) { g_err = "bad operand"; return HE_EINVAL; }
+    // b is read with this context's ring degree and limb stride: it must belong to C
+    if (!b || b->ctx != C || b->a != 1 || (a && b->level != a->level)) {
+        g_err = "bad operand (null, from another context, several ciphertexts or another level)";
+        return HE_EINVAL;
+    }
     return prim(C, a, out, [&](Exec &X) { return X.add(bt_of(a), bt_of(b), -1); });
 }
 int he_mul_int(he_ctx *C, const he_ct *a, int64_t k, he_ct **out) {
@@ -2659,7 +2667,11 @@ int he_add_const(he_ctx *C, const he_ct *a, double c, he_ct **out) {
     return prim(C, a, out, [&](Exec &X) { return X.add_const(bt_of(a), {c}); });
 }
 int he_mul(he_ctx *C, const he_ct *a, const he_ct *b, he_ct **out) {
-    if (!b || b->a != 1 || (a && b->level != a->level)) { g_err = "bad operand"; return HE_EINVAL; }
+    // b is read with this context's ring degree and limb stride: it must belong to C
+    if (!b || b->ctx != C || b->a != 1 || (a && b->level != a->level)) {
+        g_err = "bad operand (null, from another context, several ciphertexts or another level)";
+        return HE_EINVAL;
+    }
     return prim(C, a, out, [&](Exec &X) { return X.mul(bt_of(a), bt_of(b)); });
 }
 int he_rescale(he_ctx *C, const he_ct *a, he_ct **out) {
@@ -2876,7 +2888,12 @@ int he_ntt_tuning(const he_ctx *C, int32_t *variants, uint32_t n) {
 int he_set_option(he_ctx *C, int option, int64_t value) {
     if (!C) { g_err = "null context"; return HE_EINVAL; }
     if (option == HE_OPT_GRAPH) { C->use_graph = (int)value; return HE_OK; }
-    if (option == HE_OPT_NTT_VARIANT) { C->ntt_variant = (int)value; return HE_OK; }
+    if (option == HE_OPT_NTT_VARIANT) {
+        if (value < 0 || value > NTT_VARIANTS) { g_err = "NTT variant out of range"; return HE_EINVAL; }
+        C->ntt_variant = (int)value;
+        drop_graphs(C);  // captured graphs hold the previous variant's kernels
+        return HE_OK;
+    }
     if (option == HE_OPT_BOOT_HOIST) {
         C->boot_hoist = value <= 0 ? 0 : (value >= 2 ? 2 : 1);
         drop_graphs(C);  // captured graphs hold the other launch sequence

@@ -71,7 +71,8 @@ void kprof_set_bytes(double algorithmic_bytes);  // for the next launch
         if (g_kprof) kprof_mark(name, stream, true);                     \
     } while (0)
 
-// NTT workgroup-width tuning (ntt.hip): variant 1..3 per (log N, batch bucket)
+// NTT schedule tuning (ntt.hip): variant 1..NTT_VARIANTS per (log N, batch bucket)
+constexpr int NTT_VARIANTS = 3;
 void set_ntt_tuning(int logN, int bucket, int variant);
 
 // ---------------------------------------------------------------- kernels.hip

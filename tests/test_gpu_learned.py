@@ -181,3 +181,29 @@ def test_cutmax_with_learned_guess_batch16(learned):
             mc = MirrorCfg(T=3, p=[3] * 3, c=[5.0] * 3, v_hi=VHI5, v_lo=VLO5, coef=coefs, B=3.0 * y.size,
                            gold_d=2, sum_lo=1.0 * y.size)
             assert np.abs(zl - cutmax_mirror(y, mc)).max() < 1e-3
+
+
+def test_learned_cutmax_bit_exact_at_full_size(learned):
+    """the learned schedule (degree-4 guess from the trained networks, 29 levels) on one
+    request of 32000 logits at N = 2^16: every limb of Z equals the oracle's CutMax with the
+    same coefficients, from the same seed and encoded plaintext"""
+    from paper_2509_08383_amd import he
+    from test_gpu_parity import Pair
+    coefs, _, _ = learned
+    say("[gpu] learned-guess CutMax at N=2^16, bit-exact against the oracle")
+    P = Pair(he.SECURE)
+    x = llm_logits_var(5003)
+    y, _, _ = slot_layout(x, P.G.slots)
+    g, o = P.enc_values(y)
+    cfg = he.CutmaxCfg(T=3, p=[3] * 3, c=[5.0] * 3, var_lo=VLO5, var_hi=VHI5, init_degree=4, init_coef=coefs,
+                       sum_lo=1.0, sum_hi=3.0, gold_d=2)
+    Zg = P.G.cutmax([g], cfg)[0]
+    hc = ckks.HECfg(T=3, p=[3] * 3, c=[5.0] * 3, v_lo=VLO5, v_hi=VHI5, coef=coefs, sum_lo=1.0, sum_hi=3.0, gold_d=2)
+    Zo = ckks.cutmax_he(P.O, [o], hc)[0]
+    P.same(Zg, Zo, "learned cutmax")
+    assert Zg.level == 0
+    mc = MirrorCfg(T=3, p=[3] * 3, c=[5.0] * 3, v_hi=VHI5, v_lo=VLO5, coef=coefs, B=3.0 * y.size, gold_d=2,
+                   sum_lo=1.0 * y.size)
+    z = P.G.decrypt(Zg, y.size)
+    assert np.abs(z - cutmax_mirror(y, mc)).max() < 1e-3
+    assert int(np.argmax(z[:x.size])) == int(np.argmax(x))

@@ -405,3 +405,108 @@ def test_edge_inputs_are_rejected_or_handled(toy):
     mc = MirrorCfg(T=4, p=p, c=c, v_hi=vhi, v_lo=vlo, coef=coef, B=3.0 * y.size, gold_d=3, sum_lo=1.0 * y.size)
     assert np.abs(z - cutmax_mirror(y, mc)).max() < 1e-3
     assert int(np.argmax(z[:x.size])) in (i, j)
+
+
+@pytest.mark.parametrize("degree", [2, 4])
+def test_cutmax_toy_guess_degrees_bit_exact(toy, degree):
+    """the degree-2 and degree-4 initial guesses (degree 4 is the form the learned network
+    collapses to, evaluated in depth 3) inside the whole toy CutMax: bit-exact against the
+    oracle's schedule, within 1e-3 of the FP64 mirror, argmax recovered"""
+    from paper_2509_08383_amd import he
+    say(f"[gpu] cutmax toy degree-{degree} guess bit-exact")
+    T = 4 if degree == 2 else 3
+    x = toy_logits(25 + degree)
+    y, a, rep = slot_layout(x, toy.G.slots)
+    n = y.size
+    p, c, vlo, vhi, _ = toy_cfg(n, T=T)
+    coef = [list(chebyshev_invsqrt(vlo[t] / vhi[t], degree)) for t in range(T)]
+    g, o = toy.enc_values(y)
+    cfg = he.CutmaxCfg(T=T, p=p, c=c, var_lo=vlo, var_hi=vhi, init_degree=degree, init_coef=coef,
+                       sum_lo=1.0, sum_hi=3.0, gold_d=3)
+    Zg = toy.G.cutmax([g], cfg)[0]
+    hc = ckks.HECfg(T=T, p=p, c=c, v_lo=vlo, v_hi=vhi, coef=coef, sum_lo=1.0, sum_hi=3.0, gold_d=3)
+    Zo = ckks.cutmax_he(toy.O, [o], hc)[0]
+    toy.same(Zg, Zo, f"cutmax degree {degree}")
+    assert Zg.level == toy.G.L - hc.levels_needed()
+    dz = toy.G.decrypt(Zg, n)
+    mc = MirrorCfg(T=T, p=p, c=c, v_hi=vhi, v_lo=vlo, coef=coef, B=3.0 * n, gold_d=3, sum_lo=1.0 * n)
+    assert np.abs(dz - cutmax_mirror(y, mc)).max() < 1e-3
+    assert int(np.argmax(dz[:x.size])) == int(np.argmax(x))
+
+
+@pytest.mark.parametrize("sampler", ["topp", "gumbel"])
+@pytest.mark.parametrize("prescaled", [False, True])
+def test_samplers_toy_bit_exact(toy, sampler, prescaled):
+    """the samplers' server step CutMax(X + tau G) (Alg. 3; the Gumbel-max form of Sec. 3.3
+    runs the same step): with the temperature multiply on the noise ciphertext, or with
+    noise the client already scaled, bit-exact against the oracle's topp_he, and the
+    decrypted one-hot picks argmax(x/tau + g)"""
+    from paper_2509_08383_amd import he
+    from oracle.cutmax_fp64 import beta_alpha, beta_noise, gumbel_noise
+    from workloads import uniform_noise
+    say(f"[gpu] {sampler} sampler toy bit-exact (prescaled={prescaled})")
+    tau, top_p, T = 0.8, 0.9, 3
+    x = toy_logits(27)
+    u = uniform_noise(28, x.size)
+    gn = beta_noise(u, beta_alpha(top_p)) if sampler == "topp" else gumbel_noise(u)
+    y, _, _ = slot_layout(x, toy.G.slots)
+    gy, _, _ = slot_layout(gn, toy.G.slots)
+    n = y.size
+    p, c = [3] * T, [5.0] * T
+    # Gumbel noise (variance pi^2/6 times tau^2) widens the first variance
+    vlo, vhi = [0.5, 0.25, 0.3], [4.0, 0.75, 3.0]
+    coef = [list(chebyshev_invsqrt(vlo[t] / vhi[t], 3)) for t in range(T)]
+    gx, ox = toy.enc_values(y)
+    gg, og = toy.enc_values(tau * gy if prescaled else gy)
+    cfg = he.CutmaxCfg(T=T, p=p, c=c, var_lo=vlo, var_hi=vhi, init_degree=3, init_coef=coef, sum_lo=1.0,
+                       sum_hi=3.0, gold_d=3, flags=he.HE_NOISE_PRESCALED if prescaled else 0)
+    if sampler == "topp":
+        Zg = toy.G.topp_sample([gx], [gg], top_p, tau, cfg)[0]
+    else:
+        Zg = toy.G.gumbel_sample([gx], [gg], tau, cfg)[0]
+    hc = ckks.HECfg(T=T, p=p, c=c, v_lo=vlo, v_hi=vhi, coef=coef, sum_lo=1.0, sum_hi=3.0, gold_d=3)
+    Zo = ckks.topp_he(toy.O, [ox], [og], tau, hc, prescaled=prescaled)[0]
+    toy.same(Zg, Zo, f"{sampler} sample")
+    dz = toy.G.decrypt(Zg, n)
+    mc = MirrorCfg(T=T, p=p, c=c, v_hi=vhi, v_lo=vlo, coef=coef, B=3.0 * n, gold_d=3, sum_lo=1.0 * n)
+    assert np.abs(dz - cutmax_mirror(y + tau * gy, mc)).max() < 1e-3
+    assert int(np.argmax(dz[:x.size])) == int(np.argmax(x / tau + gn))
+
+
+def test_foreign_operands_and_bad_options_are_rejected(toy):
+    """a second operand from another context (another ring degree and limb stride) is
+    refused with HE_EINVAL before any kernel runs, for add, sub and mul; an NTT variant out
+    of range is refused, and a valid one drops the captured graphs (a later replay still
+    equals the eager result)"""
+    from paper_2509_08383_amd import he
+    say("[gpu] foreign operands, option checks")
+    other = he.Context(he.Params(log_n=11, n_q=6, q0_bits=40, q_bits=30, p_bits=40, dnum=3, log2_scale=30, seed=5))
+    a = toy.G.encrypt(np.ones(8))
+    b = other.encrypt(np.ones(8))
+    toy.O.nonce = toy.O.nonce + 1
+    a = toy.G.drop(a, b.level)       # same level: only the context differs
+    assert a.level == b.level == 5
+    for op in (toy.G.add, toy.G.sub, toy.G.mul):
+        with pytest.raises(he.HeError) as e:
+            op(a, b)
+        assert e.value.code == he.HE_EINVAL and "context" in str(e.value)
+    for bad in (-1, 99):
+        with pytest.raises(he.HeError) as e:
+            toy.G.set_option(he.HE_OPT_NTT_VARIANT, bad)
+        assert e.value.code == he.HE_EINVAL
+    x = toy_logits(52)
+    ct = toy.G.encrypt(x)
+    toy.O.nonce = toy.O.nonce + 1
+    p, c, vlo, vhi, coef = toy_cfg(2048)
+    cfg = he.CutmaxCfg(T=4, p=p, c=c, var_lo=vlo, var_hi=vhi, init_coef=coef, sum_lo=1.0, sum_hi=3.0)
+    ref = toy.G.export(toy.G.cutmax([ct], cfg)[0])
+    toy.G.set_option(he.HE_OPT_GRAPH, 1)
+    try:
+        for v in (1, 2, 0):
+            toy.G.set_option(he.HE_OPT_NTT_VARIANT, v)
+            for _ in range(2):
+                assert np.array_equal(toy.G.export(toy.G.cutmax([ct], cfg)[0]), ref), v
+    finally:
+        toy.G.set_option(he.HE_OPT_GRAPH, 0)
+        toy.G.set_option(he.HE_OPT_NTT_VARIANT, 0)
+    other.close()

@@ -1,7 +1,8 @@
 """GPU parity at the 128-bit parameter set (N = 2^16, 30 Q primes, dnum = 3): primitives
-bit-exact against the CPU oracle at full size; encrypted CutMax on 32000 LLM-like logits
-against the FP64 mirror within 1e-3 with the argmax recovered; the batched form (16 mixed requests)
-with 1- and 4-ciphertext requests."""
+bit-exact against the CPU oracle at full size; the measured T=3 CutMax on 32000 LLM-like logits
+bit-exact against the oracle and within 1e-3 of the FP64 mirror with the argmax recovered; the
+batched form (16 mixed requests with 1- and 4-ciphertext requests) with a request of each kind
+bit-exact against the oracle."""
 import math
 import sys
 
@@ -97,27 +98,66 @@ def test_cutmax_config2_vs_mirror(sec, seed):
     assert int(np.argmax(cutmax_exact(y, 3, 5.0, 3)[:x.size])) == int(np.argmax(x))
 
 
+def test_cutmax_config2_bit_exact(sec):
+    """the measured workload itself (the bench's 32000-logit input, T=3, p=3, c=5, degree-3
+    guess, d=3) at N = 2^16: every limb of Z equals the oracle's from the same seed and the
+    same encoded plaintext, and Z decrypts to the FP64 mirror within 1e-3"""
+    from paper_2509_08383_amd import he
+    say("[gpu] secure: CutMax T=3 on the bench input, bit-exact against the oracle")
+    x = llm_logits(0)
+    y, a, _ = slot_layout(x, sec.G.slots)
+    cfg, coef = cfg2(he)
+    g, o = sec.enc_values(y)
+    Zg = sec.G.cutmax([g], cfg)[0]
+    say(f"  GPU {sec.G.last_cutmax_ms():.1f} ms; running the oracle")
+    Zo = ckks.cutmax_he(sec.O, [o], ckks.HECfg(T=3, p=[3] * 3, c=[5.0] * 3, v_lo=VLO, v_hi=VHI, coef=coef,
+                                               sum_lo=1.0, sum_hi=3.0, gold_d=3))[0]
+    sec.same(Zg, Zo, "cutmax T=3")
+    assert Zg.level == sec.G.L - 27
+    dz = sec.G.decrypt(Zg, y.size)
+    assert np.abs(dz - cutmax_mirror(y, mirror2(y, coef))).max() < 1e-3
+    assert int(np.argmax(dz[:x.size])) == int(np.argmax(x))
+
+
 def test_cutmax_config3_batched(sec):
-    """16 requests, even ids 32000 logits (1 ciphertext), odd ids 128256 (4 ciphertexts)"""
+    """16 requests, even ids 32000 logits (1 ciphertext), odd ids 128256 (4 ciphertexts):
+    requests 0 (1 ciphertext) and 1 (4 ciphertexts) are encrypted from the same plaintexts
+    as the oracle's and their batched outputs equal the oracle's CutMax word for word; every
+    request decrypts to its FP64 mirror within 1e-3 and recovers its argmax"""
     from paper_2509_08383_amd import he
     say("[gpu] secure: batched 16 requests")
     xs = [llm_logits(200 + r, 32000 if r % 2 == 0 else 128256) for r in range(16)]
-    cts = [sec.G.encrypt(x) for x in xs]
-    sec.O.nonce = sec.O.nonce + sum(c.a for c in cts)
-    assert [c.a for c in cts] == [1, 4] * 8
     cfg, coef = cfg2(he)
+    ys = [slot_layout(x, sec.G.slots)[0] for x in xs]
+    # requests 0 and 1 through the pair (same plaintexts, counters in lockstep)
+    m0 = ckks.encode(ys[0], sec.O.N, sec.O.Delta)
+    g0 = sec.G.encrypt_coeffs(m0, sec.O.Delta, ys[0].size)
+    o0 = sec.O.encrypt_coeffs(m0, sec.O.Delta)
+    m1 = [ckks.encode(ys[1][k * sec.G.slots:(k + 1) * sec.G.slots], sec.O.N, sec.O.Delta) for k in range(4)]
+    g1 = sec.G.encrypt_coeffs(np.concatenate(m1), sec.O.Delta, ys[1].size)
+    o1 = [sec.O.encrypt_coeffs(m, sec.O.Delta) for m in m1]
+    rest = [sec.G.encrypt(x) for x in xs[2:]]
+    sec.O.nonce = sec.O.nonce + sum(c.a for c in rest)
+    cts = [g0, g1] + rest
+    assert [c.a for c in cts] == [1, 4] * 8
     Z = sec.G.cutmax(cts, cfg)
     say(f"  batch of 16: {sec.G.last_cutmax_ms():.1f} ms")
-    for r in (0, 1, 6, 15):
-        y, a, _ = slot_layout(xs[r], sec.G.slots)
-        dz = sec.G.decrypt(Z[r], y.size)
-        err = np.abs(dz - cutmax_mirror(y, mirror2(y, coef))).max()
+    for r in range(16):
+        dz = sec.G.decrypt(Z[r], ys[r].size)
+        err = np.abs(dz - cutmax_mirror(ys[r], mirror2(ys[r], coef))).max()
         assert err < 1e-3, (r, err)
         assert int(np.argmax(dz[:xs[r].size])) == int(np.argmax(xs[r])), r
-    # a batched request equals its single run bit for bit
-    for r in (0, 1):
-        Zs = sec.G.cutmax([cts[r]], cfg)[0]
-        assert np.array_equal(sec.G.export(Zs), sec.G.export(Z[r])), r
+    hc = ckks.HECfg(T=3, p=[3] * 3, c=[5.0] * 3, v_lo=VLO, v_hi=VHI, coef=coef, sum_lo=1.0, sum_hi=3.0, gold_d=3)
+    say("  oracle: request 0 (1 ciphertext)")
+    sec.same(Z[0], ckks.cutmax_he(sec.O, [o0], hc)[0], "batched request 0")
+    say("  oracle: request 1 (4 ciphertexts)")
+    Zo1 = ckks.cutmax_he(sec.O, o1, hc)
+    eg = sec.G.export(Z[1])
+    assert eg.shape[0] == 4
+    for k in range(4):
+        bad = int((eg[k] != Zo1[k].export()).sum())
+        assert bad == 0, f"batched request 1, ciphertext {k}: {bad} words differ"
+    assert Z[1].level == Zo1[0].level and Z[1].scale == Zo1[0].scale
 
 
 def test_goldschmidt_and_newton_refinements_at_full_size(sec):
