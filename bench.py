@@ -273,6 +273,68 @@ def boot_bench(he, args, x):
     return res
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_leg(prm, x, ctx, args):
+    """The oracle (plain C RNS-CKKS, OpenMP over limbs) timed on this host: the whole
+    T = 3 encrypted CutMax on the bench input at the default thread count, and one
+    top-level rotate-and-sum at one thread and at that thread count; the single-thread
+    CutMax time is the sample's single-thread time scaled by the CutMax/sample ratio
+    measured at the full thread count."""
+    from oracle import ckks
+    from oracle.cutmax_fp64 import chebyshev_invsqrt, slot_layout
+    L = ckks.lib()
+    threads = L.oc_num_threads()
+    O = ckks.Oracle(ckks.Params(prm.log_n, prm.n_q, prm.q0_bits, prm.q_bits, prm.p_bits, prm.dnum,
+                                prm.log2_scale, prm.seed, prm.hoist))
+    O.keygen_cutmax()
+    y, a, _ = slot_layout(x, O.slots)
+    oc = O.encrypt(y)
+    Ts = args.cpu_T
+    coef = [list(chebyshev_invsqrt(VLO[t] / VHI[t], 3)) for t in range(Ts)]
+    hc = ckks.HECfg(T=Ts, p=[P] * Ts, c=[C] * Ts, v_lo=VLO[:Ts], v_hi=VHI[:Ts], coef=coef, sum_lo=1.0,
+                    sum_hi=3.0)
+    c0 = time.perf_counter()
+    ckks.cutmax_he(O, [oc], hc)
+    sample_s = time.perf_counter() - c0
+    full = ks_cost(keyswitch_levels(ctx.L, T, 3, ctx.slots), ctx.alpha)
+    smp = ks_cost(keyswitch_levels(ctx.L, Ts, 3, ctx.slots), ctx.alpha)
+    cm_ms = sample_s * 1e3 * full / smp
+    what = ("the whole T=3 encrypted CutMax (Alg. 2)" if Ts == T else
+            f"a T={Ts} encrypted CutMax scaled by the level-weighted key-switch work ({full}/{smp} limb-NTTs)")
+    # one rotate-and-sum at the top level: all threads, then one thread
+    t0 = time.perf_counter()
+    O.rotsum(oc)
+    rs_all = time.perf_counter() - t0
+    L.oc_set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        O.rotsum(oc)
+        rs_one = time.perf_counter() - t0
+    finally:
+        L.oc_set_num_threads(threads)
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count()
+    return {"value": cm_ms, "unit": "ms", "cores": threads, "kind": "oracle",
+            "sample": f"{what} on the same 32000-logit input, one run, {sample_s:.2f} s at {threads} threads",
+            "single_thread_ms": cm_ms * rs_one / rs_all,
+            "single_thread_sample": f"one top-level rotate-and-sum (15 rotations as 5 hoisted steps): "
+                                    f"{rs_one:.2f} s at 1 thread, {rs_all:.2f} s at {threads} threads; "
+                                    f"the CutMax at 1 thread = CutMax at {threads} threads x that ratio",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(), "affinity_cpus": affinity}
+
+
 def batch_bench(ctx, cfg, args):
     """Batched argmaxes/s: 16 requests, even ids 32000 logits (1 ciphertext), odd ids 128256
     logits (4 ciphertexts), all advancing through one schedule (every launch covers the 40
@@ -439,31 +501,12 @@ def main():
     if not args.no_batch:
         batch = batch_bench(ctx, cfg, args)
 
-    # --- CPU oracle on a bounded sample: the T=1 schedule on the same input
+    # --- CPU oracle: the whole encrypted CutMax on the host's cores, and a bounded
+    # single-thread sample (one top-level rotate-and-sum) scaled by the same sample's
+    # all-core time
     cpu = None
     if not args.no_cpu_baseline:
-        from oracle import ckks
-        from oracle.cutmax_fp64 import chebyshev_invsqrt, slot_layout
-        O = ckks.Oracle(ckks.Params(prm.log_n, prm.n_q, prm.q0_bits, prm.q_bits, prm.p_bits, prm.dnum,
-                                    prm.log2_scale, prm.seed, prm.hoist))
-        O.keygen_cutmax()
-        y, a, _ = slot_layout(x, O.slots)
-        oc = O.encrypt(y)
-        Ts = args.cpu_T
-        coef = [list(chebyshev_invsqrt(VLO[t] / VHI[t], 3)) for t in range(Ts)]
-        hc = ckks.HECfg(T=Ts, p=[P] * Ts, c=[C] * Ts, v_lo=VLO[:Ts], v_hi=VHI[:Ts], coef=coef, sum_lo=1.0,
-                        sum_hi=3.0)
-        c0 = time.perf_counter()
-        ckks.cutmax_he(O, [oc], hc)
-        c1 = time.perf_counter()
-        sample_s = c1 - c0
-        full = ks_cost(keyswitch_levels(ctx.L, T, 3, ctx.slots), ctx.alpha)
-        smp = ks_cost(keyswitch_levels(ctx.L, Ts, 3, ctx.slots), ctx.alpha)
-        what = ("the whole T=3 encrypted CutMax (Alg. 2)" if Ts == T else
-                f"a T={Ts} encrypted CutMax scaled by the level-weighted key-switch work ({full}/{smp} limb-NTTs)")
-        cpu = {"value": sample_s * 1e3 * full / smp, "unit": "ms", "cores": ckks.lib().oc_num_threads(),
-               "kind": "oracle",
-               "sample": f"{what} on the same 32000-logit input, one run, {sample_s:.2f} s"}
+        cpu = cpu_baseline_leg(prm, x, ctx, args)
         log(f"[bench] cpu {cpu}")
 
     boot = None

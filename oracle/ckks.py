@@ -99,6 +99,8 @@ def lib():
         L.oc_ring_mul.argtypes = [V, ctypes.c_int, u64p, u64p, u64p]
         L.oc_philox4x32_10.argtypes = [ctypes.POINTER(ctypes.c_uint32)] * 3
         L.oc_num_threads.restype = ctypes.c_int
+        L.oc_set_num_threads.argtypes = [ctypes.c_int]
+        L.oc_set_num_threads.restype = None
         _lib = L
     return _lib
 

@@ -1026,3 +1026,12 @@ int oc_num_threads(void) {
     return 1;
 #endif
 }
+
+/* threads of the following parallel regions (timing at one thread and at all cores) */
+void oc_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

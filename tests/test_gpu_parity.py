@@ -381,6 +381,7 @@ def test_edge_inputs_are_rejected_or_handled(toy):
     assert e.value.code == he.HE_EINVAL
     x = toy_logits(43)
     a = toy.G.encrypt(x)
+    toy.O.nonce = toy.O.nonce + 1        # keep the counters in lockstep
     with pytest.raises(he.HeError) as e:
         toy.G.add(a, toy.G.drop(a, 3))
     assert e.value.code in (he.HE_ESTATE, he.HE_EINVAL)
@@ -401,7 +402,9 @@ def test_edge_inputs_are_rejected_or_handled(toy):
     p, c, vlo, vhi, coef = toy_cfg(y.size)
     cfg = he.CutmaxCfg(T=4, p=p, c=c, var_lo=vlo, var_hi=vhi, init_degree=3, init_coef=coef, sum_lo=1.0,
                        sum_hi=3.0, gold_d=3)
-    z = toy.G.decrypt(toy.G.cutmax([toy.G.encrypt(x)], cfg)[0], y.size)
+    ct = toy.G.encrypt(x)
+    toy.O.nonce = toy.O.nonce + 1
+    z = toy.G.decrypt(toy.G.cutmax([ct], cfg)[0], y.size)
     mc = MirrorCfg(T=4, p=p, c=c, v_hi=vhi, v_lo=vlo, coef=coef, B=3.0 * y.size, gold_d=3, sum_lo=1.0 * y.size)
     assert np.abs(z - cutmax_mirror(y, mc)).max() < 1e-3
     assert int(np.argmax(z[:x.size])) in (i, j)
@@ -474,13 +477,14 @@ def test_samplers_toy_bit_exact(toy, sampler, prescaled):
 
 
 def test_foreign_operands_and_bad_options_are_rejected(toy):
-    """a second operand from another context (another ring degree and limb stride) is
+    """a second operand from another context (another chain and limb stride) is
     refused with HE_EINVAL before any kernel runs, for add, sub and mul; an NTT variant out
     of range is refused, and a valid one drops the captured graphs (a later replay still
     equals the eager result)"""
     from paper_2509_08383_amd import he
     say("[gpu] foreign operands, option checks")
-    other = he.Context(he.Params(log_n=11, n_q=6, q0_bits=40, q_bits=30, p_bits=40, dnum=3, log2_scale=30, seed=5))
+    # the same ring degree with another chain: another limb stride and prime set
+    other = he.Context(he.Params(log_n=12, n_q=6, q0_bits=40, q_bits=30, p_bits=40, dnum=3, log2_scale=30, seed=5))
     a = toy.G.encrypt(np.ones(8))
     b = other.encrypt(np.ones(8))
     toy.O.nonce = toy.O.nonce + 1
