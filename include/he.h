@@ -255,6 +255,22 @@ int he_rotate(he_ctx *ctx, const he_ct *a, uint32_t r, he_ct **out);
 int he_rotsum(he_ctx *ctx, const he_ct *a, he_ct **out);
 int he_drop(he_ctx *ctx, const he_ct *a, uint32_t level, he_ct **out);
 
+/* he_rotsum for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, hosts that forbid hipMalloc): the same
+ * rotate-and-sum, written into the caller's existing handle `out` (from ctx,
+ * with as many ciphertexts as a; out may be a itself), whose level, scale and
+ * slot count become the result's.  Word for word equal to he_rotsum.  The call
+ * allocates nothing: its whole workspace is a static device array of 256 MiB
+ * that the library holds on every device it runs on until the process ends
+ * (its address is taken once per device by he_ctx_create).  One ciphertext at
+ * N = 2^16 needs at most 190 MiB at any level; a call that needs more returns
+ * HE_ENOMEM before any kernel runs.  Every call on one device shares that
+ * device's array: calls that overlap on one device (two threads, or two
+ * contexts on different streams) race, so serialise them.  The call returns
+ * after its kernels have finished.  Errors: HE_EINVAL for null or foreign
+ * handles or a count mismatch, HE_ENOMEM as above. */
+int he_rotsum_noalloc(he_ctx *ctx, const he_ct *a, he_ct *out);
+
 /* CKKS bootstrapping: a ciphertext whose levels are spent comes back at a high
  * level with the same slot values (the paper runs its deeper CutMax schedules,
  * T = 4 with p up to 16 (Sec. 4, Table 2), with bootstrapping, and App. B.1

@@ -16,6 +16,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -1649,6 +1650,34 @@ void ensure_workspace(he_ctx *C) {
     if (!P.iv.empty()) HIPCHK(hipMemcpyAsync(P.d_iv, P.iv.data(), P.iv.size() * 4, hipMemcpyHostToDevice, C->stream));
 }
 
+// Static scratch of the entry point that allocates nothing (he_rotsum_noalloc): the
+// whole workspace of one call (running sum, c0 gather, extended digits, key-product
+// accumulators, ModDown conversion) and its constants.  One ciphertext's rotate-and-sum
+// at N = 2^16 needs at most 190 MiB (top level of 30 primes with 10 special primes).
+// Each device holds its own copy, at the address hipGetSymbolAddress gives with that
+// device current; host code uses only that address, never the array's name.
+constexpr size_t kScratchBytes = 256ull << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+std::map<int, unsigned char *> g_scratch_ptr;  // device ordinal -> address of its scratch
+
+// once per device, with that device current (he_ctx_create)
+void scratch_setup(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr.count(device)) return;
+    void *p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    REQUIRE(p != nullptr, HE_EDEVICE, "no address for the static scratch");
+    g_scratch_ptr[device] = (unsigned char *)p;
+}
+
+unsigned char *scratch_of(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    REQUIRE(it != g_scratch_ptr.end(), HE_ESTATE, "static scratch not set up on this device");
+    return it->second;
+}
+
 // dry pass, upload, real pass
 template <class Body>
 void run2(he_ctx *C, Body &&body) {
@@ -2363,6 +2392,7 @@ int he_ctx_create(const he_params *prm, he_ctx **out) {
         REQUIRE(ndev > 0, HE_EDEVICE, "no HIP device");
         REQUIRE(prm->device >= 0 && prm->device < ndev, HE_EINVAL, "bad device ordinal");
         HIPCHK(hipSetDevice(prm->device));
+        scratch_setup(prm->device);
         if (prm->stream) C->stream = (hipStream_t)prm->stream;
         else { HIPCHK(hipStreamCreateWithFlags(&C->stream, hipStreamNonBlocking)); C->own_stream = true; }
         HIPCHK(hipEventCreate(&C->ev0));
@@ -2686,6 +2716,61 @@ int he_rotate(he_ctx *C, const he_ct *a, uint32_t r, he_ct **out) {
 }
 int he_rotsum(he_ctx *C, const he_ct *a, he_ct **out) {
     return prim(C, a, out, [&](Exec &X) { return X.rotsum(bt_of(a)); }, true);
+}
+int he_rotsum_noalloc(he_ctx *C, const he_ct *a, he_ct *out) {
+    return guarded([&]() {
+        REQUIRE(C && a && out && a->ctx == C && out->ctx == C, HE_EINVAL, "null or foreign argument");
+        REQUIRE(out->a == a->a, HE_EINVAL, "out must hold as many ciphertexts as a");
+        unsigned char *base = scratch_of(C->device);
+        HIPCHK(hipSetDevice(C->device));
+        // this call's workspace and constants live in the scratch; the context's own
+        // (hipMalloc'd) arena and pool are set aside and restored afterwards
+        struct Restore {
+            he_ctx *C;
+            Arena a;
+            Pool p;
+            ~Restore() { C->arena = a; C->pool = std::move(p); }
+        } keep{C, C->arena, std::move(C->pool)};
+        C->arena = Arena{};
+        C->pool = Pool{};
+        {
+            Exec X(C, true);
+            (void)X.rotsum(bt_of(a));
+        }
+        const size_t dbytes = (C->pool.dv.size() * 8 + 255) & ~(size_t)255;
+        const size_t ibytes = (C->pool.iv.size() * 4 + 255) & ~(size_t)255;
+        const size_t need = ((C->arena.peak + 255) & ~(size_t)255) + dbytes + ibytes;
+        if (need > kScratchBytes)
+            throw HeError(HE_ENOMEM, "he_rotsum_noalloc: the call needs " + std::to_string(need >> 20) +
+                                         " MiB of scratch; the static scratch holds " +
+                                         std::to_string(kScratchBytes >> 20) + " MiB");
+        const size_t wcap = kScratchBytes - dbytes - ibytes;
+        C->arena.base = (char *)base;
+        C->arena.cap = wcap;
+        C->arena.dry = false;
+        C->arena.top = 0;
+        C->pool.d_dv = (double *)(base + wcap);
+        C->pool.d_iv = (int *)(base + wcap + dbytes);
+        C->pool.dcap = dbytes / 8;
+        C->pool.icap = ibytes / 4;
+        C->pool.dry = false;
+        C->pool.dpos = C->pool.ipos = 0;
+        if (!C->pool.dv.empty())
+            HIPCHK(hipMemcpyAsync(C->pool.d_dv, C->pool.dv.data(), C->pool.dv.size() * 8, hipMemcpyHostToDevice,
+                                  C->stream));
+        if (!C->pool.iv.empty())
+            HIPCHK(hipMemcpyAsync(C->pool.d_iv, C->pool.iv.data(), C->pool.iv.size() * 4, hipMemcpyHostToDevice,
+                                  C->stream));
+        Exec X(C, false);
+        Bt r = X.rotsum(bt_of(a));
+        store_bt(X, r, 0, out);
+        out->n = a->n;
+        out->pad = a->pad;
+        HIPCHK(hipGetLastError());
+        // the scratch is free again when the call returns
+        HIPCHK(hipStreamSynchronize(C->stream));
+        return HE_OK;
+    });
 }
 int he_drop(he_ctx *C, const he_ct *a, uint32_t level, he_ct **out) {
     return prim(C, a, out, [&](Exec &X) { return X.copy(X.drop(bt_of(a), (int)level)); }, true);

@@ -95,6 +95,7 @@ def lib():
             "he_cmul": [_V, _V, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.POINTER(_V)],
             "he_rotate": [_V, _V, ctypes.c_uint32, ctypes.POINTER(_V)],
             "he_rotsum": [_V, _V, ctypes.POINTER(_V)],
+            "he_rotsum_noalloc": [_V, _V, _V],
             "he_drop": [_V, _V, ctypes.c_uint32, ctypes.POINTER(_V)],
             "he_bench_ntt": [_V, ctypes.c_uint32, ctypes.c_uint32, _c_dp, _c_dp],
             "he_bench_copy": [_V, ctypes.c_uint32, ctypes.c_uint32, _c_dp],
@@ -385,6 +386,11 @@ class Context:
 
     def drop(self, a, level: int):
         return self._op("he_drop", a.h, int(level))
+
+    def rotsum_noalloc(self, a, out):
+        """rotate-and-sum of a into the existing handle out, with no device allocation"""
+        _check(lib().he_rotsum_noalloc(self.h, a.h, out.h))
+        return out
 
     # bootstrapping -------------------------------------------------------------
     def boot_setup(self, cfg: BootCfg):
