@@ -608,7 +608,9 @@ def cutmax_he(O: Oracle, Y: List[Ct], cfg: HECfg, rotsum_cache=None, n_real: int
     The pad slots all hold one common value, which a tracker ciphertext follows through
     the same steps (it starts as the trivial encryption of the pad value); every slot
     sum subtracts (pad slot count) x tracker, and the variance sum subtracts the same
-    multiple of the tracker's square."""
+    multiple of the tracker's square, formed as the square of sqrt(pad slot count) times
+    the tracker's centred value (the same quantity, without multiplying the product's
+    rounding noise by the pad count)."""
     a = len(Y)
     masked = n_real is not None and n_real < a * O.slots
     n = n_real if masked else a * O.slots
@@ -626,10 +628,13 @@ def cutmax_he(O: Oracle, Y: List[Ct], cfg: HECfg, rotsum_cache=None, n_real: int
         D = [O.sub(O.mul_int(y, n), S) for y in Yall]
         kE = 1.0 / (float(n) * math.sqrt(float(n) * cfg.v_hi[t]))
         E = [O.cm_exact(d, kE, O.Delta) for d in D]
-        F = [O.mul(e, e) for e in E]
-        U = O.rotsum(O.sum_list(F[:a]))
+        F = [O.mul(e, e) for e in E[:a]]
+        U = O.rotsum(O.sum_list(F))
         if masked:
-            U = O.sub(U, O.mul_int(F[a], npad))
+            # the pad slots' share npad E_R^2, evaluated as (sqrt(npad) E_R)^2 so that the
+            # product's rounding noise is not multiplied by npad
+            Ep = O.cm_target(D[a], kE * math.sqrt(float(npad)), E[a].scale)
+            U = O.sub(U, O.mul(Ep, Ep))
         C = math.sqrt(float(n)) / cfg.c[t]
         lh = U.level - invsqr_depth(len(cfg.coef[t]) - 1, cfg.newton, cfg.goldschmidt)
         if lh < 1:

@@ -1074,9 +1074,29 @@ Bt cutmax_sched(Exec &X, Bt Y, const std::vector<Request> &reqs, const CutmaxCfg
         std::vector<double> kE(Y.cnt), dl(Y.cnt, C->Delta);
         for (int k = 0; k < Y.cnt; ++k) kE[k] = 1.0 / ((double)nct[k] * std::sqrt((double)nct[k] * cf.vhi[t]));
         Bt E = X.cmul(D, kE, dl, true);
-        Bt F = X.mul(E, E);
-        Bt U = X.rotsum(X.sum_groups(F, first, cnt));
-        if (ntrk) U = X.sub_mul_map(U, trackers(F), npad, tidx);
+        Bt U;
+        if (ntrk) {
+            // the pad slots' share npad F_R of the variance sum is formed as (sqrt(npad) E_R)^2:
+            // the product's noise is then not multiplied by npad (up to 1.2e4 for 151936 logits
+            // in 5 ciphertexts), as it would be in npad (E_R^2)
+            Bt Em = E;
+            Em.cnt = total;
+            Em.scale.resize(total);
+            const Bt Dt = trackers(D), Et = trackers(E);
+            std::vector<double> kt(ntrk), st(ntrk);
+            for (int r = 0; r < R; ++r)
+                if (tmap[r] >= 0) {
+                    kt[tidx[r]] = kE[tmap[r]] * std::sqrt((double)npad[r]);
+                    st[tidx[r]] = Et.scale[tidx[r]];
+                }
+            Bt Ep = X.cmul(Dt, kt, st, false);
+            Bt Ft = X.mul(Ep, Ep);
+            Bt F = X.mul(Em, Em);
+            U = X.sub_mul_map(X.rotsum(X.sum_groups(F, first, cnt)), Ft, std::vector<int64_t>(R, 1), tidx);
+        } else {
+            Bt F = X.mul(E, E);
+            U = X.rotsum(X.sum_groups(F, first, cnt));
+        }
         const int lh = U.level - invsqr_depth((int)cf.coef[t].size() - 1, cf.newton, cf.gold_refine);
         REQUIRE(lh >= 1, HE_EDEPTH, "chain too short");
         std::vector<double> Cc(R), SH(R);
