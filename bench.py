@@ -335,6 +335,87 @@ def cpu_baseline_leg(prm, x, ctx, args):
             "cpu_model": cpu_model(), "nproc": os.cpu_count(), "affinity_cpus": affinity}
 
 
+def learned_bench(he, ctx, args):
+    """The learned inverse-square-root initial guess against the fixed schedule.
+
+    args.learned_runs plaintext CutMax runs (Alg. 1, T = 3, p = 3, c = 5) on LLM-like
+    logits with a per-run Gumbel scale U[1.5, 4.5] and Zipf exponent U[0.9, 1.3] are
+    logged on the GPU (one variance per iteration per run); per iteration one network
+    (1-16-16-1, square activations, FP32, the library's kernels) is trained on 80% of the
+    runs and collapsed to its quartic; the held-out 20% give each guess's RMS relative
+    error of u^(-1/2) and the depth the fixed Chebyshev + Newton schedule needs to match
+    the learned error.  Then 16 requests of 32000 logits at N = 2^16 (seeds disjoint from
+    the logged runs) run the learned schedule (degree-4 guess, depth 3) and the fixed one
+    (degree-3 Chebyshev guess, depth 2): levels left, ms per batch, argmax agreement."""
+    from workloads import llm_logits_var
+    vlo, vhi = [5.0, 0.4, 0.7], [48.0, 1.0, 64.0]
+    t0 = time.perf_counter()
+    v, _ = he.variance_log(seed=7, runs=args.learned_runs)
+    t_log = time.perf_counter() - t0
+    log(f"[bench] logged {v.size} variances in {t_log:.1f} s")
+
+    def pe(c, u):
+        acc = np.zeros_like(u)
+        for a in c[::-1]:
+            acc = acc * u + a
+        return acc
+
+    def rms(h, u):
+        return float(np.sqrt(np.mean((h * np.sqrt(u) - 1.0) ** 2)))
+
+    depth_of = {1: 1, 2: 2, 3: 2, 4: 3}
+    coefs, per_t = [], []
+    t_train = 0.0
+    for t in range(3):
+        inside = (v[:, t] >= vlo[t]) & (v[:, t] <= vhi[t])
+        u = (v[inside, t] / vhi[t]).astype(np.float32)
+        ntr = int(0.8 * u.size)
+        M = he.InvSqrtMLP(seed=7 + t)
+        t1 = time.perf_counter()
+        loss = M.train(u[:ntr], epochs=args.learned_epochs, batch=1024, lr=1e-2, seed=7)
+        t_train += time.perf_counter() - t1
+        c = M.to_poly()
+        coefs.append([float(a) for a in c])
+        ut = u[ntr:].astype(np.float64)
+        e_l = rms(pe(c, ut), ut)
+        e_f = rms(pe(he.invsqrt_guess_fit(vlo[t] / vhi[t], 3), ut), ut)
+        # the fixed schedule that reaches the learned error: Chebyshev degree d + k Newton steps
+        match = None
+        for d in (1, 2, 3, 4):
+            h = pe(he.invsqrt_guess_fit(vlo[t] / vhi[t], d), ut)
+            for k in range(4):
+                if rms(h, ut) <= e_l and (match is None or depth_of[d] + 2 * k < match[0]):
+                    match = (depth_of[d] + 2 * k, d, k)
+                h = 1.5 * h - 0.5 * ut * h ** 3
+        per_t.append({"iteration": t, "variances_in_domain": int(inside.sum()), "train_samples": ntr,
+                      "train_loss": loss, "heldout_rms_learned_deg4": e_l, "heldout_rms_chebyshev_deg3": e_f,
+                      "fixed_depth_to_match_learned": match[0] if match else None,
+                      "fixed_schedule_to_match": f"degree {match[1]} + {match[2]} Newton" if match else None})
+    log(f"[bench] learned guesses trained in {t_train:.1f} s: {per_t}")
+    xs = [llm_logits_var(5000 + r) for r in range(16)]
+    cts = [ctx.encrypt(x) for x in xs]
+    out = {}
+    for name, deg, coef in (("learned", 4, coefs), ("fixed", 3, None)):
+        cfg = he.CutmaxCfg(T=3, p=[3] * 3, c=[5.0] * 3, var_lo=vlo, var_hi=vhi, init_degree=deg, init_coef=coef,
+                           sum_lo=1.0, sum_hi=3.0, gold_d=2)
+        ctx.cutmax(cts, cfg)
+        ctx.sync()
+        t1 = time.perf_counter()
+        Z = ctx.cutmax(cts, cfg)
+        ctx.sync()
+        ms = (time.perf_counter() - t1) * 1e3
+        picks = [int(np.argmax(ctx.decrypt(Z[r], xs[r].size))) for r in range(16)]
+        ok = sum(int(picks[r] == int(np.argmax(xs[r]))) for r in range(16))
+        out[name] = {"init_degree": deg, "guess_depth": depth_of[deg], "levels_used": ctx.L - Z[0].level,
+                     "levels_left": Z[0].level, "ms_per_batch16": ms, "argmax_agreement": f"{ok}/16",
+                     "picks": picks}
+        del Z
+    return {"logged_runs": args.learned_runs, "logged_variances": int(v.size), "log_s": t_log,
+            "train_s": t_train, "epochs": args.learned_epochs, "domains": {"var_lo": vlo, "var_hi": vhi},
+            "per_iteration": per_t, "batch16": out,
+            "same_picks": out["learned"]["picks"] == out["fixed"]["picks"]}
+
+
 def batch_bench(ctx, cfg, args):
     """Batched argmaxes/s: 16 requests, even ids 32000 logits (1 ciphertext), odd ids 128256
     logits (4 ciphertexts), all advancing through one schedule (every launch covers the 40
@@ -379,6 +460,10 @@ def main():
     ap.add_argument("--boot-only", action="store_true",
                     help="only the bootstrapping measurements (profiling runs of the bootstrap)")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-guess measurement")
+    ap.add_argument("--learned-runs", type=int, default=1000000,
+                    help="plaintext CutMax runs logged for the learned guess (one variance per iteration each)")
+    ap.add_argument("--learned-epochs", type=int, default=10)
     ap.add_argument("--graph", type=int, default=1,
                     help="replay each CutMax from a captured HIP graph (1) or launch eagerly (0)")
     ap.add_argument("--hoist", type=int, default=None,
@@ -501,6 +586,12 @@ def main():
     if not args.no_batch:
         batch = batch_bench(ctx, cfg, args)
 
+    # --- the learned initial guess against the fixed schedule (16 requests)
+    learned = None
+    if not args.no_learned and not args.no_batch:
+        learned = learned_bench(he, ctx, args)
+        log(f"[bench] learned {learned['batch16']}")
+
     # --- CPU oracle: the whole encrypted CutMax on the host's cores, and a bounded
     # single-thread sample (one top-level rotate-and-sum) scaled by the same sample's
     # all-core time
@@ -535,10 +626,12 @@ def main():
         "src_digest": digest,
         "argmax_ok": bool(argmax_ok),
         "batched": batch,
+        "learned_guess": learned,
         "vocab_151936": vocab_151936,
         "ntt": ntt,
         "copy": copy,
         "ntt_tuning": ctx.ntt_tuning(),
+        "ntt_tuning_report": ctx.ntt_tuning_report(),
         "roofline": roof,
         "kernels": {k: {"launches": v[0], "ms": v[1], "bytes": v[2]} for k, v in kern.items()},
         "cpu_baseline": cpu,

@@ -201,6 +201,13 @@ int he_topp_sample(he_ctx *ctx, he_ct *const *logits, he_ct *const *noise, size_
  * alpha = ln(1 - top_p)/ln(top_p), from the caller's uniform draws u. */
 int he_topp_noise(double top_p, const double *u, size_t n, double *g);
 
+/* Host helper: the fixed initial guess of the inverse square root (Alg. 2 line 5;
+ * Sec. 3.2 (ii) evaluates it on a known domain): the power-basis coefficients
+ * coef[0..degree] (host memory, degree + 1 doubles) of the polynomial of degree
+ * 1..4 interpolating u^(-1/2) at the Chebyshev nodes of [u_lo, 1], 0 < u_lo < 1,
+ * the guess he_cutmax uses when init_coef is NULL.  No GPU needed. */
+int he_invsqrt_guess_fit(double u_lo, uint32_t degree, double *coef);
+
 /* Server: Gumbel-max sampling (Sec. 3.3, "Using Gumbel Distribution" and the
  * Gumbel-max lemma): CutMax(X + temperature * G), G the client's encrypted
  * Gumbel(0,1) noise (see he_gumbel_noise); the one-hot approximates a draw
@@ -371,10 +378,19 @@ int he_profile_end(he_ctx *ctx, char *buf, size_t cap);
 #define HE_OPT_BOOT_HOIST 3
 int he_set_option(he_ctx *ctx, int option, int64_t value);
 
-/* NTT autotuner result: the workgroup-width variant (1: 4 or 8 sub-transforms
- * per workgroup, 2: 8 or 16, 3: 16 or 32 for N = 2^16 / 2^12) chosen for batch
- * buckets of <=16, <=64, <=256, <=1024, ... vectors (n entries, at most 8). */
+/* NTT autotuner result: the schedule variant chosen for batch buckets of <=4,
+ * <=16, <=64, <=256, <=1024, <=4096, ... vectors (n entries, at most 8).  Variant v =
+ * 1..6 is a workgroup width ((v - 1) % 3: 4, 8 or 16 sub-transforms per workgroup
+ * at N = 2^16, 8, 16 or 32 at 2^12) and a pass-2 twiddle form ((v - 1) / 3: 0 the
+ * full table, 1 phase-B twiddles formed as products of a row word and a small-table
+ * word); every variant gives the same output word for word. */
 int he_ntt_tuning(const he_ctx *ctx, int32_t *variants, uint32_t n);
+
+/* Every candidate the autotuner timed, as JSON in buf (cap bytes, NUL-terminated):
+ * {"logN", "variants": [names], "buckets": [{"vectors", "ms": [one forward +
+ * inverse pair per variant, best of 3 trials], "choice"}]}.  HE_EINVAL when cap is
+ * too small. */
+int he_ntt_tuning_report(const he_ctx *ctx, char *buf, size_t cap);
 
 /* ---------------------------------------------------------------------------
  * Learned initial guess for the inverse square root of Alg. 2 line 5 (an

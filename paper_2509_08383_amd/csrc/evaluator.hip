@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -291,11 +292,9 @@ struct Exec {
         for (int i = 0; i < a.cnt; ++i) v[i] = llround_d(c[i] * a.scale[i]);
         Bt o = new_bt(a.cnt, a.level);
         o.scale = a.scale;
-        ConstTab kt{residues(v, a.level), 1, a.level + 1};
-        if (go()) {
-            launch_add_const(T, vs_poly(o, 0), vs_poly(a, 0), kt, s);
-            launch_copy(T, vs_poly(o, 1), vs_poly(a, 1), s);
-        }
+        // one launch: the constant onto polynomial 0, polynomial 1 copied
+        ConstTab kt{residues(v, a.level), 2, a.level + 1};
+        if (go()) launch_add_const(T, vs_all(o), vs_all(a), kt, s, 1);
         return o;
     }
     // D_k = n_k * Y_k - S[map[k]]
@@ -353,9 +352,12 @@ struct Exec {
     // (K a - [K a_l]_centred) / q_l per limb; kres (per ct, limbs 0..l) = K mod q_i, or
     // null for a plain rescale.  The lift of the last limb to the other primes is
     // computed while loading the forward NTT, and the combine happens on its store.
-    Bt rescale(const Bt &a, const double *kres = nullptr) {
+    // With K (the integers behind kres, one per ciphertext) the inverse NTT of the last limb
+    // applies K together with N^-1 (INTT(K c) = K INTT(c)), so no separate multiply runs.
+    Bt rescale(const Bt &a, const double *kres = nullptr, const std::vector<int64_t> *K = nullptr) {
         const int l = a.level;
         REQUIRE(l >= 1, HE_EDEPTH, "rescale at level 0");
+        REQUIRE(!kres == !K, HE_EINVAL, "rescale: residues and integers go together");
         Bt o = new_bt(a.cnt, l - 1);
         for (int c = 0; c < a.cnt; ++c) o.scale[c] = a.scale[c] / (double)C->q[l];
         const size_t m = C->arena.mark();
@@ -363,14 +365,23 @@ struct Exec {
         const long long N = C->N;
         double *last = alloc_d((size_t)G * N);
         double *lift = alloc_d((size_t)G * l * N);
+        const double *kscale = nullptr;
+        const int *lprime = nullptr;
+        if (kres) {
+            // per vector (ciphertext, polynomial): N^-1 K mod q_l
+            const uint64_t ql = C->q[l], ninv = invmod_u((uint64_t)N % ql, ql);
+            std::vector<double> ks(G);
+            for (int g = 0; g < G; ++g) ks[g] = (double)mulmod_u(ninv, red_i64((*K)[g >> 1], ql), ql);
+            kscale = C->pool.push(ks);
+            lprime = C->pool.push(std::vector<int>(G, l));
+        }
         if (go()) {
             VecSet src{a.d + (long long)l * N, G, 1, (long long)a.cap * N, nullptr, C->ident + l};
-            VecSet dst{last, G, 1, N, nullptr, C->ident + l};
             if (kres) {
-                launch_mul_const(T, dst, src, ConstTab{kres + l, 2, l + 1}, s);
-                launch_ntt(T, dst, true, C->ntt_variant, s);
+                // one group of G vectors, every one modulo q_l, scaled per vector
+                launch_ntt(T, VecSet{last, G, G, 0, nullptr, lprime}, true, C->ntt_variant, s, &src, kscale);
             } else {
-                launch_ntt(T, dst, true, C->ntt_variant, s, &src);
+                launch_ntt(T, VecSet{last, G, 1, N, nullptr, C->ident + l}, true, C->ntt_variant, s, &src);
             }
             NttPro pro{1, last, N, (double)C->q[l]};
             NttEpi epi{};
@@ -544,7 +555,7 @@ struct Exec {
             K[c] = llround_d(x);
             REQUIRE(K[c] != 0 && std::llabs(K[c]) < (1LL << 62), HE_ERANGE, "constant not encodable");
         }
-        Bt o = rescale(a, residues(K, l));
+        Bt o = rescale(a, residues(K, l), &K);
         for (int c = 0; c < a.cnt; ++c)
             o.scale[c] = exact ? ((a.scale[c] * (double)K[c]) / q) / kappa[c] : s_want[c];
         return o;
@@ -2085,35 +2096,41 @@ void keygen(he_ctx *C) {
     gen_keys(C, 0);
 }
 
-// NTT autotuner: times every workgroup-width variant of the forward + inverse
-// transform at batch sizes 16, 64, 256 and 1024 vectors on random residues and
-// keeps the fastest per batch bucket (larger batches use the 1024 choice).  Runs
-// once per process and ring degree; the choice is also kept in the context.
+// NTT autotuner: times every schedule variant (workgroup width x pass-2 twiddle
+// form, NTT_VARIANTS in all) of the forward + inverse transform on random residues at
+// one batch size per bucket (about 4, 16, 64, 256, 1024 and 4096 vectors, whole groups of
+// the chain's primes as the evaluator's batches are) and keeps the fastest per bucket
+// (larger batches use the 4096 choice).  Every candidate's time is kept for
+// he_ntt_tuning_report.  Runs once per process and ring degree.
+constexpr int kTuneBuckets = 6;
 int g_tuned_logN[2] = {0, 0};
 int g_tuned_choice[2][8];
+int g_tuned_count[2][kTuneBuckets];
+double g_tuned_ms[2][kTuneBuckets][NTT_VARIANTS];
 
 void autotune_ntt(he_ctx *C) {
     const int li = C->logN == 16 ? 1 : 0;
     if (!g_tuned_logN[li]) {
-        const int counts[4] = {16, 64, 256, 1024};
-        const int N = C->N;
+        const int target[kTuneBuckets] = {4, 16, 64, 256, 1024, 4096};
+        const int N = C->N, grp = C->L + 1;
         double *buf = nullptr;
-        HIPCHK(hipMalloc(&buf, 8ull * 1024 * N));
+        HIPCHK(hipMalloc(&buf, 8ull * target[kTuneBuckets - 1] * N));
         hipEvent_t a, b;
         HIPCHK(hipEventCreate(&a));
         HIPCHK(hipEventCreate(&b));
-        const int grp = C->L + 1;
-        for (int ci = 0; ci < 4; ++ci) {
-            const int cnt = counts[ci];
-            const VecSet vs{buf, cnt, std::min(cnt, grp), (long long)std::min(cnt, grp) * N, nullptr, nullptr};
+        for (int ci = 0; ci < kTuneBuckets; ++ci) {
+            const int g = std::min(target[ci], grp), cnt = (target[ci] / g) * g;
+            g_tuned_count[li][ci] = cnt;
+            const VecSet vs{buf, cnt, g, (long long)g * N, nullptr, nullptr};
             launch_sample_uniform(C->T, vs, 99, 0x7E000000u, nullptr, C->stream);
             double best = 1e30;
             int bestv = 3;
-            for (int v = 1; v <= 3; ++v) {
+            for (int v = 1; v <= NTT_VARIANTS; ++v) {
                 launch_ntt(C->T, vs, false, v, C->stream);
                 launch_ntt(C->T, vs, true, v, C->stream);
                 // the best of 3 trials of 4 transform pairs each (small batches vary from
                 // run to run by a few microseconds)
+                double vbest = 1e30;
                 for (int trial = 0; trial < 3; ++trial) {
                     HIPCHK(hipEventRecord(a, C->stream));
                     for (int rep = 0; rep < 4; ++rep) {
@@ -2124,12 +2141,14 @@ void autotune_ntt(he_ctx *C) {
                     HIPCHK(hipEventSynchronize(b));
                     float ms = 0;
                     HIPCHK(hipEventElapsedTime(&ms, a, b));
-                    if (ms < best) { best = ms; bestv = v; }
+                    vbest = std::min(vbest, ms / 4.0);
                 }
+                g_tuned_ms[li][ci][v - 1] = vbest;
+                if (vbest < best) { best = vbest; bestv = v; }
             }
             g_tuned_choice[li][ci] = bestv;
         }
-        for (int bk = 4; bk < 8; ++bk) g_tuned_choice[li][bk] = g_tuned_choice[li][3];
+        for (int bk = kTuneBuckets; bk < 8; ++bk) g_tuned_choice[li][bk] = g_tuned_choice[li][kTuneBuckets - 1];
         hipEventDestroy(a);
         hipEventDestroy(b);
         hipFree(buf);
@@ -2613,6 +2632,15 @@ int he_gumbel_noise(const double *u, size_t n, double *g) {
     });
 }
 
+int he_invsqrt_guess_fit(double u_lo, uint32_t degree, double *coef) {
+    return guarded([&]() {
+        REQUIRE(coef && u_lo > 0 && u_lo < 1 && degree >= 1 && degree <= 4, HE_EINVAL,
+                "u_lo in (0, 1), degree 1..4, coef non-null");
+        chebyshev_invsqrt_fit(u_lo, (int)degree, coef);
+        return HE_OK;
+    });
+}
+
 void he_ct_free(he_ct *ct) {
     if (!ct) return;
     if (ct->d) hipFree(ct->d);
@@ -2987,6 +3015,31 @@ int he_ntt_tuning(const he_ctx *C, int32_t *variants, uint32_t n) {
     if (!C || !variants) { g_err = "null argument"; return HE_EINVAL; }
     const int li = C->logN == 16 ? 1 : 0;
     for (uint32_t i = 0; i < n && i < 8; ++i) variants[i] = g_tuned_choice[li][i];
+    return HE_OK;
+}
+
+int he_ntt_tuning_report(const he_ctx *C, char *buf, size_t cap) {
+    if (!C || !buf || cap == 0) { g_err = "null argument"; return HE_EINVAL; }
+    const int li = C->logN == 16 ? 1 : 0;
+    const int w[3] = {C->logN == 16 ? 4 : 8, C->logN == 16 ? 8 : 16, C->logN == 16 ? 16 : 32};
+    std::string js = "{\"logN\":" + std::to_string(C->logN) + ",\"variants\":[";
+    for (int v = 1; v <= NTT_VARIANTS; ++v) {
+        js += std::string(v > 1 ? "," : "") + "\"" + std::to_string(w[(v - 1) % 3]) + " sub-transforms per workgroup, " +
+              ((v - 1) / 3 ? "factored" : "table") + " pass-2 twiddles\"";
+    }
+    js += "],\"buckets\":[";
+    for (int b = 0; b < kTuneBuckets; ++b) {
+        char tmp[64];
+        js += std::string(b ? "," : "") + "{\"vectors\":" + std::to_string(g_tuned_count[li][b]) + ",\"ms\":[";
+        for (int v = 0; v < NTT_VARIANTS; ++v) {
+            std::snprintf(tmp, sizeof tmp, "%s%.5f", v ? "," : "", g_tuned_ms[li][b][v]);
+            js += tmp;
+        }
+        js += "],\"choice\":" + std::to_string(g_tuned_choice[li][b]) + "}";
+    }
+    js += "]}";
+    if (js.size() + 1 > cap) { g_err = "buffer too small"; return HE_EINVAL; }
+    std::memcpy(buf, js.c_str(), js.size() + 1);
     return HE_OK;
 }
 

@@ -72,7 +72,7 @@ void kprof_set_bytes(double algorithmic_bytes);  // for the next launch
     } while (0)
 
 // NTT schedule tuning (ntt.hip): variant 1..NTT_VARIANTS per (log N, batch bucket)
-constexpr int NTT_VARIANTS = 3;
+constexpr int NTT_VARIANTS = 6;
 void set_ntt_tuning(int logN, int bucket, int variant);
 
 // ---------------------------------------------------------------- kernels.hip
@@ -120,7 +120,7 @@ void launch_copy(const DevTables &T, const VecSet &out, const VecSet &a, hipStre
 void launch_mul_const(const DevTables &T, const VecSet &out, const VecSet &a, ConstTab k,
                       hipStream_t s);
 void launch_add_const(const DevTables &T, const VecSet &out, const VecSet &a, ConstTab k,
-                      hipStream_t s);
+                      hipStream_t s, int c0only = 0);
 void launch_axpy_map(const DevTables &T, const VecSet &out, const VecSet &a, ConstTab k,
                      const VecSet &b, const int *bmap, int bdiv, hipStream_t s);
 void launch_sub_mul_map(const DevTables &T, const VecSet &out, const VecSet &a, ConstTab k, const VecSet &b,

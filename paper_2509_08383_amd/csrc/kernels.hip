@@ -106,18 +106,19 @@ void launch_mul_const(const DevTables &T, const VecSet &out, const VecSet &a, Co
 }
 
 // adds the constant to every NTT-domain coefficient (a constant polynomial
-// evaluates to itself at every root)
-__global__ void k_add_const(VecSet out, VecSet a, ConstTab k, DevTables T) {
+// evaluates to itself at every root); with c0only the groups are (ciphertext,
+// polynomial) pairs and only polynomial 0 gets the constant, polynomial 1 is copied
+__global__ void k_add_const(VecSet out, VecSet a, ConstTab k, DevTables T, int c0only) {
     EW_PROLOGUE
     double *pa; int q1, g1, r1;
     vs_at(a, blockIdx.y, T.N, pa, q1, g1, r1);
-    po[x] = addm(pa[x], ct_val(k, g, r), p);
+    po[x] = (c0only && (g & 1)) ? pa[x] : addm(pa[x], ct_val(k, g, r), p);
 }
 void launch_add_const(const DevTables &T, const VecSet &out, const VecSet &a, ConstTab k,
-                      hipStream_t s) {
+                      hipStream_t s, int c0only) {
     if (out.count <= 0) return;
     kprof_set_bytes(16.0 * T.N * out.count);
-    KL("k_add_const", k_add_const, ew_grid(T, out.count), dim3(256), 0, s, out, a, k, T);
+    KL("k_add_const", k_add_const, ew_grid(T, out.count), dim3(256), 0, s, out, a, k, T, c0only);
 }
 
 // out = a * k - b[map]   (b group index = bmap[g / bdiv] * bdiv + g % bdiv)
@@ -482,9 +483,10 @@ void launch_modup(const DevTables &T, const double *v, long long vstride, double
 // the two words (polynomials 0, 1) of digit j of limb t at position x: hi 2^32 + lo,
 // exact (below 2^48); one 8-byte load of the low halves, one 4-byte load of the high
 DEV void key_pair(const KeyRef &k, int betaL, int t, int j, int N, int x, double &k0, double &k1) {
-    const long long i = (((long long)t * betaL + j) * N + x) * 2;
-    const uint2 l = *(const uint2 *)(k.lo + i);
-    const uint32_t h = *(const uint32_t *)(k.hi + i);
+    // the row offset is uniform across the wave, the position a 32-bit per-lane index
+    const long long row = ((long long)t * betaL + j) * N * 2;
+    const uint2 l = ((const uint2 *)(k.lo + row))[(unsigned)x];
+    const uint32_t h = ((const uint32_t *)(k.hi + row))[(unsigned)x];
     k0 = __builtin_fma((double)(h & 0xffffu), 4294967296.0, (double)l.x);
     k1 = __builtin_fma((double)(h >> 16), 4294967296.0, (double)l.y);
 }
@@ -568,17 +570,18 @@ void launch_inner_product(const DevTables &T, const double *ext, long long estri
 // b mod 8); every XCD is given whole targets t and walks a target's x-blocks in the
 // order of their pi-orbits (rs.xorder), so consecutive workgroups on an XCD share all
 // but one of their source blocks and re-read them from L2.
-// BETA > 0 fixes the digit count at compile time, so the loads of all digits of a
-// rotation are issued together before the first product waits on them; BETA = 0
-// reads the runtime beta (at most 8).
-template <int BETA>
-__global__ __launch_bounds__(256) void k_inner_product_rot(DevTables T, const double *__restrict__ ext,
-                                                           long long esb, long long esj, double *__restrict__ acc0,
-                                                           double *__restrict__ acc1, long long astride, RotSet rs,
-                                                           int betaL, int cnt, int beta_rt,
-                                                           int next, const int *__restrict__ ext_prime,
-                                                           int xblocks) {
+// BETA > 0 and NR > 0 fix the digit and rotation counts at compile time: the loop
+// over the rotations is unrolled and has no branch, so every gather and key load of a
+// ciphertext is issued before the first product waits on one (the loads of a wave are
+// then in flight together instead of one rotation at a time).  BETA = 0 or NR = 0 read
+// the runtime counts (at most 8 digits).
+template <int BETA, int NR>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_inner_product_rot(
+    DevTables T, const double *__restrict__ ext, long long esb, long long esj, double *__restrict__ acc0,
+    double *__restrict__ acc1, long long astride, RotSet rs, int betaL, int cnt, int beta_rt, int next,
+    const int *__restrict__ ext_prime, int xblocks) {
     const int beta = BETA > 0 ? BETA : beta_rt;
+    const int nr = NR > 0 ? NR : rs.nr;
     constexpr int JM = BETA > 0 ? BETA : 8;
     const int rk = 21 / beta > 0 ? 21 / beta : 1;  // rotations between reductions
     const int b = blockIdx.x, slot = b >> 3;
@@ -589,27 +592,57 @@ __global__ __launch_bounds__(256) void k_inner_product_rot(DevTables T, const do
     const int pt = ext_prime[t];
     const double p = T.p[pt], pinv = T.pinv[pt];
     const bool wsum = rs.c0 && t <= rs.lq;
-    for (int ct = 0; ct < cnt; ++ct) {
+    // the unrolled form serves one ciphertext (the key loads then stay inside the
+    // rotation chunks instead of being hoisted out of a ciphertext loop)
+    const int ncts = BETA > 0 && NR > 0 ? 1 : cnt;
+    for (int ct = 0; ct < ncts; ++ct) {
         const double *E = ext + ct * esb + (long long)t * T.N;
         const double *C0 = wsum ? rs.c0 + ct * rs.c0_ct + (long long)t * T.N : nullptr;
-        double s0 = 0.0, s1 = 0.0, g0 = wsum && rs.c0_id ? C0[x] : 0.0;
-        for (int r = 0; r < rs.nr; ++r) {
-            const unsigned src = aut_src((unsigned)x, rs.g[r], T.logN);
-            if (wsum) g0 = red(g0 + C0[src], p, pinv);
-            const KeyRef K = rs.key[r];
-            if (BETA > 0) {
-                double e[JM], a0[JM], a1[JM];
+        double s0 = 0.0, s1 = 0.0;
+        if (BETA > 0 && NR > 0) {
+            constexpr int R = NR > 0 ? NR : 1, J = BETA > 0 ? BETA : 1;
+            constexpr int RC = R > (J >= 3 ? 3 : 4) ? (J >= 3 ? 3 : 4) : R;  // rotations whose loads fly together
+            double g0 = wsum && rs.c0_id ? C0[x] : 0.0;
 #pragma unroll
-                for (int j = 0; j < JM; ++j) {
-                    e[j] = E[j * esj + src];
-                    key_pair(K, betaL, pt, j, T.N, x, a0[j], a1[j]);
+            for (int r0 = 0; r0 < R; r0 += RC) {
+                double e[RC][J], a0[RC][J], a1[RC][J], c[RC];
+#pragma unroll
+                for (int rr = 0; rr < RC; ++rr) {
+                    if (r0 + rr < R) {
+                        const unsigned src = aut_src((unsigned)x, rs.g[r0 + rr], T.logN);
+#pragma unroll
+                        for (int j = 0; j < J; ++j) {
+                            e[rr][j] = (E + j * esj)[src];
+                            key_pair(rs.key[r0 + rr], betaL, pt, j, T.N, x, a0[rr][j], a1[rr][j]);
+                        }
+                        c[rr] = wsum ? C0[src] : 0.0;
+                    }
                 }
 #pragma unroll
-                for (int j = 0; j < JM; ++j) {
-                    s0 += mm(e[j], a0[j], p, pinv);
-                    s1 += mm(e[j], a1[j], p, pinv);
+                for (int rr = 0; rr < RC; ++rr) {
+                    const int r = r0 + rr;
+                    if (r < R) {
+#pragma unroll
+                        for (int j = 0; j < J; ++j) {
+                            s0 += mm(e[rr][j], a0[rr][j], p, pinv);
+                            s1 += mm(e[rr][j], a1[rr][j], p, pinv);
+                        }
+                        if ((r + 1) % (21 / J) == 0) {
+                            s0 = red(s0, p, pinv);
+                            s1 = red(s1, p, pinv);
+                        }
+                        g0 += c[rr];  // c0 + sum_r sigma_r(c0): at most 16 canonical words, below 2^52
+                    }
                 }
-            } else {
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if (wsum) rs.s0[ct * rs.s0_ct + (long long)t * T.N + x] = canon(g0, p, pinv);
+        } else {
+            double g0 = wsum && rs.c0_id ? C0[x] : 0.0;
+            for (int r = 0; r < nr; ++r) {
+                const unsigned src = aut_src((unsigned)x, rs.g[r], T.logN);
+                if (wsum) g0 = red(g0 + C0[src], p, pinv);
+                const KeyRef K = rs.key[r];
 #pragma unroll
                 for (int j = 0; j < JM; ++j) {
                     if (j < beta) {
@@ -620,27 +653,30 @@ __global__ __launch_bounds__(256) void k_inner_product_rot(DevTables T, const do
                         s1 += mm(e, w1, p, pinv);
                     }
                 }
+                if ((r + 1) % rk == 0) {
+                    s0 = red(s0, p, pinv);
+                    s1 = red(s1, p, pinv);
+                }
             }
-            if ((r + 1) % rk == 0) {
-                s0 = red(s0, p, pinv);
-                s1 = red(s1, p, pinv);
-            }
+            if (wsum) rs.s0[ct * rs.s0_ct + (long long)t * T.N + x] = canon(g0, p, pinv);
         }
         acc0[ct * astride + (long long)t * T.N + x] = canon(s0, p, pinv);
         acc1[ct * astride + (long long)t * T.N + x] = canon(s1, p, pinv);
-        if (wsum) rs.s0[ct * rs.s0_ct + (long long)t * T.N + x] = canon(g0, p, pinv);
     }
 }
 // The same products with every key word of the step held in registers (NR
-// rotations, at most 3 digits) and reused for every ciphertext of the batch, on the
-// same XCD-aware grid.
-template <int NR>
-__global__ __launch_bounds__(256) void k_inner_product_rot_reg(DevTables T, const double *__restrict__ ext,
+// rotations, BETA <= 3 digits) and reused for every ciphertext of the batch, on the
+// same XCD-aware grid.  Per ciphertext the NR x BETA gathers of the extended digits
+// and the NR + 1 gathers of c0 are issued together (no branch between them), then the
+// products run.
+template <int NR, int BETA>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_inner_product_rot_reg(DevTables T, const double *__restrict__ ext,
                                                                long long esb, long long esj,
                                                                double *__restrict__ acc0, double *__restrict__ acc1,
                                                                long long astride, RotSet rs, int betaL,
-                                                               int cnt, int beta, int next,
+                                                               int cnt, int next,
                                                                const int *__restrict__ ext_prime, int xblocks) {
+    constexpr int RK = 21 / BETA;  // rotations between reductions
     const int b = blockIdx.x, slot = b >> 3;
     const int t = (b & 7) + 8 * (slot / xblocks);
     if (t >= next) return;
@@ -648,24 +684,47 @@ __global__ __launch_bounds__(256) void k_inner_product_rot_reg(DevTables T, cons
     if (x >= T.N) return;
     const int pt = ext_prime[t];
     const double p = T.p[pt], pinv = T.pinv[pt];
-    const int rk = 21 / (beta > 0 ? beta : 1);  // rotations between reductions (beta <= 3)
-    double k0[NR][3], k1[NR][3];
+    double k0[NR][BETA], k1[NR][BETA];
     unsigned src[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         src[r] = aut_src((unsigned)x, rs.g[r], T.logN);
-        const KeyRef K = rs.key[r];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            k0[r][j] = 0.0;
-            k1[r][j] = 0.0;
-            if (j < beta) key_pair(K, betaL, pt, j, T.N, x, k0[r][j], k1[r][j]);
-        }
+        for (int j = 0; j < BETA; ++j) key_pair(rs.key[r], betaL, pt, j, T.N, x, k0[r][j], k1[r][j]);
     }
     const bool wsum = rs.c0 && t <= rs.lq;
+    constexpr int RC = NR > 3 ? 3 : NR;  // rotations whose gathers are in flight together
     for (int ct = 0; ct < cnt; ++ct) {
         const double *E = ext + ct * esb + (long long)t * T.N;
         double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int r0 = 0; r0 < NR; r0 += RC) {
+            double e[RC][BETA];
+#pragma unroll
+            for (int rr = 0; rr < RC; ++rr)
+#pragma unroll
+                for (int j = 0; j < BETA; ++j)
+                    if (r0 + rr < NR) e[rr][j] = (E + j * esj)[src[r0 + rr]];
+#pragma unroll
+            for (int rr = 0; rr < RC; ++rr) {
+                const int r = r0 + rr;
+                if (r < NR) {
+#pragma unroll
+                    for (int j = 0; j < BETA; ++j) {
+                        s0 += mm(e[rr][j], k0[r][j], p, pinv);
+                        s1 += mm(e[rr][j], k1[r][j], p, pinv);
+                    }
+                    if ((r + 1) % RK == 0) {
+                        s0 = red(s0, p, pinv);
+                        s1 = red(s1, p, pinv);
+                    }
+                }
+            }
+            // keep the next chunk's gathers behind this chunk's products (register budget)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        acc0[ct * astride + (long long)t * T.N + x] = canon(s0, p, pinv);
+        acc1[ct * astride + (long long)t * T.N + x] = canon(s1, p, pinv);
         if (wsum) {
             const double *C0 = rs.c0 + ct * rs.c0_ct + (long long)t * T.N;
             double g0 = rs.c0_id ? C0[x] : 0.0;
@@ -673,23 +732,7 @@ __global__ __launch_bounds__(256) void k_inner_product_rot_reg(DevTables T, cons
             for (int r = 0; r < NR; ++r) g0 += C0[src[r]];
             rs.s0[ct * rs.s0_ct + (long long)t * T.N + x] = canon(g0, p, pinv);
         }
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                if (j < beta) {
-                    const double e = E[j * esj + src[r]];
-                    s0 += mm(e, k0[r][j], p, pinv);
-                    s1 += mm(e, k1[r][j], p, pinv);
-                }
-            }
-            if ((r + 1) % rk == 0) {
-                s0 = red(s0, p, pinv);
-                s1 = red(s1, p, pinv);
-            }
-        }
-        acc0[ct * astride + (long long)t * T.N + x] = canon(s0, p, pinv);
-        acc1[ct * astride + (long long)t * T.N + x] = canon(s1, p, pinv);
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -764,30 +807,29 @@ void launch_inner_product_rot(const DevTables &T, const double *ext, long long e
     kprof_set_bytes(T.N * next * (6.0 * 2.0 * beta * rs.nr + 8.0 * cnt * (beta + 2.0)));
     const int xblocks = (T.N + 255) / 256;
     const dim3 g1(8 * ((next + 7) / 8) * xblocks);
-    // one ciphertext: the key stream alone bounds the kernel, and the lighter
-    // generic kernel keeps more loads in flight
-    const bool reg = cnt >= 2 && beta <= 3;
-    if (reg && rs.nr == 7)
-        KL("k_inner_product_rot", k_inner_product_rot_reg<7>, g1, dim3(256), 0, s, T, ext, estride_b, estride_j, acc0,
-           acc1, astride, rs, betaL, cnt, beta, next, ext_prime, xblocks);
-    else if (reg && rs.nr == 3)
-        KL("k_inner_product_rot", k_inner_product_rot_reg<3>, g1, dim3(256), 0, s, T, ext, estride_b, estride_j, acc0,
-           acc1, astride, rs, betaL, cnt, beta, next, ext_prime, xblocks);
-    else if (reg && rs.nr == 1)
-        KL("k_inner_product_rot", k_inner_product_rot_reg<1>, g1, dim3(256), 0, s, T, ext, estride_b, estride_j, acc0,
-           acc1, astride, rs, betaL, cnt, beta, next, ext_prime, xblocks);
-    else if (beta == 3)
-        KL("k_inner_product_rot", k_inner_product_rot<3>, g1, dim3(256), 0, s, T, ext, estride_b, estride_j, acc0,
-           acc1, astride, rs, betaL, cnt, beta, next, ext_prime, xblocks);
-    else if (beta == 2)
-        KL("k_inner_product_rot", k_inner_product_rot<2>, g1, dim3(256), 0, s, T, ext, estride_b, estride_j, acc0,
-           acc1, astride, rs, betaL, cnt, beta, next, ext_prime, xblocks);
-    else if (beta == 1)
-        KL("k_inner_product_rot", k_inner_product_rot<1>, g1, dim3(256), 0, s, T, ext, estride_b, estride_j, acc0,
-           acc1, astride, rs, betaL, cnt, beta, next, ext_prime, xblocks);
-    else
-        KL("k_inner_product_rot", k_inner_product_rot<0>, g1, dim3(256), 0, s, T, ext, estride_b, estride_j, acc0,
-           acc1, astride, rs, betaL, cnt, beta, next, ext_prime, xblocks);
+    // a batch holds the step's key words in registers; one ciphertext is bound by the key
+    // stream alone, and the lighter kernel keeps more loads in flight
+    const bool reg = cnt >= 2 && beta <= 3 && (rs.nr == 7 || rs.nr == 3 || rs.nr == 1);
+#define IPR_REG(R, B)                                                                                            \
+    if (reg && rs.nr == R && beta == B) {                                                                        \
+        KL("k_inner_product_rot", (k_inner_product_rot_reg<R, B>), g1, dim3(256), 0, s, T, ext, estride_b,        \
+           estride_j, acc0, acc1, astride, rs, betaL, cnt, next, ext_prime, xblocks);                            \
+        return;                                                                                                  \
+    }
+    IPR_REG(7, 3) IPR_REG(7, 2) IPR_REG(7, 1) IPR_REG(3, 3) IPR_REG(3, 2) IPR_REG(3, 1) IPR_REG(1, 3)
+    IPR_REG(1, 2) IPR_REG(1, 1)
+#undef IPR_REG
+#define IPR(B, R)                                                                                                \
+    if (beta == B && (R == 0 || (rs.nr == R && cnt == 1))) {                                                     \
+        KL("k_inner_product_rot", (k_inner_product_rot<B, R>), g1, dim3(256), 0, s, T, ext, estride_b, estride_j, \
+           acc0, acc1, astride, rs, betaL, cnt, beta, next, ext_prime, xblocks);                                 \
+        return;                                                                                                  \
+    }
+    IPR(3, 7) IPR(2, 7) IPR(1, 7) IPR(3, 3) IPR(2, 3) IPR(1, 3) IPR(3, 1) IPR(2, 1) IPR(1, 1)
+    IPR(3, 0) IPR(2, 0) IPR(1, 0)
+#undef IPR
+    KL("k_inner_product_rot", (k_inner_product_rot<0, 0>), g1, dim3(256), 0, s, T, ext, estride_b, estride_j, acc0,
+       acc1, astride, rs, betaL, cnt, beta, next, ext_prime, xblocks);
 }
 
 // ModDown conversion: acc holds, at slots in0 .. in0+nin-1 of every group, the

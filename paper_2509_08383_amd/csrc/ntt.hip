@@ -1,5 +1,5 @@
 // Batched negacyclic NTT / inverse NTT over RNS limbs for gfx950, with an autotuned
-// workgroup width.
+// workgroup width and pass-2 twiddle form.
 //
 // Forward stage s (m = 2^s, t = N/2m) maps (a_j, a_{j+t}) to
 // (a_j + w a_{j+t}, a_j - w a_{j+t}) with w = psi^bitrev(m + j/(2t)) (Cooley-Tukey,
@@ -49,23 +49,33 @@ DEV void nvs_at(const VecSet &v, int idx, int N, double *&ptr, int &pr, int &r, 
 }
 
 // PRO / EPI: fused prologue (forward pass 1 loads) and epilogue (forward pass 2
-// stores), see NttPro / NttEpi
-template <int H, int COLS, bool PASS2, bool INV, int PRO, int EPI>
+// stores), see NttPro / NttEpi.  TWF (pass 2): the phase-B twiddles are formed from
+// two factors instead of read from the full table: with s = 2H + H + sg the stage and
+// low = (th << sg) + g < 2^(s - R), the table entry psi^brev(2^s + (b << (s - R)) + low)
+// is tw[2^s + (b << (s - R))] * tw[low] (the three index parts occupy disjoint bits, so
+// their bit reversals add), a product of one word per row and one of the first 2^(R-1)
+// words; the canonical product equals the table word, so both forms give the same
+// output word for word.  pm > 0 (pass 2): blocks walk the vectors prime-major (vector
+// y -> group y % pm, slot y / pm), so consecutive vectors share a twiddle row and
+// re-read it from L2.
+template <int H, int COLS, bool PASS2, bool INV, int PRO, int EPI, int TWF>
 __global__ __launch_bounds__(COLS *(1 << H)) void k_ntt(VecSet vs, VecSet src, const double *oscale,
-                                                        DevTables T, NttPro pro, NttEpi epi) {
+                                                        DevTables T, NttPro pro, NttEpi epi, int pm) {
     constexpr int R = 2 * H, E = 1 << H, TPS = 1 << H, SUB = 1 << R, NT = COLS * TPS;
     constexpr int NN = SUB * SUB, S2 = SUB + SUB / E;
     __shared__ double tile[COLS * S2];
     auto lds = [](int c, int k) { return PASS2 ? c * S2 + k + (k >> H) : (k + (k >> H)) * COLS + c; };
 
+    int vy = blockIdx.y;
+    if (pm > 0) vy = (vy % pm) * vs.group + vy / pm;
     double *ptr;
     int pr, r_, g_;
-    nvs_at(vs, blockIdx.y, NN, ptr, pr, r_, g_);
+    nvs_at(vs, vy, NN, ptr, pr, r_, g_);
     const double *iptr = ptr;
     if (src.base) {
         double *sp;
         int a1, a2, a3;
-        nvs_at(src, blockIdx.y, NN, sp, a1, a2, a3);
+        nvs_at(src, vy, NN, sp, a1, a2, a3);
         iptr = sp;
     }
     if (PRO == 1) iptr = pro.last + (long long)g_ * pro.l_g;
@@ -84,12 +94,19 @@ __global__ __launch_bounds__(COLS *(1 << H)) void k_ntt(VecSet vs, VecSet src, c
     // is left between the phases or behind the barrier
     double wa[NW], wb[NW];
 #pragma unroll
-    for (int sg = 0; sg < H; ++sg)
+    for (int sg = 0; sg < H; ++sg) {
+        const double row = (PASS2 && TWF) ? tw[(1 << (H + sg + soff)) + (b << (H + sg))] : 0.0;
 #pragma unroll
         for (int g = 0; g < (1 << sg); ++g) {
             wa[(1 << sg) - 1 + g] = tw[(1 << (sg + soff)) + (PASS2 ? (b << sg) : 0) + g];
-            wb[(1 << sg) - 1 + g] = tw[(1 << (H + sg + soff)) + (PASS2 ? (b << (H + sg)) : 0) + (th << sg) + g];
+            if (PASS2 && TWF) {
+                const int low = (th << sg) + g;
+                wb[(1 << sg) - 1 + g] = low == 0 ? row : ncanon(nmm(row, tw[low], p, pinv), p, pinv);
+            } else {
+                wb[(1 << sg) - 1 + g] = tw[(1 << (H + sg + soff)) + (PASS2 ? (b << (H + sg)) : 0) + (th << sg) + g];
+            }
         }
+    }
     double v[E];
     constexpr int EW = SUB / TPS;  // words per thread in the coalesced epilogue
 
@@ -255,12 +272,14 @@ __global__ __launch_bounds__(COLS *(1 << H)) void k_ntt(VecSet vs, VecSet src, c
     }
 }
 
-// tuned workgroup width per (log N, batch bucket); 0 = not tuned (use the default)
+// tuned schedule per (log N, batch bucket); 0 = not tuned (use the default).  A
+// variant v = 1..NTT_VARIANTS is a workgroup width (the (v - 1) % 3 -th of three) and a
+// pass-2 twiddle form ((v - 1) / 3: 0 full table, 1 factored phase-B twiddles).
 static int g_ntt_tune[2][8];
 
 static int bucket_of(int count) {
     int b = 0;
-    while (b < 7 && (16 << (2 * b)) < count) ++b;  // <=16, <=64, <=256, <=1024, ...
+    while (b < 7 && (4 << (2 * b)) < count) ++b;  // <=4, <=16, <=64, <=256, <=1024, <=4096, ...
     return b;
 }
 
@@ -268,13 +287,15 @@ void set_ntt_tuning(int logN, int bucket, int variant) {
     if (bucket >= 0 && bucket < 8) g_ntt_tune[logN == 16 ? 1 : 0][bucket] = variant;
 }
 
-template <int H, int COLS, int PRO, int EPI>
+template <int H, int COLS, int PRO, int EPI, int TWF>
 static void ntt_run(const DevTables &T, const VecSet &vs, const VecSet *src, bool inverse, const double *oscale,
                     const NttPro &pro, const NttEpi &epi, hipStream_t s) {
     constexpr int SUB = 1 << (2 * H), NT = COLS * (1 << H);
     dim3 grid(SUB / COLS, vs.count), block(NT);
     const VecSet none{nullptr, 0, 1, 0, nullptr, nullptr};
     const VecSet first = src ? *src : none;
+    // pass 2 walks the vectors prime-major when they form whole groups
+    const int pm = (vs.group > 1 && vs.count % vs.group == 0) ? vs.count / vs.group : 0;
     // algorithmic bytes: a limb-NTT reads and writes every word once (2 N 8 bytes), half
     // of it booked to each pass; a fused prologue reads the shared last limb once per
     // group; a fused epilogue adds its element-wise operands (in, addends)
@@ -282,8 +303,8 @@ static void ntt_run(const DevTables &T, const VecSet &vs, const VecSet *src, boo
     const double nvec = vs.count, ngrp = (vs.count + vs.group - 1) / vs.group;
     if (!inverse) {
         kprof_set_bytes(half * (PRO ? ngrp : nvec));
-        KLN(PRO ? "ntt_fwd_pass1_lift" : "ntt_fwd_pass1", (k_ntt<H, COLS, false, false, PRO, 0>), grid, block, 0, s,
-            vs, first, nullptr, T, pro, epi);
+        KLN(PRO ? "ntt_fwd_pass1_lift" : "ntt_fwd_pass1", (k_ntt<H, COLS, false, false, PRO, 0, 0>), grid, block, 0,
+            s, vs, first, nullptr, T, pro, epi, 0);
         double extra = 0.0;
         if (EPI) {
             extra = 1.0;  // in
@@ -294,12 +315,14 @@ static void ntt_run(const DevTables &T, const VecSet &vs, const VecSet *src, boo
         kprof_set_bytes(half * nvec * (1.0 + extra));
         KLN(EPI == 1 ? "ntt_fwd_pass2_moddown"
                      : (EPI == 2 ? "ntt_fwd_pass2_rescale" : (EPI == 3 ? "ntt_fwd_pass2_moddown_rescale" : "ntt_fwd_pass2")),
-            (k_ntt<H, COLS, true, false, 0, EPI>), grid, block, 0, s, vs, none, nullptr, T, pro, epi);
+            (k_ntt<H, COLS, true, false, 0, EPI, TWF>), grid, block, 0, s, vs, none, nullptr, T, pro, epi, pm);
     } else {
         kprof_set_bytes(half * nvec);
-        KLN("ntt_inv_pass2", (k_ntt<H, COLS, true, true, 0, 0>), grid, block, 0, s, vs, first, nullptr, T, pro, epi);
+        KLN("ntt_inv_pass2", (k_ntt<H, COLS, true, true, 0, 0, TWF>), grid, block, 0, s, vs, first, nullptr, T, pro,
+            epi, pm);
         kprof_set_bytes(half * nvec);
-        KLN("ntt_inv_pass1", (k_ntt<H, COLS, false, true, 0, 0>), grid, block, 0, s, vs, none, oscale, T, pro, epi);
+        KLN("ntt_inv_pass1", (k_ntt<H, COLS, false, true, 0, 0, 0>), grid, block, 0, s, vs, none, oscale, T, pro,
+            epi, 0);
     }
 }
 
@@ -309,16 +332,21 @@ static void ntt_dispatch(const DevTables &T, const VecSet &vs, bool inverse, int
     if (vs.count <= 0) return;
     int v = variant;
     if (v <= 0) v = g_ntt_tune[T.logN == 16 ? 1 : 0][bucket_of(vs.count)];
-    if (v <= 0 || v > 3) v = 3;
+    if (v <= 0 || v > NTT_VARIANTS) v = 3;
+    const int w = (v - 1) % 3, f = (v - 1) / 3;
+#define NTT_CASE(H, C0, C1, C2)                                                                            \
+    if (w == 0 && f == 0) ntt_run<H, C0, PRO, EPI, 0>(T, vs, src, inverse, oscale, pro, epi, s);           \
+    else if (w == 1 && f == 0) ntt_run<H, C1, PRO, EPI, 0>(T, vs, src, inverse, oscale, pro, epi, s);      \
+    else if (w == 2 && f == 0) ntt_run<H, C2, PRO, EPI, 0>(T, vs, src, inverse, oscale, pro, epi, s);      \
+    else if (w == 0) ntt_run<H, C0, PRO, EPI, 1>(T, vs, src, inverse, oscale, pro, epi, s);                \
+    else if (w == 1) ntt_run<H, C1, PRO, EPI, 1>(T, vs, src, inverse, oscale, pro, epi, s);                \
+    else ntt_run<H, C2, PRO, EPI, 1>(T, vs, src, inverse, oscale, pro, epi, s);
     if (T.logN == 16) {
-        if (v == 1) ntt_run<4, 4, PRO, EPI>(T, vs, src, inverse, oscale, pro, epi, s);
-        else if (v == 2) ntt_run<4, 8, PRO, EPI>(T, vs, src, inverse, oscale, pro, epi, s);
-        else ntt_run<4, 16, PRO, EPI>(T, vs, src, inverse, oscale, pro, epi, s);
+        NTT_CASE(4, 4, 8, 16)
     } else if (T.logN == 12) {
-        if (v == 1) ntt_run<3, 8, PRO, EPI>(T, vs, src, inverse, oscale, pro, epi, s);
-        else if (v == 2) ntt_run<3, 16, PRO, EPI>(T, vs, src, inverse, oscale, pro, epi, s);
-        else ntt_run<3, 32, PRO, EPI>(T, vs, src, inverse, oscale, pro, epi, s);
+        NTT_CASE(3, 8, 16, 32)
     }
+#undef NTT_CASE
 }
 
 void launch_ntt(const DevTables &T, const VecSet &vs, bool inverse, int variant, hipStream_t s,

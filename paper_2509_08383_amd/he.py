@@ -82,6 +82,7 @@ def lib():
             "he_gumbel_sample": [_V, ctypes.POINTER(_V), ctypes.POINTER(_V), ctypes.c_size_t, ctypes.c_double,
                                  ctypes.POINTER(_Cfg), ctypes.POINTER(_V)],
             "he_gumbel_noise": [_c_dp, ctypes.c_size_t, _c_dp],
+            "he_invsqrt_guess_fit": [ctypes.c_double, ctypes.c_uint32, _c_dp],
             "he_ct_info": [_V, _c_u32p, _c_u32p, _c_dp, ctypes.POINTER(ctypes.c_size_t)],
             "he_ct_export": [_V, _V, _c_u64p, ctypes.c_size_t],
             "he_ct_import": [_V, _c_u64p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_double, ctypes.c_size_t,
@@ -103,6 +104,7 @@ def lib():
             "he_sync": [_V],
             "he_set_option": [_V, ctypes.c_int, ctypes.c_int64],
             "he_ntt_tuning": [_V, ctypes.POINTER(ctypes.c_int32), ctypes.c_uint32],
+            "he_ntt_tuning_report": [_V, ctypes.c_char_p, ctypes.c_size_t],
             "he_profile_begin": [_V],
             "he_profile_end": [_V, ctypes.c_char_p, ctypes.c_size_t],
             "he_boot_setup": [_V, ctypes.POINTER(_BootCfg)],
@@ -442,6 +444,13 @@ class Context:
         _check(lib().he_ntt_tuning(self.h, v, 8))
         return list(v)
 
+    def ntt_tuning_report(self) -> dict:
+        """every NTT schedule candidate the autotuner timed, per batch bucket"""
+        import json
+        buf = ctypes.create_string_buffer(1 << 14)
+        _check(lib().he_ntt_tuning_report(self.h, buf, len(buf)))
+        return json.loads(buf.value.decode())
+
     def profile_begin(self):
         _check(lib().he_profile_begin(self.h))
 
@@ -566,3 +575,11 @@ def topp_noise(top_p: float, u: np.ndarray) -> np.ndarray:
     g = np.empty_like(u)
     _check(lib().he_topp_noise(float(top_p), _dp(u), u.size, _dp(g)))
     return g
+
+
+def invsqrt_guess_fit(u_lo: float, degree: int) -> np.ndarray:
+    """Host helper: power-basis coefficients of the Chebyshev interpolant of u^(-1/2) on
+    [u_lo, 1] (the fixed initial guess he_cutmax uses when no coefficients are given)."""
+    c = np.empty(degree + 1, dtype=np.float64)
+    _check(lib().he_invsqrt_guess_fit(float(u_lo), int(degree), _dp(c)))
+    return c

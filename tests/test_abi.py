@@ -102,3 +102,22 @@ def test_plain_c_client_bootstraps():
     assert r.returncode == 0, (r.returncode, r.stdout, r.stderr)
     f = r.stdout.split()
     assert f[0] == "boot" and float(f[2]) < 1e-3 and f[4] == "3"
+
+
+def test_invsqrt_guess_fit_is_host_only_and_matches_the_oracle():
+    """he_invsqrt_guess_fit needs no GPU: the Chebyshev interpolant of u^(-1/2) on
+    [u_lo, 1] (Sec. 3.2 (ii), a known domain) equals the oracle's own fit, and its
+    interpolation nodes are exact"""
+    _ensure_built()
+    import numpy as np
+    from paper_2509_08383_amd import he
+    from oracle.cutmax_fp64 import chebyshev_invsqrt, poly_eval
+    for u_lo in (0.05, 0.5):
+        for d in (1, 2, 3, 4):
+            c = he.invsqrt_guess_fit(u_lo, d)
+            np.testing.assert_allclose(c, chebyshev_invsqrt(u_lo, d), rtol=1e-9, atol=1e-9)
+            k = np.arange(d + 1)
+            nodes = 0.5 * (1 + u_lo) + 0.5 * (1 - u_lo) * np.cos((2 * k + 1) * np.pi / (2 * (d + 1)))
+            np.testing.assert_allclose(poly_eval(c, nodes), nodes ** -0.5, rtol=1e-9)
+    with pytest.raises(he.HeError):
+        he.invsqrt_guess_fit(1.5, 3)

@@ -143,9 +143,10 @@ def test_rotate_and_mul_low_levels_bit_exact(toy):
         toy.same(toy.G.mul(gd, toy.G.drop(gy, lv)), toy.O.mul(od, toy.O.drop(oy, lv)), f"mul@{lv}")
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6])
 def test_ntt_variants_bit_exact(toy, variant):
-    """every NTT workgroup-width variant the autotuner can pick gives the same ciphertexts"""
+    """every NTT schedule the autotuner can pick (workgroup width x pass-2 twiddle form)
+    gives the same ciphertexts"""
     from paper_2509_08383_amd import he
     say(f"[gpu] ntt variant {variant}")
     gx, ox, gy, oy = _pairs_of_ops(toy)
@@ -155,7 +156,19 @@ def test_ntt_variants_bit_exact(toy, variant):
         toy.same(toy.G.rotate(gx, 4), toy.O.rotate(ox, 4), f"rotate v{variant}")
     finally:
         toy.G.set_option(he.HE_OPT_NTT_VARIANT, 0)
-    assert all(1 <= v <= 3 for v in toy.G.ntt_tuning())
+    assert all(1 <= v <= 6 for v in toy.G.ntt_tuning())
+
+
+def test_ntt_tuning_report_lists_every_candidate(toy):
+    """the autotuner timed all 6 schedules in each of its 6 buckets and kept the fastest"""
+    rep = toy.G.ntt_tuning_report()
+    assert rep["logN"] == 12 and len(rep["variants"]) == 6 and len(rep["buckets"]) == 6
+    counts = [b["vectors"] for b in rep["buckets"]]
+    assert counts == sorted(counts) and counts[-1] > 1024
+    for b in rep["buckets"]:
+        assert len(b["ms"]) == 6 and all(m > 0 for m in b["ms"])
+        assert b["choice"] == 1 + int(np.argmin(b["ms"]))
+    assert toy.G.ntt_tuning()[:6] == [b["choice"] for b in rep["buckets"]]
 
 
 def test_rotsum_bit_exact(toy):

@@ -64,6 +64,36 @@ def test_encrypt_and_primitives_full_size(sec):
     np.testing.assert_allclose(sec.G.decrypt(sec.G.mul(gx, gy)), x * y, atol=1e-6)
 
 
+def test_ntt_variants_full_size(sec):
+    """at N = 2^16 every NTT schedule (4, 8 or 16 sub-transforms per workgroup, table or
+    factored pass-2 twiddles) gives the oracle's product and rotation word for word, on a
+    single ciphertext and inside a two-ciphertext rotate-and-sum"""
+    from paper_2509_08383_amd import he
+    say("[gpu] secure: NTT schedules bit-exact")
+    rng = np.random.default_rng(19)
+    gx, ox = sec.enc_values(rng.uniform(-2, 2, sec.G.slots))
+    gy, oy = sec.enc_values(rng.uniform(-2, 2, sec.G.slots))
+    want_mul = sec.O.mul(ox, oy).export()
+    want_rot = sec.O.rotate(ox, 3).export()
+    two = sec.G.encrypt(rng.uniform(-1, 1, 2 * sec.G.slots))
+    sec.O.nonce = sec.O.nonce + 2
+    ref_rs = None
+    try:
+        for v in range(1, 7):
+            sec.G.set_option(he.HE_OPT_NTT_VARIANT, v)
+            assert np.array_equal(sec.G.export(sec.G.mul(gx, gy))[0], want_mul), v
+            assert np.array_equal(sec.G.export(sec.G.rotate(gx, 3))[0], want_rot), v
+            rs = sec.G.export(sec.G.rotsum(two))
+            if ref_rs is None:
+                ref_rs = rs
+            assert np.array_equal(rs, ref_rs), v
+    finally:
+        sec.G.set_option(he.HE_OPT_NTT_VARIANT, 0)
+    rep = sec.G.ntt_tuning_report()
+    say(f"  tuning: {[(b['vectors'], b['choice'], [round(m, 4) for m in b['ms']]) for b in rep['buckets']]}")
+    assert rep["logN"] == 16 and all(b["choice"] == 1 + int(np.argmin(b["ms"])) for b in rep["buckets"])
+
+
 def test_cutmax_secure_T1_bit_exact(sec):
     """one CutMax iteration plus the final inverse at full size, bit for bit"""
     from paper_2509_08383_amd import he
