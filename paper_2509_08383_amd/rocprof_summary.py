@@ -1,4 +1,5 @@
-"""Per-kernel summary of rocprofv3 runs of ``bench.py`` for one encrypted CutMax.
+"""Per-kernel summary of rocprofv3 runs of ``bench.py`` for one encrypted CutMax call
+(one request, or the 16-request batch of ``--batch-only``).
 
 Inputs are rocprofv3 output directories written with ``--output-format csv`` (the
 ``*_kernel_trace.csv`` / ``*_counter_collection.csv`` pair):
@@ -45,15 +46,19 @@ def _one(d: str, suffix: str) -> str:
 
 def kernel_class(name: str) -> str:
     """Library-level name of a dispatch (the NTT template arguments spelled out)."""
-    m = re.search(r"k_ntt<(\d+), (\d+), (true|false), (true|false), (\d+), (\d+)>", name)
+    m = re.search(r"k_ntt<(\d+), (\d+), (true|false), (true|false), (\d+), (\d+)(?:, (\d+))?>", name)
     if m:
         p2, inv, pro, epi = m.group(3) == "true", m.group(4) == "true", int(m.group(5)), int(m.group(6))
         s = "ntt_" + ("inv" if inv else "fwd") + ("_pass2" if p2 else "_pass1")
         s += {1: "_lift"}.get(pro, "") + {1: "_moddown", 2: "_rescale", 3: "_moddown_rescale"}.get(epi, "")
+        if m.group(7) and int(m.group(7)):
+            s += "_factored"
         return s
     base = re.sub(r"\(.*", "", name)
     base = re.sub(r"^void ", "", base)
-    return re.sub(r"<.*", "", base.split("::")[-1])
+    base = re.sub(r"<.*", "", base.split("::")[-1])
+    # the batched rotation key products (keys held in registers) book under the same name
+    return "k_inner_product_rot" if base == "k_inner_product_rot_reg" else base
 
 
 def _trace(d: str):
@@ -129,10 +134,14 @@ def summarize(trace=None, fetch=None, write=None, valu=None, lds=None, bench_jso
     alg = {}
     digest = None
     if bench_json:
-        lines = [ln for ln in open(bench_json).read().splitlines() if ln.startswith('{"metric"')]
+        # the default line ({"metric": ...}) books the single CutMax's kernels; a --batch-only
+        # line ({"batched": ...}) books the batch's
+        lines = [ln for ln in open(bench_json).read().splitlines()
+                 if ln.startswith('{"metric"') or ln.startswith('{"batched"')]
         bj = json.loads(lines[-1])
         digest = bj.get("src_digest")
-        for k, v in bj.get("kernels", {}).items():
+        kern = bj.get("kernels") or (bj.get("batched") or {}).get("kernels") or {}
+        for k, v in kern.items():
             alg[k] = v["bytes"] / v["launches"] if v["launches"] else 0.0
 
     total = sum(dur.values())
@@ -173,7 +182,7 @@ def to_markdown(s) -> str:
     out = ["| " + " | ".join(c[0] for c in present) + " |", "|" + "---|" * len(present)]
     for e in s["kernels"]:
         out.append("| " + " | ".join(fmt.format(e[c]) if c in e else "" for c, fmt in present) + " |")
-    hdr = [f"dispatches in one CutMax: {s['dispatches']}, kernel time {s['total_ms']:.3f} ms"]
+    hdr = [f"dispatches in one timed call: {s['dispatches']}, kernel time {s['total_ms']:.3f} ms"]
     if s["fetch_scale"]:
         hdr.append(f"FETCH_SIZE calibration (plain copy of known size): x{s['fetch_scale'] / 1024:.4f} "
                    f"(bytes per counted KiB / 1024)")
