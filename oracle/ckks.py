@@ -569,6 +569,37 @@ class Oracle:
         return H
 
 
+def scaled_normalise(O: Oracle, U: Ct, E: List[Ct], coef: Sequence[float], steps, C: float) -> List[Ct]:
+    """z = E h + 1 with h ~ C u^(-1/2) from the guess g and the scaled refinements
+    x <- x (a_k - b_k x^2) (x = g sqrt(u)), carried on E (the wide-domain form):
+      Ey = E (C g),  W = b_0 u g^2 = b_0 x_0^2 (the guess evaluated twice from U: C g at the
+      scale that puts E C g at Delta, sqrt(b_0) g at the scale that puts W at Delta);
+      per step: r = a_k - W (no level), every Ey <- Ey r, and unless it is the last step
+      W <- (W b_{k+1}/b_k) r^2 (the constant multiply lands at the scale that puts the new W at
+      Delta, in parallel with r^2: two levels a step);
+      z = Ey + 1.
+    Ey carries (y - mu)/(c sigma) x_k and W carries b_k x_k^2, so no ciphertext holds
+    u^(-1/2) itself, whose range spans the domain's decades."""
+    d = len(coef) - 1
+    q = O.q
+    lg = U.level - invsqr_depth(d, 0)
+    H0 = O.invsqr(U, [g * C for g in coef], C, 0, (O.Delta * float(q[lg])) / E[0].scale)
+    b0 = float(steps[0][1])
+    sG = math.sqrt(((O.Delta * float(q[lg])) * float(q[lg - 1])) / U.scale)
+    G0 = O.invsqr(U, [g * math.sqrt(b0) for g in coef], 1.0, 0, sG)
+    Ey = [O.mul(O.drop(e, lg), H0) for e in E]
+    W = O.mul(O.drop(U, lg - 1), O.mul(G0, G0))
+    for k, (a, b) in enumerate(steps):
+        R = O.add_const(O.mul_int(W, -1), a)
+        Ey = [O.mul(O.drop(e, R.level), R) for e in Ey]
+        if k + 1 < len(steps):
+            L = W.level
+            sV = ((O.Delta * float(q[L])) * float(q[L - 1])) / (R.scale * R.scale)
+            V = O.cm_target(W, float(steps[k + 1][1]) / b, sV)
+            W = O.mul(V, O.mul(R, R))
+    return [O.add_const(e, 1.0) for e in Ey]
+
+
 def invsqr_depth(degree: int, newton: int, goldschmidt: bool = False) -> int:
     """Levels of the initial guess plus its refinements; Goldschmidt's first b = u h^2
     needs h^2 before the first update, one level more than Newton's steps."""
@@ -589,11 +620,20 @@ class HECfg:
     sum_lo: float = 1.0                # bounds of mean(y^(T)) = sum/n
     sum_hi: float = 3.0
     gold_d: int = 3
+    # per iteration, the (a_k, b_k) of scaled refinements x <- x (a_k - b_k x^2) of the guess
+    # (replace newton; an empty list keeps the guess alone)
+    scaled: Optional[Sequence[Sequence[Sequence[float]]]] = None
+
+    def inv_depth(self, t: int) -> int:
+        d = len(self.coef[t]) - 1
+        if self.scaled is not None:
+            return invsqr_depth(d, 0) + 2 * len(self.scaled[t])
+        return invsqr_depth(d, self.newton, self.goldschmidt)
 
     def levels_needed(self) -> int:
         lv = 0
         for t in range(self.T):
-            lv += 2 + invsqr_depth(len(self.coef[t]) - 1, self.newton, self.goldschmidt) + 1 \
+            lv += 2 + self.inv_depth(t) + 1 \
                 + (int(self.p[t]).bit_length() - 1) \
                 + (1 if bin(int(self.p[t])).count("1") > 1 else 0)
         return lv + self.gold_d + 3
@@ -636,13 +676,16 @@ def cutmax_he(O: Oracle, Y: List[Ct], cfg: HECfg, rotsum_cache=None, n_real: int
             Ep = O.cm_target(D[a], kE * math.sqrt(float(npad)), E[a].scale)
             U = O.sub(U, O.mul(Ep, Ep))
         C = math.sqrt(float(n)) / cfg.c[t]
-        lh = U.level - invsqr_depth(len(cfg.coef[t]) - 1, cfg.newton, cfg.goldschmidt)
+        lh = U.level - cfg.inv_depth(t)
         if lh < 1:
             raise SchedError("chain too short")
         sE = E[0].scale
-        S_H = (O.Delta * float(O.q[lh])) / sE
-        H = O.invsqr(U, [g * C for g in cfg.coef[t]], C, cfg.newton, S_H, cfg.goldschmidt)
-        Yn = [O.add_const(O.mul(O.drop(e, H.level), H), 1.0) for e in E]
+        if cfg.scaled is not None and len(cfg.scaled[t]) > 0:
+            Yn = scaled_normalise(O, U, E, cfg.coef[t], cfg.scaled[t], C)
+        else:
+            S_H = (O.Delta * float(O.q[lh])) / sE
+            H = O.invsqr(U, [g * C for g in cfg.coef[t]], C, cfg.newton, S_H, cfg.goldschmidt)
+            Yn = [O.add_const(O.mul(O.drop(e, H.level), H), 1.0) for e in E]
         Yall = [O.power(y, int(cfg.p[t])) for y in Yn]
         Y, P = Yall[:a], (Yall[a] if masked else None)
     S = O.rotsum(O.sum_list(Y))

@@ -149,6 +149,60 @@ def goldschmidt_invsqrt(x, y0, K: int):
     return y
 
 
+def scaled_newton_step(l: float, h: float):
+    """One refinement x -> x (a - b x^2) of x = y sqrt(u) (y ~ u^(-1/2)) chosen for the
+    range [l, h] of x (0 < l < h): the cubic's maximum sits at m = sqrt(a / 3b) and it
+    equioscillates, f(l) = f(h) = 1 - delta and f(m) = 1 + delta, so [l, h] maps onto
+    [1 - delta, 1 + delta] with the smallest delta a cubic of this form reaches.  From
+    f(l) = f(h): a = b (h^2 + h l + l^2); then m^2 = (h^2 + h l + l^2) / 3, f(m) = 2 b m^3 and
+    f(l) = b l h (h + l); 1 - delta + 1 + delta = 2 gives b.  a = 1.5, b = 0.5 (Newton's
+    step for the inverse square root) is the limit l, h -> 1.
+    Returns (a, b, 1 - delta, 1 + delta)."""
+    s2 = h * h + h * l + l * l
+    m3 = (s2 / 3.0) ** 1.5
+    b = 2.0 / (l * h * (h + l) + 2.0 * m3)
+    a = b * s2
+    delta = 1.0 - b * l * h * (h + l)
+    return a, b, 1.0 - delta, 1.0 + delta
+
+
+def guess_range(coef: Sequence[float], u_lo: float, points: int = 20001, margin: float = 1e-3):
+    """[min, max] of x = g(u) sqrt(u) over [u_lo, 1] on a geometric grid, widened by a
+    relative margin (the range only picks the refinement constants and the bootstrap bounds)."""
+    u = np.geomspace(u_lo, 1.0, points)
+    x = poly_eval(coef, u) * np.sqrt(u)
+    if x.min() <= 0:
+        raise DomainError("initial guess not positive on the domain")
+    return float(x.min()) * (1.0 - margin), float(x.max()) * (1.0 + margin)
+
+
+def scaled_invsqrt_plan(u_lo: float, degree: int, K: int):
+    """Wide-domain inverse square root on [u_lo, 1]: the degree-d Chebyshev guess g, then
+    K refinements x -> x (a_k - b_k x^2) each chosen for the range of x it receives.
+    Returns (g, [(a_k, b_k)], [(l_k, h_k)] for k = 0..K: the range before step k and after
+    the last)."""
+    g = chebyshev_invsqrt(u_lo, degree)
+    lo, hi = guess_range(g, u_lo)
+    steps, ranges = [], [(lo, hi)]
+    for _ in range(K):
+        a, b, lo, hi = scaled_newton_step(lo, hi)
+        steps.append((a, b))
+        ranges.append((lo, hi))
+    return g, steps, ranges
+
+
+def scaled_invsqrt(u, g: Sequence[float], steps) -> np.ndarray:
+    """g(u) refined by the coupled form of the steps: y = g(u), w = u y^2 (= x^2), then per
+    step r = a - b w, y <- y r, w <- w r^2.  Approximates u^(-1/2)."""
+    y = poly_eval(g, u)
+    w = u * y * y
+    for a, b in steps:
+        r = a - b * w
+        y = y * r
+        w = w * r * r
+    return y
+
+
 # ----------------------------------------------------------------------------
 # Algorithm 2 mirrored in the clear
 # ----------------------------------------------------------------------------
@@ -166,6 +220,8 @@ class MirrorCfg:
     B: float = 1.0                 # final sum is mapped to x = S/B in (0, 1]
     gold_d: int = 3                # Goldschmidt degree (d+1 factors)
     sum_lo: float = 0.0
+    scaled: Optional[Sequence[Sequence[Sequence[float]]]] = None  # per iteration, (a_k, b_k) of the
+    #                                  scaled refinements after the guess (replaces newton)
 
 
 class DomainError(ValueError):
@@ -194,7 +250,9 @@ def cutmax_mirror(y0: np.ndarray, cfg: MirrorCfg, check: bool = True,
         u = var / cfg.v_hi[t]
         C = math.sqrt(n) / cfg.c[t]
         h = poly_eval([g * C for g in cfg.coef[t]], u)
-        if cfg.goldschmidt:
+        if cfg.scaled is not None:
+            h = C * scaled_invsqrt(u, cfg.coef[t], cfg.scaled[t])
+        elif cfg.goldschmidt:
             h = C * goldschmidt_invsqrt(u, h / C, cfg.newton)
         else:
             for _ in range(cfg.newton):

@@ -292,3 +292,35 @@ def test_masked_padding_gives_cutmax_of_the_logits_alone():
     assert np.abs(dz - cutmax_mirror(x, mc)).max() < 1e-4
     assert int(np.argmax(dz)) == int(np.argmax(x))
     assert abs(dz.sum() - 1.0) < 1e-2
+
+
+@pytest.mark.slow
+def test_scaled_refinement_schedule_decrypts_to_the_mirror():
+    """the wide-domain inverse square root in the encrypted schedule (the guess evaluated
+    twice from u, then x <- x (a_k - b_k x^2) carried on E and on W = b_k x_k^2, the
+    Table 2 form): three iterations with a 200x variance domain and 3 scaled steps, a plain
+    guess, and 1 step, decrypt to the FP64 mirror of the same steps within 1e-6 at 2^40 and
+    recover the argmax; the level count matches the schedule's"""
+    from oracle.cutmax_fp64 import scaled_invsqrt_plan
+    O = ckks.Oracle(ckks.Params(log_n=12, n_q=36, q0_bits=48, q_bits=40, p_bits=48, dnum=3, log2_scale=40,
+                                seed=7, hoist=3))
+    O.keygen_cutmax()
+    x = toy_logits(5)
+    y, _, _ = slot_layout(x, O.slots)
+    T, K = 3, [3, 0, 1]
+    vlo, vhi = [0.01, 0.25, 0.3], [2.0, 0.75, 3.0]
+    coef, steps = [], []
+    for t in range(T):
+        g, st, _ = scaled_invsqrt_plan(vlo[t] / vhi[t], 3, K[t])
+        coef.append(list(g))
+        steps.append(st)
+    hc = ckks.HECfg(T=T, p=[3] * T, c=[5.0] * T, v_lo=vlo, v_hi=vhi, coef=coef, sum_lo=1.0, sum_hi=3.0, gold_d=3,
+                    scaled=steps)
+    assert hc.levels_needed() == 35
+    Z = ckks.cutmax_he(O, [O.encrypt(y)], hc)[0]
+    assert Z.level == 0
+    mc = MirrorCfg(T=T, p=[3] * T, c=[5.0] * T, v_hi=vhi, v_lo=vlo, coef=coef, B=3.0 * y.size, gold_d=3,
+                   sum_lo=1.0 * y.size, scaled=steps)
+    z = O.decrypt(Z)
+    assert np.abs(z - cutmax_mirror(y, mc)).max() < 1e-6
+    assert int(np.argmax(z[:x.size])) == int(np.argmax(x))
