@@ -259,6 +259,7 @@ def boot_bench(he, args, x):
     corr_ms = (time.perf_counter() - t0) * 1e3 / 3
     corr_err = float(np.abs(bctx.decrypt(out2) - v).max())
     log(f"[bench] error-corrected bootstrap {corr_ms:.2f} ms, max err {corr_err:.2e}")
+    table2 = table2_bench(he, bctx, args.table2_prompts) if args.table2_prompts > 0 else None
     res = {"params": "N=2^16, 29 Q primes (q0 48 bits, 15 x 40, 13 x 48), 10 P primes, dnum=3, "
                      "sparse ternary secret h=192",
            "levels_used": bc.levels(), "ratio_bits": bc.ratio_bits, "bootstrap_ms": boot_ms,
@@ -268,7 +269,7 @@ def boot_bench(he, args, x):
            "batch16_ms": per_batch * 1e3, "batch16_argmaxes_per_s": 16.0 / per_batch, "batch16_argmax_ok": okb,
            "vocab_151936_ms": q_ms, "vocab_151936_argmax_ok": bool(okq),
            "corrected_bootstrap_ms": corr_ms, "corrected_bootstrap_max_err_bound1": corr_err,
-           "kernels": kern}
+           "table2_schedule": table2, "kernels": kern}
     bctx.close()
     return res
 
@@ -416,6 +417,58 @@ def learned_bench(he, ctx, args):
             "same_picks": out["learned"]["picks"] == out["fixed"]["picks"]}
 
 
+# The paper's HE schedule (Table 2, Sec. 4 "HE CutMax"): T = 4, p = [16, 4, 4, 6], c = [5, 3, 3, 3].
+# Variance domains and mean(y^(T)) bounds declared from 100 synthetic prompts per vocabulary
+# size with margins; iterations 2-4 refine their guess with K scaled steps.
+TABLE2 = {
+    32768: dict(vlo=[12.0, 1e7, 4e6, 6e7], vhi=[24.0, 4e12, 1.6e10, 1.6e10], K=[0, 7, 5, 3],
+                sum_lo=1.5e5, sum_hi=2.5e6, gold_d=6, paper_ms=3373.0, paper_max_z=0.994),
+    151936: dict(vlo=[15.0, 2e6, 5e8, 2e10], vhi=[30.0, 8e10, 2e12, 2e12], K=[0, 6, 5, 3],
+                 sum_lo=1e7, sum_hi=5e7, gold_d=5, paper_ms=4607.0, paper_max_z=0.989),
+}
+
+
+def table2_bench(he, bctx, prompts):
+    """The Table 2 schedule encrypted on the bootstrappable set (error-corrected bootstraps
+    where the 15 CutMax levels run out, also inside the wide-domain inverse square root), at
+    32768 logits (1 ciphertext) and 151936 (5): ms per CutMax, mean max Z and argmax accuracy
+    over `prompts` synthetic prompts, against the paper's H100 figures (context only)."""
+    from workloads import llm_logits
+    bctx.boot_setup(he.BootCfg(ratio_bits=6, correct_bits=6))
+    out = {}
+    for V, d in TABLE2.items():
+        coef, steps, ranges = [], [], []
+        for t in range(4):
+            g, st, rg = he.invsqrt_scaled_plan(d["vlo"][t] / d["vhi"][t], 3, d["K"][t])
+            coef.append(list(g))
+            steps.append(st)
+            ranges.append(rg)
+        cfg = he.CutmaxCfg(T=4, p=[16, 4, 4, 6], c=[5.0, 3.0, 3.0, 3.0], var_lo=d["vlo"], var_hi=d["vhi"],
+                           init_degree=3, init_coef=coef, sum_lo=d["sum_lo"], sum_hi=d["sum_hi"],
+                           gold_d=d["gold_d"], flags=he.HE_BOOT | he.HE_REFINE_SCALED, ref_steps=steps,
+                           ref_range=ranges)
+        ms, mz, ok = [], [], 0
+        for s in range(prompts):
+            x = llm_logits(700 + s, V)
+            ct = bctx.encrypt(x)
+            bctx.cutmax([ct], cfg)            # first call: encodes the bootstrap's diagonals
+            bctx.sync()
+            t0 = time.perf_counter()
+            Z = bctx.cutmax([ct], cfg)[0]
+            bctx.sync()
+            ms.append((time.perf_counter() - t0) * 1e3)
+            z = bctx.decrypt(Z, V)
+            mz.append(float(z.max()))
+            ok += int(int(np.argmax(z)) == int(np.argmax(x)))
+            del ct, Z
+        out[str(V)] = {"ciphertexts": -(-V // bctx.slots), "ms_per_cutmax": float(np.median(ms)),
+                       "mean_max_Z": float(np.mean(mz)), "argmax_accuracy": f"{ok}/{prompts}",
+                       "refinement_steps": d["K"], "paper_ms_H100": d["paper_ms"], "paper_max_Z": d["paper_max_z"]}
+        log(f"[bench] Table 2 schedule at {V} logits: {out[str(V)]}")
+    bctx.boot_setup(he.BootCfg(ratio_bits=6))
+    return out
+
+
 def batch_bench(ctx, cfg, args):
     """Batched argmaxes/s: 16 requests, even ids 32000 logits (1 ciphertext), odd ids 128256
     logits (4 ciphertexts), all advancing through one schedule (every launch covers the 40
@@ -464,6 +517,8 @@ def main():
     ap.add_argument("--learned-runs", type=int, default=1000000,
                     help="plaintext CutMax runs logged for the learned guess (one variance per iteration each)")
     ap.add_argument("--learned-epochs", type=int, default=10)
+    ap.add_argument("--table2-prompts", type=int, default=4,
+                    help="prompts per vocabulary size for the paper's Table 2 schedule (bootstrapped; 0 skips)")
     ap.add_argument("--graph", type=int, default=1,
                     help="replay each CutMax from a captured HIP graph (1) or launch eagerly (0)")
     ap.add_argument("--hoist", type=int, default=None,

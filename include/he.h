@@ -99,6 +99,11 @@ typedef struct {
  *   sum_lo/sum_hi: declared bounds of mean(Y^(T)); the final inverse runs
  *     Goldschmidt's product (App. B.1) with gold_d squarings on
  *     sum/(sum_hi * n).
+ *   Bounds of any size are accepted: where var_hi of the next iteration exceeds
+ *   2^8 (sum_hi, after the last, 2^4) the iteration's output is prescaled by a
+ *   power of two 2^(-e) (the factor 2^(-e/p) on the normalised iterate, no
+ *   level), which CutMax's result does not see and which keeps 1/(n sqrt(n v))
+ *   and 1/(sum_hi n) within what one constant multiply resolves.
  *   flags: HE_NOISE_PRESCALED (he_topp_sample, he_gumbel_sample: the noise
  *     already carries the temperature); HE_REFINE_GOLDSCHMIDT (see
  *     newton_steps); HE_MASK_PAD: for a zero-padded request (n not dividing
@@ -133,12 +138,28 @@ typedef struct {
     double sum_hi;
     uint32_t gold_d;
     uint32_t flags;
+    /* HE_REFINE_SCALED only (else ignored, may be NULL): the wide-domain inverse square
+     * root the paper's Table 2 schedule needs (Sec. 4, HE CutMax: T = 4, p = [16, 4, 4, 6],
+     * c = [5, 3, 3, 3], whose later variances span up to five decades).  Per iteration t,
+     * ref_steps[t] = K_t refinements of the guess (0: the guess alone, newton_steps is then
+     * ignored); ref_coef holds, iteration after iteration, K_t pairs (a_k, b_k) of
+     * x <- x (a_k - b_k x^2), x = g(u) sqrt(u) (b_k > 0); ref_range holds K_t + 1 pairs
+     * (l_k, h_k), 0 < l_k < h_k, bounds of x before step k and after the last, which set the
+     * bootstrap bounds.  he_invsqrt_scaled_plan computes all three for a domain.  The
+     * refinement runs on E h (the centred, scaled iterate) and on W = b_k x_k^2, never on
+     * u^(-1/2) itself: with HE_BOOT, W and E h are bootstrapped in the middle of the
+     * refinement when the chain runs short (bounds 1.02 b_k h_k^2 and
+     * 1.02 sqrt(n - 1) h_k / c). */
+    const uint32_t *ref_steps;
+    const double *ref_coef;
+    const double *ref_range;
 } he_cutmax_cfg;
 
 #define HE_NOISE_PRESCALED 1u
 #define HE_REFINE_GOLDSCHMIDT 2u
 #define HE_MASK_PAD 4u
 #define HE_BOOT 8u
+#define HE_REFINE_SCALED 16u
 
 /* Context: prime chain, twiddle and basis-conversion tables, secret key, and
  * the relinearisation and rotation keys (rotation by 2^r slots for every r <
@@ -207,6 +228,19 @@ int he_topp_noise(double top_p, const double *u, size_t n, double *g);
  * 1..4 interpolating u^(-1/2) at the Chebyshev nodes of [u_lo, 1], 0 < u_lo < 1,
  * the guess he_cutmax uses when init_coef is NULL.  No GPU needed. */
 int he_invsqrt_guess_fit(double u_lo, uint32_t degree, double *coef);
+
+/* Host helper: the wide-domain inverse square root on [u_lo, 1] (HE_REFINE_SCALED): the
+ * degree-d Chebyshev guess g (coef, d + 1 doubles, as he_invsqrt_guess_fit), the range
+ * [l_0, h_0] of x = g(u) sqrt(u) over the domain (a geometric grid of 20001 points,
+ * widened by 1e-3 relative), then K refinements x <- x (a_k - b_k x^2), each chosen for
+ * the range it receives so that it maps [l, h] onto [1 - e, 1 + e] with both ends and
+ * its maximum at the equioscillation points: a = b (h^2 + h l + l^2),
+ * b = 2 / (l h (h + l) + 2 ((h^2 + h l + l^2) / 3)^(3/2)), e = 1 - b l h (h + l).
+ * steps: 2K doubles (a_k, b_k); ranges: 2(K + 1) doubles (l_k, h_k).  All host memory.
+ * HE_EINVAL for u_lo outside (0, 1), degree outside 1..4, K > 16, or a guess that is not
+ * positive on the domain.  No GPU needed. */
+int he_invsqrt_scaled_plan(double u_lo, uint32_t degree, uint32_t K, double *coef, double *steps,
+                           double *ranges);
 
 /* Server: Gumbel-max sampling (Sec. 3.3, "Using Gumbel Distribution" and the
  * Gumbel-max lemma): CutMax(X + temperature * G), G the client's encrypted

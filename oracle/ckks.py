@@ -569,15 +569,17 @@ class Oracle:
         return H
 
 
-def scaled_normalise(O: Oracle, U: Ct, E: List[Ct], coef: Sequence[float], steps, C: float) -> List[Ct]:
-    """z = E h + 1 with h ~ C u^(-1/2) from the guess g and the scaled refinements
+def scaled_normalise(O: Oracle, U: Ct, E: List[Ct], coef: Sequence[float], steps, C: float,
+                     gain: float = 1.0) -> List[Ct]:
+    """z = E h + gain with h ~ C u^(-1/2) (C already carrying the gain, the iterate's
+    prescale) from the guess g and the scaled refinements
     x <- x (a_k - b_k x^2) (x = g sqrt(u)), carried on E (the wide-domain form):
       Ey = E (C g),  W = b_0 u g^2 = b_0 x_0^2 (the guess evaluated twice from U: C g at the
       scale that puts E C g at Delta, sqrt(b_0) g at the scale that puts W at Delta);
       per step: r = a_k - W (no level), every Ey <- Ey r, and unless it is the last step
       W <- (W b_{k+1}/b_k) r^2 (the constant multiply lands at the scale that puts the new W at
       Delta, in parallel with r^2: two levels a step);
-      z = Ey + 1.
+      z = Ey + gain.
     Ey carries (y - mu)/(c sigma) x_k and W carries b_k x_k^2, so no ciphertext holds
     u^(-1/2) itself, whose range spans the domain's decades."""
     d = len(coef) - 1
@@ -597,7 +599,7 @@ def scaled_normalise(O: Oracle, U: Ct, E: List[Ct], coef: Sequence[float], steps
             sV = ((O.Delta * float(q[L])) * float(q[L - 1])) / (R.scale * R.scale)
             V = O.cm_target(W, float(steps[k + 1][1]) / b, sV)
             W = O.mul(V, O.mul(R, R))
-    return [O.add_const(e, 1.0) for e in Ey]
+    return [O.add_const(e, gain) for e in Ey]
 
 
 def invsqr_depth(degree: int, newton: int, goldschmidt: bool = False) -> int:
@@ -630,6 +632,27 @@ class HECfg:
             return invsqr_depth(d, 0) + 2 * len(self.scaled[t])
         return invsqr_depth(d, self.newton, self.goldschmidt)
 
+    def prescale(self) -> List[int]:
+        """Per iteration t, the exponent e of the power of two 2^(-e) by which its output is
+        scaled.  CutMax is unchanged when its iterate is multiplied by a positive constant
+        (Alg. 1: the next semi-standardisation, or the final division by the sum, removes
+        it), while one constant multiply cannot resolve a factor below 1/q: deep schedules
+        (p = 16 after the first iteration, Table 2) reach variances near 1e12, whose
+        1 / (n sqrt(n v)) is smaller.  e is the least exponent that brings the next
+        iteration's variance bound under 2^8, or for the last iteration the bound of the
+        mean under 2^4; it is applied as the factor 2^(-e/p) on the normalised iterate."""
+        es = []
+        for t in range(self.T):
+            e = 0
+            if t + 1 < self.T:
+                while math.ldexp(float(self.v_hi[t + 1]), -2 * e) > 256.0:
+                    e += 1
+            else:
+                while math.ldexp(float(self.sum_hi), -e) > 16.0:
+                    e += 1
+            es.append(e)
+        return es
+
     def levels_needed(self) -> int:
         lv = 0
         for t in range(self.T):
@@ -660,13 +683,17 @@ def cutmax_he(O: Oracle, Y: List[Ct], cfg: HECfg, rotsum_cache=None, n_real: int
         P = O.mul_int(Y[0], 0)
         if pad != 0.0:
             P = O.add_const(P, pad)
+    es = cfg.prescale()
     for t in range(cfg.T):
         S = O.rotsum(O.sum_list(Y))
         if masked:
             S = O.sub(S, O.mul_int(P, npad))
         Yall = Y + ([P] if masked else [])
         D = [O.sub(O.mul_int(y, n), S) for y in Yall]
-        kE = 1.0 / (float(n) * math.sqrt(float(n) * cfg.v_hi[t]))
+        # this iteration's input was prescaled by 2^(-e) (the variance by 4^(-e))
+        v_hi = math.ldexp(float(cfg.v_hi[t]), -2 * es[t - 1]) if t > 0 else float(cfg.v_hi[t])
+        gain = math.pow(2.0, -float(es[t]) / float(cfg.p[t])) if es[t] > 0 else 1.0
+        kE = 1.0 / (float(n) * math.sqrt(float(n) * v_hi))
         E = [O.cm_exact(d, kE, O.Delta) for d in D]
         F = [O.mul(e, e) for e in E[:a]]
         U = O.rotsum(O.sum_list(F))
@@ -675,23 +702,23 @@ def cutmax_he(O: Oracle, Y: List[Ct], cfg: HECfg, rotsum_cache=None, n_real: int
             # product's rounding noise is not multiplied by npad
             Ep = O.cm_target(D[a], kE * math.sqrt(float(npad)), E[a].scale)
             U = O.sub(U, O.mul(Ep, Ep))
-        C = math.sqrt(float(n)) / cfg.c[t]
+        C = math.sqrt(float(n)) / cfg.c[t] * gain
         lh = U.level - cfg.inv_depth(t)
         if lh < 1:
             raise SchedError("chain too short")
         sE = E[0].scale
         if cfg.scaled is not None and len(cfg.scaled[t]) > 0:
-            Yn = scaled_normalise(O, U, E, cfg.coef[t], cfg.scaled[t], C)
+            Yn = scaled_normalise(O, U, E, cfg.coef[t], cfg.scaled[t], C, gain)
         else:
             S_H = (O.Delta * float(O.q[lh])) / sE
             H = O.invsqr(U, [g * C for g in cfg.coef[t]], C, cfg.newton, S_H, cfg.goldschmidt)
-            Yn = [O.add_const(O.mul(O.drop(e, H.level), H), 1.0) for e in E]
+            Yn = [O.add_const(O.mul(O.drop(e, H.level), H), gain) for e in E]
         Yall = [O.power(y, int(cfg.p[t])) for y in Yn]
         Y, P = Yall[:a], (Yall[a] if masked else None)
     S = O.rotsum(O.sum_list(Y))
     if masked:
         S = O.sub(S, O.mul_int(P, npad))
-    B = cfg.sum_hi * float(n)
+    B = math.ldexp(float(cfg.sum_hi), -es[-1]) * float(n)
     X = O.cm_exact(S, 1.0 / B, O.Delta)
     E0 = O.add_const(O.mul_int(X, -1), 1.0)
     P = O.add_const(E0, 1.0)

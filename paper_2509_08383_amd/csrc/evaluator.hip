@@ -967,6 +967,16 @@ struct CutmaxCfg {
     double sum_lo = 1, sum_hi = 3;
     bool boot = false;              // bootstrap the normalised iterate when the chain runs short
     std::vector<double> guess_max;  // [T]: max of h(u) sqrt(u) / C over the declared domain
+    // [T]: factor on iteration t's normalised iterate, 2^(-e/p_t), so that its output is
+    // 2^(-e) times the plain one (vhi[t+1], vlo[t+1] or the sum bounds hold the scaled bounds)
+    std::vector<double> gain;
+    // scaled refinements (HE_REFINE_SCALED): per iteration the (a_k, b_k) of
+    // x <- x (a_k - b_k x^2) and the K+1 ranges (l_k, h_k) of x
+    bool scaled = false;
+    std::vector<std::vector<std::pair<double, double>>> steps, ranges;
+    int ksteps(int t) const { return scaled ? (int)steps[t].size() : 0; }
+    // levels of the inverse square root of iteration t (guess and refinements)
+    int inv_depth(int t) const;
 };
 
 // max over u in [u_lo, 1] of g(u) sqrt(u) after the refinement steps (1 for an exact
@@ -984,8 +994,18 @@ double guess_overshoot(const std::vector<double> &g, double u_lo, int newton) {
     return mx;
 }
 
+int CutmaxCfg::inv_depth(int t) const {
+    const int d = (int)coef[t].size() - 1;
+    if (scaled) return invsqr_depth(d, 0, false) + 2 * ksteps(t);
+    return invsqr_depth(d, newton, gold_refine);
+}
+
+// levels an iteration needs before its normalised iterate; a scaled refinement under
+// HE_BOOT bootstraps inside itself, so it needs the moments, the guess, W_0 and one level
+// left for that bootstrap
 int pre_levels(const CutmaxCfg &cf, int t) {
-    return 2 + invsqr_depth((int)cf.coef[t].size() - 1, cf.newton, cf.gold_refine) + 1;
+    if (cf.boot && cf.ksteps(t) > 0) return 2 + invsqr_depth((int)cf.coef[t].size() - 1, 0, false) + 3;
+    return 2 + cf.inv_depth(t) + 1;
 }
 int power_levels(int p) {
     int nb = 0;
@@ -998,13 +1018,74 @@ int levels_needed(const CutmaxCfg &cf) {
     for (int t = 0; t < cf.T; ++t) {
         int nb = 0;
         while ((cf.p[t] >> nb) > 1) ++nb;
-        lv += 2 + invsqr_depth((int)cf.coef[t].size() - 1, cf.newton, cf.gold_refine) + 1 + nb + (__builtin_popcount(cf.p[t]) > 1 ? 1 : 0);
+        lv += 2 + cf.inv_depth(t) + 1 + nb + (__builtin_popcount(cf.p[t]) > 1 ? 1 : 0);
     }
     return lv + cf.gold_d + 3;
 }
 
 Bt bootstrap(Exec &X, const Bt &ct, double bound);
 int boot_levels(const he_ctx *C);
+
+// z = E h + 1 with h ~ C u^(-1/2) by the scaled refinements of the guess g (the wide-domain
+// form), times the iterate's prescale gain (folded into C, and the 1 added is the gain):
+// the guess twice from U, C g at the scale that puts Ey = E C g at Delta and
+// sqrt(b_0) g at the scale that puts W = b_0 u g^2 = b_0 x_0^2 at Delta; per step
+// r = a_k - W (no level), Ey <- Ey r, and unless it is the last step
+// W <- (W b_{k+1}/b_k) r^2, the constant multiply landing at the scale that puts the new W
+// at Delta (in parallel with r^2: two levels a step); z = Ey + gain.  Ey holds
+// (y - mu)/(c sigma) x_k and W holds b_k x_k^2: neither spans the decades u^(-1/2) spans,
+// so both can be bootstrapped (HE_BOOT) before a step when the chain runs short.
+Bt scaled_normalise(Exec &X, const Bt &U, const Bt &E, const std::vector<Request> &reqs,
+                    const std::vector<int> &first, const std::vector<int> &cmap, const CutmaxCfg &cf, int t) {
+    he_ctx *C = X.C;
+    const auto &q = C->q;
+    const int R = (int)reqs.size(), K = cf.ksteps(t), d = (int)cf.coef[t].size() - 1;
+    const auto &st = cf.steps[t];
+    const auto &rg = cf.ranges[t];
+    const int lg = U.level - invsqr_depth(d, 0, false);
+    REQUIRE(lg - 2 >= 1, HE_EDEPTH, "chain too short for the refined inverse square root");
+    std::vector<double> Cc(R), SH(R), SG(R), one(R, 1.0);
+    std::vector<std::vector<double>> coefC(R), coefB(R);
+    const double sb0 = std::sqrt(st[0].second);
+    double ebound = 0.0;
+    for (int r = 0; r < R; ++r) {
+        Cc[r] = std::sqrt((double)reqs[r].n) / cf.c[t] * cf.gain[t];
+        SH[r] = (C->Delta * (double)q[lg]) / E.scale[first[r]];
+        SG[r] = std::sqrt(((C->Delta * (double)q[lg]) * (double)q[lg - 1]) / U.scale[r]);
+        for (double g : cf.coef[t]) {
+            coefC[r].push_back(g * Cc[r]);
+            coefB[r].push_back(g * sb0);
+        }
+        ebound = std::max(ebound, std::sqrt((double)reqs[r].n - 1.0) / cf.c[t] * cf.gain[t]);
+    }
+    Bt H0 = invsqr(X, U, coefC, Cc, 0, false, SH);
+    Bt G0 = invsqr(X, U, coefB, one, 0, false, SG);
+    Bt Ey = X.mul(X.drop(E, lg), H0, &cmap);
+    Bt W = X.mul(X.drop(U, lg - 1), X.mul(G0, G0));
+    for (int k = 0; k < K; ++k) {
+        // W must stay at level 1 or above for a later bootstrap: a step that produces the
+        // next W takes two levels, the last step one (its Ey needs a level for the z
+        // bootstrap before the power)
+        const int need = k + 1 < K ? 3 : 2;
+        if (W.level < need) {
+            REQUIRE(cf.boot && C->boot.ready, HE_EDEPTH, "scaled refinement needs more levels than the chain has");
+            W = bootstrap(X, W, 1.02 * st[k].second * rg[k].second * rg[k].second);
+            Ey = bootstrap(X, Ey, 1.02 * ebound * rg[k].second);
+        }
+        std::vector<double> ak(R, st[k].first);
+        Bt Rk = X.add_const(X.mul_int(W, std::vector<int64_t>(R, -1)), ak);
+        Ey = X.mul(X.drop(Ey, Rk.level), Rk, &cmap);
+        if (k + 1 < K) {
+            const int L = W.level;
+            std::vector<double> sV(R), kap(R, st[k + 1].second / st[k].second);
+            for (int r = 0; r < R; ++r)
+                sV[r] = ((C->Delta * (double)q[L]) * (double)q[L - 1]) / (Rk.scale[r] * Rk.scale[r]);
+            Bt V = X.cmul(W, kap, sV, false);
+            W = X.mul(V, X.mul(Rk, Rk));
+        }
+    }
+    return X.add_const(Ey, std::vector<double>(Ey.cnt, cf.gain[t]));
+}
 
 // Alg. 2 on a batch of requests; Y holds every request's ciphertexts.
 // Masked padding: the pad slots of a request all hold one value, followed by a
@@ -1108,17 +1189,22 @@ Bt cutmax_sched(Exec &X, Bt Y, const std::vector<Request> &reqs, const CutmaxCfg
             Bt F = X.mul(E, E);
             U = X.rotsum(X.sum_groups(F, first, cnt));
         }
-        const int lh = U.level - invsqr_depth((int)cf.coef[t].size() - 1, cf.newton, cf.gold_refine);
+        const int lh = U.level - (cf.ksteps(t) > 0 && cf.boot ? 0 : cf.inv_depth(t));
         REQUIRE(lh >= 1, HE_EDEPTH, "chain too short");
         std::vector<double> Cc(R), SH(R);
         std::vector<std::vector<double>> coefC(R);
         for (int r = 0; r < R; ++r) {
-            Cc[r] = std::sqrt((double)reqs[r].n) / cf.c[t];
+            Cc[r] = std::sqrt((double)reqs[r].n) / cf.c[t] * cf.gain[t];
             SH[r] = (C->Delta * (double)C->q[lh]) / E.scale[first[r]];
             for (double g : cf.coef[t]) coefC[r].push_back(g * Cc[r]);
         }
-        Bt H = invsqr(X, U, coefC, Cc, cf.newton, cf.gold_refine, SH);
-        Bt Yp = X.add_const(X.mul(X.drop(E, H.level), H, &cmap), std::vector<double>(Y.cnt, 1.0));
+        Bt Yp;
+        if (cf.ksteps(t) > 0) {
+            Yp = scaled_normalise(X, U, E, reqs, first, cmap, cf, t);
+        } else {
+            Bt H = invsqr(X, U, coefC, Cc, cf.scaled ? 0 : cf.newton, cf.gold_refine, SH);
+            Yp = X.add_const(X.mul(X.drop(E, H.level), H, &cmap), std::vector<double>(Y.cnt, cf.gain[t]));
+        }
         if (cf.boot) {
             // bootstrap z when the power and the next iteration's moments (or the final
             // normalisation) do not fit; |z - 1| <= (max h sqrt(u) / C) sqrt(n - 1) / c
@@ -1128,7 +1214,7 @@ Bt cutmax_sched(Exec &X, Bt Y, const std::vector<Request> &reqs, const CutmaxCfg
                 double bound = 0.0;
                 for (int r = 0; r < R; ++r)
                     bound = std::max(bound, 1.0 + cf.guess_max[t] * std::sqrt((double)reqs[r].n - 1.0) / cf.c[t]);
-                Yp = bootstrap(X, Yp, 1.02 * bound);
+                Yp = bootstrap(X, Yp, 1.02 * bound * cf.gain[t]);
             }
         }
         Bt Yn = X.power(Yp, cf.p[t]);
@@ -2217,9 +2303,56 @@ CutmaxCfg parse_cfg(he_ctx *C, const he_cutmax_cfg *cfg) {
     cf.sum_lo = cfg->sum_lo;
     cf.sum_hi = cfg->sum_hi;
     cf.boot = (cfg->flags & HE_BOOT) != 0;
+    cf.scaled = (cfg->flags & HE_REFINE_SCALED) != 0;
+    if (cf.scaled) {
+        REQUIRE(cfg->ref_steps && cfg->ref_range && !cf.gold_refine, HE_EINVAL,
+                "HE_REFINE_SCALED needs ref_steps and ref_range (and excludes HE_REFINE_GOLDSCHMIDT)");
+        size_t ic = 0, ir = 0;
+        cf.steps.resize(cf.T);
+        cf.ranges.resize(cf.T);
+        for (int t = 0; t < cf.T; ++t) {
+            const int K = (int)cfg->ref_steps[t];
+            REQUIRE(K >= 0 && K <= 16 && (K == 0 || cfg->ref_coef), HE_EINVAL, "ref_steps: 0..16 per iteration");
+            for (int k = 0; k < K; ++k, ic += 2) {
+                const double a = cfg->ref_coef[ic], b = cfg->ref_coef[ic + 1];
+                REQUIRE(std::isfinite(a) && std::isfinite(b) && b > 0 && a > 0, HE_EINVAL, "ref_coef: a, b > 0");
+                cf.steps[t].push_back({a, b});
+            }
+            for (int k = 0; k <= K; ++k, ir += 2) {
+                const double l = cfg->ref_range[ir], h = cfg->ref_range[ir + 1];
+                REQUIRE(std::isfinite(l) && std::isfinite(h) && l > 0 && l < h, HE_EINVAL, "ref_range: 0 < l < h");
+                cf.ranges[t].push_back({l, h});
+            }
+        }
+    }
+    // CutMax is unchanged when its iterate is multiplied by a positive constant (the next
+    // moments' normalisation or the final division removes it), while deep schedules reach
+    // variances near 1e12 (p = 16 after the first iteration), whose 1 / (n sqrt(n v)) lies
+    // below the 1/q that one constant multiply resolves.  Iteration t's output is therefore
+    // prescaled by 2^(-e), e the least exponent that brings the next variance bound under
+    // 2^8 (the mean bound under 2^4 before the final division), through the factor
+    // 2^(-e/p) on the normalised iterate before the power: no level, and bounds already
+    // that small keep e = 0 and the plain arithmetic.
+    cf.gain.assign(cf.T, 1.0);
+    for (int t = 0; t < cf.T; ++t) {
+        int e = 0;
+        if (t + 1 < cf.T) {
+            while (std::ldexp(cf.vhi[t + 1], -2 * e) > 256.0) ++e;
+            cf.vhi[t + 1] = std::ldexp(cf.vhi[t + 1], -2 * e);
+            cf.vlo[t + 1] = std::ldexp(cf.vlo[t + 1], -2 * e);
+        } else {
+            while (std::ldexp(cf.sum_hi, -e) > 16.0) ++e;
+            cf.sum_hi = std::ldexp(cf.sum_hi, -e);
+            cf.sum_lo = std::ldexp(cf.sum_lo, -e);
+        }
+        if (e > 0) cf.gain[t] = std::pow(2.0, -(double)e / (double)cf.p[t]);
+    }
     // (host work on every call, so only where a bootstrap bound needs it)
-    for (int t = 0; t < cf.T; ++t)
-        cf.guess_max.push_back(cf.boot ? guess_overshoot(cf.coef[t], cf.vlo[t] / cf.vhi[t], cf.newton) : 1.0);
+    for (int t = 0; t < cf.T; ++t) {
+        if (cf.ksteps(t) > 0) cf.guess_max.push_back(cf.ranges[t].back().second);
+        else cf.guess_max.push_back(cf.boot ? guess_overshoot(cf.coef[t], cf.vlo[t] / cf.vhi[t], cf.scaled ? 0 : cf.newton)
+                                            : 1.0);
+    }
     (void)C;
     return cf;
 }
@@ -2270,7 +2403,7 @@ int cutmax_impl(he_ctx *C, he_ct *const *in, he_ct *const *noise, size_t batch, 
                 char b[64];
                 gkey += "B";
                 for (int t = 0; t < cf.T; ++t) {
-                    std::snprintf(b, sizeof b, "c%.17g/%.17g", cf.c[t], cf.guess_max[t]);
+                    std::snprintf(b, sizeof b, "c%.17g/%.17g/%.17g", cf.c[t], cf.guess_max[t], cf.gain[t]);
                     gkey += b;
                 }
                 for (auto &r : reqs) gkey += "n" + std::to_string(r.n);
@@ -2278,6 +2411,19 @@ int cutmax_impl(he_ctx *C, he_ct *const *in, he_ct *const *noise, size_t batch, 
             for (auto &r : reqs) gkey += "a" + std::to_string(r.a) + (r.npad > 0 ? "m" : "");
             for (int t = 0; t < cf.T; ++t)
                 gkey += "p" + std::to_string(cf.p[t]) + "d" + std::to_string(cf.coef[t].size());
+            // scaled refinements: their step counts fix the launches, and under HE_BOOT their
+            // ranges fix the bootstrap bounds
+            if (cf.scaled) {
+                char b[64];
+                for (int t = 0; t < cf.T; ++t) {
+                    gkey += "k" + std::to_string(cf.ksteps(t));
+                    if (cf.boot)
+                        for (int k = 0; k < cf.ksteps(t); ++k) {
+                            std::snprintf(b, sizeof b, "/%.17g:%.17g", cf.steps[t][k].second, cf.ranges[t][k].second);
+                            gkey += b;
+                        }
+                }
+            }
         }
         run2(C, [&](Exec &X) {
             Bt Y = X.new_bt(total, level);
@@ -2637,6 +2783,16 @@ int he_invsqrt_guess_fit(double u_lo, uint32_t degree, double *coef) {
         REQUIRE(coef && u_lo > 0 && u_lo < 1 && degree >= 1 && degree <= 4, HE_EINVAL,
                 "u_lo in (0, 1), degree 1..4, coef non-null");
         chebyshev_invsqrt_fit(u_lo, (int)degree, coef);
+        return HE_OK;
+    });
+}
+
+int he_invsqrt_scaled_plan(double u_lo, uint32_t degree, uint32_t K, double *coef, double *steps, double *ranges) {
+    return guarded([&]() {
+        REQUIRE(coef && ranges && (K == 0 || steps) && u_lo > 0 && u_lo < 1 && degree >= 1 && degree <= 4 && K <= 16,
+                HE_EINVAL, "u_lo in (0, 1), degree 1..4, K <= 16, non-null outputs");
+        REQUIRE(invsqrt_scaled_plan(u_lo, (int)degree, (int)K, coef, steps, ranges), HE_EINVAL,
+                "the guess is not positive on the domain");
         return HE_OK;
     });
 }

@@ -240,6 +240,7 @@ uint64_t find_psi(uint64_t q, int N);
 void encode_slots(const double *z, int N, double scale, int64_t *m);
 void decode_slots(const double *m, int N, double scale, double *z);
 void chebyshev_invsqrt_fit(double u_lo, int degree, double *coef);
+bool invsqrt_scaled_plan(double u_lo, int degree, int K, double *coef, double *steps, double *ranges);
 int64_t llround_d(double x);
 
 }  // namespace he

@@ -1,4 +1,5 @@
 // Host-side number theory and encoding for the MI355X CKKS library.
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <stdexcept>
@@ -218,6 +219,46 @@ void chebyshev_invsqrt_fit(double u_lo, int degree, double *coef) {
         for (int j = c + 1; j < n; ++j) s -= A[c * n + j] * coef[j];
         coef[c] = s / A[c * n + c];
     }
+}
+
+// Wide-domain inverse square root on [u_lo, 1]: the Chebyshev guess, the range of
+// x = g(u) sqrt(u) over a geometric grid (widened by 1e-3 relative; the range only picks
+// the refinement constants and the bootstrap bounds), then K refinements
+// x <- x (a - b x^2), each the cubic that maps the range [l, h] it receives onto
+// [1 - e, 1 + e] touching both ends and its maximum: a = b s, s = h^2 + h l + l^2,
+// b = 2 / (l h (h + l) + 2 (s / 3)^(3/2)), e = 1 - b l h (h + l).
+// Returns false when the guess is not positive on the domain.
+bool invsqrt_scaled_plan(double u_lo, int degree, int K, double *coef, double *steps, double *ranges) {
+    chebyshev_invsqrt_fit(u_lo, degree, coef);
+    const int pts = 20001;
+    double lo = 1e300, hi = -1e300;
+    const double r = std::log(1.0 / u_lo);
+    for (int i = 0; i < pts; ++i) {
+        const double u = i == pts - 1 ? 1.0 : u_lo * std::exp(r * i / (pts - 1));
+        double y = 0.0;
+        for (int k = degree; k >= 0; --k) y = y * u + coef[k];
+        const double x = y * std::sqrt(u);
+        lo = std::min(lo, x);
+        hi = std::max(hi, x);
+    }
+    if (!(lo > 0.0)) return false;
+    lo *= 1.0 - 1e-3;
+    hi *= 1.0 + 1e-3;
+    ranges[0] = lo;
+    ranges[1] = hi;
+    for (int k = 0; k < K; ++k) {
+        const double s2 = hi * hi + hi * lo + lo * lo;
+        const double b = 2.0 / (lo * hi * (hi + lo) + 2.0 * std::pow(s2 / 3.0, 1.5));
+        const double a = b * s2;
+        const double e = 1.0 - b * lo * hi * (hi + lo);
+        steps[2 * k] = a;
+        steps[2 * k + 1] = b;
+        lo = 1.0 - e;
+        hi = 1.0 + e;
+        ranges[2 * k + 2] = lo;
+        ranges[2 * k + 3] = hi;
+    }
+    return true;
 }
 
 }  // namespace he

@@ -21,6 +21,7 @@ HE_NOISE_PRESCALED = 1
 HE_REFINE_GOLDSCHMIDT = 2
 HE_MASK_PAD = 4
 HE_BOOT = 8
+HE_REFINE_SCALED = 16
 HE_OPT_GRAPH, HE_OPT_NTT_VARIANT, HE_OPT_BOOT_HOIST = 1, 2, 3
 
 _c_u32p = ctypes.POINTER(ctypes.c_uint32)
@@ -54,7 +55,8 @@ class _Cfg(ctypes.Structure):
     _fields_ = [("T", ctypes.c_uint32), ("p", _c_u32p), ("c", _c_dp), ("var_lo", _c_dp),
                 ("var_hi", _c_dp), ("init_degree", ctypes.c_uint32), ("init_coef", _c_dp),
                 ("newton_steps", ctypes.c_uint32), ("sum_lo", ctypes.c_double),
-                ("sum_hi", ctypes.c_double), ("gold_d", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+                ("sum_hi", ctypes.c_double), ("gold_d", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("ref_steps", _c_u32p), ("ref_coef", _c_dp), ("ref_range", _c_dp)]
 
 
 _lib = None
@@ -83,6 +85,7 @@ def lib():
                                  ctypes.POINTER(_Cfg), ctypes.POINTER(_V)],
             "he_gumbel_noise": [_c_dp, ctypes.c_size_t, _c_dp],
             "he_invsqrt_guess_fit": [ctypes.c_double, ctypes.c_uint32, _c_dp],
+            "he_invsqrt_scaled_plan": [ctypes.c_double, ctypes.c_uint32, ctypes.c_uint32, _c_dp, _c_dp, _c_dp],
             "he_ct_info": [_V, _c_u32p, _c_u32p, _c_dp, ctypes.POINTER(ctypes.c_size_t)],
             "he_ct_export": [_V, _V, _c_u64p, ctypes.c_size_t],
             "he_ct_import": [_V, _c_u64p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_double, ctypes.c_size_t,
@@ -196,6 +199,9 @@ class CutmaxCfg:
     sum_hi: float = 3.0
     gold_d: int = 3
     flags: int = 0
+    # HE_REFINE_SCALED: per iteration, the (a_k, b_k) pairs and the K+1 (l_k, h_k) ranges
+    ref_steps: Optional[Sequence[Sequence[Sequence[float]]]] = None
+    ref_range: Optional[Sequence[Sequence[Sequence[float]]]] = None
     _keep: list = field(default_factory=list, repr=False)
 
     def c_struct(self) -> _Cfg:
@@ -210,12 +216,26 @@ class CutmaxCfg:
             assert len(flat) == T * (self.init_degree + 1)
             coef = (ctypes.c_double * len(flat))(*flat)
         self._keep = [p, c, lo, hi, coef]
+        rs = rc = rr = None
+        if self.ref_steps is not None:
+            assert self.ref_range is not None and len(self.ref_steps) == T and len(self.ref_range) == T
+            rs = (ctypes.c_uint32 * T)(*[len(st) for st in self.ref_steps])
+            fc = [float(v) for st in self.ref_steps for ab in st for v in ab]
+            fr = [float(v) for rg in self.ref_range for lh in rg for v in lh]
+            assert len(fr) == 2 * sum(len(st) + 1 for st in self.ref_steps)
+            rc = (ctypes.c_double * max(1, len(fc)))(*fc)
+            rr = (ctypes.c_double * len(fr))(*fr)
+            self._keep += [rs, rc, rr]
         s = _Cfg()
         s.T, s.p, s.c, s.var_lo, s.var_hi = T, p, c, lo, hi
         s.init_degree = self.init_degree
         s.init_coef = ctypes.cast(coef, _c_dp) if coef is not None else None
         s.newton_steps, s.sum_lo, s.sum_hi = self.newton_steps, self.sum_lo, self.sum_hi
         s.gold_d, s.flags = self.gold_d, self.flags
+        if rs is not None:
+            s.ref_steps = ctypes.cast(rs, _c_u32p)
+            s.ref_coef = ctypes.cast(rc, _c_dp)
+            s.ref_range = ctypes.cast(rr, _c_dp)
         return s
 
 
@@ -583,3 +603,13 @@ def invsqrt_guess_fit(u_lo: float, degree: int) -> np.ndarray:
     c = np.empty(degree + 1, dtype=np.float64)
     _check(lib().he_invsqrt_guess_fit(float(u_lo), int(degree), _dp(c)))
     return c
+
+
+def invsqrt_scaled_plan(u_lo: float, degree: int, K: int):
+    """Host helper: (guess coefficients, [(a_k, b_k)], [(l_k, h_k)]) of the wide-domain
+    inverse square root on [u_lo, 1] (he_invsqrt_scaled_plan)."""
+    c = np.empty(degree + 1, dtype=np.float64)
+    st = np.empty(max(1, 2 * K), dtype=np.float64)
+    rg = np.empty(2 * (K + 1), dtype=np.float64)
+    _check(lib().he_invsqrt_scaled_plan(float(u_lo), int(degree), int(K), _dp(c), _dp(st), _dp(rg)))
+    return c, [tuple(st[2 * k:2 * k + 2]) for k in range(K)], [tuple(rg[2 * k:2 * k + 2]) for k in range(K + 1)]

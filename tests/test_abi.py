@@ -121,3 +121,22 @@ def test_invsqrt_guess_fit_is_host_only_and_matches_the_oracle():
             np.testing.assert_allclose(poly_eval(c, nodes), nodes ** -0.5, rtol=1e-9)
     with pytest.raises(he.HeError):
         he.invsqrt_guess_fit(1.5, 3)
+
+
+def test_invsqrt_scaled_plan_is_host_only_and_matches_the_oracle():
+    """he_invsqrt_scaled_plan needs no GPU: its guess, refinement constants and ranges equal
+    the oracle's own plan for the same domain (wide-domain inverse square root of the Table 2
+    schedule), and it refuses a bad domain"""
+    _ensure_built()
+    import numpy as np
+    from paper_2509_08383_amd import he
+    from oracle.cutmax_fp64 import scaled_invsqrt_plan
+    for u_lo, K in ((2.5e-6, 7), (2.5e-4, 5), (0.5, 0)):
+        g, st, rg = he.invsqrt_scaled_plan(u_lo, 3, K)
+        go, sto, rgo = scaled_invsqrt_plan(u_lo, 3, K)
+        np.testing.assert_allclose(g, go, rtol=1e-9, atol=1e-9)
+        np.testing.assert_allclose(np.array(st).reshape(-1, 2) if K else np.zeros((0, 2)),
+                                   np.array(sto).reshape(-1, 2) if K else np.zeros((0, 2)), rtol=1e-9)
+        np.testing.assert_allclose(np.array(rg), np.array(rgo), rtol=1e-9)
+    with pytest.raises(he.HeError):
+        he.invsqrt_scaled_plan(0.0, 3, 2)

@@ -452,3 +452,68 @@ def test_bootstrap_full_size_ratio12():
     say(f"[gpu] bootstrap N=2^16, ratio 2^-12: max err {err:.2e}")
     assert err < 5e-2, err
     G.close()
+
+
+# Table 2 of the paper (Sec. 4, HE CutMax): T = 4, p = [16, 4, 4, 6], c = [5, 3, 3, 3]; the
+# variance domains (and mean(y^(T)) bounds) declared from 100 synthetic prompts per
+# vocabulary size with margins; the later iterations span up to five decades, so every
+# iteration after the first refines its guess with scaled steps
+TABLE2 = {
+    32768: dict(vlo=[12.0, 1e7, 4e6, 6e7], vhi=[24.0, 4e12, 1.6e10, 1.6e10], K=[0, 7, 5, 3],
+                sum_lo=1.5e5, sum_hi=2.5e6, gold_d=6),
+    151936: dict(vlo=[15.0, 2e6, 5e8, 2e10], vhi=[30.0, 8e10, 2e12, 2e12], K=[0, 6, 5, 3],
+                 sum_lo=1e7, sum_hi=5e7, gold_d=5),
+}
+
+
+def table2_cfgs(he, V, n):
+    from oracle.cutmax_fp64 import MirrorCfg, scaled_invsqrt_plan
+    d = TABLE2[V]
+    coef, steps, ranges = [], [], []
+    for t in range(4):
+        g, st, rg = scaled_invsqrt_plan(d["vlo"][t] / d["vhi"][t], 3, d["K"][t])
+        coef.append(list(g))
+        steps.append(st)
+        ranges.append(rg)
+    p, c = [16, 4, 4, 6], [5.0, 3.0, 3.0, 3.0]
+    cfg = he.CutmaxCfg(T=4, p=p, c=c, var_lo=d["vlo"], var_hi=d["vhi"], init_degree=3, init_coef=coef,
+                       sum_lo=d["sum_lo"], sum_hi=d["sum_hi"], gold_d=d["gold_d"],
+                       flags=he.HE_BOOT | he.HE_REFINE_SCALED, ref_steps=steps, ref_range=ranges)
+    mc = MirrorCfg(T=4, p=p, c=c, v_hi=d["vhi"], v_lo=d["vlo"], coef=coef, B=d["sum_hi"] * n, gold_d=d["gold_d"],
+                   sum_lo=d["sum_lo"] * n, scaled=steps)
+    return cfg, mc
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("V", [32768, 151936])
+def test_table2_schedule_bootstrapped(full, V):
+    """the paper's own HE schedule (Table 2: T = 4, p = [16, 4, 4, 6], c = [5, 3, 3, 3]) at its
+    two vocabulary sizes (32768 in one ciphertext, 151936 in five): bootstrapped (error-
+    corrected) where the 15 CutMax levels run out, the wide-domain inverse square root
+    bootstrapped in its middle; decrypts to the FP64 mirror of the same schedule within 1e-3,
+    recovers the argmax, and Z's maximum is near the printed E[max Z] (0.994 / 0.989)"""
+    from paper_2509_08383_amd import he
+    from oracle.cutmax_fp64 import cutmax_mirror, slot_layout
+    from workloads import llm_logits
+    G = full
+    x = llm_logits(20, V)
+    y, a, _ = slot_layout(x, G.slots)
+    cfg, mc = table2_cfgs(he, V, y.size)
+    try:
+        G.boot_setup(he.BootCfg(ratio_bits=6, correct_bits=6))
+        ct = G.encrypt(x)
+        G.sync()
+        t0 = time.time()
+        Z = G.cutmax([ct], cfg)[0]
+        G.sync()
+        ms = 1e3 * (time.time() - t0)
+        z = G.decrypt(Z, y.size)
+        ref = cutmax_mirror(y, mc)
+        err = float(np.abs(z - ref).max())
+        say(f"[gpu] Table 2 schedule, {V} logits ({a} ciphertexts): {ms:.0f} ms (first call), "
+            f"|Z - mirror| = {err:.2e}, max Z {z[:V].max():.4f} (mirror {ref[:V].max():.4f}), level {Z.level}")
+        assert err < 1e-3
+        assert int(np.argmax(z[:V])) == int(np.argmax(x))
+        assert z[:V].max() > 0.9
+    finally:
+        G.boot_setup(he.BootCfg(ratio_bits=6))

@@ -527,3 +527,107 @@ def test_foreign_operands_and_bad_options_are_rejected(toy):
         toy.G.set_option(he.HE_OPT_GRAPH, 0)
         toy.G.set_option(he.HE_OPT_NTT_VARIANT, 0)
     other.close()
+
+
+def _scaled_cfg(he, K, vlo, vhi):
+    from oracle.cutmax_fp64 import scaled_invsqrt_plan
+    coef, steps, ranges = [], [], []
+    for t in range(len(K)):
+        g, st, rg = scaled_invsqrt_plan(vlo[t] / vhi[t], 3, K[t])
+        coef.append(list(g))
+        steps.append(st)
+        ranges.append(rg)
+    return coef, steps, ranges
+
+
+def test_cutmax_scaled_refinement_bit_exact():
+    """the wide-domain inverse square root (HE_REFINE_SCALED: guess, then x <- x (a_k - b_k
+    x^2) carried on E h and on W = b_k x_k^2, the form of the Table 2 schedule) on a 2^40
+    toy chain: three iterations with 3, 0 and 1 refinements; one request word for word
+    against the oracle's schedule, and a batch of two requests (1 and 2 ciphertexts) whose
+    outputs equal the oracle's run of each; decrypted within 1e-3 of the FP64 mirror"""
+    from paper_2509_08383_amd import he
+    say("[gpu] scaled refinement schedule bit-exact (2^40 toy chain)")
+    P = Pair(he.Params(log_n=12, n_q=36, q0_bits=48, q_bits=40, p_bits=48, dnum=3, log2_scale=40, seed=7, hoist=3))
+    T, K = 3, [3, 0, 1]
+    vlo, vhi = [0.01, 0.25, 0.3], [2.0, 0.75, 3.0]
+    coef, steps, ranges = _scaled_cfg(he, K, vlo, vhi)
+    cfg = he.CutmaxCfg(T=T, p=[3] * T, c=[5.0] * T, var_lo=vlo, var_hi=vhi, init_degree=3, init_coef=coef,
+                       sum_lo=1.0, sum_hi=3.0, gold_d=3, flags=he.HE_REFINE_SCALED, ref_steps=steps,
+                       ref_range=ranges)
+    hc = ckks.HECfg(T=T, p=[3] * T, c=[5.0] * T, v_lo=vlo, v_hi=vhi, coef=coef, sum_lo=1.0, sum_hi=3.0, gold_d=3,
+                    scaled=steps)
+    x = toy_logits(5)
+    y, _, _ = slot_layout(x, P.G.slots)
+    g, o = P.enc_values(y)
+    Zg = P.G.cutmax([g], cfg)[0]
+    P.same(Zg, ckks.cutmax_he(P.O, [o], hc)[0], "scaled cutmax")
+    mc = MirrorCfg(T=T, p=[3] * T, c=[5.0] * T, v_hi=vhi, v_lo=vlo, coef=coef, B=3.0 * y.size, gold_d=3,
+                   sum_lo=1.0 * y.size, scaled=steps)
+    z = P.G.decrypt(Zg, y.size)
+    assert np.abs(z - cutmax_mirror(y, mc)).max() < 1e-3
+    assert int(np.argmax(z[:x.size])) == int(np.argmax(x))
+    # two requests in one call: 1024 logits (1 ciphertext) and 3000 (2 ciphertexts)
+    x2 = toy_logits(6, 3000)
+    y2, a2, _ = slot_layout(x2, P.G.slots)
+    m1 = ckks.encode(y, P.O.N, P.O.Delta)
+    m2 = [ckks.encode(y2[k * P.G.slots:(k + 1) * P.G.slots], P.O.N, P.O.Delta) for k in range(a2)]
+    g1 = P.G.encrypt_coeffs(m1, P.O.Delta, y.size)
+    o1 = P.O.encrypt_coeffs(m1, P.O.Delta)
+    g2 = P.G.encrypt_coeffs(np.concatenate(m2), P.O.Delta, y2.size)
+    o2 = [P.O.encrypt_coeffs(m, P.O.Delta) for m in m2]
+    Z = P.G.cutmax([g1, g2], cfg)
+    P.same(Z[0], ckks.cutmax_he(P.O, [o1], hc)[0], "batched request 0")
+    Zo2 = ckks.cutmax_he(P.O, o2, hc)
+    eg = P.G.export(Z[1])
+    for k in range(a2):
+        assert int((eg[k] != Zo2[k].export()).sum()) == 0, f"batched request 1, ciphertext {k}"
+    bad = he.CutmaxCfg(T=T, p=[3] * T, c=[5.0] * T, var_lo=vlo, var_hi=vhi, init_degree=3, init_coef=coef,
+                       flags=he.HE_REFINE_SCALED, ref_steps=steps, ref_range=[[(1.0, 0.5)] * (k + 1) for k in K])
+    with pytest.raises(he.HeError) as e:
+        P.G.cutmax([g1], bad)
+    assert e.value.code == he.HE_EINVAL
+
+
+
+def test_cutmax_prescaled_bit_exact():
+    """bounds that turn on the iterate's power-of-two prescale (p = 16 first: variance bound
+    1e7 for the second iteration, 2^-8 on the first output; mean bound 1.6e4, 2^-10 on the
+    last) on the 2^40 toy chain: a replicated request word for word against the oracle's
+    schedule, and a masked 1500-logit request (its pad tracker takes the same gain) beside
+    it equal to the oracle's masked run; both decrypt within 1e-3 of the FP64 mirror, which
+    has no prescale (CutMax is invariant under it)"""
+    from paper_2509_08383_amd import he
+    say("[gpu] prescaled schedule bit-exact (2^40 toy chain)")
+    P = Pair(he.Params(log_n=12, n_q=36, q0_bits=48, q_bits=40, p_bits=48, dnum=3, log2_scale=40, seed=7, hoist=3))
+    T, p, c = 2, [16, 8], [5.0, 5.0]
+    vlo, vhi = [0.5, 1e4], [2.0, 1e7]
+    coef, steps, ranges = _scaled_cfg(he, [1, 3], vlo, vhi)
+    cfg = he.CutmaxCfg(T=T, p=p, c=c, var_lo=vlo, var_hi=vhi, init_degree=3, init_coef=coef, sum_lo=4e3,
+                       sum_hi=1.6e4, gold_d=5, flags=he.HE_REFINE_SCALED | he.HE_MASK_PAD, ref_steps=steps,
+                       ref_range=ranges)
+    hc = ckks.HECfg(T=T, p=p, c=c, v_lo=vlo, v_hi=vhi, coef=coef, sum_lo=4e3, sum_hi=1.6e4, gold_d=5, scaled=steps)
+    assert hc.prescale() == [8, 10]
+    x = toy_logits(5)
+    y, _, _ = slot_layout(x, P.G.slots)
+    m1 = ckks.encode(y, P.O.N, P.O.Delta)
+    g1 = P.G.encrypt_coeffs(m1, P.O.Delta, y.size)
+    o1 = P.O.encrypt_coeffs(m1, P.O.Delta)
+    xm = toy_logits(41, 1500)
+    pad = float(xm.mean())
+    ym = np.full(P.G.slots, pad)
+    ym[:xm.size] = xm
+    m2 = ckks.encode(ym, P.O.N, P.O.Delta)
+    g2 = P.G.encrypt_coeffs(m2, P.O.Delta, xm.size)
+    g2.set_pad(pad)
+    o2 = P.O.encrypt_coeffs(m2, P.O.Delta)
+    Z = P.G.cutmax([g1, g2], cfg)
+    P.same(Z[0], ckks.cutmax_he(P.O, [o1], hc)[0], "prescaled cutmax")
+    P.same(Z[1], ckks.cutmax_he(P.O, [o2], hc, n_real=xm.size, pad=pad)[0], "prescaled masked cutmax")
+    # (the replicated request holds x twice: its argmax is taken over the first copy)
+    for v, xs, k in ((y, x, 0), (xm, xm, 1)):
+        mc = MirrorCfg(T=T, p=p, c=c, v_hi=vhi, v_lo=vlo, coef=coef, B=1.6e4 * v.size, gold_d=5,
+                       sum_lo=4e3 * v.size, scaled=steps)
+        z = P.G.decrypt(Z[k], v.size)
+        assert np.abs(z - cutmax_mirror(v, mc)).max() < 1e-3
+        assert int(np.argmax(z[:xs.size])) == int(np.argmax(xs))

@@ -324,3 +324,40 @@ def test_scaled_refinement_schedule_decrypts_to_the_mirror():
     z = O.decrypt(Z)
     assert np.abs(z - cutmax_mirror(y, mc)).max() < 1e-6
     assert int(np.argmax(z[:x.size])) == int(np.argmax(x))
+
+
+@pytest.mark.slow
+def test_prescaled_schedule_decrypts_to_the_mirror():
+    """a schedule whose bounds turn on the iterate's power-of-two prescale: p = 16 first,
+    so the second variance bound is 1e7, and the mean bound before the final division is
+    1.6e4 (the prescale is 2^-8 on the first output and 2^-10 on the last; at Table 2's
+    sizes, n = 32768 and variances near 4e12, it is what keeps 1/(n sqrt(n v)) above the
+    1/q a constant multiply resolves).  CutMax is invariant under it, so the decryption
+    equals the FP64 mirror, which has none, within 1e-6: a gain applied to the normaliser
+    but not to the added constant, or to the bounds but not to the iterate, fails this"""
+    from oracle.cutmax_fp64 import scaled_invsqrt_plan
+    O = ckks.Oracle(ckks.Params(log_n=12, n_q=36, q0_bits=48, q_bits=40, p_bits=48, dnum=3, log2_scale=40,
+                                seed=7, hoist=3))
+    O.keygen_cutmax()
+    x = toy_logits(5)
+    y, _, _ = slot_layout(x, O.slots)
+    T, p, c = 2, [16, 8], [5.0, 5.0]
+    vlo, vhi = [0.5, 1e6], [2.0, 1e7]
+    coef, steps = [], []
+    for t in range(T):
+        g, st, _ = scaled_invsqrt_plan(vlo[t] / vhi[t], 3, 1)
+        coef.append(list(g))
+        steps.append(st)
+    hc = ckks.HECfg(T=T, p=p, c=c, v_lo=vlo, v_hi=vhi, coef=coef, sum_lo=4e3, sum_hi=1.6e4, gold_d=5,
+                    scaled=steps)
+    assert hc.prescale() == [8, 10]
+    assert hc.levels_needed() == 29
+    Z = ckks.cutmax_he(O, [O.encrypt(y)], hc)[0]
+    mc = MirrorCfg(T=T, p=p, c=c, v_hi=vhi, v_lo=vlo, coef=coef, B=1.6e4 * y.size, gold_d=5,
+                   sum_lo=4e3 * y.size, scaled=steps)
+    z = O.decrypt(Z)
+    ref = cutmax_mirror(y, mc)
+    assert np.abs(z - ref).max() < 1e-6
+    assert int(np.argmax(z[:x.size])) == int(np.argmax(x))
+    # the mirror is not trivial here: the top logit holds nearly all the mass
+    assert ref.max() > 0.49
