@@ -39,7 +39,8 @@ typedef enum {
     HE_EDEVICE = -3,
     HE_EDEPTH = -4,
     HE_ERANGE = -5,
-    HE_ESTATE = -6
+    HE_ESTATE = -6,
+    HE_EIO = -7
 } he_status;
 
 typedef struct he_ctx he_ctx;
@@ -144,7 +145,7 @@ typedef struct {
      * ref_steps[t] = K_t refinements of the guess (0: the guess alone, newton_steps is then
      * ignored); ref_coef holds, iteration after iteration, K_t pairs (a_k, b_k) of
      * x <- x (a_k - b_k x^2), x = g(u) sqrt(u) (b_k > 0); ref_range holds K_t + 1 pairs
-     * (l_k, h_k), 0 < l_k < h_k, bounds of x before step k and after the last, which set the
+     * (l_k, h_k), 0 < l_k <= h_k, bounds of x before step k and after the last, which set the
      * bootstrap bounds.  he_invsqrt_scaled_plan computes all three for a domain.  The
      * refinement runs on E h (the centred, scaled iterate) and on W = b_k x_k^2, never on
      * u^(-1/2) itself: with HE_BOOT, W and E h are bootstrapped in the middle of the
@@ -406,10 +407,18 @@ int he_profile_end(he_ctx *ctx, char *buf, size_t cap);
  * forces variant k), HE_OPT_BOOT_HOIST (2, the default: the baby steps of a
  * bootstrap linear transform share one ModUp and the rotated giant-step sums share
  * one ModDown per 7 rotations; 1: only the baby steps are hoisted, equal word for
- * word to 0: one full key switch per rotation). */
+ * word to 0: one full key switch per rotation), HE_OPT_WORKSPACE_LIMIT (bytes of
+ * device workspace, the per-call buffers and constants, that one call of this
+ * context may use; 0, the default, is no limit: a call that needs more returns
+ * HE_ENOMEM after its host-side planning, before any allocation or kernel, and
+ * leaves the context and its handles usable; setting a limit below what the
+ * context holds frees the held workspace, which the next call allocates anew;
+ * keys, tables and ciphertext handles are not counted).  Device allocations that
+ * fail for lack of memory anywhere in the library return HE_ENOMEM. */
 #define HE_OPT_GRAPH 1
 #define HE_OPT_NTT_VARIANT 2
 #define HE_OPT_BOOT_HOIST 3
+#define HE_OPT_WORKSPACE_LIMIT 4
 int he_set_option(he_ctx *ctx, int option, int64_t value);
 
 /* NTT autotuner result: the schedule variant chosen for batch buckets of <=4,
@@ -450,6 +459,20 @@ int he_mlp_train(he_mlp *mlp, const float *u, size_t m, uint32_t epochs, uint32_
                  uint64_t seed, float *final_loss);
 /* coef[0..4]: power-basis coefficients of y(u) */
 int he_mlp_to_poly(const he_mlp *mlp, double *coef);
+/* File form of a trained network (1356 bytes, little-endian): "HEMLPv1\n", uint32
+ * parameter count 321 and hidden width 16, float32 mean and sd, the 321 float32
+ * weights in the order above, the float64 coefficients c0..c4 of he_mlp_to_poly, and
+ * an FNV-1a 64 checksum of everything before it.  he_mlp_save writes it (beside path,
+ * then renamed onto it, so readers see the old or the new file whole);
+ * he_mlp_load creates a network on `device` from it (weights and normalisation as
+ * saved, Adam moments zero); he_mlp_file_poly reads only the coefficients, with no
+ * GPU, for he_cutmax_cfg.init_coef.  Reads check size, magic, shape, checksum,
+ * finiteness and that the stored coefficients are the collapse of the stored weights
+ * (relative 1e-9): HE_EINVAL when they do not, HE_EIO when the file cannot be opened,
+ * read, written or renamed. */
+int he_mlp_save(const he_mlp *mlp, const char *path);
+int he_mlp_load(const char *path, int device, he_mlp **out);
+int he_mlp_file_poly(const char *path, double *coef);
 /* Training data: plaintext CutMax (Alg. 1) runs on the GPU over synthetic
  * LLM-like logits (vocab tokens zero-padded to `slots`, per-run Gumbel scale
  * ~U[1.5,4.5] and Zipf exponent ~U[0.9,1.3]); var_out[runs][T] receives the

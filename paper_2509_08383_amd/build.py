@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcutmax_he.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["kernels.hip", "ntt.hip", "evaluator.hip", "mlp.hip", "host_math.cpp", "boot_plan.cpp"]
+SOURCES = ["kernels.hip", "ntt.hip", "evaluator.hip", "mlp.hip", "host_math.cpp", "boot_plan.cpp", "mlp_file.cpp"]
 ARCH = os.environ.get("CUTMAX_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-Wno-unused-function",

@@ -171,6 +171,7 @@ struct he_ctx {
     std::map<int, const int *> xorder;  // smallest amount of a hoisted step -> x-block orbit order
     const int *xorder_id = nullptr;     // x-blocks in natural order (any rotation)
     int boot_hoist = 2;                 // 1: bootstrap baby steps share one ModUp; 2: also one ModDown per giant-step sum
+    size_t ws_limit = 0;                // HE_OPT_WORKSPACE_LIMIT: bytes of workspace a call may use (0: no limit)
     std::vector<uint32_t> key_gal;  // key index -> Galois element (0 for relinearisation)
     // graph cache keyed by a signature of the call
     std::map<std::string, hipGraphExec_t> graphs;
@@ -1251,6 +1252,9 @@ Bt cutmax_sched(Exec &X, Bt Y, const std::vector<Request> &reqs, const CutmaxCfg
 // ------------------------------------------------------------ bootstrapping
 void gen_keys(he_ctx *C, int from, int to = -1);
 static void drop_graphs(he_ctx *C);
+void dev_alloc(void **p, size_t bytes, const char *what);
+template <class T>
+void dev_alloc(T **p, size_t bytes, const char *what);
 
 // NTT-domain residues [limbs][N] of integer polynomials m[k][N] in new device
 // allocations (synchronous: set-up, outside any captured call)
@@ -1258,11 +1262,11 @@ std::vector<double *> upload_plains(he_ctx *C, const std::vector<std::vector<int
     const int N = C->N;
     std::vector<double *> out;
     int64_t *dm = nullptr;
-    HIPCHK(hipMalloc(&dm, 8ull * N * std::max<size_t>(1, m.size())));
+    dev_alloc(&dm, 8ull * N * std::max<size_t>(1, m.size()), "device buffer");
     try {
         for (size_t k = 0; k < m.size(); ++k) {
             double *pt = nullptr;
-            HIPCHK(hipMalloc(&pt, 8ull * limbs * N));
+            dev_alloc(&pt, 8ull * limbs * N, "device buffer");
             out.push_back(pt);
             HIPCHK(hipMemcpyAsync(dm + k * N, m[k].data(), 8ull * N, hipMemcpyHostToDevice, C->stream));
             const VecSet v{pt, limbs, limbs, 0, nullptr, nullptr};
@@ -1742,26 +1746,76 @@ static void drop_graphs(he_ctx *C) {
     C->graphs.clear();
 }
 
+// device allocation: out of memory is HE_ENOMEM (the error is cleared so that later
+// calls do not see it), any other failure HE_EDEVICE
+void dev_alloc(void **p, size_t bytes, const char *what) {
+    *p = nullptr;
+    const hipError_t e = hipMalloc(p, bytes);
+    if (e == hipSuccess) return;
+    *p = nullptr;
+    (void)hipGetLastError();
+    if (e == hipErrorOutOfMemory)
+        throw HeError(HE_ENOMEM, std::string(what) + ": device out of memory for " + std::to_string(bytes >> 20) + " MiB");
+    throw HeError(HE_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+template <class T>
+void dev_alloc(T **p, size_t bytes, const char *what) {
+    void *v = nullptr;
+    dev_alloc(&v, bytes, what);
+    *p = (T *)v;
+}
+
+// frees the workspace and the constant pool (the next call allocates what it needs)
+void free_workspace(he_ctx *C) {
+    drop_graphs(C);
+    if (C->arena.base) hipFree(C->arena.base);
+    C->arena.base = nullptr;
+    C->arena.cap = 0;
+    Pool &P = C->pool;
+    if (P.d_dv) hipFree(P.d_dv);
+    if (P.d_iv) hipFree(P.d_iv);
+    P.d_dv = nullptr;
+    P.d_iv = nullptr;
+    P.dcap = P.icap = 0;
+}
+
 void ensure_workspace(he_ctx *C) {
-    if (C->arena.peak > C->arena.cap || C->pool.dv.size() > C->pool.dcap || C->pool.iv.size() > C->pool.icap)
+    Pool &P = C->pool;
+    if (C->ws_limit > 0) {
+        // checked after the dry pass, before any allocation or kernel of the call
+        const size_t need = C->arena.peak + P.dv.size() * 8 + P.iv.size() * 4;
+        if (need > C->ws_limit)
+            throw HeError(HE_ENOMEM, "workspace limit: the call needs " + std::to_string((need + (1 << 20) - 1) >> 20) +
+                                         " MiB, the limit is " + std::to_string(C->ws_limit >> 20) + " MiB");
+    }
+    if (C->arena.peak > C->arena.cap || P.dv.size() > P.dcap || P.iv.size() > P.icap)
         drop_graphs(C);
     if (C->arena.peak > C->arena.cap) {
         if (C->arena.base) HIPCHK(hipFree(C->arena.base));
         C->arena.base = nullptr;
-        const size_t want = C->arena.peak + (64u << 20);
-        HIPCHK(hipMalloc(&C->arena.base, want));
+        C->arena.cap = 0;
+        size_t want = C->arena.peak + (64u << 20);
+        // under a limit the slack (growth room for later calls) stays within it
+        if (C->ws_limit > 0)
+            want = std::max(C->arena.peak, std::min(want, C->ws_limit - (P.dv.size() * 8 + P.iv.size() * 4)));
+        dev_alloc(&C->arena.base, want, "workspace");
         C->arena.cap = want;
     }
-    Pool &P = C->pool;
     if (P.dv.size() > P.dcap) {
         if (P.d_dv) HIPCHK(hipFree(P.d_dv));
-        P.dcap = P.dv.size() * 2 + 1024;
-        HIPCHK(hipMalloc(&P.d_dv, P.dcap * 8));
+        P.d_dv = nullptr;
+        P.dcap = 0;
+        const size_t want = C->ws_limit > 0 ? P.dv.size() : P.dv.size() * 2 + 1024;
+        dev_alloc(&P.d_dv, want * 8, "constant pool");
+        P.dcap = want;
     }
     if (P.iv.size() > P.icap) {
         if (P.d_iv) HIPCHK(hipFree(P.d_iv));
-        P.icap = P.iv.size() * 2 + 1024;
-        HIPCHK(hipMalloc(&P.d_iv, P.icap * 4));
+        P.d_iv = nullptr;
+        P.icap = 0;
+        const size_t want = C->ws_limit > 0 ? P.iv.size() : P.iv.size() * 2 + 1024;
+        dev_alloc(&P.d_iv, want * 4, "constant pool");
+        P.icap = want;
     }
     if (!P.dv.empty()) HIPCHK(hipMemcpyAsync(P.d_dv, P.dv.data(), P.dv.size() * 8, hipMemcpyHostToDevice, C->stream));
     if (!P.iv.empty()) HIPCHK(hipMemcpyAsync(P.d_iv, P.iv.data(), P.iv.size() * 4, hipMemcpyHostToDevice, C->stream));
@@ -2016,8 +2070,8 @@ void build_ctx(he_ctx *C, const he_params *prm) {
     std::vector<int> xid(std::max(1, N / 256));
     for (int B = 0; B < (int)xid.size(); ++B) xid[B] = B;
     const size_t o_xid = tb.i(xid);
-    HIPCHK(hipMalloc(&C->d_tab, tb.dv.size() * 8));
-    HIPCHK(hipMalloc(&C->d_itab, tb.iv.size() * 4));
+    dev_alloc(&C->d_tab, tb.dv.size() * 8, "device buffer");
+    dev_alloc(&C->d_itab, tb.iv.size() * 4, "device buffer");
     HIPCHK(hipMemcpy(C->d_tab, tb.dv.data(), tb.dv.size() * 8, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(C->d_itab, tb.iv.data(), tb.iv.size() * 4, hipMemcpyHostToDevice));
     double *D = C->d_tab;
@@ -2117,10 +2171,10 @@ void gen_keys(he_ctx *C, int from, int to) {
     int *dsmall = nullptr;
     double *te = nullptr, *tg = nullptr, *tk = nullptr;
     const size_t per = (size_t)np * N, kw = (size_t)C->betaL * 2 * per;
-    HIPCHK(hipMalloc(&dsmall, sizeof(int) * N));
-    HIPCHK(hipMalloc(&te, 8ull * per));
-    HIPCHK(hipMalloc(&tg, 8ull * per));
-    HIPCHK(hipMalloc(&tk, 8ull * kw));  // one key as doubles, packed after generation
+    dev_alloc(&dsmall, sizeof(int) * N, "device buffer");
+    dev_alloc(&te, 8ull * per, "device buffer");
+    dev_alloc(&tg, 8ull * per, "device buffer");
+    dev_alloc(&tk, 8ull * kw, "device buffer");  // one key as doubles, packed after generation
     const VecSet all_sk{C->d_sk, np, np, 0, nullptr, nullptr};
     C->keys.resize(nkeys, KeyRef{nullptr, nullptr});
     for (int k = from; k < to; ++k) {
@@ -2132,8 +2186,8 @@ void gen_keys(he_ctx *C, int from, int to) {
         }
         uint32_t *klo = nullptr;
         uint16_t *khi = nullptr;
-        HIPCHK(hipMalloc(&klo, 4ull * kw));
-        HIPCHK(hipMalloc(&khi, 2ull * kw));
+        dev_alloc(&klo, 4ull * kw, "device buffer");
+        dev_alloc(&khi, 2ull * kw, "device buffer");
         C->keys[k] = KeyRef{klo, khi};
         if (k == 0) launch_square_res(T, tg, C->d_sk, np, s);
         else {
@@ -2165,8 +2219,8 @@ void gen_keys(he_ctx *C, int from, int to) {
 void keygen(he_ctx *C) {
     const int N = C->N, np = C->np;
     int *dsmall = nullptr;
-    HIPCHK(hipMalloc(&dsmall, sizeof(int) * N));
-    HIPCHK(hipMalloc(&C->d_sk, 8ull * np * N));
+    dev_alloc(&dsmall, sizeof(int) * N, "device buffer");
+    dev_alloc(&C->d_sk, 8ull * np * N, "device buffer");
     const VecSet all_sk{C->d_sk, np, np, 0, nullptr, nullptr};
     if (C->secret_hw > 0) {
         const std::vector<int> sk = sparse_secret(N, C->secret_hw, C->seed, OBJ_SKH);
@@ -2200,7 +2254,7 @@ void autotune_ntt(he_ctx *C) {
         const int target[kTuneBuckets] = {4, 16, 64, 256, 1024, 4096};
         const int N = C->N, grp = C->L + 1;
         double *buf = nullptr;
-        HIPCHK(hipMalloc(&buf, 8ull * target[kTuneBuckets - 1] * N));
+        dev_alloc(&buf, 8ull * target[kTuneBuckets - 1] * N, "device buffer");
         hipEvent_t a, b;
         HIPCHK(hipEventCreate(&a));
         HIPCHK(hipEventCreate(&b));
@@ -2320,7 +2374,8 @@ CutmaxCfg parse_cfg(he_ctx *C, const he_cutmax_cfg *cfg) {
             }
             for (int k = 0; k <= K; ++k, ir += 2) {
                 const double l = cfg->ref_range[ir], h = cfg->ref_range[ir + 1];
-                REQUIRE(std::isfinite(l) && std::isfinite(h) && l > 0 && l < h, HE_EINVAL, "ref_range: 0 < l < h");
+                // (a plan converged to double precision gives l == h)
+                REQUIRE(std::isfinite(l) && std::isfinite(h) && l > 0 && l <= h, HE_EINVAL, "ref_range: 0 < l <= h");
                 cf.ranges[t].push_back({l, h});
             }
         }
@@ -2688,7 +2743,7 @@ int he_decrypt(he_ctx *C, const he_ct *ct, double *out, size_t n) {
         const size_t s = (size_t)C->slots;
         std::vector<double> res((size_t)nl * N), slotv((size_t)ct->a * s), mc(N);
         double *dm = nullptr;
-        HIPCHK(hipMalloc(&dm, 8ull * nl * N));
+        dev_alloc(&dm, 8ull * nl * N, "device buffer");
         try {
             for (uint32_t c = 0; c < ct->a; ++c) {
                 const double *c0 = ct->d + (size_t)c * 2 * (C->L + 1) * N, *c1 = c0 + (size_t)(C->L + 1) * N;
@@ -2820,7 +2875,7 @@ int he_ct_export(he_ctx *C, const he_ct *ct, uint64_t *limbs, size_t cap) {
         const size_t need = (size_t)ct->a * 2 * (l + 1) * N;
         REQUIRE(cap >= need, HE_EINVAL, "export buffer too small");
         double *tmp = nullptr;
-        HIPCHK(hipMalloc(&tmp, need * 8));
+        dev_alloc(&tmp, need * 8, "device buffer");
         std::vector<double> h(need);
         try {
             const VecSet dst{tmp, (int)ct->a * 2 * (l + 1), l + 1, (long long)(l + 1) * N, nullptr, nullptr};
@@ -2856,7 +2911,7 @@ int he_ct_import(he_ctx *C, const uint64_t *limbs, uint32_t a, uint32_t level, d
         he_ct *ct = new_ct(C, a);
         double *tmp = nullptr;
         try {
-            HIPCHK(hipMalloc(&tmp, words * 8));
+            dev_alloc(&tmp, words * 8, "device buffer");
             HIPCHK(hipMemcpyAsync(tmp, h.data(), words * 8, hipMemcpyHostToDevice, C->stream));
             const VecSet src{tmp, (int)a * 2 * (l + 1), l + 1, (long long)(l + 1) * N, nullptr, nullptr};
             launch_ntt(C->T, src, false, C->ntt_variant, C->stream);
@@ -3051,7 +3106,7 @@ int he_bench_ntt(he_ctx *C, uint32_t vectors, uint32_t iters, double *ms_fwd, do
         HIPCHK(hipSetDevice(C->device));
         const int N = C->N;
         double *buf = nullptr;
-        HIPCHK(hipMalloc(&buf, 8ull * vectors * N));
+        dev_alloc(&buf, 8ull * vectors * N, "device buffer");
         hipEvent_t a, b, c;
         HIPCHK(hipEventCreate(&a)); HIPCHK(hipEventCreate(&b)); HIPCHK(hipEventCreate(&c));
         const int grp = std::min<int>((int)vectors, C->L + 1);
@@ -3086,7 +3141,7 @@ int he_bench_copy(he_ctx *C, uint32_t vectors, uint32_t iters, double *ms) {
         HIPCHK(hipSetDevice(C->device));
         const int N = C->N;
         double *buf = nullptr;
-        HIPCHK(hipMalloc(&buf, 16ull * vectors * N));
+        dev_alloc(&buf, 16ull * vectors * N, "device buffer");
         hipEvent_t a, b;
         HIPCHK(hipEventCreate(&a));
         HIPCHK(hipEventCreate(&b));
@@ -3211,6 +3266,19 @@ int he_set_option(he_ctx *C, int option, int64_t value) {
     if (option == HE_OPT_BOOT_HOIST) {
         C->boot_hoist = value <= 0 ? 0 : (value >= 2 ? 2 : 1);
         drop_graphs(C);  // captured graphs hold the other launch sequence
+        return HE_OK;
+    }
+    if (option == HE_OPT_WORKSPACE_LIMIT) {
+        if (value < 0) { g_err = "workspace limit must be >= 0"; return HE_EINVAL; }
+        C->ws_limit = (size_t)value;
+        // memory held beyond the new limit is returned now
+        const size_t held = C->arena.cap + C->pool.dcap * 8 + C->pool.icap * 4;
+        if (C->ws_limit > 0 && held > C->ws_limit)
+            return guarded([&]() {
+                HIPCHK(hipStreamSynchronize(C->stream));
+                free_workspace(C);
+                return HE_OK;
+            });
         return HE_OK;
     }
     g_err = "unknown option";

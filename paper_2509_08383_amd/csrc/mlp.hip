@@ -27,11 +27,12 @@
 
 #include "../../include/he.h"
 #include "he_internal.h"
+#include "mlp_file.h"
 
 namespace {
 
-constexpr int HID = 16;
-constexpr int NP = HID + HID + HID * HID + HID + HID + 1;  // 321
+constexpr int HID = he::kMlpHidden;
+constexpr int NP = he::kMlpParams;  // 321
 constexpr int MB = 128;                                    // samples per block
 
 __global__ __launch_bounds__(MB) void k_mlp_fwd_bwd(const float *u, int m, const float *theta, float mean,
@@ -388,26 +389,49 @@ int he_mlp_to_poly(const he_mlp *M, double *coef) {
         MCHK(hipSetDevice(M->device));
         std::vector<float> th(NP);
         MCHK(hipMemcpy(th.data(), M->d_theta, NP * 4, hipMemcpyDeviceToHost));
-        const double s = M->sd, mu = M->mean;
-        // z = (u - mu)/s = z0 + z1 u
-        const double z0 = -mu / s, z1 = 1.0 / s;
-        double y[5] = {0, 0, 0, 0, 0};
-        // a1_k(u) = (W1_k z + b1_k)^2 as a quadratic q0 + q1 u + q2 u^2
-        double A1[HID][3];
-        for (int k = 0; k < HID; ++k) {
-            const double l0 = th[k] * z0 + th[HID + k], l1 = th[k] * z1;
-            A1[k][0] = l0 * l0; A1[k][1] = 2 * l0 * l1; A1[k][2] = l1 * l1;
-        }
-        for (int j = 0; j < HID; ++j) {
-            double h[3] = {th[2 * HID + HID * HID + j], 0, 0};
-            for (int k = 0; k < HID; ++k)
-                for (int d = 0; d < 3; ++d) h[d] += (double)th[2 * HID + j * HID + k] * A1[k][d];
-            const double w = th[3 * HID + HID * HID + j];
-            for (int a = 0; a < 3; ++a)
-                for (int b = 0; b < 3; ++b) y[a + b] += w * h[a] * h[b];
-        }
-        y[0] += th[NP - 1];
-        for (int d = 0; d < 5; ++d) coef[d] = y[d];
+        he::mlp_poly(th.data(), M->mean, M->sd, coef);
+        return HE_OK;
+    });
+}
+
+int he_mlp_save(const he_mlp *M, const char *path) {
+    return mguard([&]() {
+        if (!M || !path) throw MErr(HE_EINVAL, "bad argument");
+        MCHK(hipSetDevice(M->device));
+        MCHK(hipStreamSynchronize(M->s));
+        std::vector<float> th(NP);
+        MCHK(hipMemcpy(th.data(), M->d_theta, NP * 4, hipMemcpyDeviceToHost));
+        std::string err;
+        const int rc = he::mlp_file_write(path, th.data(), M->mean, M->sd, &err);
+        if (rc != HE_OK) throw MErr(rc, err);
+        return HE_OK;
+    });
+}
+
+int he_mlp_load(const char *path, int device, he_mlp **out) {
+    return mguard([&]() {
+        if (!path || !out) throw MErr(HE_EINVAL, "bad argument");
+        std::vector<float> th(NP);
+        float mean = 0, sd = 1;
+        std::string err;
+        const int rc = he::mlp_file_read(path, th.data(), &mean, &sd, nullptr, &err);
+        if (rc != HE_OK) throw MErr(rc, err);
+        he_mlp *M = nullptr;
+        int c = he_mlp_create(0, device, &M);
+        if (c != HE_OK) return c;
+        c = he_mlp_set_params(M, th.data(), NP, mean, sd);
+        if (c != HE_OK) { he_mlp_destroy(M); return c; }
+        *out = M;
+        return (int)HE_OK;
+    });
+}
+
+int he_mlp_file_poly(const char *path, double *coef) {
+    return mguard([&]() {
+        if (!path || !coef) throw MErr(HE_EINVAL, "bad argument");
+        std::string err;
+        const int rc = he::mlp_file_read(path, nullptr, nullptr, nullptr, coef, &err);
+        if (rc != HE_OK) throw MErr(rc, err);
         return HE_OK;
     });
 }

@@ -16,13 +16,13 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcutmax_he.so")
 
-HE_OK, HE_EINVAL, HE_ENOMEM, HE_EDEVICE, HE_EDEPTH, HE_ERANGE, HE_ESTATE = 0, -1, -2, -3, -4, -5, -6
+HE_OK, HE_EINVAL, HE_ENOMEM, HE_EDEVICE, HE_EDEPTH, HE_ERANGE, HE_ESTATE, HE_EIO = 0, -1, -2, -3, -4, -5, -6, -7
 HE_NOISE_PRESCALED = 1
 HE_REFINE_GOLDSCHMIDT = 2
 HE_MASK_PAD = 4
 HE_BOOT = 8
 HE_REFINE_SCALED = 16
-HE_OPT_GRAPH, HE_OPT_NTT_VARIANT, HE_OPT_BOOT_HOIST = 1, 2, 3
+HE_OPT_GRAPH, HE_OPT_NTT_VARIANT, HE_OPT_BOOT_HOIST, HE_OPT_WORKSPACE_LIMIT = 1, 2, 3, 4
 
 _c_u32p = ctypes.POINTER(ctypes.c_uint32)
 _c_u64p = ctypes.POINTER(ctypes.c_uint64)
@@ -497,6 +497,9 @@ def _mlp_lib():
             "he_mlp_train": [_V, _c_fp, ctypes.c_size_t, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_float,
                              ctypes.c_uint64, _c_fp],
             "he_mlp_to_poly": [_V, _c_dp],
+            "he_mlp_save": [_V, ctypes.c_char_p],
+            "he_mlp_load": [ctypes.c_char_p, ctypes.c_int, ctypes.POINTER(_V)],
+            "he_mlp_file_poly": [ctypes.c_char_p, _c_dp],
             "he_variance_log": [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                 ctypes.c_uint32, ctypes.c_uint32, ctypes.c_double, ctypes.c_int, _c_fp, _c_fp],
         }
@@ -523,10 +526,24 @@ def _fp(a):
 class InvSqrtMLP:
     """The learned initial guess (he_mlp): FP32 training on the GPU, collapse to a quartic."""
 
-    def __init__(self, seed: int = 0, device: int = 0):
+    def __init__(self, seed: int = 0, device: int = 0, _handle=None):
+        if _handle is not None:
+            self.h = _handle
+            return
         h = _V()
         _mcheck(_mlp_lib().he_mlp_create(seed, device, ctypes.byref(h)))
         self.h = h
+
+    @classmethod
+    def load(cls, path: str, device: int = 0) -> "InvSqrtMLP":
+        """a network from a file written by save (he_mlp_load)"""
+        h = _V()
+        _mcheck(_mlp_lib().he_mlp_load(os.fsencode(path), device, ctypes.byref(h)))
+        return cls(_handle=h)
+
+    def save(self, path: str):
+        """weights, normalisation and collapsed quartic to `path` (he_mlp_save)"""
+        _mcheck(_mlp_lib().he_mlp_save(self.h, os.fsencode(path)))
 
     def __del__(self):
         try:
@@ -569,6 +586,13 @@ class InvSqrtMLP:
         c = np.empty(5, dtype=np.float64)
         _mcheck(_mlp_lib().he_mlp_to_poly(self.h, _dp(c)))
         return c
+
+
+def mlp_file_poly(path: str) -> np.ndarray:
+    """the collapsed quartic c0..c4 stored in a learned-guess file (he_mlp_file_poly; no GPU)"""
+    c = np.empty(5, dtype=np.float64)
+    _mcheck(_mlp_lib().he_mlp_file_poly(os.fsencode(path), _dp(c)))
+    return c
 
 
 def variance_log(seed: int, runs: int, vocab: int = 32000, slots: int = 32768, T: int = 3, p: int = 3,

@@ -140,3 +140,53 @@ def test_invsqrt_scaled_plan_is_host_only_and_matches_the_oracle():
         np.testing.assert_allclose(np.array(rg), np.array(rgo), rtol=1e-9)
     with pytest.raises(he.HeError):
         he.invsqrt_scaled_plan(0.0, 3, 2)
+
+
+def _mlp_file_bytes(theta, mean, sd, poly):
+    """a learned-guess file written from the layout include/he.h documents (he_mlp_save)"""
+    import struct
+    import numpy as np
+    body = b"HEMLPv1\n" + struct.pack("<IIff", 321, 16, mean, sd) + np.asarray(theta, "<f4").tobytes() \
+        + np.asarray(poly, "<f8").tobytes()
+    h = 0xcbf29ce484222325
+    for byte in body:
+        h = ((h ^ byte) * 0x100000001b3) & 0xFFFFFFFFFFFFFFFF
+    return body + struct.pack("<Q", h)
+
+
+def test_learned_guess_file_is_read_without_gpu(tmp_path):
+    """he_mlp_file_poly reads the collapsed quartic of a learned-guess file with no GPU: a
+    file built here from the documented layout, with the quartic from the independent
+    collapse (oracle/mlp_ref.to_poly), is accepted and its coefficients returned as stored;
+    a flipped weight byte (checksum), a stored quartic that is not the weights' collapse
+    (checksum recomputed), a truncated file, another magic and a missing file are refused"""
+    _ensure_built()
+    import numpy as np
+    from paper_2509_08383_amd import he
+    from oracle.mlp_ref import to_poly
+    rng = np.random.default_rng(3)
+    theta = (0.3 * rng.standard_normal(321)).astype(np.float32)
+    mean, sd = np.float32(0.42), np.float32(0.29)
+    poly = to_poly(theta.astype(np.float64), float(mean), float(sd))
+    good = _mlp_file_bytes(theta, mean, sd, poly)
+    assert len(good) == 1356
+    f = tmp_path / "guess.bin"
+    f.write_bytes(good)
+    assert (he.mlp_file_poly(str(f)) == poly).all()
+    cases = {}
+    flipped = bytearray(good)
+    flipped[24 + 4 * 100] ^= 0x01
+    cases["checksum"] = bytes(flipped)
+    off = poly.copy()
+    off[2] *= 1.0 + 1e-6
+    cases["collapse"] = _mlp_file_bytes(theta, mean, sd, off)
+    cases["bytes"] = good[:-9]
+    cases["not a learned-guess file"] = b"HEMLPv2\n" + good[8:]
+    for what, data in cases.items():
+        f.write_bytes(data)
+        with pytest.raises(he.HeError) as e:
+            he.mlp_file_poly(str(f))
+        assert e.value.code == he.HE_EINVAL and what in str(e.value), (what, str(e.value))
+    with pytest.raises(he.HeError) as e:
+        he.mlp_file_poly(str(tmp_path / "missing.bin"))
+    assert e.value.code == he.HE_EIO

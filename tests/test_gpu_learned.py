@@ -61,6 +61,33 @@ def _run_logits(seed, run, vocab, slots):
     return x
 
 
+def test_trained_network_saves_and_loads(tmp_path):
+    """he_mlp_save / he_mlp_load / he_mlp_file_poly: a network trained a few epochs on the
+    GPU, saved and loaded into a new handle, has the same weights and normalisation bit for
+    bit, the same forward outputs and the same quartic, which the file also holds (read
+    without a network); training resumes from the loaded weights"""
+    from paper_2509_08383_amd import he
+    say("[gpu] learned guess: save, load, file quartic")
+    rng = np.random.default_rng(5)
+    u = rng.uniform(0.1, 1.0, 20000).astype(np.float32)
+    M = he.InvSqrtMLP(seed=4)
+    M.train(u, epochs=3, batch=1024, lr=1e-2, seed=1)
+    path = str(tmp_path / "guess.bin")
+    M.save(path)
+    N = he.InvSqrtMLP.load(path)
+    t0, m0, s0 = M.get_params()
+    t1, m1, s1 = N.get_params()
+    assert (t0 == t1).all() and m0 == m1 and s0 == s1
+    assert (M.forward(u) == N.forward(u)).all()
+    q = M.to_poly()
+    assert (N.to_poly() == q).all() and (he.mlp_file_poly(path) == q).all()
+    np.testing.assert_allclose(q, mlp_ref.to_poly(t0.astype(np.float64), float(m0), float(s0)), rtol=1e-9,
+                               atol=1e-12 * np.abs(q).max())
+    before = N.forward(u)
+    N.train(u, epochs=1, batch=1024, lr=1e-3, seed=2)
+    assert not (N.forward(u) == before).all()
+
+
 def test_variance_logger_matches_plaintext_cutmax():
     from paper_2509_08383_amd import he
     say("[gpu] variance logger")

@@ -631,3 +631,44 @@ def test_cutmax_prescaled_bit_exact():
         z = P.G.decrypt(Z[k], v.size)
         assert np.abs(z - cutmax_mirror(v, mc)).max() < 1e-3
         assert int(np.argmax(z[:xs.size])) == int(np.argmax(xs))
+
+
+def test_workspace_limit_returns_enomem_and_recovers(toy):
+    """HE_OPT_WORKSPACE_LIMIT: under a 1 MiB limit a CutMax and a rotate-and-sum return
+    HE_ENOMEM (the failure a full device gives, forced from the host after the call's
+    planning and before any allocation or kernel), create no output, and leave the context
+    usable; the entry point that allocates nothing still runs; with a limit the call fits in
+    and with none, the outputs equal the first call's word for word"""
+    from paper_2509_08383_amd import he
+    say("[gpu] workspace limit -> HE_ENOMEM, then recovery")
+    G = toy.G
+    x = toy_logits(9)
+    y, _, _ = slot_layout(x, G.slots)
+    g, _ = toy.enc_values(y)
+    p, c, vlo, vhi, coef = toy_cfg(y.size)
+    cfg = he.CutmaxCfg(T=4, p=p, c=c, var_lo=vlo, var_hi=vhi, init_degree=3, init_coef=coef, sum_lo=1.0,
+                       sum_hi=3.0, gold_d=3)
+    ref = G.export(G.cutmax([g], cfg)[0])
+    ref_rs = G.export(G.rotsum(g))
+    try:
+        G.set_option(he.HE_OPT_WORKSPACE_LIMIT, 1 << 20)
+        for f in (lambda: G.cutmax([g], cfg), lambda: G.rotsum(g)):
+            with pytest.raises(he.HeError) as e:
+                f()
+            assert e.value.code == he.HE_ENOMEM and "workspace limit" in str(e.value)
+        with pytest.raises(he.HeError) as e:
+            G.set_option(he.HE_OPT_WORKSPACE_LIMIT, -1)
+        assert e.value.code == he.HE_EINVAL
+        G.set_option(he.HE_OPT_WORKSPACE_LIMIT, 256 << 20)
+        assert (G.export(G.cutmax([g], cfg)[0]) == ref).all()
+        dst, _ = toy.enc_values(y)  # (encryption uses the workspace too)
+        G.set_option(he.HE_OPT_WORKSPACE_LIMIT, 1 << 20)
+        with pytest.raises(he.HeError) as e:
+            toy.G.encrypt(y)
+        assert e.value.code == he.HE_ENOMEM
+        G.rotsum_noalloc(g, dst)
+        assert (G.export(dst) == ref_rs).all()
+    finally:
+        G.set_option(he.HE_OPT_WORKSPACE_LIMIT, 0)
+    assert (G.export(G.cutmax([g], cfg)[0]) == ref).all()
+    assert (G.export(G.rotsum(g)) == ref_rs).all()
