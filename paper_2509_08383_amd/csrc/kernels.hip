@@ -575,8 +575,9 @@ void launch_inner_product(const DevTables &T, const double *ext, long long estri
 // ciphertext is issued before the first product waits on one (the loads of a wave are
 // then in flight together instead of one rotation at a time).  BETA = 0 or NR = 0 read
 // the runtime counts (at most 8 digits).
+// (with three digits 3 waves per SIMD: at 4 the unrolled form spills to scratch)
 template <int BETA, int NR>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_inner_product_rot(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BETA >= 3 ? 3 : 4))) void k_inner_product_rot(
     DevTables T, const double *__restrict__ ext, long long esb, long long esj, double *__restrict__ acc0,
     double *__restrict__ acc1, long long astride, RotSet rs, int betaL, int cnt, int beta_rt, int next,
     const int *__restrict__ ext_prime, int xblocks) {
@@ -601,7 +602,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         double s0 = 0.0, s1 = 0.0;
         if (BETA > 0 && NR > 0) {
             constexpr int R = NR > 0 ? NR : 1, J = BETA > 0 ? BETA : 1;
-            constexpr int RC = R > (J >= 3 ? 3 : 4) ? (J >= 3 ? 3 : 4) : R;  // rotations whose loads fly together
+            constexpr int RC = R > (J >= 3 ? 2 : 4) ? (J >= 3 ? 2 : 4) : R;  // rotations whose loads fly together
             double g0 = wsum && rs.c0_id ? C0[x] : 0.0;
 #pragma unroll
             for (int r0 = 0; r0 < R; r0 += RC) {
@@ -693,7 +694,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         for (int j = 0; j < BETA; ++j) key_pair(rs.key[r], betaL, pt, j, T.N, x, k0[r][j], k1[r][j]);
     }
     const bool wsum = rs.c0 && t <= rs.lq;
-    constexpr int RC = NR > 3 ? 3 : NR;  // rotations whose gathers are in flight together
+    // rotations whose gathers are in flight together (with 7 x 3 keys held, a third
+    // rotation's gathers would spill to scratch at 3 waves per SIMD)
+    constexpr int RCW = BETA >= 3 ? 2 : 3;
+    constexpr int RC = NR > RCW ? RCW : NR;
     for (int ct = 0; ct < cnt; ++ct) {
         const double *E = ext + ct * esb + (long long)t * T.N;
         double s0 = 0.0, s1 = 0.0;
