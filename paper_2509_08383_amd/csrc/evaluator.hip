@@ -1070,8 +1070,36 @@ Bt scaled_normalise(Exec &X, const Bt &U, const Bt &E, const std::vector<Request
         const int need = k + 1 < K ? 3 : 2;
         if (W.level < need) {
             REQUIRE(cf.boot && C->boot.ready, HE_EDEPTH, "scaled refinement needs more levels than the chain has");
-            W = bootstrap(X, W, 1.02 * st[k].second * rg[k].second * rg[k].second);
-            Ey = bootstrap(X, Ey, 1.02 * ebound * rg[k].second);
+            // one bootstrap of W and Ey together: W times the integer m (no level) reaches
+            // Ey's bound, and the output's scale times m gives W back, with the error W
+            // alone would have had under its own bound
+            const double bW = 1.02 * st[k].second * rg[k].second * rg[k].second;
+            const double bE = 1.02 * ebound * rg[k].second;
+            const int64_t m = std::max<int64_t>(1, (int64_t)std::floor(bE / bW));
+            const Bt Wm = m > 1 ? X.mul_int(W, std::vector<int64_t>(R, m)) : W;
+            const Bt Ed = X.drop(Ey, W.level);
+            Bt J = X.new_bt(R + Ey.cnt, W.level);
+            Bt jw = J, je = J;
+            jw.cnt = R;
+            jw.scale.assign(Wm.scale.begin(), Wm.scale.end());
+            je.cnt = Ey.cnt;
+            je.d = J.d + (long long)R * 2 * J.cap * C->N;
+            je.scale.assign(Ed.scale.begin(), Ed.scale.end());
+            for (int i = 0; i < R; ++i) J.scale[i] = Wm.scale[i];
+            for (int i = 0; i < Ey.cnt; ++i) J.scale[R + i] = Ed.scale[i];
+            if (X.go()) {
+                launch_copy(X.T, X.vs_all(jw), X.vs_all(Wm), X.s);
+                launch_copy(X.T, X.vs_all(je), X.vs_all(Ed), X.s);
+            }
+            const Bt B = bootstrap(X, J, std::max(bE, (double)m * bW));
+            W = B;
+            W.cnt = R;
+            W.scale.assign(B.scale.begin(), B.scale.begin() + R);
+            for (double &sc : W.scale) sc *= (double)m;
+            Ey = B;
+            Ey.cnt = (int)B.scale.size() - R;
+            Ey.d = B.d + (long long)R * 2 * B.cap * C->N;
+            Ey.scale.assign(B.scale.begin() + R, B.scale.end());
         }
         std::vector<double> ak(R, st[k].first);
         Bt Rk = X.add_const(X.mul_int(W, std::vector<int64_t>(R, -1)), ak);
@@ -1765,6 +1793,30 @@ void dev_alloc(T **p, size_t bytes, const char *what) {
     *p = (T *)v;
 }
 
+// device temporaries and events of one host function, released on every exit
+// (exceptions included); hipFree waits for the work still using them
+struct DevScope {
+    std::vector<void *> mem;
+    std::vector<hipEvent_t> ev;
+    template <class T>
+    T *alloc(size_t bytes, const char *what) {
+        T *p = nullptr;
+        dev_alloc(&p, bytes, what);
+        mem.push_back(p);
+        return p;
+    }
+    hipEvent_t event() {
+        hipEvent_t e = nullptr;
+        HIPCHK(hipEventCreate(&e));
+        ev.push_back(e);
+        return e;
+    }
+    ~DevScope() {
+        for (hipEvent_t e : ev) hipEventDestroy(e);
+        for (void *p : mem) hipFree(p);
+    }
+};
+
 // frees the workspace and the constant pool (the next call allocates what it needs)
 void free_workspace(he_ctx *C) {
     drop_graphs(C);
@@ -2168,13 +2220,12 @@ void gen_keys(he_ctx *C, int from, int to) {
     const int nkeys = (int)C->key_gal.size();
     if (to < 0 || to > nkeys) to = nkeys;
     if (from >= to) return;
-    int *dsmall = nullptr;
-    double *te = nullptr, *tg = nullptr, *tk = nullptr;
     const size_t per = (size_t)np * N, kw = (size_t)C->betaL * 2 * per;
-    dev_alloc(&dsmall, sizeof(int) * N, "device buffer");
-    dev_alloc(&te, 8ull * per, "device buffer");
-    dev_alloc(&tg, 8ull * per, "device buffer");
-    dev_alloc(&tk, 8ull * kw, "device buffer");  // one key as doubles, packed after generation
+    DevScope tmp;
+    int *dsmall = tmp.alloc<int>(sizeof(int) * N, "key generation");
+    double *te = tmp.alloc<double>(8ull * per, "key generation");
+    double *tg = tmp.alloc<double>(8ull * per, "key generation");
+    double *tk = tmp.alloc<double>(8ull * kw, "key generation");  // one key as doubles, packed after generation
     const VecSet all_sk{C->d_sk, np, np, 0, nullptr, nullptr};
     C->keys.resize(nkeys, KeyRef{nullptr, nullptr});
     for (int k = from; k < to; ++k) {
@@ -2186,9 +2237,11 @@ void gen_keys(he_ctx *C, int from, int to) {
         }
         uint32_t *klo = nullptr;
         uint16_t *khi = nullptr;
-        dev_alloc(&klo, 4ull * kw, "device buffer");
-        dev_alloc(&khi, 2ull * kw, "device buffer");
-        C->keys[k] = KeyRef{klo, khi};
+        // each plane owned by the context as soon as it exists (freed with it on any failure)
+        dev_alloc(&klo, 4ull * kw, "evaluation key");
+        C->keys[k] = KeyRef{klo, nullptr};
+        dev_alloc(&khi, 2ull * kw, "evaluation key");
+        C->keys[k].hi = khi;
         if (k == 0) launch_square_res(T, tg, C->d_sk, np, s);
         else {
             launch_automorph(T, VecSet{tg, np, np, 0, nullptr, nullptr}, all_sk, C->key_gal[k], s);
@@ -2211,16 +2264,15 @@ void gen_keys(he_ctx *C, int from, int to) {
     }
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipGetLastError());
-    hipFree(dsmall); hipFree(te); hipFree(tg); hipFree(tk);
 }
 
 // secret key (dense ternary from one draw per coefficient, or sparse ternary placed
 // on the host) and every evaluation key of the CutMax schedule
 void keygen(he_ctx *C) {
     const int N = C->N, np = C->np;
-    int *dsmall = nullptr;
-    dev_alloc(&dsmall, sizeof(int) * N, "device buffer");
-    dev_alloc(&C->d_sk, 8ull * np * N, "device buffer");
+    DevScope tmp;
+    int *dsmall = tmp.alloc<int>(sizeof(int) * N, "secret key");
+    dev_alloc(&C->d_sk, 8ull * np * N, "secret key");
     const VecSet all_sk{C->d_sk, np, np, 0, nullptr, nullptr};
     if (C->secret_hw > 0) {
         const std::vector<int> sk = sparse_secret(N, C->secret_hw, C->seed, OBJ_SKH);
@@ -2231,7 +2283,6 @@ void keygen(he_ctx *C) {
     launch_small_to_res(C->T, all_sk, dsmall, nullptr, C->stream);
     launch_ntt(C->T, all_sk, false, 0, C->stream);
     HIPCHK(hipStreamSynchronize(C->stream));
-    hipFree(dsmall);
     plan_rotation_keys(C);
     gen_keys(C, 0);
 }
@@ -2253,11 +2304,9 @@ void autotune_ntt(he_ctx *C) {
     if (!g_tuned_logN[li]) {
         const int target[kTuneBuckets] = {4, 16, 64, 256, 1024, 4096};
         const int N = C->N, grp = C->L + 1;
-        double *buf = nullptr;
-        dev_alloc(&buf, 8ull * target[kTuneBuckets - 1] * N, "device buffer");
-        hipEvent_t a, b;
-        HIPCHK(hipEventCreate(&a));
-        HIPCHK(hipEventCreate(&b));
+        DevScope tmp;
+        double *buf = tmp.alloc<double>(8ull * target[kTuneBuckets - 1] * N, "NTT autotuner");
+        const hipEvent_t a = tmp.event(), b = tmp.event();
         for (int ci = 0; ci < kTuneBuckets; ++ci) {
             const int g = std::min(target[ci], grp), cnt = (target[ci] / g) * g;
             g_tuned_count[li][ci] = cnt;
@@ -2289,9 +2338,6 @@ void autotune_ntt(he_ctx *C) {
             g_tuned_choice[li][ci] = bestv;
         }
         for (int bk = kTuneBuckets; bk < 8; ++bk) g_tuned_choice[li][bk] = g_tuned_choice[li][kTuneBuckets - 1];
-        hipEventDestroy(a);
-        hipEventDestroy(b);
-        hipFree(buf);
         g_tuned_logN[li] = 1;
     }
     for (int bk = 0; bk < 8; ++bk) set_ntt_tuning(C->logN, bk, g_tuned_choice[li][bk]);
@@ -3105,10 +3151,9 @@ int he_bench_ntt(he_ctx *C, uint32_t vectors, uint32_t iters, double *ms_fwd, do
         REQUIRE(C && vectors >= 1 && iters >= 1 && ms_fwd && ms_inv, HE_EINVAL, "bad argument");
         HIPCHK(hipSetDevice(C->device));
         const int N = C->N;
-        double *buf = nullptr;
-        dev_alloc(&buf, 8ull * vectors * N, "device buffer");
-        hipEvent_t a, b, c;
-        HIPCHK(hipEventCreate(&a)); HIPCHK(hipEventCreate(&b)); HIPCHK(hipEventCreate(&c));
+        DevScope tmp;
+        double *buf = tmp.alloc<double>(8ull * vectors * N, "NTT measurement");
+        const hipEvent_t a = tmp.event(), b = tmp.event(), c = tmp.event();
         const int grp = std::min<int>((int)vectors, C->L + 1);
         const VecSet vs{buf, (int)vectors, grp, (long long)grp * N, nullptr, nullptr};
         launch_sample_uniform(C->T, vs, 12345, 0x7F000000u, nullptr, C->stream);
@@ -3127,8 +3172,6 @@ int he_bench_ntt(he_ctx *C, uint32_t vectors, uint32_t iters, double *ms_fwd, do
             HIPCHK(hipEventElapsedTime(&f2, b, c));
             tf += f1; ti += f2;
         }
-        hipEventDestroy(a); hipEventDestroy(b); hipEventDestroy(c);
-        hipFree(buf);
         *ms_fwd = tf / iters;
         *ms_inv = ti / iters;
         return HE_OK;
@@ -3140,11 +3183,9 @@ int he_bench_copy(he_ctx *C, uint32_t vectors, uint32_t iters, double *ms) {
         REQUIRE(C && vectors >= 1 && iters >= 1 && ms, HE_EINVAL, "bad argument");
         HIPCHK(hipSetDevice(C->device));
         const int N = C->N;
-        double *buf = nullptr;
-        dev_alloc(&buf, 16ull * vectors * N, "device buffer");
-        hipEvent_t a, b;
-        HIPCHK(hipEventCreate(&a));
-        HIPCHK(hipEventCreate(&b));
+        DevScope tmp;
+        double *buf = tmp.alloc<double>(16ull * vectors * N, "copy measurement");
+        const hipEvent_t a = tmp.event(), b = tmp.event();
         const int grp = std::min<int>((int)vectors, C->L + 1);
         const VecSet src{buf, (int)vectors, grp, (long long)grp * N, nullptr, nullptr};
         const VecSet dst{buf + (size_t)vectors * N, (int)vectors, grp, (long long)grp * N, nullptr, nullptr};
@@ -3156,9 +3197,6 @@ int he_bench_copy(he_ctx *C, uint32_t vectors, uint32_t iters, double *ms) {
         HIPCHK(hipEventSynchronize(b));
         float f = 0;
         HIPCHK(hipEventElapsedTime(&f, a, b));
-        hipEventDestroy(a);
-        hipEventDestroy(b);
-        hipFree(buf);
         *ms = f / iters;
         return HE_OK;
     });
