@@ -611,6 +611,17 @@ def main():
         ntt[f"{cts_n}ct"] = {"vectors": vec, "fwd_ms": f, "inv_ms": i, "fwd_GBps": alg / (f * 1e-3) / 1e9,
                              "inv_GBps": alg / (i * 1e-3) / 1e9}
     log(f"[bench] ntt {ntt}")
+    # the same transforms at N = 2^12 (the toy chain's ring degree, 36 limbs a polynomial)
+    tctx = he.Context(he.TOY, device=0)
+    ntt_4096 = {}
+    for cts_n in (1, 8, 40):
+        vec = cts_n * 2 * (tctx.L + 1)
+        f, i = tctx.bench_ntt(vec, 5)
+        alg = 2.0 * tctx.N * 8 * vec
+        ntt_4096[f"{cts_n}ct"] = {"vectors": vec, "fwd_ms": f, "inv_ms": i, "fwd_GBps": alg / (f * 1e-3) / 1e9,
+                                  "inv_GBps": alg / (i * 1e-3) / 1e9}
+    del tctx
+    log(f"[bench] ntt at N=2^12 {ntt_4096}")
 
     # --- plain copy of 64 limb vectors (32 MiB read + 32 MiB written per launch): the
     # achievable-bandwidth reference, and the known-size kernel that calibrates byte counters
@@ -684,6 +695,7 @@ def main():
         "learned_guess": learned,
         "vocab_151936": vocab_151936,
         "ntt": ntt,
+        "ntt_n4096": ntt_4096,
         "copy": copy,
         "ntt_tuning": ctx.ntt_tuning(),
         "ntt_tuning_report": ctx.ntt_tuning_report(),
