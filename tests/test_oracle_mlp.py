@@ -53,8 +53,24 @@ def test_single_unit_closed_form():
 
 
 def test_loss_of_exact_guess_is_zero():
-    """a network whose output is exactly 1/sqrt(u) at the samples has zero loss"""
+    """a network whose output is exactly 1/sqrt(u) at the samples has zero loss: one hidden
+    path with z = u gives y = W3 u^4 + b3, and W3 = -256/255, b3 = 511/255 make y(1/4) = 2 and
+    y(1) = 1"""
+    H = mlp_ref.H
     u = np.array([0.25, 1.0])
     th = np.zeros(mlp_ref.NPARAM)
-    th[-1] = 1.0          # y = 1: exact at u = 1, relative error 0.5 - 1 at u = 0.25
-    assert abs(mlp_ref.loss(th, u, 0.0, 1.0) - 0.5 * (0.5 - 1.0) ** 2) < 1e-15
+    th[0] = 1.0                       # W1[0]
+    th[2 * H] = 1.0                   # W2[0][0]
+    th[3 * H + H * H] = -256.0 / 255.0  # W3[0]
+    th[-1] = 511.0 / 255.0            # b3
+    np.testing.assert_allclose(mlp_ref.forward(th, u, 0.0, 1.0), [2.0, 1.0], rtol=1e-15)
+    assert mlp_ref.loss(th, u, 0.0, 1.0) < 1e-30
+
+
+def test_loss_is_the_mean_squared_relative_error():
+    """the constant network y = 1 is exact at u = 1 and off by y sqrt(u) - 1 = -1/2 at u = 1/4:
+    the loss is the mean of the squared relative errors, 1/8"""
+    u = np.array([0.25, 1.0])
+    th = np.zeros(mlp_ref.NPARAM)
+    th[-1] = 1.0
+    assert abs(mlp_ref.loss(th, u, 0.0, 1.0) - 0.125) < 1e-15
