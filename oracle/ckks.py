@@ -66,6 +66,9 @@ def lib():
         L.oc_keygen_galois.argtypes = [V, ctypes.c_int, ctypes.c_uint64]
         L.oc_rotsum_step.restype = V
         L.oc_rotsum_step.argtypes = [V, V, ctypes.c_int, ctypes.POINTER(ctypes.c_int), u64p]
+        L.oc_rotsum_carried.restype = V
+        L.oc_rotsum_carried.argtypes = [V, V, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                        ctypes.POINTER(ctypes.c_int), u64p]
         L.oc_ct_free.argtypes = [V]
         L.oc_ct_level.argtypes = [V]
         L.oc_ct_export.argtypes = [V, V, u64p]
@@ -449,15 +452,30 @@ class Oracle:
         hoist 0: x <- x + rot(x, 2^r), r = 0..log2(slots)-1, one key switch each.
         hoist h >= 1: steps of radix R = 2^h, x <- x + sum_{r=1}^{R-1} rot(x, r k) for
         k = 1, R, R^2, ... (the last step takes the remaining bits), each step one
-        hoisted ModUp, the key products of its R-1 rotations summed, one ModDown."""
+        hoisted ModUp, the key products of its R-1 rotations summed; with several steps
+        c0 is carried as P c0 over Q u P (oc_rotsum_carried): c1 takes one ModDown a step,
+        c0 one at the end."""
         if self.prm.hoist <= 0 or self.plain:
             for r in range(int(math.log2(self.slots))):
                 x = self.add(x, self.rotate(x, r))
             return x
         keys = rotation_keys(self.slots, self.prm.hoist)
-        for amounts in hoist_steps(self.slots, self.prm.hoist):
-            x = self.rotsum_step(x, amounts, keys)
-        return x
+        steps = hoist_steps(self.slots, self.prm.hoist)
+        if len(steps) == 1:
+            return self.rotsum_step(x, steps[0], keys)
+        return self.rotsum_carried(x, steps, keys)
+
+    def rotsum_carried(self, x: Ct, steps, keys: dict) -> Ct:
+        """every hoisted step of a rotate-and-sum in one call, c0 carried as P c0 over Q u P
+        between steps (oc_rotsum_carried)"""
+        flat = [a for st in steps for a in st]
+        nr = (ctypes.c_int * len(steps))(*[len(st) for st in steps])
+        kid = (ctypes.c_int * len(flat))(*[keys[a] for a in flat])
+        gal = np.array([pow(5, a, 2 * self.N) for a in flat], dtype=np.uint64)
+        h = lib().oc_rotsum_carried(self.h, x.h, len(steps), nr, kid, _p(gal, u64p))
+        if not h:
+            raise SchedError("rotate-and-sum: missing key")
+        return Ct(self, h, x.scale)
 
     def rotsum_step(self, x: Ct, amounts: Sequence[int], keys: dict) -> Ct:
         """x + sum_r rot(x, a_r) with one hoisted key switch (oc_rotsum_step)."""

@@ -563,61 +563,61 @@ oc_ct *oc_mul_int_rescale(const oc_ctx *C, const oc_ct *a, int64_t K) {
     return r;
 }
 
-/* ModDown of the NTT-domain accumulators acc0/acc1 over Q_l u P ([l+1+alpha][N],
- * gidx = global prime index of each extended limb; transformed back in place):
+/* ModDown of one NTT-domain accumulator acc over Q_l u P ([l+1+alpha][N], gidx = global
+ * prime index of each extended limb; transformed back in place):
  * out_i = (acc_i - conv_P->q_i(acc_P)) * P^-1 mod q_i, coefficient domain */
-static void moddown(const oc_ctx *C, int l, uint64_t *acc0, uint64_t *acc1, const int *gidx, uint64_t *out0,
-                    uint64_t *out1) {
+static void moddown_one(const oc_ctx *C, int l, uint64_t *acc, const int *gidx, uint64_t *out) {
     int N = C->N, nq = l + 1, A = C->alpha, next = nq + A;
     /* back to coefficients */
     #pragma omp parallel for schedule(dynamic)
-    for (int k = 0; k < 2 * next; k++) {
-        int kk = k % next; uint64_t *acc = k < next ? acc0 : acc1;
-        inv(C, gidx[kk], acc + (size_t)kk * N);
-    }
-    /* ModDown: out_i = (acc_i - conv_P->q_i(acc_P)) * P^-1 mod q_i, where the conversion
-     * lifts each [acc_m * Phat_m^-1]_{p_m} to its centred representative, so the
-     * division by P rounds with a mean-zero error */
+    for (int k = 0; k < next; k++) inv(C, gidx[k], acc + (size_t)k * N);
+    /* out_i = (acc_i - conv_P->q_i(acc_P)) * P^-1 mod q_i, where the conversion lifts each
+     * [acc_m * Phat_m^-1]_{p_m} to its centred representative, so the division by P
+     * rounds with a mean-zero error */
     uint64_t *phinv = (uint64_t *)malloc(8 * A);
     for (int m = 0; m < A; m++) {
         uint64_t pm = C->q[C->L + 1 + m], v = 1;
         for (int b = 0; b < A; b++) if (b != m) v = mulm(v, C->q[C->L + 1 + b] % pm, pm);
         phinv[m] = invm(v, pm);
     }
-    for (int c = 0; c < 2; c++) {
-        uint64_t *acc = c ? acc1 : acc0, *out = c ? out1 : out0;
-        uint64_t *w = (uint64_t *)malloc(8 * (size_t)A * N);
-        for (int m = 0; m < A; m++) {
-            uint64_t pm = C->q[C->L + 1 + m];
-            for (int i = 0; i < N; i++) w[(size_t)m * N + i] = mulm(acc[(size_t)(nq + m) * N + i], phinv[m], pm);
-        }
-        #pragma omp parallel for schedule(dynamic)
-        for (int k = 0; k < nq; k++) {
-            uint64_t q = C->q[k];
-            uint64_t *ph = (uint64_t *)malloc(8 * A);
-            uint64_t Pm = 1;
-            for (int m = 0; m < A; m++) {
-                uint64_t v = 1;
-                for (int b = 0; b < A; b++) if (b != m) v = mulm(v, C->q[C->L + 1 + b] % q, q);
-                ph[m] = v;
-                Pm = mulm(Pm, C->q[C->L + 1 + m] % q, q);
-            }
-            uint64_t Pinv = invm(Pm, q);
-            for (int i = 0; i < N; i++) {
-                uint64_t s = 0;
-                for (int m = 0; m < A; m++) {
-                    /* centred lift of w_m to (-p_m/2, p_m/2], then reduced mod q_k */
-                    uint64_t pm = C->q[C->L + 1 + m], v = w[(size_t)m * N + i];
-                    uint64_t vk = v > (pm - 1) / 2 ? subm(0, (pm - v) % q, q) : v % q;
-                    s = addm(s, mulm(vk, ph[m], q), q);
-                }
-                out[(size_t)k * N + i] = mulm(subm(acc[(size_t)k * N + i], s, q), Pinv, q);
-            }
-            free(ph);
-        }
-        free(w);
+    uint64_t *w = (uint64_t *)malloc(8 * (size_t)A * N);
+    for (int m = 0; m < A; m++) {
+        uint64_t pm = C->q[C->L + 1 + m];
+        for (int i = 0; i < N; i++) w[(size_t)m * N + i] = mulm(acc[(size_t)(nq + m) * N + i], phinv[m], pm);
     }
+    #pragma omp parallel for schedule(dynamic)
+    for (int k = 0; k < nq; k++) {
+        uint64_t q = C->q[k];
+        uint64_t *ph = (uint64_t *)malloc(8 * A);
+        uint64_t Pm = 1;
+        for (int m = 0; m < A; m++) {
+            uint64_t v = 1;
+            for (int b = 0; b < A; b++) if (b != m) v = mulm(v, C->q[C->L + 1 + b] % q, q);
+            ph[m] = v;
+            Pm = mulm(Pm, C->q[C->L + 1 + m] % q, q);
+        }
+        uint64_t Pinv = invm(Pm, q);
+        for (int i = 0; i < N; i++) {
+            uint64_t s = 0;
+            for (int m = 0; m < A; m++) {
+                /* centred lift of w_m to (-p_m/2, p_m/2], then reduced mod q_k */
+                uint64_t pm = C->q[C->L + 1 + m], v = w[(size_t)m * N + i];
+                uint64_t vk = v > (pm - 1) / 2 ? subm(0, (pm - v) % q, q) : v % q;
+                s = addm(s, mulm(vk, ph[m], q), q);
+            }
+            out[(size_t)k * N + i] = mulm(subm(acc[(size_t)k * N + i], s, q), Pinv, q);
+        }
+        free(ph);
+    }
+    free(w);
     free(phinv);
+}
+
+/* ModDown of the two accumulators of a key switch */
+static void moddown(const oc_ctx *C, int l, uint64_t *acc0, uint64_t *acc1, const int *gidx, uint64_t *out0,
+                    uint64_t *out1) {
+    moddown_one(C, l, acc0, gidx, out0);
+    moddown_one(C, l, acc1, gidx, out1);
 }
 
 /* key products of a key switch of d (level l, coefficient domain) with key kidx.
@@ -929,19 +929,18 @@ static void automorph_limb(const uint64_t *in, uint64_t *out, int N, uint64_t g,
  *   A    = sum_r sum_j sigma_r(ModUp_j(c1)) * key_{r,j}
  *   out0 = c0 + sum_r sigma_r(c0) + ModDown(A)_0,   out1 = c1 + ModDown(A)_1.
  * (Halevi-Shoup hoisting of the ModUp, and one ModDown for the whole sum.) */
-oc_ct *oc_rotsum_step(const oc_ctx *C, const oc_ct *x, int nr, const int *kidx, const uint64_t *gal) {
-    if (nr < 1) return NULL;
-    for (int r = 0; r < nr; r++)
-        if (kidx[r] < 1 || kidx[r] >= C->nkeys || !C->keys[kidx[r]]) return NULL;
-    int N = C->N, l = x->level, nq = l + 1, A = C->alpha, next = nq + A;
+/* the key products of one hoisted step: the digits of d (c1, coefficient domain, level l)
+ * are extended once and every rotation r applies sigma_r to the extended digits before
+ * multiplying by its own key; acc0/acc1 [l+1+alpha][N] (zeroed by the caller) receive
+ * sum_r sum_j sigma_r(ModUp_j(d)) key_{r,j} in the NTT domain, gidx the global prime index
+ * of each extended limb */
+static void hoisted_products(const oc_ctx *C, const uint64_t *d, int l, int nr, const int *kidx,
+                             const uint64_t *gal, uint64_t *acc0, uint64_t *acc1, int *gidx) {
+    int N = C->N, nq = l + 1, A = C->alpha, next = nq + A;
     int beta = n_digits(C, l);
     size_t per = (size_t)C->np * N;
-    const uint64_t *d = x->c[1];
-    int *gidx = (int *)malloc(sizeof(int) * next);
     for (int k = 0; k < nq; k++) gidx[k] = k;
     for (int m = 0; m < A; m++) gidx[nq + m] = C->L + 1 + m;
-    uint64_t *acc0 = (uint64_t *)calloc((size_t)next * N, 8);
-    uint64_t *acc1 = (uint64_t *)calloc((size_t)next * N, 8);
     for (int j = 0; j < beta; j++) {
         int lo = j * A, hi = lo + A; if (hi > nq) hi = nq;
         int dl = hi - lo;
@@ -989,6 +988,17 @@ oc_ct *oc_rotsum_step(const oc_ctx *C, const oc_ct *x, int nr, const int *kidx, 
         }
         free(qhinv); free(vv);
     }
+}
+
+oc_ct *oc_rotsum_step(const oc_ctx *C, const oc_ct *x, int nr, const int *kidx, const uint64_t *gal) {
+    if (nr < 1) return NULL;
+    for (int r = 0; r < nr; r++)
+        if (kidx[r] < 1 || kidx[r] >= C->nkeys || !C->keys[kidx[r]]) return NULL;
+    int N = C->N, l = x->level, nq = l + 1, A = C->alpha, next = nq + A;
+    int *gidx = (int *)malloc(sizeof(int) * next);
+    uint64_t *acc0 = (uint64_t *)calloc((size_t)next * N, 8);
+    uint64_t *acc1 = (uint64_t *)calloc((size_t)next * N, 8);
+    hoisted_products(C, x->c[1], l, nr, kidx, gal, acc0, acc1, gidx);
     oc_ct *o = ct_new(C, l);
     moddown(C, l, acc0, acc1, gidx, o->c[0], o->c[1]);
     size_t n = (size_t)nq * N;
@@ -1008,6 +1018,76 @@ oc_ct *oc_rotsum_step(const oc_ctx *C, const oc_ct *x, int nr, const int *kidx, 
             o->c[1][z] = addm(o->c[1][z], x->c[1][z], C->q[p]);
         }
     free(s0); free(acc0); free(acc1); free(gidx);
+    return o;
+}
+
+/* A hoisted rotate-and-sum of several steps (step s: rotations gal[off_s .. off_s + nr[s])
+ * with keys kidx alike) that carries c0 as X0 = P c0 over Q_l u P (coefficient domain)
+ * instead of dividing it by P after every step:
+ *   X0 = P c0 on the Q limbs, 0 on the P limbs (P c0 vanishes mod each p_m);
+ *   per step, with A0, A1 the step's key products (hoisted_products of c1):
+ *     X0 <- X0 + sum_r sigma_r(X0) + INTT(A0)      on every limb of Q_l u P
+ *     c1 <- c1 + ModDown(A1)
+ *   and at the end c0 = ModDown(X0).
+ * ModDown(X0) = (X0_Q - conv(X0_P)) P^-1 divides the exact sum P (c0 + sum of the rotated
+ * c0s) + sum of the A0s by P once, so the result is x plus every rotation of every step,
+ * as with a ModDown per step, but rounded once. */
+oc_ct *oc_rotsum_carried(const oc_ctx *C, const oc_ct *x, int nsteps, const int *nr, const int *kidx,
+                         const uint64_t *gal) {
+    if (nsteps < 1) return NULL;
+    int tot = 0;
+    for (int s_ = 0; s_ < nsteps; s_++) {
+        if (nr[s_] < 1) return NULL;
+        tot += nr[s_];
+    }
+    for (int r = 0; r < tot; r++)
+        if (kidx[r] < 1 || kidx[r] >= C->nkeys || !C->keys[kidx[r]]) return NULL;
+    int N = C->N, l = x->level, nq = l + 1, A = C->alpha, next = nq + A;
+    int *gidx = (int *)malloc(sizeof(int) * next);
+    for (int k = 0; k < nq; k++) gidx[k] = k;
+    for (int m = 0; m < A; m++) gidx[nq + m] = C->L + 1 + m;
+    size_t ne = (size_t)next * N;
+    uint64_t *X0 = (uint64_t *)calloc(ne, 8), *S = (uint64_t *)malloc(8 * ne), *t = (uint64_t *)malloc(8 * N);
+    uint64_t *c1 = (uint64_t *)malloc(8 * (size_t)nq * N);
+    memcpy(c1, x->c[1], 8 * (size_t)nq * N);
+    for (int k = 0; k < nq; k++) {
+        uint64_t q = C->q[k], Pm = 1;
+        for (int m = 0; m < A; m++) Pm = mulm(Pm, C->q[C->L + 1 + m] % q, q);
+        for (int i = 0; i < N; i++) X0[(size_t)k * N + i] = mulm(x->c[0][(size_t)k * N + i], Pm, q);
+    }
+    uint64_t *acc0 = (uint64_t *)malloc(8 * ne), *acc1 = (uint64_t *)malloc(8 * ne);
+    oc_ct *o = ct_new(C, l);
+    int off = 0;
+    for (int s_ = 0; s_ < nsteps; s_++) {
+        memset(acc0, 0, 8 * ne);
+        memset(acc1, 0, 8 * ne);
+        hoisted_products(C, c1, l, nr[s_], kidx + off, gal + off, acc0, acc1, gidx);
+        /* X0 + sum_r sigma_r(X0) + INTT(A0) on every extended limb */
+        memcpy(S, X0, 8 * ne);
+        for (int k = 0; k < next; k++) {
+            uint64_t pk = C->q[gidx[k]];
+            for (int r = 0; r < nr[s_]; r++) {
+                automorph_limb(X0 + (size_t)k * N, t, N, gal[off + r], pk);
+                for (int i = 0; i < N; i++) S[(size_t)k * N + i] = addm(S[(size_t)k * N + i], t[i], pk);
+            }
+            inv(C, gidx[k], acc0 + (size_t)k * N);
+            for (int i = 0; i < N; i++)
+                X0[(size_t)k * N + i] = addm(S[(size_t)k * N + i], acc0[(size_t)k * N + i], pk);
+        }
+        /* c1 + ModDown(A1) */
+        moddown_one(C, l, acc1, gidx, o->c[1]);
+        for (int p = 0; p < nq; p++)
+            for (int i = 0; i < N; i++) {
+                size_t z = (size_t)p * N + i;
+                c1[z] = addm(o->c[1][z], c1[z], C->q[p]);
+            }
+        off += nr[s_];
+    }
+    /* c0 = ModDown(X0): to the NTT domain first (moddown_one takes NTT-domain limbs) */
+    for (int k = 0; k < next; k++) fwd(C, gidx[k], X0 + (size_t)k * N);
+    moddown_one(C, l, X0, gidx, o->c[0]);
+    memcpy(o->c[1], c1, 8 * (size_t)nq * N);
+    free(X0); free(S); free(t); free(c1); free(acc0); free(acc1); free(gidx);
     return o;
 }
 

@@ -437,15 +437,19 @@ struct Exec {
     }
 
     // ext_pre: the extended digits of d already computed (modup), d unused
+    // acc_out (optional): the key-product accumulators [cnt][2][next] go there (and stay
+    // after the call) instead of to workspace; md_poly1: the ModDown and the output cover
+    // polynomial 1 only (polynomial 0's accumulator is left in acc_out)
     void keyswitch(const double *d, long long dstride, int cnt, int l, int kidx, double *out, long long ostride,
                    Addend a1 = Addend{nullptr, 0, 0, 0}, Addend a2 = Addend{nullptr, 0, 0, 0},
-                   const RotSet *rot = nullptr, bool mrescale = false, const double *ext_pre = nullptr) {
+                   const RotSet *rot = nullptr, bool mrescale = false, const double *ext_pre = nullptr,
+                   double *acc_out = nullptr, bool md_poly1 = false) {
         const int A = C->alpha, next = l + 1 + A, beta = (l + 1 + A - 1) / A;
         const long long N = C->N;
         const size_t m = C->arena.mark();
         double *dcoef = ext_pre ? nullptr : alloc_d((size_t)cnt * (l + 1) * N);
         double *ext = ext_pre ? const_cast<double *>(ext_pre) : alloc_d((size_t)cnt * beta * next * N);
-        double *acc = alloc_d((size_t)cnt * 2 * next * N);
+        double *acc = acc_out ? acc_out : alloc_d((size_t)cnt * 2 * next * N);
         double *conv = alloc_d((size_t)cnt * 2 * (l + 1) * N);
         if (go() && !ext_pre) {
             // coefficient-domain digits, already scaled by Qhat_i^-1 (folded into N^-1)
@@ -498,6 +502,29 @@ struct Exec {
                 epi.cst2 = C->qlinv + (long long)l * (C->L + 1);
                 launch_ntt_fused(T, VecSet{conv, cnt * 2 * l, l, (long long)l * N, nullptr, nullptr}, NttPro{}, epi,
                                  C->ntt_variant, s);
+                C->arena.release(m);
+                return;
+            }
+            if (md_poly1) {
+                // polynomial 1 alone: groups are ciphertexts (stride 2 next N in acc, 2
+                // ostride in out)
+                double *acc1 = acc + (long long)next * N;
+                launch_ntt(T, VecSet{acc1 + (long long)(l + 1) * N, cnt * A, A, 2LL * next * N, nullptr, C->pprime},
+                           true, C->ntt_variant, s, nullptr, C->md_scale);
+                launch_moddown_conv(T, acc1, 2LL * next * N, conv, (long long)(l + 1) * N, cnt,
+                                    MdIn{l + 1, A, C->pprime, C->phat, C->L + 1, l + 1}, s);
+                NttEpi epi{};
+                epi.kind = 1;
+                epi.poly1 = 1;
+                epi.out = out + ostride;
+                epi.o_g = 2 * ostride;
+                epi.in = acc1;
+                epi.i_g = 2LL * next * N;
+                epi.add1 = a1.p; epi.a1_ct = a1.ct; epi.a1_poly = a1.poly; epi.m1 = a1.mask;
+                epi.add2 = a2.p; epi.a2_ct = a2.ct; epi.a2_poly = a2.poly; epi.m2 = a2.mask;
+                epi.cst = C->Pinv;
+                launch_ntt_fused(T, VecSet{conv, cnt * (l + 1), l + 1, (long long)(l + 1) * N, nullptr, nullptr},
+                                 NttPro{}, epi, C->ntt_variant, s);
                 C->arena.release(m);
                 return;
             }
@@ -762,15 +789,26 @@ struct Exec {
     // a time, or hoisted steps x <- x + sum_r rot(x, a_r)
     Bt rotsum(const Bt &a) {
         if (C->hoist >= 1) {
-            // the first step reads a and writes o, the others update o in place
+            const auto steps = hoist_steps(C->slots, C->hoist);
             Bt o = new_bt(a.cnt, a.level);
             o.scale = a.scale;
-            bool first = true;
-            for (const auto &st : hoist_steps(C->slots, C->hoist)) {
+            if (steps.size() == 1) {
                 const size_t m = C->arena.mark();
-                rotsum_step(first ? a : o, o, st);
+                rotsum_step(a, o, steps[0]);
                 C->arena.release(m);
-                first = false;
+                return o;
+            }
+            // c0 is carried as P c0 over Q_l u P from step to step (in the key products'
+            // accumulator of polynomial 0, two buffers used in turn), so only c1 takes a
+            // ModDown per step and c0 one at the end; the first step reads a, the others
+            // update o's c1 in place
+            const int next = a.level + 1 + C->alpha;
+            double *accb[2] = {alloc_d((size_t)a.cnt * 2 * next * C->N), alloc_d((size_t)a.cnt * 2 * next * C->N)};
+            for (size_t k = 0; k < steps.size(); ++k) {
+                const size_t m = C->arena.mark();
+                rotsum_step_carried(k == 0 ? a : o, o, steps[k], k == 0 ? nullptr : accb[(k - 1) & 1], accb[k & 1],
+                                    k + 1 == steps.size());
+                C->arena.release(m);
             }
             return o;
         }
@@ -812,6 +850,42 @@ struct Exec {
         keyswitch(x.d + (long long)x.cap * N, 2LL * x.cap * N, x.cnt, l, -1, y.d, (long long)y.cap * N,
                   Addend{s0, (long long)(l + 1) * N, 0, 1}, Addend{x.d, 2LL * x.cap * N, (long long)x.cap * N, 2},
                   &rs);
+    }
+
+    // one hoisted step with c0 carried as X0 = P c0 over Q_l u P: the key products fold
+    // X0 + sum_r sigma_r(X0) into polynomial 0's accumulator (the first step forms it from
+    // x's c0 over Q_l times [P]_{q_i}; P c0 vanishes on the P limbs), so acc0 becomes the
+    // next X0; c1 takes its ModDown:  y1 = c1 + MD_1.  The last step takes the ModDown of
+    // both polynomials, y0 = MD(X0) = c0 + sum of every step's rotations.
+    void rotsum_step_carried(const Bt &x, const Bt &y, const std::vector<int> &amounts, const double *x0,
+                             double *acc, bool last) {
+        const int l = x.level, next = l + 1 + C->alpha;
+        const long long N = C->N;
+        REQUIRE(!amounts.empty() && (int)amounts.size() <= kMaxHoist, HE_EINVAL, "hoisted step size");
+        RotSet rs{};
+        rs.nr = (int)amounts.size();
+        rs.xorder = C->xorder.at(amounts[0]);
+        for (int r = 0; r < rs.nr; ++r) {
+            auto it = C->rot_key.find(amounts[r]);
+            REQUIRE(it != C->rot_key.end(), HE_ESTATE, "no key for a hoisted rotation");
+            rs.key[r] = C->keys[it->second];
+            rs.g[r] = C->key_gal[it->second];
+        }
+        rs.c0_id = 1;
+        rs.fold = 1;
+        if (x0) {
+            rs.c0 = x0;
+            rs.c0_ct = 2LL * next * N;
+            rs.lq = next - 1;
+        } else {
+            rs.c0 = x.d;
+            rs.c0_ct = 2LL * x.cap * N;
+            rs.lq = l;
+            rs.c0_mul = C->pmod;
+        }
+        keyswitch(x.d + (long long)x.cap * N, 2LL * x.cap * N, x.cnt, l, -1, y.d, (long long)y.cap * N,
+                  Addend{nullptr, 0, 0, 0}, Addend{x.d, 2LL * x.cap * N, (long long)x.cap * N, 2}, &rs, false,
+                  nullptr, acc, !last);
     }
 
     Bt power(const Bt &y, int p) {

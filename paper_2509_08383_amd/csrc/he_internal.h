@@ -111,6 +111,9 @@ struct NttEpi {
     const double *kmul;
     int kstride;
     const double *cst2;
+    // 0: vector groups alternate the two polynomials (group g = 2 ct + poly); 1: every
+    // group is polynomial 1 of ciphertext g (the addends are indexed accordingly)
+    int poly1;
 };
 void launch_ntt_fused(const DevTables &T, const VecSet &vs, const NttPro &pro, const NttEpi &epi, int variant,
                       hipStream_t s);
@@ -191,6 +194,11 @@ struct RotSet {
     int lq;
     const int *xorder;  // the N/256 x-blocks in the orbit order of g[0] (device)
     int c0_id;          // 1: s0 includes c0 itself (rotate-and-sum), 0: only the rotated copies
+    // fold != 0: instead of writing s0, acc0 <- acc0 + s0 on every limb t <= lq (limbs
+    // above lq take acc0 alone); c0_mul (per extended limb, may be null) multiplies the
+    // sum first (rotate-and-sum carrying P c0 over Q u P between its hoisted steps)
+    int fold;
+    const double *c0_mul;
     // multi != 0: rotation r acts on its own ciphertext: extended digits ext_r[r] (same
     // strides as ext) and c0 at c0_r[r] (stride c0_ct); s0 = sum_r sigma_r(c0_r)
     int multi;

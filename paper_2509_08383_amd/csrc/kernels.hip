@@ -575,6 +575,21 @@ void launch_inner_product(const DevTables &T, const double *ext, long long estri
 // ciphertext is issued before the first product waits on one (the loads of a wave are
 // then in flight together instead of one rotation at a time).  BETA = 0 or NR = 0 read
 // the runtime counts (at most 8 digits).
+// c0 + sum_r sigma_r(c0) (g0, below 2^52) on the limbs that have it: written to s0, or
+// with rs.fold added to the key-product sum s0 (below 2^51.6), times rs.c0_mul[t] when
+// given; returns the new key-product sum (canonical when folded)
+DEV double c0_sum(const RotSet &rs, bool wsum, double g0, double s0, int ct, int t, int x, int N, double p,
+                  double pinv) {
+    if (!wsum) return s0;
+    double gc = canon(g0, p, pinv);
+    if (!rs.fold) {
+        rs.s0[ct * rs.s0_ct + (long long)t * N + x] = gc;
+        return s0;
+    }
+    if (rs.c0_mul) gc = canon(mm(gc, rs.c0_mul[t], p, pinv), p, pinv);
+    const double o = canon(s0, p, pinv) + gc;
+    return o >= p ? o - p : o;
+}
 // (with three digits 3 waves per SIMD: at 4 the unrolled form spills to scratch)
 template <int BETA, int NR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BETA >= 3 ? 3 : 4))) void k_inner_product_rot(
@@ -637,7 +652,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BETA >= 3 ?
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
-            if (wsum) rs.s0[ct * rs.s0_ct + (long long)t * T.N + x] = canon(g0, p, pinv);
+            s0 = c0_sum(rs, wsum, g0, s0, ct, t, x, T.N, p, pinv);
         } else {
             double g0 = wsum && rs.c0_id ? C0[x] : 0.0;
             for (int r = 0; r < nr; ++r) {
@@ -659,7 +674,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BETA >= 3 ?
                     s1 = red(s1, p, pinv);
                 }
             }
-            if (wsum) rs.s0[ct * rs.s0_ct + (long long)t * T.N + x] = canon(g0, p, pinv);
+            s0 = c0_sum(rs, wsum, g0, s0, ct, t, x, T.N, p, pinv);
         }
         acc0[ct * astride + (long long)t * T.N + x] = canon(s0, p, pinv);
         acc1[ct * astride + (long long)t * T.N + x] = canon(s1, p, pinv);
@@ -671,7 +686,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BETA >= 3 ?
 // and the NR + 1 gathers of c0 are issued together (no branch between them), then the
 // products run.
 template <int NR, int BETA>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_inner_product_rot_reg(DevTables T, const double *__restrict__ ext,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BETA >= 3 && NR >= 7 ? 2 : 3))) void k_inner_product_rot_reg(DevTables T, const double *__restrict__ ext,
                                                                long long esb, long long esj,
                                                                double *__restrict__ acc0, double *__restrict__ acc1,
                                                                long long astride, RotSet rs, int betaL,
@@ -694,9 +709,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         for (int j = 0; j < BETA; ++j) key_pair(rs.key[r], betaL, pt, j, T.N, x, k0[r][j], k1[r][j]);
     }
     const bool wsum = rs.c0 && t <= rs.lq;
-    // rotations whose gathers are in flight together (with 7 x 3 keys held, a third
-    // rotation's gathers would spill to scratch at 3 waves per SIMD)
-    constexpr int RCW = BETA >= 3 ? 2 : 3;
+    // rotations whose gathers are in flight together: 7 x 3 keys held and the running sum
+    // kept for the c0 fold take 2 waves per SIMD, which leaves room for all 7 at once
+    constexpr int RCW = BETA >= 3 && NR >= 7 ? 7 : 3;
     constexpr int RC = NR > RCW ? RCW : NR;
     for (int ct = 0; ct < cnt; ++ct) {
         const double *E = ext + ct * esb + (long long)t * T.N;
@@ -727,15 +742,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             // keep the next chunk's gathers behind this chunk's products (register budget)
             __builtin_amdgcn_sched_barrier(0);
         }
-        acc0[ct * astride + (long long)t * T.N + x] = canon(s0, p, pinv);
         acc1[ct * astride + (long long)t * T.N + x] = canon(s1, p, pinv);
         if (wsum) {
             const double *C0 = rs.c0 + ct * rs.c0_ct + (long long)t * T.N;
             double g0 = rs.c0_id ? C0[x] : 0.0;
 #pragma unroll
             for (int r = 0; r < NR; ++r) g0 += C0[src[r]];
-            rs.s0[ct * rs.s0_ct + (long long)t * T.N + x] = canon(g0, p, pinv);
+            s0 = c0_sum(rs, true, g0, s0, ct, t, x, T.N, p, pinv);
         }
+        acc0[ct * astride + (long long)t * T.N + x] = canon(s0, p, pinv);
         __builtin_amdgcn_sched_barrier(0);
     }
 }

@@ -148,10 +148,11 @@ __global__ __launch_bounds__(COLS *(1 << H)) void k_ntt(VecSet vs, VecSet src, c
         if (EPI) {
             rN = (long long)r_ * NN;
             const double *in = epi.in + (long long)g_ * epi.i_g + rN;
-            const bool use1 = epi.add1 && ((epi.m1 >> (g_ & 1)) & 1);
-            const bool use2 = epi.add2 && ((epi.m2 >> (g_ & 1)) & 1);
-            const double *ad1 = use1 ? epi.add1 + (long long)(g_ >> 1) * epi.a1_ct + (g_ & 1) * epi.a1_poly + rN : nullptr;
-            const double *ad2 = use2 ? epi.add2 + (long long)(g_ >> 1) * epi.a2_ct + (g_ & 1) * epi.a2_poly + rN : nullptr;
+            const int ect = epi.poly1 ? g_ : g_ >> 1, epl = epi.poly1 ? 1 : g_ & 1;
+            const bool use1 = epi.add1 && ((epi.m1 >> epl) & 1);
+            const bool use2 = epi.add2 && ((epi.m2 >> epl) & 1);
+            const double *ad1 = use1 ? epi.add1 + (long long)ect * epi.a1_ct + epl * epi.a1_poly + rN : nullptr;
+            const double *ad2 = use2 ? epi.add2 + (long long)ect * epi.a2_ct + epl * epi.a2_poly + rN : nullptr;
 #pragma unroll
             for (int i = 0; i < EW; ++i) {
                 const int idx = tid + NT * i, k = idx % SUB, cc = idx / SUB;

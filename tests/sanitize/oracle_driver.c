@@ -43,6 +43,7 @@ oc_ct *oc_rotate_gal(const oc_ctx *, const oc_ct *, int, uint64_t);
 oc_ct *oc_mul_plain(const oc_ctx *, const oc_ct *, const int64_t *);
 oc_ct *oc_modraise(const oc_ctx *, const oc_ct *, int);
 oc_ct *oc_rotsum_step(const oc_ctx *, const oc_ct *, int, const int *, const uint64_t *);
+oc_ct *oc_rotsum_carried(const oc_ctx *, const oc_ct *, int, const int *, const int *, const uint64_t *);
 oc_ct *oc_automorph(const oc_ctx *, const oc_ct *, uint64_t);
 int oc_num_threads(void);
 void oc_set_num_threads(int);
@@ -108,7 +109,7 @@ int main(void) {
     CHECK(memcmp(buf, buf2, 8 * 2 * (size_t)(L + 1) * N) == 0, "export/import");
 
     /* every operation once, results freed */
-    oc_ct *r[24];
+    oc_ct *r[32];
     int k = 0;
     r[k++] = oc_add(C, x, y);
     r[k++] = oc_sub(C, x, y);
@@ -129,6 +130,9 @@ int main(void) {
         int kid[3] = {1, 2, 20};
         uint64_t gal[3] = {5, 25 % (2 * (uint64_t)N), powmod(5, 3, 2 * (uint64_t)N)};
         r[k++] = oc_rotsum_step(C, x, 3, kid, gal);
+        const int nr2[2] = {2, 1};
+        r[k++] = oc_rotsum_carried(C, x, 2, nr2, kid, gal);
+        r[k++] = oc_rotsum_carried(C, r[4], 2, nr2, kid, gal);   /* at a lower level */
     }
     oc_ct *low = oc_drop(C, x, 0);
     r[k++] = oc_modraise(C, low, L);

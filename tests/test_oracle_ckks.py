@@ -204,6 +204,32 @@ def test_hoisted_rotsum_gives_the_slot_sum(h):
     np.testing.assert_allclose(O.decrypt(O.rotsum_step(d, amounts, keys)), want, atol=1e-4)
 
 
+@pytest.mark.parametrize("h", [2, 3])
+def test_carried_rotsum_equals_the_step_by_step_form(h):
+    """c0 carried as P c0 over Q u P between hoisted steps, one ModDown at the end: the same
+    rotations as a ModDown per step (the sum of x over every rotation of every step), so
+    both decrypt to the slot sum; they differ only by the ModDowns' rounding, on the order
+    of the encryption noise (2^-30 scale on the toy chain), also at a level whose last
+    digit is partial.  A carried c0 missing its factor P (or a step's rotated copies)
+    would be off by the whole slot sum."""
+    O = ckks.Oracle(dataclasses.replace(TOY, hoist=h))
+    O.keygen_cutmax()
+    x = np.random.default_rng(70 + h).uniform(-1, 1, O.slots)
+    keys = ckks.rotation_keys(O.slots, h)
+    steps = ckks.hoist_steps(O.slots, h)
+    assert len(steps) >= 2
+    for lv in (O.L, 4):
+        cx = O.drop(O.encrypt(x), lv)
+        stepwise = cx
+        for amounts in steps:
+            stepwise = O.rotsum_step(stepwise, amounts, keys)
+        carried = O.rotsum_carried(cx, steps, keys)
+        assert carried.level == lv
+        dc, ds = O.decrypt(carried), O.decrypt(stepwise)
+        np.testing.assert_allclose(dc, x.sum(), atol=1e-3)
+        assert np.abs(dc - ds).max() < 1e-5
+
+
 def test_tampered_limb_is_detected(toy):
     x = np.random.default_rng(5).uniform(-1, 1, toy.slots)
     ct = toy.encrypt(x)
