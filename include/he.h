@@ -305,7 +305,7 @@ int he_drop(he_ctx *ctx, const he_ct *a, uint32_t level, he_ct **out);
  * allocates nothing: its whole workspace is a static device array of 256 MiB
  * that the library holds on every device it runs on until the process ends
  * (its address is taken once per device by he_ctx_create).  One ciphertext at
- * N = 2^16 needs at most 190 MiB at any level; a call that needs more returns
+ * N = 2^16 needs at most about 215 MiB at any level; a call that needs more returns
  * HE_ENOMEM before any kernel runs.  Every call on one device shares that
  * device's array: calls that overlap on one device (two threads, or two
  * contexts on different streams) race, so serialise them.  The call returns

@@ -1948,9 +1948,10 @@ void ensure_workspace(he_ctx *C) {
 }
 
 // Static scratch of the entry point that allocates nothing (he_rotsum_noalloc): the
-// whole workspace of one call (running sum, c0 gather, extended digits, key-product
-// accumulators, ModDown conversion) and its constants.  One ciphertext's rotate-and-sum
-// at N = 2^16 needs at most 190 MiB (top level of 30 primes with 10 special primes).
+// whole workspace of one call (running sum, extended digits, the two key-product
+// accumulators that carry c0 between steps, ModDown conversion) and its constants.  One
+// ciphertext's rotate-and-sum at N = 2^16 needs about 215 MiB at the top level (30
+// primes with 10 special primes).
 // Each device holds its own copy, at the address hipGetSymbolAddress gives with that
 // device current; host code uses only that address, never the array's name.
 constexpr size_t kScratchBytes = 256ull << 20;
