@@ -1047,7 +1047,7 @@ oc_ct *oc_rotsum_carried(const oc_ctx *C, const oc_ct *x, int nsteps, const int 
     for (int k = 0; k < nq; k++) gidx[k] = k;
     for (int m = 0; m < A; m++) gidx[nq + m] = C->L + 1 + m;
     size_t ne = (size_t)next * N;
-    uint64_t *X0 = (uint64_t *)calloc(ne, 8), *S = (uint64_t *)malloc(8 * ne), *t = (uint64_t *)malloc(8 * N);
+    uint64_t *X0 = (uint64_t *)calloc(ne, 8), *S = (uint64_t *)malloc(8 * ne);
     uint64_t *c1 = (uint64_t *)malloc(8 * (size_t)nq * N);
     memcpy(c1, x->c[1], 8 * (size_t)nq * N);
     for (int k = 0; k < nq; k++) {
@@ -1062,20 +1062,24 @@ oc_ct *oc_rotsum_carried(const oc_ctx *C, const oc_ct *x, int nsteps, const int 
         memset(acc0, 0, 8 * ne);
         memset(acc1, 0, 8 * ne);
         hoisted_products(C, c1, l, nr[s_], kidx + off, gal + off, acc0, acc1, gidx);
-        /* X0 + sum_r sigma_r(X0) + INTT(A0) on every extended limb */
+        /* X0 + sum_r sigma_r(X0) + INTT(A0) on every extended limb (limbs independent) */
         memcpy(S, X0, 8 * ne);
+        #pragma omp parallel for schedule(dynamic)
         for (int k = 0; k < next; k++) {
             uint64_t pk = C->q[gidx[k]];
+            uint64_t *tk = (uint64_t *)malloc(8 * N);
             for (int r = 0; r < nr[s_]; r++) {
-                automorph_limb(X0 + (size_t)k * N, t, N, gal[off + r], pk);
-                for (int i = 0; i < N; i++) S[(size_t)k * N + i] = addm(S[(size_t)k * N + i], t[i], pk);
+                automorph_limb(X0 + (size_t)k * N, tk, N, gal[off + r], pk);
+                for (int i = 0; i < N; i++) S[(size_t)k * N + i] = addm(S[(size_t)k * N + i], tk[i], pk);
             }
             inv(C, gidx[k], acc0 + (size_t)k * N);
             for (int i = 0; i < N; i++)
                 X0[(size_t)k * N + i] = addm(S[(size_t)k * N + i], acc0[(size_t)k * N + i], pk);
+            free(tk);
         }
         /* c1 + ModDown(A1) */
         moddown_one(C, l, acc1, gidx, o->c[1]);
+        #pragma omp parallel for schedule(static)
         for (int p = 0; p < nq; p++)
             for (int i = 0; i < N; i++) {
                 size_t z = (size_t)p * N + i;
@@ -1084,10 +1088,11 @@ oc_ct *oc_rotsum_carried(const oc_ctx *C, const oc_ct *x, int nsteps, const int 
         off += nr[s_];
     }
     /* c0 = ModDown(X0): to the NTT domain first (moddown_one takes NTT-domain limbs) */
+    #pragma omp parallel for schedule(dynamic)
     for (int k = 0; k < next; k++) fwd(C, gidx[k], X0 + (size_t)k * N);
     moddown_one(C, l, X0, gidx, o->c[0]);
     memcpy(o->c[1], c1, 8 * (size_t)nq * N);
-    free(X0); free(S); free(t); free(c1); free(acc0); free(acc1); free(gidx);
+    free(X0); free(S); free(c1); free(acc0); free(acc1); free(gidx);
     return o;
 }
 
