@@ -755,6 +755,92 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BETA >= 3 &
     }
 }
 
+// The same products for a step whose automorphisms keep every aligned 256-word block
+// within at most NS = 2 blocks: the block an automorphism sends block X to depends only
+// on its Galois element mod N/128, so when those residues take at most one value h
+// besides 1, the sources of block X are X itself and (NS = 2) one block Y.  Each
+// ciphertext's source blocks of the BETA digits and of c0 are staged in LDS with one
+// coalesced word per thread and block, and the gathers read LDS: NS (BETA + 1) words per
+// position pass through the vector memory path instead of NR (BETA + 1) + 1.  smask bit
+// r marks the rotations whose residue is h (sources in Y = the image of X under gh).
+// The next ciphertext's words are loaded while the current one's products run (two LDS
+// buffers, one barrier per ciphertext).  Every key word of the step stays in registers.
+template <int NR, int BETA, int NS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_inner_product_rot_lds(
+    DevTables T, const double *__restrict__ ext, long long esb, long long esj, double *__restrict__ acc0,
+    double *__restrict__ acc1, long long astride, RotSet rs, int betaL, int cnt, int next,
+    const int *__restrict__ ext_prime, int xblocks, uint32_t gh, uint32_t smask) {
+    constexpr int RK = 21 / BETA;  // rotations between reductions
+    constexpr int NQ = BETA + 1;   // the digits, then c0
+    __shared__ double sw[2][NS][NQ][256];
+    const int b = blockIdx.x, slot = b >> 3;
+    const int t = (b & 7) + 8 * (slot / xblocks);
+    if (t >= next) return;  // uniform over the workgroup
+    const int xb = rs.xorder[slot % xblocks], tid = threadIdx.x;
+    const int x = xb * 256 + tid;  // N is a multiple of 256: every thread has a position
+    const int pt = ext_prime[t];
+    const double p = T.p[pt], pinv = T.pinv[pt];
+    const bool wsum = rs.c0 && t <= rs.lq;
+    // word offset of each staged block: X, then Y
+    long long sbo[NS];
+    sbo[0] = (long long)xb * 256;
+    if (NS == 2) sbo[NS - 1] = (long long)(aut_src((unsigned)xb * 256u, gh, T.logN) >> 8) * 256;
+    double k0[NR][BETA], k1[NR][BETA];
+    int so[NR];  // LDS word of rotation r's source: block slot * 256 + offset in the block
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const unsigned src = aut_src((unsigned)x, rs.g[r], T.logN);
+        so[r] = (NS == 2 && ((smask >> r) & 1) ? 256 : 0) + (int)(src & 255u);
+#pragma unroll
+        for (int j = 0; j < BETA; ++j) key_pair(rs.key[r], betaL, pt, j, T.N, x, k0[r][j], k1[r][j]);
+    }
+    double w[NS][NQ];
+    auto fetch = [&](int ct) {
+        const double *E = ext + ct * esb + (long long)t * T.N + tid;
+        const double *C0 = wsum ? rs.c0 + ct * rs.c0_ct + (long long)t * T.N + tid : nullptr;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+#pragma unroll
+            for (int j = 0; j < BETA; ++j) w[s][j] = E[j * esj + sbo[s]];
+            w[s][BETA] = wsum ? C0[sbo[s]] : 0.0;
+        }
+    };
+    fetch(0);
+    for (int ct = 0; ct < cnt; ++ct) {
+        const int buf = ct & 1;
+        double *L = &sw[buf][0][0][0];
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) L[(s * NQ + q) * 256 + tid] = w[s][q];
+        __syncthreads();
+        if (ct + 1 < cnt) fetch(ct + 1);
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int o = so[r] + (so[r] >> 8) * (NQ - 1) * 256;  // slot s -> (s NQ + j) 256
+#pragma unroll
+            for (int j = 0; j < BETA; ++j) {
+                const double e = L[o + j * 256];
+                s0 += mm(e, k0[r][j], p, pinv);
+                s1 += mm(e, k1[r][j], p, pinv);
+            }
+            if ((r + 1) % RK == 0) {
+                s0 = red(s0, p, pinv);
+                s1 = red(s1, p, pinv);
+            }
+        }
+        acc1[ct * astride + (long long)t * T.N + x] = canon(s1, p, pinv);
+        if (wsum) {
+            double g0 = rs.c0_id ? L[BETA * 256 + tid] : 0.0;
+#pragma unroll
+            for (int r = 0; r < NR; ++r) g0 += L[so[r] + (so[r] >> 8) * (NQ - 1) * 256 + BETA * 256];
+            s0 = c0_sum(rs, true, g0, s0, ct, t, x, T.N, p, pinv);
+        }
+        acc0[ct * astride + (long long)t * T.N + x] = canon(s0, p, pinv);
+    }
+}
+
 // The key products of rotations of different ciphertexts summed in one pass (the giant
 // steps of a bootstrap linear transform, whose rotated parts share one ModDown): rotation
 // r gathers its own extended digits rs.ext_r[r] and c0 rs.c0_r[r]; otherwise as
@@ -826,6 +912,34 @@ void launch_inner_product_rot(const DevTables &T, const double *ext, long long e
     kprof_set_bytes(T.N * next * (6.0 * 2.0 * beta * rs.nr + 8.0 * cnt * (beta + 2.0)));
     const int xblocks = (T.N + 255) / 256;
     const dim3 g1(8 * ((next + 7) / 8) * xblocks);
+    // a step whose Galois elements take at most one residue h != 1 mod N/128 reads its
+    // sources from at most two blocks per output block (staged in LDS)
+    if (T.logN >= 9 && beta <= 3 && (rs.nr == 7 || rs.nr == 3)) {
+        const uint32_t rm = (uint32_t)(T.N / 128);
+        uint32_t h = 0, gh = 1, smask = 0;
+        bool two = true;
+        for (int r = 0; r < rs.nr && two; ++r) {
+            const uint32_t res = rs.g[r] % rm;
+            if (res == 1u) continue;
+            if (h == 0u) {
+                h = res;
+                gh = rs.g[r];
+            }
+            if (res != h) two = false;
+            smask |= 1u << r;
+        }
+        if (two) {
+#define IPL(R, B, S)                                                                                             \
+    if (rs.nr == R && beta == B && (h ? 2 : 1) == S) {                                                           \
+        KL("k_inner_product_rot", (k_inner_product_rot_lds<R, B, S>), g1, dim3(256), 0, s, T, ext, estride_b,     \
+           estride_j, acc0, acc1, astride, rs, betaL, cnt, next, ext_prime, xblocks, gh, smask);                  \
+        return;                                                                                                  \
+    }
+            IPL(7, 3, 1) IPL(7, 3, 2) IPL(7, 2, 1) IPL(7, 2, 2) IPL(7, 1, 1) IPL(7, 1, 2)
+            IPL(3, 3, 1) IPL(3, 3, 2) IPL(3, 2, 1) IPL(3, 2, 2) IPL(3, 1, 1) IPL(3, 1, 2)
+#undef IPL
+        }
+    }
     // a batch holds the step's key words in registers; one ciphertext is bound by the key
     // stream alone, and the lighter kernel keeps more loads in flight
     const bool reg = cnt >= 2 && beta <= 3 && (rs.nr == 7 || rs.nr == 3 || rs.nr == 1);

@@ -57,8 +57,8 @@ def kernel_class(name: str) -> str:
     base = re.sub(r"\(.*", "", name)
     base = re.sub(r"^void ", "", base)
     base = re.sub(r"<.*", "", base.split("::")[-1])
-    # the batched rotation key products (keys held in registers) book under the same name
-    return "k_inner_product_rot" if base == "k_inner_product_rot_reg" else base
+    # the batched and LDS-staged rotation key products book under the same name
+    return "k_inner_product_rot" if base in ("k_inner_product_rot_reg", "k_inner_product_rot_lds") else base
 
 
 def _trace(d: str):
