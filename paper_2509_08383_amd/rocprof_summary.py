@@ -8,6 +8,8 @@ Inputs are rocprofv3 output directories written with ``--output-format csv`` (th
 * ``--fetch DIR`` / ``--write DIR``: ``--pmc FETCH_SIZE`` and ``--pmc WRITE_SIZE`` runs;
 * ``--valu DIR``: a run with SQ_INSTS_VALU, SQ_INSTS_VALU_{FMA,MUL,ADD}_F64, GRBM_GUI_ACTIVE;
 * ``--lds DIR``: a run with SQ_INSTS_LDS, SQ_LDS_BANK_CONFLICT, SQ_LDS_IDX_ACTIVE;
+* ``--tex DIR``: a run with TA_TA_BUSY and TD_TD_BUSY (the texture address and data
+  units of the vector memory path, one of each per CU);
 * ``--bench-json FILE``: bench.py's JSON line with the event profiler's algorithmic
   bytes per kernel and the digest of the library sources that ran.
 
@@ -20,7 +22,9 @@ Byte counters are calibrated with the bench's plain copy of 64 limb vectors (the
 k_copy dispatches with grid 65536 x 64, 32 MiB read and 32 MiB written each): the
 scale of each counter is known bytes / counter value.  VALU utilisation is
 SQ_INSTS_VALU / (256 CUs x kernel cycles at 2.4 GHz): every CU retires at most one
-wave64 VALU instruction per cycle (4 SIMDs, 4 cycles each), FP64 included.
+wave64 VALU instruction per cycle (4 SIMDs, 4 cycles each), FP64 included.  The busy
+fractions of the texture units are their busy-cycle counts summed over the 256 CUs,
+divided by 256 x kernel cycles.
 """
 from __future__ import annotations
 
@@ -92,8 +96,8 @@ def copy_dispatches(rows):
             and r.get("Grid_Size_X") == "65536"]
 
 
-def summarize(trace=None, fetch=None, write=None, valu=None, lds=None, bench_json=None):
-    base = trace or fetch or write or valu or lds
+def summarize(trace=None, fetch=None, write=None, valu=None, lds=None, bench_json=None, tex=None):
+    base = trace or fetch or write or valu or lds or tex
     rows = _trace(base)
     win = cutmax_window(rows)
     dur = {}
@@ -131,6 +135,7 @@ def summarize(trace=None, fetch=None, write=None, valu=None, lds=None, bench_jso
     vv = raw(valu, ["SQ_INSTS_VALU", "SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_ADD_F64",
                     "SQ_INSTS_VALU_INT32", "SQ_INSTS_VALU_TRANS_F64"])
     ll = raw(lds, ["SQ_INSTS_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_LDS_IDX_ACTIVE"])
+    tx = raw(tex, ["TA_TA_BUSY", "TD_TD_BUSY"])
     alg = {}
     digest = None
     if bench_json:
@@ -168,6 +173,9 @@ def summarize(trace=None, fetch=None, write=None, valu=None, lds=None, bench_jso
         if ll:
             act = sum(ll[i]["SQ_LDS_IDX_ACTIVE"] for i in ids)
             e["lds_conflict"] = sum(ll[i]["SQ_LDS_BANK_CONFLICT"] for i in ids) / act if act else 0.0
+        if tx:
+            e["ta_busy"] = sum(tx[i]["TA_TA_BUSY"] for i in ids) / (CUS * t * CLOCK_HZ)
+            e["td_busy"] = sum(tx[i]["TD_TD_BUSY"] for i in ids) / (CUS * t * CLOCK_HZ)
         res.append(e)
     res.sort(key=lambda e: -e["total_ms"])
     return {"dispatches": len(win), "total_ms": total * 1e3, "fetch_scale": fscale, "write_scale": wscale,
@@ -177,7 +185,8 @@ def summarize(trace=None, fetch=None, write=None, valu=None, lds=None, bench_jso
 def to_markdown(s) -> str:
     cols = [("kernel", "{}"), ("launches", "{}"), ("total_ms", "{:.3f}"), ("avg_us", "{:.1f}"), ("share", "{:.1%}"),
             ("alg_MiB", "{:.1f}"), ("fetch_MiB", "{:.1f}"), ("write_MiB", "{:.1f}"), ("hbm_GBps", "{:.0f}"),
-            ("valu_util", "{:.1%}"), ("f64_share", "{:.0%}"), ("int32_share", "{:.0%}"), ("lds_conflict", "{:.1%}")]
+            ("valu_util", "{:.1%}"), ("f64_share", "{:.0%}"), ("int32_share", "{:.0%}"), ("lds_conflict", "{:.1%}"),
+            ("ta_busy", "{:.0%}"), ("td_busy", "{:.0%}")]
     present = [c for c in cols if any(c[0] in e for e in s["kernels"])]
     out = ["| " + " | ".join(c[0] for c in present) + " |", "|" + "---|" * len(present)]
     for e in s["kernels"]:
@@ -193,13 +202,13 @@ def to_markdown(s) -> str:
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    for k in ("trace", "fetch", "write", "valu", "lds"):
+    for k in ("trace", "fetch", "write", "valu", "lds", "tex"):
         ap.add_argument("--" + k)
     ap.add_argument("--bench-json", help="a file holding bench.py's JSON line (algorithmic bytes, "
                     "source digest); the counter runs' own logs hold one")
     ap.add_argument("--json-out", help="also write the summary as JSON to this file")
     a = ap.parse_args()
-    s = summarize(a.trace, a.fetch, a.write, a.valu, a.lds, a.bench_json)
+    s = summarize(a.trace, a.fetch, a.write, a.valu, a.lds, a.bench_json, a.tex)
     if a.json_out:
         with open(a.json_out, "w") as fh:
             json.dump(s, fh, indent=1)

@@ -61,6 +61,20 @@ def test_window_calibration_and_aggregation(tmp_path):
     assert "ntt_fwd_pass1" in rs.to_markdown(s)
 
 
+def test_texture_unit_busy_fraction(tmp_path):
+    rows = _trace(["he::k_inner_product_rot_lds<7, 3, 1>(a)"])
+    # timed dispatch 3 lasts 3000 ns = 7200 cycles at 2.4 GHz on each of 256 CUs
+    cyc = 256 * 3000e-9 * 2.4e9
+    cnt = [{"Dispatch_Id": r["Dispatch_Id"], "Counter_Name": c, "Counter_Value": v * cyc}
+           for r in rows for c, v in (("TA_TA_BUSY", 0.5), ("TD_TD_BUSY", 0.25))]
+    _write(str(tmp_path / "tex"), rows, cnt)
+    s = rs.summarize(tex=str(tmp_path / "tex"))
+    (e,) = s["kernels"]
+    assert e["kernel"] == "k_inner_product_rot"
+    assert e["ta_busy"] == pytest.approx(0.5) and e["td_busy"] == pytest.approx(0.25)
+    assert "ta_busy" in rs.to_markdown(s)
+
+
 def test_mismatched_halves_are_rejected(tmp_path):
     rows = _trace(["he::k_modup<10, 8>(a)"])
     rows[2]["Kernel_Name"] = "he::k_tensor(a)"        # the timed half launches another kernel
@@ -76,3 +90,5 @@ def test_kernel_class_names():
     assert rs.kernel_class("void he::k_ntt<4, 16, true, false, 0, 3, 0>(x)") == "ntt_fwd_pass2_moddown_rescale"
     assert rs.kernel_class("void he::k_ntt<4, 16, true, true, 0, 0, 1>(x)") == "ntt_inv_pass2_factored"
     assert rs.kernel_class("void he::k_inner_product_rot<3>(he::DevTables)") == "k_inner_product_rot"
+    assert rs.kernel_class("void he::k_inner_product_rot_reg<7, 3>(x)") == "k_inner_product_rot"
+    assert rs.kernel_class("void he::k_inner_product_rot_lds<7, 3, 2>(x)") == "k_inner_product_rot"
