@@ -462,27 +462,32 @@ struct Exec {
                 dg.lo[j] = j * A;
                 dg.dl[j] = std::min(A, l + 1 - j * A);
             }
+            // the digits' own limbs are not copied: the key products read them from d
             launch_modup(T, dcoef, (long long)(l + 1) * N, ext, (long long)beta * next * N, (long long)next * N, d,
-                         dstride, cnt, beta, next, C->ext_prime[l], dg, s);
+                         dstride, cnt, beta, next, C->ext_prime[l], dg, s, true);
             // every digit's converted limbs in one transform
             const int nd = C->ndall[l];
             launch_ntt(T, VecSet{ext, cnt * nd, nd, (long long)beta * next * N, C->ndall_slot[l], C->ndall_prime[l]},
                        false, C->ntt_variant, s);
         }
         if (go()) {
-            if (rot)
+            const OwnSrc own = ext_pre ? OwnSrc{} : OwnSrc{d, dstride, A, l};
+            if (rot) {
+                RotSet rs = *rot;
+                if (!rs.multi) rs.own = own;
                 launch_inner_product_rot(T, ext, (long long)beta * next * N, (long long)next * N, acc,
-                                         acc + (long long)next * N, 2LL * next * N, *rot, C->betaL, cnt, beta,
+                                         acc + (long long)next * N, 2LL * next * N, rs, C->betaL, cnt, beta,
                                          next, C->ext_prime[l], s);
-            else if (mrescale)
+            } else if (mrescale) {
                 launch_inner_product(T, ext, (long long)beta * next * N, (long long)next * N, acc,
                                      acc + (long long)next * N, 2LL * next * N, C->keys[kidx], C->betaL, cnt,
                                      beta, next, C->ext_prime[l], s, a1.p + (long long)l * N, a1.ct, a1.poly, l,
-                                     C->pmod_h[l]);
-            else
+                                     C->pmod_h[l], own);
+            } else {
                 launch_inner_product(T, ext, (long long)beta * next * N, (long long)next * N, acc,
                                      acc + (long long)next * N, 2LL * next * N, C->keys[kidx], C->betaL, cnt,
-                                     beta, next, C->ext_prime[l], s);
+                                     beta, next, C->ext_prime[l], s, nullptr, 0, 0, -1, 0.0, own);
+            }
             if (mrescale) {
                 // B = {q_l, P} to the coefficient domain, scaled by Bhat^-1; convert to q_0..q_{l-1};
                 // transform and combine on store: (acc - conv) (P q_l)^-1 + d q_l^-1

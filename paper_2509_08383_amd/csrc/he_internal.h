@@ -139,15 +139,24 @@ struct ModUpDigits {
     const double *qhat[8];  // [dl][next] per digit
     int lo[8], dl[8];
 };
+// skip_own: the digits' own slots are not written (their readers take them from dntt)
 void launch_modup(const DevTables &T, const double *v, long long vstride, double *ext, long long esb,
                   long long esj, const double *dntt, long long nstride, int cnt, int beta, int next,
-                  const int *ext_prime, const ModUpDigits &dg, hipStream_t s);
+                  const int *ext_prime, const ModUpDigits &dg, hipStream_t s, bool skip_own = false);
+// Where the key products read a digit's own limbs: with p set, limb t <= l of digit
+// t / alpha (the NTT-domain input word itself) is read at p + ct * ct_stride + t N
+// instead of from the extended digits; p null: every limb from the extended digits.
+struct OwnSrc {
+    const double *p;
+    long long ct_stride;
+    int alpha, l;
+};
 void launch_inner_product(const DevTables &T, const double *ext, long long estride_b,
                           long long estride_j, double *acc0, double *acc1, long long astride,
                           KeyRef key, int betaL, int cnt,
                           int beta, int next, const int *ext_prime, hipStream_t s,
                           const double *dadd = nullptr, long long dct = 0, long long dpoly = 0, int tl = -1,
-                          double pmodl = 0.0);
+                          double pmodl = 0.0, const OwnSrc &own = OwnSrc{});
 void launch_pack_key(const double *src, uint32_t *lo, uint16_t *hi, int beta, int np, int N, hipStream_t s);
 
 // terms of a plaintext-times-ciphertext sum (bootstrap linear transforms): plaintext
@@ -204,6 +213,7 @@ struct RotSet {
     int multi;
     const double *ext_r[kMaxHoist];
     const double *c0_r[kMaxHoist];
+    OwnSrc own;  // the digits' own limbs (not with multi)
 };
 void launch_inner_product_rot(const DevTables &T, const double *ext, long long estride_b, long long estride_j,
                               double *acc0, double *acc1, long long astride, const RotSet &rs, int betaL,

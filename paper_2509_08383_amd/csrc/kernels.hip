@@ -358,7 +358,8 @@ void launch_lincomb(const DevTables &T, double *out, long long oct, long long op
 // v holds v_a = [d_{lo+a} * Qhat_a^-1]_{q_{lo+a}} in the coefficient domain (the
 // inverse NTT applied that scaling); for every extended slot t outside the digit
 // ext_j,t = sum_a v~_a [Qhat_a]_{prime(t)} with v~_a the centred representative of v_a
-// (|v~_a| <= q/2); digit slots copy the NTT-domain input.
+// (|v~_a| <= q/2); digit slots copy the NTT-domain input, or are left unwritten with
+// skip_own (the key products then read those words from the input).
 // Grid: x = blocks of TB target slots (fastest, so the v words of one coefficient
 // block stay in L2 across target blocks), y = coefficient blocks, z = (ciphertext,
 // digit).  The block's [Qhat_a]_{prime(t)} table and moduli are staged in LDS (every
@@ -385,7 +386,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                                                double *__restrict__ ext, long long esb, long long esj,
                                                const double *__restrict__ dntt, long long nstride, int beta,
                                                int next, const int *__restrict__ ext_prime, ModUpDigits dg,
-                                               int ntb, int cblk, int nz) {
+                                               int ntb, int cblk, int nz, int skip_own) {
     __shared__ double sq[DL * TB];
     __shared__ double sp[TB], si[TB];
     ConvIdx ix;
@@ -435,8 +436,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         double acc = 0.0;
 #pragma unroll
         for (int a = 0; a < DL; ++a) acc += mm(va[a], sq[a * TB + tt], p, pinv);
-        if (t >= lo && t < lo + dl) X[(long long)t * T.N] = dntt[ct * nstride + (long long)t * T.N + x];
-        else X[(long long)t * T.N] = canon(acc, p, pinv);
+        if (t >= lo && t < lo + dl) {
+            if (!skip_own) X[(long long)t * T.N] = dntt[ct * nstride + (long long)t * T.N + x];
+        } else {
+            X[(long long)t * T.N] = canon(acc, p, pinv);
+        }
     }
 }
 
@@ -446,13 +450,13 @@ static int digit_len(int dl) { return dl <= 4 ? 4 : dl <= 8 ? 8 : dl <= 10 ? 10 
 template <int TB>
 static void modup_tb(int DL, int cblk, int nz, hipStream_t s, const DevTables &T, const double *v, long long vstride,
                      double *ext, long long esb, long long esj, const double *dntt, long long nstride, int beta,
-                     int next, const int *ext_prime, const ModUpDigits &dg) {
+                     int next, const int *ext_prime, const ModUpDigits &dg, int skip_own) {
     const int ntb = (next + TB - 1) / TB;
     const dim3 grid = conv_grid(ntb, cblk, nz);
 #define MU_CASE(D)                                                                                          \
     case D:                                                                                                 \
         KL("k_modup", (k_modup<D, TB>), grid, dim3(256), 0, s, T, v, vstride, ext, esb, esj, dntt, nstride, \
-           beta, next, ext_prime, dg, ntb, cblk, nz);                                                       \
+           beta, next, ext_prime, dg, ntb, cblk, nz, skip_own);                                             \
         break;
     switch (DL) { MU_CASE(4) MU_CASE(8) MU_CASE(10) MU_CASE(12) MU_CASE(16) }
 #undef MU_CASE
@@ -460,7 +464,7 @@ static void modup_tb(int DL, int cblk, int nz, hipStream_t s, const DevTables &T
 
 void launch_modup(const DevTables &T, const double *v, long long vstride, double *ext, long long esb,
                   long long esj, const double *dntt, long long nstride, int cnt, int beta, int next,
-                  const int *ext_prime, const ModUpDigits &dg, hipStream_t s) {
+                  const int *ext_prime, const ModUpDigits &dg, hipStream_t s, bool skip_own) {
     if (cnt <= 0) return;
     int dmax = 0;
     for (int j = 0; j < beta; ++j) dmax = dg.dl[j] > dmax ? dg.dl[j] : dmax;
@@ -470,14 +474,15 @@ void launch_modup(const DevTables &T, const double *v, long long vstride, double
     const bool wide = (long long)((next + 7) / 8) * cblk * cnt * beta >= 2048;
     int lp1 = 0;
     for (int j = 0; j < beta; ++j) lp1 += dg.dl[j];
-    // the l+1 digit words and the l+1 NTT-domain words in, every extended slot out
-    kprof_set_bytes(8.0 * T.N * cnt * (2.0 * lp1 + (double)beta * next));
+    // the l+1 digit words in, every extended slot out; the l+1 NTT-domain words in and
+    // out again unless skipped
+    kprof_set_bytes(8.0 * T.N * cnt * (skip_own ? (double)beta * next : 2.0 * lp1 + (double)beta * next));
     if (wide)
         modup_tb<8>(DL, cblk, cnt * beta, s, T, v, vstride, ext, esb, esj, dntt, nstride, beta, next, ext_prime,
-                    dg);
+                    dg, skip_own ? 1 : 0);
     else
         modup_tb<4>(DL, cblk, cnt * beta, s, T, v, vstride, ext, esb, esj, dntt, nstride, beta, next, ext_prime,
-                    dg);
+                    dg, skip_own ? 1 : 0);
 }
 
 // the two words (polynomials 0, 1) of digit j of limb t at position x: hi 2^32 + lo,
@@ -508,6 +513,11 @@ void launch_pack_key(const double *src, uint32_t *lo, uint16_t *hi, int beta, in
     KL("k_pack_key", k_pack_key, dim3(4096), dim3(256), 0, s, src, lo, hi, beta, np, N);
 }
 
+// the digit whose own limb is extended slot t when the key products read the own limbs
+// from the NTT-domain input (ModUp then skipped their copy), else -1; uniform over a
+// workgroup, which covers one slot
+DEV int own_digit(const OwnSrc &o, int t) { return (o.p && t <= o.l) ? t / o.alpha : -1; }
+
 // acc_c[ct][t] = sum_j ext[ct][j][t] * key[j][c][prime(t)]; the key words are
 // read once per (t, x) and reused for every ciphertext of the batch.
 // With dadd, slot tl also gets [P]_{q_tl} times the words dadd[ct dct + c dpoly + x]
@@ -515,10 +525,12 @@ void launch_pack_key(const double *src, uint32_t *lo, uint16_t *hi, int beta, in
 __global__ void k_inner_product(DevTables T, const double *ext, long long esb, long long esj,
                                 double *acc0, double *acc1, long long astride, KeyRef key,
                                 int betaL, int cnt, int beta, const int *ext_prime,
-                                const double *dadd, long long dct, long long dpoly, int tl, double pmodl) {
+                                const double *dadd, long long dct, long long dpoly, int tl, double pmodl,
+                                OwnSrc own) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= T.N) return;
     const int t = blockIdx.y;
+    const int oj = own_digit(own, t);
     const int pt = ext_prime[t];
     const double p = T.p[pt], pinv = T.pinv[pt];
     double k0[8], k1[8];
@@ -530,7 +542,8 @@ __global__ void k_inner_product(DevTables T, const double *ext, long long esb, l
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             if (j < beta) {
-                const double e = ext[ct * esb + j * esj + (long long)t * T.N + x];
+                const double *D = j == oj ? own.p + ct * own.ct_stride : ext + ct * esb + j * esj;
+                const double e = D[(long long)t * T.N + x];
                 s0 += mm(e, k0[j], p, pinv);
                 s1 += mm(e, k1[j], p, pinv);
             }
@@ -547,13 +560,13 @@ void launch_inner_product(const DevTables &T, const double *ext, long long estri
                           long long estride_j, double *acc0, double *acc1, long long astride,
                           KeyRef key, int betaL, int cnt,
                           int beta, int next, const int *ext_prime, hipStream_t s, const double *dadd,
-                          long long dct, long long dpoly, int tl, double pmodl) {
+                          long long dct, long long dpoly, int tl, double pmodl, const OwnSrc &own) {
     if (cnt <= 0) return;
     // key words (6 bytes each) once, extended digits and both accumulators per ciphertext
     kprof_set_bytes(T.N * next * (6.0 * 2.0 * beta + 8.0 * cnt * (beta + 2.0)));
     KL("k_inner_product", k_inner_product, dim3((T.N + 255) / 256, next), dim3(256), 0, s, T, ext,
                        estride_b, estride_j, acc0, acc1, astride, key, betaL, cnt,
-                       beta, ext_prime, dadd, dct, dpoly, tl, pmodl);
+                       beta, ext_prime, dadd, dct, dpoly, tl, pmodl, own);
 }
 
 // Inner product of a hoisted rotate-and-sum step: for rotation r with Galois
@@ -608,11 +621,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BETA >= 3 ?
     const int pt = ext_prime[t];
     const double p = T.p[pt], pinv = T.pinv[pt];
     const bool wsum = rs.c0 && t <= rs.lq;
+    const int oj = own_digit(rs.own, t);
     // the unrolled form serves one ciphertext (the key loads then stay inside the
     // rotation chunks instead of being hoisted out of a ciphertext loop)
     const int ncts = BETA > 0 && NR > 0 ? 1 : cnt;
     for (int ct = 0; ct < ncts; ++ct) {
         const double *E = ext + ct * esb + (long long)t * T.N;
+        const double *O = oj >= 0 ? rs.own.p + ct * rs.own.ct_stride + (long long)t * T.N : nullptr;
         const double *C0 = wsum ? rs.c0 + ct * rs.c0_ct + (long long)t * T.N : nullptr;
         double s0 = 0.0, s1 = 0.0;
         if (BETA > 0 && NR > 0) {
@@ -628,7 +643,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BETA >= 3 ?
                         const unsigned src = aut_src((unsigned)x, rs.g[r0 + rr], T.logN);
 #pragma unroll
                         for (int j = 0; j < J; ++j) {
-                            e[rr][j] = (E + j * esj)[src];
+                            e[rr][j] = (j == oj ? O : E + j * esj)[src];
                             key_pair(rs.key[r0 + rr], betaL, pt, j, T.N, x, a0[rr][j], a1[rr][j]);
                         }
                         c[rr] = wsum ? C0[src] : 0.0;
@@ -662,7 +677,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BETA >= 3 ?
 #pragma unroll
                 for (int j = 0; j < JM; ++j) {
                     if (j < beta) {
-                        const double e = E[j * esj + src];
+                        const double e = (j == oj ? O : E + j * esj)[src];
                         double w0, w1;
                         key_pair(K, betaL, pt, j, T.N, x, w0, w1);
                         s0 += mm(e, w0, p, pinv);
@@ -713,8 +728,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BETA >= 3 &
     // kept for the c0 fold take 2 waves per SIMD, which leaves room for all 7 at once
     constexpr int RCW = BETA >= 3 && NR >= 7 ? 7 : 3;
     constexpr int RC = NR > RCW ? RCW : NR;
+    const int oj = own_digit(rs.own, t);
     for (int ct = 0; ct < cnt; ++ct) {
         const double *E = ext + ct * esb + (long long)t * T.N;
+        const double *O = oj >= 0 ? rs.own.p + ct * rs.own.ct_stride + (long long)t * T.N : nullptr;
         double s0 = 0.0, s1 = 0.0;
 #pragma unroll
         for (int r0 = 0; r0 < NR; r0 += RC) {
@@ -723,7 +740,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BETA >= 3 &
             for (int rr = 0; rr < RC; ++rr)
 #pragma unroll
                 for (int j = 0; j < BETA; ++j)
-                    if (r0 + rr < NR) e[rr][j] = (E + j * esj)[src[r0 + rr]];
+                    if (r0 + rr < NR) e[rr][j] = (j == oj ? O : E + j * esj)[src[r0 + rr]];
 #pragma unroll
             for (int rr = 0; rr < RC; ++rr) {
                 const int r = r0 + rr;
@@ -795,13 +812,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         for (int j = 0; j < BETA; ++j) key_pair(rs.key[r], betaL, pt, j, T.N, x, k0[r][j], k1[r][j]);
     }
     double w[NS][NQ];
+    const int oj = own_digit(rs.own, t);
     auto fetch = [&](int ct) {
         const double *E = ext + ct * esb + (long long)t * T.N + tid;
+        const double *O = oj >= 0 ? rs.own.p + ct * rs.own.ct_stride + (long long)t * T.N + tid : nullptr;
         const double *C0 = wsum ? rs.c0 + ct * rs.c0_ct + (long long)t * T.N + tid : nullptr;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
 #pragma unroll
-            for (int j = 0; j < BETA; ++j) w[s][j] = E[j * esj + sbo[s]];
+            for (int j = 0; j < BETA; ++j) w[s][j] = (j == oj ? O : E + j * esj)[sbo[s]];
             w[s][BETA] = wsum ? C0[sbo[s]] : 0.0;
         }
     };
