@@ -48,8 +48,8 @@ typedef struct he_ct he_ct;
 
 /* CKKS parameters.  log_n in {12, 16}; n_q >= 2 Q primes (levels = n_q - 1);
  * bit sizes in [20, 48] (the kernels compute modulo these primes in the FP64
- * pipe, exact below 2^52, and store evaluation keys as 48-bit words, 6 bytes
- * each); dnum >= 1 key-switching digits; log2_scale is the
+ * pipe, exact below 2^52, and store evaluation key words in 5 bytes for
+ * primes below 2^40 and 6 bytes for the others); dnum >= 1 key-switching digits; log2_scale is the
  * encoding scale Delta = 2^log2_scale; seed keys every random draw
  * (Philox4x32-10).  device: HIP device ordinal.  stream: a hipStream_t the
  * library enqueues on (for example PyTorch's current stream), or NULL for a

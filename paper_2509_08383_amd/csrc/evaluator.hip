@@ -139,7 +139,9 @@ struct he_ctx {
     double *d_tab = nullptr;
     int *d_itab = nullptr;
     double *d_sk = nullptr;  // [np][N] NTT domain
-    std::vector<KeyRef> keys;  // packed 48-bit words (owned)
+    std::vector<KeyRef> keys;  // packed 40- and 48-bit words (owned)
+    std::vector<int> khb_host;  // per prime: high-part bytes of a key word (1 or 2)
+    size_t key_hi_bytes = 0;    // bytes of one key's high plane
     // level-indexed conversion tables (device pointers into d_tab / d_itab)
     std::vector<const int *> ext_prime;                 // [L+1] -> [l+1+alpha]
     std::vector<std::vector<const double *>> vinv, qhat;  // [L+1][beta_l]
@@ -2061,6 +2063,19 @@ void build_ctx(he_ctx *C, const he_params *prm) {
     }
     const size_t o_p = tb.d(pd), o_pinv = tb.d(pinv), o_tw = tb.d(tw), o_itw = tb.d(itw), o_ninv = tb.d(ninv),
                  o_two32 = tb.d(two32);
+    // evaluation-key high plane: 1 byte per word above the low 32 bits for primes below
+    // 2^40, else 2; each prime's beta_L rows of both polynomials contiguous
+    C->khb_host.assign(np, 2);
+    std::vector<int> khoff(np);
+    size_t hoff = 0;
+    for (int i = 0; i < np; ++i) {
+        C->khb_host[i] = q[i] < (1ull << 40) ? 1 : 2;
+        khoff[i] = (int)hoff;
+        hoff += (size_t)C->khb_host[i] * 2 * N * C->betaL;
+    }
+    REQUIRE(hoff < (1ull << 31), HE_EINVAL, "key plane offsets exceed 32 bits");
+    C->key_hi_bytes = hoff;
+    const size_t o_khb = tb.i(C->khb_host), o_khoff = tb.i(khoff);
     std::vector<int> ident(np);
     for (int i = 0; i < np; ++i) ident[i] = i;
     const size_t o_ident = tb.i(ident);
@@ -2208,7 +2223,8 @@ void build_ctx(he_ctx *C, const he_params *prm) {
     HIPCHK(hipMemcpy(C->d_itab, tb.iv.data(), tb.iv.size() * 4, hipMemcpyHostToDevice));
     double *D = C->d_tab;
     int *I = C->d_itab;
-    C->T = DevTables{N, C->logN, np, L, A, D + o_p, D + o_pinv, D + o_tw, D + o_itw, D + o_ninv, D + o_two32};
+    C->T = DevTables{N, C->logN, np, L, A, D + o_p, D + o_pinv, D + o_tw, D + o_itw, D + o_ninv, D + o_two32,
+                     I + o_khb, I + o_khoff, C->khb_host.data()};
     C->ident = I + o_ident;
     C->pprime = I + o_pprime;
     C->phinv = D + o_phinv; C->phat = D + o_phat; C->Pinv = D + o_Pinv; C->pmod = D + o_pmod;
@@ -2312,15 +2328,15 @@ void gen_keys(he_ctx *C, int from, int to) {
         if (C->keys[k].lo) {
             HIPCHK(hipStreamSynchronize(s));
             hipFree(const_cast<uint32_t *>(C->keys[k].lo));
-            hipFree(const_cast<uint16_t *>(C->keys[k].hi));
+            hipFree(const_cast<uint8_t *>(C->keys[k].hi));
             C->keys[k] = KeyRef{nullptr, nullptr};
         }
         uint32_t *klo = nullptr;
-        uint16_t *khi = nullptr;
+        uint8_t *khi = nullptr;
         // each plane owned by the context as soon as it exists (freed with it on any failure)
         dev_alloc(&klo, 4ull * kw, "evaluation key");
         C->keys[k] = KeyRef{klo, nullptr};
-        dev_alloc(&khi, 2ull * kw, "evaluation key");
+        dev_alloc(&khi, C->key_hi_bytes, "evaluation key");
         C->keys[k].hi = khi;
         if (k == 0) launch_square_res(T, tg, C->d_sk, np, s);
         else {
@@ -2340,7 +2356,7 @@ void gen_keys(he_ctx *C, int from, int to) {
             const int lo = j * C->alpha, hi = std::min(lo + C->alpha, C->L + 1);
             launch_keyb(T, kb, ka, te, C->d_sk, tg, C->pmod, np, lo, hi, s);
         }
-        launch_pack_key(tk, klo, khi, C->betaL, np, N, s);
+        launch_pack_key(T, tk, klo, khi, C->betaL, np, N, s);
     }
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipGetLastError());
@@ -2778,7 +2794,7 @@ void he_ctx_destroy(he_ctx *C) {
     for (auto &g : C->graphs) hipGraphExecDestroy(g.second);
     for (const KeyRef &k : C->keys) {
         hipFree(const_cast<uint32_t *>(k.lo));
-        hipFree(const_cast<uint16_t *>(k.hi));
+        hipFree(const_cast<uint8_t *>(k.hi));
     }
     hipFree(C->d_sk); hipFree(C->d_tab); hipFree(C->d_itab);
     for (auto &e : C->pt_cache) hipFree(e.second);

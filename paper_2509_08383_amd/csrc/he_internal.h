@@ -26,6 +26,11 @@ struct DevTables {
     const double *itw;   // [np][N] psi^-bitrev(k)
     const double *ninv;  // [np] N^-1 mod p
     const double *two32; // [np] 2^32 mod p
+    // evaluation-key high parts: bytes per word above the low 32 bits for each prime
+    // (1 below 2^40, else 2) and the byte offset of each prime's rows in the high plane
+    const int *khb;      // [np] (device)
+    const int *khoff;    // [np] (device)
+    const int *khb_h;    // [np] the same widths in host memory (byte accounting)
 };
 
 // A set of N-word vectors: vector v lives in group g = v / group at slot
@@ -48,13 +53,15 @@ struct ConstTab {
 };
 
 // An evaluation key of residues below 2^48 with the two polynomials of a digit
-// interleaved: word (limb t, digit j, position x, polynomial c) is at index
-// ((t beta_L + j) N + x) 2 + c, so a lane reads both words of a digit with one 8-byte
-// and one 4-byte load and a wave's loads are contiguous.  Stored as two planes: the
-// low 32 bits and the high 16 bits of every word (6 bytes a word).
+// interleaved, stored as two planes.  Low plane: the low 32 bits of word (limb t, digit
+// j, position x, polynomial c) at index ((t beta_L + j) N + x) 2 + c.  High plane: the
+// bits above 32, in hb = khb[t] bytes (1 for primes below 2^40, 2 for the others), the
+// rows of prime t from byte khoff[t] on and word (j, x, c) at khoff[t] + ((j N + x) 2 + c)
+// hb.  A lane reads both words of a digit with one 8-byte load and one 2- or 4-byte load
+// (5 or 6 bytes a word), and a wave's loads are contiguous.
 struct KeyRef {
     const uint32_t *lo;
-    const uint16_t *hi;
+    const uint8_t *hi;
 };
 
 // optional per-kernel profiler: when set, every launch is bracketed by HIP
@@ -157,7 +164,8 @@ void launch_inner_product(const DevTables &T, const double *ext, long long estri
                           int beta, int next, const int *ext_prime, hipStream_t s,
                           const double *dadd = nullptr, long long dct = 0, long long dpoly = 0, int tl = -1,
                           double pmodl = 0.0, const OwnSrc &own = OwnSrc{});
-void launch_pack_key(const double *src, uint32_t *lo, uint16_t *hi, int beta, int np, int N, hipStream_t s);
+void launch_pack_key(const DevTables &T, const double *src, uint32_t *lo, uint8_t *hi, int beta, int np, int N,
+                     hipStream_t s);
 
 // terms of a plaintext-times-ciphertext sum (bootstrap linear transforms): plaintext
 // pt[t] ([limbs][N], NTT domain) times ciphertext x[t] (ciphertext c at x + c xct,

@@ -485,20 +485,26 @@ void launch_modup(const DevTables &T, const double *v, long long vstride, double
                     dg, skip_own ? 1 : 0);
 }
 
-// the two words (polynomials 0, 1) of digit j of limb t at position x: hi 2^32 + lo,
-// exact (below 2^48); one 8-byte load of the low halves, one 4-byte load of the high
-DEV void key_pair(const KeyRef &k, int betaL, int t, int j, int N, int x, double &k0, double &k1) {
-    // the row offset is uniform across the wave, the position a 32-bit per-lane index
+// the two words (polynomials 0, 1) of digit j of prime t at position x: hi 2^32 + lo,
+// exact (below 2^48); one 8-byte load of the low halves and one aligned 4-byte load of
+// the high parts, without a branch: with 2-byte high parts (hb = 1) the dword at x / 2
+// holds positions x and x ^ 1 and the lane takes its half
+DEV void key_pair(const KeyRef &k, const DevTables &T, int betaL, int t, int j, int N, int x, double &k0,
+                  double &k1) {
+    // the row offsets are uniform across the wave, the position a 32-bit per-lane index
     const long long row = ((long long)t * betaL + j) * N * 2;
     const uint2 l = ((const uint2 *)(k.lo + row))[(unsigned)x];
-    const uint32_t h = ((const uint32_t *)(k.hi + row))[(unsigned)x];
-    k0 = __builtin_fma((double)(h & 0xffffu), 4294967296.0, (double)l.x);
-    k1 = __builtin_fma((double)(h >> 16), 4294967296.0, (double)l.y);
+    const int hb = T.khb[t];
+    const uint32_t *hr = (const uint32_t *)(k.hi + T.khoff[t] + (long long)j * N * 2 * hb);
+    const uint32_t w = hr[(unsigned)x >> (2 - hb)] >> (hb == 1 ? 16u * ((unsigned)x & 1u) : 0u);
+    const uint32_t m = hb == 1 ? 0xffu : 0xffffu;
+    k0 = __builtin_fma((double)(w & m), 4294967296.0, (double)l.x);
+    k1 = __builtin_fma((double)((w >> (8 * hb)) & m), 4294967296.0, (double)l.y);
 }
 
 // src [beta][2][np][N] doubles -> packed planes with the polynomials interleaved
-__global__ void k_pack_key(const double *__restrict__ src, uint32_t *__restrict__ lo, uint16_t *__restrict__ hi,
-                           int beta, int np, int N) {
+__global__ void k_pack_key(const double *__restrict__ src, uint32_t *__restrict__ lo, uint8_t *__restrict__ hi,
+                           int beta, int np, int N, DevTables T) {
     const size_t per = (size_t)np * N, n = (size_t)beta * 2 * per;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
         const size_t jc = i / per, pos = i - jc * per;  // jc = 2 j + c, pos = t N + x
@@ -506,11 +512,25 @@ __global__ void k_pack_key(const double *__restrict__ src, uint32_t *__restrict_
         const size_t o = ((t * (size_t)beta + j) * (size_t)N + x) * 2 + c;
         const uint64_t v = (uint64_t)src[i];
         lo[o] = (uint32_t)v;
-        hi[o] = (uint16_t)(v >> 32);
+        const int hb = T.khb[t];
+        const size_t ho = (size_t)T.khoff[t] + ((j * (size_t)N + x) * 2 + c) * (size_t)hb;
+        if (hb == 2) *(uint16_t *)(hi + ho) = (uint16_t)(v >> 32);
+        else hi[ho] = (uint8_t)(v >> 32);
     }
 }
-void launch_pack_key(const double *src, uint32_t *lo, uint16_t *hi, int beta, int np, int N, hipStream_t s) {
-    KL("k_pack_key", k_pack_key, dim3(4096), dim3(256), 0, s, src, lo, hi, beta, np, N);
+void launch_pack_key(const DevTables &T, const double *src, uint32_t *lo, uint8_t *hi, int beta, int np, int N,
+                     hipStream_t s) {
+    KL("k_pack_key", k_pack_key, dim3(4096), dim3(256), 0, s, src, lo, hi, beta, np, N, T);
+}
+
+// bytes per position of one key row pair (both polynomials, 8 low bytes and 2 hb high
+// bytes a slot) summed over the extended slots of a level with `next` slots (the Q
+// primes 0..l, then the P primes)
+static double key_row_bytes(const DevTables &T, int next) {
+    const int l = next - T.alpha - 1;
+    double b = 0.0;
+    for (int t = 0; t < next; ++t) b += 8.0 + 2.0 * T.khb_h[t <= l ? t : T.L + 1 + (t - l - 1)];
+    return b;
 }
 
 // the digit whose own limb is extended slot t when the key products read the own limbs
@@ -536,7 +556,7 @@ __global__ void k_inner_product(DevTables T, const double *ext, long long esb, l
     double k0[8], k1[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j)
-        if (j < beta) key_pair(key, betaL, pt, j, T.N, x, k0[j], k1[j]);
+        if (j < beta) key_pair(key, T, betaL, pt, j, T.N, x, k0[j], k1[j]);
     for (int ct = 0; ct < cnt; ++ct) {
         double s0 = 0.0, s1 = 0.0;
 #pragma unroll
@@ -562,8 +582,8 @@ void launch_inner_product(const DevTables &T, const double *ext, long long estri
                           int beta, int next, const int *ext_prime, hipStream_t s, const double *dadd,
                           long long dct, long long dpoly, int tl, double pmodl, const OwnSrc &own) {
     if (cnt <= 0) return;
-    // key words (6 bytes each) once, extended digits and both accumulators per ciphertext
-    kprof_set_bytes(T.N * next * (6.0 * 2.0 * beta + 8.0 * cnt * (beta + 2.0)));
+    // key words (5 or 6 bytes each) once, extended digits and both accumulators per ciphertext
+    kprof_set_bytes(T.N * (beta * key_row_bytes(T, next) + 8.0 * next * cnt * (beta + 2.0)));
     KL("k_inner_product", k_inner_product, dim3((T.N + 255) / 256, next), dim3(256), 0, s, T, ext,
                        estride_b, estride_j, acc0, acc1, astride, key, betaL, cnt,
                        beta, ext_prime, dadd, dct, dpoly, tl, pmodl, own);
@@ -644,7 +664,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BETA >= 3 ?
 #pragma unroll
                         for (int j = 0; j < J; ++j) {
                             e[rr][j] = (j == oj ? O : E + j * esj)[src];
-                            key_pair(rs.key[r0 + rr], betaL, pt, j, T.N, x, a0[rr][j], a1[rr][j]);
+                            key_pair(rs.key[r0 + rr], T, betaL, pt, j, T.N, x, a0[rr][j], a1[rr][j]);
                         }
                         c[rr] = wsum ? C0[src] : 0.0;
                     }
@@ -679,7 +699,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BETA >= 3 ?
                     if (j < beta) {
                         const double e = (j == oj ? O : E + j * esj)[src];
                         double w0, w1;
-                        key_pair(K, betaL, pt, j, T.N, x, w0, w1);
+                        key_pair(K, T, betaL, pt, j, T.N, x, w0, w1);
                         s0 += mm(e, w0, p, pinv);
                         s1 += mm(e, w1, p, pinv);
                     }
@@ -721,7 +741,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BETA >= 3 &
     for (int r = 0; r < NR; ++r) {
         src[r] = aut_src((unsigned)x, rs.g[r], T.logN);
 #pragma unroll
-        for (int j = 0; j < BETA; ++j) key_pair(rs.key[r], betaL, pt, j, T.N, x, k0[r][j], k1[r][j]);
+        for (int j = 0; j < BETA; ++j) key_pair(rs.key[r], T, betaL, pt, j, T.N, x, k0[r][j], k1[r][j]);
     }
     const bool wsum = rs.c0 && t <= rs.lq;
     // rotations whose gathers are in flight together: 7 x 3 keys held and the running sum
@@ -809,7 +829,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         const unsigned src = aut_src((unsigned)x, rs.g[r], T.logN);
         so[r] = (NS == 2 && ((smask >> r) & 1) ? 256 : 0) + (int)(src & 255u);
 #pragma unroll
-        for (int j = 0; j < BETA; ++j) key_pair(rs.key[r], betaL, pt, j, T.N, x, k0[r][j], k1[r][j]);
+        for (int j = 0; j < BETA; ++j) key_pair(rs.key[r], T, betaL, pt, j, T.N, x, k0[r][j], k1[r][j]);
     }
     double w[NS][NQ];
     const int oj = own_digit(rs.own, t);
@@ -891,7 +911,7 @@ __global__ __launch_bounds__(256) void k_inner_product_multi(DevTables T, long l
 #pragma unroll
             for (int j = 0; j < BETA; ++j) {
                 e[j] = E[j * esj + src];
-                key_pair(K, betaL, pt, j, T.N, x, a0[j], a1[j]);
+                key_pair(K, T, betaL, pt, j, T.N, x, a0[j], a1[j]);
             }
 #pragma unroll
             for (int j = 0; j < BETA; ++j) {
@@ -914,7 +934,7 @@ void launch_inner_product_rot(const DevTables &T, const double *ext, long long e
                               int cnt, int beta, int next, const int *ext_prime, hipStream_t s) {
     if (cnt <= 0) return;
     if (rs.multi) {
-        kprof_set_bytes(T.N * next * (6.0 * 2.0 * beta * rs.nr + 8.0 * cnt * (beta * rs.nr + 2.0)));
+        kprof_set_bytes(T.N * (beta * rs.nr * key_row_bytes(T, next) + 8.0 * next * cnt * (beta * rs.nr + 2.0)));
         const int xblocks = (T.N + 255) / 256;
         const dim3 g1(8 * ((next + 7) / 8) * xblocks);
 #define IPM_CASE(B)                                                                                            \
@@ -928,7 +948,7 @@ void launch_inner_product_rot(const DevTables &T, const double *ext, long long e
     }
     // every rotation's key words once; the extended digits and both accumulators
     // once per ciphertext
-    kprof_set_bytes(T.N * next * (6.0 * 2.0 * beta * rs.nr + 8.0 * cnt * (beta + 2.0)));
+    kprof_set_bytes(T.N * (beta * rs.nr * key_row_bytes(T, next) + 8.0 * next * cnt * (beta + 2.0)));
     const int xblocks = (T.N + 255) / 256;
     const dim3 g1(8 * ((next + 7) / 8) * xblocks);
     // a step whose Galois elements take at most one residue h != 1 mod N/128 reads its
