@@ -441,15 +441,19 @@ struct Exec {
     // ext_pre: the extended digits of d already computed (modup), d unused
     // acc_out (optional): the key-product accumulators [cnt][2][next] go there (and stay
     // after the call) instead of to workspace; md_poly1: the ModDown and the output cover
-    // polynomial 1 only (polynomial 0's accumulator is left in acc_out)
+    // polynomial 1 only (polynomial 0's accumulator is left in acc_out).
+    // d_half: [cnt][l+1][N] holding the first inverse-NTT pass of d (written by the
+    // previous call's chain_out), used in place for the ModUp input; chain_out (with
+    // md_poly1): the output polynomial's first inverse-NTT pass goes there as well
     void keyswitch(const double *d, long long dstride, int cnt, int l, int kidx, double *out, long long ostride,
                    Addend a1 = Addend{nullptr, 0, 0, 0}, Addend a2 = Addend{nullptr, 0, 0, 0},
                    const RotSet *rot = nullptr, bool mrescale = false, const double *ext_pre = nullptr,
-                   double *acc_out = nullptr, bool md_poly1 = false) {
+                   double *acc_out = nullptr, bool md_poly1 = false, double *d_half = nullptr,
+                   double *chain_out = nullptr) {
         const int A = C->alpha, next = l + 1 + A, beta = (l + 1 + A - 1) / A;
         const long long N = C->N;
         const size_t m = C->arena.mark();
-        double *dcoef = ext_pre ? nullptr : alloc_d((size_t)cnt * (l + 1) * N);
+        double *dcoef = ext_pre ? nullptr : d_half ? d_half : alloc_d((size_t)cnt * (l + 1) * N);
         double *ext = ext_pre ? const_cast<double *>(ext_pre) : alloc_d((size_t)cnt * beta * next * N);
         double *acc = acc_out ? acc_out : alloc_d((size_t)cnt * 2 * next * N);
         double *conv = alloc_d((size_t)cnt * 2 * (l + 1) * N);
@@ -457,7 +461,8 @@ struct Exec {
             // coefficient-domain digits, already scaled by Qhat_i^-1 (folded into N^-1)
             VecSet vd{dcoef, cnt * (l + 1), l + 1, (long long)(l + 1) * N, nullptr, nullptr};
             const VecSet vsrc{const_cast<double *>(d), cnt * (l + 1), l + 1, dstride, nullptr, nullptr};
-            launch_ntt(T, vd, true, C->ntt_variant, s, &vsrc, C->mu_scale[l]);
+            if (d_half) launch_ntt(T, vd, true, C->ntt_variant, s, nullptr, C->mu_scale[l], true);
+            else launch_ntt(T, vd, true, C->ntt_variant, s, &vsrc, C->mu_scale[l]);
             ModUpDigits dg{};
             for (int j = 0; j < beta; ++j) {
                 dg.qhat[j] = C->qhat[l][j];
@@ -530,6 +535,8 @@ struct Exec {
                 epi.add1 = a1.p; epi.a1_ct = a1.ct; epi.a1_poly = a1.poly; epi.m1 = a1.mask;
                 epi.add2 = a2.p; epi.a2_ct = a2.ct; epi.a2_poly = a2.poly; epi.m2 = a2.mask;
                 epi.cst = C->Pinv;
+                epi.chain = chain_out;
+                epi.ch_g = (long long)(l + 1) * N;
                 launch_ntt_fused(T, VecSet{conv, cnt * (l + 1), l + 1, (long long)(l + 1) * N, nullptr, nullptr},
                                  NttPro{}, epi, C->ntt_variant, s);
                 C->arena.release(m);
@@ -809,12 +816,16 @@ struct Exec {
             // accumulator of polynomial 0, two buffers used in turn), so only c1 takes a
             // ModDown per step and c0 one at the end; the first step reads a, the others
             // update o's c1 in place
+            // Each step but the last also writes the first inverse-NTT pass of its output
+            // c1 (chained into its ModDown epilogue) to dhalf, the next step's ModUp input.
             const int next = a.level + 1 + C->alpha;
             double *accb[2] = {alloc_d((size_t)a.cnt * 2 * next * C->N), alloc_d((size_t)a.cnt * 2 * next * C->N)};
+            double *dhalf = alloc_d((size_t)a.cnt * (a.level + 1) * C->N);
             for (size_t k = 0; k < steps.size(); ++k) {
                 const size_t m = C->arena.mark();
+                const bool last = k + 1 == steps.size();
                 rotsum_step_carried(k == 0 ? a : o, o, steps[k], k == 0 ? nullptr : accb[(k - 1) & 1], accb[k & 1],
-                                    k + 1 == steps.size());
+                                    last, k == 0 ? nullptr : dhalf, last ? nullptr : dhalf);
                 C->arena.release(m);
             }
             return o;
@@ -865,7 +876,7 @@ struct Exec {
     // next X0; c1 takes its ModDown:  y1 = c1 + MD_1.  The last step takes the ModDown of
     // both polynomials, y0 = MD(X0) = c0 + sum of every step's rotations.
     void rotsum_step_carried(const Bt &x, const Bt &y, const std::vector<int> &amounts, const double *x0,
-                             double *acc, bool last) {
+                             double *acc, bool last, double *d_half, double *chain_out) {
         const int l = x.level, next = l + 1 + C->alpha;
         const long long N = C->N;
         REQUIRE(!amounts.empty() && (int)amounts.size() <= kMaxHoist, HE_EINVAL, "hoisted step size");
@@ -892,7 +903,7 @@ struct Exec {
         }
         keyswitch(x.d + (long long)x.cap * N, 2LL * x.cap * N, x.cnt, l, -1, y.d, (long long)y.cap * N,
                   Addend{nullptr, 0, 0, 0}, Addend{x.d, 2LL * x.cap * N, (long long)x.cap * N, 2}, &rs, false,
-                  nullptr, acc, !last);
+                  nullptr, acc, !last, d_half, chain_out);
     }
 
     Bt power(const Bt &y, int p) {

@@ -84,9 +84,11 @@ void set_ntt_tuning(int logN, int bucket, int variant);
 
 // ---------------------------------------------------------------- kernels.hip
 // in place, or from *src into vs; the inverse multiplies by oscale[r] (per slot)
-// instead of N^-1 when oscale is given
+// instead of N^-1 when oscale is given.  strided_only (inverse, in place): vs already
+// holds the first inverse pass (the contiguous-block stages, as a chained forward
+// epilogue writes it) and only the second runs.
 void launch_ntt(const DevTables &T, const VecSet &vs, bool inverse, int variant, hipStream_t s,
-                const VecSet *src = nullptr, const double *oscale = nullptr);
+                const VecSet *src = nullptr, const double *oscale = nullptr, bool strided_only = false);
 
 // Forward-NTT prologue: kind 1 loads, for vector (g, r), the centred lift of the
 // coefficient-domain word last[g * l_g + j] (modulo ql) reduced modulo prime(r).
@@ -101,7 +103,10 @@ struct NttPro {
 //   kind 2 (rescale): out = (K in - w) * cst[r], K = kmul[(g >> 1) * kstride + r] or 1
 //   kind 3 (ModDown by P q_l): out = (in - w) * cst[r] + add1 * cst2[r]
 // with in = in[g * i_g + r N + j], out[g * o_g + r N + j], addk[(g>>1) ak_ct +
-// (g&1) ak_poly + r N + j] applied when bit (g & 1) of mk is set.
+// (g&1) ak_poly + r N + j] applied when bit (g & 1) of mk is set.  chain (kind 1): the
+// output words also go through the first pass of the inverse NTT (its contiguous-block
+// stages, which cover the same blocks) into chain[g * ch_g + r N + j], the input of a
+// following inverse NTT's second pass.
 struct NttEpi {
     int kind;
     double *out;
@@ -121,6 +126,8 @@ struct NttEpi {
     // 0: vector groups alternate the two polynomials (group g = 2 ct + poly); 1: every
     // group is polynomial 1 of ciphertext g (the addends are indexed accordingly)
     int poly1;
+    double *chain;
+    long long ch_g;
 };
 void launch_ntt_fused(const DevTables &T, const VecSet &vs, const NttPro &pro, const NttEpi &epi, int variant,
                       hipStream_t s);

@@ -23,6 +23,8 @@
 // reduction; GS stages reduce the sum every stage; outputs canonical in [0, p).
 #include "he_internal.h"
 
+#include <stdexcept>
+
 namespace he {
 
 #define DEV __device__ __forceinline__
@@ -49,7 +51,8 @@ DEV void nvs_at(const VecSet &v, int idx, int N, double *&ptr, int &pr, int &r, 
 }
 
 // PRO / EPI: fused prologue (forward pass 1 loads) and epilogue (forward pass 2
-// stores), see NttPro / NttEpi.  TWF (pass 2): the phase-B twiddles are formed from
+// stores), see NttPro / NttEpi; EPI 4 is the ModDown epilogue (kind 1) followed by the
+// inverse NTT's first pass on the output blocks (epi.chain).  TWF (pass 2): the phase-B twiddles are formed from
 // two factors instead of read from the full table: with s = 2H + H + sg the stage and
 // low = (th << sg) + g < 2^(s - R), the table entry psi^brev(2^s + (b << (s - R)) + low)
 // is tw[2^s + (b << (s - R))] * tw[low] (the three index parts occupy disjoint bits, so
@@ -143,7 +146,7 @@ __global__ __launch_bounds__(COLS *(1 << H)) void k_ntt(VecSet vs, VecSet src, c
         for (int e = 0; e < E; ++e) tile[lds(c, th + TPS * e)] = nred(v[e], p, pinv);
         __syncthreads();
         // epilogue operands, in flight while phase B computes
-        double ex[EPI ? EW : 1], es[(EPI == 1 || EPI == 3) ? EW : 1];
+        double ex[EPI ? EW : 1], es[(EPI == 1 || EPI == 3 || EPI == 4) ? EW : 1];
         long long rN = 0;
         if (EPI) {
             rN = (long long)r_ * NN;
@@ -158,7 +161,7 @@ __global__ __launch_bounds__(COLS *(1 << H)) void k_ntt(VecSet vs, VecSet src, c
                 const int idx = tid + NT * i, k = idx % SUB, cc = idx / SUB;
                 const long long j = gidx(cc, k);
                 ex[i] = in[j];
-                if (EPI == 1) es[i] = (use1 ? ad1[j] : 0.0) + (use2 ? ad2[j] : 0.0);
+                if (EPI == 1 || EPI == 4) es[i] = (use1 ? ad1[j] : 0.0) + (use2 ? ad2[j] : 0.0);
                 if (EPI == 3) es[i] = use1 ? ad1[j] : 0.0;
             }
         }
@@ -206,9 +209,66 @@ __global__ __launch_bounds__(COLS *(1 << H)) void k_ntt(VecSet vs, VecSet src, c
                     double x = ex[i];
                     if (EPI == 2 && epi.kmul) x = nmm(x, km, p, pinv);
                     double o = nmm(x - w, cst, p, pinv);
-                    if (EPI == 1) o += es[i];
+                    if (EPI == 1 || EPI == 4) o += es[i];
                     if (EPI == 3) o += nmm(es[i], cst2, p, pinv);
-                    out[gidx(cc, k)] = ncanon(o, p, pinv);
+                    const double oc = ncanon(o, p, pinv);
+                    out[gidx(cc, k)] = oc;
+                    if (EPI == 4) tile[lds(cc, k)] = oc;  // the word this thread read
+                }
+                if (EPI == 4) {
+                    // the inverse NTT's first pass on the output blocks (as the inverse
+                    // kernel's pass over contiguous blocks runs it, full twiddle table)
+                    const double *itw = T.itw + (long long)pr * NN;
+#pragma unroll
+                    for (int sg = 0; sg < H; ++sg) {
+#pragma unroll
+                        for (int g = 0; g < (1 << sg); ++g) {
+                            wa[(1 << sg) - 1 + g] = itw[(1 << (sg + soff)) + (b << sg) + g];
+                            wb[(1 << sg) - 1 + g] = itw[(1 << (H + sg + soff)) + (b << (H + sg)) + (th << sg) + g];
+                        }
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int e = 0; e < E; ++e) v[e] = tile[lds(c, th * E + e)];
+#pragma unroll
+                    for (int sg = H - 1; sg >= 0; --sg) {
+                        const int hd = E >> (sg + 1);
+#pragma unroll
+                        for (int g = 0; g < (1 << sg); ++g) {
+                            const double w = wb[(1 << sg) - 1 + g];
+#pragma unroll
+                            for (int i = 0; i < hd; ++i) {
+                                const int e0 = g * 2 * hd + i, e1 = e0 + hd;
+                                const double x = v[e0], y = v[e1];
+                                v[e0] = nred(x + y, p, pinv);
+                                v[e1] = nmm(x - y, w, p, pinv);
+                            }
+                        }
+                    }
+                    // each thread rewrites only the tile words it read
+#pragma unroll
+                    for (int e = 0; e < E; ++e) tile[lds(c, th * E + e)] = nred(v[e], p, pinv);
+                    __syncthreads();
+#pragma unroll
+                    for (int e = 0; e < E; ++e) v[e] = tile[lds(c, th + TPS * e)];
+#pragma unroll
+                    for (int sg = H - 1; sg >= 0; --sg) {
+                        const int hd = E >> (sg + 1);
+#pragma unroll
+                        for (int g = 0; g < (1 << sg); ++g) {
+                            const double w = wa[(1 << sg) - 1 + g];
+#pragma unroll
+                            for (int i = 0; i < hd; ++i) {
+                                const int e0 = g * 2 * hd + i, e1 = e0 + hd;
+                                const double x = v[e0], y = v[e1];
+                                v[e0] = nred(x + y, p, pinv);
+                                v[e1] = nmm(x - y, w, p, pinv);
+                            }
+                        }
+                    }
+                    double *cp = epi.chain + (long long)g_ * epi.ch_g + rN;
+#pragma unroll
+                    for (int e = 0; e < E; ++e) cp[gidx(c, th + TPS * e)] = ncanon(v[e], p, pinv);
                 }
             }
         }
@@ -290,7 +350,7 @@ void set_ntt_tuning(int logN, int bucket, int variant) {
 
 template <int H, int COLS, int PRO, int EPI, int TWF>
 static void ntt_run(const DevTables &T, const VecSet &vs, const VecSet *src, bool inverse, const double *oscale,
-                    const NttPro &pro, const NttEpi &epi, hipStream_t s) {
+                    const NttPro &pro, const NttEpi &epi, hipStream_t s, bool strided_only) {
     constexpr int SUB = 1 << (2 * H), NT = COLS * (1 << H);
     dim3 grid(SUB / COLS, vs.count), block(NT);
     const VecSet none{nullptr, 0, 1, 0, nullptr, nullptr};
@@ -309,18 +369,21 @@ static void ntt_run(const DevTables &T, const VecSet &vs, const VecSet *src, boo
         double extra = 0.0;
         if (EPI) {
             extra = 1.0;  // in
-            if (EPI == 1 && epi.add1) extra += __builtin_popcount(epi.m1 & 3) * 0.5;
-            if (EPI == 1 && epi.add2) extra += __builtin_popcount(epi.m2 & 3) * 0.5;
+            if ((EPI == 1 || EPI == 4) && epi.add1) extra += __builtin_popcount(epi.m1 & 3) * 0.5;
+            if ((EPI == 1 || EPI == 4) && epi.add2) extra += __builtin_popcount(epi.m2 & 3) * 0.5;
             if (EPI == 3) extra += 1.0;
+            if (EPI == 4) extra += 0.5;  // the chained pass's output
         }
         kprof_set_bytes(half * nvec * (1.0 + extra));
-        KLN(EPI == 1 ? "ntt_fwd_pass2_moddown"
+        KLN(EPI == 4 ? "ntt_fwd_pass2_moddown_chain" : EPI == 1 ? "ntt_fwd_pass2_moddown"
                      : (EPI == 2 ? "ntt_fwd_pass2_rescale" : (EPI == 3 ? "ntt_fwd_pass2_moddown_rescale" : "ntt_fwd_pass2")),
             (k_ntt<H, COLS, true, false, 0, EPI, TWF>), grid, block, 0, s, vs, none, nullptr, T, pro, epi, pm);
     } else {
-        kprof_set_bytes(half * nvec);
-        KLN("ntt_inv_pass2", (k_ntt<H, COLS, true, true, 0, 0, TWF>), grid, block, 0, s, vs, first, nullptr, T, pro,
-            epi, pm);
+        if (!strided_only) {
+            kprof_set_bytes(half * nvec);
+            KLN("ntt_inv_pass2", (k_ntt<H, COLS, true, true, 0, 0, TWF>), grid, block, 0, s, vs, first, nullptr, T,
+                pro, epi, pm);
+        }
         kprof_set_bytes(half * nvec);
         KLN("ntt_inv_pass1", (k_ntt<H, COLS, false, true, 0, 0, 0>), grid, block, 0, s, vs, none, oscale, T, pro,
             epi, 0);
@@ -329,19 +392,20 @@ static void ntt_run(const DevTables &T, const VecSet &vs, const VecSet *src, boo
 
 template <int PRO, int EPI>
 static void ntt_dispatch(const DevTables &T, const VecSet &vs, bool inverse, int variant, hipStream_t s,
-                         const VecSet *src, const double *oscale, const NttPro &pro, const NttEpi &epi) {
+                         const VecSet *src, const double *oscale, const NttPro &pro, const NttEpi &epi,
+                         bool strided_only = false) {
     if (vs.count <= 0) return;
     int v = variant;
     if (v <= 0) v = g_ntt_tune[T.logN == 16 ? 1 : 0][bucket_of(vs.count)];
     if (v <= 0 || v > NTT_VARIANTS) v = 3;
     const int w = (v - 1) % 3, f = (v - 1) / 3;
 #define NTT_CASE(H, C0, C1, C2)                                                                            \
-    if (w == 0 && f == 0) ntt_run<H, C0, PRO, EPI, 0>(T, vs, src, inverse, oscale, pro, epi, s);           \
-    else if (w == 1 && f == 0) ntt_run<H, C1, PRO, EPI, 0>(T, vs, src, inverse, oscale, pro, epi, s);      \
-    else if (w == 2 && f == 0) ntt_run<H, C2, PRO, EPI, 0>(T, vs, src, inverse, oscale, pro, epi, s);      \
-    else if (w == 0) ntt_run<H, C0, PRO, EPI, 1>(T, vs, src, inverse, oscale, pro, epi, s);                \
-    else if (w == 1) ntt_run<H, C1, PRO, EPI, 1>(T, vs, src, inverse, oscale, pro, epi, s);                \
-    else ntt_run<H, C2, PRO, EPI, 1>(T, vs, src, inverse, oscale, pro, epi, s);
+    if (w == 0 && f == 0) ntt_run<H, C0, PRO, EPI, 0>(T, vs, src, inverse, oscale, pro, epi, s, strided_only);           \
+    else if (w == 1 && f == 0) ntt_run<H, C1, PRO, EPI, 0>(T, vs, src, inverse, oscale, pro, epi, s, strided_only);      \
+    else if (w == 2 && f == 0) ntt_run<H, C2, PRO, EPI, 0>(T, vs, src, inverse, oscale, pro, epi, s, strided_only);      \
+    else if (w == 0) ntt_run<H, C0, PRO, EPI, 1>(T, vs, src, inverse, oscale, pro, epi, s, strided_only);                \
+    else if (w == 1) ntt_run<H, C1, PRO, EPI, 1>(T, vs, src, inverse, oscale, pro, epi, s, strided_only);                \
+    else ntt_run<H, C2, PRO, EPI, 1>(T, vs, src, inverse, oscale, pro, epi, s, strided_only);
     if (T.logN == 16) {
         NTT_CASE(4, 4, 8, 16)
     } else if (T.logN == 12) {
@@ -351,15 +415,18 @@ static void ntt_dispatch(const DevTables &T, const VecSet &vs, bool inverse, int
 }
 
 void launch_ntt(const DevTables &T, const VecSet &vs, bool inverse, int variant, hipStream_t s,
-                const VecSet *src, const double *oscale) {
+                const VecSet *src, const double *oscale, bool strided_only) {
     const NttPro pro{};
     const NttEpi epi{};
-    ntt_dispatch<0, 0>(T, vs, inverse, variant, s, src, oscale, pro, epi);
+    if (strided_only && (!inverse || src)) throw std::invalid_argument("strided_only: in-place inverse only");
+    ntt_dispatch<0, 0>(T, vs, inverse, variant, s, src, oscale, pro, epi, strided_only);
 }
 
 void launch_ntt_fused(const DevTables &T, const VecSet &vs, const NttPro &pro, const NttEpi &epi, int variant,
                       hipStream_t s) {
     if (pro.kind == 1 && epi.kind == 2) ntt_dispatch<1, 2>(T, vs, false, variant, s, nullptr, nullptr, pro, epi);
+    else if (pro.kind == 0 && epi.kind == 1 && epi.chain)
+        ntt_dispatch<0, 4>(T, vs, false, variant, s, nullptr, nullptr, pro, epi);
     else if (pro.kind == 0 && epi.kind == 1) ntt_dispatch<0, 1>(T, vs, false, variant, s, nullptr, nullptr, pro, epi);
     else if (pro.kind == 1 && epi.kind == 0) ntt_dispatch<1, 0>(T, vs, false, variant, s, nullptr, nullptr, pro, epi);
     else if (pro.kind == 0 && epi.kind == 2) ntt_dispatch<0, 2>(T, vs, false, variant, s, nullptr, nullptr, pro, epi);
