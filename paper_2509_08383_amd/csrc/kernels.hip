@@ -721,7 +721,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BETA >= 3 ?
 // and the NR + 1 gathers of c0 are issued together (no branch between them), then the
 // products run.
 template <int NR, int BETA>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BETA >= 3 && NR >= 7 ? 2 : 3))) void k_inner_product_rot_reg(DevTables T, const double *__restrict__ ext,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_inner_product_rot_reg(DevTables T, const double *__restrict__ ext,
                                                                long long esb, long long esj,
                                                                double *__restrict__ acc0, double *__restrict__ acc1,
                                                                long long astride, RotSet rs, int betaL,
@@ -744,9 +744,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BETA >= 3 &
         for (int j = 0; j < BETA; ++j) key_pair(rs.key[r], T, betaL, pt, j, T.N, x, k0[r][j], k1[r][j]);
     }
     const bool wsum = rs.c0 && t <= rs.lq;
-    // rotations whose gathers are in flight together: 7 x 3 keys held and the running sum
-    // kept for the c0 fold take 2 waves per SIMD, which leaves room for all 7 at once
-    constexpr int RCW = BETA >= 3 && NR >= 7 ? 7 : 3;
+    // rotations whose gathers are in flight together: with 7 x 3 keys held, chunks of 5
+    // fit 3 waves per SIMD without spilling (160 VGPRs)
+    constexpr int RCW = BETA >= 3 && NR >= 7 ? 5 : 3;
     constexpr int RC = NR > RCW ? RCW : NR;
     const int oj = own_digit(rs.own, t);
     for (int ct = 0; ct < cnt; ++ct) {
