@@ -442,18 +442,19 @@ struct Exec {
     // acc_out (optional): the key-product accumulators [cnt][2][next] go there (and stay
     // after the call) instead of to workspace; md_poly1: the ModDown and the output cover
     // polynomial 1 only (polynomial 0's accumulator is left in acc_out).
-    // d_half: [cnt][l+1][N] holding the first inverse-NTT pass of d (written by the
-    // previous call's chain_out), used in place for the ModUp input; chain_out (with
-    // md_poly1): the output polynomial's first inverse-NTT pass goes there as well
+    // dbuf: [cnt][l+1][N] for the coefficient-domain digits (the ModUp input) instead of
+    // workspace; with dbuf_half it already holds the first inverse-NTT pass of d (written
+    // by the previous call's chain_out) and only the second runs, in place.  chain_out
+    // (with md_poly1): the output polynomial's first inverse-NTT pass goes there as well
     void keyswitch(const double *d, long long dstride, int cnt, int l, int kidx, double *out, long long ostride,
                    Addend a1 = Addend{nullptr, 0, 0, 0}, Addend a2 = Addend{nullptr, 0, 0, 0},
                    const RotSet *rot = nullptr, bool mrescale = false, const double *ext_pre = nullptr,
-                   double *acc_out = nullptr, bool md_poly1 = false, double *d_half = nullptr,
-                   double *chain_out = nullptr) {
+                   double *acc_out = nullptr, bool md_poly1 = false, double *dbuf = nullptr,
+                   bool dbuf_half = false, double *chain_out = nullptr) {
         const int A = C->alpha, next = l + 1 + A, beta = (l + 1 + A - 1) / A;
         const long long N = C->N;
         const size_t m = C->arena.mark();
-        double *dcoef = ext_pre ? nullptr : d_half ? d_half : alloc_d((size_t)cnt * (l + 1) * N);
+        double *dcoef = ext_pre ? nullptr : dbuf ? dbuf : alloc_d((size_t)cnt * (l + 1) * N);
         double *ext = ext_pre ? const_cast<double *>(ext_pre) : alloc_d((size_t)cnt * beta * next * N);
         double *acc = acc_out ? acc_out : alloc_d((size_t)cnt * 2 * next * N);
         double *conv = alloc_d((size_t)cnt * 2 * (l + 1) * N);
@@ -461,7 +462,7 @@ struct Exec {
             // coefficient-domain digits, already scaled by Qhat_i^-1 (folded into N^-1)
             VecSet vd{dcoef, cnt * (l + 1), l + 1, (long long)(l + 1) * N, nullptr, nullptr};
             const VecSet vsrc{const_cast<double *>(d), cnt * (l + 1), l + 1, dstride, nullptr, nullptr};
-            if (d_half) launch_ntt(T, vd, true, C->ntt_variant, s, nullptr, C->mu_scale[l], true);
+            if (dbuf_half) launch_ntt(T, vd, true, C->ntt_variant, s, nullptr, C->mu_scale[l], true);
             else launch_ntt(T, vd, true, C->ntt_variant, s, &vsrc, C->mu_scale[l]);
             ModUpDigits dg{};
             for (int j = 0; j < beta; ++j) {
@@ -574,13 +575,29 @@ struct Exec {
         for (int c = 0; c < a.cnt; ++c) o.scale[c] = (a.scale[c] * b.scale[bmap ? (*bmap)[c] : c]) / (double)C->q[l];
         const size_t m = C->arena.mark();
         double *t = alloc_d((size_t)a.cnt * 3 * (l + 1) * N);
+        // the key switch's ModUp input: the first inverse-NTT pass of d2, run by the
+        // tensor launch itself on the blocks it forms
+        double *dc = alloc_d((size_t)a.cnt * (l + 1) * N);
         const int *dmap = bmap ? C->pool.push(*bmap) : nullptr;
-        if (go())
-            launch_tensor(T, t, t + (l + 1) * N, t + 2 * (l + 1) * N, 3LL * (l + 1) * N, a.d, b.d,
-                          2LL * a.cap * N, 2LL * b.cap * N, dmap, (long long)a.cap * N, (long long)b.cap * N,
-                          a.cnt, l + 1, s);
+        if (go()) {
+            NttPro pro{};
+            pro.kind = 2;
+            pro.ta = a.d;
+            pro.tb = b.d;
+            pro.ta_ct = 2LL * a.cap * N;
+            pro.tb_ct = 2LL * b.cap * N;
+            pro.ta_poly = (long long)a.cap * N;
+            pro.tb_poly = (long long)b.cap * N;
+            pro.tmap = dmap;
+            pro.td = t;
+            pro.td_ct = 3LL * (l + 1) * N;
+            pro.td_poly = (long long)(l + 1) * N;
+            launch_tensor_intt(T, VecSet{dc, a.cnt * (l + 1), l + 1, (long long)(l + 1) * N, nullptr, nullptr}, pro,
+                               C->ntt_variant, s);
+        }
         keyswitch(t + 2 * (l + 1) * N, 3LL * (l + 1) * N, a.cnt, l, 0, o.d, (long long)o.cap * N,
-                  Addend{t, 3LL * (l + 1) * N, (long long)(l + 1) * N, 3}, Addend{nullptr, 0, 0, 0}, nullptr, true);
+                  Addend{t, 3LL * (l + 1) * N, (long long)(l + 1) * N, 3}, Addend{nullptr, 0, 0, 0}, nullptr, true,
+                  nullptr, nullptr, false, dc, true);
         C->arena.release(m);
         return o;
     }
@@ -816,8 +833,9 @@ struct Exec {
             // accumulator of polynomial 0, two buffers used in turn), so only c1 takes a
             // ModDown per step and c0 one at the end; the first step reads a, the others
             // update o's c1 in place
-            // Each step but the last also writes the first inverse-NTT pass of its output
-            // c1 (chained into its ModDown epilogue) to dhalf, the next step's ModUp input.
+            // dhalf holds every step's ModUp input; each step but the last also writes the
+            // first inverse-NTT pass of its output c1 there (chained into its ModDown
+            // epilogue, after its own ModUp has read it).
             const int next = a.level + 1 + C->alpha;
             double *accb[2] = {alloc_d((size_t)a.cnt * 2 * next * C->N), alloc_d((size_t)a.cnt * 2 * next * C->N)};
             double *dhalf = alloc_d((size_t)a.cnt * (a.level + 1) * C->N);
@@ -825,7 +843,7 @@ struct Exec {
                 const size_t m = C->arena.mark();
                 const bool last = k + 1 == steps.size();
                 rotsum_step_carried(k == 0 ? a : o, o, steps[k], k == 0 ? nullptr : accb[(k - 1) & 1], accb[k & 1],
-                                    last, k == 0 ? nullptr : dhalf, last ? nullptr : dhalf);
+                                    last, dhalf, k > 0, last ? nullptr : dhalf);
                 C->arena.release(m);
             }
             return o;
@@ -876,7 +894,7 @@ struct Exec {
     // next X0; c1 takes its ModDown:  y1 = c1 + MD_1.  The last step takes the ModDown of
     // both polynomials, y0 = MD(X0) = c0 + sum of every step's rotations.
     void rotsum_step_carried(const Bt &x, const Bt &y, const std::vector<int> &amounts, const double *x0,
-                             double *acc, bool last, double *d_half, double *chain_out) {
+                             double *acc, bool last, double *dbuf, bool dbuf_half, double *chain_out) {
         const int l = x.level, next = l + 1 + C->alpha;
         const long long N = C->N;
         REQUIRE(!amounts.empty() && (int)amounts.size() <= kMaxHoist, HE_EINVAL, "hoisted step size");
@@ -903,7 +921,7 @@ struct Exec {
         }
         keyswitch(x.d + (long long)x.cap * N, 2LL * x.cap * N, x.cnt, l, -1, y.d, (long long)y.cap * N,
                   Addend{nullptr, 0, 0, 0}, Addend{x.d, 2LL * x.cap * N, (long long)x.cap * N, 2}, &rs, false,
-                  nullptr, acc, !last, d_half, chain_out);
+                  nullptr, acc, !last, dbuf, dbuf_half, chain_out);
     }
 
     Bt power(const Bt &y, int p) {

@@ -92,11 +92,20 @@ void launch_ntt(const DevTables &T, const VecSet &vs, bool inverse, int variant,
 
 // Forward-NTT prologue: kind 1 loads, for vector (g, r), the centred lift of the
 // coefficient-domain word last[g * l_g + j] (modulo ql) reduced modulo prime(r).
+// Inverse-NTT prologue (first pass): kind 2 forms, for vector (g, r) = (ciphertext,
+// limb), the tensor of ciphertexts a (ta + g ta_ct) and b (tb + tmap[g] tb_ct, tmap
+// null: g), polynomial 1 at + ta_poly / + tb_poly: d0 = a0 b0, d1 = a0 b1 + a1 b0,
+// d2 = a1 b1 at td + g td_ct + k td_poly + r N; d2 is the word the pass transforms.
 struct NttPro {
     int kind;
     const double *last;
     long long l_g;
     double ql;
+    const double *ta, *tb;
+    long long ta_ct, tb_ct, ta_poly, tb_poly;
+    const int *tmap;
+    double *td;
+    long long td_ct, td_poly;
 };
 // Forward-NTT epilogue on the transformed word w of vector (g, r), position j:
 //   kind 1 (ModDown): out = (in - w) * cst[r] + [m1] add1 + [m2] add2
@@ -131,6 +140,9 @@ struct NttEpi {
 };
 void launch_ntt_fused(const DevTables &T, const VecSet &vs, const NttPro &pro, const NttEpi &epi, int variant,
                       hipStream_t s);
+// the tensor of pro (kind 2) and the first pass of the inverse NTT of its d2 into vs
+// (the second pass is launch_ntt(..., strided_only) on vs)
+void launch_tensor_intt(const DevTables &T, const VecSet &vs, const NttPro &pro, int variant, hipStream_t s);
 void launch_add(const DevTables &T, const VecSet &out, const VecSet &a, const VecSet &b, int sign,
                 hipStream_t s);
 void launch_copy(const DevTables &T, const VecSet &out, const VecSet &a, hipStream_t s);
@@ -144,9 +156,6 @@ void launch_sub_mul_map(const DevTables &T, const VecSet &out, const VecSet &a, 
                         const int *bmap, int bdiv, hipStream_t s);
 void launch_sum_groups(const DevTables &T, const VecSet &out, const VecSet &in, const int *first,
                        const int *cnt, int gdiv, hipStream_t s);
-void launch_tensor(const DevTables &T, double *d0, double *d1, double *d2, long long dstride,
-                   const double *a, const double *b, long long astride, long long bstride,
-                   const int *bmap, long long apoly, long long bpoly, int cnt, int limbs, hipStream_t s);
 void launch_automorph(const DevTables &T, const VecSet &out, const VecSet &in, uint64_t galois,
                       hipStream_t s);
 struct ModUpDigits {

@@ -186,31 +186,6 @@ void launch_sum_groups(const DevTables &T, const VecSet &out, const VecSet &in, 
     KL("k_sum_groups", k_sum_groups, ew_grid(T, out.count), dim3(256), 0, s, out, in, first, cnt, gdiv, T);
 }
 
-// d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1 per (ciphertext, limb)
-__global__ void k_tensor(DevTables T, double *d0, double *d1, double *d2, long long dstride,
-                         const double *a, const double *b, long long astride, long long bstride,
-                         const int *bmap, long long apoly, long long bpoly, int limbs) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= T.N) return;
-    const int ct = blockIdx.y / limbs, li = blockIdx.y % limbs;
-    const double p = T.p[li], pinv = T.pinv[li];
-    const int cb = bmap ? bmap[ct] : ct;
-    const long long o = (long long)li * T.N + x;
-    const double *A = a + ct * astride, *B = b + cb * bstride;
-    const double a0 = A[o], a1 = A[apoly + o], b0 = B[o], b1 = B[bpoly + o];
-    d0[ct * dstride + o] = canon(mm(a0, b0, p, pinv), p, pinv);
-    d1[ct * dstride + o] = canon(mm(a0, b1, p, pinv) + mm(a1, b0, p, pinv), p, pinv);
-    d2[ct * dstride + o] = canon(mm(a1, b1, p, pinv), p, pinv);
-}
-void launch_tensor(const DevTables &T, double *d0, double *d1, double *d2, long long dstride,
-                   const double *a, const double *b, long long astride, long long bstride,
-                   const int *bmap, long long apoly, long long bpoly, int cnt, int limbs, hipStream_t s) {
-    if (cnt <= 0) return;
-    kprof_set_bytes(8.0 * T.N * cnt * limbs * 7);  // 4 words in, 3 out
-    KL("k_tensor", k_tensor, dim3((T.N + 255) / 256, cnt * limbs), dim3(256), 0, s, T, d0, d1,
-                       d2, dstride, a, b, astride, bstride, bmap, apoly, bpoly, limbs);
-}
-
 // NTT-domain Galois automorphism X -> X^g: out[j] = in[j'] with
 // 2 bitrev(j') + 1 = (2 bitrev(j) + 1) g mod 2N.  2N divides 2^32, so the
 // product is taken modulo 2^32 and masked.

@@ -274,7 +274,26 @@ __global__ __launch_bounds__(COLS *(1 << H)) void k_ntt(VecSet vs, VecSet src, c
         }
     } else {
         // phase B first (low bits), stages descending
-        if (PASS2) {
+        if (PASS2 && PRO == 2) {
+            // the tensor of the two ciphertexts at this limb; d2 is transformed
+            const double *A = pro.ta + (long long)g_ * pro.ta_ct + (long long)r_ * NN;
+            const double *B = pro.tb + (long long)(pro.tmap ? pro.tmap[g_] : g_) * pro.tb_ct + (long long)r_ * NN;
+            double *D = pro.td + (long long)g_ * pro.td_ct + (long long)r_ * NN;
+#pragma unroll
+            for (int i = 0; i < EW; ++i) {
+                const int idx = tid + NT * i, k = idx % SUB, cc = idx / SUB;
+                const long long j = gidx(cc, k);
+                const double a0 = A[j], a1 = A[pro.ta_poly + j], b0 = B[j], b1 = B[pro.tb_poly + j];
+                const double d2 = ncanon(nmm(a1, b1, p, pinv), p, pinv);
+                D[j] = ncanon(nmm(a0, b0, p, pinv), p, pinv);
+                D[pro.td_poly + j] = ncanon(nmm(a0, b1, p, pinv) + nmm(a1, b0, p, pinv), p, pinv);
+                D[2 * pro.td_poly + j] = d2;
+                tile[lds(cc, k)] = d2;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[e] = tile[lds(c, th * E + e)];
+        } else if (PASS2) {
 #pragma unroll
             for (int i = 0; i < EW; ++i) {
                 const int idx = tid + NT * i, k = idx % SUB, cc = idx / SUB;
@@ -348,9 +367,10 @@ void set_ntt_tuning(int logN, int bucket, int variant) {
     if (bucket >= 0 && bucket < 8) g_ntt_tune[logN == 16 ? 1 : 0][bucket] = variant;
 }
 
+// passes (inverse): bit 0 the first (contiguous-block) pass, bit 1 the second
 template <int H, int COLS, int PRO, int EPI, int TWF>
 static void ntt_run(const DevTables &T, const VecSet &vs, const VecSet *src, bool inverse, const double *oscale,
-                    const NttPro &pro, const NttEpi &epi, hipStream_t s, bool strided_only) {
+                    const NttPro &pro, const NttEpi &epi, hipStream_t s, int passes) {
     constexpr int SUB = 1 << (2 * H), NT = COLS * (1 << H);
     dim3 grid(SUB / COLS, vs.count), block(NT);
     const VecSet none{nullptr, 0, 1, 0, nullptr, nullptr};
@@ -379,11 +399,13 @@ static void ntt_run(const DevTables &T, const VecSet &vs, const VecSet *src, boo
                      : (EPI == 2 ? "ntt_fwd_pass2_rescale" : (EPI == 3 ? "ntt_fwd_pass2_moddown_rescale" : "ntt_fwd_pass2")),
             (k_ntt<H, COLS, true, false, 0, EPI, TWF>), grid, block, 0, s, vs, none, nullptr, T, pro, epi, pm);
     } else {
-        if (!strided_only) {
-            kprof_set_bytes(half * nvec);
-            KLN("ntt_inv_pass2", (k_ntt<H, COLS, true, true, 0, 0, TWF>), grid, block, 0, s, vs, first, nullptr, T,
-                pro, epi, pm);
+        if (passes & 1) {
+            // the tensor prologue reads 4 words and writes 3 besides the pass's output
+            kprof_set_bytes(half * nvec * (PRO == 2 ? 8.0 : 1.0));
+            KLN(PRO == 2 ? "ntt_inv_pass2_tensor" : "ntt_inv_pass2", (k_ntt<H, COLS, true, true, PRO, 0, TWF>), grid,
+                block, 0, s, vs, first, nullptr, T, pro, epi, pm);
         }
+        if (!(passes & 2)) return;
         kprof_set_bytes(half * nvec);
         KLN("ntt_inv_pass1", (k_ntt<H, COLS, false, true, 0, 0, 0>), grid, block, 0, s, vs, none, oscale, T, pro,
             epi, 0);
@@ -393,19 +415,19 @@ static void ntt_run(const DevTables &T, const VecSet &vs, const VecSet *src, boo
 template <int PRO, int EPI>
 static void ntt_dispatch(const DevTables &T, const VecSet &vs, bool inverse, int variant, hipStream_t s,
                          const VecSet *src, const double *oscale, const NttPro &pro, const NttEpi &epi,
-                         bool strided_only = false) {
+                         int passes = 3) {
     if (vs.count <= 0) return;
     int v = variant;
     if (v <= 0) v = g_ntt_tune[T.logN == 16 ? 1 : 0][bucket_of(vs.count)];
     if (v <= 0 || v > NTT_VARIANTS) v = 3;
     const int w = (v - 1) % 3, f = (v - 1) / 3;
 #define NTT_CASE(H, C0, C1, C2)                                                                            \
-    if (w == 0 && f == 0) ntt_run<H, C0, PRO, EPI, 0>(T, vs, src, inverse, oscale, pro, epi, s, strided_only);           \
-    else if (w == 1 && f == 0) ntt_run<H, C1, PRO, EPI, 0>(T, vs, src, inverse, oscale, pro, epi, s, strided_only);      \
-    else if (w == 2 && f == 0) ntt_run<H, C2, PRO, EPI, 0>(T, vs, src, inverse, oscale, pro, epi, s, strided_only);      \
-    else if (w == 0) ntt_run<H, C0, PRO, EPI, 1>(T, vs, src, inverse, oscale, pro, epi, s, strided_only);                \
-    else if (w == 1) ntt_run<H, C1, PRO, EPI, 1>(T, vs, src, inverse, oscale, pro, epi, s, strided_only);                \
-    else ntt_run<H, C2, PRO, EPI, 1>(T, vs, src, inverse, oscale, pro, epi, s, strided_only);
+    if (w == 0 && f == 0) ntt_run<H, C0, PRO, EPI, 0>(T, vs, src, inverse, oscale, pro, epi, s, passes);           \
+    else if (w == 1 && f == 0) ntt_run<H, C1, PRO, EPI, 0>(T, vs, src, inverse, oscale, pro, epi, s, passes);      \
+    else if (w == 2 && f == 0) ntt_run<H, C2, PRO, EPI, 0>(T, vs, src, inverse, oscale, pro, epi, s, passes);      \
+    else if (w == 0) ntt_run<H, C0, PRO, EPI, 1>(T, vs, src, inverse, oscale, pro, epi, s, passes);                \
+    else if (w == 1) ntt_run<H, C1, PRO, EPI, 1>(T, vs, src, inverse, oscale, pro, epi, s, passes);                \
+    else ntt_run<H, C2, PRO, EPI, 1>(T, vs, src, inverse, oscale, pro, epi, s, passes);
     if (T.logN == 16) {
         NTT_CASE(4, 4, 8, 16)
     } else if (T.logN == 12) {
@@ -419,7 +441,12 @@ void launch_ntt(const DevTables &T, const VecSet &vs, bool inverse, int variant,
     const NttPro pro{};
     const NttEpi epi{};
     if (strided_only && (!inverse || src)) throw std::invalid_argument("strided_only: in-place inverse only");
-    ntt_dispatch<0, 0>(T, vs, inverse, variant, s, src, oscale, pro, epi, strided_only);
+    ntt_dispatch<0, 0>(T, vs, inverse, variant, s, src, oscale, pro, epi, strided_only ? 2 : 3);
+}
+
+void launch_tensor_intt(const DevTables &T, const VecSet &vs, const NttPro &pro, int variant, hipStream_t s) {
+    if (pro.kind != 2) throw std::invalid_argument("launch_tensor_intt: tensor prologue expected");
+    ntt_dispatch<2, 0>(T, vs, true, variant, s, nullptr, nullptr, pro, NttEpi{}, 1);
 }
 
 void launch_ntt_fused(const DevTables &T, const VecSet &vs, const NttPro &pro, const NttEpi &epi, int variant,
