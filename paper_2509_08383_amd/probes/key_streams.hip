@@ -1,7 +1,10 @@
 // Probe of the HBM read rate the rotation key products can reach: S key streams per
 // limb (each word a uint2 low part and a uint32 high part, as the packed keys), read once
 // per position, in the library's row layout (one row per rotation and digit) and in a
-// layout where the S rows of each 64-position wave block are contiguous; and a 1 GiB copy.
+// layout where the S rows of each 64-position wave block are contiguous; the row layout
+// with 2-byte high parts on limbs 1..29 (the 40-bit primes of the top level of the
+// secure set: a lane reads the dword of positions x and x ^ 1 and takes its half, as
+// the library does); and a 1 GiB copy.
 // Every access is in bounds: rows x N words, N = 65536, S <= 42, 40 limbs.
 //   hipcc --offload-arch=gfx950 -O3 -Xclang -target-feature -Xclang -packed-fp32-ops \
 //       paper_2509_08383_amd/probes/key_streams.hip -o /tmp/key_streams && /tmp/key_streams
@@ -43,6 +46,25 @@ __global__ __launch_bounds__(256) void blocked(const uint2 *lo, const uint32_t *
     }
     out[(long long)t * N + x] = s;
 }
+// rows, with 2-byte high parts on limbs [nlo, nhi]: the high row of such a limb holds N/2
+// dwords (two positions each)
+template <int S>
+__global__ __launch_bounds__(256) void mixed(const uint2 *lo, const uint32_t *hi, double *out, int N, int limbs,
+                                             int nlo, int nhi) {
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    const int t = blockIdx.y;
+    if (x >= N || t >= limbs) return;
+    const bool nr = t >= nlo && t <= nhi;
+    double s = 0;
+#pragma unroll
+    for (int r = 0; r < S; ++r) {
+        const long long row = ((long long)t * S + r) * N;
+        const uint2 l = lo[row + x];
+        const uint32_t h = hi[row + (nr ? (x >> 1) : x)] >> (nr ? 16u * ((unsigned)x & 1u) : 0u);
+        s += (double)l.x + (double)l.y + (double)h;
+    }
+    out[(long long)t * N + x] = s;
+}
 __global__ void copyk(const double4 *a, double4 *b, long long n) {
     long long i = (long long)blockIdx.x * 256 + threadIdx.x;
     if (i < n) b[i] = a[i];
@@ -53,7 +75,8 @@ int run(int limbs, const uint2 *lo, const uint32_t *hi, double *out, int N) {
     hipEvent_t a, b;
     CHK(hipEventCreate(&a)); CHK(hipEventCreate(&b));
     dim3 grid(N / 256, limbs);
-    float best1 = 1e9, best2 = 1e9;
+    float best1 = 1e9, best2 = 1e9, best3 = 1e9;
+    const int nlo = 1, nhi = limbs >= 30 ? 29 : limbs - 1;
     for (int it = 0; it < 6; ++it) {
         CHK(hipEventRecord(a));
         hipLaunchKernelGGL(rows<S>, grid, dim3(256), 0, 0, lo, hi, out, N, limbs);
@@ -63,10 +86,18 @@ int run(int limbs, const uint2 *lo, const uint32_t *hi, double *out, int N) {
         hipLaunchKernelGGL(blocked<S>, grid, dim3(256), 0, 0, lo, hi, out, N, limbs);
         CHK(hipEventRecord(b)); CHK(hipEventSynchronize(b));
         CHK(hipEventElapsedTime(&ms, a, b)); if (it) best2 = ms < best2 ? ms : best2;
+        CHK(hipEventRecord(a));
+        hipLaunchKernelGGL(mixed<S>, grid, dim3(256), 0, 0, lo, hi, out, N, limbs, nlo, nhi);
+        CHK(hipEventRecord(b)); CHK(hipEventSynchronize(b));
+        CHK(hipEventElapsedTime(&ms, a, b)); if (it) best3 = ms < best3 ? ms : best3;
     }
     const double bytes = (double)limbs * N * (S * 12.0 + 8.0);
-    printf("S=%2d limbs=%d  rows: %.1f us %.0f GB/s   blocked: %.1f us %.0f GB/s\n", S, limbs, best1 * 1e3,
-           bytes / best1 / 1e6, best2 * 1e3, bytes / best2 / 1e6);
+    const int nn = nhi - nlo + 1;
+    const double bytes3 = (double)N * (limbs * (S * 12.0 + 8.0) - nn * S * 2.0);
+    printf("S=%2d limbs=%d  rows: %.1f us %.0f GB/s   blocked: %.1f us %.0f GB/s   5-byte rows on %d limbs: %.1f us "
+           "%.0f GB/s\n",
+           S, limbs, best1 * 1e3, bytes / best1 / 1e6, best2 * 1e3, bytes / best2 / 1e6, nn, best3 * 1e3,
+           bytes3 / best3 / 1e6);
     return 0;
 }
 
