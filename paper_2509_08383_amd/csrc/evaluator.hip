@@ -470,13 +470,15 @@ struct Exec {
                 dg.lo[j] = j * A;
                 dg.dl[j] = std::min(A, l + 1 - j * A);
             }
-            // the digits' own limbs are not copied: the key products read them from d
-            launch_modup(T, dcoef, (long long)(l + 1) * N, ext, (long long)beta * next * N, (long long)next * N, d,
-                         dstride, cnt, beta, next, C->ext_prime[l], dg, s, true);
-            // every digit's converted limbs in one transform
+            // the basis conversion of every digit inside the first pass of the converted
+            // limbs' forward NTT; the digits' own limbs are neither copied nor transformed
+            // (the key products read them from d)
+            launch_modup_ntt(T, dcoef, (long long)(l + 1) * N, ext, (long long)beta * next * N, (long long)next * N,
+                             cnt, beta, next, C->ext_prime[l], dg, s);
             const int nd = C->ndall[l];
-            launch_ntt(T, VecSet{ext, cnt * nd, nd, (long long)beta * next * N, C->ndall_slot[l], C->ndall_prime[l]},
-                       false, C->ntt_variant, s);
+            launch_ntt_fwd_pass2(
+                T, VecSet{ext, cnt * nd, nd, (long long)beta * next * N, C->ndall_slot[l], C->ndall_prime[l]},
+                C->ntt_variant, s);
         }
         if (go()) {
             const OwnSrc own = ext_pre ? OwnSrc{} : OwnSrc{d, dstride, A, l};

@@ -140,6 +140,8 @@ struct NttEpi {
 };
 void launch_ntt_fused(const DevTables &T, const VecSet &vs, const NttPro &pro, const NttEpi &epi, int variant,
                       hipStream_t s);
+// the second pass of the forward NTT alone (vs holds the first pass's output)
+void launch_ntt_fwd_pass2(const DevTables &T, const VecSet &vs, int variant, hipStream_t s);
 // the tensor of pro (kind 2) and the first pass of the inverse NTT of its d2 into vs
 // (the second pass is launch_ntt(..., strided_only) on vs)
 void launch_tensor_intt(const DevTables &T, const VecSet &vs, const NttPro &pro, int variant, hipStream_t s);
@@ -166,6 +168,12 @@ struct ModUpDigits {
 void launch_modup(const DevTables &T, const double *v, long long vstride, double *ext, long long esb,
                   long long esj, const double *dntt, long long nstride, int cnt, int beta, int next,
                   const int *ext_prime, const ModUpDigits &dg, hipStream_t s, bool skip_own = false);
+// ModUp of every digit (as launch_modup with skip_own) fused with the first pass of the
+// forward NTT of the converted slots; launch_ntt_fwd_pass2 over those slots completes
+// the transform
+void launch_modup_ntt(const DevTables &T, const double *v, long long vstride, double *ext, long long esb,
+                      long long esj, int cnt, int beta, int next, const int *ext_prime, const ModUpDigits &dg,
+                      hipStream_t s);
 // Where the key products read a digit's own limbs: with p set, limb t <= l of digit
 // t / alpha (the NTT-domain input word itself) is read at p + ct * ct_stride + t N
 // instead of from the extended digits; p null: every limb from the extended digits.
@@ -212,6 +220,26 @@ void launch_lt_giants(const DevTables &T, const LtGiants &g, int cnt, int limbs,
 // out = sum_t k_t x_t with integer constants (residues kres[(t cnt + c) limbs + i])
 void launch_lincomb(const DevTables &T, double *out, long long oct, long long opoly, const LtTerms &tm,
                     const double *kres, int cnt, int limbs, hipStream_t s);
+
+// Basis-conversion grids are one-dimensional and XCD-aware: workgroup b runs on XCD
+// b mod 8, and the target blocks of one coefficient block (which all read the same
+// input words) are consecutive workgroups of one XCD, so the input is fetched from
+// HBM once and re-read from that XCD's L2.  conv_idx returns false for padding
+// workgroups.
+struct ConvIdx {
+    int tb, cb, z;
+};
+__device__ __forceinline__ bool conv_idx(int b, int ntb, int cblk, int nz, ConvIdx &o) {
+    const int slot = b >> 3, c = (slot / ntb) * 8 + (b & 7);
+    if (c >= cblk * nz) return false;
+    o.tb = slot % ntb;
+    o.cb = c % cblk;
+    o.z = c / cblk;
+    return true;
+}
+inline dim3 conv_grid(int ntb, int cblk, int nz) { return dim3(8 * ntb * ((cblk * nz + 7) / 8)); }
+// smallest compiled digit length that holds dl words
+inline int digit_len(int dl) { return dl <= 4 ? 4 : dl <= 8 ? 8 : dl <= 10 ? 10 : dl <= 12 ? 12 : 16; }
 
 // rotations of one hoisted rotate-and-sum step: key and Galois element of each
 constexpr int kMaxHoist = 15;

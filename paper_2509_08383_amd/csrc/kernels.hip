@@ -341,20 +341,7 @@ void launch_lincomb(const DevTables &T, double *out, long long oct, long long op
 // lane reads the same word: a broadcast); terms a >= dl and own-digit targets carry
 // zero constants, so the DL products of a target run without branches as independent
 // chains.  |sum| <= DL (p/2 + 2^44) < 2^52 for DL <= 16.
-// Basis-conversion grids are one-dimensional and XCD-aware: workgroup b runs on XCD
-// b mod 8, and the target blocks of one coefficient block (which all read the same
-// input words) are consecutive workgroups of one XCD, so the input is fetched from
-// HBM once and re-read from that XCD's L2.  Returns false for padding workgroups.
-struct ConvIdx { int tb, cb, z; };
-DEV bool conv_idx(int b, int ntb, int cblk, int nz, ConvIdx &o) {
-    const int slot = b >> 3, c = (slot / ntb) * 8 + (b & 7);
-    if (c >= cblk * nz) return false;
-    o.tb = slot % ntb;
-    o.cb = c % cblk;
-    o.z = c / cblk;
-    return true;
-}
-static dim3 conv_grid(int ntb, int cblk, int nz) { return dim3(8 * ntb * ((cblk * nz + 7) / 8)); }
+// (Basis-conversion grids: conv_idx / conv_grid in he_internal.h.)
 
 template <int DL, int TB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_modup(DevTables T, const double *__restrict__ v, long long vstride,
@@ -418,9 +405,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         }
     }
 }
-
-// smallest compiled digit length that holds dl words
-static int digit_len(int dl) { return dl <= 4 ? 4 : dl <= 8 ? 8 : dl <= 10 ? 10 : dl <= 12 ? 12 : 16; }
 
 template <int TB>
 static void modup_tb(int DL, int cblk, int nz, hipStream_t s, const DevTables &T, const double *v, long long vstride,

@@ -352,6 +352,140 @@ __global__ __launch_bounds__(COLS *(1 << H)) void k_ntt(VecSet vs, VecSet src, c
     }
 }
 
+// ModUp fused into the first pass of the forward NTT of the extended digits.  For
+// digit j of ciphertext ct the converted slots are t in [0, lo) u [lo + dl, next); the
+// k-th of them is t = k < lo ? k : k + dl.  A workgroup takes COLS columns of the
+// first pass (positions c + SUB k, the strided sub-problems) of one (ct, j) and TB
+// consecutive converted slots: each thread loads the dl coefficient-domain digit words
+// v_a of its E positions once, centres them, accumulates sum_a v~_a [Qhat_a]_{prime(t)}
+// for its TB targets (the basis conversion, as k_modup), and runs the pass's stages on
+// each target in turn, storing the pass's output; the second pass is the ordinary one.
+// The arithmetic is that of k_modup followed by the first pass, word for word.  The
+// grid is XCD-aware as the other basis conversions (target blocks of one column block
+// consecutive on one XCD, so the digit words are re-read from its L2).
+template <int H, int COLS, int DL, int TB>
+__global__ __launch_bounds__(COLS *(1 << H)) void k_modup_ntt(DevTables T, const double *__restrict__ v,
+                                                               long long vstride, double *__restrict__ ext,
+                                                               long long esb, long long esj, int beta, int next,
+                                                               const int *__restrict__ ext_prime, ModUpDigits dg,
+                                                               int ntb, int cblk, int nz) {
+    constexpr int R = 2 * H, E = 1 << H, TPS = 1 << H, SUB = 1 << R, NT = COLS * TPS;
+    constexpr int NN = SUB * SUB, S2 = SUB + SUB / E, NW = (1 << H) - 1;
+    __shared__ double tile[COLS * S2];
+    __shared__ double sq[DL * TB];
+    __shared__ double sp[TB], si[TB];
+    __shared__ int spt[TB];
+    auto lds = [](int c, int k) { return (k + (k >> H)) * COLS + c; };
+    ConvIdx ix;
+    if (!conv_idx(blockIdx.x, ntb, cblk, nz, ix)) return;  // uniform over the workgroup
+    const int ct = ix.z / beta, j = ix.z - (ix.z / beta) * beta;
+    const int lo = dg.lo[j], dl = dg.dl[j], ncv = next - dl, k0 = ix.tb * TB;
+    if (k0 >= ncv) return;  // uniform
+    const int tid = threadIdx.x;
+    {
+        const double *qh = dg.qhat[j];
+        for (int i = tid; i < DL * TB; i += NT) {
+            const int a = i / TB, kk = k0 + (i - (i / TB) * TB);
+            const int t = kk < lo ? kk : kk + dl;
+            sq[i] = (a < dl && kk < ncv) ? qh[a * next + t] : 0.0;
+        }
+        if (tid < TB) {
+            const int kk = k0 + tid, t = kk < lo ? kk : kk + dl;
+            const int pt = ext_prime[kk < ncv ? t : 0];
+            sp[tid] = T.p[pt];
+            si[tid] = T.pinv[pt];
+            spt[tid] = pt;
+        }
+    }
+    __syncthreads();
+    const int c = tid % COLS, th = tid / COLS;
+    const long long col = (long long)ix.cb * COLS + c;
+    // the digit words as centred representatives, the conversion of every target
+    double acc[TB][E];
+#pragma unroll
+    for (int tt = 0; tt < TB; ++tt)
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc[tt][e] = 0.0;
+    const double *vp = v + ct * vstride + (long long)lo * NN + col;
+#pragma unroll
+    for (int a = 0; a < DL; ++a) {
+        if (a < dl) {
+            const double qa = T.p[lo + a];
+            double w[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const double u = vp[(long long)a * NN + (long long)SUB * (th + TPS * e)];
+                w[e] = u > 0.5 * (qa - 1.0) ? u - qa : u;
+            }
+#pragma unroll
+            for (int tt = 0; tt < TB; ++tt)
+#pragma unroll
+                for (int e = 0; e < E; ++e) acc[tt][e] += nmm(w[e], sq[a * TB + tt], sp[tt], si[tt]);
+        }
+    }
+#pragma unroll
+    for (int tt = 0; tt < TB; ++tt) {
+        const int kk = k0 + tt;
+        if (kk >= ncv) break;  // uniform
+        const int t = kk < lo ? kk : kk + dl;
+        const double p = sp[tt], pinv = si[tt];
+        const double *tw = T.tw + (long long)spt[tt] * NN;
+        double wa[NW], wb[NW];
+#pragma unroll
+        for (int sg = 0; sg < H; ++sg) {
+#pragma unroll
+            for (int g = 0; g < (1 << sg); ++g) {
+                wa[(1 << sg) - 1 + g] = tw[(1 << sg) + g];
+                wb[(1 << sg) - 1 + g] = tw[(1 << (H + sg)) + (th << sg) + g];
+            }
+        }
+        double x[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) x[e] = ncanon(acc[tt][e], p, pinv);
+        // phase A (high bits of k)
+#pragma unroll
+        for (int sg = 0; sg < H; ++sg) {
+            const int hd = E >> (sg + 1);
+#pragma unroll
+            for (int g = 0; g < (1 << sg); ++g) {
+                const double w = wa[(1 << sg) - 1 + g];
+#pragma unroll
+                for (int i = 0; i < hd; ++i) {
+                    const int e0 = g * 2 * hd + i, e1 = e0 + hd;
+                    const double u = nmm(x[e1], w, p, pinv);
+                    x[e1] = x[e0] - u;
+                    x[e0] = x[e0] + u;
+                }
+            }
+        }
+        if (tt > 0) __syncthreads();  // the previous target's tile reads are done
+#pragma unroll
+        for (int e = 0; e < E; ++e) tile[lds(c, th + TPS * e)] = nred(x[e], p, pinv);
+        __syncthreads();
+        // phase B (low bits of k)
+#pragma unroll
+        for (int e = 0; e < E; ++e) x[e] = tile[lds(c, th * E + e)];
+#pragma unroll
+        for (int sg = 0; sg < H; ++sg) {
+            const int hd = E >> (sg + 1);
+#pragma unroll
+            for (int g = 0; g < (1 << sg); ++g) {
+                const double w = wb[(1 << sg) - 1 + g];
+#pragma unroll
+                for (int i = 0; i < hd; ++i) {
+                    const int e0 = g * 2 * hd + i, e1 = e0 + hd;
+                    const double u = nmm(x[e1], w, p, pinv);
+                    x[e1] = x[e0] - u;
+                    x[e0] = x[e0] + u;
+                }
+            }
+        }
+        double *X = ext + ct * esb + j * esj + (long long)t * NN + col;
+#pragma unroll
+        for (int e = 0; e < E; ++e) X[(long long)SUB * (th * E + e)] = ncanon(x[e], p, pinv);
+    }
+}
+
 // tuned schedule per (log N, batch bucket); 0 = not tuned (use the default).  A
 // variant v = 1..NTT_VARIANTS is a workgroup width (the (v - 1) % 3 -th of three) and a
 // pass-2 twiddle form ((v - 1) / 3: 0 full table, 1 factored phase-B twiddles).
@@ -367,7 +501,8 @@ void set_ntt_tuning(int logN, int bucket, int variant) {
     if (bucket >= 0 && bucket < 8) g_ntt_tune[logN == 16 ? 1 : 0][bucket] = variant;
 }
 
-// passes (inverse): bit 0 the first (contiguous-block) pass, bit 1 the second
+// passes: bit 0 the first pass launched (forward: strided; inverse: contiguous blocks),
+// bit 1 the second
 template <int H, int COLS, int PRO, int EPI, int TWF>
 static void ntt_run(const DevTables &T, const VecSet &vs, const VecSet *src, bool inverse, const double *oscale,
                     const NttPro &pro, const NttEpi &epi, hipStream_t s, int passes) {
@@ -383,9 +518,12 @@ static void ntt_run(const DevTables &T, const VecSet &vs, const VecSet *src, boo
     const double half = 8.0 * SUB * SUB;
     const double nvec = vs.count, ngrp = (vs.count + vs.group - 1) / vs.group;
     if (!inverse) {
-        kprof_set_bytes(half * (PRO ? ngrp : nvec));
-        KLN(PRO ? "ntt_fwd_pass1_lift" : "ntt_fwd_pass1", (k_ntt<H, COLS, false, false, PRO, 0, 0>), grid, block, 0,
-            s, vs, first, nullptr, T, pro, epi, 0);
+        if (passes & 1) {
+            kprof_set_bytes(half * (PRO ? ngrp : nvec));
+            KLN(PRO ? "ntt_fwd_pass1_lift" : "ntt_fwd_pass1", (k_ntt<H, COLS, false, false, PRO, 0, 0>), grid, block,
+                0, s, vs, first, nullptr, T, pro, epi, 0);
+        }
+        if (!(passes & 2)) return;
         double extra = 0.0;
         if (EPI) {
             extra = 1.0;  // in
@@ -442,6 +580,42 @@ void launch_ntt(const DevTables &T, const VecSet &vs, bool inverse, int variant,
     const NttEpi epi{};
     if (strided_only && (!inverse || src)) throw std::invalid_argument("strided_only: in-place inverse only");
     ntt_dispatch<0, 0>(T, vs, inverse, variant, s, src, oscale, pro, epi, strided_only ? 2 : 3);
+}
+
+void launch_ntt_fwd_pass2(const DevTables &T, const VecSet &vs, int variant, hipStream_t s) {
+    ntt_dispatch<0, 0>(T, vs, false, variant, s, nullptr, nullptr, NttPro{}, NttEpi{}, 2);
+}
+
+template <int H, int COLS, int TB>
+static void modup_ntt_run(int DL, const DevTables &T, const double *v, long long vstride, double *ext, long long esb,
+                          long long esj, int cnt, int beta, int next, const int *ext_prime, const ModUpDigits &dg,
+                          hipStream_t s) {
+    int dmin = next;
+    for (int j = 0; j < beta; ++j) dmin = dg.dl[j] < dmin ? dg.dl[j] : dmin;
+    const int ntb = (next - dmin + TB - 1) / TB, cblk = (1 << (2 * H)) / COLS, nz = cnt * beta;
+    const dim3 grid = conv_grid(ntb, cblk, nz);
+#define MN_CASE(D)                                                                                                \
+    case D:                                                                                                       \
+        KLN("k_modup_ntt", (k_modup_ntt<H, COLS, D, TB>), grid, dim3(COLS << H), 0, s, T, v, vstride, ext, esb, \
+            esj, beta, next, ext_prime, dg, ntb, cblk, nz);                                                       \
+        break;
+    switch (DL) { MN_CASE(4) MN_CASE(8) MN_CASE(10) MN_CASE(12) MN_CASE(16) }
+#undef MN_CASE
+}
+
+void launch_modup_ntt(const DevTables &T, const double *v, long long vstride, double *ext, long long esb,
+                      long long esj, int cnt, int beta, int next, const int *ext_prime, const ModUpDigits &dg,
+                      hipStream_t s) {
+    if (cnt <= 0) return;
+    int dmax = 0;
+    for (int j = 0; j < beta; ++j) dmax = dg.dl[j] > dmax ? dg.dl[j] : dmax;
+    // the l+1 digit words in, every converted slot (after the first pass) out
+    kprof_set_bytes(8.0 * T.N * cnt * ((double)beta * next));
+    if (T.logN == 16) modup_ntt_run<4, 16, 2>(digit_len(dmax), T, v, vstride, ext, esb, esj, cnt, beta, next,
+                                              ext_prime, dg, s);
+    else if (T.logN == 12) modup_ntt_run<3, 32, 2>(digit_len(dmax), T, v, vstride, ext, esb, esj, cnt, beta, next,
+                                                   ext_prime, dg, s);
+    else throw std::invalid_argument("launch_modup_ntt: log N must be 12 or 16");
 }
 
 void launch_tensor_intt(const DevTables &T, const VecSet &vs, const NttPro &pro, int variant, hipStream_t s) {
