@@ -504,7 +504,7 @@ struct Exec {
                 launch_ntt(T, VecSet{acc + (long long)l * N, cnt * 2 * (A + 1), A + 1, (long long)next * N, nullptr,
                                      C->ext_prime[l] + l},
                            true, C->ntt_variant, s, nullptr, C->mr_scale[l]);
-                launch_moddown_conv(T, acc, (long long)next * N, conv, (long long)l * N, cnt * 2,
+                launch_moddown_ntt(T, acc, (long long)next * N, conv, (long long)l * N, cnt * 2,
                                     MdIn{l, A + 1, C->ext_prime[l] + l, C->mr_phat[l], l, l}, s);
                 NttEpi epi{};
                 epi.kind = 3;
@@ -516,7 +516,7 @@ struct Exec {
                 epi.cst = C->mr_inv[l];
                 epi.cst2 = C->qlinv + (long long)l * (C->L + 1);
                 launch_ntt_fused(T, VecSet{conv, cnt * 2 * l, l, (long long)l * N, nullptr, nullptr}, NttPro{}, epi,
-                                 C->ntt_variant, s);
+                                 C->ntt_variant, s, 2);
                 C->arena.release(m);
                 return;
             }
@@ -526,7 +526,7 @@ struct Exec {
                 double *acc1 = acc + (long long)next * N;
                 launch_ntt(T, VecSet{acc1 + (long long)(l + 1) * N, cnt * A, A, 2LL * next * N, nullptr, C->pprime},
                            true, C->ntt_variant, s, nullptr, C->md_scale);
-                launch_moddown_conv(T, acc1, 2LL * next * N, conv, (long long)(l + 1) * N, cnt,
+                launch_moddown_ntt(T, acc1, 2LL * next * N, conv, (long long)(l + 1) * N, cnt,
                                     MdIn{l + 1, A, C->pprime, C->phat, C->L + 1, l + 1}, s);
                 NttEpi epi{};
                 epi.kind = 1;
@@ -541,14 +541,14 @@ struct Exec {
                 epi.chain = chain_out;
                 epi.ch_g = (long long)(l + 1) * N;
                 launch_ntt_fused(T, VecSet{conv, cnt * (l + 1), l + 1, (long long)(l + 1) * N, nullptr, nullptr},
-                                 NttPro{}, epi, C->ntt_variant, s);
+                                 NttPro{}, epi, C->ntt_variant, s, 2);
                 C->arena.release(m);
                 return;
             }
             // P slots to the coefficient domain, scaled by Phat_m^-1
             launch_ntt(T, VecSet{acc + (long long)(l + 1) * N, cnt * 2 * A, A, (long long)next * N, nullptr, C->pprime},
                        true, C->ntt_variant, s, nullptr, C->md_scale);
-            launch_moddown_conv(T, acc, (long long)next * N, conv, (long long)(l + 1) * N, cnt * 2,
+            launch_moddown_ntt(T, acc, (long long)next * N, conv, (long long)(l + 1) * N, cnt * 2,
                                 MdIn{l + 1, A, C->pprime, C->phat, C->L + 1, l + 1}, s);
             // transform the conversion and combine on store: (acc - conv) P^-1 + addends
             NttEpi epi{};
@@ -561,7 +561,7 @@ struct Exec {
             epi.add2 = a2.p; epi.a2_ct = a2.ct; epi.a2_poly = a2.poly; epi.m2 = a2.mask;
             epi.cst = C->Pinv;
             launch_ntt_fused(T, VecSet{conv, cnt * 2 * (l + 1), l + 1, (long long)(l + 1) * N, nullptr, nullptr},
-                             NttPro{}, epi, C->ntt_variant, s);
+                             NttPro{}, epi, C->ntt_variant, s, 2);
         }
         C->arena.release(m);
     }

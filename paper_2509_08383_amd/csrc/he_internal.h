@@ -138,8 +138,10 @@ struct NttEpi {
     double *chain;
     long long ch_g;
 };
+// passes: 3 both; 2 the second alone (vs holds the first pass's output, as
+// launch_moddown_ntt writes it)
 void launch_ntt_fused(const DevTables &T, const VecSet &vs, const NttPro &pro, const NttEpi &epi, int variant,
-                      hipStream_t s);
+                      hipStream_t s, int passes = 3);
 // the second pass of the forward NTT alone (vs holds the first pass's output)
 void launch_ntt_fwd_pass2(const DevTables &T, const VecSet &vs, int variant, hipStream_t s);
 // the tensor of pro (kind 2) and the first pass of the inverse NTT of its d2 into vs
@@ -278,8 +280,14 @@ struct MdIn {
     const double *ph;
     int phs, ntgt;
 };
-void launch_moddown_conv(const DevTables &T, const double *acc, long long astride, double *conv,
-                         long long cstride, int groups, const MdIn &md, hipStream_t s);
+// ModDown conversion fused with the first pass of the forward NTT of its output: acc
+// holds, at slots in0 .. in0+nin-1 of every group, the coefficient-domain words
+// w_m = [A_m Bhat_m^-1]_{b_m} of the basis being divided out (the inverse NTT applied
+// the scaling); each is lifted to its centred representative and conv_i = sum_m w_m
+// [Bhat_m]_{q_i} for the targets i < ntgt (prime i), transformed by the first pass;
+// launch_ntt_fused(..., passes = 2) on conv completes the transform
+void launch_moddown_ntt(const DevTables &T, const double *acc, long long astride, double *conv, long long cstride,
+                        int groups, const MdIn &md, hipStream_t s);
 void launch_sample_uniform(const DevTables &T, const VecSet &out, uint64_t seed, uint32_t obj,
                            const int *gprime, hipStream_t s);
 void launch_sample_small(int *out, int N, uint64_t seed, uint32_t obj, int kind, hipStream_t s);

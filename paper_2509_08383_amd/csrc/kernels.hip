@@ -963,86 +963,6 @@ void launch_inner_product_rot(const DevTables &T, const double *ext, long long e
        acc1, astride, rs, betaL, cnt, beta, next, ext_prime, xblocks);
 }
 
-// ModDown conversion: acc holds, at slots in0 .. in0+nin-1 of every group, the
-// coefficient-domain words w_m = [A_m * Bhat_m^-1]_{b_m} of the basis being divided
-// out (the inverse NTT applied the scaling): P (in0 = level+1) or P q_level (in0 =
-// level, the rescale folded in).  Each is lifted to its centred representative and
-// conv_i = sum_m w_m [Bhat_m]_{q_i} for the targets i < ntgt.  acc holds groups at
-// astride; conv [groups][ntgt].  Grid: x = blocks of TB targets, y = coefficient
-// blocks, z = group; the block's [Bhat_m]_{q_i} table is staged in LDS as in k_modup.
-template <int AL, int TB>
-__global__ __launch_bounds__(256) void k_moddown_conv(DevTables T, const double *__restrict__ acc,
-                                                      long long astride, double *__restrict__ conv,
-                                                      long long cstride, MdIn md, int ntb, int cblk, int nz) {
-    __shared__ double sq[AL * TB];
-    __shared__ double sp[TB], si[TB];
-    ConvIdx ix;
-    if (!conv_idx(blockIdx.x, ntb, cblk, nz, ix)) return;
-    const int i0 = ix.tb * TB, tid = threadIdx.x;
-    for (int k = tid; k < AL * TB; k += blockDim.x) {
-        const int m = k / TB, i = i0 + (k - (k / TB) * TB);
-        sq[k] = (m < md.nin && i < md.ntgt) ? md.ph[m * md.phs + i] : 0.0;
-    }
-    if (tid < TB) {
-        const int i = i0 + tid < md.ntgt ? i0 + tid : 0;
-        sp[tid] = T.p[i];
-        si[tid] = T.pinv[i];
-    }
-    __syncthreads();
-    const int x = ix.cb * blockDim.x + tid;
-    if (x >= T.N) return;
-    const double *Ac = acc + ix.z * astride + (long long)md.in0 * T.N + x;
-    double w[AL];
-#pragma unroll
-    for (int m = 0; m < AL; ++m) {
-        if (m < md.nin) {
-            const double p = T.p[md.in_prime[m]];
-            const double u = Ac[(long long)m * T.N];
-            w[m] = u > 0.5 * (p - 1.0) ? u - p : u;
-        } else {
-            w[m] = 0.0;
-        }
-    }
-    double *out = conv + ix.z * cstride + x;
-#pragma unroll
-    for (int ii = 0; ii < TB; ++ii) {
-        const int i = i0 + ii;
-        if (i >= md.ntgt) break;
-        const double p = sp[ii], pinv = si[ii];
-        double sacc = 0.0;
-#pragma unroll
-        for (int m = 0; m < AL; ++m) sacc += mm(w[m], sq[m * TB + ii], p, pinv);
-        out[(long long)i * T.N] = canon(sacc, p, pinv);
-    }
-}
-
-template <int TB>
-static void conv_tb(int AL, int cblk, int nz, hipStream_t s, const DevTables &T, const double *acc, long long astride,
-                    double *conv, long long cstride, const MdIn &md) {
-    const int ntb = (md.ntgt + TB - 1) / TB;
-    const dim3 grid = conv_grid(ntb, cblk, nz);
-#define MD_CASE(D)                                                                                             \
-    case D:                                                                                                    \
-        KL("k_moddown_conv", (k_moddown_conv<D, TB>), grid, dim3(256), 0, s, T, acc, astride, conv, cstride, \
-           md, ntb, cblk, nz);                                                                                 \
-        break;
-    switch (AL) { MD_CASE(4) MD_CASE(8) MD_CASE(10) MD_CASE(12) MD_CASE(16) }
-#undef MD_CASE
-}
-
-void launch_moddown_conv(const DevTables &T, const double *acc, long long astride, double *conv,
-                         long long cstride, int groups, const MdIn &md, hipStream_t s) {
-    if (groups <= 0) return;
-    const int AL = digit_len(md.nin);
-    const int cblk = (T.N + 255) / 256;
-    const bool wide = (long long)((md.ntgt + 7) / 8) * cblk * groups >= 2048;
-    kprof_set_bytes(8.0 * T.N * groups * (md.nin + md.ntgt));
-    if (wide)
-        conv_tb<8>(AL, cblk, groups, s, T, acc, astride, conv, cstride, md);
-    else
-        conv_tb<4>(AL, cblk, groups, s, T, acc, astride, conv, cstride, md);
-}
-
 // ---------------------------------------------------------------- sampling
 // Philox4x32-10 (Salmon et al., SC 2011), counter (i, prime, obj, attempt).
 DEV void philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1,

@@ -352,6 +352,64 @@ __global__ __launch_bounds__(COLS *(1 << H)) void k_ntt(VecSet vs, VecSet src, c
     }
 }
 
+// The forward NTT's first pass on one vector's E words held by a thread (canonical,
+// at positions c + SUB (th + TPS e) of its COLS-column block): H stages in registers,
+// the exchange through the tile, H stages, stored at X[SUB (th E + e)] (X = the
+// vector's column c).  Word for word the pass k_ntt runs.  Contains one barrier; the
+// caller separates consecutive uses of the tile with another.
+template <int H, int COLS>
+DEV void pass1_words(double (&x)[1 << H], const double *tw, double p, double pinv, double *tile, int c, int th,
+                     double *X) {
+    constexpr int E = 1 << H, TPS = 1 << H, SUB = 1 << (2 * H), NW = (1 << H) - 1;
+    auto lds = [](int cc, int k) { return (k + (k >> H)) * COLS + cc; };
+    double wa[NW], wb[NW];
+#pragma unroll
+    for (int sg = 0; sg < H; ++sg) {
+#pragma unroll
+        for (int g = 0; g < (1 << sg); ++g) {
+            wa[(1 << sg) - 1 + g] = tw[(1 << sg) + g];
+            wb[(1 << sg) - 1 + g] = tw[(1 << (H + sg)) + (th << sg) + g];
+        }
+    }
+#pragma unroll
+    for (int sg = 0; sg < H; ++sg) {
+        const int hd = E >> (sg + 1);
+#pragma unroll
+        for (int g = 0; g < (1 << sg); ++g) {
+            const double w = wa[(1 << sg) - 1 + g];
+#pragma unroll
+            for (int i = 0; i < hd; ++i) {
+                const int e0 = g * 2 * hd + i, e1 = e0 + hd;
+                const double u = nmm(x[e1], w, p, pinv);
+                x[e1] = x[e0] - u;
+                x[e0] = x[e0] + u;
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) tile[lds(c, th + TPS * e)] = nred(x[e], p, pinv);
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) x[e] = tile[lds(c, th * E + e)];
+#pragma unroll
+    for (int sg = 0; sg < H; ++sg) {
+        const int hd = E >> (sg + 1);
+#pragma unroll
+        for (int g = 0; g < (1 << sg); ++g) {
+            const double w = wb[(1 << sg) - 1 + g];
+#pragma unroll
+            for (int i = 0; i < hd; ++i) {
+                const int e0 = g * 2 * hd + i, e1 = e0 + hd;
+                const double u = nmm(x[e1], w, p, pinv);
+                x[e1] = x[e0] - u;
+                x[e0] = x[e0] + u;
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) X[(long long)SUB * (th * E + e)] = ncanon(x[e], p, pinv);
+}
+
 // ModUp fused into the first pass of the forward NTT of the extended digits.  For
 // digit j of ciphertext ct the converted slots are t in [0, lo) u [lo + dl, next); the
 // k-th of them is t = k < lo ? k : k + dl.  A workgroup takes COLS columns of the
@@ -370,12 +428,11 @@ __global__ __launch_bounds__(COLS *(1 << H)) void k_modup_ntt(DevTables T, const
                                                                const int *__restrict__ ext_prime, ModUpDigits dg,
                                                                int ntb, int cblk, int nz) {
     constexpr int R = 2 * H, E = 1 << H, TPS = 1 << H, SUB = 1 << R, NT = COLS * TPS;
-    constexpr int NN = SUB * SUB, S2 = SUB + SUB / E, NW = (1 << H) - 1;
+    constexpr int NN = SUB * SUB, S2 = SUB + SUB / E;
     __shared__ double tile[COLS * S2];
     __shared__ double sq[DL * TB];
     __shared__ double sp[TB], si[TB];
     __shared__ int spt[TB];
-    auto lds = [](int c, int k) { return (k + (k >> H)) * COLS + c; };
     ConvIdx ix;
     if (!conv_idx(blockIdx.x, ntb, cblk, nz, ix)) return;  // uniform over the workgroup
     const int ct = ix.z / beta, j = ix.z - (ix.z / beta) * beta;
@@ -429,60 +486,79 @@ __global__ __launch_bounds__(COLS *(1 << H)) void k_modup_ntt(DevTables T, const
         if (kk >= ncv) break;  // uniform
         const int t = kk < lo ? kk : kk + dl;
         const double p = sp[tt], pinv = si[tt];
-        const double *tw = T.tw + (long long)spt[tt] * NN;
-        double wa[NW], wb[NW];
-#pragma unroll
-        for (int sg = 0; sg < H; ++sg) {
-#pragma unroll
-            for (int g = 0; g < (1 << sg); ++g) {
-                wa[(1 << sg) - 1 + g] = tw[(1 << sg) + g];
-                wb[(1 << sg) - 1 + g] = tw[(1 << (H + sg)) + (th << sg) + g];
-            }
-        }
         double x[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) x[e] = ncanon(acc[tt][e], p, pinv);
-        // phase A (high bits of k)
-#pragma unroll
-        for (int sg = 0; sg < H; ++sg) {
-            const int hd = E >> (sg + 1);
-#pragma unroll
-            for (int g = 0; g < (1 << sg); ++g) {
-                const double w = wa[(1 << sg) - 1 + g];
-#pragma unroll
-                for (int i = 0; i < hd; ++i) {
-                    const int e0 = g * 2 * hd + i, e1 = e0 + hd;
-                    const double u = nmm(x[e1], w, p, pinv);
-                    x[e1] = x[e0] - u;
-                    x[e0] = x[e0] + u;
-                }
-            }
-        }
         if (tt > 0) __syncthreads();  // the previous target's tile reads are done
+        pass1_words<H, COLS>(x, T.tw + (long long)spt[tt] * NN, p, pinv, tile, c, th,
+                             ext + ct * esb + j * esj + (long long)t * NN + col);
+    }
+}
+
+// ModDown conversion fused into the first pass of the forward NTT of its output: the
+// centred lift of the md.nin input limbs of group z (|w| <= p_m / 2), converted to every
+// target q_i, i < md.ntgt (|sum| <= AL (p/2 + 2^44) < 2^52 for AL <= 16), then the
+// pass, on the grid and with the TB-target blocks of k_modup_ntt.
+template <int H, int COLS, int AL, int TB>
+__global__ __launch_bounds__(COLS *(1 << H)) void k_moddown_ntt(DevTables T, const double *__restrict__ acc,
+                                                                 long long astride, double *__restrict__ conv,
+                                                                 long long cstride, MdIn md, int ntb, int cblk,
+                                                                 int nz) {
+    constexpr int R = 2 * H, E = 1 << H, TPS = 1 << H, SUB = 1 << R, NT = COLS * TPS;
+    constexpr int NN = SUB * SUB, S2 = SUB + SUB / E;
+    __shared__ double tile[COLS * S2];
+    __shared__ double sq[AL * TB];
+    __shared__ double sp[TB], si[TB];
+    ConvIdx ix;
+    if (!conv_idx(blockIdx.x, ntb, cblk, nz, ix)) return;  // uniform over the workgroup
+    const int i0 = ix.tb * TB;
+    if (i0 >= md.ntgt) return;  // uniform
+    const int tid = threadIdx.x;
+    for (int k = tid; k < AL * TB; k += NT) {
+        const int m = k / TB, i = i0 + (k - (k / TB) * TB);
+        sq[k] = (m < md.nin && i < md.ntgt) ? md.ph[m * md.phs + i] : 0.0;
+    }
+    if (tid < TB) {
+        const int i = i0 + tid < md.ntgt ? i0 + tid : 0;
+        sp[tid] = T.p[i];
+        si[tid] = T.pinv[i];
+    }
+    __syncthreads();
+    const int c = tid % COLS, th = tid / COLS;
+    const long long col = (long long)ix.cb * COLS + c;
+    double sacc[TB][E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) tile[lds(c, th + TPS * e)] = nred(x[e], p, pinv);
-        __syncthreads();
-        // phase B (low bits of k)
+    for (int ii = 0; ii < TB; ++ii)
 #pragma unroll
-        for (int e = 0; e < E; ++e) x[e] = tile[lds(c, th * E + e)];
+        for (int e = 0; e < E; ++e) sacc[ii][e] = 0.0;
+    const double *Ac = acc + ix.z * astride + (long long)md.in0 * NN + col;
 #pragma unroll
-        for (int sg = 0; sg < H; ++sg) {
-            const int hd = E >> (sg + 1);
+    for (int m = 0; m < AL; ++m) {
+        if (m < md.nin) {
+            const double pm = T.p[md.in_prime[m]];
+            double w[E];
 #pragma unroll
-            for (int g = 0; g < (1 << sg); ++g) {
-                const double w = wb[(1 << sg) - 1 + g];
-#pragma unroll
-                for (int i = 0; i < hd; ++i) {
-                    const int e0 = g * 2 * hd + i, e1 = e0 + hd;
-                    const double u = nmm(x[e1], w, p, pinv);
-                    x[e1] = x[e0] - u;
-                    x[e0] = x[e0] + u;
-                }
+            for (int e = 0; e < E; ++e) {
+                const double u = Ac[(long long)m * NN + (long long)SUB * (th + TPS * e)];
+                w[e] = u > 0.5 * (pm - 1.0) ? u - pm : u;
             }
-        }
-        double *X = ext + ct * esb + j * esj + (long long)t * NN + col;
 #pragma unroll
-        for (int e = 0; e < E; ++e) X[(long long)SUB * (th * E + e)] = ncanon(x[e], p, pinv);
+            for (int ii = 0; ii < TB; ++ii)
+#pragma unroll
+                for (int e = 0; e < E; ++e) sacc[ii][e] += nmm(w[e], sq[m * TB + ii], sp[ii], si[ii]);
+        }
+    }
+#pragma unroll
+    for (int ii = 0; ii < TB; ++ii) {
+        const int i = i0 + ii;
+        if (i >= md.ntgt) break;  // uniform
+        const double p = sp[ii], pinv = si[ii];
+        double x[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) x[e] = ncanon(sacc[ii][e], p, pinv);
+        if (ii > 0) __syncthreads();  // the previous target's tile reads are done
+        pass1_words<H, COLS>(x, T.tw + (long long)i * NN, p, pinv, tile, c, th,
+                             conv + ix.z * cstride + (long long)i * NN + col);
     }
 }
 
@@ -618,21 +694,52 @@ void launch_modup_ntt(const DevTables &T, const double *v, long long vstride, do
     else throw std::invalid_argument("launch_modup_ntt: log N must be 12 or 16");
 }
 
+template <int H, int COLS, int TB>
+static void moddown_ntt_run(int AL, const DevTables &T, const double *acc, long long astride, double *conv,
+                            long long cstride, int groups, const MdIn &md, hipStream_t s) {
+    const int ntb = (md.ntgt + TB - 1) / TB, cblk = (1 << (2 * H)) / COLS;
+    const dim3 grid = conv_grid(ntb, cblk, groups);
+#define MDN_CASE(D)                                                                                                \
+    case D:                                                                                                        \
+        KLN("k_moddown_ntt", (k_moddown_ntt<H, COLS, D, TB>), grid, dim3(COLS << H), 0, s, T, acc, astride, conv, \
+            cstride, md, ntb, cblk, groups);                                                                       \
+        break;
+    switch (AL) { MDN_CASE(4) MDN_CASE(8) MDN_CASE(10) MDN_CASE(12) MDN_CASE(16) }
+#undef MDN_CASE
+}
+
+void launch_moddown_ntt(const DevTables &T, const double *acc, long long astride, double *conv, long long cstride,
+                        int groups, const MdIn &md, hipStream_t s) {
+    if (groups <= 0) return;
+    // the inputs in, every target (after the first pass) out
+    kprof_set_bytes(8.0 * T.N * groups * (md.nin + md.ntgt));
+    if (T.logN == 16 && groups < 8)
+        moddown_ntt_run<4, 16, 1>(digit_len(md.nin), T, acc, astride, conv, cstride, groups, md, s);
+    else if (T.logN == 16) moddown_ntt_run<4, 16, 2>(digit_len(md.nin), T, acc, astride, conv, cstride, groups, md, s);
+    else if (T.logN == 12) moddown_ntt_run<3, 32, 2>(digit_len(md.nin), T, acc, astride, conv, cstride, groups, md, s);
+    else throw std::invalid_argument("launch_moddown_ntt: log N must be 12 or 16");
+}
+
 void launch_tensor_intt(const DevTables &T, const VecSet &vs, const NttPro &pro, int variant, hipStream_t s) {
     if (pro.kind != 2) throw std::invalid_argument("launch_tensor_intt: tensor prologue expected");
     ntt_dispatch<2, 0>(T, vs, true, variant, s, nullptr, nullptr, pro, NttEpi{}, 1);
 }
 
 void launch_ntt_fused(const DevTables &T, const VecSet &vs, const NttPro &pro, const NttEpi &epi, int variant,
-                      hipStream_t s) {
-    if (pro.kind == 1 && epi.kind == 2) ntt_dispatch<1, 2>(T, vs, false, variant, s, nullptr, nullptr, pro, epi);
+                      hipStream_t s, int passes) {
+    if (pro.kind == 1 && epi.kind == 2)
+        ntt_dispatch<1, 2>(T, vs, false, variant, s, nullptr, nullptr, pro, epi, passes);
     else if (pro.kind == 0 && epi.kind == 1 && epi.chain)
-        ntt_dispatch<0, 4>(T, vs, false, variant, s, nullptr, nullptr, pro, epi);
-    else if (pro.kind == 0 && epi.kind == 1) ntt_dispatch<0, 1>(T, vs, false, variant, s, nullptr, nullptr, pro, epi);
-    else if (pro.kind == 1 && epi.kind == 0) ntt_dispatch<1, 0>(T, vs, false, variant, s, nullptr, nullptr, pro, epi);
-    else if (pro.kind == 0 && epi.kind == 2) ntt_dispatch<0, 2>(T, vs, false, variant, s, nullptr, nullptr, pro, epi);
-    else if (pro.kind == 0 && epi.kind == 3) ntt_dispatch<0, 3>(T, vs, false, variant, s, nullptr, nullptr, pro, epi);
-    else ntt_dispatch<0, 0>(T, vs, false, variant, s, nullptr, nullptr, pro, epi);
+        ntt_dispatch<0, 4>(T, vs, false, variant, s, nullptr, nullptr, pro, epi, passes);
+    else if (pro.kind == 0 && epi.kind == 1)
+        ntt_dispatch<0, 1>(T, vs, false, variant, s, nullptr, nullptr, pro, epi, passes);
+    else if (pro.kind == 1 && epi.kind == 0)
+        ntt_dispatch<1, 0>(T, vs, false, variant, s, nullptr, nullptr, pro, epi, passes);
+    else if (pro.kind == 0 && epi.kind == 2)
+        ntt_dispatch<0, 2>(T, vs, false, variant, s, nullptr, nullptr, pro, epi, passes);
+    else if (pro.kind == 0 && epi.kind == 3)
+        ntt_dispatch<0, 3>(T, vs, false, variant, s, nullptr, nullptr, pro, epi, passes);
+    else ntt_dispatch<0, 0>(T, vs, false, variant, s, nullptr, nullptr, pro, epi, passes);
 }
 
 }  // namespace he
