@@ -54,7 +54,7 @@ def kernel_class(name: str) -> str:
     if m:
         p2, inv, pro, epi = m.group(3) == "true", m.group(4) == "true", int(m.group(5)), int(m.group(6))
         s = "ntt_" + ("inv" if inv else "fwd") + ("_pass2" if p2 else "_pass1")
-        s += {1: "_lift"}.get(pro, "") + {1: "_moddown", 2: "_rescale", 3: "_moddown_rescale",
+        s += {1: "_lift", 2: "_tensor"}.get(pro, "") + {1: "_moddown", 2: "_rescale", 3: "_moddown_rescale",
                                           4: "_moddown_chain"}.get(epi, "")
         if m.group(7) and int(m.group(7)):
             s += "_factored"

@@ -90,6 +90,7 @@ def test_kernel_class_names():
     assert rs.kernel_class("void he::k_ntt<4, 16, true, false, 0, 3, 0>(x)") == "ntt_fwd_pass2_moddown_rescale"
     assert rs.kernel_class("void he::k_ntt<4, 16, true, true, 0, 0, 1>(x)") == "ntt_inv_pass2_factored"
     assert rs.kernel_class("void he::k_ntt<4, 8, true, false, 0, 4, 0>(x)") == "ntt_fwd_pass2_moddown_chain"
+    assert rs.kernel_class("void he::k_ntt<4, 16, true, true, 2, 0, 1>(x)") == "ntt_inv_pass2_tensor_factored"
     assert rs.kernel_class("void he::k_inner_product_rot<3>(he::DevTables)") == "k_inner_product_rot"
     assert rs.kernel_class("void he::k_inner_product_rot_reg<7, 3>(x)") == "k_inner_product_rot"
     assert rs.kernel_class("void he::k_inner_product_rot_lds<7, 3, 2>(x)") == "k_inner_product_rot"
