@@ -166,13 +166,12 @@ struct ModUpDigits {
     const double *qhat[8];  // [dl][next] per digit
     int lo[8], dl[8];
 };
-// skip_own: the digits' own slots are not written (their readers take them from dntt)
 void launch_modup(const DevTables &T, const double *v, long long vstride, double *ext, long long esb,
                   long long esj, const double *dntt, long long nstride, int cnt, int beta, int next,
-                  const int *ext_prime, const ModUpDigits &dg, hipStream_t s, bool skip_own = false);
-// ModUp of every digit (as launch_modup with skip_own) fused with the first pass of the
-// forward NTT of the converted slots; launch_ntt_fwd_pass2 over those slots completes
-// the transform
+                  const int *ext_prime, const ModUpDigits &dg, hipStream_t s);
+// ModUp of every digit (as launch_modup, the own slots left unwritten) fused with the
+// first pass of the forward NTT of the converted slots; launch_ntt_fwd_pass2 over those
+// slots completes the transform
 void launch_modup_ntt(const DevTables &T, const double *v, long long vstride, double *ext, long long esb,
                       long long esj, int cnt, int beta, int next, const int *ext_prime, const ModUpDigits &dg,
                       hipStream_t s);

@@ -333,8 +333,9 @@ void launch_lincomb(const DevTables &T, double *out, long long oct, long long op
 // v holds v_a = [d_{lo+a} * Qhat_a^-1]_{q_{lo+a}} in the coefficient domain (the
 // inverse NTT applied that scaling); for every extended slot t outside the digit
 // ext_j,t = sum_a v~_a [Qhat_a]_{prime(t)} with v~_a the centred representative of v_a
-// (|v~_a| <= q/2); digit slots copy the NTT-domain input, or are left unwritten with
-// skip_own (the key products then read those words from the input).
+// (|v~_a| <= q/2); digit slots copy the NTT-domain input.  (The key switch itself runs
+// the conversion fused with the NTT, k_modup_ntt; this form serves the extended digits
+// the bootstrap's multi-rotation products precompute.)
 // Grid: x = blocks of TB target slots (fastest, so the v words of one coefficient
 // block stay in L2 across target blocks), y = coefficient blocks, z = (ciphertext,
 // digit).  The block's [Qhat_a]_{prime(t)} table and moduli are staged in LDS (every
@@ -348,7 +349,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                                                double *__restrict__ ext, long long esb, long long esj,
                                                const double *__restrict__ dntt, long long nstride, int beta,
                                                int next, const int *__restrict__ ext_prime, ModUpDigits dg,
-                                               int ntb, int cblk, int nz, int skip_own) {
+                                               int ntb, int cblk, int nz) {
     __shared__ double sq[DL * TB];
     __shared__ double sp[TB], si[TB];
     ConvIdx ix;
@@ -398,24 +399,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         double acc = 0.0;
 #pragma unroll
         for (int a = 0; a < DL; ++a) acc += mm(va[a], sq[a * TB + tt], p, pinv);
-        if (t >= lo && t < lo + dl) {
-            if (!skip_own) X[(long long)t * T.N] = dntt[ct * nstride + (long long)t * T.N + x];
-        } else {
-            X[(long long)t * T.N] = canon(acc, p, pinv);
-        }
+        if (t >= lo && t < lo + dl) X[(long long)t * T.N] = dntt[ct * nstride + (long long)t * T.N + x];
+        else X[(long long)t * T.N] = canon(acc, p, pinv);
     }
 }
 
 template <int TB>
 static void modup_tb(int DL, int cblk, int nz, hipStream_t s, const DevTables &T, const double *v, long long vstride,
                      double *ext, long long esb, long long esj, const double *dntt, long long nstride, int beta,
-                     int next, const int *ext_prime, const ModUpDigits &dg, int skip_own) {
+                     int next, const int *ext_prime, const ModUpDigits &dg) {
     const int ntb = (next + TB - 1) / TB;
     const dim3 grid = conv_grid(ntb, cblk, nz);
 #define MU_CASE(D)                                                                                          \
     case D:                                                                                                 \
         KL("k_modup", (k_modup<D, TB>), grid, dim3(256), 0, s, T, v, vstride, ext, esb, esj, dntt, nstride, \
-           beta, next, ext_prime, dg, ntb, cblk, nz, skip_own);                                             \
+           beta, next, ext_prime, dg, ntb, cblk, nz);                                                       \
         break;
     switch (DL) { MU_CASE(4) MU_CASE(8) MU_CASE(10) MU_CASE(12) MU_CASE(16) }
 #undef MU_CASE
@@ -423,7 +421,7 @@ static void modup_tb(int DL, int cblk, int nz, hipStream_t s, const DevTables &T
 
 void launch_modup(const DevTables &T, const double *v, long long vstride, double *ext, long long esb,
                   long long esj, const double *dntt, long long nstride, int cnt, int beta, int next,
-                  const int *ext_prime, const ModUpDigits &dg, hipStream_t s, bool skip_own) {
+                  const int *ext_prime, const ModUpDigits &dg, hipStream_t s) {
     if (cnt <= 0) return;
     int dmax = 0;
     for (int j = 0; j < beta; ++j) dmax = dg.dl[j] > dmax ? dg.dl[j] : dmax;
@@ -435,13 +433,13 @@ void launch_modup(const DevTables &T, const double *v, long long vstride, double
     for (int j = 0; j < beta; ++j) lp1 += dg.dl[j];
     // the l+1 digit words in, every extended slot out; the l+1 NTT-domain words in and
     // out again unless skipped
-    kprof_set_bytes(8.0 * T.N * cnt * (skip_own ? (double)beta * next : 2.0 * lp1 + (double)beta * next));
+    kprof_set_bytes(8.0 * T.N * cnt * (2.0 * lp1 + (double)beta * next));
     if (wide)
         modup_tb<8>(DL, cblk, cnt * beta, s, T, v, vstride, ext, esb, esj, dntt, nstride, beta, next, ext_prime,
-                    dg, skip_own ? 1 : 0);
+                    dg);
     else
         modup_tb<4>(DL, cblk, cnt * beta, s, T, v, vstride, ext, esb, esj, dntt, nstride, beta, next, ext_prime,
-                    dg, skip_own ? 1 : 0);
+                    dg);
 }
 
 // the two words (polynomials 0, 1) of digit j of prime t at position x: hi 2^32 + lo,

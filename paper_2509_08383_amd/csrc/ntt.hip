@@ -593,26 +593,36 @@ static void ntt_run(const DevTables &T, const VecSet &vs, const VecSet *src, boo
     // group; a fused epilogue adds its element-wise operands (in, addends)
     const double half = 8.0 * SUB * SUB;
     const double nvec = vs.count, ngrp = (vs.count + vs.group - 1) / vs.group;
-    if (!inverse) {
-        if (passes & 1) {
-            kprof_set_bytes(half * (PRO ? ngrp : nvec));
-            KLN(PRO ? "ntt_fwd_pass1_lift" : "ntt_fwd_pass1", (k_ntt<H, COLS, false, false, PRO, 0, 0>), grid, block,
-                0, s, vs, first, nullptr, T, pro, epi, 0);
+    // a prologue or epilogue kind of one direction is not instantiated for the other
+    if (inverse ? (EPI != 0 || PRO == 1) : PRO == 2)
+        throw std::invalid_argument("ntt: prologue or epilogue kind of the other direction");
+    if constexpr (PRO != 2) {
+        if (!inverse) {
+            if (passes & 1) {
+                kprof_set_bytes(half * (PRO ? ngrp : nvec));
+                KLN(PRO ? "ntt_fwd_pass1_lift" : "ntt_fwd_pass1", (k_ntt<H, COLS, false, false, PRO, 0, 0>), grid,
+                    block, 0, s, vs, first, nullptr, T, pro, epi, 0);
+            }
+            if (!(passes & 2)) return;
+            double extra = 0.0;
+            if (EPI) {
+                extra = 1.0;  // in
+                if ((EPI == 1 || EPI == 4) && epi.add1) extra += __builtin_popcount(epi.m1 & 3) * 0.5;
+                if ((EPI == 1 || EPI == 4) && epi.add2) extra += __builtin_popcount(epi.m2 & 3) * 0.5;
+                if (EPI == 3) extra += 1.0;
+                if (EPI == 4) extra += 0.5;  // the chained pass's output
+            }
+            kprof_set_bytes(half * nvec * (1.0 + extra));
+            KLN(EPI == 4   ? "ntt_fwd_pass2_moddown_chain"
+                : EPI == 1 ? "ntt_fwd_pass2_moddown"
+                : EPI == 2 ? "ntt_fwd_pass2_rescale"
+                : EPI == 3 ? "ntt_fwd_pass2_moddown_rescale"
+                           : "ntt_fwd_pass2",
+                (k_ntt<H, COLS, true, false, 0, EPI, TWF>), grid, block, 0, s, vs, none, nullptr, T, pro, epi, pm);
+            return;
         }
-        if (!(passes & 2)) return;
-        double extra = 0.0;
-        if (EPI) {
-            extra = 1.0;  // in
-            if ((EPI == 1 || EPI == 4) && epi.add1) extra += __builtin_popcount(epi.m1 & 3) * 0.5;
-            if ((EPI == 1 || EPI == 4) && epi.add2) extra += __builtin_popcount(epi.m2 & 3) * 0.5;
-            if (EPI == 3) extra += 1.0;
-            if (EPI == 4) extra += 0.5;  // the chained pass's output
-        }
-        kprof_set_bytes(half * nvec * (1.0 + extra));
-        KLN(EPI == 4 ? "ntt_fwd_pass2_moddown_chain" : EPI == 1 ? "ntt_fwd_pass2_moddown"
-                     : (EPI == 2 ? "ntt_fwd_pass2_rescale" : (EPI == 3 ? "ntt_fwd_pass2_moddown_rescale" : "ntt_fwd_pass2")),
-            (k_ntt<H, COLS, true, false, 0, EPI, TWF>), grid, block, 0, s, vs, none, nullptr, T, pro, epi, pm);
-    } else {
+    }
+    if constexpr (EPI == 0 && PRO != 1) {
         if (passes & 1) {
             // the tensor prologue reads 4 words and writes 3 besides the pass's output
             kprof_set_bytes(half * nvec * (PRO == 2 ? 8.0 : 1.0));
