@@ -1,5 +1,5 @@
 """GPU parity at the 128-bit parameter set (N = 2^16, 30 Q primes, dnum = 3): primitives
-bit-exact against the CPU oracle at full size; the measured T=3 CutMax on 32000 LLM-like logits
+and a two-ciphertext rotate-and-sum bit-exact against the CPU oracle at full size; the measured T=3 CutMax on 32000 LLM-like logits
 bit-exact against the oracle and within 1e-3 of the FP64 mirror with the argmax recovered; the
 batched form (16 mixed requests with 1- and 4-ciphertext requests) with a request of each kind
 bit-exact against the oracle."""
@@ -62,6 +62,27 @@ def test_encrypt_and_primitives_full_size(sec):
     sec.same(sec.G.mul(sec.G.drop(gx, lv), sec.G.drop(gy, lv)), sec.O.mul(sec.O.drop(ox, lv), sec.O.drop(oy, lv)),
              "mul@9")
     np.testing.assert_allclose(sec.G.decrypt(sec.G.mul(gx, gy)), x * y, atol=1e-6)
+
+
+def test_rotsum_two_ciphertexts_full_size(sec):
+    """rotate-and-sum of a two-ciphertext handle at the top level and at level 12: the
+    batched key products (keys held in registers for the first two hoisted steps, sources
+    staged in LDS for the last three, two ciphertexts each), the fused basis conversions
+    with two ciphertexts and the chained first inverse passes, word for word against the
+    oracle on each ciphertext"""
+    say("[gpu] secure: rotsum of a 2-ciphertext handle")
+    rng = np.random.default_rng(21)
+    m = np.concatenate([ckks.encode(rng.uniform(-1, 1, sec.O.slots), sec.O.N, sec.O.Delta) for _ in range(2)])
+    g2 = sec.G.encrypt_coeffs(m, sec.O.Delta, 2 * sec.G.slots)
+    o2 = [sec.O.encrypt_coeffs(m[k * sec.O.N:(k + 1) * sec.O.N], sec.O.Delta) for k in range(2)]
+    for lv in (None, 12):
+        gi = g2 if lv is None else sec.G.drop(g2, lv)
+        oi = o2 if lv is None else [sec.O.drop(o, lv) for o in o2]
+        eg = sec.G.export(sec.G.rotsum(gi))
+        assert eg.shape[0] == 2
+        for k in range(2):
+            bad = int((eg[k] != sec.O.rotsum(oi[k]).export()).sum())
+            assert bad == 0, f"level {lv}, ciphertext {k}: {bad} words differ"
 
 
 def test_ntt_variants_full_size(sec):
