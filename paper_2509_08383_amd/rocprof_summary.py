@@ -11,7 +11,10 @@ Inputs are rocprofv3 output directories written with ``--output-format csv`` (th
 * ``--tex DIR``: a run with TA_TA_BUSY and TD_TD_BUSY (the texture address and data
   units of the vector memory path, one of each per CU);
 * ``--bench-json FILE``: bench.py's JSON line with the event profiler's algorithmic
-  bytes per kernel and the digest of the library sources that ran.
+  bytes per kernel and the digest of the library sources that ran;
+* ``--per-launch NAME`` (with ``--trace``): instead of the table, every dispatch of the
+  kernel class NAME in the timed call, in launch order, with its template instance and
+  duration.
 
 The dispatches of the timed CutMax are the second half of those between the last
 encryption kernel (k_encfinish) and the first decryption kernel (k_decmul): the bench
@@ -183,6 +186,18 @@ def summarize(trace=None, fetch=None, write=None, valu=None, lds=None, bench_jso
             "src_digest": digest, "kernels": res}
 
 
+def per_launch(trace: str, name: str):
+    """[(template instance, grid x, microseconds)] of the class' dispatches in the timed call"""
+    out = []
+    for r in cutmax_window(_trace(trace)):
+        if kernel_class(r["Kernel_Name"]) != name:
+            continue
+        inst = re.sub(r"\(.*", "", r["Kernel_Name"]).replace("void ", "").replace("he::", "")
+        us = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
+        out.append((inst, r.get("Grid_Size_X", ""), us))
+    return out
+
+
 def to_markdown(s) -> str:
     cols = [("kernel", "{}"), ("launches", "{}"), ("total_ms", "{:.3f}"), ("avg_us", "{:.1f}"), ("share", "{:.1%}"),
             ("alg_MiB", "{:.1f}"), ("fetch_MiB", "{:.1f}"), ("write_MiB", "{:.1f}"), ("hbm_GBps", "{:.0f}"),
@@ -208,7 +223,14 @@ def main():
     ap.add_argument("--bench-json", help="a file holding bench.py's JSON line (algorithmic bytes, "
                     "source digest); the counter runs' own logs hold one")
     ap.add_argument("--json-out", help="also write the summary as JSON to this file")
+    ap.add_argument("--per-launch", help="list every dispatch of this kernel class instead")
     a = ap.parse_args()
+    if a.per_launch:
+        rows = per_launch(a.trace, a.per_launch)
+        print("| # | instance | grid | us |\n|---|---|---|---|")
+        for i, (inst, gx, us) in enumerate(rows):
+            print(f"| {i} | `{inst}` | {gx} | {us:.1f} |")
+        return
     s = summarize(a.trace, a.fetch, a.write, a.valu, a.lds, a.bench_json, a.tex)
     if a.json_out:
         with open(a.json_out, "w") as fh:

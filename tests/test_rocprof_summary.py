@@ -75,6 +75,16 @@ def test_texture_unit_busy_fraction(tmp_path):
     assert "ta_busy" in rs.to_markdown(s)
 
 
+def test_per_launch_lists_the_timed_dispatches_of_a_class(tmp_path):
+    rows = _trace(["void he::k_inner_product_rot_lds<7, 3, 1>(he::DevTables)", "he::k_modup<10, 8>(a)",
+                   "void he::k_inner_product_rot<3, 7>(he::DevTables)"])
+    _write(str(tmp_path / "trace"), rows)
+    got = rs.per_launch(str(tmp_path / "trace"), "k_inner_product_rot")
+    # the timed half: dispatches 5 and 7 (5000 and 7000 ns)
+    assert [g[0] for g in got] == ["k_inner_product_rot_lds<7, 3, 1>", "k_inner_product_rot<3, 7>"]
+    assert [g[2] for g in got] == [5.0, 7.0]
+
+
 def test_mismatched_halves_are_rejected(tmp_path):
     rows = _trace(["he::k_modup<10, 8>(a)"])
     rows[2]["Kernel_Name"] = "he::k_tensor(a)"        # the timed half launches another kernel
