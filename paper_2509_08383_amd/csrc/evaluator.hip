@@ -2208,12 +2208,15 @@ void build_ctx(he_ctx *C, const he_params *prm) {
             o_ndp[l].push_back(tb.i(npr));
         }
         o_mus[l] = tb.d(mus);
+        // converted limbs of all digits, listed prime by prime: the two or three limbs of one
+        // prime are adjacent, so the NTT blocks of one column range that share its twiddle
+        // row run back to back on one XCD and re-read the row from its L2
         std::vector<int> as, ap;
-        for (int j = 0; j < beta; ++j) {
-            const int lo = j * A, dl = std::min(A, l + 1 - lo);
-            for (int t = 0; t < next; ++t)
+        for (int t = 0; t < next; ++t)
+            for (int j = 0; j < beta; ++j) {
+                const int lo = j * A, dl = std::min(A, l + 1 - lo);
                 if (!(t >= lo && t < lo + dl)) { as.push_back(j * next + t); ap.push_back(ep[t]); }
-        }
+            }
         C->ndall[l] = (int)as.size();
         o_nas[l] = tb.i(as);
         o_nap[l] = tb.i(ap);
